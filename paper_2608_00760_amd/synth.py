@@ -1,0 +1,156 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle runs.
+
+This module draws fields only; it contains none of the solver's arithmetic.
+Every field is a float64 numpy array of shape (N+1, N+1, N+1) on the vertices
+of an N-cell grid with unit spacing, x slowest, z fastest.
+
+Recipes (the paper's Monte Carlo tissue data are not available; these stand
+in for coefficient fields and sources of the same kind):
+  grf       Gaussian random field with power spectrum proportional to k^-3:
+            white noise N(0,1), FFT, amplitude scaled by |k|^-3/2 with integer
+            wavenumbers, k = 0 removed, inverse FFT, normalised to sample mean 0
+            and standard deviation 1.
+  log D     clip(grf, -ln 100, ln 100): mean log 1, std 1, contrast <= 1e4.
+  log mua   ln 0.05 + grf (independent seed).
+  blob      exp(-|x - c|^2 / (2 sigma^2)) on vertex coordinates.
+  q         sum of 16 blobs, centres ~ U[0.15N, 0.85N]^3, sigma ~ U[2, 6],
+            amplitude ~ U[0.5, 1.5], plus N(0, 0.01^2) noise.
+  tangents  N(0, 1); boundary entries of dq, dlogmua and rhobar are zeroed
+            (they are ignored by the operator), dlogD keeps them.
+"""
+import math
+
+import numpy as np
+
+try:
+    import scipy.fft as _fft
+    _FFT_KW = {"workers": -1}
+except ImportError:  # numpy fallback
+    _fft = np.fft
+    _FFT_KW = {}
+
+
+def shape(N):
+    return (N + 1, N + 1, N + 1)
+
+
+def grf(N, seed, slope=-3.0):
+    """Zero-mean unit-variance Gaussian random field with P(k) ~ k^slope."""
+    rng = np.random.default_rng(seed)
+    n = N + 1
+    w = rng.standard_normal(shape(N))
+    W = _fft.rfftn(w, **_FFT_KW)
+    kx = np.fft.fftfreq(n) * n
+    kz = np.fft.rfftfreq(n) * n
+    k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
+    k2[0, 0, 0] = 1.0
+    amp = k2 ** (slope / 4.0)          # |k|^(slope/2)
+    amp[0, 0, 0] = 0.0
+    W *= amp
+    f = _fft.irfftn(W, s=shape(N), **_FFT_KW)
+    f -= f.mean()
+    f /= f.std()
+    return np.ascontiguousarray(f)
+
+
+def coords(N):
+    x = np.arange(N + 1, dtype=np.float64)
+    return x[:, None, None], x[None, :, None], x[None, None, :]
+
+
+def blob(N, centre, sigma, amplitude=1.0):
+    X, Y, Z = coords(N)
+    r2 = (X - centre[0]) ** 2 + (Y - centre[1]) ** 2 + (Z - centre[2]) ** 2
+    return amplitude * np.exp(-r2 / (2.0 * sigma * sigma))
+
+
+def zero_boundary(f):
+    f = f.copy()
+    f[0, :, :] = f[-1, :, :] = 0.0
+    f[:, 0, :] = f[:, -1, :] = 0.0
+    f[:, :, 0] = f[:, :, -1] = 0.0
+    return f
+
+
+def normal(N, seed, zero_bdry=True):
+    f = np.random.default_rng(seed).standard_normal(shape(N))
+    return zero_boundary(f) if zero_bdry else f
+
+
+def log_coefficients(N, seed_D, seed_mu):
+    logD = np.clip(grf(N, seed_D), -math.log(100.0), math.log(100.0))
+    logmua = math.log(0.05) + grf(N, seed_mu)
+    return logD, logmua
+
+
+def blob_source(N, seed, nblobs=16, noise=0.01):
+    rng = np.random.default_rng(seed)
+    q = np.zeros(shape(N))
+    for _ in range(nblobs):
+        c = rng.uniform(0.15 * N, 0.85 * N, size=3)
+        s = rng.uniform(2.0, 6.0)
+        a = rng.uniform(0.5, 1.5)
+        q += blob(N, c, s, a)
+    q += noise * rng.standard_normal(shape(N))
+    return q
+
+
+def constant_case(N=32):
+    """Constant coefficients D = 1, mua = 0.1 and a centred blob (sigma 3)."""
+    D = np.ones(shape(N))
+    mua = np.full(shape(N), 0.1)
+    q = blob(N, (N / 2, N / 2, N / 2), 3.0)
+    return {"N": N, "logD": np.log(D), "logmua": np.log(mua), "D": D, "mua": mua, "q": q}
+
+
+def grf_case(N, base_seed):
+    """Log-normal GRF coefficients and a 16-blob source.  Seeds are
+    base_seed+1 (log D), +2 (log mua), +3 (q), +4 (cotangent rhobar)."""
+    logD, logmua = log_coefficients(N, base_seed + 1, base_seed + 2)
+    q = blob_source(N, base_seed + 3)
+    return {"N": N, "logD": logD, "logmua": logmua, "D": np.exp(logD), "mua": np.exp(logmua), "q": q,
+            "rhobar": normal(N, base_seed + 4)}
+
+
+def tangents(N, base_seed):
+    """Tangents (dq, dlogD, dlogmua) and cotangent rhobar, seeds base_seed+1..+4."""
+    return {"dq": normal(N, base_seed + 1), "dlogD": normal(N, base_seed + 2, zero_bdry=False),
+            "dlogmua": normal(N, base_seed + 3), "rhobar": normal(N, base_seed + 4)}
+
+
+# Named workloads (sizes and seeds).
+def small_constant():
+    """32^3 cells, D = 1, mua = 0.1, centred blob; tangents seeds 1001-1004."""
+    c = constant_case(32)
+    c.update(tangents(32, 1000))
+    return c
+
+
+def grf_128():
+    """128^3 cells, GRF coefficients, seeds 2001-2004."""
+    return grf_case(128, 2000)
+
+
+def grf_256():
+    """256^3 cells, GRF coefficients, seeds 3001-3004."""
+    return grf_case(256, 3000)
+
+
+def grf_512():
+    """512^3 cells, GRF coefficients, seeds 5001-5004."""
+    return grf_case(512, 5000)
+
+
+def serving_stream(nreq=512, sizes=(64, 96, 128, 192), seed=4999, rate=None):
+    """Request descriptors for the serving stream: grid size, mode
+    ('jvp' or 'vjp', 50/50), per-request field seed 4000+r and Poisson arrival
+    times (exponential gaps with the given rate; None = all at t = 0)."""
+    rng = np.random.default_rng(seed)
+    Ns = rng.choice(np.array(sizes), size=nreq)
+    modes = rng.choice(np.array(["jvp", "vjp"]), size=nreq)
+    if rate is None:
+        t = np.zeros(nreq)
+    else:
+        t = np.cumsum(rng.exponential(1.0 / rate, size=nreq))
+    return [{"id": r, "N": int(Ns[r]), "mode": str(modes[r]), "seed": 4000 + r, "arrival": float(t[r])}
+            for r in range(nreq)]
