@@ -1,0 +1,168 @@
+"""Benchmark: forward solve + VJP pairs per second on one MI355X.
+
+Workload: 256^3 cells (257^3 vertices), log D and log mua Gaussian random
+fields (power spectrum k^-3, std 1, means log 1 and log 0.05, D contrast
+<= 1e4), source = 16 Gaussian blobs + N(0, 0.01^2) noise, cotangent N(0, 1);
+float32 V(2,2)-cycles inside float64 iterative refinement, forward and
+pull-back each to 1e-10 relative residual.  One step = coefficient set-up
+(exp, validation, hierarchy) + forward solve + pull-back with all three
+gradients, on inputs already resident in device memory.
+
+Prints one JSON line.  The dominant kernel's roofline figure comes from HIP
+events around its launches during the timed steps (on its launch stream);
+the CPU baseline is the FP64 oracle timed on a bounded sample of the same
+workload on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(c, cycles_fwd, cycles_adj):
+    """Time the oracle on a bounded sample: hierarchy set-up, 2 forward
+    cycles, 2 adjoint cycles (with gradients); scale to a full fwd+VJP pair
+    with the cycle counts the solve needs."""
+    from oracle import ref
+    t0 = time.perf_counter()
+    H = ref.Hierarchy(c["D"], c["mua"])
+    t1 = time.perf_counter()
+    rho, _ = H.forward(c["q"], fixed_cycles=2)
+    t2 = time.perf_counter()
+    H.vjp(rho, c["rhobar"], fixed_cycles=2)
+    t3 = time.perf_counter()
+    setup, fwd2, adj2 = t1 - t0, t2 - t1, t3 - t2
+    pair_s = setup + fwd2 / 2 * cycles_fwd + adj2 / 2 * cycles_adj
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / pair_s, "unit": "fwd+VJP pairs/s", "cores": min(cores, os.cpu_count() or cores),
+            "kind": "oracle",
+            "sample": "N=%d: hierarchy set-up %.2fs + 2 forward V-cycles %.2fs + 2 adjoint V-cycles with gradients "
+                      "%.2fs, scaled to %d forward + %d adjoint cycles (FP64, C/OpenMP)"
+                      % (c["N"], setup, fwd2, adj2, cycles_fwd, cycles_adj)}
+
+
+def run_steps(P, t, bufs, steps):
+    import torch
+    info_f = info_a = None
+    for _ in range(steps):
+        P.set_log_coefficients(t["logD"], t["logmua"])
+        _, info_f = P.forward(t["q"], out=bufs[0])
+        _, info_a = P.vjp(bufs[0], t["rhobar"], out=bufs[1:])
+    return info_f, info_a
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--precision", default="fp32-in-fp64", choices=["fp32-in-fp64", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the solver has no multi-GPU path (requested --gpus %d)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2608_00760_amd import synth
+    from paper_2608_00760_amd.solver import Options, Plan
+
+    N = args.size
+    log("generating inputs N=%d" % N)
+    c = synth.grf_case(N, {128: 2000, 256: 3000, 512: 5000}.get(N, 3000))
+    dev = torch.device("cuda:0")
+    t = {k: torch.from_numpy(c[k]).to(dev) for k in ("logD", "logmua", "q", "rhobar")}
+    shape = t["q"].shape
+    bufs = [torch.empty(shape, dtype=torch.float64, device=dev) for _ in range(4)]
+
+    P = Plan(Options(N, precision=args.precision, rtol=1e-10, max_cycles=100))
+    log("plan: %d levels, %.2f GB" % (P.levels, P.bytes / 1e9))
+    run_steps(P, t, bufs, args.warmup)
+    torch.cuda.synchronize()
+    P.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info_f, info_a = run_steps(P, t, bufs, args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stats = P.timing_read()
+    P.timing(False)
+    ms_per_step = elapsed / args.steps * 1e3
+    log("step %.3f ms, fwd cycles %d (%.2e), adj cycles %d (%.2e)" % (
+        ms_per_step, info_f["cycles"], info_f["rel_residual"], info_a["cycles"], info_a["rel_residual"]))
+    dom = max(stats, key=lambda k: stats[k]["ms"])
+    d = stats[dom]
+    avg_ms = d["ms"] / max(d["launches"], 1)
+    bytes_per_launch = d["bytes"] / max(d["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    kernels = {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / max(v["launches"], 1),
+                   "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None,
+                   "share": v["ms"] / (elapsed * 1e3)} for k, v in stats.items() if v["launches"]}
+
+    fp64 = None
+    if args.precision != "fp64" and not args.no_fp64_compare:
+        P64 = Plan(Options(N, precision="fp64", rtol=1e-10, max_cycles=100))
+        run_steps(P64, t, bufs, 1)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        k64 = max(2, args.steps // 3)
+        f64, a64 = run_steps(P64, t, bufs, k64)
+        torch.cuda.synchronize()
+        fp64 = {"ms_per_step": (time.perf_counter() - s0) / k64 * 1e3, "cycles_fwd": f64["cycles"],
+                "cycles_adj": a64["cycles"]}
+        P64.close()
+        log("fp64 solver: %.3f ms/step" % fp64["ms_per_step"])
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample")
+        cpu = cpu_baseline(c, info_f["cycles"], info_a["cycles"])
+        log("oracle: %.4f pairs/s (%s)" % (cpu["value"], cpu["sample"]))
+
+    nv = (N + 1) ** 3
+    out = {
+        "metric": "fwd+VJP solves/s at 256^3 (1e-10 rel. residual); GB/s vs HBM peak",
+        "value": args.steps / elapsed,
+        "unit": "fwd+VJP pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-in-f64" if args.precision == "fp32-in-fp64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "diffusion-absorption multigrid solve + adjoint, %d^3 cells, GRF log-normal D (contrast "
+                               "<=1e4) and mua, 16-blob source, V(2,2) RB-GS, rtol 1e-10, set-up+forward+VJP per step"
+                               % N,
+                   "N": N, "precision": args.precision, "rtol": 1e-10,
+                   "cycles_fwd": info_f["cycles"], "cycles_adj": info_a["cycles"],
+                   "rel_residual_fwd": info_f["rel_residual"], "rel_residual_adj": info_a["rel_residual"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": bytes_per_launch},
+        "kernels": kernels,
+        "fp64_solver": fp64,
+        "latency_p50_p99": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

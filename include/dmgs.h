@@ -1,0 +1,201 @@
+/*
+ * dmgs.h -- C ABI of the differentiable geometric-multigrid solver for the
+ * steady-state diffusion-absorption equation on an AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Problem (paper, Sec. 2, Eq. (maineq)): -div(D grad rho) + mua rho = q on a
+ * cube with Dirichlet boundary rho = g, discretised by a second-order 7-point
+ * finite-difference stencil on a vertex-centred grid of N cells per axis
+ * ((N+1)^3 vertices, spacing h).  The solver S (Sec. 2.2, Eq. (Eqcomp)) is
+ * a sequence of V(nu_pre, nu_post)-cycles of red-black Gauss-Seidel with
+ * full-weighting restriction (Eq. (rest)), trilinear prolongation
+ * I = 2^3 R^T (Sec. 2.3.3), operators rediscretised on every level and an
+ * exact solve on the coarsest level (N_c = 2 or 3).  The push-forward
+ * (Sec. 2.3) and the pull-back S^dagger (Sec. 2.4, Eq. (EqcompT)) are exposed
+ * with respect to q and, extending the paper (Sec. 4 lists it as future
+ * work), with respect to log D and log mua as adjoint-state derivatives of
+ * the discrete solution.
+ *
+ * Conventions for every entry point:
+ *  - Field arrays are DEVICE pointers to dense C-order float64 arrays of
+ *    (N+1)^3 entries, x slowest, z fastest: v = (x*(N+1) + y)*(N+1) + z.
+ *    They are owned by the caller and must stay valid until the work enqueued
+ *    on `stream` has finished.  Outputs must not alias inputs.
+ *  - Boundary vertices (any coordinate 0 or N) of q, mua, tangents and
+ *    cotangents are ignored; D is read on all vertices (boundary faces need
+ *    it).  Outputs are written on all vertices (boundary: g for rho, 0 for
+ *    tangents and gradients except logD_bar, which is defined on all
+ *    vertices).
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *    it.  Calls that solve to a tolerance wait for the per-cycle residual and
+ *    so return after the work has finished.  With fixed_cycles > 0 a solve
+ *    does not wait, unless `info` is given: then the call waits at the end
+ *    to fill in the final residual and the device time.
+ *  - A plan may be used by one host thread and one stream at a time; use
+ *    several plans for concurrency.
+ *  - Every function returns a dmgs_status; no C++ exception crosses the ABI.
+ *    dmgs_last_error() gives a thread-local message for the last failure.
+ *    `info` may be NULL.
+ */
+#ifndef DMGS_H
+#define DMGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dmgs_plan_s *dmgs_plan;
+
+typedef enum dmgs_status {
+    DMGS_OK = 0,
+    DMGS_ERR_INVALID = 1,        /* bad options, sizes, coefficients or call order */
+    DMGS_ERR_OOM = 2,            /* device allocation failed */
+    DMGS_ERR_NOT_CONVERGED = 3,  /* max_cycles reached; outputs hold the last iterate */
+    DMGS_ERR_NONFINITE = 4,      /* NaN/Inf in an input or in the residual */
+    DMGS_ERR_HIP = 5,            /* a HIP runtime call failed */
+    DMGS_ERR_BUDGET = 6          /* request exceeds the memory budget (serving) */
+} dmgs_status;
+
+enum dmgs_precision {
+    DMGS_FP64 = 0,          /* every step in float64 */
+    DMGS_FP32_IN_FP64 = 1   /* float32 V-cycles inside float64 iterative refinement:
+                               fine residual, solution update and coarsest solve in float64 */
+};
+enum dmgs_smoother { DMGS_RBGS = 0 };
+enum dmgs_face_mean { DMGS_FACE_ARITH = 0, DMGS_FACE_HARMONIC = 1 };
+
+typedef struct dmgs_options {
+    int32_t n[3];          /* cells per axis; all three equal, N = c*2^m, c in {2,3}, 2 <= N <= 1024 */
+    int32_t precision;     /* dmgs_precision */
+    int32_t smoother;      /* dmgs_smoother (red-black Gauss-Seidel, Sec. 2.3.1) */
+    int32_t nu_pre;        /* pre-smoothing sweeps (red-black pairs), 0..8; default 2 */
+    int32_t nu_post;       /* post-smoothing sweeps, 0..8; default 2 */
+    int32_t max_cycles;    /* tolerance mode: give up after this many cycles */
+    int32_t fixed_cycles;  /* > 0: exactly this many cycles in every solve (Sec. 2.4, second mode) */
+    int32_t face_mean;     /* dmgs_face_mean: D on a face = arithmetic or harmonic mean */
+    double h;              /* grid spacing (> 0) */
+    double bc_value;       /* Dirichlet value g of rho on the boundary */
+    double rtol;           /* tolerance mode: stop when ||r||_2 / ||r_0||_2 <= rtol over interior vertices */
+} dmgs_options;
+
+typedef struct dmgs_info {
+    int32_t cycles;        /* V-cycles (or refinement steps) applied */
+    int32_t status;        /* dmgs_status of the call */
+    double rel_residual;   /* final ||r|| / ||r_0|| of the solve (adjoint: ||rhobar - A qbar|| / ||rhobar||) */
+    double device_ms;      /* device time of the call, from events on `stream` */
+} dmgs_info;
+
+/* Fill `opt` with the defaults: V(2,2), RB-GS, FP64, arithmetic face mean,
+ * h = 1, g = 0, rtol = 1e-10, max_cycles = 200, fixed_cycles = 0. */
+void dmgs_default_options(int32_t n, dmgs_options *opt);
+
+/* Device bytes a plan with these options allocates (hierarchy + scratch); 0
+ * for invalid options.  Used for admission by memory footprint. */
+size_t dmgs_workspace_bytes(const dmgs_options *opt);
+
+/* Create a plan: validate options and allocate the level hierarchy on the
+ * current device.  Errors: DMGS_ERR_INVALID, DMGS_ERR_OOM, DMGS_ERR_HIP. */
+int dmgs_plan_create(const dmgs_options *opt, dmgs_plan *out);
+int dmgs_plan_destroy(dmgs_plan plan);
+
+/* Number of levels and cells per axis on level k (k = 0 finest). */
+int dmgs_plan_levels(dmgs_plan plan);
+int dmgs_plan_level_n(dmgs_plan plan, int k);
+
+/* Coefficient set-up (Sec. 2.2: operators rediscretised on every level):
+ * copy D and mua, check D > 0, mua >= 0 (interior) and finiteness
+ * (DMGS_ERR_INVALID otherwise; this check waits for the stream), and build
+ * the coarse levels by full weighting on coarse interior vertices and
+ * injection on coarse boundary vertices.  The log variant takes log D and
+ * log mua and exponentiates on the device.  Must precede any solve. */
+int dmgs_set_coefficients(dmgs_plan plan, const double *D, const double *mua, void *stream);
+int dmgs_set_log_coefficients(dmgs_plan plan, const double *logD, const double *logmua, void *stream);
+
+/* Forward solve rho = S(q) (Sec. 2.2, Sec. 2.4). */
+int dmgs_forward(dmgs_plan plan, const double *q, double *rho, dmgs_info *info, void *stream);
+
+/* Push-forward: drho = S(dq - dA rho) with homogeneous boundary, where dA is
+ * the derivative of the operator along (dlogD, dlogmua) (Sec. 2.3: in q the
+ * Jacobian of S is S itself).  rho must be the forward solution for the
+ * current coefficients.  Any tangent may be NULL (= zero). */
+int dmgs_jvp(dmgs_plan plan, const double *rho, const double *dq, const double *dlogD,
+             const double *dlogmua, double *drho, dmgs_info *info, void *stream);
+
+/* Pull-back (Sec. 2.4, Eq. (EqcompT)): qbar = S^dagger rhobar, computed as
+ * the transposed V-cycles (each cycle's steps reversed and transposed, which
+ * is a V-cycle with black half-sweeps before red ones), then
+ *   logmua_bar = -mua * qbar * rho                      (interior, 0 on boundary)
+ *   logD_bar_v = -sum_{faces f=(a,b) at v} dD_f/dlogD_v (qbar_a - qbar_b)(rho_a - rho_b) / h^2
+ * with qbar = 0 and rho = g on boundary vertices.  logD_bar / logmua_bar may
+ * be NULL (not computed).  Tolerance mode stops on ||rhobar - A qbar|| /
+ * ||rhobar|| <= rtol; fixed mode applies exactly fixed_cycles cycles, making
+ * the result the exact transpose of the fixed-cycle forward map. */
+int dmgs_vjp(dmgs_plan plan, const double *rho, const double *rhobar, double *qbar,
+             double *logD_bar, double *logmua_bar, dmgs_info *info, void *stream);
+
+/* One-shot convenience: create, set coefficients, forward, destroy. */
+int dmgs_solve_once(const dmgs_options *opt, const double *D, const double *mua, const double *q,
+                    double *rho, dmgs_info *info, void *stream);
+
+const char *dmgs_status_string(int status);
+const char *dmgs_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing (profiling aid).  While enabled, every launch of a kernel
+ * class on the finest level is bracketed by HIP events on the stream it is
+ * launched on; elapsed times are collected at the plan's synchronisation
+ * points and at the end of every call.  Each record also carries the
+ * algorithmic bytes of the launch (every input read once, every output
+ * written once).  Enabling resets the counters.
+ * ------------------------------------------------------------------------- */
+enum dmgs_kernel_class {
+    DMGS_K_SMOOTH = 0,           /* smoothing pass (red-black sweeps)                 */
+    DMGS_K_DEFECT_RESTRICT = 1,  /* defect and full-weighting restriction             */
+    DMGS_K_PROLONG = 2,          /* prolongation and correction                        */
+    DMGS_K_RESIDUAL = 3,         /* float64 residual (norm; refinement cast)          */
+    DMGS_K_UPDATE = 4,           /* refinement update u += e                           */
+    DMGS_K_COEF = 5,             /* coefficient set-up and hierarchy build             */
+    DMGS_K_GRAD = 6,             /* tangent right-hand side and coefficient gradients  */
+    DMGS_K_COUNT = 7
+};
+int dmgs_timing_enable(dmgs_plan plan, int enable);
+int dmgs_timing_read(dmgs_plan plan, int kernel_class, int64_t *launches, double *total_ms,
+                     double *algorithmic_bytes);
+
+/* ---------------------------------------------------------------------------
+ * Diagnostic entry points: each runs one pass of the cycle on level k of a
+ * plan whose coefficients are set, on caller device arrays of level k's size
+ * ((N_k+1)^3, or (N_{k+1}+1)^3 for coarse arrays).  `fp32` selects the
+ * float32 instantiation used inside iterative refinement (arrays are then
+ * float32, coefficients the plan's float32 copies).  order 0 = red half-sweep
+ * first (forward), 1 = black first (transposed cycle).  Used by the parity
+ * tests; not needed to solve.
+ * ------------------------------------------------------------------------- */
+
+/* out = A_k u on interior vertices, 0 on the boundary. */
+int dmgs_debug_apply(dmgs_plan plan, int k, int fp32, const void *u, void *out, void *stream);
+/* Copy level k's coefficient fields (float64) into caller arrays. */
+int dmgs_debug_level_coefficients(dmgs_plan plan, int k, double *D, double *mua, void *stream);
+/* Pre-smoothing pass: u_out = nu_pre red-black sweeps applied to u_in with
+ * right-hand side q (Sec. 2.3.1), then qc = R (q - A_k u_out) on the coarse
+ * interior (Eq. (defect), Eq. (rest)), 0 on the coarse boundary. */
+int dmgs_debug_pre(dmgs_plan plan, int k, int fp32, int order, const void *u_in, const void *q,
+                   void *u_out, void *qc, void *stream);
+/* Post-smoothing pass: u_out = nu_post sweeps applied to u_in + I ec
+ * (Sec. 2.3.3). */
+int dmgs_debug_post(dmgs_plan plan, int k, int fp32, int order, const void *u_in, const void *ec,
+                    const void *q, void *u_out, void *stream);
+/* Exact solve on the coarsest level: u = A_c^{-1} q (boundary of u = 0). */
+int dmgs_debug_coarsest(dmgs_plan plan, int fp32, const void *q, void *u, void *stream);
+/* Exactly ncycles V-cycles applied to u (float64, in place) with right-hand
+ * side q, from whatever u holds (its boundary entries are the Dirichlet values). */
+int dmgs_debug_cycles(dmgs_plan plan, int order, int ncycles, const double *q, double *u, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMGS_H */

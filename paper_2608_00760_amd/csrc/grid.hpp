@@ -1,0 +1,57 @@
+// grid.hpp -- indexing and stencil helpers shared by the HIP kernels.
+//
+// Vertex-centred grid with N cells per axis: (N+1)^3 vertices, x slowest,
+// z fastest, v = (x*(N+1) + y)*(N+1) + z.  Interior vertices (the unknowns)
+// have all coordinates in [1, N-1]; the boundary layer holds the Dirichlet
+// value of the iterate (g on the finest level, 0 for coarse corrections).
+//
+// The operator (paper, Eq. (maineq), second-order finite differences):
+//   (A u)_i = sum_{6 neighbours j} c_ij (u_i - u_j) + mua_i u_i,
+//   c_ij = D_f / h^2, D_f = (D_i + D_j)/2 (or the harmonic mean).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dmgs {
+
+constexpr int kWave = 64;
+
+__host__ __device__ inline int64_t vidx(int n, int x, int y, int z) {
+    return ((int64_t)x * n + y) * n + z;
+}
+
+__host__ __device__ inline bool is_interior(int N, int x, int y, int z) {
+    return x > 0 && x < N && y > 0 && y < N && z > 0 && z < N;
+}
+
+// Per-level stencil constants in the arithmetic type T.
+template <class T>
+struct Stencil {
+    T half_inv_h2;   // 1 / (2 h^2): arithmetic face mean
+    T two_inv_h2;    // 2 / h^2: harmonic face mean
+    int harmonic;
+};
+
+template <class T>
+__device__ __forceinline__ T face_coef(T Da, T Db, const Stencil<T>& s) {
+    return s.harmonic ? (Da * Db) / (Da + Db) * s.two_inv_h2 : (Da + Db) * s.half_inv_h2;
+}
+
+// Deterministic block sum of a double (wave64 shuffles, then LDS); result in
+// thread 0.  blockDim.x must be a multiple of 64 and at most 1024.
+__device__ inline double block_sum(double v) {
+    __shared__ double wsum[16];
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+    int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    if (lane == 0) wsum[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        int nw = blockDim.x / kWave;
+        for (int i = 0; i < nw; i++) s += wsum[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+}  // namespace dmgs

@@ -1,0 +1,359 @@
+// kernels_basic.hpp -- one-operation-per-launch HIP kernels of the V-cycle:
+// the coefficient hierarchy, red-black half-sweeps, defect, restriction,
+// prolongation, the coarsest exact solve, residual norms, iterative
+// refinement casts and the derivative kernels.  Used on every level whose
+// arrays are too small for the fused streaming kernels, and by the
+// diagnostic entry points.
+#pragma once
+#include "grid.hpp"
+
+namespace dmgs {
+
+// ---------------------------------------------------------------------------
+// Fill, copy, cast
+
+template <class T>
+__global__ void k_init_iterate(T* __restrict__ u, int N, T g) {
+    int n = N + 1;
+    int64_t nv = (int64_t)n * n * n;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        int z = (int)(v % n), y = (int)((v / n) % n), x = (int)(v / ((int64_t)n * n));
+        u[v] = is_interior(N, x, y, z) ? T(0) : g;
+    }
+}
+
+template <class T>
+__global__ void k_fill(T* __restrict__ a, int64_t nv, T val) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x)
+        a[v] = val;
+}
+
+__global__ void k_exp_copy(const double* __restrict__ a, double* __restrict__ b, int64_t nv) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x)
+        b[v] = exp(a[v]);
+}
+
+__global__ void k_cast_f32(const double* __restrict__ a, float* __restrict__ b, int64_t nv) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x)
+        b[v] = (float)a[v];
+}
+
+// D > 0 and finite on every vertex, mua >= 0 and finite on interior vertices.
+__global__ void k_validate(const double* __restrict__ D, const double* __restrict__ mu, int N, int* __restrict__ bad) {
+    int n = N + 1;
+    int64_t nv = (int64_t)n * n * n;
+    int b = 0;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        int z = (int)(v % n), y = (int)((v / n) % n), x = (int)(v / ((int64_t)n * n));
+        double d = D[v];
+        if (!(d > 0.0) || !isfinite(d)) b = 1;
+        if (is_interior(N, x, y, z)) {
+            double m = mu[v];
+            if (!(m >= 0.0) || !isfinite(m)) b = 1;
+        }
+    }
+    if (b) atomicOr(bad, 1);
+}
+
+// Coefficient transfer to the next coarser level: full weighting
+// (1/64)(1,2,1)^3 on coarse interior vertices, injection on coarse boundary
+// vertices.
+__global__ void k_coarsen_coef(const double* __restrict__ f, double* __restrict__ c, int Nf) {
+    int Nc = Nf / 2, nf = Nf + 1, nc = Nc + 1;
+    int64_t nv = (int64_t)nc * nc * nc;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        int Z = (int)(v % nc), Y = (int)((v / nc) % nc), X = (int)(v / ((int64_t)nc * nc));
+        if (!is_interior(Nc, X, Y, Z)) { c[v] = f[vidx(nf, 2 * X, 2 * Y, 2 * Z)]; continue; }
+        double s = 0.0;
+        for (int a = -1; a <= 1; a++)
+            for (int b = -1; b <= 1; b++) {
+                double wab = (double)((2 - abs(a)) * (2 - abs(b)));
+                const double* row = f + vidx(nf, 2 * X + a, 2 * Y + b, 2 * Z);
+                s += wab * (row[-1] + 2.0 * row[0] + row[1]);
+            }
+        c[v] = s * (1.0 / 64.0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Red-black Gauss-Seidel half-sweep on colour c (0 = red = (x+y+z) even), in
+// place: u_i <- (q_i + sum_j c_ij u_j) / (sum_j c_ij + mua_i).  Each thread
+// updates one vertex of the colour; rows are interleaved by colour.
+template <class T>
+__global__ void k_gs_half(T* __restrict__ u, const T* __restrict__ q, const T* __restrict__ D,
+                          const T* __restrict__ mu, int N, Stencil<T> s, int colour) {
+    int M = N / 2, Ni = N - 1;
+    int64_t total = (int64_t)Ni * Ni * M;
+    int64_t lin = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (lin >= total) return;
+    int t = (int)(lin % M);
+    int64_t rem = lin / M;
+    int y = 1 + (int)(rem % Ni), x = 1 + (int)(rem / Ni);
+    int z = 1 + ((x + y + 1 + colour) & 1) + 2 * t;
+    if (z > N - 1) return;
+    int n = N + 1;
+    int64_t i = vidx(n, x, y, z);
+    int64_t sx = (int64_t)n * n;
+    T Di = D[i];
+    T c0 = face_coef(Di, D[i + sx], s), c1 = face_coef(Di, D[i - sx], s);
+    T c2 = face_coef(Di, D[i + n], s), c3 = face_coef(Di, D[i - n], s);
+    T c4 = face_coef(Di, D[i + 1], s), c5 = face_coef(Di, D[i - 1], s);
+    T num = q[i] + c0 * u[i + sx] + c1 * u[i - sx] + c2 * u[i + n] + c3 * u[i - n] + c4 * u[i + 1] + c5 * u[i - 1];
+    T den = mu[i] + c0 + c1 + c2 + c3 + c4 + c5;
+    u[i] = num / den;
+}
+
+// r = q - A u on interior vertices (0 on the boundary); mode 1 writes A u instead.
+template <class T>
+__global__ void k_defect(const T* __restrict__ u, const T* __restrict__ q, const T* __restrict__ D,
+                         const T* __restrict__ mu, T* __restrict__ r, int N, Stencil<T> s, int apply_only) {
+    int n = N + 1;
+    int64_t nv = (int64_t)n * n * n, sx = (int64_t)n * n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
+        int z = (int)(i % n), y = (int)((i / n) % n), x = (int)(i / sx);
+        if (!is_interior(N, x, y, z)) { r[i] = T(0); continue; }
+        T Di = D[i], ui = u[i];
+        T Au = mu[i] * ui + face_coef(Di, D[i + sx], s) * (ui - u[i + sx]) + face_coef(Di, D[i - sx], s) * (ui - u[i - sx]) +
+               face_coef(Di, D[i + n], s) * (ui - u[i + n]) + face_coef(Di, D[i - n], s) * (ui - u[i - n]) +
+               face_coef(Di, D[i + 1], s) * (ui - u[i + 1]) + face_coef(Di, D[i - 1], s) * (ui - u[i - 1]);
+        r[i] = apply_only ? Au : q[i] - Au;
+    }
+}
+
+// Full-weighting restriction qc = R r (1/64)(1,2,1)^3 on coarse interior
+// vertices, 0 on the coarse boundary.
+template <class T>
+__global__ void k_restrict(const T* __restrict__ r, T* __restrict__ qc, int Nf) {
+    int Nc = Nf / 2, nf = Nf + 1, nc = Nc + 1;
+    int64_t nv = (int64_t)nc * nc * nc;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        int Z = (int)(v % nc), Y = (int)((v / nc) % nc), X = (int)(v / ((int64_t)nc * nc));
+        if (!is_interior(Nc, X, Y, Z)) { qc[v] = T(0); continue; }
+        T s = T(0);
+        for (int a = -1; a <= 1; a++)
+            for (int b = -1; b <= 1; b++) {
+                T wab = T((2 - abs(a)) * (2 - abs(b)));
+                const T* row = r + vidx(nf, 2 * X + a, 2 * Y + b, 2 * Z);
+                s += wab * (row[-1] + T(2) * row[0] + row[1]);
+            }
+        qc[v] = s * T(1.0 / 64.0);
+    }
+}
+
+// u += I ec on fine interior vertices (trilinear interpolation, I = 8 R^T).
+template <class T>
+__global__ void k_prolong_add(const T* __restrict__ ec, T* __restrict__ u, int Nf) {
+    int nf = Nf + 1, nc = Nf / 2 + 1;
+    int64_t nv = (int64_t)nf * nf * nf;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        int z = (int)(v % nf), y = (int)((v / nf) % nf), x = (int)(v / ((int64_t)nf * nf));
+        if (!is_interior(Nf, x, y, z)) continue;
+        int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
+        int x1 = x0 + (x & 1), y1 = y0 + (y & 1), z1 = z0 + (z & 1);
+        T s = ec[vidx(nc, x0, y0, z0)] + ec[vidx(nc, x0, y0, z1)] + ec[vidx(nc, x0, y1, z0)] + ec[vidx(nc, x0, y1, z1)] +
+              ec[vidx(nc, x1, y0, z0)] + ec[vidx(nc, x1, y0, z1)] + ec[vidx(nc, x1, y1, z0)] + ec[vidx(nc, x1, y1, z1)];
+        // each of the 8 gathered corners repeats a corner when a coordinate is
+        // even, so the sum equals 8 x (trilinear value); scale by 1/8.
+        u[v] += s * T(0.125);
+    }
+}
+
+// Exact solve on a level with at most 8 interior unknowns (N = 2 or 3), one
+// thread, in float64 whatever T is: assemble the dense matrix and Cholesky.
+// Boundary entries of u are the Dirichlet values and move to the right side.
+template <class T>
+__global__ void k_exact_solve(const T* __restrict__ q, T* __restrict__ u, const double* __restrict__ D,
+                              const double* __restrict__ mu, int N, Stencil<double> s) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int n = N + 1, m = (N - 1) * (N - 1) * (N - 1);
+    double A[8][8], b[8];
+    int64_t vid[8];
+    int t = 0;
+    for (int x = 1; x < N; x++)
+        for (int y = 1; y < N; y++)
+            for (int z = 1; z < N; z++) vid[t++] = vidx(n, x, y, z);
+    for (int r = 0; r < m; r++)
+        for (int c = 0; c < m; c++) A[r][c] = 0.0;
+    const int off[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+    t = 0;
+    for (int x = 1; x < N; x++)
+        for (int y = 1; y < N; y++)
+            for (int z = 1; z < N; z++, t++) {
+                int64_t i = vid[t];
+                A[t][t] = mu[i];
+                b[t] = (double)q[i];
+                for (int e = 0; e < 6; e++) {
+                    int xa = x + off[e][0], ya = y + off[e][1], za = z + off[e][2];
+                    int64_t j = vidx(n, xa, ya, za);
+                    double c = face_coef(D[i], D[j], s);
+                    A[t][t] += c;
+                    if (is_interior(N, xa, ya, za)) {
+                        int tj = ((xa - 1) * (N - 1) + (ya - 1)) * (N - 1) + (za - 1);
+                        A[t][tj] -= c;
+                    } else {
+                        b[t] += c * (double)u[j];
+                    }
+                }
+            }
+    for (int j = 0; j < m; j++) {
+        double d = A[j][j];
+        for (int p = 0; p < j; p++) d -= A[j][p] * A[j][p];
+        d = sqrt(d);
+        A[j][j] = d;
+        for (int i = j + 1; i < m; i++) {
+            double acc = A[i][j];
+            for (int p = 0; p < j; p++) acc -= A[i][p] * A[j][p];
+            A[i][j] = acc / d;
+        }
+    }
+    for (int i = 0; i < m; i++) {
+        double acc = b[i];
+        for (int p = 0; p < i; p++) acc -= A[i][p] * b[p];
+        b[i] = acc / A[i][i];
+    }
+    for (int i = m - 1; i >= 0; i--) {
+        double acc = b[i];
+        for (int p = i + 1; p < m; p++) acc -= A[p][i] * b[p];
+        b[i] = acc / A[i][i];
+    }
+    for (int r = 0; r < m; r++) u[vid[r]] = (T)b[r];
+}
+
+// ---------------------------------------------------------------------------
+// Norms (float64 accumulation, deterministic two-stage reduction).
+
+// partial[block] = sum over the block's interior vertices of (q - A u)^2
+// (or of q^2 when u == nullptr).
+template <class T>
+__global__ void k_resid_sq(const T* __restrict__ u, const T* __restrict__ q, const T* __restrict__ D,
+                           const T* __restrict__ mu, int N, Stencil<T> s, double* __restrict__ partial) {
+    int n = N + 1;
+    int64_t nv = (int64_t)n * n * n, sx = (int64_t)n * n;
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
+        int z = (int)(i % n), y = (int)((i / n) % n), x = (int)(i / sx);
+        if (!is_interior(N, x, y, z)) continue;
+        T r = q[i];
+        if (u) {
+            T Di = D[i], ui = u[i];
+            r -= mu[i] * ui + face_coef(Di, D[i + sx], s) * (ui - u[i + sx]) + face_coef(Di, D[i - sx], s) * (ui - u[i - sx]) +
+                 face_coef(Di, D[i + n], s) * (ui - u[i + n]) + face_coef(Di, D[i - n], s) * (ui - u[i - n]) +
+                 face_coef(Di, D[i + 1], s) * (ui - u[i + 1]) + face_coef(Di, D[i - 1], s) * (ui - u[i - 1]);
+        }
+        acc += (double)r * (double)r;
+    }
+    double b = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = b;
+}
+
+// out[slot] = sum of partial[0..count) in a fixed order (one block).
+__global__ void k_sum_partials(const double* __restrict__ partial, int count, double* __restrict__ out, int slot) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) acc += partial[i];
+    double b = block_sum(acc);
+    if (threadIdx.x == 0) out[slot] = b;
+}
+
+// Iterative refinement, float64 step: r32 = float(q - A u) on interior
+// vertices (0 on the boundary), partial[block] = sum of (q - A u)^2.
+__global__ void k_resid_cast(const double* __restrict__ u, const double* __restrict__ q, const double* __restrict__ D,
+                             const double* __restrict__ mu, int N, Stencil<double> s, float* __restrict__ r32,
+                             double* __restrict__ partial) {
+    int n = N + 1;
+    int64_t nv = (int64_t)n * n * n, sx = (int64_t)n * n;
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
+        int z = (int)(i % n), y = (int)((i / n) % n), x = (int)(i / sx);
+        if (!is_interior(N, x, y, z)) { r32[i] = 0.0f; continue; }
+        double Di = D[i], ui = u[i];
+        double r = q[i] - (mu[i] * ui + face_coef(Di, D[i + sx], s) * (ui - u[i + sx]) + face_coef(Di, D[i - sx], s) * (ui - u[i - sx]) +
+                           face_coef(Di, D[i + n], s) * (ui - u[i + n]) + face_coef(Di, D[i - n], s) * (ui - u[i - n]) +
+                           face_coef(Di, D[i + 1], s) * (ui - u[i + 1]) + face_coef(Di, D[i - 1], s) * (ui - u[i - 1]));
+        r32[i] = (float)r;
+        acc += r * r;
+    }
+    double b = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = b;
+}
+
+// Iterative refinement, float64 step: u += e (e float32; boundary of e is 0).
+__global__ void k_add_correction(double* __restrict__ u, const float* __restrict__ e, int64_t nv) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x)
+        u[v] += (double)e[v];
+}
+
+// ---------------------------------------------------------------------------
+// Derivatives with respect to the coefficients (adjoint-state derivatives of
+// the discrete solution).
+
+// rhs = dq - (dA) rho on interior vertices (0 on the boundary), where
+// (dA rho)_i = sum_j dD_f,ij/h^2 (rho_i - rho_j) + mua_i dlogmua_i rho_i and
+// dD_f is the derivative of the face mean along dlogD.  Null tangents are 0.
+__global__ void k_tangent_rhs(const double* __restrict__ rho, const double* __restrict__ dq,
+                              const double* __restrict__ dlogD, const double* __restrict__ dlogmu,
+                              const double* __restrict__ D, const double* __restrict__ mu, int N, double inv_h2,
+                              int harmonic, double* __restrict__ rhs) {
+    int n = N + 1;
+    int64_t nv = (int64_t)n * n * n, sx = (int64_t)n * n;
+    const int64_t off[6] = {sx, -sx, (int64_t)n, -(int64_t)n, 1, -1};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
+        int z = (int)(i % n), y = (int)((i / n) % n), x = (int)(i / sx);
+        if (!is_interior(N, x, y, z)) { rhs[i] = 0.0; continue; }
+        double ri = rho[i], Di = D[i];
+        double acc = dlogmu ? mu[i] * dlogmu[i] * ri : 0.0;
+        if (dlogD) {
+            double dDi = Di * dlogD[i];
+            for (int e = 0; e < 6; e++) {
+                int64_t j = i + off[e];
+                double Dj = D[j], dDj = Dj * dlogD[j], dDf;
+                if (harmonic) {
+                    double sum = Di + Dj;
+                    dDf = 2.0 * (Dj * Dj * dDi + Di * Di * dDj) / (sum * sum);
+                } else {
+                    dDf = 0.5 * (dDi + dDj);
+                }
+                acc += dDf * inv_h2 * (ri - rho[j]);
+            }
+        }
+        rhs[i] = (dq ? dq[i] : 0.0) - acc;
+    }
+}
+
+// Coefficient gradients from the adjoint state lam = qbar:
+//   logmua_bar_i = -mua_i lam_i rho_i (interior, 0 on the boundary)
+//   logD_bar_v   = -sum_{faces (v,j), v or j interior} dD_f/dlogD_v (lam_v - lam_j)(rho_v - rho_j) / h^2
+// with lam = 0 on boundary vertices.
+__global__ void k_coef_grads(const double* __restrict__ rho, const double* __restrict__ lam,
+                             const double* __restrict__ D, const double* __restrict__ mu, int N, double inv_h2,
+                             int harmonic, double* __restrict__ gD, double* __restrict__ gmu) {
+    int n = N + 1;
+    int64_t nv = (int64_t)n * n * n, sx = (int64_t)n * n;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        int z = (int)(v % n), y = (int)((v / n) % n), x = (int)(v / sx);
+        bool vin = is_interior(N, x, y, z);
+        double lv = vin ? lam[v] : 0.0, rv = rho[v], Dv = D[v];
+        if (gmu) gmu[v] = vin ? -mu[v] * lam[v] * rv : 0.0;
+        if (!gD) continue;
+        double acc = 0.0;
+        const int o[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+        for (int e = 0; e < 6; e++) {
+            int xa = x + o[e][0], ya = y + o[e][1], za = z + o[e][2];
+            if (xa < 0 || xa > N || ya < 0 || ya > N || za < 0 || za > N) continue;
+            bool jin = is_interior(N, xa, ya, za);
+            if (!vin && !jin) continue;
+            int64_t j = vidx(n, xa, ya, za);
+            double lj = jin ? lam[j] : 0.0, Dj = D[j];
+            double dcdv;
+            if (harmonic) {
+                double sum = Dv + Dj;
+                dcdv = 2.0 * Dj * Dj * Dv / (sum * sum);
+            } else {
+                dcdv = 0.5 * Dv;
+            }
+            acc += dcdv * (lv - lj) * (rv - rho[j]);
+        }
+        gD[v] = -acc * inv_h2;
+    }
+}
+
+}  // namespace dmgs

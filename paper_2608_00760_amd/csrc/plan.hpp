@@ -1,0 +1,82 @@
+// plan.hpp -- the resident level hierarchy of a solver plan.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/dmgs.h"
+#include "grid.hpp"
+
+namespace dmgs {
+
+constexpr int kMaxLevels = 12;
+constexpr int kMaxPartials = 2048;   // blocks of the first reduction stage
+
+struct Level {
+    int N = 0, n = 0;
+    int64_t nv = 0;
+    double h = 1.0, inv_h2 = 1.0;
+    // coefficient hierarchy (float64 on every level; float32 copies in
+    // iterative-refinement plans)
+    double *D64 = nullptr, *mu64 = nullptr;
+    float *D32 = nullptr, *mu32 = nullptr;
+    // iterate, right-hand side and scratch of the cycle on this level
+    double *u64 = nullptr, *q64 = nullptr, *t64 = nullptr;
+    float *u32 = nullptr, *q32 = nullptr, *t32 = nullptr;
+
+    template <class T> Stencil<T> stencil(int harmonic) const {
+        Stencil<T> s;
+        s.half_inv_h2 = (T)(0.5 * inv_h2);
+        s.two_inv_h2 = (T)(2.0 * inv_h2);
+        s.harmonic = harmonic;
+        return s;
+    }
+};
+
+template <class T> struct Typed;
+template <> struct Typed<double> {
+    static double* D(const Level& l) { return l.D64; }
+    static double* mu(const Level& l) { return l.mu64; }
+    static double* u(const Level& l) { return l.u64; }
+    static double* q(const Level& l) { return l.q64; }
+    static double* t(const Level& l) { return l.t64; }
+};
+template <> struct Typed<float> {
+    static float* D(const Level& l) { return l.D32; }
+    static float* mu(const Level& l) { return l.mu32; }
+    static float* u(const Level& l) { return l.u32; }
+    static float* q(const Level& l) { return l.q32; }
+    static float* t(const Level& l) { return l.t32; }
+};
+
+}  // namespace dmgs
+
+namespace dmgs {
+constexpr int kTimerSlots = 512;
+struct TimerRec {
+    int cls;
+    double bytes;
+};
+}  // namespace dmgs
+
+struct dmgs_plan_s {
+    dmgs_options opt;
+    int L = 0;
+    dmgs::Level lev[dmgs::kMaxLevels];
+    double* scratch64 = nullptr;   // finest-level float64 scratch (tangent right-hand side)
+    double* partial = nullptr;     // first-stage reduction partials
+    double* dnorm = nullptr;       // device reduction results (4 slots)
+    double* hnorm = nullptr;       // pinned host mirror of dnorm
+    int* dflag = nullptr;          // device validation flag
+    int* hflag = nullptr;          // pinned host mirror
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    bool coef_set = false;
+    // kernel timing (profiling aid)
+    bool timing = false;
+    hipEvent_t tev[2 * dmgs::kTimerSlots] = {};
+    dmgs::TimerRec trec[dmgs::kTimerSlots];
+    int tpending = 0;
+    int64_t t_count[DMGS_K_COUNT] = {};
+    double t_ms[DMGS_K_COUNT] = {};
+    double t_bytes[DMGS_K_COUNT] = {};
+    size_t bytes = 0;
+    int device = 0;
+};

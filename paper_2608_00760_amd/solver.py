@@ -1,0 +1,200 @@
+"""Python face of the C ABI: a Plan holding the resident level hierarchy.
+
+Tensors are torch float64 (float32 for the float32 diagnostic passes) CUDA
+tensors of shape (N+1, N+1, N+1), C-contiguous, on the plan's device.  Every
+array argument is checked on the host (shape, dtype, device, layout) before
+anything is launched; PyTorch only supplies device memory and the stream.
+"""
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _abi
+
+_PREC = {"fp64": _abi.DMGS_FP64, "fp32-in-fp64": _abi.DMGS_FP32_IN_FP64, "mixed": _abi.DMGS_FP32_IN_FP64}
+_FACE = {"arith": _abi.DMGS_FACE_ARITH, "harmonic": _abi.DMGS_FACE_HARMONIC}
+
+
+@dataclass
+class Options:
+    N: int
+    precision: str = "fp64"          # "fp64" | "fp32-in-fp64"
+    rtol: float = 1e-10
+    max_cycles: int = 200
+    fixed_cycles: int = 0
+    nu_pre: int = 2
+    nu_post: int = 2
+    face_mean: str = "arith"
+    h: float = 1.0
+    bc_value: float = 0.0
+
+    def to_c(self):
+        o = _abi.default_options(self.N)
+        o.precision = _PREC[self.precision]
+        o.rtol = float(self.rtol)
+        o.max_cycles = int(self.max_cycles)
+        o.fixed_cycles = int(self.fixed_cycles)
+        o.nu_pre, o.nu_post = int(self.nu_pre), int(self.nu_post)
+        o.face_mean = _FACE[self.face_mean]
+        o.h, o.bc_value = float(self.h), float(self.bc_value)
+        return o
+
+
+def workspace_bytes(opts: Options) -> int:
+    o = opts.to_c()
+    return int(_abi.lib().dmgs_workspace_bytes(C.byref(o)))
+
+
+def _stream(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    def __init__(self, opts: Options, device=None):
+        self.opts = opts
+        self.N = opts.N
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else torch.device(device).index or 0)
+        self._c = opts.to_c()
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = _abi.lib().dmgs_plan_create(C.byref(self._c), C.byref(self._h))
+        if st != _abi.DMGS_OK:
+            raise _abi.DMGSError(st, "dmgs_plan_create")
+        self.levels = _abi.lib().dmgs_plan_levels(self._h)
+        self.level_N = [_abi.lib().dmgs_plan_level_n(self._h, k) for k in range(self.levels)]
+        self.bytes = workspace_bytes(opts)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _abi.lib().dmgs_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- argument checks ------------------------------------------------------------
+    def _shape(self, k=0):
+        n = self.level_N[k] + 1
+        return (n, n, n)
+
+    def _arr(self, t, name, k=0, dtype=torch.float64, optional=False):
+        if t is None:
+            if optional:
+                return None
+            raise ValueError("%s is required" % name)
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor" % name)
+        if t.dtype != dtype or t.device != self.device or tuple(t.shape) != self._shape(k) or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s tensor of shape %s on %s (got %s %s %s)"
+                             % (name, dtype, self._shape(k), self.device, t.dtype, tuple(t.shape), t.device))
+        return C.c_void_p(t.data_ptr())
+
+    def _empty(self, k=0, dtype=torch.float64):
+        return torch.empty(self._shape(k), dtype=dtype, device=self.device)
+
+    def _call(self, fn, where, *args, info=None, check=True):
+        with torch.cuda.device(self.device):
+            st = fn(self._h, *args)
+        if check and st != _abi.DMGS_OK:
+            raise _abi.DMGSError(st, where, info.as_dict() if info is not None else None)
+        return st
+
+    # ---- solver ---------------------------------------------------------------------
+    def set_coefficients(self, D, mua):
+        self._call(_abi.lib().dmgs_set_coefficients, "dmgs_set_coefficients", self._arr(D, "D"),
+                   self._arr(mua, "mua"), _stream(self.device))
+
+    def set_log_coefficients(self, logD, logmua):
+        self._call(_abi.lib().dmgs_set_log_coefficients, "dmgs_set_log_coefficients", self._arr(logD, "logD"),
+                   self._arr(logmua, "logmua"), _stream(self.device))
+
+    def forward(self, q, out=None, check=True):
+        rho = self._empty() if out is None else out
+        info = _abi.Info()
+        self._call(_abi.lib().dmgs_forward, "dmgs_forward", self._arr(q, "q"), self._arr(rho, "rho"),
+                   C.byref(info), _stream(self.device), info=info, check=check)
+        return rho, info.as_dict()
+
+    def jvp(self, rho, dq=None, dlogD=None, dlogmua=None, out=None, check=True):
+        drho = self._empty() if out is None else out
+        info = _abi.Info()
+        self._call(_abi.lib().dmgs_jvp, "dmgs_jvp", self._arr(rho, "rho"), self._arr(dq, "dq", optional=True),
+                   self._arr(dlogD, "dlogD", optional=True), self._arr(dlogmua, "dlogmua", optional=True),
+                   self._arr(drho, "drho"), C.byref(info), _stream(self.device), info=info, check=check)
+        return drho, info.as_dict()
+
+    def vjp(self, rho, rhobar, coef_grads=True, out=None, check=True):
+        if out is None:
+            qbar = self._empty()
+            gD = self._empty() if coef_grads else None
+            gmu = self._empty() if coef_grads else None
+        else:
+            qbar, gD, gmu = out
+        info = _abi.Info()
+        self._call(_abi.lib().dmgs_vjp, "dmgs_vjp", self._arr(rho, "rho"), self._arr(rhobar, "rhobar"),
+                   self._arr(qbar, "qbar"), self._arr(gD, "logD_bar", optional=True),
+                   self._arr(gmu, "logmua_bar", optional=True), C.byref(info), _stream(self.device),
+                   info=info, check=check)
+        return (qbar, gD, gmu), info.as_dict()
+
+    # ---- kernel timing ----------------------------------------------------------------
+    def timing(self, enable=True):
+        """Enable (and reset) or disable per-class timing of finest-level launches."""
+        self._call(_abi.lib().dmgs_timing_enable, "dmgs_timing_enable", int(bool(enable)))
+
+    def timing_read(self):
+        """{class: {"launches", "ms", "bytes"}} accumulated since timing was enabled."""
+        out = {}
+        for c, name in enumerate(_abi.KERNEL_CLASSES):
+            n, ms, b = C.c_int64(0), C.c_double(0.0), C.c_double(0.0)
+            self._call(_abi.lib().dmgs_timing_read, "dmgs_timing_read", c, C.byref(n), C.byref(ms), C.byref(b))
+            out[name] = {"launches": n.value, "ms": ms.value, "bytes": b.value}
+        return out
+
+    # ---- diagnostic passes (parity tests) -------------------------------------------
+    def debug_apply(self, k, u, fp32=False):
+        dt = torch.float32 if fp32 else torch.float64
+        out = self._empty(k, dt)
+        self._call(_abi.lib().dmgs_debug_apply, "dmgs_debug_apply", int(k), int(fp32), self._arr(u, "u", k, dt),
+                   self._arr(out, "out", k, dt), _stream(self.device))
+        return out
+
+    def debug_level_coefficients(self, k):
+        D, mu = self._empty(k), self._empty(k)
+        self._call(_abi.lib().dmgs_debug_level_coefficients, "dmgs_debug_level_coefficients", int(k),
+                   self._arr(D, "D", k), self._arr(mu, "mua", k), _stream(self.device))
+        return D, mu
+
+    def debug_pre(self, k, u_in, q, order=0, fp32=False):
+        dt = torch.float32 if fp32 else torch.float64
+        u_out, qc = self._empty(k, dt), self._empty(k + 1, dt)
+        self._call(_abi.lib().dmgs_debug_pre, "dmgs_debug_pre", int(k), int(fp32), int(order),
+                   self._arr(u_in, "u_in", k, dt), self._arr(q, "q", k, dt), self._arr(u_out, "u_out", k, dt),
+                   self._arr(qc, "qc", k + 1, dt), _stream(self.device))
+        return u_out, qc
+
+    def debug_post(self, k, u_in, ec, q, order=0, fp32=False):
+        dt = torch.float32 if fp32 else torch.float64
+        u_out = self._empty(k, dt)
+        self._call(_abi.lib().dmgs_debug_post, "dmgs_debug_post", int(k), int(fp32), int(order),
+                   self._arr(u_in, "u_in", k, dt), self._arr(ec, "ec", k + 1, dt), self._arr(q, "q", k, dt),
+                   self._arr(u_out, "u_out", k, dt), _stream(self.device))
+        return u_out
+
+    def debug_coarsest(self, q, fp32=False):
+        k = self.levels - 1
+        dt = torch.float32 if fp32 else torch.float64
+        u = self._empty(k, dt)
+        self._call(_abi.lib().dmgs_debug_coarsest, "dmgs_debug_coarsest", int(fp32), self._arr(q, "q", k, dt),
+                   self._arr(u, "u", k, dt), _stream(self.device))
+        return u
+
+    def debug_cycles(self, q, u, ncycles, order=0):
+        u = u.clone()
+        self._call(_abi.lib().dmgs_debug_cycles, "dmgs_debug_cycles", int(order), int(ncycles),
+                   self._arr(q, "q"), self._arr(u, "u"), _stream(self.device))
+        return u

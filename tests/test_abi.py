@@ -1,0 +1,72 @@
+"""CPU checks of the boundary: the HIP library loads, exports every symbol
+declared in include/dmgs.h, and its pure host logic (defaults, footprint,
+option validation) behaves as documented.  No GPU call is made."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "dmgs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmgs_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_2608_00760_amd import _abi, _build
+    if not os.path.exists(_abi.LIB_PATH):
+        _build.build(force=False)
+    _abi.lib()
+    return _abi
+
+
+def test_every_declared_symbol_is_exported(abi):
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(abi.lib(), n), n
+    assert sorted(abi.SIGNATURES) == names
+
+
+def test_default_options_and_footprint(abi):
+    o = abi.default_options(256)
+    assert tuple(o.n) == (256, 256, 256) and o.nu_pre == 2 and o.nu_post == 2 and o.rtol == 1e-10
+    lib = abi.lib()
+    b64 = lib.dmgs_workspace_bytes(C.byref(o))
+    nv = 257 ** 3
+    assert b64 >= 4 * nv * 8            # D, mu, scratch, defect on the finest level
+    o.precision = abi.DMGS_FP32_IN_FP64
+    b32 = lib.dmgs_workspace_bytes(C.byref(o))
+    assert b32 > b64 - nv * 8
+    for bad in (5, 20, 1, 0, 2048):
+        ob = abi.default_options(bad)
+        assert lib.dmgs_workspace_bytes(C.byref(ob)) == 0, bad
+    ob = abi.default_options(64)
+    ob.n[2] = 32
+    assert lib.dmgs_workspace_bytes(C.byref(ob)) == 0
+    ob = abi.default_options(64)
+    ob.nu_pre = ob.nu_post = 0
+    assert lib.dmgs_workspace_bytes(C.byref(ob)) == 0
+    for good in (2, 3, 6, 96, 192, 512):
+        assert lib.dmgs_workspace_bytes(C.byref(abi.default_options(good))) > 0
+
+
+def test_status_strings(abi):
+    assert abi.status_string(0) == "ok"
+    assert abi.status_string(3) == "not converged"
+
+
+def test_product_path_has_no_oracle_or_fallback():
+    """The package never imports the oracle and has no CPU solve path."""
+    pkg = os.path.join(ROOT, "paper_2608_00760_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.lower() or f == "synth.py", f
+                assert "dmgs_ref" not in text, f

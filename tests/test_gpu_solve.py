@@ -1,0 +1,179 @@
+"""End-to-end parity of forward, push-forward and pull-back with the oracle.
+
+* Fixed-cycle mode (Sec. 2.4, second mode) in float64: the GPU and the oracle
+  apply the same linear map S_n and its transpose, so solutions and all
+  gradients agree to 1e-12 of the largest entry, and the dot-product identity
+  <JVP, w> = <v, VJP> holds to 1e-12 on the GPU alone.
+* Tolerance mode: every GPU solution has relative residual <= 1e-10 as
+  evaluated by the oracle's operator, and the gradients agree with the
+  oracle's (solved to 1e-13) to 1e-8 relative (both float64 and
+  float32-in-float64).
+* Closed form: the 32^3 constant-coefficient workload against the DST-I
+  solution.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, rel_max, say
+
+pytestmark = pytest.mark.gpu
+
+
+def plan_for(D, mu, **kw):
+    from paper_2608_00760_amd.solver import Options, Plan
+    N = D.shape[0] - 1
+    P = Plan(Options(N, **kw))
+    P.set_coefficients(dev(D), dev(mu))
+    return P
+
+
+def rel_residual(H, u, q, bc=0.0):
+    N = H.N
+    r = H.defect(0, u, q)
+    u0 = np.zeros_like(u)
+    u0[[0, -1], :, :] = bc; u0[:, [0, -1], :] = bc; u0[:, :, [0, -1]] = bc
+    return np.linalg.norm(r) / np.linalg.norm(H.defect(0, u0, q))
+
+
+def grf_inputs(N, seed):
+    from paper_2608_00760_amd import synth
+    c = synth.grf_case(N, seed)
+    c.update({k: v for k, v in synth.tangents(N, seed + 100).items() if k != "rhobar"})
+    return c
+
+
+@pytest.mark.parametrize("N,n", [(8, 4), (32, 15), (24, 6), (96, 5), (128, 4)])
+@pytest.mark.parametrize("face_mean", ["arith", "harmonic"])
+def test_fixed_cycles_forward_jvp_vjp(N, n, face_mean):
+    from oracle import ref
+    say("fixed N=%d n=%d %s" % (N, n, face_mean))
+    c = grf_inputs(N, 100 * N)
+    H = ref.Hierarchy(c["D"], c["mua"], face_mean=face_mean)
+    P = plan_for(c["D"], c["mua"], fixed_cycles=n, face_mean=face_mean)
+    rho, info = P.forward(dev(c["q"]))
+    rr, _ = H.forward(c["q"], fixed_cycles=n)
+    assert info["cycles"] == n
+    assert rel_max(host(rho), rr) <= 1e-12
+    drho, _ = P.jvp(rho, dev(c["dq"]), dev(c["dlogD"]), dev(c["dlogmua"]))
+    dr, _ = H.jvp(rr, c["dq"], c["dlogD"], c["dlogmua"], fixed_cycles=n)
+    assert rel_max(host(drho), dr) <= 1e-12
+    (qb, gD, gmu), _ = P.vjp(rho, dev(c["rhobar"]))
+    (rqb, rgD, rgmu), _ = H.vjp(rr, c["rhobar"], fixed_cycles=n)
+    assert rel_max(host(qb), rqb) <= 1e-12
+    assert rel_max(host(gD), rgD) <= 1e-12
+    assert rel_max(host(gmu), rgmu) <= 1e-12
+    # dot-product identity on the GPU alone
+    lhs = float((drho * dev(c["rhobar"])).sum())
+    rhs = float((dev(c["dq"]) * qb).sum() + (dev(c["dlogD"]) * gD).sum() + (dev(c["dlogmua"]) * gmu).sum())
+    assert abs(lhs - rhs) <= 1e-12 * float(drho.norm()) * float(np.linalg.norm(c["rhobar"]))
+
+
+def test_small_constant_workload_closed_form():
+    """32^3, D = 1, mua = 0.1, centred blob; one JVP and one VJP."""
+    from oracle import ref
+    from paper_2608_00760_amd import synth
+    from test_oracle_closed_form import dst_solve
+    say("small constant workload")
+    c = synth.small_constant()
+    H = ref.Hierarchy(c["D"], c["mua"])
+    P = plan_for(c["D"], c["mua"])
+    rho, info = P.forward(dev(c["q"]))
+    u = host(rho)
+    assert info["rel_residual"] <= 1e-10 and rel_residual(H, u, c["q"]) <= 1e-10
+    assert rel_max(u, dst_solve(c["q"], 1.0, 0.1, 1.0)) <= 1e-9
+    rr, _ = H.forward(c["q"], rtol=1e-14, max_cycles=100)
+    drho, _ = P.jvp(rho, dev(c["dq"]), dev(c["dlogD"]), dev(c["dlogmua"]))
+    dr, _ = H.jvp(rr, c["dq"], c["dlogD"], c["dlogmua"], rtol=1e-14, max_cycles=100)
+    assert rel_max(host(drho), dr) <= 1e-8
+    (qb, gD, gmu), vinfo = P.vjp(rho, dev(c["rhobar"]))
+    (rqb, rgD, rgmu), _ = H.vjp(rr, c["rhobar"], rtol=1e-14, max_cycles=100)
+    for g, r in ((qb, rqb), (gD, rgD), (gmu, rgmu)):
+        assert rel_max(host(g), r) <= 1e-8
+    assert rel_max(host(qb), dst_solve(c["rhobar"], 1.0, 0.1, 1.0)) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32-in-fp64"])
+@pytest.mark.parametrize("N", [64, 96, 128])
+def test_tolerance_mode_forward_vjp_against_oracle(precision, N):
+    """Forward + VJP to 1e-10 on GRF coefficients; gradients within 1e-8."""
+    from oracle import ref
+    say("tolerance %s N=%d" % (precision, N))
+    c = grf_inputs(N, 7 * N)
+    H = ref.Hierarchy(c["D"], c["mua"])
+    P = plan_for(c["D"], c["mua"], precision=precision)
+    rho, info = P.forward(dev(c["q"]))
+    u = host(rho)
+    assert info["rel_residual"] <= 1e-10
+    assert rel_residual(H, u, c["q"]) <= 1e-10
+    rr, _ = H.forward(c["q"], rtol=1e-13, max_cycles=200)
+    (qb, gD, gmu), vinfo = P.vjp(rho, dev(c["rhobar"]))
+    lam = host(qb)
+    assert vinfo["rel_residual"] <= 1e-10
+    assert np.linalg.norm(c["rhobar"] - H.apply(0, lam)) / np.linalg.norm(c["rhobar"]) <= 1e-10
+    (rqb, rgD, rgmu), _ = H.vjp(rr, c["rhobar"], rtol=1e-13, max_cycles=200)
+    errs = {"u": rel_max(u, rr), "q": rel_max(lam, rqb), "logD": rel_max(host(gD), rgD),
+            "logmua": rel_max(host(gmu), rgmu)}
+    say("errors vs oracle", {k: "%.2e" % v for k, v in errs.items()}, "cycles", info["cycles"], vinfo["cycles"])
+    assert max(errs.values()) <= 1e-8, errs
+    drho, jinfo = P.jvp(rho, dev(c["dq"]), dev(c["dlogD"]), dev(c["dlogmua"]))
+    dr, _ = H.jvp(rr, c["dq"], c["dlogD"], c["dlogmua"], rtol=1e-13, max_cycles=200)
+    assert rel_max(host(drho), dr) <= 1e-8
+
+
+def test_boundary_value_and_small_grids():
+    from oracle import ref
+    from paper_2608_00760_amd import synth
+    say("boundary value and single-level grids")
+    for N in (2, 3, 6, 12):
+        logD, logmu = synth.log_coefficients(N, N, N + 1)
+        D, mu = np.exp(logD), np.exp(logmu)
+        q = synth.normal(N, 3)
+        H = ref.Hierarchy(D, mu, bc=0.5)
+        rr, _ = H.forward(q, rtol=1e-13)
+        for prec in ("fp64", "fp32-in-fp64"):
+            P = plan_for(D, mu, bc_value=0.5, precision=prec, rtol=1e-12)
+            rho, info = P.forward(dev(q))
+            assert rel_max(host(rho), rr) <= 1e-10, (N, prec, info)
+
+
+def test_error_paths():
+    import torch
+    from paper_2608_00760_amd import _abi, synth
+    from paper_2608_00760_amd.solver import Options, Plan
+    say("error paths")
+    N = 16
+    D = np.ones(synth.shape(N)); mu = np.full(synth.shape(N), 0.1)
+    with pytest.raises(_abi.DMGSError) as e:
+        Plan(Options(20))
+    assert e.value.status == _abi.DMGS_ERR_INVALID
+    P = Plan(Options(N, max_cycles=2, rtol=1e-14))
+    with pytest.raises(_abi.DMGSError):
+        P.forward(dev(synth.normal(N, 1)))            # coefficients not set
+    bad = D.copy(); bad[3, 4, 5] = -1.0
+    with pytest.raises(_abi.DMGSError) as e:
+        P.set_coefficients(dev(bad), dev(mu))
+    assert e.value.status == _abi.DMGS_ERR_INVALID
+    P.set_coefficients(dev(D), dev(mu))
+    rho, info = P.forward(dev(synth.normal(N, 1)), check=False)
+    assert info["status"] == _abi.DMGS_ERR_NOT_CONVERGED and info["cycles"] == 2
+    q = synth.normal(N, 2); q[5, 5, 5] = np.nan
+    rho, info = P.forward(dev(q), check=False)
+    assert info["status"] == _abi.DMGS_ERR_NONFINITE
+    with pytest.raises(ValueError):
+        P.forward(torch.zeros((N, N, N), dtype=torch.float64, device="cuda:0"))
+    zero, info = P.forward(dev(np.zeros(synth.shape(N))))
+    assert info["cycles"] == 0 and float(zero.abs().max()) == 0.0
+
+
+def test_determinism_bitwise():
+    from paper_2608_00760_amd import synth
+    say("determinism")
+    c = grf_inputs(64, 5)
+    for prec in ("fp64", "fp32-in-fp64"):
+        P = plan_for(c["D"], c["mua"], precision=prec)
+        a, _ = P.forward(dev(c["q"]))
+        b, _ = P.forward(dev(c["q"]))
+        assert bool((a == b).all())
+        (ga, _, _), _ = P.vjp(a, dev(c["rhobar"]))
+        (gb, _, _), _ = P.vjp(a, dev(c["rhobar"]))
+        assert bool((ga == gb).all())
