@@ -7,9 +7,12 @@ seeded inputs, on every level of grids that span several tiles and have
 ragged tails.
 
 Tolerances: float64 passes agree to 1e-13 of the largest entry (rounding
-order and fused multiply-adds only).  Float32 passes run on float32-rounded
-inputs and coefficients rounded to float32, so they agree to 2e-5
-(a few float32 roundings per update, over two sweeps).
+order and fused multiply-adds only).  The restricted defect R(q - A u) is a
+difference of terms of size |q| and |A u| that largely cancel after
+smoothing, so its rounding error is measured against max|q| + max|A u|
+rather than against its own size.  Float32 passes run on float32-rounded
+inputs and coefficients rounded to float32, so they agree to 2e-5 on the
+same scales (a few float32 roundings per update, over two sweeps).
 """
 import numpy as np
 import pytest
@@ -39,6 +42,11 @@ def oracle_pre(H, k, u, q, order, nu=2):
         u = H.gs_half(k, first, u, q)
         u = H.gs_half(k, 1 - first, u, q)
     return u, H.restrict(k, H.defect(k, u, q))
+
+
+def defect_scale(H, k, u, q):
+    """Size of the terms whose difference is the defect q - A u."""
+    return np.abs(q).max() + np.abs(H.apply(k, u)).max()
 
 
 def oracle_post(H, k, u, ec, q, order, nu=2):
@@ -87,7 +95,7 @@ def test_pre_and_post_passes_fp64(N, order, face_mean):
         gu, gqc = P.debug_pre(k, dev(u), dev(q), order=order)
         ru, rqc = oracle_pre(H, k, u, q, order)
         assert rel_max(host(gu), ru) <= 1e-13, (k, "pre u")
-        assert rel_max(host(gqc), rqc) <= 1e-13, (k, "pre qc")
+        assert np.abs(host(gqc) - rqc).max() <= 1e-13 * defect_scale(H, k, ru, q), (k, "pre qc")
         gp = P.debug_post(k, dev(u), dev(ec), dev(q), order=order)
         assert rel_max(host(gp), oracle_post(H, k, u, ec, q, order)) <= 1e-13, (k, "post")
 
@@ -107,7 +115,7 @@ def test_pre_and_post_passes_fp32(N, order):
         gu, gqc = P.debug_pre(k, dev(u, torch.float32), dev(q, torch.float32), order=order, fp32=True)
         ru, rqc = oracle_pre(H, k, u, q, order)
         assert rel_max(host(gu), ru) <= 2e-5, (k, "pre u")
-        assert rel_max(host(gqc), rqc) <= 2e-5, (k, "pre qc")
+        assert np.abs(host(gqc) - rqc).max() <= 2e-5 * defect_scale(H, k, ru, q), (k, "pre qc")
         gp = P.debug_post(k, dev(u, torch.float32), dev(ec, torch.float32), dev(q, torch.float32), order=order, fp32=True)
         assert rel_max(host(gp), oracle_post(H, k, u, ec, q, order)) <= 2e-5, (k, "post")
 
