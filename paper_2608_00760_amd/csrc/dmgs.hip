@@ -7,9 +7,13 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
+#include <algorithm>
+#include <utility>
 #include <new>
 
 #include "kernels_basic.hpp"
+#include "kernels_stream.hpp"
 #include "plan.hpp"
 
 using namespace dmgs;
@@ -104,10 +108,10 @@ size_t footprint(const dmgs_options* o) {
     size_t b = 0;
     for (int k = 0; k < s.L; k++) {
         b += 2 * s.nv[k] * sizeof(double);                            // D64, mu64
-        if (ir) b += 5 * s.nv[k] * sizeof(float);                     // D32, mu32, u32, q32, t32
-        else b += (k > 0 ? 3 : 1) * s.nv[k] * sizeof(double);         // (u64, q64), t64
+        if (ir) b += 6 * s.nv[k] * sizeof(float);                     // D32, mu32, w32, u32, q32, t32
+        else b += (k > 0 ? 4 : 2) * s.nv[k] * sizeof(double);         // w64, (u64, q64), t64
     }
-    b += s.nv[0] * sizeof(double);                                    // scratch64
+    b += (ir ? 2 : 1) * s.nv[0] * sizeof(double);                     // scratch64 (+ xalt64)
     b += kMaxPartials * sizeof(double) + 4 * sizeof(double) + sizeof(int);
     return b;
 }
@@ -128,11 +132,12 @@ void free_plan(dmgs_plan P) {
     if (!P) return;
     for (int k = 0; k < P->L; k++) {
         Level& l = P->lev[k];
-        void* ps[] = {l.D64, l.mu64, l.D32, l.mu32, l.u64, l.q64, l.t64, l.u32, l.q32, l.t32};
+        void* ps[] = {l.D64, l.mu64, l.w64, l.D32, l.mu32, l.w32, l.u64, l.q64, l.t64, l.u32, l.q32, l.t32};
         for (void* p : ps)
             if (p) (void)hipFree(p);
     }
     if (P->scratch64) (void)hipFree(P->scratch64);
+    if (P->xalt64) (void)hipFree(P->xalt64);
     if (P->partial) (void)hipFree(P->partial);
     if (P->dnorm) (void)hipFree(P->dnorm);
     if (P->dflag) (void)hipFree(P->dflag);
@@ -194,11 +199,21 @@ int tend(dmgs_plan P, int slot, int cls, double bytes, hipStream_t st) {
     } while (0)
 
 // ---------------------------------------------------------------------------
-// Cycle building blocks (one launch per operation).
+// Cycle building blocks.  Levels with N >= kFuseMin use the fused streaming
+// passes (out of place, ping-pong between the level's two buffers); smaller
+// levels use one launch per operation, in place.
 
 template <class T>
 int fill(T* a, int64_t nv, T val, hipStream_t st) {
     hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(nv)), dim3(kBlock), 0, st, a, nv, val);
+    LAUNCHCHK();
+    return DMGS_OK;
+}
+
+template <class T>
+int set_boundary(T* u, int N, T g, hipStream_t st) {
+    int n = N + 1;
+    hipLaunchKernelGGL(k_set_boundary<T>, dim3(grid_for((int64_t)n * n, 1024), 6), dim3(kBlock), 0, st, u, N, g);
     LAUNCHCHK();
     return DMGS_OK;
 }
@@ -233,25 +248,126 @@ int apply_or_defect(dmgs_plan P, int k, const T* u, const T* q, T* out, int appl
     return DMGS_OK;
 }
 
-// pre pass: nu_pre sweeps in place on u, then qc = R (q - A u).
-template <class T>
-int pre_pass(dmgs_plan P, int k, T* u, const T* q, T* qc, int order, hipStream_t st) {
-    const Level& l = P->lev[k];
-    TRY(sweeps<T>(P, k, u, q, P->opt.nu_pre, order, st));
-    T* r = Typed<T>::t(l);
-    TRY(apply_or_defect<T>(P, k, u, q, r, 0, st));
-    TIMED(P, k, DMGS_K_DEFECT_RESTRICT, (double)(l.nv + P->lev[k + 1].nv) * sizeof(T), st,
-          hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(P->lev[k + 1].nv)), dim3(kBlock), 0, st, (const T*)r, qc, l.N));
+// --- fused pass dispatch -------------------------------------------------------
+
+// chunk of x-planes per workgroup: enough workgroups to fill the chip,
+// but chunks long enough to amortise the wavefront's start-up planes
+int choose_chunk(int interior, int tiles) {
+    int want = 2048;
+    int nch = (want + tiles - 1) / tiles;
+    int chunk = (interior + nch - 1) / nch;
+    if (chunk < 16) chunk = 16;
+    if (chunk > interior) chunk = interior;
+    return chunk;
+}
+
+// Sweep-pass tiles (TY x TZ); the float32 choice is selectable for tuning
+// by DMGS_SWEEP_CFG = 0 (16 x 64), 1 (8 x 64), 2 (16 x 32).
+template <class T, int TY, int TZ, bool HARM>
+int launch_sweep(const SweepArgs<T>& a0, int N, bool zero, hipStream_t st) {
+    SweepArgs<T> a = a0;
+    constexpr int NT = SweepShape<TY, TZ>::NT;
+    a.tiles_y = (N + TY - 1) / TY;
+    a.tiles_z = (N + TZ - 1) / TZ;
+    a.chunk = choose_chunk(N - 1, a.tiles_y * a.tiles_z);
+    a.nchunks = (N - 1 + a.chunk - 1) / a.chunk;
+    int nb = a.tiles_y * a.tiles_z * a.nchunks;
+    if (zero) hipLaunchKernelGGL((k_rb_sweep_col<T, TY, TZ, true, HARM>), dim3(nb), dim3(NT), 0, st, a);
+    else hipLaunchKernelGGL((k_rb_sweep_col<T, TY, TZ, false, HARM>), dim3(nb), dim3(NT), 0, st, a);
+    LAUNCHCHK();
     return DMGS_OK;
 }
 
-// post pass: u += I ec, then nu_post sweeps in place.
+template <class T, bool HARM>
+int launch_sweep_cfg(dmgs_plan P, const SweepArgs<T>& a, int N, bool zero, hipStream_t st) {
+    if constexpr (sizeof(T) == 8) {
+        return launch_sweep<T, 8, 64, HARM>(a, N, zero, st);
+    } else {
+        switch (P->cfg_sweep) {
+            case 1: return launch_sweep<T, 8, 64, HARM>(a, N, zero, st);
+            case 2: return launch_sweep<T, 16, 32, HARM>(a, N, zero, st);
+            default: return launch_sweep<T, 16, 64, HARM>(a, N, zero, st);
+        }
+    }
+}
+
+// One fused sweep pass: u_out = one red-black sweep applied to u_in (or to
+// 0 when zero).
 template <class T>
-int post_pass(dmgs_plan P, int k, T* u, const T* ec, const T* q, int order, hipStream_t st) {
+int smooth_pass(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int order, bool zero, hipStream_t st) {
     const Level& l = P->lev[k];
-    TIMED(P, k, DMGS_K_PROLONG, (double)(2 * l.nv + P->lev[k + 1].nv) * sizeof(T), st,
-          hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, ec, u, l.N));
-    return sweeps<T>(P, k, u, q, P->opt.nu_post, order, st);
+    SweepArgs<T> a;
+    a.u_in = u_in;
+    a.u_out = u_out;
+    a.q = q;
+    a.D = Typed<T>::D(l);
+    a.w = Typed<T>::w(l);
+    a.N = l.N;
+    a.order = order;
+    a.st = l.stencil<T>(harmonic(P));
+    // algorithmic bytes: read u (unless zero), q, D, w, write u
+    double words = zero ? 4.0 : 5.0;
+    int slot;
+    TRY(tbeg(P, k, st, &slot));
+    if (harmonic(P)) TRY((launch_sweep_cfg<T, true>(P, a, l.N, zero, st)));
+    else TRY((launch_sweep_cfg<T, false>(P, a, l.N, zero, st)));
+    TRY(tend(P, slot, DMGS_K_SMOOTH, words * l.nv * sizeof(T), st));
+    return DMGS_OK;
+}
+
+template <class T, int TYC, int TZC, bool HARM>
+int launch_restrict(const RestrictArgs<T>& a0, int Nc, hipStream_t st) {
+    RestrictArgs<T> a = a0;
+    constexpr int NT = RestrictShape<TYC, TZC>::NT;
+    a.tiles_y = (Nc - 1 + TYC - 1) / TYC;
+    a.tiles_z = (Nc - 1 + TZC - 1) / TZC;
+    a.chunk = std::max(4, choose_chunk(Nc - 1, a.tiles_y * a.tiles_z) / 2);
+    if (a.chunk > Nc - 1) a.chunk = Nc - 1;
+    a.nchunks = (Nc - 1 + a.chunk - 1) / a.chunk;
+    int nb = a.tiles_y * a.tiles_z * a.nchunks;
+    hipLaunchKernelGGL((k_defect_restrict_col<T, TYC, TZC, HARM>), dim3(nb), dim3(NT), 0, st, a);
+    LAUNCHCHK();
+    return DMGS_OK;
+}
+
+template <class T>
+int defect_restrict(dmgs_plan P, int k, const T* u, const T* q, T* qc, hipStream_t st) {
+    const Level& l = P->lev[k];
+    const Level& c = P->lev[k + 1];
+    RestrictArgs<T> a;
+    a.u = u;
+    a.q = q;
+    a.D = Typed<T>::D(l);
+    a.mu = Typed<T>::mu(l);
+    a.qc = qc;
+    a.N = l.N;
+    a.st = l.stencil<T>(harmonic(P));
+    constexpr int TYC = 8, TZC = sizeof(T) == 4 ? 32 : 16;
+    int slot;
+    TRY(tbeg(P, k, st, &slot));
+    if (harmonic(P)) TRY((launch_restrict<T, TYC, TZC, true>(a, c.N, st)));
+    else TRY((launch_restrict<T, TYC, TZC, false>(a, c.N, st)));
+    TRY(tend(P, slot, DMGS_K_DEFECT_RESTRICT, (4.0 * l.nv + c.nv) * sizeof(T), st));
+    return DMGS_OK;
+}
+
+// Smoothing phase of `nsweeps` red-black sweeps on level k starting from
+// *cur (zero: from 0; ec: add I ec first, in place).  Result left in *cur,
+// which swaps between the level's two buffers.
+template <class T>
+int smooth_phase(dmgs_plan P, int k, T** cur, T** other, const T* q, int nsweeps, int order, bool zero, const T* ec,
+                 hipStream_t st) {
+    const Level& l = P->lev[k];
+    if (ec) {
+        TIMED(P, k, DMGS_K_PROLONG, (double)(2 * l.nv + P->lev[k + 1].nv) * sizeof(T), st,
+              hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, ec, *cur, l.N));
+    }
+    if (nsweeps == 0 && zero) TRY(fill<T>(*cur, l.nv, T(0), st));
+    for (int i = 0; i < nsweeps; i++) {
+        TRY(smooth_pass<T>(P, k, *cur, *other, q, order, i == 0 && zero, st));
+        std::swap(*cur, *other);
+    }
+    return DMGS_OK;
 }
 
 template <class T>
@@ -263,41 +379,101 @@ int coarsest(dmgs_plan P, const T* q, T* u, hipStream_t st) {
     return DMGS_OK;
 }
 
-// One V-cycle on level k: u[k] updated in place with right-hand side q[k];
-// coarser levels use the plan's arrays of type T (start-from-zero
-// corrections).
-template <class T>
-int vcycle(dmgs_plan P, int k, T* u, const T* q, int order, hipStream_t st) {
-    if (k == P->L - 1) return coarsest<T>(P, q, u, st);
-    const Level& c = P->lev[k + 1];
-    T* uc = Typed<T>::u(c);
-    T* qc = Typed<T>::q(c);
-    TRY(pre_pass<T>(P, k, u, q, qc, order, st));
-    TRY(fill<T>(uc, c.nv, T(0), st));
-    TRY(vcycle<T>(P, k + 1, uc, qc, order, st));
-    return post_pass<T>(P, k, u, uc, q, order, st);
-}
+bool fused_level(dmgs_plan P, int k) { return P->lev[k].N >= P->cfg_fuse_min && k < P->L - 1; }
 
-// Squared residual norm of level 0 (float64) into dnorm[slot]; u == nullptr
-// gives ||q||^2.
-int resid_sq64(dmgs_plan P, const double* u, const double* q, int slot, hipStream_t st) {
-    const Level& l = P->lev[0];
-    unsigned nb = grid_for(l.nv, kMaxPartials);
-    TIMED(P, 0, DMGS_K_RESIDUAL, 4.0 * l.nv * sizeof(double), st,
-          hipLaunchKernelGGL(k_resid_sq<double>, dim3(nb), dim3(kBlock), 0, st, u, q, (const double*)l.D64,
-                             (const double*)l.mu64, l.N, l.stencil<double>(harmonic(P)), P->partial));
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, P->dnorm, slot);
+// Pre-smoothing pass on level k: nu_pre sweeps from *cur (or from 0), then
+// qc = R (q - A u).  Simple levels work in place.
+template <class T>
+int pre_pass(dmgs_plan P, int k, T** cur, T** other, const T* q, T* qc, int order, bool zero, hipStream_t st) {
+    const Level& l = P->lev[k];
+    if (fused_level(P, k)) {
+        TRY(smooth_phase<T>(P, k, cur, other, q, P->opt.nu_pre, order, zero, (const T*)nullptr, st));
+        return defect_restrict<T>(P, k, *cur, q, qc, st);
+    }
+    if (zero) TRY(fill<T>(*cur, l.nv, T(0), st));
+    TRY(sweeps<T>(P, k, *cur, q, P->opt.nu_pre, order, st));
+    T* r = *other;   // scratch for the defect
+    TRY(apply_or_defect<T>(P, k, *cur, q, r, 0, st));
+    hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(P->lev[k + 1].nv)), dim3(kBlock), 0, st, (const T*)r, qc, l.N);
     LAUNCHCHK();
+    // the simple path used the other buffer as scratch: restore its boundary
     return DMGS_OK;
 }
 
-// Iterative-refinement residual: level-0 q32 = float(b - A x), ||.||^2 into dnorm[slot].
-int resid_cast(dmgs_plan P, const double* x, const double* b, int slot, hipStream_t st) {
+// Post-smoothing pass on level k: u = *cur + I ec, then nu_post sweeps.
+template <class T>
+int post_pass(dmgs_plan P, int k, T** cur, T** other, const T* ec, const T* q, int order, hipStream_t st) {
+    const Level& l = P->lev[k];
+    if (fused_level(P, k)) return smooth_phase<T>(P, k, cur, other, q, P->opt.nu_post, order, false, ec, st);
+    TIMED(P, k, DMGS_K_PROLONG, (double)(2 * l.nv + P->lev[k + 1].nv) * sizeof(T), st,
+          hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, ec, *cur, l.N));
+    return sweeps<T>(P, k, *cur, q, P->opt.nu_post, order, st);
+}
+
+// One V-cycle on level k with right-hand side q, iterate in *cur (the
+// level's other buffer is *other).  zero: the iterate starts from 0 (coarse
+// corrections, refinement corrections).  On return *cur holds the result.
+template <class T>
+int vcycle(dmgs_plan P, int k, T** cur, T** other, const T* q, int order, bool zero, hipStream_t st) {
+    if (k == P->L - 1) {
+        if (zero) TRY(fill<T>(*cur, P->lev[k].nv, T(0), st));
+        return coarsest<T>(P, q, *cur, st);
+    }
+    const Level& c = P->lev[k + 1];
+    T* qc = Typed<T>::q(c);
+    TRY(pre_pass<T>(P, k, cur, other, q, qc, order, zero, st));
+    T* ccur = Typed<T>::u(c);
+    T* coth = Typed<T>::t(c);
+    TRY(vcycle<T>(P, k + 1, &ccur, &coth, qc, order, true, st));
+    return post_pass<T>(P, k, cur, other, ccur, q, order, st);
+}
+
+// ||b - A x||^2 into dnorm[slot] with the fused float64 kernel; with e, also
+// x_out = x + e and r32 = float(b - A x_out).
+template <bool HAS_E, bool HARM>
+void launch_ir(const IrArgs& a0, int N, hipStream_t st, unsigned* nb_out) {
+    constexpr int TY = 16, TZ = 64;
+    IrArgs a = a0;
+    a.tiles_y = (N + TY - 1) / TY;
+    a.tiles_z = (N + TZ - 1) / TZ;
+    a.chunk = choose_chunk(N - 1, a.tiles_y * a.tiles_z);
+    a.nchunks = (N - 1 + a.chunk - 1) / a.chunk;
+    while (a.tiles_y * a.tiles_z * a.nchunks > kMaxPartials) {
+        a.chunk *= 2;
+        a.nchunks = (N - 1 + a.chunk - 1) / a.chunk;
+    }
+    unsigned nb = (unsigned)(a.tiles_y * a.tiles_z * a.nchunks);
+    hipLaunchKernelGGL((k_ir_residual_col<TY, TZ, HAS_E, HARM>), dim3(nb), dim3(IrShape<TY, TZ>::NT), 0, st, a);
+    *nb_out = nb;
+}
+
+int ir_step(dmgs_plan P, const double* x, const float* e, double* x_out, const double* b, float* r32, int slot,
+            hipStream_t st) {
     const Level& l = P->lev[0];
-    unsigned nb = grid_for(l.nv, kMaxPartials);
-    TIMED(P, 0, DMGS_K_RESIDUAL, 36.0 * l.nv, st,
-          hipLaunchKernelGGL(k_resid_cast, dim3(nb), dim3(kBlock), 0, st, x, b, (const double*)l.D64, (const double*)l.mu64,
-                             l.N, l.stencil<double>(harmonic(P)), l.q32, P->partial));
+    IrArgs a;
+    a.x = x;
+    a.e = e;
+    a.x_out = x_out;
+    a.b = b;
+    a.D = l.D64;
+    a.mu = l.mu64;
+    a.r32 = r32;
+    a.partial = P->partial;
+    a.N = l.N;
+    a.st = l.stencil<double>(harmonic(P));
+    double bytes = 32.0 * l.nv + (e ? 4.0 * l.nv : 0.0) + (x_out ? 8.0 * l.nv : 0.0) + (r32 ? 4.0 * l.nv : 0.0);
+    unsigned nb = 0;
+    int tslot;
+    TRY(tbeg(P, 0, st, &tslot));
+    if (e) {
+        if (harmonic(P)) launch_ir<true, true>(a, l.N, st, &nb);
+        else launch_ir<true, false>(a, l.N, st, &nb);
+    } else {
+        if (harmonic(P)) launch_ir<false, true>(a, l.N, st, &nb);
+        else launch_ir<false, false>(a, l.N, st, &nb);
+    }
+    LAUNCHCHK();
+    TRY(tend(P, tslot, DMGS_K_RESIDUAL, bytes, st));
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, P->dnorm, slot);
     LAUNCHCHK();
     return DMGS_OK;
@@ -321,7 +497,10 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
     int cycles = 0, status = DMGS_OK;
     double r0 = 0.0, rel = 0.0;
     if (!is_ir(P)) {
-        TRY(resid_sq64(P, x, b, 0, st));
+        double* cur = x;
+        double* oth = l0.t64;
+        TRY(set_boundary<double>(oth, l0.N, bc, st));
+        TRY(ir_step(P, cur, nullptr, nullptr, b, nullptr, 0, st));
         if (!fixed) {
             TRY(read_norms(P, st));
             r0 = std::sqrt(P->hnorm[0]);
@@ -329,28 +508,31 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
             if (r0 == 0.0) goto done;
         }
         for (cycles = 1;; cycles++) {
-            TRY(vcycle<double>(P, 0, x, b, order, st));
+            TRY(vcycle<double>(P, 0, &cur, &oth, b, order, false, st));
             if (fixed) {
                 if (cycles == o.fixed_cycles) break;
                 continue;
             }
-            TRY(resid_sq64(P, x, b, 1, st));
+            TRY(ir_step(P, cur, nullptr, nullptr, b, nullptr, 1, st));
             TRY(read_norms(P, st));
             rel = std::sqrt(P->hnorm[1]) / r0;
             if (!std::isfinite(rel)) { set_error("non-finite residual after %d cycles", cycles); status = DMGS_ERR_NONFINITE; break; }
             if (rel <= o.rtol) break;
             if (cycles >= o.max_cycles) { set_error("not converged after %d cycles (rel %.3e)", cycles, rel); status = DMGS_ERR_NOT_CONVERGED; break; }
         }
+        if (cur != x) HIPCHK(hipMemcpyAsync(x, cur, l0.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
         if (fixed && info) {
-            TRY(resid_sq64(P, x, b, 1, st));
+            TRY(ir_step(P, x, nullptr, nullptr, b, nullptr, 1, st));
             TRY(read_norms(P, st));
             r0 = std::sqrt(P->hnorm[0]);
             rel = std::sqrt(P->hnorm[1]) / (r0 > 0.0 ? r0 : 1.0);
         }
     } else {
-        float* e = l0.u32;
+        double* xc = x;
+        double* xo = P->xalt64;
+        TRY(set_boundary<double>(xo, l0.N, bc, st));
+        TRY(ir_step(P, xc, nullptr, nullptr, b, l0.q32, 0, st));
         for (cycles = 0;; cycles++) {
-            TRY(resid_cast(P, x, b, cycles == 0 ? 0 : 1, st));
             if (!fixed) {
                 TRY(read_norms(P, st));
                 if (cycles == 0) {
@@ -367,11 +549,13 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
             } else if (cycles == o.fixed_cycles) {
                 break;
             }
-            TRY(fill<float>(e, l0.nv, 0.0f, st));
-            TRY(vcycle<float>(P, 0, e, l0.q32, order, st));
-            TIMED(P, 0, DMGS_K_UPDATE, 20.0 * l0.nv, st,
-                  hipLaunchKernelGGL(k_add_correction, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, x, (const float*)e, l0.nv));
+            float* e = l0.u32;
+            float* eo = l0.t32;
+            TRY(vcycle<float>(P, 0, &e, &eo, l0.q32, order, true, st));
+            TRY(ir_step(P, xc, e, xo, b, l0.q32, 1, st));
+            std::swap(xc, xo);
         }
+        if (xc != x) HIPCHK(hipMemcpyAsync(x, xc, l0.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
         if (fixed && info) {
             TRY(read_norms(P, st));
             r0 = std::sqrt(P->hnorm[0]);
@@ -433,12 +617,20 @@ int build_hierarchy(dmgs_plan P, hipStream_t st) {
         hipLaunchKernelGGL(k_coarsen_coef, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)f.mu64, c.mu64, f.N);
         LAUNCHCHK();
     }
-    if (is_ir(P)) {
-        for (int k = 0; k < P->L; k++) {
-            Level& l = P->lev[k];
+    for (int k = 0; k < P->L; k++) {
+        Level& l = P->lev[k];
+        dim3 g(1, l.n, l.n);
+        if (is_ir(P)) {
             hipLaunchKernelGGL(k_cast_f32, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, (const double*)l.D64, l.D32, l.nv);
             LAUNCHCHK();
             hipLaunchKernelGGL(k_cast_f32, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, (const double*)l.mu64, l.mu32, l.nv);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_inv_diag<float>, g, dim3(kBlock), 0, st, (const double*)l.D64, (const double*)l.mu64, l.N,
+                               l.stencil<double>(harmonic(P)), l.w32);
+            LAUNCHCHK();
+        } else {
+            hipLaunchKernelGGL(k_inv_diag<double>, g, dim3(kBlock), 0, st, (const double*)l.D64, (const double*)l.mu64,
+                               l.N, l.stencil<double>(harmonic(P)), l.w64);
             LAUNCHCHK();
         }
     }
@@ -454,16 +646,38 @@ int debug_check(dmgs_plan P, int k, int fp32, bool need_coarse) {
     return DMGS_OK;
 }
 
+// Scratch of level k with the element type T (float64 plans: t64;
+// refinement plans: t32).
+template <class T>
+T* level_scratch(dmgs_plan P, int k) { return Typed<T>::t(P->lev[k]); }
+
 template <class T>
 int debug_pre_t(dmgs_plan P, int k, int order, const T* u_in, const T* q, T* u_out, T* qc, hipStream_t st) {
-    HIPCHK(hipMemcpyAsync(u_out, u_in, P->lev[k].nv * sizeof(T), hipMemcpyDeviceToDevice, st));
-    return pre_pass<T>(P, k, u_out, q, qc, order, st);
+    const Level& l = P->lev[k];
+    T* scratch = level_scratch<T>(P, k);
+    if (!scratch) { set_error("no scratch of this type on level %d", k); return DMGS_ERR_INVALID; }
+    HIPCHK(hipMemcpyAsync(u_out, u_in, l.nv * sizeof(T), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(scratch, u_in, l.nv * sizeof(T), hipMemcpyDeviceToDevice, st));
+    TRY(fill<T>(qc, P->lev[k + 1].nv, T(0), st));   // coarse boundary entries are 0
+    T* cur = u_out;
+    T* oth = scratch;
+    TRY(pre_pass<T>(P, k, &cur, &oth, q, qc, order, false, st));
+    if (cur != u_out) HIPCHK(hipMemcpyAsync(u_out, cur, l.nv * sizeof(T), hipMemcpyDeviceToDevice, st));
+    return DMGS_OK;
 }
 
 template <class T>
 int debug_post_t(dmgs_plan P, int k, int order, const T* u_in, const T* ec, const T* q, T* u_out, hipStream_t st) {
-    HIPCHK(hipMemcpyAsync(u_out, u_in, P->lev[k].nv * sizeof(T), hipMemcpyDeviceToDevice, st));
-    return post_pass<T>(P, k, u_out, ec, q, order, st);
+    const Level& l = P->lev[k];
+    T* scratch = level_scratch<T>(P, k);
+    if (!scratch) { set_error("no scratch of this type on level %d", k); return DMGS_ERR_INVALID; }
+    HIPCHK(hipMemcpyAsync(u_out, u_in, l.nv * sizeof(T), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(scratch, u_in, l.nv * sizeof(T), hipMemcpyDeviceToDevice, st));
+    T* cur = u_out;
+    T* oth = scratch;
+    TRY(post_pass<T>(P, k, &cur, &oth, ec, q, order, st));
+    if (cur != u_out) HIPCHK(hipMemcpyAsync(u_out, cur, l.nv * sizeof(T), hipMemcpyDeviceToDevice, st));
+    return DMGS_OK;
 }
 
 }  // namespace
@@ -520,16 +734,19 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
         if (ir) {
             if (st == DMGS_OK) st = dalloc(P, &l.D32, l.nv);
             if (st == DMGS_OK) st = dalloc(P, &l.mu32, l.nv);
+            if (st == DMGS_OK) st = dalloc(P, &l.w32, l.nv);
             if (st == DMGS_OK) st = dalloc(P, &l.u32, l.nv);
             if (st == DMGS_OK) st = dalloc(P, &l.q32, l.nv);
             if (st == DMGS_OK) st = dalloc(P, &l.t32, l.nv);
         } else {
+            if (st == DMGS_OK) st = dalloc(P, &l.w64, l.nv);
             if (k > 0 && st == DMGS_OK) st = dalloc(P, &l.u64, l.nv);
             if (k > 0 && st == DMGS_OK) st = dalloc(P, &l.q64, l.nv);
             if (st == DMGS_OK) st = dalloc(P, &l.t64, l.nv);
         }
     }
     if (st == DMGS_OK) st = dalloc(P, &P->scratch64, P->lev[0].nv);
+    if (ir && st == DMGS_OK) st = dalloc(P, &P->xalt64, P->lev[0].nv);
     if (st == DMGS_OK) st = dalloc(P, &P->partial, kMaxPartials);
     if (st == DMGS_OK) st = dalloc(P, &P->dnorm, 4);
     if (st == DMGS_OK) st = dalloc(P, &P->dflag, 1);
@@ -545,6 +762,19 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
         set_error("hipEventCreate failed");
         st = DMGS_ERR_HIP;
     }
+    // every work buffer starts at 0: the passes never write boundary layers,
+    // and coarse corrections have homogeneous boundaries
+    for (int k = 0; k < P->L && st == DMGS_OK; k++) {
+        Level& l = P->lev[k];
+        void* ps[] = {l.u64, l.q64, l.t64, l.u32, l.q32, l.t32};
+        size_t sz[] = {8, 8, 8, 4, 4, 4};
+        for (int j = 0; j < 6 && st == DMGS_OK; j++)
+            if (ps[j] && hipMemset(ps[j], 0, l.nv * sz[j]) != hipSuccess) { set_error("hipMemset failed"); st = DMGS_ERR_HIP; }
+    }
+    P->cfg_sweep = 0;
+    P->cfg_fuse_min = 32;
+    if (const char* e = std::getenv("DMGS_SWEEP_CFG")) P->cfg_sweep = std::min(2, std::max(0, std::atoi(e)));
+    if (const char* e = std::getenv("DMGS_FUSE_MIN")) P->cfg_fuse_min = std::max(8, std::atoi(e));
     if (st != DMGS_OK) {
         free_plan(P);
         return st;
@@ -698,7 +928,6 @@ int dmgs_debug_pre(dmgs_plan P, int k, int fp32, int order, const void* u_in, co
     TRY(debug_check(P, k, fp32, true));
     hipStream_t st = (hipStream_t)stream;
     if (fp32) return debug_pre_t<float>(P, k, order, (const float*)u_in, (const float*)q, (float*)u_out, (float*)qc, st);
-    if (!P->lev[k].t64) { set_error("no float64 scratch"); return DMGS_ERR_INVALID; }
     return debug_pre_t<double>(P, k, order, (const double*)u_in, (const double*)q, (double*)u_out, (double*)qc, st);
 }
 
@@ -726,7 +955,12 @@ int dmgs_debug_cycles(dmgs_plan P, int order, int ncycles, const double* q, doub
     TRY(debug_check(P, 0, 0, false));
     if (is_ir(P)) { set_error("dmgs_debug_cycles needs a DMGS_FP64 plan"); return DMGS_ERR_INVALID; }
     hipStream_t st = (hipStream_t)stream;
-    for (int c = 0; c < ncycles; c++) TRY(vcycle<double>(P, 0, u, q, order, st));
+    const Level& l0 = P->lev[0];
+    HIPCHK(hipMemcpyAsync(l0.t64, u, l0.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+    double* cur = u;
+    double* oth = l0.t64;
+    for (int c = 0; c < ncycles; c++) TRY(vcycle<double>(P, 0, &cur, &oth, q, order, false, st));
+    if (cur != u) HIPCHK(hipMemcpyAsync(u, cur, l0.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
     return DMGS_OK;
 }
 

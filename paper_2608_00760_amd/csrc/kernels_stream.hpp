@@ -1,0 +1,554 @@
+// kernels_stream.hpp -- streaming kernels for the large levels.
+//
+// All kernels march along x (the slowest axis) over a chunk of planes; each
+// workgroup owns a (y, z) tile and each thread a pair of vertices (y, z),
+// (y, z+1) of a column, z even.  A column's values on the few planes around
+// the march front live in registers (a ring of named planes, so nothing
+// moves between registers and loads stay in flight for several steps); only
+// in-plane neighbours go through LDS.  Memory operations are buffer
+// instructions with per-plane resources: loads outside the grid return 0 and
+// stores outside the tile are dropped, so there are no branches around
+// memory operations.
+//
+//  k_rb_sweep_col      one red-black Gauss-Seidel sweep, out of place.
+//  k_defect_restrict_col  r = q - A u and full-weighting restriction.
+//  k_ir_residual_col   float64 refinement step: x_out = x + e,
+//                      r32 = float(b - A x_out), ||b - A x_out||^2.
+#pragma once
+#include <type_traits>
+
+#include "grid.hpp"
+
+namespace dmgs {
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of tiles so neighbouring tiles share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+    const int kXcd = 8;
+    if (nblocks % kXcd) return b;
+    return (b % kXcd) * (nblocks / kXcd) + b / kXcd;
+}
+
+// Barrier that waits only for this wave's LDS operations (not for global
+// loads still in flight, which __syncthreads() would drain).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Buffer resources: loads at offsets outside [0, num_records) return 0 and
+// stores there are dropped.  One resource per plane keeps offsets within 32
+// bits for any grid.
+constexpr int kOob = 0x7ffffff0;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, int64_t plane_bytes, int p, bool valid) {
+    const char* b = reinterpret_cast<const char*>(base) + (valid ? (int64_t)p * plane_bytes : 0);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(b), 0, valid ? (int)plane_bytes : 0, 0x00020000);
+}
+
+template <class T> __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int off);
+template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <class T> __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, int off);
+template <> __device__ __forceinline__ void buf_store<float>(float v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+template <> __device__ __forceinline__ void buf_store<double>(double v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, off,
+                                          0, 0);
+}
+
+// Face coefficient with the face mean fixed at compile time.
+template <bool HARM, class T>
+__device__ __forceinline__ T face(T Da, T Db, const Stencil<T>& s) {
+    if (HARM) return (Da * Db) / (Da + Db) * s.two_inv_h2;
+    return (Da + Db) * s.half_inv_h2;
+}
+
+// ---------------------------------------------------------------------------
+// Red-black sweep.
+//
+// At march step s the first colour is updated on plane s (tile plus a ring
+// of 1, recomputed by neighbouring tiles) and the second colour on plane s-1
+// (tile), whose first-colour neighbours are then final.  Plane s is
+// published to a 3-slot LDS ring at the start of the step; the first stage
+// writes its updates into that slot and the second stage reads the slot of
+// plane s-1, so one barrier per step suffices.  Every pair holds one vertex
+// of each colour on every plane; threads are laid out so that each wave
+// covers rows of one parity, which makes the colour's position in the pair
+// uniform across the wave.  The update uses the precomputed inverse
+// diagonal w = 1 / (sum_j c_ij + mua_i).
+
+template <class T>
+struct SweepArgs {
+    const T* u_in;   // iterate before the sweep (ignored when starting from zero)
+    T* u_out;        // iterate after the sweep (tile interiors written)
+    const T* q;
+    const T* D;
+    const T* w;      // inverse diagonal
+    int N;
+    int order;       // colour of the first stage: 0 red, 1 black
+    int tiles_y, tiles_z, chunk, nchunks;
+    Stencil<T> st;
+};
+
+template <class T>
+struct SweepPlane {
+    T u0, u1, D0, D1, q0, q1, w0, w1;
+};
+
+template <int TY, int TZ>
+struct SweepShape {
+    static constexpr int NP = TZ / 2 + 2, RY = TY + 4, RZ = 2 * NP, RA = RY * RZ;
+    static constexpr int ROWS_HALF = RY / 2;
+    static constexpr int HALF = (ROWS_HALF * NP + 63) / 64 * 64;
+    static constexpr int NT = 2 * HALF;
+    static_assert(TY % 2 == 0 && TZ % 2 == 0, "even tile");
+};
+
+template <class T, int TY, int TZ, bool ZERO_INIT, bool HARM>
+__global__ __launch_bounds__((SweepShape<TY, TZ>::NT)) void k_rb_sweep_col(SweepArgs<T> a) {
+    using Sh = SweepShape<TY, TZ>;
+    constexpr int NP = Sh::NP, RY = Sh::RY, RZ = Sh::RZ, RA = Sh::RA, HALF = Sh::HALF;
+    __shared__ T sU[3][RA];
+    __shared__ T sD[3][RA];
+    const int N = a.N, n = N + 1;
+    const int64_t sx = (int64_t)n * n;
+    const int64_t plane_bytes = sx * (int64_t)sizeof(T);
+    const int tid = threadIdx.x;
+    const int hp = tid >= HALF ? 1 : 0;                 // row parity of this wave
+    const int th = tid - hp * HALF;
+    const bool act = th < Sh::ROWS_HALF * NP;
+    const int ly = act ? 2 * (th / NP) + hp : hp, pz = act ? th % NP : 0;
+    const int nb = a.tiles_y * a.tiles_z * a.nchunks;
+    const int b = xcd_tile(blockIdx.x, nb);
+    const int bz = b % a.tiles_z, by = (b / a.tiles_z) % a.tiles_y, bx = b / (a.tiles_z * a.tiles_y);
+    const int y0 = by * TY, z0 = bz * TZ;
+    const int y = y0 - 2 + ly, zl = z0 - 2 + 2 * pz;
+    const int xa = 1 + bx * a.chunk, xb = min(N, xa + a.chunk);   // output planes [xa, xb)
+    const int e0 = ly * RZ + 2 * pz;
+    const bool yin = act && y >= 0 && y <= N;
+    const bool zin0 = zl >= 0 && zl <= N, zin1 = zl + 1 <= N;
+    const int off0 = (yin && zin0) ? (int)(((int64_t)y * n + zl) * sizeof(T)) : kOob;
+    const int off1 = (yin && zin1) ? (int)(((int64_t)y * n + zl + 1) * sizeof(T)) : kOob;
+    const bool y_int = y >= 1 && y <= N - 1;
+    const bool ring1 = act && y_int && ly >= 1 && ly <= RY - 2;
+    const bool tile = act && y_int && ly >= 2 && ly < 2 + TY;
+    auto z_ok = [&](int z, int ring) { return z >= max(1, z0 - ring) && z <= min(N - 1, z0 + TZ - 1 + ring); };
+    const int p_lo = max(0, xa - 2), p_hi = min(N, xb + 1);
+    const int soff0 = (tile && z_ok(zl, 0)) ? off0 : kOob;
+    const int soff1 = (tile && z_ok(zl + 1, 0)) ? off1 : kOob;
+    // the two vertices of the pair: which may be updated by each stage
+    const bool r1_0 = ring1 && z_ok(zl, 1), r1_1 = ring1 && z_ok(zl + 1, 1);
+    const bool t0_0 = tile && z_ok(zl, 0), t0_1 = tile && z_ok(zl + 1, 0);
+    // colour parity of the wave: element of the first colour on plane s is
+    // (s + hp + order) & 1 (y0 - 2 is even)
+    const int wpar = __builtin_amdgcn_readfirstlane(hp + a.order);
+
+    auto load = [&](int p, SweepPlane<T>& P) {
+        const bool pv = p >= p_lo && p <= p_hi;
+        const auto rD = plane_rsrc(a.D, plane_bytes, p, pv);
+        const auto rQ = plane_rsrc(a.q, plane_bytes, p, pv);
+        const auto rW = plane_rsrc(a.w, plane_bytes, p, pv);
+        if (ZERO_INIT) {
+            P.u0 = P.u1 = T(0);
+        } else {
+            const auto rU = plane_rsrc(a.u_in, plane_bytes, p, pv);
+            P.u0 = buf_load<T>(rU, off0);
+            P.u1 = buf_load<T>(rU, off1);
+        }
+        P.D0 = buf_load<T>(rD, off0); P.D1 = buf_load<T>(rD, off1);
+        P.q0 = buf_load<T>(rQ, off0); P.q1 = buf_load<T>(rQ, off1);
+        P.w0 = buf_load<T>(rW, off0); P.w1 = buf_load<T>(rW, off1);
+    };
+
+    // Gauss-Seidel update of element O of the pair on a plane:
+    // v = w (q + sum_j c_ij u_j); in-plane neighbours from LDS slot (U, Dl),
+    // x-neighbours from the planes below (Pb) and above (Pa).
+    auto update = [&](auto Oc, const T* U, const T* Dl, const SweepPlane<T>& Pb, const SweepPlane<T>& P,
+                      const SweepPlane<T>& Pa) -> T {
+        constexpr int O = decltype(Oc)::value;
+        const int e = e0 + O;
+        const T Di = O ? P.D1 : P.D0;
+        const T uzl = O ? P.u0 : U[e - 1], uzr = O ? U[e + 1] : P.u1;
+        const T Dzl = O ? P.D0 : Dl[e - 1], Dzr = O ? Dl[e + 1] : P.D1;
+        const T cxm = face<HARM>(Di, O ? Pb.D1 : Pb.D0, a.st), cxp = face<HARM>(Di, O ? Pa.D1 : Pa.D0, a.st);
+        const T cym = face<HARM>(Di, Dl[e - RZ], a.st), cyp = face<HARM>(Di, Dl[e + RZ], a.st);
+        const T czl = face<HARM>(Di, Dzl, a.st), czr = face<HARM>(Di, Dzr, a.st);
+        const T num = (O ? P.q1 : P.q0) + cxm * (O ? Pb.u1 : Pb.u0) + cxp * (O ? Pa.u1 : Pa.u0) + cym * U[e - RZ] +
+                      cyp * U[e + RZ] + czl * uzl + czr * uzr;
+        return num * (O ? P.w1 : P.w0);
+    };
+
+    auto step = [&](int s, SweepPlane<T>& Pm2, SweepPlane<T>& Pm1, SweepPlane<T>& P0, SweepPlane<T>& Pp1) {
+        const int sl = (s + 3) % 3, slm = (s + 2) % 3;
+        T* U = sU[sl];
+        T* Dl = sD[sl];
+        if (act) { U[e0] = P0.u0; U[e0 + 1] = P0.u1; Dl[e0] = P0.D0; Dl[e0 + 1] = P0.D1; }
+        lds_barrier();
+        const bool st1 = s >= 1 && s <= N - 1 && s >= xa - 1 && s <= xb;
+        const int sm = s - 1;
+        const bool st2 = sm >= xa && sm < xb;
+        const T* Um = sU[slm];
+        const T* Dm = sD[slm];
+        if ((s + wpar) & 1) {   // first colour at element 1 on plane s (and second colour at element 1 on s-1)
+            if (st1 && r1_1) { const T v = update(std::integral_constant<int, 1>(), U, Dl, Pm1, P0, Pp1); P0.u1 = v; U[e0 + 1] = v; }
+            if (st2 && t0_1) Pm1.u1 = update(std::integral_constant<int, 1>(), Um, Dm, Pm2, Pm1, P0);
+        } else {
+            if (st1 && r1_0) { const T v = update(std::integral_constant<int, 0>(), U, Dl, Pm1, P0, Pp1); P0.u0 = v; U[e0] = v; }
+            if (st2 && t0_0) Pm1.u0 = update(std::integral_constant<int, 0>(), Um, Dm, Pm2, Pm1, P0);
+        }
+        // output plane s-1 (both vertices of the pair are final)
+        const auto rO = plane_rsrc(a.u_out, plane_bytes, sm, st2);
+        buf_store<T>(Pm1.u0, rO, soff0);
+        buf_store<T>(Pm1.u1, rO, soff1);
+    };
+
+    // register ring of six planes; the step loop is unrolled by six so planes
+    // never move between registers and a load issued at step s is first used
+    // at step s + 3.  Plane s-2 is dead after step s; its registers take s+4.
+    SweepPlane<T> R0, R1, R2, R3, R4, R5;
+    R0.u0 = R0.u1 = R0.D0 = R0.D1 = T(0);
+    load(xa - 2, R1);
+    load(xa - 1, R2);
+    load(xa, R3);
+    load(xa + 1, R4);
+    load(xa + 2, R5);
+    for (int s0 = xa - 1; s0 <= xb; s0 += 6) {
+        step(s0, R0, R1, R2, R3); load(s0 + 4, R0);
+        if (s0 + 1 > xb) break;
+        step(s0 + 1, R1, R2, R3, R4); load(s0 + 5, R1);
+        if (s0 + 2 > xb) break;
+        step(s0 + 2, R2, R3, R4, R5); load(s0 + 6, R2);
+        if (s0 + 3 > xb) break;
+        step(s0 + 3, R3, R4, R5, R0); load(s0 + 7, R3);
+        if (s0 + 4 > xb) break;
+        step(s0 + 4, R4, R5, R0, R1); load(s0 + 8, R4);
+        if (s0 + 5 > xb) break;
+        step(s0 + 5, R5, R0, R1, R2); load(s0 + 9, R5);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Defect and full-weighting restriction.  Each workgroup owns a TYC x TZC
+// tile of coarse interior vertices and a chunk of coarse planes; threads own
+// fine column pairs of the region the tile's stencils cover (plus a ring of
+// 1 for the operator).  At fine plane p the residual is formed in LDS, then
+// each coarse vertex of the tile sums its 3 x 3 in-plane weights
+// (1,2,1) x (1,2,1) and accumulates along x with weights (1,2,1); the /64
+// is applied when the coarse plane completes.
+
+template <class T>
+struct RestrictArgs {
+    const T* u;
+    const T* q;
+    const T* D;
+    const T* mu;
+    T* qc;
+    int N;   // fine cells per axis
+    int tiles_y, tiles_z, chunk, nchunks;
+    Stencil<T> st;
+};
+
+template <class T>
+struct ResPlane {
+    T u0, u1, D0, D1, q0, q1, m0, m1;
+};
+
+template <int TYC, int TZC>
+struct RestrictShape {
+    static constexpr int NP = TZC + 2, RY = 2 * TYC + 3, RZ = 2 * NP, RA = RY * RZ;
+    static constexpr int NT = (RY * NP + 63) / 64 * 64;
+    static_assert(TYC * TZC <= NT, "coarse tile larger than the workgroup");
+};
+
+template <class T, int TYC, int TZC, bool HARM>
+__global__ __launch_bounds__((RestrictShape<TYC, TZC>::NT)) void k_defect_restrict_col(RestrictArgs<T> a) {
+    using Sh = RestrictShape<TYC, TZC>;
+    constexpr int NP = Sh::NP, RY = Sh::RY, RZ = Sh::RZ, RA = Sh::RA;
+    __shared__ T sU[2][RA];
+    __shared__ T sD[2][RA];
+    __shared__ T sR[RA];
+    const int N = a.N, n = N + 1, Nc = N / 2, ncv = Nc + 1;
+    const int64_t sx = (int64_t)n * n, plane_bytes = sx * (int64_t)sizeof(T);
+    const int64_t cplane_bytes = (int64_t)ncv * ncv * (int64_t)sizeof(T);
+    const int tid = threadIdx.x;
+    const bool act = tid < RY * NP;
+    const int ly = act ? tid / NP : 0, pz = act ? tid % NP : 0;
+    const int nb = a.tiles_y * a.tiles_z * a.nchunks;
+    const int b = xcd_tile(blockIdx.x, nb);
+    const int bz = b % a.tiles_z, by = (b / a.tiles_z) % a.tiles_y, bx = b / (a.tiles_z * a.tiles_y);
+    const int Y0 = 1 + by * TYC, Z0 = 1 + bz * TZC;
+    const int Xa = 1 + bx * a.chunk, Xb = min(Nc, Xa + a.chunk);   // coarse planes [Xa, Xb)
+    const int y = 2 * Y0 - 2 + ly, zl = 2 * Z0 - 2 + 2 * pz;
+    const int e0 = ly * RZ + 2 * pz;
+    const bool yin = act && y >= 0 && y <= N;
+    const int off0 = (yin && zl <= N) ? (int)(((int64_t)y * n + zl) * sizeof(T)) : kOob;
+    const int off1 = (yin && zl + 1 <= N) ? (int)(((int64_t)y * n + zl + 1) * sizeof(T)) : kOob;
+    // residual needed on region rows/cols 1 .. R-2 (interior vertices only)
+    const bool rrow = act && ly >= 1 && ly <= RY - 2 && y >= 1 && y <= N - 1;
+    const bool rc0 = rrow && 2 * pz >= 1 && zl >= 1 && zl <= N - 1;
+    const bool rc1 = rrow && 2 * pz + 1 <= RZ - 2 && zl + 1 >= 1 && zl + 1 <= N - 1;
+    // coarse vertex owned by this thread
+    const bool cown = tid < TYC * TZC;
+    const int lyc = cown ? tid / TZC : 0, lzc = cown ? tid % TZC : 0;
+    const int Yc = Y0 + lyc, Zc = Z0 + lzc;
+    const int coff = (cown && Yc <= Nc - 1 && Zc <= Nc - 1) ? (int)(((int64_t)Yc * ncv + Zc) * sizeof(T)) : kOob;
+    const int cc = (2 * lyc + 2) * RZ + 2 * lzc + 2;   // fine centre in the region
+    const int p_first = 2 * Xa - 1, p_last = 2 * Xb - 1;
+    const int p_lo = p_first - 1, p_hi = p_last + 1;
+
+    auto load = [&](int p, ResPlane<T>& P) {
+        const bool pv = p >= p_lo && p <= p_hi && p >= 0 && p <= N;
+        const auto rU = plane_rsrc(a.u, plane_bytes, p, pv);
+        const auto rD = plane_rsrc(a.D, plane_bytes, p, pv);
+        const auto rQ = plane_rsrc(a.q, plane_bytes, p, pv);
+        const auto rM = plane_rsrc(a.mu, plane_bytes, p, pv);
+        P.u0 = buf_load<T>(rU, off0); P.u1 = buf_load<T>(rU, off1);
+        P.D0 = buf_load<T>(rD, off0); P.D1 = buf_load<T>(rD, off1);
+        P.q0 = buf_load<T>(rQ, off0); P.q1 = buf_load<T>(rQ, off1);
+        P.m0 = buf_load<T>(rM, off0); P.m1 = buf_load<T>(rM, off1);
+    };
+    auto resid = [&](auto Oc, const T* U, const T* Dl, const ResPlane<T>& Pb, const ResPlane<T>& P,
+                     const ResPlane<T>& Pa) -> T {
+        constexpr int O = decltype(Oc)::value;
+        const int e = e0 + O;
+        const T ui = O ? P.u1 : P.u0, Di = O ? P.D1 : P.D0;
+        const T uzl = O ? P.u0 : U[e - 1], uzr = O ? U[e + 1] : P.u1;
+        const T Dzl = O ? P.D0 : Dl[e - 1], Dzr = O ? Dl[e + 1] : P.D1;
+        const T Au = (O ? P.m1 : P.m0) * ui + face<HARM>(Di, O ? Pb.D1 : Pb.D0, a.st) * (ui - (O ? Pb.u1 : Pb.u0)) +
+                     face<HARM>(Di, O ? Pa.D1 : Pa.D0, a.st) * (ui - (O ? Pa.u1 : Pa.u0)) +
+                     face<HARM>(Di, Dl[e - RZ], a.st) * (ui - U[e - RZ]) + face<HARM>(Di, Dl[e + RZ], a.st) * (ui - U[e + RZ]) +
+                     face<HARM>(Di, Dzl, a.st) * (ui - uzl) + face<HARM>(Di, Dzr, a.st) * (ui - uzr);
+        return (O ? P.q1 : P.q0) - Au;
+    };
+
+    T acc = T(0);
+    auto step = [&](int p, ResPlane<T>& Pm1, ResPlane<T>& P0, ResPlane<T>& Pp1) {
+        const int sl = p & 1;
+        T* U = sU[sl];
+        T* Dl = sD[sl];
+        if (act) { U[e0] = P0.u0; U[e0 + 1] = P0.u1; Dl[e0] = P0.D0; Dl[e0 + 1] = P0.D1; }
+        lds_barrier();
+        const bool pin = p >= 1 && p <= N - 1;
+        const T r0 = (pin && rc0) ? resid(std::integral_constant<int, 0>(), U, Dl, Pm1, P0, Pp1) : T(0);
+        const T r1 = (pin && rc1) ? resid(std::integral_constant<int, 1>(), U, Dl, Pm1, P0, Pp1) : T(0);
+        if (act) { sR[e0] = r0; sR[e0 + 1] = r1; }
+        lds_barrier();
+        if (cown) {
+            auto row = [&](int c) { return (sR[c - 1] + T(2) * sR[c]) + sR[c + 1]; };
+            const T w = (row(cc - RZ) + T(2) * row(cc)) + row(cc + RZ);
+            if (p & 1) {   // p = 2X - 1: completes coarse plane X - 1, starts X
+                if (p > p_first) {
+                    const int X = (p - 1) / 2;
+                    const auto rC = plane_rsrc(a.qc, cplane_bytes, X, true);
+                    buf_store<T>((acc + w) * T(1.0 / 64.0), rC, coff);
+                }
+                acc = w;
+            } else {
+                acc += T(2) * w;
+            }
+        }
+    };
+
+    // register ring of four planes; plane p-1 is dead after step p and its
+    // registers take plane p+3
+    ResPlane<T> R0, R1, R2, R3;
+    load(p_first - 1, R0);
+    load(p_first, R1);
+    load(p_first + 1, R2);
+    load(p_first + 2, R3);
+    for (int p0 = p_first; p0 <= p_last; p0 += 4) {
+        step(p0, R0, R1, R2); load(p0 + 3, R0);
+        if (p0 + 1 > p_last) break;
+        step(p0 + 1, R1, R2, R3); load(p0 + 4, R1);
+        if (p0 + 2 > p_last) break;
+        step(p0 + 2, R2, R3, R0); load(p0 + 5, R2);
+        if (p0 + 3 > p_last) break;
+        step(p0 + 3, R3, R0, R1); load(p0 + 6, R3);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Float64 refinement step (and the plain float64 residual norm): threads own
+// column pairs of the tile plus a ring of 1 in y and one pair in z.
+//   x_out = x + e  (e float32; HAS_E false: no correction)     on the tile
+//   r32   = float(b - A x_out)                                 on the tile
+//   partial[block] = sum over the tile of (b - A x_out)^2
+// x_out and r32 may be null (not written).
+
+struct IrArgs {
+    const double* x;
+    const float* e;
+    double* x_out;
+    const double* b;
+    const double* D;
+    const double* mu;
+    float* r32;
+    double* partial;
+    int N;
+    int tiles_y, tiles_z, chunk, nchunks;
+    Stencil<double> st;
+};
+
+struct IrPlane {
+    double x0, x1, D0, D1, b0, b1, m0, m1;
+    float e0, e1;
+};
+
+template <int TY, int TZ>
+struct IrShape {
+    static constexpr int NP = TZ / 2 + 2, RY = TY + 2, RZ = 2 * NP, RA = RY * RZ;
+    static constexpr int NT = (RY * NP + 63) / 64 * 64;
+};
+
+template <int TY, int TZ, bool HAS_E, bool HARM>
+__global__ __launch_bounds__((IrShape<TY, TZ>::NT)) void k_ir_residual_col(IrArgs a) {
+    using Sh = IrShape<TY, TZ>;
+    constexpr int NP = Sh::NP, RY = Sh::RY, RZ = Sh::RZ, RA = Sh::RA;
+    __shared__ double sU[2][RA];
+    __shared__ double sD[2][RA];
+    const int N = a.N, n = N + 1;
+    const int64_t sx = (int64_t)n * n;
+    const int64_t pb8 = sx * 8, pb4 = sx * 4;
+    const int tid = threadIdx.x;
+    const bool act = tid < RY * NP;
+    const int ly = act ? tid / NP : 0, pz = act ? tid % NP : 0;
+    const int nb = a.tiles_y * a.tiles_z * a.nchunks;
+    const int bid = xcd_tile(blockIdx.x, nb);
+    const int bz = bid % a.tiles_z, by = (bid / a.tiles_z) % a.tiles_y, bx = bid / (a.tiles_z * a.tiles_y);
+    const int y0 = by * TY, z0 = bz * TZ;
+    const int y = y0 - 1 + ly, zl = z0 - 2 + 2 * pz;
+    const int xa = 1 + bx * a.chunk, xb = min(N, xa + a.chunk);   // planes [xa, xb)
+    const int e0 = ly * RZ + 2 * pz;
+    const bool yin = act && y >= 0 && y <= N;
+    const int64_t v0 = (int64_t)y * n + zl;
+    const int o8_0 = (yin && zl >= 0 && zl <= N) ? (int)(v0 * 8) : kOob;
+    const int o8_1 = (yin && zl + 1 <= N) ? (int)((v0 + 1) * 8) : kOob;
+    const int o4_0 = (yin && zl >= 0 && zl <= N) ? (int)(v0 * 4) : kOob;
+    const int o4_1 = (yin && zl + 1 <= N) ? (int)((v0 + 1) * 4) : kOob;
+    const bool tile_y = act && ly >= 1 && ly <= TY && y >= 1 && y <= N - 1;
+    const bool t0 = tile_y && zl >= max(1, z0) && zl <= min(N - 1, z0 + TZ - 1);
+    const bool t1 = tile_y && zl + 1 >= max(1, z0) && zl + 1 <= min(N - 1, z0 + TZ - 1);
+    const int s8_0 = t0 ? o8_0 : kOob, s8_1 = t1 ? o8_1 : kOob;
+    const int s4_0 = t0 ? o4_0 : kOob, s4_1 = t1 ? o4_1 : kOob;
+    const int p_lo = xa - 1, p_hi = xb;
+
+    auto load = [&](int p, IrPlane& P) {
+        const bool pv = p >= p_lo && p <= p_hi;
+        const auto rX = plane_rsrc(a.x, pb8, p, pv);
+        const auto rD = plane_rsrc(a.D, pb8, p, pv);
+        const auto rB = plane_rsrc(a.b, pb8, p, pv);
+        const auto rM = plane_rsrc(a.mu, pb8, p, pv);
+        P.x0 = buf_load<double>(rX, o8_0); P.x1 = buf_load<double>(rX, o8_1);
+        P.D0 = buf_load<double>(rD, o8_0); P.D1 = buf_load<double>(rD, o8_1);
+        P.b0 = buf_load<double>(rB, o8_0); P.b1 = buf_load<double>(rB, o8_1);
+        P.m0 = buf_load<double>(rM, o8_0); P.m1 = buf_load<double>(rM, o8_1);
+        if (HAS_E) {
+            const auto rE = plane_rsrc(a.e, pb4, p, pv);
+            P.e0 = buf_load<float>(rE, o4_0); P.e1 = buf_load<float>(rE, o4_1);
+        } else {
+            P.e0 = P.e1 = 0.0f;
+        }
+    };
+    auto u0of = [&](const IrPlane& P) { return HAS_E ? P.x0 + (double)P.e0 : P.x0; };
+    auto u1of = [&](const IrPlane& P) { return HAS_E ? P.x1 + (double)P.e1 : P.x1; };
+
+    double acc = 0.0;
+    auto step = [&](int p, IrPlane& Pm1, IrPlane& P0, IrPlane& Pp1) {
+        const int sl = p & 1;
+        double* U = sU[sl];
+        double* Dl = sD[sl];
+        const double u0 = u0of(P0), u1 = u1of(P0);
+        if (act) { U[e0] = u0; U[e0 + 1] = u1; Dl[e0] = P0.D0; Dl[e0 + 1] = P0.D1; }
+        lds_barrier();
+        auto res = [&](auto Oc) -> double {
+            constexpr int O = decltype(Oc)::value;
+            const int e = e0 + O;
+            const double ui = O ? u1 : u0, Di = O ? P0.D1 : P0.D0;
+            const double uzl = O ? u0 : U[e - 1], uzr = O ? U[e + 1] : u1;
+            const double Dzl = O ? P0.D0 : Dl[e - 1], Dzr = O ? Dl[e + 1] : P0.D1;
+            const double ub = O ? u1of(Pm1) : u0of(Pm1), ua = O ? u1of(Pp1) : u0of(Pp1);
+            const double Au = (O ? P0.m1 : P0.m0) * ui + face<HARM>(Di, O ? Pm1.D1 : Pm1.D0, a.st) * (ui - ub) +
+                              face<HARM>(Di, O ? Pp1.D1 : Pp1.D0, a.st) * (ui - ua) +
+                              face<HARM>(Di, Dl[e - RZ], a.st) * (ui - U[e - RZ]) +
+                              face<HARM>(Di, Dl[e + RZ], a.st) * (ui - U[e + RZ]) + face<HARM>(Di, Dzl, a.st) * (ui - uzl) +
+                              face<HARM>(Di, Dzr, a.st) * (ui - uzr);
+            return (O ? P0.b1 : P0.b0) - Au;
+        };
+        const bool pin = p >= xa && p < xb;
+        const double r0 = (pin && t0) ? res(std::integral_constant<int, 0>()) : 0.0;
+        const double r1 = (pin && t1) ? res(std::integral_constant<int, 1>()) : 0.0;
+        acc += r0 * r0 + r1 * r1;
+        const auto rO = plane_rsrc(a.x_out, pb8, p, pin && a.x_out != nullptr);
+        buf_store<double>(u0, rO, s8_0);
+        buf_store<double>(u1, rO, s8_1);
+        const auto rR = plane_rsrc(a.r32, pb4, p, pin && a.r32 != nullptr);
+        buf_store<float>((float)r0, rR, s4_0);
+        buf_store<float>((float)r1, rR, s4_1);
+    };
+
+    IrPlane R0, R1, R2, R3;
+    load(xa - 1, R0);
+    load(xa, R1);
+    load(xa + 1, R2);
+    load(xa + 2, R3);
+    for (int p0 = xa; p0 < xb; p0 += 4) {
+        step(p0, R0, R1, R2); load(p0 + 3, R0);
+        if (p0 + 1 >= xb) break;
+        step(p0 + 1, R1, R2, R3); load(p0 + 4, R1);
+        if (p0 + 2 >= xb) break;
+        step(p0 + 2, R2, R3, R0); load(p0 + 5, R2);
+        if (p0 + 3 >= xb) break;
+        step(p0 + 3, R3, R0, R1); load(p0 + 6, R3);
+    }
+    // deterministic block sum (fixed order over waves)
+    __shared__ double wsum[Sh::NT / 64];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (tid % 64 == 0) wsum[tid / 64] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double s = 0.0;
+        for (int i = 0; i < Sh::NT / 64; i++) s += wsum[i];
+        a.partial[blockIdx.x] = s;
+    }
+}
+
+// Set the boundary layer of an iterate to g (interior untouched).
+template <class T>
+__global__ void k_set_boundary(T* __restrict__ u, int N, T g) {
+    const int n = N + 1;
+    const int64_t sx = (int64_t)n * n;
+    const int face_id = blockIdx.y;   // 0: x=0, 1: x=N, 2: y=0, 3: y=N, 4: z=0, 5: z=N
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n * n; t += gridDim.x * blockDim.x) {
+        const int i = t / n, j = t - (t / n) * n;
+        const int c = (face_id & 1) ? N : 0;
+        int64_t v;
+        if (face_id < 2) v = (int64_t)c * sx + (int64_t)i * n + j;
+        else if (face_id < 4) v = (int64_t)i * sx + (int64_t)c * n + j;
+        else v = (int64_t)i * sx + (int64_t)j * n + c;
+        u[v] = g;
+    }
+}
+
+// Inverse diagonal w = 1 / (sum_j c_ij + mua_i) on interior vertices (0 on
+// the boundary), formed in float64 and stored as T.
+template <class T>
+__global__ void k_inv_diag(const double* __restrict__ D, const double* __restrict__ mu, int N, Stencil<double> st,
+                           T* __restrict__ w) {
+    const int n = N + 1;
+    const int x = blockIdx.z, yy = blockIdx.y;
+    const int64_t sx = (int64_t)n * n;
+    for (int z = threadIdx.x; z < n; z += blockDim.x) {
+        const int64_t i = (int64_t)x * sx + (int64_t)yy * n + z;
+        if (!is_interior(N, x, yy, z)) { w[i] = T(0); continue; }
+        const double Di = D[i];
+        const double d = mu[i] + face_coef(Di, D[i + sx], st) + face_coef(Di, D[i - sx], st) +
+                         face_coef(Di, D[i + n], st) + face_coef(Di, D[i - n], st) + face_coef(Di, D[i + 1], st) +
+                         face_coef(Di, D[i - 1], st);
+        w[i] = (T)(1.0 / d);
+    }
+}
+
+}  // namespace dmgs

@@ -16,8 +16,8 @@ struct Level {
     double h = 1.0, inv_h2 = 1.0;
     // coefficient hierarchy (float64 on every level; float32 copies in
     // iterative-refinement plans)
-    double *D64 = nullptr, *mu64 = nullptr;
-    float *D32 = nullptr, *mu32 = nullptr;
+    double *D64 = nullptr, *mu64 = nullptr, *w64 = nullptr;   // w: inverse diagonal
+    float *D32 = nullptr, *mu32 = nullptr, *w32 = nullptr;
     // iterate, right-hand side and scratch of the cycle on this level
     double *u64 = nullptr, *q64 = nullptr, *t64 = nullptr;
     float *u32 = nullptr, *q32 = nullptr, *t32 = nullptr;
@@ -35,6 +35,7 @@ template <class T> struct Typed;
 template <> struct Typed<double> {
     static double* D(const Level& l) { return l.D64; }
     static double* mu(const Level& l) { return l.mu64; }
+    static double* w(const Level& l) { return l.w64; }
     static double* u(const Level& l) { return l.u64; }
     static double* q(const Level& l) { return l.q64; }
     static double* t(const Level& l) { return l.t64; }
@@ -42,6 +43,7 @@ template <> struct Typed<double> {
 template <> struct Typed<float> {
     static float* D(const Level& l) { return l.D32; }
     static float* mu(const Level& l) { return l.mu32; }
+    static float* w(const Level& l) { return l.w32; }
     static float* u(const Level& l) { return l.u32; }
     static float* q(const Level& l) { return l.q32; }
     static float* t(const Level& l) { return l.t32; }
@@ -62,6 +64,9 @@ struct dmgs_plan_s {
     int L = 0;
     dmgs::Level lev[dmgs::kMaxLevels];
     double* scratch64 = nullptr;   // finest-level float64 scratch (tangent right-hand side)
+    double* xalt64 = nullptr;      // second finest-level float64 iterate (refinement ping-pong)
+    // fused-pass configuration
+    int cfg_sweep = 0, cfg_fuse_min = 32;
     double* partial = nullptr;     // first-stage reduction partials
     double* dnorm = nullptr;       // device reduction results (4 slots)
     double* hnorm = nullptr;       // pinned host mirror of dnorm
