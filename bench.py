@@ -70,6 +70,7 @@ def main():
     ap.add_argument("--precision", default="fp32-in-fp64", choices=["fp32-in-fp64", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--inner", type=int, default=2, help="float32 V-cycles per refinement step")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU path (requested --gpus %d)"
@@ -89,7 +90,7 @@ def main():
     shape = t["q"].shape
     bufs = [torch.empty(shape, dtype=torch.float64, device=dev) for _ in range(4)]
 
-    P = Plan(Options(N, precision=args.precision, rtol=1e-10, max_cycles=100))
+    P = Plan(Options(N, precision=args.precision, rtol=1e-10, max_cycles=100, ir_inner_cycles=args.inner))
     log("plan: %d levels, %.2f GB" % (P.levels, P.bytes / 1e9))
     run_steps(P, t, bufs, args.warmup)
     torch.cuda.synchronize()
@@ -150,7 +151,7 @@ def main():
         "config": {"workload": "diffusion-absorption multigrid solve + adjoint, %d^3 cells, GRF log-normal D (contrast "
                                "<=1e4) and mua, 16-blob source, V(2,2) RB-GS, rtol 1e-10, set-up+forward+VJP per step"
                                % N,
-                   "N": N, "precision": args.precision, "rtol": 1e-10,
+                   "N": N, "precision": args.precision, "rtol": 1e-10, "ir_inner_cycles": args.inner,
                    "cycles_fwd": info_f["cycles"], "cycles_adj": info_a["cycles"],
                    "rel_residual_fwd": info_f["rel_residual"], "rel_residual_adj": info_a["rel_residual"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",

@@ -79,6 +79,8 @@ typedef struct dmgs_options {
     double h;              /* grid spacing (> 0) */
     double bc_value;       /* Dirichlet value g of rho on the boundary */
     double rtol;           /* tolerance mode: stop when ||r||_2 / ||r_0||_2 <= rtol over interior vertices */
+    int32_t ir_inner_cycles; /* DMGS_FP32_IN_FP64: float32 V-cycles per refinement step, 1..8 (default 2) */
+    int32_t reserved;
 } dmgs_options;
 
 typedef struct dmgs_info {
@@ -89,7 +91,9 @@ typedef struct dmgs_info {
 } dmgs_info;
 
 /* Fill `opt` with the defaults: V(2,2), RB-GS, FP64, arithmetic face mean,
- * h = 1, g = 0, rtol = 1e-10, max_cycles = 200, fixed_cycles = 0. */
+ * h = 1, g = 0, rtol = 1e-10, max_cycles = 200, fixed_cycles = 0,
+ * ir_inner_cycles = 2.  In DMGS_FP32_IN_FP64 plans a "cycle" of max_cycles,
+ * fixed_cycles and info.cycles is one refinement step. */
 void dmgs_default_options(int32_t n, dmgs_options *opt);
 
 /* Device bytes a plan with these options allocates (hierarchy + scratch); 0

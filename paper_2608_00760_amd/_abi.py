@@ -20,7 +20,8 @@ class Options(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("precision", C.c_int32), ("smoother", C.c_int32),
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("max_cycles", C.c_int32),
                 ("fixed_cycles", C.c_int32), ("face_mean", C.c_int32), ("h", C.c_double),
-                ("bc_value", C.c_double), ("rtol", C.c_double)]
+                ("bc_value", C.c_double), ("rtol", C.c_double), ("ir_inner_cycles", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -14,6 +14,7 @@
 
 #include "kernels_basic.hpp"
 #include "kernels_stream.hpp"
+#include "kernels_small.hpp"
 #include "plan.hpp"
 
 using namespace dmgs;
@@ -83,6 +84,10 @@ int check_options(const dmgs_options* o) {
     if (o->face_mean != DMGS_FACE_ARITH && o->face_mean != DMGS_FACE_HARMONIC) { set_error("bad face_mean"); return DMGS_ERR_INVALID; }
     if (!(o->h > 0.0) || !std::isfinite(o->h) || !std::isfinite(o->bc_value)) { set_error("bad h or bc_value"); return DMGS_ERR_INVALID; }
     if (o->fixed_cycles < 0 || o->fixed_cycles > 100000) { set_error("bad fixed_cycles"); return DMGS_ERR_INVALID; }
+    if (o->precision == DMGS_FP32_IN_FP64 && (o->ir_inner_cycles < 1 || o->ir_inner_cycles > 8)) {
+        set_error("bad ir_inner_cycles %d", o->ir_inner_cycles);
+        return DMGS_ERR_INVALID;
+    }
     if (o->fixed_cycles == 0 && (!(o->rtol > 0.0) || o->max_cycles < 1)) { set_error("bad rtol or max_cycles"); return DMGS_ERR_INVALID; }
     return DMGS_OK;
 }
@@ -250,13 +255,13 @@ int apply_or_defect(dmgs_plan P, int k, const T* u, const T* q, T* out, int appl
 
 // --- fused pass dispatch -------------------------------------------------------
 
-// chunk of x-planes per workgroup: enough workgroups to fill the chip,
-// but chunks long enough to amortise the wavefront's start-up planes
+// chunk of x-planes per workgroup: about 512 workgroups (two per CU), chunks
+// of at least 4 planes (each chunk re-reads a few planes at its ends)
 int choose_chunk(int interior, int tiles) {
-    int want = 2048;
+    int want = 512;
     int nch = (want + tiles - 1) / tiles;
     int chunk = (interior + nch - 1) / nch;
-    if (chunk < 16) chunk = 16;
+    if (chunk < 4) chunk = 4;
     if (chunk > interior) chunk = interior;
     return chunk;
 }
@@ -264,7 +269,7 @@ int choose_chunk(int interior, int tiles) {
 // Sweep-pass tiles (TY x TZ); the float32 choice is selectable for tuning
 // by DMGS_SWEEP_CFG = 0 (16 x 64), 1 (8 x 64), 2 (16 x 32).
 template <class T, int TY, int TZ, bool HARM>
-int launch_sweep(const SweepArgs<T>& a0, int N, bool zero, hipStream_t st) {
+int launch_sweep(const SweepArgs<T>& a0, int N, int mode, hipStream_t st) {
     SweepArgs<T> a = a0;
     constexpr int NT = SweepShape<TY, TZ>::NT;
     a.tiles_y = (N + TY - 1) / TY;
@@ -272,29 +277,32 @@ int launch_sweep(const SweepArgs<T>& a0, int N, bool zero, hipStream_t st) {
     a.chunk = choose_chunk(N - 1, a.tiles_y * a.tiles_z);
     a.nchunks = (N - 1 + a.chunk - 1) / a.chunk;
     int nb = a.tiles_y * a.tiles_z * a.nchunks;
-    if (zero) hipLaunchKernelGGL((k_rb_sweep_col<T, TY, TZ, true, HARM>), dim3(nb), dim3(NT), 0, st, a);
-    else hipLaunchKernelGGL((k_rb_sweep_col<T, TY, TZ, false, HARM>), dim3(nb), dim3(NT), 0, st, a);
+    if (mode == kSweepZero) hipLaunchKernelGGL((k_rb_sweep_col<T, TY, TZ, kSweepZero, HARM>), dim3(nb), dim3(NT), 0, st, a);
+    else if (mode == kSweepProlong) hipLaunchKernelGGL((k_rb_sweep_col<T, TY, TZ, kSweepProlong, HARM>), dim3(nb), dim3(NT), 0, st, a);
+    else hipLaunchKernelGGL((k_rb_sweep_col<T, TY, TZ, kSweepPlain, HARM>), dim3(nb), dim3(NT), 0, st, a);
     LAUNCHCHK();
     return DMGS_OK;
 }
 
 template <class T, bool HARM>
-int launch_sweep_cfg(dmgs_plan P, const SweepArgs<T>& a, int N, bool zero, hipStream_t st) {
+int launch_sweep_cfg(dmgs_plan P, const SweepArgs<T>& a, int N, int mode, hipStream_t st) {
     if constexpr (sizeof(T) == 8) {
-        return launch_sweep<T, 8, 64, HARM>(a, N, zero, st);
+        return launch_sweep<T, 8, 64, HARM>(a, N, mode, st);
     } else {
+        if (N <= 64) return launch_sweep<T, 8, 32, HARM>(a, N, mode, st);
         switch (P->cfg_sweep) {
-            case 1: return launch_sweep<T, 8, 64, HARM>(a, N, zero, st);
-            case 2: return launch_sweep<T, 16, 32, HARM>(a, N, zero, st);
-            default: return launch_sweep<T, 16, 64, HARM>(a, N, zero, st);
+            case 1: return launch_sweep<T, 8, 64, HARM>(a, N, mode, st);
+            case 2: return launch_sweep<T, 16, 32, HARM>(a, N, mode, st);
+            default: return launch_sweep<T, 16, 64, HARM>(a, N, mode, st);
         }
     }
 }
 
 // One fused sweep pass: u_out = one red-black sweep applied to u_in (or to
-// 0 when zero).
+// 0 when zero, or to u_in + I ec when ec is given).
 template <class T>
-int smooth_pass(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int order, bool zero, hipStream_t st) {
+int smooth_pass(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int order, bool zero, const T* ec,
+                hipStream_t st) {
     const Level& l = P->lev[k];
     SweepArgs<T> a;
     a.u_in = u_in;
@@ -302,15 +310,17 @@ int smooth_pass(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int ord
     a.q = q;
     a.D = Typed<T>::D(l);
     a.w = Typed<T>::w(l);
+    a.ec = ec;
     a.N = l.N;
     a.order = order;
     a.st = l.stencil<T>(harmonic(P));
-    // algorithmic bytes: read u (unless zero), q, D, w, write u
-    double words = zero ? 4.0 : 5.0;
+    const int mode = zero ? kSweepZero : (ec ? kSweepProlong : kSweepPlain);
+    // algorithmic bytes: read u (unless zero), q, D, w, (ec), write u
+    double words = (zero ? 4.0 : 5.0) + (ec ? 0.125 : 0.0);
     int slot;
     TRY(tbeg(P, k, st, &slot));
-    if (harmonic(P)) TRY((launch_sweep_cfg<T, true>(P, a, l.N, zero, st)));
-    else TRY((launch_sweep_cfg<T, false>(P, a, l.N, zero, st)));
+    if (harmonic(P)) TRY((launch_sweep_cfg<T, true>(P, a, l.N, mode, st)));
+    else TRY((launch_sweep_cfg<T, false>(P, a, l.N, mode, st)));
     TRY(tend(P, slot, DMGS_K_SMOOTH, words * l.nv * sizeof(T), st));
     return DMGS_OK;
 }
@@ -352,19 +362,22 @@ int defect_restrict(dmgs_plan P, int k, const T* u, const T* q, T* qc, hipStream
 }
 
 // Smoothing phase of `nsweeps` red-black sweeps on level k starting from
-// *cur (zero: from 0; ec: add I ec first, in place).  Result left in *cur,
-// which swaps between the level's two buffers.
+// *cur (zero: from 0; ec: add I ec first, fused into the first sweep).
+// Result left in *cur, which swaps between the level's two buffers.
 template <class T>
 int smooth_phase(dmgs_plan P, int k, T** cur, T** other, const T* q, int nsweeps, int order, bool zero, const T* ec,
                  hipStream_t st) {
     const Level& l = P->lev[k];
-    if (ec) {
-        TIMED(P, k, DMGS_K_PROLONG, (double)(2 * l.nv + P->lev[k + 1].nv) * sizeof(T), st,
-              hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, ec, *cur, l.N));
+    if (nsweeps == 0) {
+        if (zero) TRY(fill<T>(*cur, l.nv, T(0), st));
+        if (ec) {
+            TIMED(P, k, DMGS_K_PROLONG, (double)(2 * l.nv + P->lev[k + 1].nv) * sizeof(T), st,
+                  hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, ec, *cur, l.N));
+        }
+        return DMGS_OK;
     }
-    if (nsweeps == 0 && zero) TRY(fill<T>(*cur, l.nv, T(0), st));
     for (int i = 0; i < nsweeps; i++) {
-        TRY(smooth_pass<T>(P, k, *cur, *other, q, order, i == 0 && zero, st));
+        TRY(smooth_pass<T>(P, k, *cur, *other, q, order, i == 0 && zero, i == 0 ? ec : nullptr, st));
         std::swap(*cur, *other);
     }
     return DMGS_OK;
@@ -410,11 +423,46 @@ int post_pass(dmgs_plan P, int k, T** cur, T** other, const T* ec, const T* q, i
     return sweeps<T>(P, k, *cur, q, P->opt.nu_post, order, st);
 }
 
+template <class T, bool HARM>
+int launch_small_t(dmgs_plan P, int k, const T* q, T* u, int order, hipStream_t st) {
+    SmallArgs<T> a;
+    int Ns[kSmallMaxLevels];
+    a.nlev = P->L - k;
+    for (int i = 0; i < a.nlev; i++) {
+        const Level& l = P->lev[k + i];
+        a.lev[i].N = Ns[i] = l.N;
+        a.lev[i].D = Typed<T>::D(l);
+        a.lev[i].w = Typed<T>::w(l);
+        a.lev[i].mu = Typed<T>::mu(l);
+        a.lev[i].st = l.stencil<T>(HARM);
+    }
+    const Level& c = P->lev[P->L - 1];
+    a.q = q;
+    a.u = u;
+    a.Dc = c.D64;
+    a.muc = c.mu64;
+    a.stc = c.stencil<double>(HARM);
+    a.nu_pre = P->opt.nu_pre;
+    a.nu_post = P->opt.nu_post;
+    a.order = order;
+    size_t bytes = small_lds_bytes<T>(Ns, a.nlev);
+    hipLaunchKernelGGL((k_small_vcycle<T, HARM>), dim3(1), dim3(kSmallThreads), bytes, st, a);
+    LAUNCHCHK();
+    return DMGS_OK;
+}
+
+template <class T>
+int small_level(dmgs_plan P) { return sizeof(T) == 4 ? P->small32 : P->small64; }
+
 // One V-cycle on level k with right-hand side q, iterate in *cur (the
 // level's other buffer is *other).  zero: the iterate starts from 0 (coarse
 // corrections, refinement corrections).  On return *cur holds the result.
 template <class T>
 int vcycle(dmgs_plan P, int k, T** cur, T** other, const T* q, int order, bool zero, hipStream_t st) {
+    if (k > 0 && k == small_level<T>(P) && zero) {
+        if (harmonic(P)) return launch_small_t<T, true>(P, k, q, *cur, order, st);
+        return launch_small_t<T, false>(P, k, q, *cur, order, st);
+    }
     if (k == P->L - 1) {
         if (zero) TRY(fill<T>(*cur, P->lev[k].nv, T(0), st));
         return coarsest<T>(P, q, *cur, st);
@@ -551,7 +599,8 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
             }
             float* e = l0.u32;
             float* eo = l0.t32;
-            TRY(vcycle<float>(P, 0, &e, &eo, l0.q32, order, true, st));
+            for (int ic = 0; ic < o.ir_inner_cycles; ic++)
+                TRY(vcycle<float>(P, 0, &e, &eo, l0.q32, order, ic == 0, st));
             TRY(ir_step(P, xc, e, xo, b, l0.q32, 1, st));
             std::swap(xc, xo);
         }
@@ -701,6 +750,7 @@ void dmgs_default_options(int32_t n, dmgs_options* o) {
     o->h = 1.0;
     o->bc_value = 0.0;
     o->rtol = 1e-10;
+    o->ir_inner_cycles = 2;
 }
 
 size_t dmgs_workspace_bytes(const dmgs_options* o) {
@@ -772,7 +822,28 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
             if (ps[j] && hipMemset(ps[j], 0, l.nv * sz[j]) != hipSuccess) { set_error("hipMemset failed"); st = DMGS_ERR_HIP; }
     }
     P->cfg_sweep = 0;
-    P->cfg_fuse_min = 32;
+    P->cfg_fuse_min = ir ? 32 : 16;
+    // first level handled by the single-workgroup kernel (N <= 16 in float32,
+    // N <= 8 in float64, all remaining levels within the LDS budget)
+    P->small32 = P->small64 = -1;
+    for (int k = 1; k < P->L && st == DMGS_OK; k++) {
+        int Ns[kSmallMaxLevels];
+        int nl = P->L - k;
+        if (nl > kSmallMaxLevels) continue;
+        for (int i = 0; i < nl; i++) Ns[i] = P->lev[k + i].N;
+        if (P->small32 < 0 && P->lev[k].N <= 16 && small_lds_bytes<float>(Ns, nl) <= 160 * 1024) P->small32 = k;
+        if (P->small64 < 0 && P->lev[k].N <= 8 && small_lds_bytes<double>(Ns, nl) <= 160 * 1024) P->small64 = k;
+    }
+    if (st == DMGS_OK) {
+        const int lim = 160 * 1024;
+        const void* fns[] = {(const void*)k_small_vcycle<float, false>, (const void*)k_small_vcycle<float, true>,
+                             (const void*)k_small_vcycle<double, false>, (const void*)k_small_vcycle<double, true>};
+        for (const void* f : fns)
+            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) {
+                set_error("hipFuncSetAttribute failed");
+                st = DMGS_ERR_HIP;
+            }
+    }
     if (const char* e = std::getenv("DMGS_SWEEP_CFG")) P->cfg_sweep = std::min(2, std::max(0, std::atoi(e)));
     if (const char* e = std::getenv("DMGS_FUSE_MIN")) P->cfg_fuse_min = std::max(8, std::atoi(e));
     if (st != DMGS_OK) {

@@ -37,6 +37,13 @@ __device__ __forceinline__ T face_coef(T Da, T Db, const Stencil<T>& s) {
     return s.harmonic ? (Da * Db) / (Da + Db) * s.two_inv_h2 : (Da + Db) * s.half_inv_h2;
 }
 
+// Face coefficient with the face mean fixed at compile time.
+template <bool HARM, class T>
+__device__ __forceinline__ T face(T Da, T Db, const Stencil<T>& s) {
+    if (HARM) return (Da * Db) / (Da + Db) * s.two_inv_h2;
+    return (Da + Db) * s.half_inv_h2;
+}
+
 // Deterministic block sum of a double (wave64 shuffles, then LDS); result in
 // thread 0.  blockDim.x must be a multiple of 64 and at most 1024.
 __device__ inline double block_sum(double v) {

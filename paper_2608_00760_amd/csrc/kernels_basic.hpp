@@ -158,13 +158,13 @@ __global__ void k_prolong_add(const T* __restrict__ ec, T* __restrict__ u, int N
     }
 }
 
-// Exact solve on a level with at most 8 interior unknowns (N = 2 or 3), one
-// thread, in float64 whatever T is: assemble the dense matrix and Cholesky.
-// Boundary entries of u are the Dirichlet values and move to the right side.
-template <class T>
-__global__ void k_exact_solve(const T* __restrict__ q, T* __restrict__ u, const double* __restrict__ D,
-                              const double* __restrict__ mu, int N, Stencil<double> s) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// Exact solve on a level with at most 8 interior unknowns (N = 2 or 3), by
+// one thread, in float64 whatever the storage types: assemble the dense
+// matrix and factor it (Cholesky).  Boundary entries of u are the Dirichlet
+// values and move to the right-hand side; interior entries of u are written.
+template <class Tq, class Tu>
+__device__ void dense_exact_solve(const Tq* q, Tu* u, const double* __restrict__ D, const double* __restrict__ mu, int N,
+                                  Stencil<double> s) {
     int n = N + 1, m = (N - 1) * (N - 1) * (N - 1);
     double A[8][8], b[8];
     int64_t vid[8];
@@ -216,7 +216,14 @@ __global__ void k_exact_solve(const T* __restrict__ q, T* __restrict__ u, const 
         for (int p = i + 1; p < m; p++) acc -= A[p][i] * b[p];
         b[i] = acc / A[i][i];
     }
-    for (int r = 0; r < m; r++) u[vid[r]] = (T)b[r];
+    for (int r = 0; r < m; r++) u[vid[r]] = (Tu)b[r];
+}
+
+template <class T>
+__global__ void k_exact_solve(const T* __restrict__ q, T* __restrict__ u, const double* __restrict__ D,
+                              const double* __restrict__ mu, int N, Stencil<double> s) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    dense_exact_solve(q, u, D, mu, N, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -59,13 +59,6 @@ template <> __device__ __forceinline__ void buf_store<double>(double v, __amdgpu
                                           0, 0);
 }
 
-// Face coefficient with the face mean fixed at compile time.
-template <bool HARM, class T>
-__device__ __forceinline__ T face(T Da, T Db, const Stencil<T>& s) {
-    if (HARM) return (Da * Db) / (Da + Db) * s.two_inv_h2;
-    return (Da + Db) * s.half_inv_h2;
-}
-
 // ---------------------------------------------------------------------------
 // Red-black sweep.
 //
@@ -87,11 +80,17 @@ struct SweepArgs {
     const T* q;
     const T* D;
     const T* w;      // inverse diagonal
+    const T* ec;     // coarse correction added by prolongation (MODE 2)
     int N;
     int order;       // colour of the first stage: 0 red, 1 black
     int tiles_y, tiles_z, chunk, nchunks;
     Stencil<T> st;
 };
+
+// Plane-load modes of the sweep: the iterate is read as is, starts from
+// zero, or gets the trilinear prolongation I ec of a coarse correction added
+// (post-smoothing after the coarse-grid correction).
+enum SweepMode { kSweepPlain = 0, kSweepZero = 1, kSweepProlong = 2 };
 
 template <class T>
 struct SweepPlane {
@@ -107,8 +106,9 @@ struct SweepShape {
     static_assert(TY % 2 == 0 && TZ % 2 == 0, "even tile");
 };
 
-template <class T, int TY, int TZ, bool ZERO_INIT, bool HARM>
+template <class T, int TY, int TZ, int MODE, bool HARM>
 __global__ __launch_bounds__((SweepShape<TY, TZ>::NT)) void k_rb_sweep_col(SweepArgs<T> a) {
+    constexpr bool ZERO_INIT = MODE == kSweepZero, PROLONG = MODE == kSweepProlong;
     using Sh = SweepShape<TY, TZ>;
     constexpr int NP = Sh::NP, RY = Sh::RY, RZ = Sh::RZ, RA = Sh::RA, HALF = Sh::HALF;
     __shared__ T sU[3][RA];
@@ -145,6 +145,16 @@ __global__ __launch_bounds__((SweepShape<TY, TZ>::NT)) void k_rb_sweep_col(Sweep
     // colour parity of the wave: element of the first colour on plane s is
     // (s + hp + order) & 1 (y0 - 2 is even)
     const int wpar = __builtin_amdgcn_readfirstlane(hp + a.order);
+    // prolongation: coarse vertices around the pair (Z = zl/2; the odd
+    // element also uses Z+1); coarse boundary values are 0, so fine boundary
+    // vertices get no correction
+    const int ncv = N / 2 + 1;
+    const int64_t cplane_bytes = (int64_t)ncv * ncv * (int64_t)sizeof(T);
+    const int Yc0 = y >> 1, Yc1 = (y >> 1) + (y & 1), Zc = zl >> 1;
+    const int co00 = (PROLONG && yin && zin0) ? (int)(((int64_t)Yc0 * ncv + Zc) * sizeof(T)) : kOob;
+    const int co10 = (PROLONG && yin && zin0) ? (int)(((int64_t)Yc1 * ncv + Zc) * sizeof(T)) : kOob;
+    const int co01 = (PROLONG && yin && zin1) ? (int)(((int64_t)Yc0 * ncv + Zc + 1) * sizeof(T)) : kOob;
+    const int co11 = (PROLONG && yin && zin1) ? (int)(((int64_t)Yc1 * ncv + Zc + 1) * sizeof(T)) : kOob;
 
     auto load = [&](int p, SweepPlane<T>& P) {
         const bool pv = p >= p_lo && p <= p_hi;
@@ -157,6 +167,17 @@ __global__ __launch_bounds__((SweepShape<TY, TZ>::NT)) void k_rb_sweep_col(Sweep
             const auto rU = plane_rsrc(a.u_in, plane_bytes, p, pv);
             P.u0 = buf_load<T>(rU, off0);
             P.u1 = buf_load<T>(rU, off1);
+        }
+        if (PROLONG) {
+            const auto rA = plane_rsrc(a.ec, cplane_bytes, p >> 1, pv);
+            const auto rB = plane_rsrc(a.ec, cplane_bytes, (p >> 1) + (p & 1), pv);
+            const T a00 = buf_load<T>(rA, co00), a10 = buf_load<T>(rA, co10), b00 = buf_load<T>(rB, co00),
+                    b10 = buf_load<T>(rB, co10);
+            const T a01 = buf_load<T>(rA, co01), a11 = buf_load<T>(rA, co11), b01 = buf_load<T>(rB, co01),
+                    b11 = buf_load<T>(rB, co11);
+            const T s0 = (a00 + a10) + (b00 + b10);
+            P.u0 += s0 * T(0.25);
+            P.u1 += (s0 + ((a01 + a11) + (b01 + b11))) * T(0.125);
         }
         P.D0 = buf_load<T>(rD, off0); P.D1 = buf_load<T>(rD, off1);
         P.q0 = buf_load<T>(rQ, off0); P.q1 = buf_load<T>(rQ, off1);

@@ -28,6 +28,7 @@ class Options:
     face_mean: str = "arith"
     h: float = 1.0
     bc_value: float = 0.0
+    ir_inner_cycles: int = 2
 
     def to_c(self):
         o = _abi.default_options(self.N)
@@ -38,6 +39,7 @@ class Options:
         o.nu_pre, o.nu_post = int(self.nu_pre), int(self.nu_post)
         o.face_mean = _FACE[self.face_mean]
         o.h, o.bc_value = float(self.h), float(self.bc_value)
+        o.ir_inner_cycles = int(self.ir_inner_cycles)
         return o
 
 
