@@ -59,9 +59,10 @@ def coords(N):
 
 
 def blob(N, centre, sigma, amplitude=1.0):
-    X, Y, Z = coords(N)
-    r2 = (X - centre[0]) ** 2 + (Y - centre[1]) ** 2 + (Z - centre[2]) ** 2
-    return amplitude * np.exp(-r2 / (2.0 * sigma * sigma))
+    """amplitude * exp(-|x - c|^2 / (2 sigma^2)), as a product of 1D factors."""
+    x = np.arange(N + 1, dtype=np.float64)
+    g = [np.exp(-(x - centre[a]) ** 2 / (2.0 * sigma * sigma)) for a in range(3)]
+    return amplitude * (g[0][:, None, None] * g[1][None, :, None]) * g[2][None, None, :]
 
 
 def zero_boundary(f):
@@ -154,3 +155,53 @@ def serving_stream(nreq=512, sizes=(64, 96, 128, 192), seed=4999, rate=None):
         t = np.cumsum(rng.exponential(1.0 / rate, size=nreq))
     return [{"id": r, "N": int(Ns[r]), "mode": str(modes[r]), "seed": 4000 + r, "arrival": float(t[r])}
             for r in range(nreq)]
+
+
+# ---------------------------------------------------------------------------
+# Device-side generators (serving requests draw their fields on the GPU from
+# a per-request seeded torch generator; same recipes as above, a different
+# random stream).
+
+def grf_torch(N, gen, device, slope=-3.0):
+    import torch
+    n = N + 1
+    w = torch.randn((n, n, n), generator=gen, device=device, dtype=torch.float64)
+    W = torch.fft.rfftn(w)
+    kx = torch.fft.fftfreq(n, device=device, dtype=torch.float64) * n
+    kz = torch.fft.rfftfreq(n, device=device, dtype=torch.float64) * n
+    k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
+    k2[0, 0, 0] = 1.0
+    amp = k2 ** (slope / 4.0)
+    amp[0, 0, 0] = 0.0
+    f = torch.fft.irfftn(W * amp, s=(n, n, n))
+    f = f - f.mean()
+    f = f / f.std(correction=0)
+    return f.contiguous()
+
+
+def blob_source_torch(N, gen, device, nblobs=16, noise=0.01):
+    import torch
+    n = N + 1
+    par = torch.rand((nblobs, 5), generator=gen, device=device, dtype=torch.float64).cpu().numpy()
+    x = torch.arange(n, device=device, dtype=torch.float64)
+    q = torch.zeros((n, n, n), device=device, dtype=torch.float64)
+    for b in range(nblobs):
+        c = 0.15 * N + 0.7 * N * par[b, :3]
+        s = 2.0 + 4.0 * par[b, 3]
+        a = 0.5 + par[b, 4]
+        gx = torch.exp(-(x - c[0]) ** 2 / (2 * s * s))
+        gy = torch.exp(-(x - c[1]) ** 2 / (2 * s * s))
+        gz = torch.exp(-(x - c[2]) ** 2 / (2 * s * s))
+        q += a * gx[:, None, None] * gy[None, :, None] * gz[None, None, :]
+    q += noise * torch.randn((n, n, n), generator=gen, device=device, dtype=torch.float64)
+    return q.contiguous()
+
+
+def zero_boundary_torch(f):
+    f[0] = 0
+    f[-1] = 0
+    f[:, 0] = 0
+    f[:, -1] = 0
+    f[:, :, 0] = 0
+    f[:, :, -1] = 0
+    return f
