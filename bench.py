@@ -51,6 +51,34 @@ def cpu_baseline(c, cycles_fwd, cycles_adj):
                       % (c["N"], setup, fwd2, adj2, cycles_fwd, cycles_adj)}
 
 
+def serving_leg(nreq):
+    """The serving stream: nreq requests, grid sizes uniform over {64, 96, 128,
+    192}^3, 50/50 forward+JVP / forward+VJP, each with its own seeded fields.
+    First all at t = 0 (saturation throughput), then Poisson arrivals at 0.8 x
+    that rate for p50/p99 latency."""
+    from paper_2608_00760_amd import synth
+    from paper_2608_00760_amd.serving import Request, Server, summarize
+    budget = 96 << 30
+
+    def reqs(rate):
+        return [Request(id=d["id"], N=d["N"], mode=d["mode"], seed=d["seed"], arrival=d["arrival"])
+                for d in synth.serving_stream(nreq=nreq, rate=rate)]
+
+    srv = Server(budget_bytes=budget, max_slots=8, keep_results=False)
+    srv.run(reqs(None)[:16], realtime=False)      # warm-up: plans for every size
+    burst = summarize(srv.run(reqs(None), realtime=False))
+    rate = 0.8 * burst["requests_per_s"]
+    pois = summarize(srv.run(reqs(rate), realtime=True))
+    peak = srv.adm.peak
+    srv.close()
+    return {"requests": nreq, "sizes": [64, 96, 128, 192], "modes": "50/50 fwd+JVP / fwd+VJP",
+            "saturation_requests_per_s": burst["requests_per_s"], "saturation_solves_per_s": burst["solves_per_s"],
+            "poisson_rate_per_s": rate, "p50_ms": pois["p50_ms"], "p99_ms": pois["p99_ms"],
+            "requests_per_s": pois["requests_per_s"], "solves_per_s": pois["solves_per_s"],
+            "errors": pois["errors"] + burst["errors"], "budget_GB": budget / 1e9, "peak_accounted_GB": peak / 1e9,
+            "max_slots": 8}
+
+
 def run_steps(P, t, bufs, steps):
     import torch
     info_f = info_a = None
@@ -71,6 +99,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--inner", type=int, default=2, help="float32 V-cycles per refinement step")
+    ap.add_argument("--serving-requests", type=int, default=512, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the library's plain streaming copy (256 MiB, 3 times): HBM counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU path (requested --gpus %d)"
@@ -80,7 +111,16 @@ def main():
     import numpy as np
     import torch
     from paper_2608_00760_amd import synth
-    from paper_2608_00760_amd.solver import Options, Plan
+    from paper_2608_00760_amd.solver import Options, Plan, stream_copy
+
+    if args.copy_calibration:
+        nbytes = 256 << 20
+        src = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            ms = stream_copy(src, dst)
+            print(json.dumps({"copy_bytes": nbytes, "ms": ms, "GBps_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}))
+        return
 
     N = args.size
     log("generating inputs N=%d" % N)
@@ -128,10 +168,20 @@ def main():
         P64.close()
         log("fp64 solver: %.3f ms/step" % fp64["ms_per_step"])
 
+    serving = None
+    if args.serving_requests > 0:
+        log("serving stream: %d requests" % args.serving_requests)
+        serving = serving_leg(args.serving_requests)
+        log("serving: p50 %.2f ms p99 %.2f ms, %.1f requests/s (saturation %.1f)" % (
+            serving["p50_ms"], serving["p99_ms"], serving["requests_per_s"], serving["saturation_requests_per_s"]))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
-        cpu = cpu_baseline(c, info_f["cycles"], info_a["cycles"])
+        # the oracle runs plain V-cycles: scale by the V-cycles the solve needs
+        # (refinement steps x float32 cycles per step in the mixed solver)
+        vc = args.inner if args.precision == "fp32-in-fp64" else 1
+        cpu = cpu_baseline(c, info_f["cycles"] * vc, info_a["cycles"] * vc)
         log("oracle: %.4f pairs/s (%s)" % (cpu["value"], cpu["sample"]))
 
     nv = (N + 1) ** 3
@@ -159,7 +209,7 @@ def main():
                      "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": bytes_per_launch},
         "kernels": kernels,
         "fp64_solver": fp64,
-        "latency_p50_p99": None,
+        "latency_p50_p99": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -194,6 +194,9 @@ int dmgs_debug_post(dmgs_plan plan, int k, int fp32, int order, const void *u_in
                     const void *q, void *u_out, void *stream);
 /* Exact solve on the coarsest level: u = A_c^{-1} q (boundary of u = 0). */
 int dmgs_debug_coarsest(dmgs_plan plan, int fp32, const void *q, void *u, void *stream);
+/* Plain streaming copy of `bytes` (a multiple of 16) from src to dst, both
+ * device pointers: a kernel of known traffic, to calibrate memory counters. */
+int dmgs_debug_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 /* Exactly ncycles V-cycles applied to u (float64, in place) with right-hand
  * side q, from whatever u holds (its boundary entries are the Dirichlet values). */
 int dmgs_debug_cycles(dmgs_plan plan, int order, int ncycles, const double *q, double *u, void *stream);

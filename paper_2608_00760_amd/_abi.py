@@ -56,6 +56,7 @@ SIGNATURES = {
     "dmgs_debug_post": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
     "dmgs_debug_coarsest": (_i, [_vp, _i, _vp, _vp, _vp]),
     "dmgs_debug_cycles": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "dmgs_debug_stream_copy": (_i, [_vp, _vp, C.c_size_t, _vp]),
     "dmgs_timing_enable": (_i, [_vp, _i]),
     "dmgs_timing_read": (_i, [_vp, _i, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
 }

@@ -1022,6 +1022,14 @@ int dmgs_debug_coarsest(dmgs_plan P, int fp32, const void* q, void* u, void* str
     return coarsest<double>(P, (const double*)q, (double*)u, st);
 }
 
+int dmgs_debug_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+    if (!src || !dst || bytes % 16) { set_error("stream copy needs 16-byte multiples"); return DMGS_ERR_INVALID; }
+    hipLaunchKernelGGL(k_stream_copy, dim3(4096), dim3(256), 0, (hipStream_t)stream, (const float4*)src, (float4*)dst,
+                       (int64_t)(bytes / 16));
+    HIPCHK(hipGetLastError());
+    return DMGS_OK;
+}
+
 int dmgs_debug_cycles(dmgs_plan P, int order, int ncycles, const double* q, double* u, void* stream) {
     TRY(debug_check(P, 0, 0, false));
     if (is_ir(P)) { set_error("dmgs_debug_cycles needs a DMGS_FP64 plan"); return DMGS_ERR_INVALID; }

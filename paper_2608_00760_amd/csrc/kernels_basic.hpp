@@ -28,6 +28,11 @@ __global__ void k_fill(T* __restrict__ a, int64_t nv, T val) {
         a[v] = val;
 }
 
+// Plain streaming copy of 16-byte words (used to calibrate memory counters).
+__global__ void k_stream_copy(const float4* __restrict__ a, float4* __restrict__ b, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) b[i] = a[i];
+}
+
 __global__ void k_exp_copy(const double* __restrict__ a, double* __restrict__ b, int64_t nv) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x)
         b[v] = exp(a[v]);

@@ -48,6 +48,22 @@ def workspace_bytes(opts: Options) -> int:
     return int(_abi.lib().dmgs_workspace_bytes(C.byref(o)))
 
 
+def stream_copy(src, dst):
+    """Library's plain streaming copy src -> dst (same-size CUDA tensors);
+    returns the event-timed milliseconds."""
+    import torch
+    assert src.is_cuda and dst.is_cuda and src.nbytes == dst.nbytes and src.is_contiguous() and dst.is_contiguous()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    st = _abi.lib().dmgs_debug_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), src.nbytes,
+                                           _stream(src.device))
+    e1.record()
+    if st != _abi.DMGS_OK:
+        raise _abi.DMGSError(st, "dmgs_debug_stream_copy")
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
 def _stream(device):
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
