@@ -79,6 +79,36 @@ def serving_leg(nreq):
             "max_slots": 8}
 
 
+def kernel_source_hash():
+    """sha256 over the name and contents of the kernel sources (csrc/*.hpp and
+    csrc/dmgs.hip, sorted by path)."""
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2608_00760_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hpp")) + [os.path.join(csrc, "dmgs.hip")]):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    import re
+    path = os.path.join(ROOT, "profiles", "level0_sweep_256_traffic.md")
+    try:
+        with open(path) as fh:
+            m = re.search(r"```json\n(.*?)```", fh.read(), re.S)
+        rec = json.loads(m.group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def run_steps(P, t, bufs, steps):
     import torch
     info_f = info_a = None
@@ -205,7 +235,8 @@ def main():
                    "cycles_fwd": info_f["cycles"], "cycles_adj": info_a["cycles"],
                    "rel_residual_fwd": info_f["rel_residual"], "rel_residual_adj": info_a["rel_residual"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": measured_traffic(dom) if N == 256 and args.precision == "fp32-in-fp64" else None,
                      "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": bytes_per_launch},
         "kernels": kernels,
         "fp64_solver": fp64,
