@@ -185,7 +185,8 @@ int dmgs_debug_apply(dmgs_plan plan, int k, int fp32, const void *u, void *out, 
 int dmgs_debug_level_coefficients(dmgs_plan plan, int k, double *D, double *mua, void *stream);
 /* Pre-smoothing pass: u_out = nu_pre red-black sweeps applied to u_in with
  * right-hand side q (Sec. 2.3.1), then qc = R (q - A_k u_out) on the coarse
- * interior (Eq. (defect), Eq. (rest)), 0 on the coarse boundary. */
+ * interior (Eq. (defect), Eq. (rest)), 0 on the coarse boundary.  u_in NULL:
+ * start from the zero iterate with a zero boundary (a coarse-level pass). */
 int dmgs_debug_pre(dmgs_plan plan, int k, int fp32, int order, const void *u_in, const void *q,
                    void *u_out, void *qc, void *stream);
 /* Post-smoothing pass: u_out = nu_post sweeps applied to u_in + I ec

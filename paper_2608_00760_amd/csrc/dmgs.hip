@@ -14,6 +14,7 @@
 
 #include "kernels_basic.hpp"
 #include "kernels_stream.hpp"
+#include "kernels_sweep2.hpp"
 #include "kernels_small.hpp"
 #include "plan.hpp"
 
@@ -325,6 +326,86 @@ int smooth_pass(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int ord
     return DMGS_OK;
 }
 
+// Two-sweep passes (float32): tiles of 16 x 64; chunks of x-planes sized
+// for about cfg_sweep2_wgs workgroups, at least 8 planes (a chunk
+// recomputes 3 planes at each end).
+template <class T, int TY, int TZ, bool HARM>
+int launch_sweep2(dmgs_plan P, const SweepArgs<T>& a0, int N, int mode, hipStream_t st) {
+    SweepArgs<T> a = a0;
+    constexpr int NT = Sweep2Shape<TY, TZ>::NT;
+    constexpr size_t lds = sweep2_lds_bytes<T, TY, TZ>();
+    a.tiles_y = (N + TY - 1) / TY;
+    a.tiles_z = (N + TZ - 1) / TZ;
+    const int tiles = a.tiles_y * a.tiles_z;
+    const int nch = std::max(1, (P->cfg_sweep2_wgs + tiles - 1) / tiles);
+    a.chunk = std::min(N - 1, std::max(8, (N - 1 + nch - 1) / nch));
+    a.nchunks = (N - 1 + a.chunk - 1) / a.chunk;
+    const int nb = tiles * a.nchunks;
+    if (mode == kSweepZero) hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepZero, HARM>), dim3(nb), dim3(NT), lds, st, a);
+    else if (mode == kSweepProlong) hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepProlong, HARM>), dim3(nb), dim3(NT), lds, st, a);
+    else hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepPlain, HARM>), dim3(nb), dim3(NT), lds, st, a);
+    LAUNCHCHK();
+    return DMGS_OK;
+}
+
+constexpr int kSweep2TY = 16, kSweep2TZ = 64;
+
+// Dynamic-LDS limits of the two-sweep kernels (set once per plan).
+int sweep2_attributes() {
+    constexpr int lds = (int)sweep2_lds_bytes<float, kSweep2TY, kSweep2TZ>();
+    const void* fns[] = {
+        (const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepPlain, false>,
+        (const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepZero, false>,
+        (const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepProlong, false>,
+        (const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepPlain, true>,
+        (const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepZero, true>,
+        (const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepProlong, true>};
+    for (const void* f : fns)
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) {
+            set_error("hipFuncSetAttribute failed");
+            return DMGS_ERR_HIP;
+        }
+    return DMGS_OK;
+}
+
+// Two-sweep passes need a zero Dirichlet boundary (float32 corrections)
+// and whole-field buffer offsets below kOob.
+bool use_sweep2(dmgs_plan P, int k, size_t tsize) {
+    return tsize == 4 && P->lev[k].N >= P->cfg_sweep2_min && sweep2_fits<float>(P->lev[k].N);
+}
+
+// One two-sweep pass: u_out = two red-black sweeps applied to u_in (or to
+// 0, or to u_in + I ec).
+template <class T>
+int smooth_pass2(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int order, bool zero, const T* ec,
+                 hipStream_t st) {
+    const Level& l = P->lev[k];
+    SweepArgs<T> a;
+    a.u_in = u_in;
+    a.u_out = u_out;
+    a.q = q;
+    a.D = Typed<T>::D(l);
+    a.w = Typed<T>::w(l);
+    a.ec = ec;
+    a.N = l.N;
+    a.order = order;
+    a.st = l.stencil<T>(harmonic(P));
+    const int mode = zero ? kSweepZero : (ec ? kSweepProlong : kSweepPlain);
+    // algorithmic bytes: read u (unless zero), q, D, w, (ec), write u -- once for both sweeps
+    double words = (zero ? 4.0 : 5.0) + (ec ? 0.125 : 0.0);
+    int slot;
+    TRY(tbeg(P, k, st, &slot));
+    if constexpr (sizeof(T) == 4) {
+        if (harmonic(P)) TRY((launch_sweep2<T, kSweep2TY, kSweep2TZ, true>(P, a, l.N, mode, st)));
+        else TRY((launch_sweep2<T, kSweep2TY, kSweep2TZ, false>(P, a, l.N, mode, st)));
+    } else {
+        set_error("two-sweep pass is float32 only");
+        return DMGS_ERR_INVALID;
+    }
+    TRY(tend(P, slot, DMGS_K_SMOOTH, words * l.nv * sizeof(T), st));
+    return DMGS_OK;
+}
+
 template <class T, int TYC, int TZC, bool HARM>
 int launch_restrict(const RestrictArgs<T>& a0, int Nc, hipStream_t st) {
     RestrictArgs<T> a = a0;
@@ -376,8 +457,16 @@ int smooth_phase(dmgs_plan P, int k, T** cur, T** other, const T* q, int nsweeps
         }
         return DMGS_OK;
     }
-    for (int i = 0; i < nsweeps; i++) {
-        TRY(smooth_pass<T>(P, k, *cur, *other, q, order, i == 0 && zero, i == 0 ? ec : nullptr, st));
+    for (int i = 0; i < nsweeps;) {
+        const bool z = i == 0 && zero;
+        const T* e = i == 0 ? ec : nullptr;
+        if (nsweeps - i >= 2 && use_sweep2(P, k, sizeof(T))) {
+            TRY(smooth_pass2<T>(P, k, *cur, *other, q, order, z, e, st));
+            i += 2;
+        } else {
+            TRY(smooth_pass<T>(P, k, *cur, *other, q, order, z, e, st));
+            i += 1;
+        }
         std::swap(*cur, *other);
     }
     return DMGS_OK;
@@ -705,12 +794,17 @@ int debug_pre_t(dmgs_plan P, int k, int order, const T* u_in, const T* q, T* u_o
     const Level& l = P->lev[k];
     T* scratch = level_scratch<T>(P, k);
     if (!scratch) { set_error("no scratch of this type on level %d", k); return DMGS_ERR_INVALID; }
-    HIPCHK(hipMemcpyAsync(u_out, u_in, l.nv * sizeof(T), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(scratch, u_in, l.nv * sizeof(T), hipMemcpyDeviceToDevice, st));
+    if (u_in) {
+        HIPCHK(hipMemcpyAsync(u_out, u_in, l.nv * sizeof(T), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(scratch, u_in, l.nv * sizeof(T), hipMemcpyDeviceToDevice, st));
+    } else {   // zero iterate: both buffers get a zero boundary
+        TRY(fill<T>(u_out, l.nv, T(0), st));
+        TRY(fill<T>(scratch, l.nv, T(0), st));
+    }
     TRY(fill<T>(qc, P->lev[k + 1].nv, T(0), st));   // coarse boundary entries are 0
     T* cur = u_out;
     T* oth = scratch;
-    TRY(pre_pass<T>(P, k, &cur, &oth, q, qc, order, false, st));
+    TRY(pre_pass<T>(P, k, &cur, &oth, q, qc, order, u_in == nullptr, st));
     if (cur != u_out) HIPCHK(hipMemcpyAsync(u_out, cur, l.nv * sizeof(T), hipMemcpyDeviceToDevice, st));
     return DMGS_OK;
 }
@@ -844,6 +938,11 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
                 st = DMGS_ERR_HIP;
             }
     }
+    if (st == DMGS_OK) st = sweep2_attributes();
+    P->cfg_sweep2_min = 129;
+    P->cfg_sweep2_wgs = 256;
+    if (const char* e = std::getenv("DMGS_SWEEP2_MIN")) P->cfg_sweep2_min = std::max(16, std::atoi(e));
+    if (const char* e = std::getenv("DMGS_SWEEP2_WGS")) P->cfg_sweep2_wgs = std::max(16, std::atoi(e));
     if (const char* e = std::getenv("DMGS_SWEEP_CFG")) P->cfg_sweep = std::min(2, std::max(0, std::atoi(e)));
     if (const char* e = std::getenv("DMGS_FUSE_MIN")) P->cfg_fuse_min = std::max(8, std::atoi(e));
     if (st != DMGS_OK) {
@@ -997,6 +1096,7 @@ int dmgs_debug_level_coefficients(dmgs_plan P, int k, double* D, double* mua, vo
 int dmgs_debug_pre(dmgs_plan P, int k, int fp32, int order, const void* u_in, const void* q, void* u_out, void* qc,
                    void* stream) {
     TRY(debug_check(P, k, fp32, true));
+    if (!q || !u_out || !qc) { set_error("q, u_out and qc are required"); return DMGS_ERR_INVALID; }
     hipStream_t st = (hipStream_t)stream;
     if (fp32) return debug_pre_t<float>(P, k, order, (const float*)u_in, (const float*)q, (float*)u_out, (float*)qc, st);
     return debug_pre_t<double>(P, k, order, (const double*)u_in, (const double*)q, (double*)u_out, (double*)qc, st);

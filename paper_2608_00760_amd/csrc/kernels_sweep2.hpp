@@ -1,0 +1,276 @@
+// kernels_sweep2.hpp -- two red-black Gauss-Seidel sweeps in one streaming
+// pass (temporal blocking along x), for iterates with a zero Dirichlet
+// boundary (the float32 corrections of the refinement solver).
+//
+// A V(2,2) cycle smooths twice before and twice after the coarse-grid
+// correction; doing both sweeps of a phase in one pass reads the level's
+// fields once instead of twice.  The four colour updates of the two sweeps
+// (first colour, second colour, first, second) run as a pipeline along the
+// march: at step s, stage j updates plane s - j.  Every stage sees its
+// neighbours in exactly the state the sequential order gives:
+//   stage 0 on plane s     first colour,  neighbours before any update;
+//   stage 1 on plane s-1   second colour, neighbours after stage 0;
+//   stage 2 on plane s-2   first colour,  neighbours after stage 1;
+//   stage 3 on plane s-3   second colour, neighbours after stage 2.
+// In y and z, stage j is applied to the tile plus a ring of 3 - j vertices
+// (neighbouring tiles recompute the ring), so the tile's final values need
+// nothing from other workgroups.  Along x, a chunk [xa, xb) runs steps
+// xa-3 .. xb+2: the final values of its planes depend only on stage j
+// applied to planes [xa-3+j, xb+2-j], which the pipeline computes from
+// loaded data; what the first and last steps compute outside those ranges
+// is never read by them.  Planes at or beyond the grid boundary need no
+// special case: there the inverse diagonal w is 0 and loads return 0, so an
+// update reproduces the zero boundary value.
+//
+// Threads own a column pair (y; z, z+1), z even, of the tile plus a ring of
+// 4, and keep eight planes of their pair in a register ring (planes s-4 ..
+// s+3; s+2 and s+3 are loads in flight).  In-plane neighbours go through an
+// eight-slot LDS ring of planes holding {u, D}, laid out by pair element so
+// that consecutive lanes read consecutive 8-byte words; with eight slots
+// and the march unrolled by eight, every slot address is a compile-time
+// offset.  Each stage updates its colour in its plane's slot in place (it
+// reads only the other colour), the four stages of a step touch four
+// different slots, and a slot is republished five steps after its last
+// use, so one barrier per step orders everything.  Stages are applied to
+// every lane and the result is selected by the lane's ring membership.  At
+// step s all four stages update the same element of the pair, (s + row
+// parity + order) mod 2, uniform across a wave because waves hold rows of
+// one parity.
+#pragma once
+#include "kernels_stream.hpp"
+
+namespace dmgs {
+
+template <int TY, int TZ>
+struct Sweep2Shape {
+    static constexpr int R = 4;                              // ring of loaded vertices
+    static constexpr int NP = TZ / 2 + R, RY = TY + 2 * R;   // pairs per row, rows
+    static constexpr int RA = RY * NP;                       // pairs per plane (per element)
+    static constexpr int ROWS_HALF = RY / 2;
+    static constexpr int HALF = (ROWS_HALF * NP + 63) / 64 * 64;
+    static constexpr int NT = 2 * HALF;
+    static constexpr int SLOTS = 8;
+    static constexpr int PAD = NP + 2;                       // guard entries before and after the ring
+    static constexpr int ENTRIES = SLOTS * 2 * RA + 2 * PAD;
+    static_assert(TY % 2 == 0 && TZ % 2 == 0, "even tile");
+};
+
+template <class T>
+struct UD {
+    T u, D;
+};
+
+template <class T, int TY, int TZ>
+constexpr size_t sweep2_lds_bytes() {
+    return (size_t)Sweep2Shape<TY, TZ>::ENTRIES * sizeof(UD<T>);
+}
+
+// Largest level the two-sweep pass takes: buffer offsets of a whole field
+// (plus a few planes beyond it) stay below kOob.
+template <class T>
+__host__ __device__ constexpr bool sweep2_fits(int N) {
+    return ((int64_t)(N + 1) * (N + 1) * (N + 20) + 64) * (int64_t)sizeof(T) < (int64_t)kOob;
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const void* base, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+
+template <class T, int TY, int TZ, int MODE, bool HARM>
+__global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(SweepArgs<T> a) {
+    constexpr bool ZERO_INIT = MODE == kSweepZero, PROLONG = MODE == kSweepProlong;
+    using Sh = Sweep2Shape<TY, TZ>;
+    constexpr int R = Sh::R, NP = Sh::NP, RA = Sh::RA, HALF = Sh::HALF;
+    // slot k, element O: ring[(k * 2 + O) * RA + ly * NP + pz]
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    UD<T>* const ring = reinterpret_cast<UD<T>*>(lds_raw) + Sh::PAD;
+    const int N = a.N, n = N + 1;
+    const int plane_bytes = n * n * (int)sizeof(T);
+    const int field_bytes = n * plane_bytes;
+    const int tid = threadIdx.x;
+    const int hp = tid >= HALF ? 1 : 0;                 // row parity of this wave
+    // lanes past the half's pairs (in its last wave) repeat the first pairs
+    // of the half: they compute and write bit-identical values and store
+    // nothing to memory
+    const int th0 = tid - hp * HALF;
+    const bool own = th0 < Sh::ROWS_HALF * NP;
+    const int th = own ? th0 : th0 - Sh::ROWS_HALF * NP;
+    const int ly = 2 * (th / NP) + hp, pz = th % NP;
+    const int nb = a.tiles_y * a.tiles_z * a.nchunks;
+    const int b = xcd_tile(blockIdx.x, nb);
+    const int bz = b % a.tiles_z, by = (b / a.tiles_z) % a.tiles_y, bx = b / (a.tiles_z * a.tiles_y);
+    const int y0 = by * TY, z0 = bz * TZ;
+    const int y = y0 - R + ly, zl = z0 - R + 2 * pz;
+    const int xa = 1 + bx * a.chunk, xb = min(N, xa + a.chunk);   // output planes [xa, xb)
+    const int pe = ly * NP + pz;                                   // this pair's index in a slot
+    // in-plane offset of element 0 (element 1 is the next word); rows outside
+    // the grid read 0, columns just outside it read finite neighbours' data
+    // that no update of an interior vertex uses
+    const int off = (y >= 0 && y <= N) ? (y * n + zl) * (int)sizeof(T) : kOob;
+    // ring membership: stage j updates a vertex within 3 - j of the tile
+    auto in_ring = [&](int z, int r) {
+        return y >= max(1, y0 - r) && y <= min(N - 1, y0 + TY - 1 + r) && z >= max(1, z0 - r) &&
+               z <= min(N - 1, z0 + TZ - 1 + r);
+    };
+    bool m0[4], m1[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        m0[j] = in_ring(zl, 3 - j);
+        m1[j] = in_ring(zl + 1, 3 - j);
+    }
+    const int soff0 = (own && m0[3]) ? off : kOob;   // tile vertices are stored
+    const int soff1 = (own && m1[3]) ? off + (int)sizeof(T) : kOob;
+    const auto rU = field_rsrc(a.u_in, field_bytes), rD = field_rsrc(a.D, field_bytes);
+    const auto rQ = field_rsrc(a.q, field_bytes), rW = field_rsrc(a.w, field_bytes);
+    const auto rO = field_rsrc(a.u_out, field_bytes);
+    // prolongation: coarse vertices around the pair (the odd element also
+    // uses Z+1); coarse boundary values are 0
+    const int ncv = N / 2 + 1;
+    const int cplane_bytes = ncv * ncv * (int)sizeof(T);
+    const auto rC = field_rsrc(a.ec, PROLONG ? (int64_t)ncv * cplane_bytes : 0);
+    const bool pin = PROLONG && y >= 0 && y <= N && zl >= 0 && zl <= N;
+    const int Yc0 = y >> 1, Yc1 = (y >> 1) + (y & 1), Zc = zl >> 1;
+    const int co0 = pin ? (Yc0 * ncv + Zc) * (int)sizeof(T) : kOob;
+    const int co1 = pin ? (Yc1 * ncv + Zc) * (int)sizeof(T) : kOob;
+
+    // zero the ring once: every value a stage reads is then finite
+    for (int i = tid; i < Sh::ENTRIES; i += Sh::NT) reinterpret_cast<UD<T>*>(lds_raw)[i] = UD<T>{T(0), T(0)};
+    __syncthreads();
+
+    auto load = [&](int p, SweepPlane<T>& P) {
+        const int vo = off + p * plane_bytes;   // p < 0 or p > N: outside the field
+        if (ZERO_INIT) {
+            P.u0 = P.u1 = T(0);
+        } else {
+            P.u0 = buf_load<T>(rU, vo);
+            P.u1 = buf_load<T>(rU, vo + (int)sizeof(T));
+        }
+        if (PROLONG) {
+            const int ca = co0 + (p >> 1) * cplane_bytes, cb = co1 + (p >> 1) * cplane_bytes;
+            const int pa = (p & 1) * cplane_bytes;
+            const T a00 = buf_load<T>(rC, ca), a10 = buf_load<T>(rC, cb);
+            const T b00 = buf_load<T>(rC, ca + pa), b10 = buf_load<T>(rC, cb + pa);
+            const T a01 = buf_load<T>(rC, ca + (int)sizeof(T)), a11 = buf_load<T>(rC, cb + (int)sizeof(T));
+            const T b01 = buf_load<T>(rC, ca + pa + (int)sizeof(T)), b11 = buf_load<T>(rC, cb + pa + (int)sizeof(T));
+            const T s0 = (a00 + a10) + (b00 + b10);
+            P.u0 += s0 * T(0.25);
+            P.u1 += (s0 + ((a01 + a11) + (b01 + b11))) * T(0.125);
+        }
+        P.D0 = buf_load<T>(rD, vo); P.D1 = buf_load<T>(rD, vo + (int)sizeof(T));
+        P.q0 = buf_load<T>(rQ, vo); P.q1 = buf_load<T>(rQ, vo + (int)sizeof(T));
+        P.w0 = buf_load<T>(rW, vo); P.w1 = buf_load<T>(rW, vo + (int)sizeof(T));
+    };
+
+    // Gauss-Seidel value of element O of the pair on a plane whose slot is
+    // S: w (q + sum_j c_ij u_j); x-neighbours from the planes below (Pb) and
+    // above (Pa), the in-pair z-neighbour from registers, the others from
+    // the slot.
+    auto update = [&](auto Oc, const UD<T>* S, const SweepPlane<T>& Pb, const SweepPlane<T>& P,
+                      const SweepPlane<T>& Pa) -> T {
+        constexpr int O = decltype(Oc)::value;
+        const UD<T>* So = S + O * RA + pe;          // same element, this pair
+        const UD<T> ym = So[-NP], yp = So[NP];
+        // z-neighbour outside the pair: element 1 of the pair to the left
+        // (O = 0) or element 0 of the pair to the right (O = 1)
+        const UD<T> zo = O ? S[pe + 1] : S[RA + pe - 1];
+        const T Di = O ? P.D1 : P.D0;
+        const T uzl = O ? P.u0 : zo.u, uzr = O ? zo.u : P.u1;
+        const T Dzl = O ? P.D0 : zo.D, Dzr = O ? zo.D : P.D1;
+        const T Dxm = O ? Pb.D1 : Pb.D0, Dxp = O ? Pa.D1 : Pa.D0;
+        const T uxm = O ? Pb.u1 : Pb.u0, uxp = O ? Pa.u1 : Pa.u0;
+        T num;
+        if (HARM) {
+            // harmonic mean; the smallest normal number in the denominator
+            // keeps 0/0 (outside the grid, D = 0) finite and changes no
+            // rounding for D >= 1e-30
+            auto hf = [&](T Da, T Db) { return (Da * Db) / ((Da + Db) + T(1.17549435e-38)) * a.st.two_inv_h2; };
+            num = (O ? P.q1 : P.q0) + hf(Di, Dxm) * uxm + hf(Di, Dxp) * uxp + hf(Di, ym.D) * ym.u + hf(Di, yp.D) * yp.u +
+                  hf(Di, Dzl) * uzl + hf(Di, Dzr) * uzr;
+        } else {
+            // arithmetic mean: c_ij = (D_i + D_j) / (2 h^2), the common factor applied once
+            const T s = ((Di + Dxm) * uxm + (Di + Dxp) * uxp) + ((Di + ym.D) * ym.u + (Di + yp.D) * yp.u) +
+                        ((Di + Dzl) * uzl + (Di + Dzr) * uzr);
+            num = (O ? P.q1 : P.q0) + s * a.st.half_inv_h2;
+        }
+        return num * (O ? P.w1 : P.w0);
+    };
+
+    // stage j at unrolled step K updates element O of plane s - j (slot (K - j) mod 8)
+    auto stage = [&](auto Oc, auto Jc, auto Kc, SweepPlane<T>& Pb, SweepPlane<T>& P, SweepPlane<T>& Pa) {
+        constexpr int O = decltype(Oc)::value, J = decltype(Jc)::value, K = decltype(Kc)::value;
+        UD<T>* S = ring + ((K - J + 8) & 7) * 2 * RA;
+        const T v = update(Oc, S, Pb, P, Pa);
+        if (O) {
+            P.u1 = m1[J] ? v : P.u1;
+            if (J < 3) S[RA + pe].u = P.u1;
+        } else {
+            P.u0 = m0[J] ? v : P.u0;
+            if (J < 3) S[pe].u = P.u0;
+        }
+    };
+    auto stages = [&](auto Oc, auto Kc, SweepPlane<T>& Pm4, SweepPlane<T>& Pm3, SweepPlane<T>& Pm2,
+                      SweepPlane<T>& Pm1, SweepPlane<T>& P0, SweepPlane<T>& Pp1) {
+        stage(Oc, std::integral_constant<int, 0>(), Kc, Pm1, P0, Pp1);
+        stage(Oc, std::integral_constant<int, 1>(), Kc, Pm2, Pm1, P0);
+        stage(Oc, std::integral_constant<int, 2>(), Kc, Pm3, Pm2, Pm1);
+        stage(Oc, std::integral_constant<int, 3>(), Kc, Pm4, Pm3, Pm2);
+    };
+
+    const int s0 = xa - 3, s_end = xb + 2;
+    const int par0 = __builtin_amdgcn_readfirstlane((s0 + hp + a.order) & 1);   // element updated at step s0
+    auto step = [&](auto Kc, int s, SweepPlane<T>& Pm4, SweepPlane<T>& Pm3, SweepPlane<T>& Pm2, SweepPlane<T>& Pm1,
+                    SweepPlane<T>& P0, SweepPlane<T>& Pp1) {
+        constexpr int K = decltype(Kc)::value;
+        UD<T>* S = ring + K * 2 * RA;
+        S[pe] = UD<T>{P0.u0, P0.D0};
+        S[RA + pe] = UD<T>{P0.u1, P0.D1};
+        lds_barrier();
+        if (par0 ^ (K & 1)) stages(std::integral_constant<int, 1>(), Kc, Pm4, Pm3, Pm2, Pm1, P0, Pp1);
+        else stages(std::integral_constant<int, 0>(), Kc, Pm4, Pm3, Pm2, Pm1, P0, Pp1);
+        const int po = s - 3;   // final
+        if (po >= xa && po < xb) {
+            buf_store<T>(Pm3.u0, rO, soff0 + po * plane_bytes);
+            buf_store<T>(Pm3.u1, rO, soff1 + po * plane_bytes);
+        }
+    };
+
+    // register ring of eight planes, the march unrolled by eight so planes
+    // never move between registers; after step s, plane s-4 is dead and its
+    // registers take plane s+4 (first used at step s+3).
+    SweepPlane<T> R0, R1, R2, R3, R4, R5, R6, R7;
+    load(s0 - 4, R0);
+    load(s0 - 3, R1);
+    load(s0 - 2, R2);
+    load(s0 - 1, R3);
+    load(s0, R4);
+    load(s0 + 1, R5);
+    load(s0 + 2, R6);
+    load(s0 + 3, R7);
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    using I4 = std::integral_constant<int, 4>;
+    using I5 = std::integral_constant<int, 5>;
+    using I6 = std::integral_constant<int, 6>;
+    using I7 = std::integral_constant<int, 7>;
+    for (int s = s0; s <= s_end; s += 8) {
+        step(I0(), s, R0, R1, R2, R3, R4, R5); load(s + 4, R0);
+        if (s + 1 > s_end) break;
+        step(I1(), s + 1, R1, R2, R3, R4, R5, R6); load(s + 5, R1);
+        if (s + 2 > s_end) break;
+        step(I2(), s + 2, R2, R3, R4, R5, R6, R7); load(s + 6, R2);
+        if (s + 3 > s_end) break;
+        step(I3(), s + 3, R3, R4, R5, R6, R7, R0); load(s + 7, R3);
+        if (s + 4 > s_end) break;
+        step(I4(), s + 4, R4, R5, R6, R7, R0, R1); load(s + 8, R4);
+        if (s + 5 > s_end) break;
+        step(I5(), s + 5, R5, R6, R7, R0, R1, R2); load(s + 9, R5);
+        if (s + 6 > s_end) break;
+        step(I6(), s + 6, R6, R7, R0, R1, R2, R3); load(s + 10, R6);
+        if (s + 7 > s_end) break;
+        step(I7(), s + 7, R7, R0, R1, R2, R3, R4); load(s + 11, R7);
+    }
+}
+
+}  // namespace dmgs

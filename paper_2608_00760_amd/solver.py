@@ -190,8 +190,9 @@ class Plan:
     def debug_pre(self, k, u_in, q, order=0, fp32=False):
         dt = torch.float32 if fp32 else torch.float64
         u_out, qc = self._empty(k, dt), self._empty(k + 1, dt)
+        uin = None if u_in is None else self._arr(u_in, "u_in", k, dt)   # None: start from zero
         self._call(_abi.lib().dmgs_debug_pre, "dmgs_debug_pre", int(k), int(fp32), int(order),
-                   self._arr(u_in, "u_in", k, dt), self._arr(q, "q", k, dt), self._arr(u_out, "u_out", k, dt),
+                   uin, self._arr(q, "q", k, dt), self._arr(u_out, "u_out", k, dt),
                    self._arr(qc, "qc", k + 1, dt), _stream(self.device))
         return u_out, qc
 

@@ -100,12 +100,22 @@ def test_pre_and_post_passes_fp64(N, order, face_mean):
         assert rel_max(host(gp), oracle_post(H, k, u, ec, q, order)) <= 1e-13, (k, "post")
 
 
+# Float32 smoothing-pass variants: the plan's default choice, two-sweep
+# passes forced on every level with N >= 16 (several x-chunks), and the same
+# with one chunk per tile column.
+PASS_VARIANTS = {"default": {}, "sweep2": {"DMGS_SWEEP2_MIN": "16"},
+                 "sweep2_one_chunk": {"DMGS_SWEEP2_MIN": "16", "DMGS_SWEEP2_WGS": "16"}}
+
+
 @pytest.mark.parametrize("N", SIZES)
 @pytest.mark.parametrize("order", [0, 1])
-def test_pre_and_post_passes_fp32(N, order):
+@pytest.mark.parametrize("variant", list(PASS_VARIANTS))
+def test_pre_and_post_passes_fp32(N, order, variant, monkeypatch):
     from paper_2608_00760_amd import synth
     import torch
-    say("passes fp32 N=%d order=%d" % (N, order))
+    say("passes fp32 N=%d order=%d %s" % (N, order, variant))
+    for key, val in PASS_VARIANTS[variant].items():
+        monkeypatch.setenv(key, val)
     P, H = make(N, 40 + N, precision="fp32-in-fp64")
     for k in range(P.levels - 1):
         Nk = H.Ns[k]
@@ -116,6 +126,11 @@ def test_pre_and_post_passes_fp32(N, order):
         ru, rqc = oracle_pre(H, k, u, q, order)
         assert rel_max(host(gu), ru) <= 2e-5, (k, "pre u")
         assert np.abs(host(gqc) - rqc).max() <= 2e-5 * defect_scale(H, k, ru, q), (k, "pre qc")
+        # from the zero iterate (coarse levels, first float32 cycle)
+        gz, gzc = P.debug_pre(k, None, dev(q, torch.float32), order=order, fp32=True)
+        rz, rzc = oracle_pre(H, k, np.zeros_like(q), q, order)
+        assert rel_max(host(gz), rz) <= 2e-5, (k, "pre from zero u")
+        assert np.abs(host(gzc) - rzc).max() <= 2e-5 * defect_scale(H, k, rz, q), (k, "pre from zero qc")
         gp = P.debug_post(k, dev(u, torch.float32), dev(ec, torch.float32), dev(q, torch.float32), order=order, fp32=True)
         assert rel_max(host(gp), oracle_post(H, k, u, ec, q, order)) <= 2e-5, (k, "post")
 
