@@ -939,7 +939,7 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
             }
     }
     if (st == DMGS_OK) st = sweep2_attributes();
-    P->cfg_sweep2_min = 129;
+    P->cfg_sweep2_min = 64;
     P->cfg_sweep2_wgs = 256;
     if (const char* e = std::getenv("DMGS_SWEEP2_MIN")) P->cfg_sweep2_min = std::max(16, std::atoi(e));
     if (const char* e = std::getenv("DMGS_SWEEP2_WGS")) P->cfg_sweep2_wgs = std::max(16, std::atoi(e));

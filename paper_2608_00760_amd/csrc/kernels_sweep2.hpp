@@ -145,21 +145,30 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
             P.u0 = buf_load<T>(rU, vo);
             P.u1 = buf_load<T>(rU, vo + (int)sizeof(T));
         }
-        if (PROLONG) {
-            const int ca = co0 + (p >> 1) * cplane_bytes, cb = co1 + (p >> 1) * cplane_bytes;
-            const int pa = (p & 1) * cplane_bytes;
-            const T a00 = buf_load<T>(rC, ca), a10 = buf_load<T>(rC, cb);
-            const T b00 = buf_load<T>(rC, ca + pa), b10 = buf_load<T>(rC, cb + pa);
-            const T a01 = buf_load<T>(rC, ca + (int)sizeof(T)), a11 = buf_load<T>(rC, cb + (int)sizeof(T));
-            const T b01 = buf_load<T>(rC, ca + pa + (int)sizeof(T)), b11 = buf_load<T>(rC, cb + pa + (int)sizeof(T));
-            const T s0 = (a00 + a10) + (b00 + b10);
-            P.u0 += s0 * T(0.25);
-            P.u1 += (s0 + ((a01 + a11) + (b01 + b11))) * T(0.125);
-        }
         P.D0 = buf_load<T>(rD, vo); P.D1 = buf_load<T>(rD, vo + (int)sizeof(T));
         P.q0 = buf_load<T>(rQ, vo); P.q1 = buf_load<T>(rQ, vo + (int)sizeof(T));
         P.w0 = buf_load<T>(rW, vo); P.w1 = buf_load<T>(rW, vo + (int)sizeof(T));
     };
+    // prolongation of the coarse correction onto the pair of plane p: the
+    // coarse values are loaded two steps before plane p is first used (they
+    // are few and cached) and added one step before
+    struct Coarse {
+        T a00, a10, b00, b10, a01, a11, b01, b11;
+    };
+    auto load_coarse = [&](int p, Coarse& C) {
+        const int ca = co0 + (p >> 1) * cplane_bytes, cb = co1 + (p >> 1) * cplane_bytes;
+        const int pa = (p & 1) * cplane_bytes;
+        C.a00 = buf_load<T>(rC, ca); C.a10 = buf_load<T>(rC, cb);
+        C.b00 = buf_load<T>(rC, ca + pa); C.b10 = buf_load<T>(rC, cb + pa);
+        C.a01 = buf_load<T>(rC, ca + (int)sizeof(T)); C.a11 = buf_load<T>(rC, cb + (int)sizeof(T));
+        C.b01 = buf_load<T>(rC, ca + pa + (int)sizeof(T)); C.b11 = buf_load<T>(rC, cb + pa + (int)sizeof(T));
+    };
+    auto add_coarse = [&](const Coarse& C, SweepPlane<T>& P) {
+        const T s0 = (C.a00 + C.a10) + (C.b00 + C.b10);
+        P.u0 += s0 * T(0.25);
+        P.u1 += (s0 + ((C.a01 + C.a11) + (C.b01 + C.b11))) * T(0.125);
+    };
+    Coarse Ca, Cb;   // planes p with (p - s0) even, odd
 
     // Gauss-Seidel value of element O of the pair on a plane whose slot is
     // S: w (q + sum_j c_ij u_j); x-neighbours from the planes below (Pb) and
@@ -221,6 +230,7 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
     auto step = [&](auto Kc, int s, SweepPlane<T>& Pm4, SweepPlane<T>& Pm3, SweepPlane<T>& Pm2, SweepPlane<T>& Pm1,
                     SweepPlane<T>& P0, SweepPlane<T>& Pp1) {
         constexpr int K = decltype(Kc)::value;
+        if (PROLONG) add_coarse((K & 1) ? Ca : Cb, Pp1);   // plane s+1, first used now
         UD<T>* S = ring + K * 2 * RA;
         S[pe] = UD<T>{P0.u0, P0.D0};
         S[RA + pe] = UD<T>{P0.u1, P0.D1};
@@ -232,6 +242,7 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
             buf_store<T>(Pm3.u0, rO, soff0 + po * plane_bytes);
             buf_store<T>(Pm3.u1, rO, soff1 + po * plane_bytes);
         }
+        if (PROLONG) load_coarse(s + 2, (K & 1) ? Cb : Ca);   // before the plane loads of this step
     };
 
     // register ring of eight planes, the march unrolled by eight so planes
@@ -246,6 +257,14 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
     load(s0 + 1, R5);
     load(s0 + 2, R6);
     load(s0 + 3, R7);
+    if (PROLONG) {   // planes up to s0 now, s0+1 at step s0
+        SweepPlane<T>* Ps[] = {&R0, &R1, &R2, &R3, &R4};
+        for (int i = 0; i < 5; i++) {
+            load_coarse(s0 - 4 + i, Ca);
+            add_coarse(Ca, *Ps[i]);
+        }
+        load_coarse(s0 + 1, Cb);
+    }
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;

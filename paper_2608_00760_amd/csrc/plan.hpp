@@ -67,7 +67,7 @@ struct dmgs_plan_s {
     double* xalt64 = nullptr;      // second finest-level float64 iterate (refinement ping-pong)
     // fused-pass configuration
     int cfg_sweep = 0, cfg_fuse_min = 32;
-    int cfg_sweep2_min = 129, cfg_sweep2_wgs = 256;   // two-sweep passes: smallest N, target workgroups
+    int cfg_sweep2_min = 64, cfg_sweep2_wgs = 256;   // two-sweep passes: smallest N, target workgroups
     int small32 = -1, small64 = -1;   // first level of the single-workgroup coarse kernel
     double* partial = nullptr;     // first-stage reduction partials
     double* dnorm = nullptr;       // device reduction results (4 slots)
