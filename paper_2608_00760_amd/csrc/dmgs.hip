@@ -517,12 +517,15 @@ int launch_small_t(dmgs_plan P, int k, const T* q, T* u, int order, hipStream_t 
     SmallArgs<T> a;
     int Ns[kSmallMaxLevels];
     a.nlev = P->L - k;
+    int off = 0;
     for (int i = 0; i < a.nlev; i++) {
         const Level& l = P->lev[k + i];
         a.lev[i].N = Ns[i] = l.N;
+        a.lev[i].nv = (int)l.nv;
+        a.lev[i].off = off;
+        off += 4 * (int)l.nv;
         a.lev[i].D = Typed<T>::D(l);
         a.lev[i].w = Typed<T>::w(l);
-        a.lev[i].mu = Typed<T>::mu(l);
         a.lev[i].st = l.stencil<T>(HARM);
     }
     const Level& c = P->lev[P->L - 1];
@@ -534,6 +537,7 @@ int launch_small_t(dmgs_plan P, int k, const T* q, T* u, int order, hipStream_t 
     a.nu_pre = P->opt.nu_pre;
     a.nu_post = P->opt.nu_post;
     a.order = order;
+    a.roff = off;
     size_t bytes = small_lds_bytes<T>(Ns, a.nlev);
     hipLaunchKernelGGL((k_small_vcycle<T, HARM>), dim3(1), dim3(kSmallThreads), bytes, st, a);
     LAUNCHCHK();

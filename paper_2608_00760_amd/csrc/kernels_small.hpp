@@ -7,6 +7,14 @@
 // restriction, prolongation) is one barrier-separated phase, and the coarsest
 // level is solved exactly in float64 by one thread.  This replaces dozens of
 // launches of a few microseconds each per cycle by one.
+//
+// The work of a phase is spread over the threads with power-of-two padded
+// index maps (plane, row, column from shifts and masks).  The operator's
+// diagonal is taken as 1/w from the inverse diagonal the smoother uses.  A
+// level entered from a zero iterate starts its first half-sweep without
+// neighbours (u = w q on the first colour), which is folded into the phase
+// that produces q; the prolongated correction is added only to the colour
+// the next half-sweep reads (the other colour is overwritten by it).
 #pragma once
 #include "grid.hpp"
 #include "kernels_basic.hpp"
@@ -19,9 +27,10 @@ constexpr int kSmallThreads = 1024;
 template <class T>
 struct SmallLevel {
     int N;
+    int off;       // LDS offset (elements) of the level's arrays u, q, D, w (each nv long)
+    int nv;        // (N+1)^3
     const T* D;    // level coefficient arrays, (N+1)^3
     const T* w;    // inverse diagonal
-    const T* mu;
     Stencil<T> st;
 };
 
@@ -35,106 +44,128 @@ struct SmallArgs {
     const double* muc;
     Stencil<double> stc;
     int nu_pre, nu_post, order;
+    int roff;                          // LDS offset of the defect scratch
 };
 
+// LDS layout: level i's u, q, D, w at offsets off_i + {0, 1, 2, 3} nv_i,
+// levels in order, then the defect scratch (nv of the first level).
 template <class T>
 __host__ __device__ inline size_t small_lds_bytes(const int* Ns, int nlev) {
     size_t b = 0, first = 0;
     for (int i = 0; i < nlev; i++) {
         size_t n = (size_t)Ns[i] + 1, nv = n * n * n;
         if (i == 0) first = nv;
-        b += 5 * nv * sizeof(T);   // u, q, D, w, mu
+        b += 4 * nv * sizeof(T);   // u, q, D, w
     }
     return b + first * sizeof(T);  // defect scratch
 }
 
+__device__ __forceinline__ int ilog2_ceil(int v) { return v <= 1 ? 0 : 32 - __builtin_clz(v - 1); }
+
 template <class T, bool HARM>
 __global__ __launch_bounds__(kSmallThreads) void k_small_vcycle(SmallArgs<T> a) {
     extern __shared__ __align__(16) unsigned char small_smem[];
-    T* base = reinterpret_cast<T*>(small_smem);
-    T *U[kSmallMaxLevels], *Q[kSmallMaxLevels], *D[kSmallMaxLevels], *W[kSmallMaxLevels], *M[kSmallMaxLevels];
+    T* const base = reinterpret_cast<T*>(small_smem);
+    // level arrays addressed from the LDS base (no pointer tables: they
+    // would be indexed at run time and lose the address space)
+    auto U = [&](int i) { return base + a.lev[i].off; };
+    auto Q = [&](int i) { return base + a.lev[i].off + a.lev[i].nv; };
+    auto D = [&](int i) { return base + a.lev[i].off + 2 * a.lev[i].nv; };
+    auto W = [&](int i) { return base + a.lev[i].off + 3 * a.lev[i].nv; };
+    T* const R = base + a.roff;
     const int tid = threadIdx.x;
+    const int first = a.order ? 1 : 0;   // colour of the first half-sweep
+    const bool pre1 = a.nu_pre > 0;        // the first half-sweep from zero is folded in
+
+    // level arrays into LDS: every load of the level is issued before the
+    // first LDS write; the first level starts its pre-smoothing from zero,
+    // so its first half-sweep is u = w q on the first colour
     {
-        T* p = base;
+        constexpr int kPer = (17 * 17 * 17 + kSmallThreads - 1) / kSmallThreads;   // N <= 16
         for (int i = 0; i < a.nlev; i++) {
-            int n = a.lev[i].N + 1, nv = n * n * n;
-            U[i] = p; p += nv;
-            Q[i] = p; p += nv;
-            D[i] = p; p += nv;
-            W[i] = p; p += nv;
-            M[i] = p; p += nv;
-        }
-        for (int i = a.nlev; i < kSmallMaxLevels; i++) U[i] = Q[i] = D[i] = W[i] = M[i] = nullptr;
-    }
-    T* R = base;   // defect scratch follows the last level
-    for (int i = 0; i < a.nlev; i++) {
-        const int n = a.lev[i].N + 1;
-        R += 5 * n * n * n;
-    }
-    for (int i = 0; i < a.nlev; i++) {
-        const int n = a.lev[i].N + 1, nv = n * n * n;
-        for (int v = tid; v < nv; v += kSmallThreads) {
-            U[i][v] = T(0);
-            Q[i][v] = i == 0 ? a.q[v] : T(0);
-            D[i][v] = a.lev[i].D[v];
-            W[i][v] = a.lev[i].w[v];
-            M[i][v] = a.lev[i].mu[v];
+            const int N = a.lev[i].N, n = N + 1, nv = n * n * n;
+            T d[kPer], w[kPer], q[kPer];
+#pragma unroll
+            for (int k = 0; k < kPer; k++) {
+                const int v = tid + k * kSmallThreads;
+                d[k] = v < nv ? a.lev[i].D[v] : T(0);
+                w[k] = v < nv ? a.lev[i].w[v] : T(0);
+                q[k] = (i == 0 && v < nv) ? a.q[v] : T(0);
+            }
+#pragma unroll
+            for (int k = 0; k < kPer; k++) {
+                const int v = tid + k * kSmallThreads;
+                if (v < nv) {
+                    D(i)[v] = d[k];
+                    W(i)[v] = w[k];
+                    Q(i)[v] = q[k];
+                    T u0 = T(0);
+                    if (i == 0) {
+                        const int z = v % n, y = (v / n) % n, x = v / (n * n);
+                        if (pre1 && ((x + y + z) & 1) == first) u0 = w[k] * q[k];   // w = 0 on the boundary
+                    }
+                    U(i)[v] = u0;
+                }
+            }
         }
     }
     __syncthreads();
 
-    auto sweep_half = [&](int i, int colour) {
-        const int N = a.lev[i].N, n = N + 1, Ni = N - 1, M2 = N / 2;
-        const Stencil<T> st = a.lev[i].st;
-        T* u = U[i];
-        const T *q = Q[i], *Dl = D[i], *w = W[i];
-        const int total = Ni * Ni * M2;
-        for (int t = tid; t < total; t += kSmallThreads) {
-            const int zz = t % M2, r = t / M2;
-            const int y = 1 + r % Ni, x = 1 + r / Ni;
-            const int z = 1 + ((x + y + 1 + colour) & 1) + 2 * zz;
-            if (z > N - 1) continue;
-            const int v = (x * n + y) * n + z, sx = n * n;
-            const T Di = Dl[v];
-            const T num = q[v] + face<HARM>(Di, Dl[v + sx], st) * u[v + sx] + face<HARM>(Di, Dl[v - sx], st) * u[v - sx] +
-                          face<HARM>(Di, Dl[v + n], st) * u[v + n] + face<HARM>(Di, Dl[v - n], st) * u[v - n] +
-                          face<HARM>(Di, Dl[v + 1], st) * u[v + 1] + face<HARM>(Di, Dl[v - 1], st) * u[v - 1];
-            u[v] = num * w[v];
-        }
-        __syncthreads();
-    };
-    auto sweeps = [&](int i, int count) {
-        const int first = a.order ? 1 : 0;
-        for (int c = 0; c < count; c++) {
-            sweep_half(i, first);
-            sweep_half(i, 1 - first);
-        }
-    };
-    auto defect_restrict = [&](int i) {
+    // thread map of the interior points of one colour: plane offset, row
+    // and pair index from shifts; NP2 = pow2 >= N/2 pairs, NY2 = pow2 >= N-1 rows
+    auto half_sweep = [&](int i, int colour) {
         const int N = a.lev[i].N, n = N + 1, sx = n * n;
+        const int lz = ilog2_ceil(N / 2), ly = ilog2_ceil(N - 1), lp = lz + ly;
         const Stencil<T> st = a.lev[i].st;
-        const T *u = U[i], *q = Q[i], *Dl = D[i], *mu = M[i];
-        const int nv = n * n * n;
-        for (int v = tid; v < nv; v += kSmallThreads) {
-            const int z = v % n, y = (v / n) % n, x = v / sx;
-            T r = T(0);
-            if (is_interior(N, x, y, z)) {
-                const T Di = Dl[v], ui = u[v];
-                const T Au = mu[v] * ui + face<HARM>(Di, Dl[v + sx], st) * (ui - u[v + sx]) +
-                             face<HARM>(Di, Dl[v - sx], st) * (ui - u[v - sx]) + face<HARM>(Di, Dl[v + n], st) * (ui - u[v + n]) +
-                             face<HARM>(Di, Dl[v - n], st) * (ui - u[v - n]) + face<HARM>(Di, Dl[v + 1], st) * (ui - u[v + 1]) +
-                             face<HARM>(Di, Dl[v - 1], st) * (ui - u[v - 1]);
-                r = q[v] - Au;
+        T* u = U(i);
+        const T *q = Q(i), *Dl = D(i), *w = W(i);
+        for (int it = tid; it < ((N - 1) << lp); it += kSmallThreads) {
+            const int zz = it & ((1 << lz) - 1), y = 1 + ((it >> lz) & ((1 << ly) - 1)), x = 1 + (it >> lp);
+            {
+                const int z = 1 + ((x + y + 1 + colour) & 1) + 2 * zz;
+                if (y > N - 1 || z > N - 1) continue;
+                const int v = (x * n + y) * n + z;
+                const T Di = Dl[v];
+                const T num = q[v] + face<HARM>(Di, Dl[v + sx], st) * u[v + sx] + face<HARM>(Di, Dl[v - sx], st) * u[v - sx] +
+                              face<HARM>(Di, Dl[v + n], st) * u[v + n] + face<HARM>(Di, Dl[v - n], st) * u[v - n] +
+                              face<HARM>(Di, Dl[v + 1], st) * u[v + 1] + face<HARM>(Di, Dl[v - 1], st) * u[v - 1];
+                u[v] = num * w[v];
             }
-            R[v] = r;
         }
         __syncthreads();
-        const int Nc = N / 2, nc = Nc + 1, nvc = nc * nc * nc;
-        T* qc = Q[i + 1];
-        for (int V = tid; V < nvc; V += kSmallThreads) {
-            const int Z = V % nc, Y = (V / nc) % nc, X = V / (nc * nc);
-            T s = T(0);
-            if (is_interior(Nc, X, Y, Z)) {
+    };
+    // r = q - A u on the interior (the restriction reads interior points only);
+    // the diagonal of A is 1/w
+    auto defect = [&](int i) {
+        const int N = a.lev[i].N, n = N + 1, sx = n * n;
+        const int lz = ilog2_ceil(N - 1), lp = 2 * lz;
+        const Stencil<T> st = a.lev[i].st;
+        const T *u = U(i), *q = Q(i), *Dl = D(i), *w = W(i);
+        for (int it = tid; it < ((N - 1) << lp); it += kSmallThreads) {
+            const int z = 1 + (it & ((1 << lz) - 1)), y = 1 + ((it >> lz) & ((1 << lz) - 1)), x = 1 + (it >> lp);
+            if (y <= N - 1 && z <= N - 1) {
+                const int v = (x * n + y) * n + z;
+                const T Di = Dl[v];
+                const T off = face<HARM>(Di, Dl[v + sx], st) * u[v + sx] + face<HARM>(Di, Dl[v - sx], st) * u[v - sx] +
+                              face<HARM>(Di, Dl[v + n], st) * u[v + n] + face<HARM>(Di, Dl[v - n], st) * u[v - n] +
+                              face<HARM>(Di, Dl[v + 1], st) * u[v + 1] + face<HARM>(Di, Dl[v - 1], st) * u[v - 1];
+                R[v] = q[v] - (u[v] / w[v] - off);
+            }
+        }
+        __syncthreads();
+    };
+    // q_{i+1} = R r on the coarse interior, and the first half-sweep of
+    // level i+1 from its zero iterate (u = w q on the first colour)
+    auto restrict_start = [&](int i) {
+        const int N = a.lev[i].N, n = N + 1;
+        const int Nc = N / 2, nc = Nc + 1;
+        const int lz = ilog2_ceil(Nc - 1), lp = 2 * lz;
+        T *qc = Q(i + 1), *uc = U(i + 1);
+        const T* wc = W(i + 1);
+        for (int it = tid; it < ((Nc - 1) << lp); it += kSmallThreads) {
+            const int Z = 1 + (it & ((1 << lz) - 1)), Y = 1 + ((it >> lz) & ((1 << lz) - 1)), X = 1 + (it >> lp);
+            if (Y <= Nc - 1 && Z <= Nc - 1) {
+                T s = T(0);
                 for (int da = -1; da <= 1; da++)
                     for (int db = -1; db <= 1; db++) {
                         const T wab = T((2 - abs(da)) * (2 - abs(db)));
@@ -142,42 +173,59 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_vcycle(SmallArgs<T> a) 
                         s += wab * (row[-1] + T(2) * row[0] + row[1]);
                     }
                 s *= T(1.0 / 64.0);
+                const int V = (X * nc + Y) * nc + Z;
+                qc[V] = s;
+                uc[V] = (pre1 && ((X + Y + Z) & 1) == first) ? wc[V] * s : T(0);
             }
-            qc[V] = s;
         }
         __syncthreads();
     };
-    auto prolong_add = [&](int i) {
+    // u_i += I u_{i+1} on the interior points of one colour
+    auto prolong_add = [&](int i, int colour) {
         const int N = a.lev[i].N, n = N + 1, nc = N / 2 + 1;
-        T* u = U[i];
-        const T* ec = U[i + 1];
-        const int nv = n * n * n;
-        for (int v = tid; v < nv; v += kSmallThreads) {
-            const int z = v % n, y = (v / n) % n, x = v / (n * n);
-            if (!is_interior(N, x, y, z)) continue;
-            const int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
-            const int x1 = x0 + (x & 1), y1 = y0 + (y & 1), z1 = z0 + (z & 1);
-            auto E = [&](int X, int Y, int Z) { return ec[(X * nc + Y) * nc + Z]; };
-            const T s = E(x0, y0, z0) + E(x0, y0, z1) + E(x0, y1, z0) + E(x0, y1, z1) + E(x1, y0, z0) + E(x1, y0, z1) +
-                        E(x1, y1, z0) + E(x1, y1, z1);
-            u[v] += s * T(0.125);
+        const int lz = ilog2_ceil(N / 2), ly = ilog2_ceil(N - 1), lp = lz + ly;
+        T* u = U(i);
+        const T* ec = U(i + 1);
+        for (int it = tid; it < ((N - 1) << lp); it += kSmallThreads) {
+            const int zz = it & ((1 << lz) - 1), y = 1 + ((it >> lz) & ((1 << ly) - 1)), x = 1 + (it >> lp);
+            {
+                const int z = 1 + ((x + y + 1 + colour) & 1) + 2 * zz;
+                if (y > N - 1 || z > N - 1) continue;
+                const int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
+                const int x1 = x0 + (x & 1), y1 = y0 + (y & 1), z1 = z0 + (z & 1);
+                auto E = [&](int X, int Y, int Z) { return ec[(X * nc + Y) * nc + Z]; };
+                const T s = E(x0, y0, z0) + E(x0, y0, z1) + E(x0, y1, z0) + E(x0, y1, z1) + E(x1, y0, z0) +
+                            E(x1, y0, z1) + E(x1, y1, z0) + E(x1, y1, z1);
+                u[(x * n + y) * n + z] += s * T(0.125);
+            }
         }
         __syncthreads();
+    };
+    // nu sweeps, the first half-sweep of the first one already done when skip1
+    auto sweeps = [&](int i, int count, bool skip1) {
+        for (int c = 0; c < count; c++) {
+            if (!(skip1 && c == 0)) half_sweep(i, first);
+            half_sweep(i, 1 - first);
+        }
     };
 
     const int L = a.nlev;
-    for (int i = 0; i < L - 1; i++) {   // down: coarse iterates start from zero
-        sweeps(i, a.nu_pre);
-        defect_restrict(i);
+    for (int i = 0; i < L - 1; i++) {   // down: every level starts from a zero iterate
+        sweeps(i, a.nu_pre, pre1);
+        defect(i);
+        restrict_start(i);
     }
-    if (tid == 0) dense_exact_solve(Q[L - 1], U[L - 1], a.Dc, a.muc, a.lev[L - 1].N, a.stc);
+    if (tid == 0) dense_exact_solve(Q(L - 1), U(L - 1), a.Dc, a.muc, a.lev[L - 1].N, a.stc);
     __syncthreads();
     for (int i = L - 2; i >= 0; i--) {  // up
-        prolong_add(i);
-        sweeps(i, a.nu_post);
+        // the next half-sweep updates the first colour from the second
+        // colour's values; with no post-smoothing both colours are corrected
+        prolong_add(i, 1 - first);
+        if (a.nu_post == 0) prolong_add(i, first);
+        sweeps(i, a.nu_post, false);
     }
     const int n0 = a.lev[0].N + 1, nv0 = n0 * n0 * n0;
-    for (int v = tid; v < nv0; v += kSmallThreads) a.u[v] = U[0][v];
+    for (int v = tid; v < nv0; v += kSmallThreads) a.u[v] = U(0)[v];
 }
 
 }  // namespace dmgs
