@@ -15,6 +15,7 @@
 #include "kernels_basic.hpp"
 #include "kernels_stream.hpp"
 #include "kernels_sweep2.hpp"
+#include "kernels_block.hpp"
 #include "kernels_small.hpp"
 #include "plan.hpp"
 
@@ -483,11 +484,85 @@ int coarsest(dmgs_plan P, const T* q, T* u, hipStream_t st) {
 
 bool fused_level(dmgs_plan P, int k) { return P->lev[k].N >= P->cfg_fuse_min && k < P->L - 1; }
 
+// Mid-size float32 levels run each smoothing phase as one block launch
+// (zero boundary: the refinement corrections; two sweeps each way).
+template <class T>
+bool block_level(dmgs_plan P, int k) {
+    const int N = P->lev[k].N;
+    return sizeof(T) == 4 && is_ir(P) && k < P->L - 1 && N > 16 && N <= P->cfg_block_max && P->opt.nu_pre == 2 &&
+           P->opt.nu_post == 2;
+}
+
+constexpr int kBlockB = 8;
+
+template <class T, int MODE, bool HARM>
+int launch_block_t(dmgs_plan P, const BlockArgs<T>& a, hipStream_t st) {
+    const int nb3 = a.nb * a.nb * a.nb;
+    const size_t lds = BlockShape<kBlockB, MODE>::lds_bytes(sizeof(T));
+    hipLaunchKernelGGL((k_block_pass<T, kBlockB, MODE, HARM>), dim3(nb3), dim3(kBlockThreads), lds, st, a);
+    LAUNCHCHK();
+    return DMGS_OK;
+}
+
+// One block phase on level k: pre (from *cur or from zero; qc written) or
+// post (*cur + I ec); the result goes to *other and the buffers swap.
+template <class T>
+int block_phase(dmgs_plan P, int k, T** cur, T** other, const T* q, T* qc, const T* ec, int order, bool zero,
+                bool post, hipStream_t st) {
+    const Level& l = P->lev[k];
+    BlockArgs<T> a;
+    a.u_in = *cur;
+    a.u_out = *other;
+    a.q = q;
+    a.D = Typed<T>::D(l);
+    a.w = Typed<T>::w(l);
+    a.ec = ec;
+    a.qc = qc;
+    a.N = l.N;
+    a.nb = (l.N - 1 + kBlockB - 1) / kBlockB;
+    a.order = order;
+    a.st = l.stencil<T>(harmonic(P));
+    const int mode = post ? kBlockPost : (zero ? kBlockPreZero : kBlockPre);
+    const double words = (zero ? 4.0 : 5.0) + 0.125;
+    int slot;
+    TRY(tbeg(P, k, st, &slot));
+    if constexpr (sizeof(T) == 4) {
+        const bool h = harmonic(P);
+        if (mode == kBlockPost) TRY(h ? (launch_block_t<T, kBlockPost, true>(P, a, st)) : (launch_block_t<T, kBlockPost, false>(P, a, st)));
+        else if (mode == kBlockPre) TRY(h ? (launch_block_t<T, kBlockPre, true>(P, a, st)) : (launch_block_t<T, kBlockPre, false>(P, a, st)));
+        else TRY(h ? (launch_block_t<T, kBlockPreZero, true>(P, a, st)) : (launch_block_t<T, kBlockPreZero, false>(P, a, st)));
+    } else {
+        set_error("block passes are float32 only");
+        return DMGS_ERR_INVALID;
+    }
+    TRY(tend(P, slot, DMGS_K_SMOOTH, words * l.nv * sizeof(T), st));
+    std::swap(*cur, *other);
+    return DMGS_OK;
+}
+
+// Dynamic-LDS limits of the block kernels (set once per plan).
+int block_attributes() {
+    const void* fns[] = {
+        (const void*)k_block_pass<float, kBlockB, kBlockPreZero, false>, (const void*)k_block_pass<float, kBlockB, kBlockPreZero, true>,
+        (const void*)k_block_pass<float, kBlockB, kBlockPre, false>, (const void*)k_block_pass<float, kBlockB, kBlockPre, true>,
+        (const void*)k_block_pass<float, kBlockB, kBlockPost, false>, (const void*)k_block_pass<float, kBlockB, kBlockPost, true>};
+    const int lims[] = {(int)BlockShape<kBlockB, kBlockPreZero>::lds_bytes(4), (int)BlockShape<kBlockB, kBlockPreZero>::lds_bytes(4),
+                        (int)BlockShape<kBlockB, kBlockPre>::lds_bytes(4), (int)BlockShape<kBlockB, kBlockPre>::lds_bytes(4),
+                        (int)BlockShape<kBlockB, kBlockPost>::lds_bytes(4), (int)BlockShape<kBlockB, kBlockPost>::lds_bytes(4)};
+    for (int i = 0; i < 6; i++)
+        if (hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, lims[i]) != hipSuccess) {
+            set_error("hipFuncSetAttribute failed");
+            return DMGS_ERR_HIP;
+        }
+    return DMGS_OK;
+}
+
 // Pre-smoothing pass on level k: nu_pre sweeps from *cur (or from 0), then
 // qc = R (q - A u).  Simple levels work in place.
 template <class T>
 int pre_pass(dmgs_plan P, int k, T** cur, T** other, const T* q, T* qc, int order, bool zero, hipStream_t st) {
     const Level& l = P->lev[k];
+    if (block_level<T>(P, k)) return block_phase<T>(P, k, cur, other, q, qc, (const T*)nullptr, order, zero, false, st);
     if (fused_level(P, k)) {
         TRY(smooth_phase<T>(P, k, cur, other, q, P->opt.nu_pre, order, zero, (const T*)nullptr, st));
         return defect_restrict<T>(P, k, *cur, q, qc, st);
@@ -506,6 +581,7 @@ int pre_pass(dmgs_plan P, int k, T** cur, T** other, const T* q, T* qc, int orde
 template <class T>
 int post_pass(dmgs_plan P, int k, T** cur, T** other, const T* ec, const T* q, int order, hipStream_t st) {
     const Level& l = P->lev[k];
+    if (block_level<T>(P, k)) return block_phase<T>(P, k, cur, other, q, (T*)nullptr, ec, order, false, true, st);
     if (fused_level(P, k)) return smooth_phase<T>(P, k, cur, other, q, P->opt.nu_post, order, false, ec, st);
     TIMED(P, k, DMGS_K_PROLONG, (double)(2 * l.nv + P->lev[k + 1].nv) * sizeof(T), st,
           hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, ec, *cur, l.N));
@@ -943,6 +1019,9 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
             }
     }
     if (st == DMGS_OK) st = sweep2_attributes();
+    if (st == DMGS_OK) st = block_attributes();
+    P->cfg_block_max = 64;
+    if (const char* e = std::getenv("DMGS_BLOCK_MAX")) P->cfg_block_max = std::atoi(e);
     P->cfg_sweep2_min = 64;
     P->cfg_sweep2_wgs = 256;
     if (const char* e = std::getenv("DMGS_SWEEP2_MIN")) P->cfg_sweep2_min = std::max(16, std::atoi(e));

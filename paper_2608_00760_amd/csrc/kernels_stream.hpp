@@ -43,6 +43,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, i
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(b), 0, valid ? (int)plane_bytes : 0, 0x00020000);
 }
 
+// Resource over a whole field of `bytes` (< 2^31) bytes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const void* base, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+
 template <class T> __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int off);
 template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));

@@ -72,10 +72,6 @@ __host__ __device__ constexpr bool sweep2_fits(int N) {
     return ((int64_t)(N + 1) * (N + 1) * (N + 20) + 64) * (int64_t)sizeof(T) < (int64_t)kOob;
 }
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const void* base, int64_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
-}
-
 template <class T, int TY, int TZ, int MODE, bool HARM>
 __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(SweepArgs<T> a) {
     constexpr bool ZERO_INIT = MODE == kSweepZero, PROLONG = MODE == kSweepProlong;
