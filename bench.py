@@ -214,7 +214,20 @@ def main():
         cpu = cpu_baseline(c, info_f["cycles"] * vc, info_a["cycles"] * vc)
         log("oracle: %.4f pairs/s (%s)" % (cpu["value"], cpu["sample"]))
 
+    # V-cycle time against the one-pass-per-operator byte model: 4 sweeps of 5
+    # words, defect and restriction 4 + 1/8, prolongation and correction
+    # 2 + 1/8 words per fine vertex, times the size of all levels over the
+    # finest; the refinement residual, set-up and gradient passes are taken out
     nv = (N + 1) ** 3
+    word = 4 if args.precision == "fp32-in-fp64" else 8
+    levels = sum(((N >> k) + 1) ** 3 for k in range(P.levels)) / nv
+    model_bytes = 26.25 * word * nv * levels
+    vc = (args.inner if args.precision == "fp32-in-fp64" else 1) * (info_f["cycles"] + info_a["cycles"])
+    other_ms = sum(stats[k]["ms"] for k in ("residual", "update", "coef", "grad") if k in stats)
+    vcycle_us = (elapsed * 1e3 - other_ms) / args.steps / vc * 1e3
+    vcycle = {"vcycles_per_step": vc, "us": vcycle_us, "model_bytes": model_bytes,
+              "model_GBps": model_bytes / (vcycle_us * 1e-6) / 1e9,
+              "frac": model_bytes / (vcycle_us * 1e-6) / 1e9 / HBM_PEAK_GBPS}
     out = {
         "metric": "fwd+VJP solves/s at 256^3 (1e-10 rel. residual); GB/s vs HBM peak",
         "value": args.steps / elapsed,
@@ -239,6 +252,7 @@ def main():
                      "traffic": measured_traffic(dom) if N == 256 and args.precision == "fp32-in-fp64" else None,
                      "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": bytes_per_launch},
         "kernels": kernels,
+        "vcycle": vcycle,
         "fp64_solver": fp64,
         "latency_p50_p99": serving,
         "cpu_baseline": cpu,
