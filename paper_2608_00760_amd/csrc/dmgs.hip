@@ -407,13 +407,17 @@ int smooth_pass2(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int or
     return DMGS_OK;
 }
 
+// Chunks of coarse planes sized for about cfg_dr_wgs workgroups (each
+// chunk re-reads the fine planes at its ends), at least 4.
 template <class T, int TYC, int TZC, bool HARM>
-int launch_restrict(const RestrictArgs<T>& a0, int Nc, hipStream_t st) {
+int launch_restrict(dmgs_plan P, const RestrictArgs<T>& a0, int Nc, hipStream_t st) {
     RestrictArgs<T> a = a0;
     constexpr int NT = RestrictShape<TYC, TZC>::NT;
     a.tiles_y = (Nc - 1 + TYC - 1) / TYC;
     a.tiles_z = (Nc - 1 + TZC - 1) / TZC;
-    a.chunk = std::max(4, choose_chunk(Nc - 1, a.tiles_y * a.tiles_z) / 2);
+    const int tiles = a.tiles_y * a.tiles_z;
+    const int nch = std::max(1, (P->cfg_dr_wgs + tiles - 1) / tiles);
+    a.chunk = std::max(4, (Nc - 1 + nch - 1) / nch);
     if (a.chunk > Nc - 1) a.chunk = Nc - 1;
     a.nchunks = (Nc - 1 + a.chunk - 1) / a.chunk;
     int nb = a.tiles_y * a.tiles_z * a.nchunks;
@@ -437,8 +441,8 @@ int defect_restrict(dmgs_plan P, int k, const T* u, const T* q, T* qc, hipStream
     constexpr int TYC = 8, TZC = sizeof(T) == 4 ? 32 : 16;
     int slot;
     TRY(tbeg(P, k, st, &slot));
-    if (harmonic(P)) TRY((launch_restrict<T, TYC, TZC, true>(a, c.N, st)));
-    else TRY((launch_restrict<T, TYC, TZC, false>(a, c.N, st)));
+    if (harmonic(P)) TRY((launch_restrict<T, TYC, TZC, true>(P, a, c.N, st)));
+    else TRY((launch_restrict<T, TYC, TZC, false>(P, a, c.N, st)));
     TRY(tend(P, slot, DMGS_K_DEFECT_RESTRICT, (4.0 * l.nv + c.nv) * sizeof(T), st));
     return DMGS_OK;
 }
@@ -1021,6 +1025,8 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     if (st == DMGS_OK) st = sweep2_attributes();
     if (st == DMGS_OK) st = block_attributes();
     P->cfg_block_max = 64;
+    P->cfg_dr_wgs = 512;
+    if (const char* e = std::getenv("DMGS_DR_WGS")) P->cfg_dr_wgs = std::max(16, std::atoi(e));
     if (const char* e = std::getenv("DMGS_BLOCK_MAX")) P->cfg_block_max = std::atoi(e);
     P->cfg_sweep2_min = 64;
     P->cfg_sweep2_wgs = 256;

@@ -69,6 +69,7 @@ struct dmgs_plan_s {
     int cfg_sweep = 0, cfg_fuse_min = 32;
     int cfg_sweep2_min = 64, cfg_sweep2_wgs = 256;   // two-sweep passes: smallest N, target workgroups
     int cfg_block_max = 64;                         // block passes: largest N
+    int cfg_dr_wgs = 512;                           // defect-restriction passes: target workgroups
     int small32 = -1, small64 = -1;   // first level of the single-workgroup coarse kernel
     double* partial = nullptr;     // first-stage reduction partials
     double* dnorm = nullptr;       // device reduction results (4 slots)
