@@ -52,6 +52,9 @@ struct Sweep2Shape {
     static constexpr int SLOTS = 8;
     static constexpr int PAD = NP + 2;                       // guard entries before and after the ring
     static constexpr int ENTRIES = SLOTS * 2 * RA + 2 * PAD;
+    // coarse-correction planes (prolongation): rows and columns of the coarse
+    // vertices the tile plus its ring interpolates from, four planes
+    static constexpr int CRY = RY / 2 + 1, CRZ = NP + 1, CPL = CRY * CRZ, CSLOTS = 4;
     static_assert(TY % 2 == 0 && TZ % 2 == 0, "even tile");
 };
 
@@ -62,7 +65,8 @@ struct UD {
 
 template <class T, int TY, int TZ>
 constexpr size_t sweep2_lds_bytes() {
-    return (size_t)Sweep2Shape<TY, TZ>::ENTRIES * sizeof(UD<T>);
+    using Sh = Sweep2Shape<TY, TZ>;
+    return (size_t)Sh::ENTRIES * sizeof(UD<T>) + (size_t)Sh::CSLOTS * Sh::CPL * sizeof(T);
 }
 
 // Largest level the two-sweep pass takes: buffer offsets of a whole field
@@ -145,9 +149,8 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
         P.q0 = buf_load<T>(rQ, vo); P.q1 = buf_load<T>(rQ, vo + (int)sizeof(T));
         P.w0 = buf_load<T>(rW, vo); P.w1 = buf_load<T>(rW, vo + (int)sizeof(T));
     };
-    // prolongation of the coarse correction onto the pair of plane p: the
-    // coarse values are loaded two steps before plane p is first used (they
-    // are few and cached) and added one step before
+    // prolongation of the coarse correction onto the pair of plane p, from
+    // memory (the planes before the first step)
     struct Coarse {
         T a00, a10, b00, b10, a01, a11, b01, b11;
     };
@@ -164,7 +167,29 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
         P.u0 += s0 * T(0.25);
         P.u1 += (s0 + ((C.a01 + C.a11) + (C.b01 + C.b11))) * T(0.125);
     };
-    Coarse Ca, Cb;   // planes p with (p - s0) even, odd
+    // ... and from the LDS planes of the coarse correction during the march:
+    // coarse plane X is loaded at step 2X-4 by the first CPL threads, stored
+    // at step 2X-3 and read at steps 2X-2 .. 2X (fine planes 2X-1 .. 2X+1);
+    // writing a plane again stores the same values
+    T* const cring = reinterpret_cast<T*>(lds_raw + Sh::ENTRIES * sizeof(UD<T>));
+    const bool cloader = PROLONG && tid < Sh::CPL;
+    const int cy = tid / Sh::CRZ, cz = tid % Sh::CRZ;
+    const int cY = y0 / 2 - 2 + cy, cZ = z0 / 2 - 2 + cz;
+    const int coff = (cloader && cY >= 0 && cY < ncv && cZ >= 0 && cZ < ncv) ? (cY * ncv + cZ) * (int)sizeof(T) : kOob;
+    auto coarse_plane = [&](int X) {   // this loader thread's value of coarse plane X (0 outside the grid)
+        return buf_load<T>(rC, (X >= 0 && X < ncv) ? coff + X * cplane_bytes : kOob);
+    };
+    const int cl0 = (ly >> 1) * Sh::CRZ + pz;   // this pair's coarse row (even y) and column in a plane
+    const int cl1 = cl0 + hp * Sh::CRZ;         // the row below for odd y
+    auto add_coarse_lds = [&](int p, SweepPlane<T>& P) {
+        const int X0 = p >> 1, X1 = X0 + (p & 1);
+        const T* A = cring + (X0 & 3) * Sh::CPL;
+        const T* B = cring + (X1 & 3) * Sh::CPL;
+        const T s0 = (A[cl0] + A[cl1]) + (B[cl0] + B[cl1]);
+        P.u0 += s0 * T(0.25);
+        P.u1 += (s0 + ((A[cl0 + 1] + A[cl1 + 1]) + (B[cl0 + 1] + B[cl1 + 1]))) * T(0.125);
+    };
+    T cg = T(0);   // loader: coarse value in flight
 
     // Gauss-Seidel value of element O of the pair on a plane whose slot is
     // S: w (q + sum_j c_ij u_j); x-neighbours from the planes below (Pb) and
@@ -226,11 +251,17 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
     auto step = [&](auto Kc, int s, SweepPlane<T>& Pm4, SweepPlane<T>& Pm3, SweepPlane<T>& Pm2, SweepPlane<T>& Pm1,
                     SweepPlane<T>& P0, SweepPlane<T>& Pp1) {
         constexpr int K = decltype(Kc)::value;
-        if (PROLONG) add_coarse((K & 1) ? Ca : Cb, Pp1);   // plane s+1, first used now
         UD<T>* S = ring + K * 2 * RA;
         S[pe] = UD<T>{P0.u0, P0.D0};
         S[RA + pe] = UD<T>{P0.u1, P0.D1};
         lds_barrier();
+        if (PROLONG) {
+            add_coarse_lds(s + 1, Pp1);   // plane s+1, first used now
+            if (cloader) {
+                cring[(((s + 3) >> 1) & 3) * Sh::CPL + tid] = cg;   // coarse plane loaded at step s-1
+                cg = coarse_plane((s + 4) >> 1);
+            }
+        }
         if (par0 ^ (K & 1)) stages(std::integral_constant<int, 1>(), Kc, Pm4, Pm3, Pm2, Pm1, P0, Pp1);
         else stages(std::integral_constant<int, 0>(), Kc, Pm4, Pm3, Pm2, Pm1, P0, Pp1);
         const int po = s - 3;   // final
@@ -238,7 +269,6 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
             buf_store<T>(Pm3.u0, rO, soff0 + po * plane_bytes);
             buf_store<T>(Pm3.u1, rO, soff1 + po * plane_bytes);
         }
-        if (PROLONG) load_coarse(s + 2, (K & 1) ? Cb : Ca);   // before the plane loads of this step
     };
 
     // register ring of eight planes, the march unrolled by eight so planes
@@ -253,13 +283,17 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
     load(s0 + 1, R5);
     load(s0 + 2, R6);
     load(s0 + 3, R7);
-    if (PROLONG) {   // planes up to s0 now, s0+1 at step s0
+    if (PROLONG) {   // planes up to s0 from memory; coarse planes of steps s0 and s0+1 into LDS
         SweepPlane<T>* Ps[] = {&R0, &R1, &R2, &R3, &R4};
         for (int i = 0; i < 5; i++) {
-            load_coarse(s0 - 4 + i, Ca);
-            add_coarse(Ca, *Ps[i]);
+            Coarse C;
+            load_coarse(s0 - 4 + i, C);
+            add_coarse(C, *Ps[i]);
         }
-        load_coarse(s0 + 1, Cb);
+        if (cloader) {
+            for (int X = (s0 + 1) >> 1; X <= ((s0 + 2) >> 1); X++) cring[(X & 3) * Sh::CPL + tid] = coarse_plane(X);
+            cg = coarse_plane((s0 + 3) >> 1);
+        }
     }
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
