@@ -229,7 +229,9 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
     auto stage = [&](auto Oc, auto Jc, auto Kc, SweepPlane<T>& Pb, SweepPlane<T>& P, SweepPlane<T>& Pa) {
         constexpr int O = decltype(Oc)::value, J = decltype(Jc)::value, K = decltype(Kc)::value;
         UD<T>* S = ring + ((K - J + 8) & 7) * 2 * RA;
-        const T v = update(Oc, S, Pb, P, Pa);
+        // from a zero iterate every neighbour of the first colour is 0: the
+        // update is w q (the same value the full formula gives)
+        const T v = (ZERO_INIT && J == 0) ? (O ? P.q1 * P.w1 : P.q0 * P.w0) : update(Oc, S, Pb, P, Pa);
         if (O) {
             P.u1 = m1[J] ? v : P.u1;
             if (J < 3) S[RA + pe].u = P.u1;
