@@ -146,7 +146,6 @@ void free_plan(dmgs_plan P) {
     if (P->scratch64) (void)hipFree(P->scratch64);
     if (P->xalt64) (void)hipFree(P->xalt64);
     if (P->partial) (void)hipFree(P->partial);
-    if (P->dnorm) (void)hipFree(P->dnorm);
     if (P->dflag) (void)hipFree(P->dflag);
     if (P->hnorm) (void)hipHostFree(P->hnorm);
     if (P->hflag) (void)hipHostFree(P->hflag);
@@ -649,9 +648,9 @@ int vcycle(dmgs_plan P, int k, T** cur, T** other, const T* q, int order, bool z
     return post_pass<T>(P, k, cur, other, ccur, q, order, st);
 }
 
-// ||b - A x||^2 into dnorm[slot] with the fused float64 kernel; with e, also
+// ||b - A x||^2 into the plan's host norm slot `slot` (fused float64 kernel); with e, also
 // x_out = x + e and r32 = float(b - A x_out).
-template <bool HAS_E, bool HARM>
+template <bool HAS_E, bool X_ZERO, bool HARM>
 void launch_ir(const IrArgs& a0, int N, hipStream_t st, unsigned* nb_out) {
     constexpr int TY = 16, TZ = 64;
     IrArgs a = a0;
@@ -664,12 +663,14 @@ void launch_ir(const IrArgs& a0, int N, hipStream_t st, unsigned* nb_out) {
         a.nchunks = (N - 1 + a.chunk - 1) / a.chunk;
     }
     unsigned nb = (unsigned)(a.tiles_y * a.tiles_z * a.nchunks);
-    hipLaunchKernelGGL((k_ir_residual_col<TY, TZ, HAS_E, HARM>), dim3(nb), dim3(IrShape<TY, TZ>::NT), 0, st, a);
+    hipLaunchKernelGGL((k_ir_residual_col<TY, TZ, HAS_E, X_ZERO, HARM>), dim3(nb), dim3(IrShape<TY, TZ>::NT), 0, st, a);
     *nb_out = nb;
 }
 
+// x_zero: x is 0 everywhere (the boundary value is 0 and nothing has been
+// added yet); x is not read.
 int ir_step(dmgs_plan P, const double* x, const float* e, double* x_out, const double* b, float* r32, int slot,
-            hipStream_t st) {
+            hipStream_t st, bool x_zero = false) {
     const Level& l = P->lev[0];
     IrArgs a;
     a.x = x;
@@ -682,26 +683,30 @@ int ir_step(dmgs_plan P, const double* x, const float* e, double* x_out, const d
     a.partial = P->partial;
     a.N = l.N;
     a.st = l.stencil<double>(harmonic(P));
-    double bytes = 32.0 * l.nv + (e ? 4.0 * l.nv : 0.0) + (x_out ? 8.0 * l.nv : 0.0) + (r32 ? 4.0 * l.nv : 0.0);
+    double bytes = (x_zero ? (e ? 24.0 : 8.0) : 32.0) * l.nv + (e ? 4.0 * l.nv : 0.0) + (x_out ? 8.0 * l.nv : 0.0) +
+                   (r32 ? 4.0 * l.nv : 0.0);
     unsigned nb = 0;
     int tslot;
     TRY(tbeg(P, 0, st, &tslot));
+    const bool h = harmonic(P);
     if (e) {
-        if (harmonic(P)) launch_ir<true, true>(a, l.N, st, &nb);
-        else launch_ir<true, false>(a, l.N, st, &nb);
+        if (x_zero) h ? launch_ir<true, true, true>(a, l.N, st, &nb) : launch_ir<true, true, false>(a, l.N, st, &nb);
+        else h ? launch_ir<true, false, true>(a, l.N, st, &nb) : launch_ir<true, false, false>(a, l.N, st, &nb);
     } else {
-        if (harmonic(P)) launch_ir<false, true>(a, l.N, st, &nb);
-        else launch_ir<false, false>(a, l.N, st, &nb);
+        if (x_zero) h ? launch_ir<false, true, true>(a, l.N, st, &nb) : launch_ir<false, true, false>(a, l.N, st, &nb);
+        else h ? launch_ir<false, false, true>(a, l.N, st, &nb) : launch_ir<false, false, false>(a, l.N, st, &nb);
     }
     LAUNCHCHK();
     TRY(tend(P, tslot, DMGS_K_RESIDUAL, bytes, st));
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, P->dnorm, slot);
+    // the final sum goes straight to the plan's pinned host slots
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, P->hnorm, slot);
     LAUNCHCHK();
     return DMGS_OK;
 }
 
+// The reduction kernels write the norms into pinned host memory; waiting for
+// the stream makes them readable.
 int read_norms(dmgs_plan P, hipStream_t st) {
-    HIPCHK(hipMemcpyAsync(P->hnorm, P->dnorm, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (P->timing) TRY(timing_flush(P));
     return DMGS_OK;
@@ -713,8 +718,16 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
     const dmgs_options& o = P->opt;
     const Level& l0 = P->lev[0];
     const bool fixed = o.fixed_cycles > 0;
-    hipLaunchKernelGGL(k_init_iterate<double>, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, x, l0.N, bc);
-    LAUNCHCHK();
+    // with a zero boundary value the refinement's first steps treat the
+    // zero iterate implicitly (x is neither cleared nor read; only its
+    // boundary is set, and it is cleared if no correction is applied)
+    const bool x_zero = is_ir(P) && bc == 0.0;
+    if (x_zero) {
+        TRY(set_boundary<double>(x, l0.N, 0.0, st));
+    } else {
+        hipLaunchKernelGGL(k_init_iterate<double>, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, x, l0.N, bc);
+        LAUNCHCHK();
+    }
     int cycles = 0, status = DMGS_OK;
     double r0 = 0.0, rel = 0.0;
     if (!is_ir(P)) {
@@ -752,7 +765,7 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
         double* xc = x;
         double* xo = P->xalt64;
         TRY(set_boundary<double>(xo, l0.N, bc, st));
-        TRY(ir_step(P, xc, nullptr, nullptr, b, l0.q32, 0, st));
+        TRY(ir_step(P, xc, nullptr, nullptr, b, l0.q32, 0, st, x_zero));
         for (cycles = 0;; cycles++) {
             if (!fixed) {
                 TRY(read_norms(P, st));
@@ -774,8 +787,12 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
             float* eo = l0.t32;
             for (int ic = 0; ic < o.ir_inner_cycles; ic++)
                 TRY(vcycle<float>(P, 0, &e, &eo, l0.q32, order, ic == 0, st));
-            TRY(ir_step(P, xc, e, xo, b, l0.q32, 1, st));
+            TRY(ir_step(P, xc, e, xo, b, l0.q32, 1, st, x_zero && cycles == 0));
             std::swap(xc, xo);
+        }
+        if (x_zero && cycles == 0) {
+            hipLaunchKernelGGL(k_init_iterate<double>, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, x, l0.N, 0.0);
+            LAUNCHCHK();
         }
         if (xc != x) HIPCHK(hipMemcpyAsync(x, xc, l0.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
         if (fixed && info) {
@@ -976,9 +993,9 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     if (st == DMGS_OK) st = dalloc(P, &P->scratch64, P->lev[0].nv);
     if (ir && st == DMGS_OK) st = dalloc(P, &P->xalt64, P->lev[0].nv);
     if (st == DMGS_OK) st = dalloc(P, &P->partial, kMaxPartials);
-    if (st == DMGS_OK) st = dalloc(P, &P->dnorm, 4);
+
     if (st == DMGS_OK) st = dalloc(P, &P->dflag, 1);
-    if (st == DMGS_OK && hipHostMalloc((void**)&P->hnorm, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    if (st == DMGS_OK && hipHostMalloc((void**)&P->hnorm, 4 * sizeof(double), hipHostMallocCoherent) != hipSuccess) {
         set_error("hipHostMalloc failed");
         st = DMGS_ERR_OOM;
     }

@@ -429,7 +429,9 @@ struct IrShape {
     static constexpr int NT = (RY * NP + 63) / 64 * 64;
 };
 
-template <int TY, int TZ, bool HAS_E, bool HARM>
+// X_ZERO: the iterate x is 0 everywhere (not read): with e, x_out = e;
+// without e, the residual is b itself.
+template <int TY, int TZ, bool HAS_E, bool X_ZERO, bool HARM>
 __global__ __launch_bounds__((IrShape<TY, TZ>::NT)) void k_ir_residual_col(IrArgs a) {
     using Sh = IrShape<TY, TZ>;
     constexpr int NP = Sh::NP, RY = Sh::RY, RZ = Sh::RZ, RA = Sh::RA;
@@ -467,10 +469,18 @@ __global__ __launch_bounds__((IrShape<TY, TZ>::NT)) void k_ir_residual_col(IrArg
         const auto rD = plane_rsrc(a.D, pb8, p, pv);
         const auto rB = plane_rsrc(a.b, pb8, p, pv);
         const auto rM = plane_rsrc(a.mu, pb8, p, pv);
-        P.x0 = buf_load<double>(rX, o8_0); P.x1 = buf_load<double>(rX, o8_1);
-        P.D0 = buf_load<double>(rD, o8_0); P.D1 = buf_load<double>(rD, o8_1);
+        if (X_ZERO) {
+            P.x0 = P.x1 = 0.0;
+        } else {
+            P.x0 = buf_load<double>(rX, o8_0); P.x1 = buf_load<double>(rX, o8_1);
+        }
         P.b0 = buf_load<double>(rB, o8_0); P.b1 = buf_load<double>(rB, o8_1);
-        P.m0 = buf_load<double>(rM, o8_0); P.m1 = buf_load<double>(rM, o8_1);
+        if (X_ZERO && !HAS_E) {   // A 0 = 0: no coefficients needed
+            P.D0 = P.D1 = P.m0 = P.m1 = 0.0;
+        } else {
+            P.D0 = buf_load<double>(rD, o8_0); P.D1 = buf_load<double>(rD, o8_1);
+            P.m0 = buf_load<double>(rM, o8_0); P.m1 = buf_load<double>(rM, o8_1);
+        }
         if (HAS_E) {
             const auto rE = plane_rsrc(a.e, pb4, p, pv);
             P.e0 = buf_load<float>(rE, o4_0); P.e1 = buf_load<float>(rE, o4_1);
@@ -491,6 +501,7 @@ __global__ __launch_bounds__((IrShape<TY, TZ>::NT)) void k_ir_residual_col(IrArg
         lds_barrier();
         auto res = [&](auto Oc) -> double {
             constexpr int O = decltype(Oc)::value;
+            if (X_ZERO && !HAS_E) return O ? P0.b1 : P0.b0;
             const int e = e0 + O;
             const double ui = O ? u1 : u0, Di = O ? P0.D1 : P0.D0;
             const double uzl = O ? u0 : U[e - 1], uzr = O ? U[e + 1] : u1;
