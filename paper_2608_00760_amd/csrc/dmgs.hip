@@ -119,7 +119,7 @@ size_t footprint(const dmgs_options* o) {
         else b += (k > 0 ? 4 : 2) * s.nv[k] * sizeof(double);         // w64, (u64, q64), t64
     }
     b += (ir ? 2 : 1) * s.nv[0] * sizeof(double);                     // scratch64 (+ xalt64)
-    b += kMaxPartials * sizeof(double) + 4 * sizeof(double) + sizeof(int);
+    b += kMaxPartials * sizeof(double) + kCoarseMax * kCoarseMax * sizeof(double) + 4 * sizeof(double) + sizeof(int);
     return b;
 }
 
@@ -146,6 +146,7 @@ void free_plan(dmgs_plan P) {
     if (P->scratch64) (void)hipFree(P->scratch64);
     if (P->xalt64) (void)hipFree(P->xalt64);
     if (P->partial) (void)hipFree(P->partial);
+    if (P->cinv) (void)hipFree(P->cinv);
     if (P->dflag) (void)hipFree(P->dflag);
     if (P->hnorm) (void)hipHostFree(P->hnorm);
     if (P->hflag) (void)hipHostFree(P->hflag);
@@ -607,12 +608,9 @@ int launch_small_t(dmgs_plan P, int k, const T* q, T* u, int order, hipStream_t 
         a.lev[i].w = Typed<T>::w(l);
         a.lev[i].st = l.stencil<T>(HARM);
     }
-    const Level& c = P->lev[P->L - 1];
     a.q = q;
     a.u = u;
-    a.Dc = c.D64;
-    a.muc = c.mu64;
-    a.stc = c.stencil<double>(HARM);
+    a.cinv = P->cinv;
     a.nu_pre = P->opt.nu_pre;
     a.nu_post = P->opt.nu_post;
     a.order = order;
@@ -856,6 +854,12 @@ int build_hierarchy(dmgs_plan P, hipStream_t st) {
         hipLaunchKernelGGL(k_coarsen_coef, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)f.mu64, c.mu64, f.N);
         LAUNCHCHK();
     }
+    {
+        const Level& c = P->lev[P->L - 1];
+        hipLaunchKernelGGL(k_coarse_inverse, dim3(1), dim3(64), 0, st, (const double*)c.D64, (const double*)c.mu64, c.N,
+                           c.stencil<double>(harmonic(P)), P->cinv);
+        LAUNCHCHK();
+    }
     for (int k = 0; k < P->L; k++) {
         Level& l = P->lev[k];
         dim3 g(1, l.n, l.n);
@@ -993,6 +997,7 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     if (st == DMGS_OK) st = dalloc(P, &P->scratch64, P->lev[0].nv);
     if (ir && st == DMGS_OK) st = dalloc(P, &P->xalt64, P->lev[0].nv);
     if (st == DMGS_OK) st = dalloc(P, &P->partial, kMaxPartials);
+    if (st == DMGS_OK) st = dalloc(P, &P->cinv, kCoarseMax * kCoarseMax);
 
     if (st == DMGS_OK) st = dalloc(P, &P->dflag, 1);
     if (st == DMGS_OK && hipHostMalloc((void**)&P->hnorm, 4 * sizeof(double), hipHostMallocCoherent) != hipSuccess) {
@@ -1026,11 +1031,11 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
         int nl = P->L - k;
         if (nl > kSmallMaxLevels) continue;
         for (int i = 0; i < nl; i++) Ns[i] = P->lev[k + i].N;
-        if (P->small32 < 0 && P->lev[k].N <= 16 && small_lds_bytes<float>(Ns, nl) <= 160 * 1024) P->small32 = k;
-        if (P->small64 < 0 && P->lev[k].N <= 8 && small_lds_bytes<double>(Ns, nl) <= 160 * 1024) P->small64 = k;
+        if (P->small32 < 0 && P->lev[k].N <= 16 && small_lds_bytes<float>(Ns, nl) <= kSmallLdsLimit) P->small32 = k;
+        if (P->small64 < 0 && P->lev[k].N <= 8 && small_lds_bytes<double>(Ns, nl) <= kSmallLdsLimit) P->small64 = k;
     }
     if (st == DMGS_OK) {
-        const int lim = 160 * 1024;
+        const int lim = (int)kSmallLdsLimit;
         const void* fns[] = {(const void*)k_small_vcycle<float, false>, (const void*)k_small_vcycle<float, true>,
                              (const void*)k_small_vcycle<double, false>, (const void*)k_small_vcycle<double, true>};
         for (const void* f : fns)

@@ -224,6 +224,45 @@ __device__ void dense_exact_solve(const Tq* q, Tu* u, const double* __restrict__
     for (int r = 0; r < m; r++) u[vid[r]] = (Tu)b[r];
 }
 
+// Inverse of the coarsest operator, for coarse solves by a matrix-vector
+// product (corrections, whose boundary values are 0).  The unknowns are the
+// m = (N-1)^3 <= 8 interior vertices in x, y, z order; A is assembled in
+// float64 as above and inverted by Gauss-Jordan elimination without
+// pivoting (A is symmetric positive definite and diagonally dominant).  One
+// workgroup of 64 threads; thread t owns row t.  inv is m x m, row-major.
+constexpr int kCoarseMax = 8;
+__global__ void k_coarse_inverse(const double* __restrict__ D, const double* __restrict__ mu, int N, Stencil<double> s,
+                                 double* __restrict__ inv) {
+    __shared__ double M[kCoarseMax][2 * kCoarseMax];
+    const int Nm = N - 1, m = Nm * Nm * Nm, n = N + 1, t = threadIdx.x;
+    if (t < m) {
+        const int x = 1 + t / (Nm * Nm), y = 1 + (t / Nm) % Nm, z = 1 + t % Nm;
+        for (int j = 0; j < 2 * m; j++) M[t][j] = 0.0;
+        const int64_t i = vidx(n, x, y, z);
+        const int off[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+        double d = mu[i];
+        for (int e = 0; e < 6; e++) {
+            const int xa = x + off[e][0], ya = y + off[e][1], za = z + off[e][2];
+            const double c = face_coef(D[i], D[vidx(n, xa, ya, za)], s);
+            d += c;
+            if (is_interior(N, xa, ya, za)) M[t][((xa - 1) * Nm + (ya - 1)) * Nm + (za - 1)] = -c;
+        }
+        M[t][t] = d;
+        M[t][m + t] = 1.0;
+    }
+    __syncthreads();
+    for (int p = 0; p < m; p++) {
+        // rows other than p only change their own entries and read row p
+        if (t < m && t != p) {
+            const double f = M[t][p] / M[p][p];
+            for (int j = 0; j < 2 * m; j++) M[t][j] -= f * M[p][j];
+        }
+        __syncthreads();
+    }
+    if (t < m)
+        for (int j = 0; j < m; j++) inv[t * m + j] = M[t][m + j] / M[t][t];
+}
+
 template <class T>
 __global__ void k_exact_solve(const T* __restrict__ q, T* __restrict__ u, const double* __restrict__ D,
                               const double* __restrict__ mu, int N, Stencil<double> s) {

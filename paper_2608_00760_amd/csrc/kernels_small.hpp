@@ -5,7 +5,8 @@
 // iterate, right-hand side and coefficients of every such level live in LDS,
 // each step of the cycle (red-black half-sweeps, defect, full-weighting
 // restriction, prolongation) is one barrier-separated phase, and the coarsest
-// level is solved exactly in float64 by one thread.  This replaces dozens of
+// level is solved exactly in float64 by a product with the inverse of its
+// operator (formed once per coefficient set).  This replaces dozens of
 // launches of a few microseconds each per cycle by one.
 //
 // The work of a phase is spread over the threads with power-of-two padded
@@ -40,15 +41,16 @@ struct SmallArgs {
     SmallLevel<T> lev[kSmallMaxLevels];
     const T* q;                        // right-hand side on the first small level
     T* u;                              // result on the first small level (whole array written)
-    const double* Dc;                  // coarsest level coefficients in float64
-    const double* muc;
-    Stencil<double> stc;
+    const double* cinv;                // inverse of the coarsest operator (m x m, m = (Nc-1)^3 <= 8)
     int nu_pre, nu_post, order;
     int roff;                          // LDS offset of the defect scratch
 };
 
 // LDS layout: level i's u, q, D, w at offsets off_i + {0, 1, 2, 3} nv_i,
 // levels in order, then the defect scratch (nv of the first level).
+// Dynamic LDS available beside the kernel's own coarse-inverse array.
+constexpr size_t kSmallLdsLimit = 160 * 1024 - 64 * sizeof(double);
+
 template <class T>
 __host__ __device__ inline size_t small_lds_bytes(const int* Ns, int nlev) {
     size_t b = 0, first = 0;
@@ -77,37 +79,52 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_vcycle(SmallArgs<T> a) 
     const int first = a.order ? 1 : 0;   // colour of the first half-sweep
     const bool pre1 = a.nu_pre > 0;        // the first half-sweep from zero is folded in
 
-    // level arrays into LDS: every load of the level is issued before the
-    // first LDS write; the first level starts its pre-smoothing from zero,
-    // so its first half-sweep is u = w q on the first colour
+    // level arrays into LDS, with every global load issued before the first
+    // LDS write (the first level has at most 17^3 vertices, the others at
+    // most 9^3, one per thread); the first level starts its pre-smoothing
+    // from zero, so its first half-sweep is u = w q on the first colour
+    __shared__ double sinv[kCoarseMax * kCoarseMax];
     {
-        constexpr int kPer = (17 * 17 * 17 + kSmallThreads - 1) / kSmallThreads;   // N <= 16
-        for (int i = 0; i < a.nlev; i++) {
-            const int N = a.lev[i].N, n = N + 1, nv = n * n * n;
-            T d[kPer], w[kPer], q[kPer];
+        constexpr int kPer = (17 * 17 * 17 + kSmallThreads - 1) / kSmallThreads;
+        const int n0 = a.lev[0].N + 1, nv0 = a.lev[0].nv;
+        const int Nc = a.lev[a.nlev - 1].N, mc = (Nc - 1) * (Nc - 1) * (Nc - 1);
+        T d[kPer], w[kPer], q[kPer], dl[kSmallMaxLevels], wl[kSmallMaxLevels];
+        double ci = 0.0;
+        if (tid < mc * mc) ci = a.cinv[tid];
 #pragma unroll
-            for (int k = 0; k < kPer; k++) {
-                const int v = tid + k * kSmallThreads;
-                d[k] = v < nv ? a.lev[i].D[v] : T(0);
-                w[k] = v < nv ? a.lev[i].w[v] : T(0);
-                q[k] = (i == 0 && v < nv) ? a.q[v] : T(0);
-            }
+        for (int k = 0; k < kPer; k++) {
+            const int v = tid + k * kSmallThreads;
+            d[k] = v < nv0 ? a.lev[0].D[v] : T(0);
+            w[k] = v < nv0 ? a.lev[0].w[v] : T(0);
+            q[k] = v < nv0 ? a.q[v] : T(0);
+        }
 #pragma unroll
-            for (int k = 0; k < kPer; k++) {
-                const int v = tid + k * kSmallThreads;
-                if (v < nv) {
-                    D(i)[v] = d[k];
-                    W(i)[v] = w[k];
-                    Q(i)[v] = q[k];
-                    T u0 = T(0);
-                    if (i == 0) {
-                        const int z = v % n, y = (v / n) % n, x = v / (n * n);
-                        if (pre1 && ((x + y + z) & 1) == first) u0 = w[k] * q[k];   // w = 0 on the boundary
-                    }
-                    U(i)[v] = u0;
-                }
+        for (int i = 1; i < kSmallMaxLevels; i++) {
+            const bool in = i < a.nlev && tid < a.lev[i].nv;
+            dl[i] = in ? a.lev[i].D[tid] : T(0);
+            wl[i] = in ? a.lev[i].w[tid] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; k++) {
+            const int v = tid + k * kSmallThreads;
+            if (v < nv0) {
+                D(0)[v] = d[k];
+                W(0)[v] = w[k];
+                Q(0)[v] = q[k];
+                const int z = v % n0, y = (v / n0) % n0, x = v / (n0 * n0);
+                U(0)[v] = (pre1 && ((x + y + z) & 1) == first) ? w[k] * q[k] : T(0);   // w = 0 on the boundary
             }
         }
+#pragma unroll
+        for (int i = 1; i < kSmallMaxLevels; i++) {
+            if (i < a.nlev && tid < a.lev[i].nv) {
+                D(i)[tid] = dl[i];
+                W(i)[tid] = wl[i];
+                Q(i)[tid] = T(0);
+                U(i)[tid] = T(0);
+            }
+        }
+        if (tid < mc * mc) sinv[tid] = ci;
     }
     __syncthreads();
 
@@ -215,8 +232,17 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_vcycle(SmallArgs<T> a) 
         defect(i);
         restrict_start(i);
     }
-    if (tid == 0) dense_exact_solve(Q(L - 1), U(L - 1), a.Dc, a.muc, a.lev[L - 1].N, a.stc);
-    __syncthreads();
+    {   // coarsest level: u = A^-1 q on the interior unknowns (x, y, z order)
+        const int Nc = a.lev[L - 1].N, Nm = Nc - 1, mc = Nm * Nm * Nm, nc = Nc + 1;
+        auto vid = [&](int c) { return ((1 + c / (Nm * Nm)) * nc + 1 + (c / Nm) % Nm) * nc + 1 + c % Nm; };
+        if (tid < mc) {
+            const T* qc = Q(L - 1);
+            double acc = 0.0;
+            for (int c = 0; c < mc; c++) acc += sinv[tid * mc + c] * (double)qc[vid(c)];
+            U(L - 1)[vid(tid)] = (T)acc;
+        }
+        __syncthreads();
+    }
     for (int i = L - 2; i >= 0; i--) {  // up
         // the next half-sweep updates the first colour from the second
         // colour's values; with no post-smoothing both colours are corrected

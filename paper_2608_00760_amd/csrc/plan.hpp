@@ -72,6 +72,7 @@ struct dmgs_plan_s {
     int cfg_dr_wgs = 512;                           // defect-restriction passes: target workgroups
     int small32 = -1, small64 = -1;   // first level of the single-workgroup coarse kernel
     double* partial = nullptr;     // first-stage reduction partials
+    double* cinv = nullptr;        // inverse of the coarsest operator (kCoarseMax^2 entries)
     double* hnorm = nullptr;       // pinned host memory the reductions write their norms to (4 slots)
     int* dflag = nullptr;          // device validation flag
     int* hflag = nullptr;          // pinned host mirror
