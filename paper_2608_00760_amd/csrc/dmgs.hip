@@ -832,13 +832,21 @@ int end_call(dmgs_plan P, int status, dmgs_info* info, hipStream_t st) {
     return status;
 }
 
-int build_hierarchy(dmgs_plan P, hipStream_t st) {
+// Coefficient hierarchy from the finest level's D64 and mu64.  from_log:
+// they are formed here from logD and logmu (exp and validation in one pass).
+int build_hierarchy(dmgs_plan P, hipStream_t st, const double* logD = nullptr, const double* logmu = nullptr) {
     Level& l0 = P->lev[0];
     *P->hflag = 0;
     HIPCHK(hipMemsetAsync(P->dflag, 0, sizeof(int), st));
-    TIMED(P, 0, DMGS_K_COEF, 16.0 * l0.nv, st,
-          hipLaunchKernelGGL(k_validate, dim3(grid_for(l0.nv, 4096)), dim3(kBlock), 0, st, (const double*)l0.D64,
-                             (const double*)l0.mu64, l0.N, P->dflag));
+    if (logD) {
+        TIMED(P, 0, DMGS_K_COEF, 32.0 * l0.nv, st,
+              hipLaunchKernelGGL(k_exp_validate, dim3(grid_for(l0.nv, 4096)), dim3(kBlock), 0, st, logD, logmu, l0.D64,
+                                 l0.mu64, l0.N, P->dflag));
+    } else {
+        TIMED(P, 0, DMGS_K_COEF, 16.0 * l0.nv, st,
+              hipLaunchKernelGGL(k_validate, dim3(grid_for(l0.nv, 4096)), dim3(kBlock), 0, st, (const double*)l0.D64,
+                                 (const double*)l0.mu64, l0.N, P->dflag));
+    }
     HIPCHK(hipMemcpyAsync(P->hflag, P->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (*P->hflag) {
@@ -849,9 +857,8 @@ int build_hierarchy(dmgs_plan P, hipStream_t st) {
     for (int k = 1; k < P->L; k++) {
         const Level& f = P->lev[k - 1];
         Level& c = P->lev[k];
-        hipLaunchKernelGGL(k_coarsen_coef, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)f.D64, c.D64, f.N);
-        LAUNCHCHK();
-        hipLaunchKernelGGL(k_coarsen_coef, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)f.mu64, c.mu64, f.N);
+        hipLaunchKernelGGL(k_coarsen_coef, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)f.D64,
+                           (const double*)f.mu64, c.D64, c.mu64, f.N);
         LAUNCHCHK();
     }
     {
@@ -862,20 +869,15 @@ int build_hierarchy(dmgs_plan P, hipStream_t st) {
     }
     for (int k = 0; k < P->L; k++) {
         Level& l = P->lev[k];
-        dim3 g(1, l.n, l.n);
         if (is_ir(P)) {
-            hipLaunchKernelGGL(k_cast_f32, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, (const double*)l.D64, l.D32, l.nv);
-            LAUNCHCHK();
-            hipLaunchKernelGGL(k_cast_f32, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, (const double*)l.mu64, l.mu32, l.nv);
-            LAUNCHCHK();
-            hipLaunchKernelGGL(k_inv_diag<float>, g, dim3(kBlock), 0, st, (const double*)l.D64, (const double*)l.mu64, l.N,
-                               l.stencil<double>(harmonic(P)), l.w32);
-            LAUNCHCHK();
+            hipLaunchKernelGGL(k_level_prep<float>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, (const double*)l.D64,
+                               (const double*)l.mu64, l.N, l.stencil<double>(harmonic(P)), l.w32, l.D32, l.mu32);
         } else {
-            hipLaunchKernelGGL(k_inv_diag<double>, g, dim3(kBlock), 0, st, (const double*)l.D64, (const double*)l.mu64,
-                               l.N, l.stencil<double>(harmonic(P)), l.w64);
-            LAUNCHCHK();
+            hipLaunchKernelGGL(k_level_prep<double>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, (const double*)l.D64,
+                               (const double*)l.mu64, l.N, l.stencil<double>(harmonic(P)), l.w64, (float*)nullptr,
+                               (float*)nullptr);
         }
+        LAUNCHCHK();
     }
     P->coef_set = true;
     return DMGS_OK;
@@ -1089,12 +1091,7 @@ int dmgs_set_log_coefficients(dmgs_plan P, const double* logD, const double* log
     if (!P || !logD || !logmua) { set_error("NULL argument"); return DMGS_ERR_INVALID; }
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipSetDevice(P->device));
-    Level& l0 = P->lev[0];
-    hipLaunchKernelGGL(k_exp_copy, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, logD, l0.D64, l0.nv);
-    LAUNCHCHK();
-    hipLaunchKernelGGL(k_exp_copy, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, logmua, l0.mu64, l0.nv);
-    LAUNCHCHK();
-    return build_hierarchy(P, st);
+    return build_hierarchy(P, st, logD, logmua);
 }
 
 int dmgs_forward(dmgs_plan P, const double* q, double* rho, dmgs_info* info, void* stream) {

@@ -33,50 +33,84 @@ __global__ void k_stream_copy(const float4* __restrict__ a, float4* __restrict__
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) b[i] = a[i];
 }
 
-__global__ void k_exp_copy(const double* __restrict__ a, double* __restrict__ b, int64_t nv) {
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x)
-        b[v] = exp(a[v]);
-}
-
-__global__ void k_cast_f32(const double* __restrict__ a, float* __restrict__ b, int64_t nv) {
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x)
-        b[v] = (float)a[v];
-}
-
 // D > 0 and finite on every vertex, mua >= 0 and finite on interior vertices.
+__device__ __forceinline__ bool coef_ok(double d, double m, bool interior) {
+    return d > 0.0 && isfinite(d) && (!interior || (m >= 0.0 && isfinite(m)));
+}
+
 __global__ void k_validate(const double* __restrict__ D, const double* __restrict__ mu, int N, int* __restrict__ bad) {
-    int n = N + 1;
-    int64_t nv = (int64_t)n * n * n;
+    const int n = N + 1, nv = n * n * n;
     int b = 0;
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
-        int z = (int)(v % n), y = (int)((v / n) % n), x = (int)(v / ((int64_t)n * n));
-        double d = D[v];
-        if (!(d > 0.0) || !isfinite(d)) b = 1;
-        if (is_interior(N, x, y, z)) {
-            double m = mu[v];
-            if (!(m >= 0.0) || !isfinite(m)) b = 1;
-        }
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+        const int z = v % n, y = (v / n) % n, x = v / (n * n);
+        if (!coef_ok(D[v], mu[v], is_interior(N, x, y, z))) b = 1;
+    }
+    if (b) atomicOr(bad, 1);
+}
+
+// Coefficients from their logarithms (D = exp(log D), mua = exp(log mua)),
+// checked as k_validate checks them.
+__global__ void k_exp_validate(const double* __restrict__ logD, const double* __restrict__ logmu, double* __restrict__ D,
+                               double* __restrict__ mu, int N, int* __restrict__ bad) {
+    const int n = N + 1, nv = n * n * n;
+    int b = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+        const int z = v % n, y = (v / n) % n, x = v / (n * n);
+        const double d = exp(logD[v]), m = exp(logmu[v]);
+        D[v] = d;
+        mu[v] = m;
+        if (!coef_ok(d, m, is_interior(N, x, y, z))) b = 1;
     }
     if (b) atomicOr(bad, 1);
 }
 
 // Coefficient transfer to the next coarser level: full weighting
 // (1/64)(1,2,1)^3 on coarse interior vertices, injection on coarse boundary
-// vertices.
-__global__ void k_coarsen_coef(const double* __restrict__ f, double* __restrict__ c, int Nf) {
-    int Nc = Nf / 2, nf = Nf + 1, nc = Nc + 1;
-    int64_t nv = (int64_t)nc * nc * nc;
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
-        int Z = (int)(v % nc), Y = (int)((v / nc) % nc), X = (int)(v / ((int64_t)nc * nc));
-        if (!is_interior(Nc, X, Y, Z)) { c[v] = f[vidx(nf, 2 * X, 2 * Y, 2 * Z)]; continue; }
-        double s = 0.0;
-        for (int a = -1; a <= 1; a++)
-            for (int b = -1; b <= 1; b++) {
-                double wab = (double)((2 - abs(a)) * (2 - abs(b)));
-                const double* row = f + vidx(nf, 2 * X + a, 2 * Y + b, 2 * Z);
-                s += wab * (row[-1] + 2.0 * row[0] + row[1]);
-            }
-        c[v] = s * (1.0 / 64.0);
+// vertices.  D and mua in one pass.
+__device__ __forceinline__ double coarsen_at(const double* __restrict__ f, int Nc, int nf, int X, int Y, int Z) {
+    if (!is_interior(Nc, X, Y, Z)) return f[vidx(nf, 2 * X, 2 * Y, 2 * Z)];
+    double s = 0.0;
+    for (int a = -1; a <= 1; a++)
+        for (int b = -1; b <= 1; b++) {
+            const double wab = (double)((2 - abs(a)) * (2 - abs(b)));
+            const double* row = f + vidx(nf, 2 * X + a, 2 * Y + b, 2 * Z);
+            s += wab * (row[-1] + 2.0 * row[0] + row[1]);
+        }
+    return s * (1.0 / 64.0);
+}
+
+__global__ void k_coarsen_coef(const double* __restrict__ fD, const double* __restrict__ fmu, double* __restrict__ cD,
+                               double* __restrict__ cmu, int Nf) {
+    const int Nc = Nf / 2, nf = Nf + 1, nc = Nc + 1, nv = nc * nc * nc;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+        const int Z = v % nc, Y = (v / nc) % nc, X = v / (nc * nc);
+        cD[v] = coarsen_at(fD, Nc, nf, X, Y, Z);
+        cmu[v] = coarsen_at(fmu, Nc, nf, X, Y, Z);
+    }
+}
+
+// Smoother data of one level from its float64 coefficients: the inverse
+// diagonal w = 1 / (sum_j c_ij + mua_i) on interior vertices (0 on the
+// boundary), formed in float64 and stored as T, and, when D32 is given,
+// float32 copies of D and mua.
+template <class T>
+__global__ void k_level_prep(const double* __restrict__ D, const double* __restrict__ mu, int N, Stencil<double> st,
+                             T* __restrict__ w, float* __restrict__ D32, float* __restrict__ mu32) {
+    const int n = N + 1, sx = n * n, nv = sx * n;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
+        const int z = i % n, y = (i / n) % n, x = i / sx;
+        const double Di = D[i], mi = mu[i];
+        if (D32) {
+            D32[i] = (float)Di;
+            mu32[i] = (float)mi;
+        }
+        if (!is_interior(N, x, y, z)) {
+            w[i] = T(0);
+            continue;
+        }
+        const double d = mi + face_coef(Di, D[i + sx], st) + face_coef(Di, D[i - sx], st) + face_coef(Di, D[i + n], st) +
+                         face_coef(Di, D[i - n], st) + face_coef(Di, D[i + 1], st) + face_coef(Di, D[i - 1], st);
+        w[i] = (T)(1.0 / d);
     }
 }
 

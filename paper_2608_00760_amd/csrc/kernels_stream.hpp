@@ -569,23 +569,4 @@ __global__ void k_set_boundary(T* __restrict__ u, int N, T g) {
     }
 }
 
-// Inverse diagonal w = 1 / (sum_j c_ij + mua_i) on interior vertices (0 on
-// the boundary), formed in float64 and stored as T.
-template <class T>
-__global__ void k_inv_diag(const double* __restrict__ D, const double* __restrict__ mu, int N, Stencil<double> st,
-                           T* __restrict__ w) {
-    const int n = N + 1;
-    const int x = blockIdx.z, yy = blockIdx.y;
-    const int64_t sx = (int64_t)n * n;
-    for (int z = threadIdx.x; z < n; z += blockDim.x) {
-        const int64_t i = (int64_t)x * sx + (int64_t)yy * n + z;
-        if (!is_interior(N, x, yy, z)) { w[i] = T(0); continue; }
-        const double Di = D[i];
-        const double d = mu[i] + face_coef(Di, D[i + sx], st) + face_coef(Di, D[i - sx], st) +
-                         face_coef(Di, D[i + n], st) + face_coef(Di, D[i - n], st) + face_coef(Di, D[i + 1], st) +
-                         face_coef(Di, D[i - 1], st);
-        w[i] = (T)(1.0 / d);
-    }
-}
-
 }  // namespace dmgs
