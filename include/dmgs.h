@@ -27,10 +27,11 @@
  *    tangents and gradients except logD_bar, which is defined on all
  *    vertices).
  *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
- *    it.  Calls that solve to a tolerance wait for the per-cycle residual and
- *    so return after the work has finished.  With fixed_cycles > 0 a solve
- *    does not wait, unless `info` is given: then the call waits at the end
- *    to fill in the final residual and the device time.
+ *    it.  Calls that solve to a tolerance wait for the per-step residual
+ *    norms; outputs are complete in stream order (work the call enqueued may
+ *    still run when it returns).  With `info` given, every call waits at the
+ *    end for all of its work, to fill in the final residual and the device
+ *    time.  With fixed_cycles > 0 a solve does not wait otherwise.
  *  - A plan may be used by one host thread and one stream at a time; use
  *    several plans for concurrency.
  *  - Every function returns a dmgs_status; no C++ exception crosses the ABI.

@@ -152,6 +152,7 @@ void free_plan(dmgs_plan P) {
     if (P->hflag) (void)hipHostFree(P->hflag);
     if (P->ev_start) (void)hipEventDestroy(P->ev_start);
     if (P->ev_stop) (void)hipEventDestroy(P->ev_stop);
+    if (P->ev_norm) (void)hipEventDestroy(P->ev_norm);
     for (int i = 0; i < 2 * kTimerSlots; i++)
         if (P->tev[i]) (void)hipEventDestroy(P->tev[i]);
     delete P;
@@ -163,8 +164,11 @@ int harmonic(dmgs_plan P) { return P->opt.face_mean == DMGS_FACE_HARMONIC; }
 // ---------------------------------------------------------------------------
 // Kernel timing: finest-level launches bracketed by events when enabled.
 
-int timing_flush(dmgs_plan P) {
-    for (int i = 0; i < P->tpending; i++) {
+// Accumulate the first `upto` pending slots (all by default); later slots
+// move to the front.
+int timing_flush(dmgs_plan P, int upto = -1) {
+    if (upto < 0 || upto > P->tpending) upto = P->tpending;
+    for (int i = 0; i < upto; i++) {
         float ms = 0.f;
         HIPCHK(hipEventSynchronize(P->tev[2 * i + 1]));
         HIPCHK(hipEventElapsedTime(&ms, P->tev[2 * i], P->tev[2 * i + 1]));
@@ -173,7 +177,12 @@ int timing_flush(dmgs_plan P) {
         P->t_ms[c] += ms;
         P->t_bytes[c] += P->trec[i].bytes;
     }
-    P->tpending = 0;
+    for (int i = upto; i < P->tpending; i++) {
+        std::swap(P->tev[2 * (i - upto)], P->tev[2 * i]);
+        std::swap(P->tev[2 * (i - upto) + 1], P->tev[2 * i + 1]);
+        P->trec[i - upto] = P->trec[i];
+    }
+    P->tpending -= upto;
     return DMGS_OK;
 }
 
@@ -627,8 +636,11 @@ int small_level(dmgs_plan P) { return sizeof(T) == 4 ? P->small32 : P->small64; 
 // One V-cycle on level k with right-hand side q, iterate in *cur (the
 // level's other buffer is *other).  zero: the iterate starts from 0 (coarse
 // corrections, refinement corrections).  On return *cur holds the result.
+// smoothed: the pre-smoothing of level k has already been enqueued (level k
+// uses the streaming passes); the cycle continues with the defect.
 template <class T>
-int vcycle(dmgs_plan P, int k, T** cur, T** other, const T* q, int order, bool zero, hipStream_t st) {
+int vcycle(dmgs_plan P, int k, T** cur, T** other, const T* q, int order, bool zero, hipStream_t st,
+           bool smoothed = false) {
     if (k > 0 && k == small_level<T>(P) && zero) {
         if (harmonic(P)) return launch_small_t<T, true>(P, k, q, *cur, order, st);
         return launch_small_t<T, false>(P, k, q, *cur, order, st);
@@ -639,7 +651,8 @@ int vcycle(dmgs_plan P, int k, T** cur, T** other, const T* q, int order, bool z
     }
     const Level& c = P->lev[k + 1];
     T* qc = Typed<T>::q(c);
-    TRY(pre_pass<T>(P, k, cur, other, q, qc, order, zero, st));
+    if (smoothed) TRY(defect_restrict<T>(P, k, *cur, q, qc, st));
+    else TRY(pre_pass<T>(P, k, cur, other, q, qc, order, zero, st));
     T* ccur = Typed<T>::u(c);
     T* coth = Typed<T>::t(c);
     TRY(vcycle<T>(P, k + 1, &ccur, &coth, qc, order, true, st));
@@ -699,14 +712,18 @@ int ir_step(dmgs_plan P, const double* x, const float* e, double* x_out, const d
     // the final sum goes straight to the plan's pinned host slots
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, P->hnorm, slot);
     LAUNCHCHK();
+    HIPCHK(hipEventRecord(P->ev_norm, st));
+    P->tmark = P->tpending;
     return DMGS_OK;
 }
 
 // The reduction kernels write the norms into pinned host memory; waiting for
-// the stream makes them readable.
+// the event after the last of them makes them readable (work enqueued after
+// it may still be running).
 int read_norms(dmgs_plan P, hipStream_t st) {
-    HIPCHK(hipStreamSynchronize(st));
-    if (P->timing) TRY(timing_flush(P));
+    (void)st;
+    HIPCHK(hipEventSynchronize(P->ev_norm));
+    if (P->timing) TRY(timing_flush(P, P->tmark));
     return DMGS_OK;
 }
 
@@ -764,8 +781,23 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
         double* xo = P->xalt64;
         TRY(set_boundary<double>(xo, l0.N, bc, st));
         TRY(ir_step(P, xc, nullptr, nullptr, b, l0.q32, 0, st, x_zero));
+        // While the host waits for a step's residual norm, the first
+        // smoothing pass of the next step is already enqueued when the
+        // residual is not expected to meet the tolerance yet (predicted from
+        // the last contraction factor).  The pass writes only the
+        // correction buffers, so a step that does converge discards it.
+        const bool can_speculate = !fixed && P->L > 1 && fused_level(P, 0) && !block_level<float>(P, 0);
+        double rel1 = 1.0, rel2 = 1.0;   // relative residuals of the last two steps
         for (cycles = 0;; cycles++) {
+            float* e = l0.u32;
+            float* eo = l0.t32;
+            bool smoothed = false;
             if (!fixed) {
+                const double rho = cycles >= 2 ? rel1 / rel2 : 0.1;
+                if (can_speculate && cycles < o.max_cycles && (cycles == 0 || rel1 * rho > o.rtol)) {
+                    TRY(smooth_phase<float>(P, 0, &e, &eo, l0.q32, o.nu_pre, order, true, (const float*)nullptr, st));
+                    smoothed = true;
+                }
                 TRY(read_norms(P, st));
                 if (cycles == 0) {
                     r0 = std::sqrt(P->hnorm[0]);
@@ -778,13 +810,13 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
                     if (rel <= o.rtol) break;
                 }
                 if (cycles >= o.max_cycles) { set_error("not converged after %d steps (rel %.3e)", cycles, rel); status = DMGS_ERR_NOT_CONVERGED; break; }
+                rel2 = rel1;
+                rel1 = rel;
             } else if (cycles == o.fixed_cycles) {
                 break;
             }
-            float* e = l0.u32;
-            float* eo = l0.t32;
             for (int ic = 0; ic < o.ir_inner_cycles; ic++)
-                TRY(vcycle<float>(P, 0, &e, &eo, l0.q32, order, ic == 0, st));
+                TRY(vcycle<float>(P, 0, &e, &eo, l0.q32, order, ic == 0, st, ic == 0 && smoothed));
             TRY(ir_step(P, xc, e, xo, b, l0.q32, 1, st, x_zero && cycles == 0));
             std::swap(xc, xo);
         }
@@ -1010,7 +1042,8 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
         set_error("hipHostMalloc failed");
         st = DMGS_ERR_OOM;
     }
-    if (st == DMGS_OK && (hipEventCreate(&P->ev_start) != hipSuccess || hipEventCreate(&P->ev_stop) != hipSuccess)) {
+    if (st == DMGS_OK && (hipEventCreate(&P->ev_start) != hipSuccess || hipEventCreate(&P->ev_stop) != hipSuccess ||
+                          hipEventCreateWithFlags(&P->ev_norm, hipEventDisableTiming) != hipSuccess)) {
         set_error("hipEventCreate failed");
         st = DMGS_ERR_HIP;
     }

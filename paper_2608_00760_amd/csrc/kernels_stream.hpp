@@ -260,7 +260,8 @@ __global__ __launch_bounds__((SweepShape<TY, TZ>::NT)) void k_rb_sweep_col(Sweep
 // Defect and full-weighting restriction.  Each workgroup owns a TYC x TZC
 // tile of coarse interior vertices and a chunk of coarse planes; threads own
 // fine column pairs of the region the tile's stencils cover (plus a ring of
-// 1 for the operator).  At fine plane p the residual is formed in LDS, then
+// 1 for the operator).  At fine plane p the residual is formed in LDS, and
+// one step later (after the next step's barrier, so one barrier per step)
 // each coarse vertex of the tile sums its 3 x 3 in-plane weights
 // (1,2,1) x (1,2,1) and accumulates along x with weights (1,2,1); the /64
 // is applied when the coarse plane completes.
@@ -295,7 +296,7 @@ __global__ __launch_bounds__((RestrictShape<TYC, TZC>::NT)) void k_defect_restri
     constexpr int NP = Sh::NP, RY = Sh::RY, RZ = Sh::RZ, RA = Sh::RA;
     __shared__ T sU[2][RA];
     __shared__ T sD[2][RA];
-    __shared__ T sR[RA];
+    __shared__ T sR[2][RA];
     const int N = a.N, n = N + 1, Nc = N / 2, ncv = Nc + 1;
     const int64_t sx = (int64_t)n * n, plane_bytes = sx * (int64_t)sizeof(T);
     const int64_t cplane_bytes = (int64_t)ncv * ncv * (int64_t)sizeof(T);
@@ -351,6 +352,22 @@ __global__ __launch_bounds__((RestrictShape<TYC, TZC>::NT)) void k_defect_restri
     };
 
     T acc = T(0);
+    // restriction of the residual of plane p (in sR[p & 1]) into the coarse accumulator
+    auto restrict_plane = [&](int p) {
+        const T* Rp = sR[p & 1];
+        auto row = [&](int c) { return (Rp[c - 1] + T(2) * Rp[c]) + Rp[c + 1]; };
+        const T w = (row(cc - RZ) + T(2) * row(cc)) + row(cc + RZ);
+        if (p & 1) {   // p = 2X - 1: completes coarse plane X - 1, starts X
+            if (p > p_first) {
+                const int X = (p - 1) / 2;
+                const auto rC = plane_rsrc(a.qc, cplane_bytes, X, true);
+                buf_store<T>((acc + w) * T(1.0 / 64.0), rC, coff);
+            }
+            acc = w;
+        } else {
+            acc += T(2) * w;
+        }
+    };
     auto step = [&](int p, ResPlane<T>& Pm1, ResPlane<T>& P0, ResPlane<T>& Pp1) {
         const int sl = p & 1;
         T* U = sU[sl];
@@ -360,22 +377,9 @@ __global__ __launch_bounds__((RestrictShape<TYC, TZC>::NT)) void k_defect_restri
         const bool pin = p >= 1 && p <= N - 1;
         const T r0 = (pin && rc0) ? resid(std::integral_constant<int, 0>(), U, Dl, Pm1, P0, Pp1) : T(0);
         const T r1 = (pin && rc1) ? resid(std::integral_constant<int, 1>(), U, Dl, Pm1, P0, Pp1) : T(0);
-        if (act) { sR[e0] = r0; sR[e0 + 1] = r1; }
-        lds_barrier();
-        if (cown) {
-            auto row = [&](int c) { return (sR[c - 1] + T(2) * sR[c]) + sR[c + 1]; };
-            const T w = (row(cc - RZ) + T(2) * row(cc)) + row(cc + RZ);
-            if (p & 1) {   // p = 2X - 1: completes coarse plane X - 1, starts X
-                if (p > p_first) {
-                    const int X = (p - 1) / 2;
-                    const auto rC = plane_rsrc(a.qc, cplane_bytes, X, true);
-                    buf_store<T>((acc + w) * T(1.0 / 64.0), rC, coff);
-                }
-                acc = w;
-            } else {
-                acc += T(2) * w;
-            }
-        }
+        if (act) { sR[sl][e0] = r0; sR[sl][e0 + 1] = r1; }
+        // sR[sl ^ 1] was written before this step's barrier
+        if (cown && p > p_first) restrict_plane(p - 1);
     };
 
     // register ring of four planes; plane p-1 is dead after step p and its
@@ -394,6 +398,8 @@ __global__ __launch_bounds__((RestrictShape<TYC, TZC>::NT)) void k_defect_restri
         if (p0 + 3 > p_last) break;
         step(p0 + 3, R3, R0, R1); load(p0 + 6, R3);
     }
+    lds_barrier();
+    if (cown) restrict_plane(p_last);
 }
 
 // ---------------------------------------------------------------------------

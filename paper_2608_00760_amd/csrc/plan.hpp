@@ -77,6 +77,8 @@ struct dmgs_plan_s {
     int* dflag = nullptr;          // device validation flag
     int* hflag = nullptr;          // pinned host mirror
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    hipEvent_t ev_norm = nullptr;  // recorded after the last norm reduction
+    int tmark = 0;                 // timer slots recorded before ev_norm
     bool coef_set = false;
     // kernel timing (profiling aid)
     bool timing = false;
