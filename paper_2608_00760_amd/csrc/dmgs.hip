@@ -51,6 +51,10 @@ void set_error(const char* fmt, ...) {
 
 constexpr int kBlock = 256;
 
+// One thread per vertex in whole blocks, rounded up to a multiple of the 8
+// XCDs (kernels using vertex_of_thread()).
+unsigned vertex_grid(int64_t nv) { return (unsigned)(((nv + kBlock - 1) / kBlock + 7) / 8 * 8); }
+
 unsigned grid_for(int64_t work, int64_t cap = 1 << 20) {
     int64_t b = (work + kBlock - 1) / kBlock;
     if (b < 1) b = 1;
@@ -817,9 +821,17 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
             }
             for (int ic = 0; ic < o.ir_inner_cycles; ic++)
                 TRY(vcycle<float>(P, 0, &e, &eo, l0.q32, order, ic == 0, st, ic == 0 && smoothed));
-            TRY(ir_step(P, xc, e, xo, b, l0.q32, 1, st, x_zero && cycles == 0));
-            std::swap(xc, xo);
+            if (x_zero && cycles == 0 && (P->ir_steps[order] & 1)) {
+                // the first update reads no iterate, so it may write x in
+                // place: with an odd number of steps (as the last solve of
+                // this kind took) the result then ends in x, not in xalt64
+                TRY(ir_step(P, xc, e, xc, b, l0.q32, 1, st, true));
+            } else {
+                TRY(ir_step(P, xc, e, xo, b, l0.q32, 1, st, x_zero && cycles == 0));
+                std::swap(xc, xo);
+            }
         }
+        P->ir_steps[order] = cycles;
         if (x_zero && cycles == 0) {
             hipLaunchKernelGGL(k_init_iterate<double>, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, x, l0.N, 0.0);
             LAUNCHCHK();
@@ -1142,7 +1154,7 @@ int dmgs_jvp(dmgs_plan P, const double* rho, const double* dq, const double* dlo
     if (!rho || !drho) { set_error("NULL argument"); return DMGS_ERR_INVALID; }
     const Level& l0 = P->lev[0];
     TIMED(P, 0, DMGS_K_GRAD, 56.0 * l0.nv, st,
-          hipLaunchKernelGGL(k_tangent_rhs, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, rho, dq, dlogD, dlogmua,
+          hipLaunchKernelGGL(k_tangent_rhs, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, rho, dq, dlogD, dlogmua,
                              (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, harmonic(P), P->scratch64));
     int s = solve(P, P->scratch64, drho, 0.0, 0, info, st);
     return end_call(P, s, info, st);
@@ -1157,7 +1169,7 @@ int dmgs_vjp(dmgs_plan P, const double* rho, const double* rhobar, double* qbar,
     if ((s == DMGS_OK || s == DMGS_ERR_NOT_CONVERGED) && (logD_bar || logmua_bar)) {
         const Level& l0 = P->lev[0];
         TIMED(P, 0, DMGS_K_GRAD, 48.0 * l0.nv, st,
-              hipLaunchKernelGGL(k_coef_grads, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, rho, (const double*)qbar,
+              hipLaunchKernelGGL(k_coef_grads, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, rho, (const double*)qbar,
                                  (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, harmonic(P), logD_bar,
                                  logmua_bar));
     }

@@ -14,6 +14,15 @@
 
 namespace dmgs {
 
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of tiles so neighbouring tiles share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+    const int kXcd = 8;
+    if (nblocks % kXcd) return b;
+    return (b % kXcd) * (nblocks / kXcd) + b / kXcd;
+}
+
+
 constexpr int kWave = 64;
 
 __host__ __device__ inline int64_t vidx(int n, int x, int y, int z) {

@@ -371,6 +371,13 @@ __global__ void k_add_correction(double* __restrict__ u, const float* __restrict
 // Derivatives with respect to the coefficients (adjoint-state derivatives of
 // the discrete solution).
 
+// The two derivative kernels below take one vertex per thread over a grid of
+// whole blocks rounded up to a multiple of 8, blocks remapped so that each
+// XCD walks a contiguous slab (the x +- 1 planes stay in its L2).
+__device__ __forceinline__ int vertex_of_thread() {
+    return xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+}
+
 // rhs = dq - (dA) rho on interior vertices (0 on the boundary), where
 // (dA rho)_i = sum_j dD_f,ij/h^2 (rho_i - rho_j) + mua_i dlogmua_i rho_i and
 // dD_f is the derivative of the face mean along dlogD.  Null tangents are 0.
@@ -378,30 +385,30 @@ __global__ void k_tangent_rhs(const double* __restrict__ rho, const double* __re
                               const double* __restrict__ dlogD, const double* __restrict__ dlogmu,
                               const double* __restrict__ D, const double* __restrict__ mu, int N, double inv_h2,
                               int harmonic, double* __restrict__ rhs) {
-    int n = N + 1;
-    int64_t nv = (int64_t)n * n * n, sx = (int64_t)n * n;
-    const int64_t off[6] = {sx, -sx, (int64_t)n, -(int64_t)n, 1, -1};
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
-        int z = (int)(i % n), y = (int)((i / n) % n), x = (int)(i / sx);
-        if (!is_interior(N, x, y, z)) { rhs[i] = 0.0; continue; }
-        double ri = rho[i], Di = D[i];
-        double acc = dlogmu ? mu[i] * dlogmu[i] * ri : 0.0;
-        if (dlogD) {
-            double dDi = Di * dlogD[i];
-            for (int e = 0; e < 6; e++) {
-                int64_t j = i + off[e];
-                double Dj = D[j], dDj = Dj * dlogD[j], dDf;
-                if (harmonic) {
-                    double sum = Di + Dj;
-                    dDf = 2.0 * (Dj * Dj * dDi + Di * Di * dDj) / (sum * sum);
-                } else {
-                    dDf = 0.5 * (dDi + dDj);
-                }
-                acc += dDf * inv_h2 * (ri - rho[j]);
+    const int n = N + 1, sx = n * n, nv = sx * n;
+    const int i = vertex_of_thread();
+    if (i >= nv) return;
+    const int z = i % n, y = (i / n) % n, x = i / sx;
+    if (!is_interior(N, x, y, z)) { rhs[i] = 0.0; return; }
+    const int off[6] = {sx, -sx, n, -n, 1, -1};
+    const double ri = rho[i], Di = D[i];
+    double acc = dlogmu ? mu[i] * dlogmu[i] * ri : 0.0;
+    if (dlogD) {
+        const double dDi = Di * dlogD[i];
+        for (int e = 0; e < 6; e++) {
+            const int j = i + off[e];
+            const double Dj = D[j], dDj = Dj * dlogD[j];
+            double dDf;
+            if (harmonic) {
+                const double sum = Di + Dj;
+                dDf = 2.0 * (Dj * Dj * dDi + Di * Di * dDj) / (sum * sum);
+            } else {
+                dDf = 0.5 * (dDi + dDj);
             }
+            acc += dDf * inv_h2 * (ri - rho[j]);
         }
-        rhs[i] = (dq ? dq[i] : 0.0) - acc;
     }
+    rhs[i] = (dq ? dq[i] : 0.0) - acc;
 }
 
 // Coefficient gradients from the adjoint state lam = qbar:
@@ -411,34 +418,33 @@ __global__ void k_tangent_rhs(const double* __restrict__ rho, const double* __re
 __global__ void k_coef_grads(const double* __restrict__ rho, const double* __restrict__ lam,
                              const double* __restrict__ D, const double* __restrict__ mu, int N, double inv_h2,
                              int harmonic, double* __restrict__ gD, double* __restrict__ gmu) {
-    int n = N + 1;
-    int64_t nv = (int64_t)n * n * n, sx = (int64_t)n * n;
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
-        int z = (int)(v % n), y = (int)((v / n) % n), x = (int)(v / sx);
-        bool vin = is_interior(N, x, y, z);
-        double lv = vin ? lam[v] : 0.0, rv = rho[v], Dv = D[v];
-        if (gmu) gmu[v] = vin ? -mu[v] * lam[v] * rv : 0.0;
-        if (!gD) continue;
-        double acc = 0.0;
-        const int o[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
-        for (int e = 0; e < 6; e++) {
-            int xa = x + o[e][0], ya = y + o[e][1], za = z + o[e][2];
-            if (xa < 0 || xa > N || ya < 0 || ya > N || za < 0 || za > N) continue;
-            bool jin = is_interior(N, xa, ya, za);
-            if (!vin && !jin) continue;
-            int64_t j = vidx(n, xa, ya, za);
-            double lj = jin ? lam[j] : 0.0, Dj = D[j];
-            double dcdv;
-            if (harmonic) {
-                double sum = Dv + Dj;
-                dcdv = 2.0 * Dj * Dj * Dv / (sum * sum);
-            } else {
-                dcdv = 0.5 * Dv;
-            }
-            acc += dcdv * (lv - lj) * (rv - rho[j]);
+    const int n = N + 1, sx = n * n, nv = sx * n;
+    const int v = vertex_of_thread();
+    if (v >= nv) return;
+    const int z = v % n, y = (v / n) % n, x = v / sx;
+    const bool vin = is_interior(N, x, y, z);
+    const double lv = vin ? lam[v] : 0.0, rv = rho[v], Dv = D[v];
+    if (gmu) gmu[v] = vin ? -mu[v] * lv * rv : 0.0;
+    if (!gD) return;
+    double acc = 0.0;
+    const int o[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+    for (int e = 0; e < 6; e++) {
+        const int xa = x + o[e][0], ya = y + o[e][1], za = z + o[e][2];
+        if (xa < 0 || xa > N || ya < 0 || ya > N || za < 0 || za > N) continue;
+        const bool jin = is_interior(N, xa, ya, za);
+        if (!vin && !jin) continue;
+        const int j = (xa * n + ya) * n + za;
+        const double lj = jin ? lam[j] : 0.0, Dj = D[j];
+        double dcdv;
+        if (harmonic) {
+            const double sum = Dv + Dj;
+            dcdv = 2.0 * Dj * Dj * Dv / (sum * sum);
+        } else {
+            dcdv = 0.5 * Dv;
         }
-        gD[v] = -acc * inv_h2;
+        acc += dcdv * (lv - lj) * (rv - rho[j]);
     }
+    gD[v] = -acc * inv_h2;
 }
 
 }  // namespace dmgs

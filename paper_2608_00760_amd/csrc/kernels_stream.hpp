@@ -21,14 +21,6 @@
 
 namespace dmgs {
 
-// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of tiles so neighbouring tiles share an L2.
-__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
-    const int kXcd = 8;
-    if (nblocks % kXcd) return b;
-    return (b % kXcd) * (nblocks / kXcd) + b / kXcd;
-}
-
 // Barrier that waits only for this wave's LDS operations (not for global
 // loads still in flight, which __syncthreads() would drain).
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }

@@ -79,6 +79,7 @@ struct dmgs_plan_s {
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     hipEvent_t ev_norm = nullptr;  // recorded after the last norm reduction
     int tmark = 0;                 // timer slots recorded before ev_norm
+    int ir_steps[2] = {0, 0};      // refinement steps of the last solve, by cycle order
     bool coef_set = false;
     // kernel timing (profiling aid)
     bool timing = false;
