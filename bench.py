@@ -128,7 +128,8 @@ def main():
     ap.add_argument("--precision", default="fp32-in-fp64", choices=["fp32-in-fp64", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
-    ap.add_argument("--inner", type=int, default=2, help="float32 V-cycles per refinement step")
+    ap.add_argument("--inner", type=int, default=8, help="float32 V-cycles per refinement step (the most, when adaptive)")
+    ap.add_argument("--no-adaptive", action="store_true", help="run --inner V-cycles in every refinement step")
     ap.add_argument("--serving-requests", type=int, default=512, help="requests in the serving stream (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the library's plain streaming copy (256 MiB, 3 times): HBM counter calibration")
@@ -160,7 +161,8 @@ def main():
     shape = t["q"].shape
     bufs = [torch.empty(shape, dtype=torch.float64, device=dev) for _ in range(4)]
 
-    P = Plan(Options(N, precision=args.precision, rtol=1e-10, max_cycles=100, ir_inner_cycles=args.inner))
+    P = Plan(Options(N, precision=args.precision, rtol=1e-10, max_cycles=100, ir_inner_cycles=args.inner,
+                     ir_adaptive=not args.no_adaptive))
     log("plan: %d levels, %.2f GB" % (P.levels, P.bytes / 1e9))
     run_steps(P, t, bufs, args.warmup)
     torch.cuda.synchronize()
@@ -210,8 +212,7 @@ def main():
         log("timing the oracle on a bounded sample")
         # the oracle runs plain V-cycles: scale by the V-cycles the solve needs
         # (refinement steps x float32 cycles per step in the mixed solver)
-        vc = args.inner if args.precision == "fp32-in-fp64" else 1
-        cpu = cpu_baseline(c, info_f["cycles"] * vc, info_a["cycles"] * vc)
+        cpu = cpu_baseline(c, info_f["vcycles"], info_a["vcycles"])
         log("oracle: %.4f pairs/s (%s)" % (cpu["value"], cpu["sample"]))
 
     # V-cycle time against the one-pass-per-operator byte model: 4 sweeps of 5
@@ -222,7 +223,7 @@ def main():
     word = 4 if args.precision == "fp32-in-fp64" else 8
     levels = sum(((N >> k) + 1) ** 3 for k in range(P.levels)) / nv
     model_bytes = 26.25 * word * nv * levels
-    vc = (args.inner if args.precision == "fp32-in-fp64" else 1) * (info_f["cycles"] + info_a["cycles"])
+    vc = info_f["vcycles"] + info_a["vcycles"]
     other_ms = sum(stats[k]["ms"] for k in ("residual", "update", "coef", "grad") if k in stats)
     vcycle_us = (elapsed * 1e3 - other_ms) / args.steps / vc * 1e3
     vcycle = {"vcycles_per_step": vc, "us": vcycle_us, "model_bytes": model_bytes,
@@ -245,7 +246,9 @@ def main():
                                "<=1e4) and mua, 16-blob source, V(2,2) RB-GS, rtol 1e-10, set-up+forward+VJP per step"
                                % N,
                    "N": N, "precision": args.precision, "rtol": 1e-10, "ir_inner_cycles": args.inner,
-                   "cycles_fwd": info_f["cycles"], "cycles_adj": info_a["cycles"],
+                   "ir_adaptive": not args.no_adaptive,
+                   "steps_fwd": info_f["cycles"], "steps_adj": info_a["cycles"],
+                   "vcycles_fwd": info_f["vcycles"], "vcycles_adj": info_a["vcycles"],
                    "rel_residual_fwd": info_f["rel_residual"], "rel_residual_adj": info_a["rel_residual"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,

@@ -80,8 +80,11 @@ typedef struct dmgs_options {
     double h;              /* grid spacing (> 0) */
     double bc_value;       /* Dirichlet value g of rho on the boundary */
     double rtol;           /* tolerance mode: stop when ||r||_2 / ||r_0||_2 <= rtol over interior vertices */
-    int32_t ir_inner_cycles; /* DMGS_FP32_IN_FP64: float32 V-cycles per refinement step, 1..8 (default 2) */
-    int32_t reserved;
+    int32_t ir_inner_cycles; /* DMGS_FP32_IN_FP64: float32 V-cycles per refinement step, 1..16 (default 8);
+                                with ir_adaptive, the most a step runs */
+    int32_t ir_adaptive;   /* DMGS_FP32_IN_FP64, tolerance mode: nonzero (default) = after the first step,
+                              run as many V-cycles per step as the contraction factor observed so far
+                              predicts the tolerance needs, at most ir_inner_cycles */
 } dmgs_options;
 
 typedef struct dmgs_info {
@@ -89,12 +92,15 @@ typedef struct dmgs_info {
     int32_t status;        /* dmgs_status of the call */
     double rel_residual;   /* final ||r|| / ||r_0|| of the solve (adjoint: ||rhobar - A qbar|| / ||rhobar||) */
     double device_ms;      /* device time of the call, from events on `stream` */
+    int32_t vcycles;       /* V-cycles applied (float32 V-cycles over all refinement steps) */
+    int32_t reserved;
 } dmgs_info;
 
 /* Fill `opt` with the defaults: V(2,2), RB-GS, FP64, arithmetic face mean,
  * h = 1, g = 0, rtol = 1e-10, max_cycles = 200, fixed_cycles = 0,
- * ir_inner_cycles = 2.  In DMGS_FP32_IN_FP64 plans a "cycle" of max_cycles,
- * fixed_cycles and info.cycles is one refinement step. */
+ * ir_inner_cycles = 8, ir_adaptive = 1.  In DMGS_FP32_IN_FP64 plans a
+ * "cycle" of max_cycles, fixed_cycles and info.cycles is one refinement
+ * step. */
 void dmgs_default_options(int32_t n, dmgs_options *opt);
 
 /* Device bytes a plan with these options allocates (hierarchy + scratch); 0

@@ -21,16 +21,16 @@ class Options(C.Structure):
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("max_cycles", C.c_int32),
                 ("fixed_cycles", C.c_int32), ("face_mean", C.c_int32), ("h", C.c_double),
                 ("bc_value", C.c_double), ("rtol", C.c_double), ("ir_inner_cycles", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("ir_adaptive", C.c_int32)]
 
 
 class Info(C.Structure):
     _fields_ = [("cycles", C.c_int32), ("status", C.c_int32), ("rel_residual", C.c_double),
-                ("device_ms", C.c_double)]
+                ("device_ms", C.c_double), ("vcycles", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {"cycles": self.cycles, "status": self.status, "rel_residual": self.rel_residual,
-                "device_ms": self.device_ms}
+                "device_ms": self.device_ms, "vcycles": self.vcycles}
 
 
 # name -> (restype, argtypes); the exported symbols of include/dmgs.h

@@ -90,7 +90,7 @@ int check_options(const dmgs_options* o) {
     if (o->face_mean != DMGS_FACE_ARITH && o->face_mean != DMGS_FACE_HARMONIC) { set_error("bad face_mean"); return DMGS_ERR_INVALID; }
     if (!(o->h > 0.0) || !std::isfinite(o->h) || !std::isfinite(o->bc_value)) { set_error("bad h or bc_value"); return DMGS_ERR_INVALID; }
     if (o->fixed_cycles < 0 || o->fixed_cycles > 100000) { set_error("bad fixed_cycles"); return DMGS_ERR_INVALID; }
-    if (o->precision == DMGS_FP32_IN_FP64 && (o->ir_inner_cycles < 1 || o->ir_inner_cycles > 8)) {
+    if (o->precision == DMGS_FP32_IN_FP64 && (o->ir_inner_cycles < 1 || o->ir_inner_cycles > 16)) {
         set_error("bad ir_inner_cycles %d", o->ir_inner_cycles);
         return DMGS_ERR_INVALID;
     }
@@ -747,7 +747,7 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
         hipLaunchKernelGGL(k_init_iterate<double>, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, x, l0.N, bc);
         LAUNCHCHK();
     }
-    int cycles = 0, status = DMGS_OK;
+    int cycles = 0, vcycles = 0, status = DMGS_OK;
     double r0 = 0.0, rel = 0.0;
     if (!is_ir(P)) {
         double* cur = x;
@@ -787,18 +787,24 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
         TRY(ir_step(P, xc, nullptr, nullptr, b, l0.q32, 0, st, x_zero));
         // While the host waits for a step's residual norm, the first
         // smoothing pass of the next step is already enqueued when the
-        // residual is not expected to meet the tolerance yet (predicted from
-        // the last contraction factor).  The pass writes only the
-        // correction buffers, so a step that does converge discards it.
+        // residual is not expected to meet the tolerance yet.  The pass
+        // writes only the correction buffers, so a step that does converge
+        // discards it.  With ir_adaptive, a step after the first runs the
+        // number of V-cycles the per-cycle contraction factor observed so
+        // far predicts the tolerance needs (at most ir_inner_cycles).
         const bool can_speculate = !fixed && P->L > 1 && fused_level(P, 0) && !block_level<float>(P, 0);
-        double rel1 = 1.0, rel2 = 1.0;   // relative residuals of the last two steps
+        const bool adaptive = !fixed && o.ir_adaptive;
+        double rel1 = 1.0;     // relative residual before the last step
+        double rate = 0.0;     // per-V-cycle contraction factor (0: not known yet)
+        int inner = o.ir_inner_cycles;
         for (cycles = 0;; cycles++) {
             float* e = l0.u32;
             float* eo = l0.t32;
             bool smoothed = false;
             if (!fixed) {
-                const double rho = cycles >= 2 ? rel1 / rel2 : 0.1;
-                if (can_speculate && cycles < o.max_cycles && (cycles == 0 || rel1 * rho > o.rtol)) {
+                // residual the last step is expected to reach
+                const double pred = cycles == 0 ? 1.0 : rel1 * std::pow(rate > 0.0 ? rate : 0.5, inner);
+                if (can_speculate && cycles < o.max_cycles && pred > o.rtol) {
                     TRY(smooth_phase<float>(P, 0, &e, &eo, l0.q32, o.nu_pre, order, true, (const float*)nullptr, st));
                     smoothed = true;
                 }
@@ -812,15 +818,21 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
                     rel = std::sqrt(P->hnorm[1]) / r0;
                     if (!std::isfinite(rel)) { set_error("non-finite residual after %d steps", cycles); status = DMGS_ERR_NONFINITE; break; }
                     if (rel <= o.rtol) break;
+                    rate = rel < rel1 ? std::pow(rel / rel1, 1.0 / inner) : 0.0;
                 }
                 if (cycles >= o.max_cycles) { set_error("not converged after %d steps (rel %.3e)", cycles, rel); status = DMGS_ERR_NOT_CONVERGED; break; }
-                rel2 = rel1;
                 rel1 = rel;
+                inner = o.ir_inner_cycles;
+                if (adaptive && rate > 0.0) {
+                    const double need = std::ceil(std::log(o.rtol / rel) / std::log(rate) - 1e-6);
+                    inner = (int)std::min<double>(inner, std::max(1.0, need));
+                }
             } else if (cycles == o.fixed_cycles) {
                 break;
             }
-            for (int ic = 0; ic < o.ir_inner_cycles; ic++)
+            for (int ic = 0; ic < inner; ic++)
                 TRY(vcycle<float>(P, 0, &e, &eo, l0.q32, order, ic == 0, st, ic == 0 && smoothed));
+            vcycles += inner;
             if (x_zero && cycles == 0 && (P->ir_steps[order] & 1)) {
                 // the first update reads no iterate, so it may write x in
                 // place: with an odd number of steps (as the last solve of
@@ -846,6 +858,7 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
 done:
     if (info) {
         info->cycles = cycles;
+        info->vcycles = is_ir(P) ? vcycles : cycles;
         info->rel_residual = rel;
         info->status = status;
     }
@@ -995,7 +1008,8 @@ void dmgs_default_options(int32_t n, dmgs_options* o) {
     o->h = 1.0;
     o->bc_value = 0.0;
     o->rtol = 1e-10;
-    o->ir_inner_cycles = 2;
+    o->ir_inner_cycles = 8;
+    o->ir_adaptive = 1;
 }
 
 size_t dmgs_workspace_bytes(const dmgs_options* o) {

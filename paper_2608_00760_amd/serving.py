@@ -135,11 +135,12 @@ class Server:
     """Continuous-batching server for DMGS solves on one GPU."""
 
     def __init__(self, budget_bytes=64 << 30, max_slots=8, precision="fp32-in-fp64", rtol=1e-10, device="cuda:0",
-                 keep_results=True, ir_inner_cycles=2):
+                 keep_results=True, ir_inner_cycles=8, ir_adaptive=True):
         import torch
         from .solver import Options, workspace_bytes
         self.device = torch.device(device)
-        self.opts = dict(precision=precision, rtol=rtol, max_cycles=200, ir_inner_cycles=ir_inner_cycles)
+        self.opts = dict(precision=precision, rtol=rtol, max_cycles=200, ir_inner_cycles=ir_inner_cycles,
+                         ir_adaptive=ir_adaptive)
         self.adm = Admission(budget_bytes, max_slots)
         self.keep = keep_results
         self.pool = collections.defaultdict(list)   # N -> idle plans

@@ -28,7 +28,8 @@ class Options:
     face_mean: str = "arith"
     h: float = 1.0
     bc_value: float = 0.0
-    ir_inner_cycles: int = 2
+    ir_inner_cycles: int = 8          # float32 V-cycles per refinement step (the most, when adaptive)
+    ir_adaptive: bool = True          # later steps run the V-cycles the observed contraction predicts
 
     def to_c(self):
         o = _abi.default_options(self.N)
@@ -40,6 +41,7 @@ class Options:
         o.face_mean = _FACE[self.face_mean]
         o.h, o.bc_value = float(self.h), float(self.bc_value)
         o.ir_inner_cycles = int(self.ir_inner_cycles)
+        o.ir_adaptive = 1 if self.ir_adaptive else 0
         return o
 
 

@@ -177,3 +177,25 @@ def test_determinism_bitwise():
         (ga, _, _), _ = P.vjp(a, dev(c["rhobar"]))
         (gb, _, _), _ = P.vjp(a, dev(c["rhobar"]))
         assert bool((ga == gb).all())
+
+
+def test_adaptive_refinement_steps():
+    """Adaptive inner V-cycle counts reach the tolerance with no more float32
+    V-cycles than fixed two-cycle steps need (plus one), in fewer steps."""
+    from paper_2608_00760_amd import synth
+    say("adaptive refinement")
+    N = 64
+    c = grf_inputs(N, 11)
+    Pa = plan_for(c["D"], c["mua"], precision="fp32-in-fp64")
+    Pf = plan_for(c["D"], c["mua"], precision="fp32-in-fp64", ir_inner_cycles=2, ir_adaptive=False)
+    ra, ia = Pa.forward(dev(c["q"]))
+    rf, if_ = Pf.forward(dev(c["q"]))
+    assert ia["rel_residual"] <= 1e-10 and if_["rel_residual"] <= 1e-10
+    assert if_["vcycles"] == 2 * if_["cycles"]
+    assert ia["vcycles"] <= if_["vcycles"] + 1 and ia["cycles"] < if_["cycles"], (ia, if_)
+    assert rel_max(host(ra), host(rf)) <= 1e-8
+    (qa, _, _), va = Pa.vjp(ra, dev(c["rhobar"]))
+    (qf, _, _), vf = Pf.vjp(rf, dev(c["rhobar"]))
+    assert va["rel_residual"] <= 1e-10 and vf["rel_residual"] <= 1e-10
+    assert va["vcycles"] <= vf["vcycles"] + 1 and va["cycles"] < vf["cycles"], (va, vf)
+    assert rel_max(host(qa), host(qf)) <= 1e-8
