@@ -119,7 +119,7 @@ size_t footprint(const dmgs_options* o) {
     size_t b = 0;
     for (int k = 0; k < s.L; k++) {
         b += 2 * s.nv[k] * sizeof(double);                            // D64, mu64
-        if (ir) b += 6 * s.nv[k] * sizeof(float);                     // D32, mu32, w32, u32, q32, t32
+        if (ir) b += (k < s.L - 1 ? 7 : 6) * s.nv[k] * sizeof(float);  // D32, mu32, w32, u32, q32, t32, (r32)
         else b += (k > 0 ? 4 : 2) * s.nv[k] * sizeof(double);         // w64, (u64, q64), t64
     }
     b += (ir ? 2 : 1) * s.nv[0] * sizeof(double);                     // scratch64 (+ xalt64)
@@ -143,7 +143,7 @@ void free_plan(dmgs_plan P) {
     if (!P) return;
     for (int k = 0; k < P->L; k++) {
         Level& l = P->lev[k];
-        void* ps[] = {l.D64, l.mu64, l.w64, l.D32, l.mu32, l.w32, l.u64, l.q64, l.t64, l.u32, l.q32, l.t32};
+        void* ps[] = {l.D64, l.mu64, l.w64, l.D32, l.mu32, l.w32, l.u64, l.q64, l.t64, l.u32, l.q32, l.t32, l.r32};
         for (void* p : ps)
             if (p) (void)hipFree(p);
     }
@@ -343,11 +343,12 @@ int smooth_pass(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int ord
 // Two-sweep passes (float32): tiles of 16 x 64; chunks of x-planes sized
 // for about cfg_sweep2_wgs workgroups, at least 8 planes (a chunk
 // recomputes 3 planes at each end).
-template <class T, int TY, int TZ, bool HARM>
+template <class T, int TY, int TZ, bool HARM, bool DEFECT>
 int launch_sweep2(dmgs_plan P, const SweepArgs<T>& a0, int N, int mode, hipStream_t st) {
     SweepArgs<T> a = a0;
-    constexpr int NT = Sweep2Shape<TY, TZ>::NT;
-    constexpr size_t lds = sweep2_lds_bytes<T, TY, TZ>();
+    constexpr int RING = DEFECT ? 5 : 4;
+    constexpr int NT = Sweep2Shape<TY, TZ, RING>::NT;
+    constexpr size_t lds = sweep2_lds_bytes<T, TY, TZ, RING>();
     a.tiles_y = (N + TY - 1) / TY;
     a.tiles_z = (N + TZ - 1) / TZ;
     const int tiles = a.tiles_y * a.tiles_z;
@@ -355,9 +356,9 @@ int launch_sweep2(dmgs_plan P, const SweepArgs<T>& a0, int N, int mode, hipStrea
     a.chunk = std::min(N - 1, std::max(8, (N - 1 + nch - 1) / nch));
     a.nchunks = (N - 1 + a.chunk - 1) / a.chunk;
     const int nb = tiles * a.nchunks;
-    if (mode == kSweepZero) hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepZero, HARM>), dim3(nb), dim3(NT), lds, st, a);
-    else if (mode == kSweepProlong) hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepProlong, HARM>), dim3(nb), dim3(NT), lds, st, a);
-    else hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepPlain, HARM>), dim3(nb), dim3(NT), lds, st, a);
+    if (mode == kSweepZero) hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepZero, HARM, DEFECT>), dim3(nb), dim3(NT), lds, st, a);
+    else if (mode == kSweepPlain) hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepPlain, HARM, DEFECT>), dim3(nb), dim3(NT), lds, st, a);
+    else if constexpr (!DEFECT) hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepProlong, HARM>), dim3(nb), dim3(NT), lds, st, a);
     LAUNCHCHK();
     return DMGS_OK;
 }
@@ -367,15 +368,20 @@ constexpr int kSweep2TY = 16, kSweep2TZ = 64;
 // Dynamic-LDS limits of the two-sweep kernels (set once per plan).
 int sweep2_attributes() {
     constexpr int lds = (int)sweep2_lds_bytes<float, kSweep2TY, kSweep2TZ>();
-    const void* fns[] = {
-        (const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepPlain, false>,
-        (const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepZero, false>,
-        (const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepProlong, false>,
-        (const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepPlain, true>,
-        (const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepZero, true>,
-        (const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepProlong, true>};
-    for (const void* f : fns)
-        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) {
+    constexpr int ldsd = (int)sweep2_lds_bytes<float, kSweep2TY, kSweep2TZ, 5>();
+    const std::pair<const void*, int> fns[] = {
+        {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepPlain, false>, lds},
+        {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepZero, false>, lds},
+        {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepProlong, false>, lds},
+        {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepPlain, true>, lds},
+        {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepZero, true>, lds},
+        {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepProlong, true>, lds},
+        {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepPlain, false, true>, ldsd},
+        {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepZero, false, true>, ldsd},
+        {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepPlain, true, true>, ldsd},
+        {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepZero, true, true>, ldsd}};
+    for (const auto& f : fns)
+        if (hipFuncSetAttribute(f.first, hipFuncAttributeMaxDynamicSharedMemorySize, f.second) != hipSuccess) {
             set_error("hipFuncSetAttribute failed");
             return DMGS_ERR_HIP;
         }
@@ -392,7 +398,7 @@ bool use_sweep2(dmgs_plan P, int k, size_t tsize) {
 // 0, or to u_in + I ec).
 template <class T>
 int smooth_pass2(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int order, bool zero, const T* ec,
-                 hipStream_t st) {
+                 hipStream_t st, T* r = nullptr) {
     const Level& l = P->lev[k];
     SweepArgs<T> a;
     a.u_in = u_in;
@@ -401,17 +407,22 @@ int smooth_pass2(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int or
     a.D = Typed<T>::D(l);
     a.w = Typed<T>::w(l);
     a.ec = ec;
+    a.r = r;
     a.N = l.N;
     a.order = order;
     a.st = l.stencil<T>(harmonic(P));
     const int mode = zero ? kSweepZero : (ec ? kSweepProlong : kSweepPlain);
-    // algorithmic bytes: read u (unless zero), q, D, w, (ec), write u -- once for both sweeps
-    double words = (zero ? 4.0 : 5.0) + (ec ? 0.125 : 0.0);
+    if (r && ec) { set_error("two-sweep pass: defect only after pre-smoothing"); return DMGS_ERR_INVALID; }
+    // algorithmic bytes: read u (unless zero), q, D, w, (ec), write u, (r) -- once for both sweeps
+    double words = (zero ? 4.0 : 5.0) + (ec ? 0.125 : 0.0) + (r ? 1.0 : 0.0);
     int slot;
     TRY(tbeg(P, k, st, &slot));
     if constexpr (sizeof(T) == 4) {
-        if (harmonic(P)) TRY((launch_sweep2<T, kSweep2TY, kSweep2TZ, true>(P, a, l.N, mode, st)));
-        else TRY((launch_sweep2<T, kSweep2TY, kSweep2TZ, false>(P, a, l.N, mode, st)));
+        const bool h = harmonic(P);
+        if (r) TRY(h ? (launch_sweep2<T, kSweep2TY, kSweep2TZ, true, true>(P, a, l.N, mode, st))
+                     : (launch_sweep2<T, kSweep2TY, kSweep2TZ, false, true>(P, a, l.N, mode, st)));
+        else TRY(h ? (launch_sweep2<T, kSweep2TY, kSweep2TZ, true, false>(P, a, l.N, mode, st))
+                   : (launch_sweep2<T, kSweep2TY, kSweep2TZ, false, false>(P, a, l.N, mode, st)));
     } else {
         set_error("two-sweep pass is float32 only");
         return DMGS_ERR_INVALID;
@@ -422,7 +433,7 @@ int smooth_pass2(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int or
 
 // Chunks of coarse planes sized for about cfg_dr_wgs workgroups (each
 // chunk re-reads the fine planes at its ends), at least 4.
-template <class T, int TYC, int TZC, bool HARM>
+template <class T, int TYC, int TZC, bool HARM, bool FROM_R>
 int launch_restrict(dmgs_plan P, const RestrictArgs<T>& a0, int Nc, hipStream_t st) {
     RestrictArgs<T> a = a0;
     constexpr int NT = RestrictShape<TYC, TZC>::NT;
@@ -434,13 +445,16 @@ int launch_restrict(dmgs_plan P, const RestrictArgs<T>& a0, int Nc, hipStream_t 
     if (a.chunk > Nc - 1) a.chunk = Nc - 1;
     a.nchunks = (Nc - 1 + a.chunk - 1) / a.chunk;
     int nb = a.tiles_y * a.tiles_z * a.nchunks;
-    hipLaunchKernelGGL((k_defect_restrict_col<T, TYC, TZC, HARM>), dim3(nb), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL((k_defect_restrict_col<T, TYC, TZC, HARM, FROM_R>), dim3(nb), dim3(NT), 0, st, a);
     LAUNCHCHK();
     return DMGS_OK;
 }
 
+// qc = R (q - A u); from_r: u holds the defect itself after pre-smoothing
+// whose first colour was `order` (the other colour's defect is 0), qc = R u.
 template <class T>
-int defect_restrict(dmgs_plan P, int k, const T* u, const T* q, T* qc, hipStream_t st) {
+int defect_restrict(dmgs_plan P, int k, const T* u, const T* q, T* qc, hipStream_t st, bool from_r = false,
+                    int order = 0) {
     const Level& l = P->lev[k];
     const Level& c = P->lev[k + 1];
     RestrictArgs<T> a;
@@ -450,22 +464,27 @@ int defect_restrict(dmgs_plan P, int k, const T* u, const T* q, T* qc, hipStream
     a.mu = Typed<T>::mu(l);
     a.qc = qc;
     a.N = l.N;
+    a.rzero = order ? 0 : 1;
     a.st = l.stencil<T>(harmonic(P));
     constexpr int TYC = 8, TZC = sizeof(T) == 4 ? 32 : 16;
     int slot;
     TRY(tbeg(P, k, st, &slot));
-    if (harmonic(P)) TRY((launch_restrict<T, TYC, TZC, true>(P, a, c.N, st)));
-    else TRY((launch_restrict<T, TYC, TZC, false>(P, a, c.N, st)));
-    TRY(tend(P, slot, DMGS_K_DEFECT_RESTRICT, (4.0 * l.nv + c.nv) * sizeof(T), st));
+    if (from_r) TRY((launch_restrict<T, TYC, TZC, false, true>(P, a, c.N, st)));
+    else if (harmonic(P)) TRY((launch_restrict<T, TYC, TZC, true, false>(P, a, c.N, st)));
+    else TRY((launch_restrict<T, TYC, TZC, false, false>(P, a, c.N, st)));
+    TRY(tend(P, slot, DMGS_K_DEFECT_RESTRICT, ((from_r ? 1.0 : 4.0) * l.nv + c.nv) * sizeof(T), st));
     return DMGS_OK;
 }
 
 // Smoothing phase of `nsweeps` red-black sweeps on level k starting from
 // *cur (zero: from 0; ec: add I ec first, fused into the first sweep).
 // Result left in *cur, which swaps between the level's two buffers.
+// rout: when the phase ends with a two-sweep pass, that pass also writes
+// the defect of the result to rout and *rdone is set.
 template <class T>
 int smooth_phase(dmgs_plan P, int k, T** cur, T** other, const T* q, int nsweeps, int order, bool zero, const T* ec,
-                 hipStream_t st) {
+                 hipStream_t st, T* rout = nullptr, bool* rdone = nullptr) {
+    if (rdone) *rdone = false;
     const Level& l = P->lev[k];
     if (nsweeps == 0) {
         if (zero) TRY(fill<T>(*cur, l.nv, T(0), st));
@@ -479,7 +498,10 @@ int smooth_phase(dmgs_plan P, int k, T** cur, T** other, const T* q, int nsweeps
         const bool z = i == 0 && zero;
         const T* e = i == 0 ? ec : nullptr;
         if (nsweeps - i >= 2 && use_sweep2(P, k, sizeof(T))) {
-            TRY(smooth_pass2<T>(P, k, *cur, *other, q, order, z, e, st));
+            const bool want = P->cfg_defect == 2 || (P->cfg_defect == 1 && z);
+            T* r = (want && nsweeps - i == 2 && !e && rout && rdone) ? rout : nullptr;
+            TRY(smooth_pass2<T>(P, k, *cur, *other, q, order, z, e, st, r));
+            if (r) *rdone = true;
             i += 2;
         } else {
             TRY(smooth_pass<T>(P, k, *cur, *other, q, order, z, e, st));
@@ -581,8 +603,10 @@ int pre_pass(dmgs_plan P, int k, T** cur, T** other, const T* q, T* qc, int orde
     const Level& l = P->lev[k];
     if (block_level<T>(P, k)) return block_phase<T>(P, k, cur, other, q, qc, (const T*)nullptr, order, zero, false, st);
     if (fused_level(P, k)) {
-        TRY(smooth_phase<T>(P, k, cur, other, q, P->opt.nu_pre, order, zero, (const T*)nullptr, st));
-        return defect_restrict<T>(P, k, *cur, q, qc, st);
+        bool rdone;
+        T* r = Typed<T>::r(l);
+        TRY(smooth_phase<T>(P, k, cur, other, q, P->opt.nu_pre, order, zero, (const T*)nullptr, st, r, &rdone));
+        return rdone ? defect_restrict<T>(P, k, r, q, qc, st, true, order) : defect_restrict<T>(P, k, *cur, q, qc, st);
     }
     if (zero) TRY(fill<T>(*cur, l.nv, T(0), st));
     TRY(sweeps<T>(P, k, *cur, q, P->opt.nu_pre, order, st));
@@ -641,10 +665,11 @@ int small_level(dmgs_plan P) { return sizeof(T) == 4 ? P->small32 : P->small64; 
 // level's other buffer is *other).  zero: the iterate starts from 0 (coarse
 // corrections, refinement corrections).  On return *cur holds the result.
 // smoothed: the pre-smoothing of level k has already been enqueued (level k
-// uses the streaming passes); the cycle continues with the defect.
+// uses the streaming passes); the cycle continues with the defect, which
+// that pre-smoothing already wrote to the level's r buffer when rdone.
 template <class T>
 int vcycle(dmgs_plan P, int k, T** cur, T** other, const T* q, int order, bool zero, hipStream_t st,
-           bool smoothed = false) {
+           bool smoothed = false, bool rdone = false) {
     if (k > 0 && k == small_level<T>(P) && zero) {
         if (harmonic(P)) return launch_small_t<T, true>(P, k, q, *cur, order, st);
         return launch_small_t<T, false>(P, k, q, *cur, order, st);
@@ -655,7 +680,8 @@ int vcycle(dmgs_plan P, int k, T** cur, T** other, const T* q, int order, bool z
     }
     const Level& c = P->lev[k + 1];
     T* qc = Typed<T>::q(c);
-    if (smoothed) TRY(defect_restrict<T>(P, k, *cur, q, qc, st));
+    if (smoothed) TRY(rdone ? defect_restrict<T>(P, k, Typed<T>::r(P->lev[k]), q, qc, st, true, order)
+                            : defect_restrict<T>(P, k, *cur, q, qc, st));
     else TRY(pre_pass<T>(P, k, cur, other, q, qc, order, zero, st));
     T* ccur = Typed<T>::u(c);
     T* coth = Typed<T>::t(c);
@@ -800,12 +826,13 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
         for (cycles = 0;; cycles++) {
             float* e = l0.u32;
             float* eo = l0.t32;
-            bool smoothed = false;
+            bool smoothed = false, rdone = false;
             if (!fixed) {
                 // residual the last step is expected to reach
                 const double pred = cycles == 0 ? 1.0 : rel1 * std::pow(rate > 0.0 ? rate : 0.5, inner);
                 if (can_speculate && cycles < o.max_cycles && pred > o.rtol) {
-                    TRY(smooth_phase<float>(P, 0, &e, &eo, l0.q32, o.nu_pre, order, true, (const float*)nullptr, st));
+                    TRY(smooth_phase<float>(P, 0, &e, &eo, l0.q32, o.nu_pre, order, true, (const float*)nullptr, st,
+                                            l0.r32, &rdone));
                     smoothed = true;
                 }
                 TRY(read_norms(P, st));
@@ -831,7 +858,7 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
                 break;
             }
             for (int ic = 0; ic < inner; ic++)
-                TRY(vcycle<float>(P, 0, &e, &eo, l0.q32, order, ic == 0, st, ic == 0 && smoothed));
+                TRY(vcycle<float>(P, 0, &e, &eo, l0.q32, order, ic == 0, st, ic == 0 && smoothed, rdone));
             vcycles += inner;
             if (x_zero && cycles == 0 && (P->ir_steps[order] & 1)) {
                 // the first update reads no iterate, so it may write x in
@@ -1047,6 +1074,7 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
             if (st == DMGS_OK) st = dalloc(P, &l.u32, l.nv);
             if (st == DMGS_OK) st = dalloc(P, &l.q32, l.nv);
             if (st == DMGS_OK) st = dalloc(P, &l.t32, l.nv);
+            if (k < s.L - 1 && st == DMGS_OK) st = dalloc(P, &l.r32, l.nv);
         } else {
             if (st == DMGS_OK) st = dalloc(P, &l.w64, l.nv);
             if (k > 0 && st == DMGS_OK) st = dalloc(P, &l.u64, l.nv);
@@ -1110,6 +1138,7 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     P->cfg_block_max = 64;
     P->cfg_dr_wgs = 512;
     if (const char* e = std::getenv("DMGS_DR_WGS")) P->cfg_dr_wgs = std::max(16, std::atoi(e));
+    if (const char* e = std::getenv("DMGS_SWEEP2_DEFECT")) P->cfg_defect = std::min(2, std::max(0, std::atoi(e)));
     if (const char* e = std::getenv("DMGS_BLOCK_MAX")) P->cfg_block_max = std::atoi(e);
     P->cfg_sweep2_min = 64;
     P->cfg_sweep2_wgs = 256;

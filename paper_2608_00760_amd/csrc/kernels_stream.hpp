@@ -78,6 +78,7 @@ struct SweepArgs {
     const T* D;
     const T* w;      // inverse diagonal
     const T* ec;     // coarse correction added by prolongation (MODE 2)
+    T* r;            // defect of the result (two-sweep passes with DEFECT)
     int N;
     int order;       // colour of the first stage: 0 red, 1 black
     int tiles_y, tiles_z, chunk, nchunks;
@@ -266,6 +267,7 @@ struct RestrictArgs {
     const T* mu;
     T* qc;
     int N;   // fine cells per axis
+    int rzero;   // FROM_R: colour ((x+y+z) mod 2) whose defect is 0 and not read
     int tiles_y, tiles_z, chunk, nchunks;
     Stencil<T> st;
 };
@@ -282,7 +284,9 @@ struct RestrictShape {
     static_assert(TYC * TZC <= NT, "coarse tile larger than the workgroup");
 };
 
-template <class T, int TYC, int TZC, bool HARM>
+// FROM_R: the fine defect is given (in a.u, 0 off the interior; the colour
+// a.rzero is taken as 0 and not read) and only restricted.
+template <class T, int TYC, int TZC, bool HARM, bool FROM_R = false>
 __global__ __launch_bounds__((RestrictShape<TYC, TZC>::NT)) void k_defect_restrict_col(RestrictArgs<T> a) {
     using Sh = RestrictShape<TYC, TZC>;
     constexpr int NP = Sh::NP, RY = Sh::RY, RZ = Sh::RZ, RA = Sh::RA;
@@ -321,10 +325,11 @@ __global__ __launch_bounds__((RestrictShape<TYC, TZC>::NT)) void k_defect_restri
     auto load = [&](int p, ResPlane<T>& P) {
         const bool pv = p >= p_lo && p <= p_hi && p >= 0 && p <= N;
         const auto rU = plane_rsrc(a.u, plane_bytes, p, pv);
+        P.u0 = buf_load<T>(rU, off0); P.u1 = buf_load<T>(rU, off1);
+        if (FROM_R) return;
         const auto rD = plane_rsrc(a.D, plane_bytes, p, pv);
         const auto rQ = plane_rsrc(a.q, plane_bytes, p, pv);
         const auto rM = plane_rsrc(a.mu, plane_bytes, p, pv);
-        P.u0 = buf_load<T>(rU, off0); P.u1 = buf_load<T>(rU, off1);
         P.D0 = buf_load<T>(rD, off0); P.D1 = buf_load<T>(rD, off1);
         P.q0 = buf_load<T>(rQ, off0); P.q1 = buf_load<T>(rQ, off1);
         P.m0 = buf_load<T>(rM, off0); P.m1 = buf_load<T>(rM, off1);
@@ -364,11 +369,18 @@ __global__ __launch_bounds__((RestrictShape<TYC, TZC>::NT)) void k_defect_restri
         const int sl = p & 1;
         T* U = sU[sl];
         T* Dl = sD[sl];
-        if (act) { U[e0] = P0.u0; U[e0 + 1] = P0.u1; Dl[e0] = P0.D0; Dl[e0 + 1] = P0.D1; }
+        if (act && !FROM_R) { U[e0] = P0.u0; U[e0 + 1] = P0.u1; Dl[e0] = P0.D0; Dl[e0 + 1] = P0.D1; }
         lds_barrier();
         const bool pin = p >= 1 && p <= N - 1;
-        const T r0 = (pin && rc0) ? resid(std::integral_constant<int, 0>(), U, Dl, Pm1, P0, Pp1) : T(0);
-        const T r1 = (pin && rc1) ? resid(std::integral_constant<int, 1>(), U, Dl, Pm1, P0, Pp1) : T(0);
+        T r0, r1;
+        if (FROM_R) {
+            const bool z0c = ((p + y + zl) & 1) == a.rzero;   // colour of element 0 is the zero colour
+            r0 = (pin && rc0 && !z0c) ? P0.u0 : T(0);
+            r1 = (pin && rc1 && z0c) ? P0.u1 : T(0);
+        } else {
+            r0 = (pin && rc0) ? resid(std::integral_constant<int, 0>(), U, Dl, Pm1, P0, Pp1) : T(0);
+            r1 = (pin && rc1) ? resid(std::integral_constant<int, 1>(), U, Dl, Pm1, P0, Pp1) : T(0);
+        }
         if (act) { sR[sl][e0] = r0; sR[sl][e0 + 1] = r1; }
         // sR[sl ^ 1] was written before this step's barrier
         if (cown && p > p_first) restrict_plane(p - 1);

@@ -36,14 +36,26 @@
 // step s all four stages update the same element of the pair, (s + row
 // parity + order) mod 2, uniform across a wave because waves hold rows of
 // one parity.
+//
+// With DEFECT the pass also writes the defect r = q - A u of its result on
+// the tile (the restriction of the next coarser right-hand side then reads
+// r alone).  The loaded ring grows to 5 so that the final values are known
+// on the tile plus a ring of 1, the stages run one step earlier and one
+// step longer, the last stage publishes its values to the slot too, and at
+// step s the defect of plane s - 4 is formed from the slots of planes s - 4
+// and s - 5 and the registers of plane s - 3.  After a red-black sweep the
+// residual of the colour updated last is zero (its update solved its own
+// equation with its neighbours' final values), so only the first colour's
+// residual is computed and stored; the reader takes the second colour's as
+// 0.  Waves with no tile vertex skip the defect.
 #pragma once
 #include "kernels_stream.hpp"
 
 namespace dmgs {
 
-template <int TY, int TZ>
+template <int TY, int TZ, int RING = 4>
 struct Sweep2Shape {
-    static constexpr int R = 4;                              // ring of loaded vertices
+    static constexpr int R = RING;                           // ring of loaded vertices
     static constexpr int NP = TZ / 2 + R, RY = TY + 2 * R;   // pairs per row, rows
     static constexpr int RA = RY * NP;                       // pairs per plane (per element)
     static constexpr int ROWS_HALF = RY / 2;
@@ -63,9 +75,9 @@ struct UD {
     T u, D;
 };
 
-template <class T, int TY, int TZ>
+template <class T, int TY, int TZ, int RING = 4>
 constexpr size_t sweep2_lds_bytes() {
-    using Sh = Sweep2Shape<TY, TZ>;
+    using Sh = Sweep2Shape<TY, TZ, RING>;
     return (size_t)Sh::ENTRIES * sizeof(UD<T>) + (size_t)Sh::CSLOTS * Sh::CPL * sizeof(T);
 }
 
@@ -76,10 +88,11 @@ __host__ __device__ constexpr bool sweep2_fits(int N) {
     return ((int64_t)(N + 1) * (N + 1) * (N + 20) + 64) * (int64_t)sizeof(T) < (int64_t)kOob;
 }
 
-template <class T, int TY, int TZ, int MODE, bool HARM>
-__global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(SweepArgs<T> a) {
+template <class T, int TY, int TZ, int MODE, bool HARM, bool DEFECT = false>
+__global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_rb_sweep2_col(SweepArgs<T> a) {
     constexpr bool ZERO_INIT = MODE == kSweepZero, PROLONG = MODE == kSweepProlong;
-    using Sh = Sweep2Shape<TY, TZ>;
+    static_assert(!(DEFECT && PROLONG), "the defect is formed after pre-smoothing only");
+    using Sh = Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>;
     constexpr int R = Sh::R, NP = Sh::NP, RA = Sh::RA, HALF = Sh::HALF;
     // slot k, element O: ring[(k * 2 + O) * RA + ly * NP + pz]
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -107,7 +120,7 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
     // the grid read 0, columns just outside it read finite neighbours' data
     // that no update of an interior vertex uses
     const int off = (y >= 0 && y <= N) ? (y * n + zl) * (int)sizeof(T) : kOob;
-    // ring membership: stage j updates a vertex within 3 - j of the tile
+    // ring membership: stage j updates a vertex within R - 1 - j of the tile
     auto in_ring = [&](int z, int r) {
         return y >= max(1, y0 - r) && y <= min(N - 1, y0 + TY - 1 + r) && z >= max(1, z0 - r) &&
                z <= min(N - 1, z0 + TZ - 1 + r);
@@ -115,11 +128,12 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
     bool m0[4], m1[4];
 #pragma unroll
     for (int j = 0; j < 4; j++) {
-        m0[j] = in_ring(zl, 3 - j);
-        m1[j] = in_ring(zl + 1, 3 - j);
+        m0[j] = in_ring(zl, R - 1 - j);
+        m1[j] = in_ring(zl + 1, R - 1 - j);
     }
-    const int soff0 = (own && m0[3]) ? off : kOob;   // tile vertices are stored
-    const int soff1 = (own && m1[3]) ? off + (int)sizeof(T) : kOob;
+    const int soff0 = (own && in_ring(zl, 0)) ? off : kOob;   // tile vertices are stored
+    const int soff1 = (own && in_ring(zl + 1, 0)) ? off + (int)sizeof(T) : kOob;
+    const auto rR = field_rsrc(a.r, DEFECT ? field_bytes : 0);
     const auto rU = field_rsrc(a.u_in, field_bytes), rD = field_rsrc(a.D, field_bytes);
     const auto rQ = field_rsrc(a.q, field_bytes), rW = field_rsrc(a.w, field_bytes);
     const auto rO = field_rsrc(a.u_out, field_bytes);
@@ -191,11 +205,11 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
     };
     T cg = T(0);   // loader: coarse value in flight
 
-    // Gauss-Seidel value of element O of the pair on a plane whose slot is
-    // S: w (q + sum_j c_ij u_j); x-neighbours from the planes below (Pb) and
-    // above (Pa), the in-pair z-neighbour from registers, the others from
-    // the slot.
-    auto update = [&](auto Oc, const UD<T>* S, const SweepPlane<T>& Pb, const SweepPlane<T>& P,
+    // q + sum_j c_ij u_j at element O of the pair on a plane whose slot is
+    // S (the Gauss-Seidel value is w times it); x-neighbours from the planes
+    // below (Pb) and above (Pa), the in-pair z-neighbour from registers, the
+    // others from the slot.
+    auto gs_num = [&](auto Oc, const UD<T>* S, const SweepPlane<T>& Pb, const SweepPlane<T>& P,
                       const SweepPlane<T>& Pa) -> T {
         constexpr int O = decltype(Oc)::value;
         const UD<T>* So = S + O * RA + pe;          // same element, this pair
@@ -222,7 +236,12 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
                         ((Di + Dzl) * uzl + (Di + Dzr) * uzr);
             num = (O ? P.q1 : P.q0) + s * a.st.half_inv_h2;
         }
-        return num * (O ? P.w1 : P.w0);
+        return num;
+    };
+    auto update = [&](auto Oc, const UD<T>* S, const SweepPlane<T>& Pb, const SweepPlane<T>& P,
+                      const SweepPlane<T>& Pa) -> T {
+        constexpr int O = decltype(Oc)::value;
+        return gs_num(Oc, S, Pb, P, Pa) * (O ? P.w1 : P.w0);
     };
 
     // stage j at unrolled step K updates element O of plane s - j (slot (K - j) mod 8)
@@ -234,11 +253,31 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
         const T v = (ZERO_INIT && J == 0) ? (O ? P.q1 * P.w1 : P.q0 * P.w0) : update(Oc, S, Pb, P, Pa);
         if (O) {
             P.u1 = m1[J] ? v : P.u1;
-            if (J < 3) S[RA + pe].u = P.u1;
+            if (J < 3 || DEFECT) S[RA + pe].u = P.u1;
         } else {
             P.u0 = m0[J] ? v : P.u0;
-            if (J < 3) S[pe].u = P.u0;
+            if (J < 3 || DEFECT) S[pe].u = P.u0;
         }
+    };
+    // defect of plane s - 4 (final since step s - 1) at element O, the
+    // colour of the first half-sweep: x-neighbour below from the slot of
+    // plane s - 5, above from the registers of plane s - 3 (final after this
+    // step's last stage)
+    const bool dwave = __builtin_amdgcn_ballot_w64(soff0 != kOob || soff1 != kOob) != 0;
+    auto defect = [&](auto Oc, auto Kc, int s, const SweepPlane<T>& Pm4, const SweepPlane<T>& Pm3) {
+        if (!dwave) return;
+        constexpr int O = decltype(Oc)::value, K = decltype(Kc)::value;
+        const UD<T>* S4 = ring + ((K + 4) & 7) * 2 * RA;
+        const UD<T> xm = ring[((K + 3) & 7) * 2 * RA + O * RA + pe];
+        SweepPlane<T> Pb;
+        Pb.u0 = Pb.u1 = xm.u;
+        Pb.D0 = Pb.D1 = xm.D;
+        const T num = gs_num(Oc, S4, Pb, Pm4, Pm3);
+        // diagonal 1/w by the hardware reciprocal (1 ulp; the difference is
+        // rounded in float32 anyway)
+        const T r = num - (O ? Pm4.u1 * __builtin_amdgcn_rcpf(Pm4.w1) : Pm4.u0 * __builtin_amdgcn_rcpf(Pm4.w0));
+        const int po = s - 4;
+        if (po >= xa && po < xb) buf_store<T>(r, rR, (O ? soff1 : soff0) + po * plane_bytes);
     };
     auto stages = [&](auto Oc, auto Kc, SweepPlane<T>& Pm4, SweepPlane<T>& Pm3, SweepPlane<T>& Pm2,
                       SweepPlane<T>& Pm1, SweepPlane<T>& P0, SweepPlane<T>& Pp1) {
@@ -248,7 +287,8 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
         stage(Oc, std::integral_constant<int, 3>(), Kc, Pm4, Pm3, Pm2);
     };
 
-    const int s0 = xa - 3, s_end = xb + 2;
+    // with DEFECT, final values are needed on planes xa - 1 .. xb
+    const int s0 = xa - 3 - (DEFECT ? 1 : 0), s_end = xb + 2 + (DEFECT ? 1 : 0);
     const int par0 = __builtin_amdgcn_readfirstlane((s0 + hp + a.order) & 1);   // element updated at step s0
     auto step = [&](auto Kc, int s, SweepPlane<T>& Pm4, SweepPlane<T>& Pm3, SweepPlane<T>& Pm2, SweepPlane<T>& Pm1,
                     SweepPlane<T>& P0, SweepPlane<T>& Pp1) {
@@ -264,8 +304,13 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ>::NT)) void k_rb_sweep2_col(Swe
                 cg = coarse_plane((s + 4) >> 1);
             }
         }
-        if (par0 ^ (K & 1)) stages(std::integral_constant<int, 1>(), Kc, Pm4, Pm3, Pm2, Pm1, P0, Pp1);
-        else stages(std::integral_constant<int, 0>(), Kc, Pm4, Pm3, Pm2, Pm1, P0, Pp1);
+        if (par0 ^ (K & 1)) {
+            stages(std::integral_constant<int, 1>(), Kc, Pm4, Pm3, Pm2, Pm1, P0, Pp1);
+            if (DEFECT) defect(std::integral_constant<int, 1>(), Kc, s, Pm4, Pm3);
+        } else {
+            stages(std::integral_constant<int, 0>(), Kc, Pm4, Pm3, Pm2, Pm1, P0, Pp1);
+            if (DEFECT) defect(std::integral_constant<int, 0>(), Kc, s, Pm4, Pm3);
+        }
         const int po = s - 3;   // final
         if (po >= xa && po < xb) {
             buf_store<T>(Pm3.u0, rO, soff0 + po * plane_bytes);

@@ -21,6 +21,7 @@ struct Level {
     // iterate, right-hand side and scratch of the cycle on this level
     double *u64 = nullptr, *q64 = nullptr, *t64 = nullptr;
     float *u32 = nullptr, *q32 = nullptr, *t32 = nullptr;
+    float* r32 = nullptr;   // fine defect written by pre-smoothing passes (iterative-refinement plans, not the coarsest)
 
     template <class T> Stencil<T> stencil(int harmonic) const {
         Stencil<T> s;
@@ -39,6 +40,7 @@ template <> struct Typed<double> {
     static double* u(const Level& l) { return l.u64; }
     static double* q(const Level& l) { return l.q64; }
     static double* t(const Level& l) { return l.t64; }
+    static double* r(const Level&) { return nullptr; }
 };
 template <> struct Typed<float> {
     static float* D(const Level& l) { return l.D32; }
@@ -47,6 +49,7 @@ template <> struct Typed<float> {
     static float* u(const Level& l) { return l.u32; }
     static float* q(const Level& l) { return l.q32; }
     static float* t(const Level& l) { return l.t32; }
+    static float* r(const Level& l) { return l.r32; }
 };
 
 }  // namespace dmgs
@@ -70,6 +73,7 @@ struct dmgs_plan_s {
     int cfg_sweep2_min = 64, cfg_sweep2_wgs = 256;   // two-sweep passes: smallest N, target workgroups
     int cfg_block_max = 64;                         // block passes: largest N
     int cfg_dr_wgs = 512;                           // defect-restriction passes: target workgroups
+    int cfg_defect = 2;   // two-sweep pre-smoothing writes the defect: 0 never, 1 from a zero iterate, 2 always
     int small32 = -1, small64 = -1;   // first level of the single-workgroup coarse kernel
     double* partial = nullptr;     // first-stage reduction partials
     double* cinv = nullptr;        // inverse of the coarsest operator (kCoarseMax^2 entries)

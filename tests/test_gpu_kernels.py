@@ -103,8 +103,11 @@ def test_pre_and_post_passes_fp64(N, order, face_mean):
 # Float32 smoothing-pass variants: the plan's default choice, two-sweep
 # passes forced on every level with N >= 16 (several x-chunks), and the same
 # with one chunk per tile column.
+# the two-sweep pre-smoothing writes the defect (the restriction then reads
+# it) unless DMGS_SWEEP2_DEFECT=0, which keeps the fused defect-restriction
 PASS_VARIANTS = {"default": {}, "sweep2": {"DMGS_SWEEP2_MIN": "16"},
-                 "sweep2_one_chunk": {"DMGS_SWEEP2_MIN": "16", "DMGS_SWEEP2_WGS": "16"}}
+                 "sweep2_one_chunk": {"DMGS_SWEEP2_MIN": "16", "DMGS_SWEEP2_WGS": "16"},
+                 "sweep2_no_defect": {"DMGS_SWEEP2_MIN": "16", "DMGS_SWEEP2_DEFECT": "0"}}
 
 
 @pytest.mark.parametrize("N", SIZES)
