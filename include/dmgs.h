@@ -147,6 +147,21 @@ int dmgs_jvp(dmgs_plan plan, const double *rho, const double *dq, const double *
 int dmgs_vjp(dmgs_plan plan, const double *rho, const double *rhobar, double *qbar,
              double *logD_bar, double *logmua_bar, dmgs_info *info, void *stream);
 
+/* Forward solve and VJP of one sample together: rho = S q (as
+ * dmgs_forward) and qbar = S^dagger rhobar with the coefficient gradients (as
+ * dmgs_vjp, evaluated at this rho).  The adjoint solve does not depend on
+ * rho (Sec. 2.4: S^dagger is a solve with the transposed cycle), so the two
+ * solves run concurrently: the adjoint one on a second stream of the plan,
+ * driven from a second host thread, ordered after the work already on
+ * `stream`; `stream` waits for it before the gradient pass.  The first call
+ * allocates the second set of work buffers (dmgs_workspace_bytes does not
+ * count them).  rho, qbar, logD_bar and logmua_bar must not alias each other
+ * or the inputs; logD_bar / logmua_bar may be NULL.  info_fwd and info_vjp
+ * describe the two solves (either may be NULL); the returned status is the
+ * forward solve's, else the adjoint's. */
+int dmgs_forward_vjp(dmgs_plan plan, const double *q, const double *rhobar, double *rho, double *qbar,
+                     double *logD_bar, double *logmua_bar, dmgs_info *info_fwd, dmgs_info *info_vjp, void *stream);
+
 /* One-shot convenience: create, set coefficients, forward, destroy. */
 int dmgs_solve_once(const dmgs_options *opt, const double *D, const double *mua, const double *q,
                     double *rho, dmgs_info *info, void *stream);
@@ -155,12 +170,16 @@ const char *dmgs_status_string(int status);
 const char *dmgs_last_error(void);
 
 /* ---------------------------------------------------------------------------
- * Kernel timing (profiling aid).  While enabled, every launch of a kernel
- * class on the finest level is bracketed by HIP events on the stream it is
- * launched on; elapsed times are collected at the plan's synchronisation
- * points and at the end of every call.  Each record also carries the
- * algorithmic bytes of the launch (every input read once, every output
- * written once).  Enabling resets the counters.
+ * Kernel timing (profiling aid).  dmgs_timing_enable(plan, n): n = 0 off;
+ * n >= 1: one launch in n of each kernel class on the finest level (every
+ * launch for n = 1) is bracketed by HIP events on the stream it is launched
+ * on; elapsed times are collected at the plan's synchronisation points and
+ * at the end of every call.  Each record also carries the algorithmic bytes
+ * of the launch (every input read once, every output written once).
+ * dmgs_timing_read returns the number of finest-level launches of the class
+ * and its time and bytes scaled from the timed launches to all of them.
+ * Enabling resets the counters.  Work of the second stream of
+ * dmgs_forward_vjp is not timed.
  * ------------------------------------------------------------------------- */
 enum dmgs_kernel_class {
     DMGS_K_SMOOTH = 0,           /* smoothing pass (red-black sweeps)                 */

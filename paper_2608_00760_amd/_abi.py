@@ -47,6 +47,7 @@ SIGNATURES = {
     "dmgs_forward": (_i, [_vp, _vp, _vp, C.POINTER(Info), _vp]),
     "dmgs_jvp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Info), _vp]),
     "dmgs_vjp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Info), _vp]),
+    "dmgs_forward_vjp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Info), C.POINTER(Info), _vp]),
     "dmgs_solve_once": (_i, [C.POINTER(Options), _vp, _vp, _vp, _vp, C.POINTER(Info), _vp]),
     "dmgs_status_string": (C.c_char_p, [_i]),
     "dmgs_last_error": (C.c_char_p, []),

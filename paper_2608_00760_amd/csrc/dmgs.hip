@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <utility>
 #include <new>
+#include <string>
+#include <thread>
 
 #include "kernels_basic.hpp"
 #include "kernels_stream.hpp"
@@ -141,16 +143,24 @@ int dalloc(dmgs_plan P, T** p, int64_t count) {
 
 void free_plan(dmgs_plan P) {
     if (!P) return;
+    if (P->twin) free_plan(P->twin);
+    if (P->twin_stream) (void)hipStreamDestroy(P->twin_stream);
+    if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+    if (P->ev_join) (void)hipEventDestroy(P->ev_join);
     for (int k = 0; k < P->L; k++) {
         Level& l = P->lev[k];
-        void* ps[] = {l.D64, l.mu64, l.w64, l.D32, l.mu32, l.w32, l.u64, l.q64, l.t64, l.u32, l.q32, l.t32, l.r32};
-        for (void* p : ps)
+        void* work[] = {l.u64, l.q64, l.t64, l.u32, l.q32, l.t32, l.r32};
+        for (void* p : work)
+            if (p) (void)hipFree(p);
+        if (!P->owns_coef) continue;
+        void* coef[] = {l.D64, l.mu64, l.w64, l.D32, l.mu32, l.w32};
+        for (void* p : coef)
             if (p) (void)hipFree(p);
     }
     if (P->scratch64) (void)hipFree(P->scratch64);
     if (P->xalt64) (void)hipFree(P->xalt64);
     if (P->partial) (void)hipFree(P->partial);
-    if (P->cinv) (void)hipFree(P->cinv);
+    if (P->cinv && P->owns_coef) (void)hipFree(P->cinv);
     if (P->dflag) (void)hipFree(P->dflag);
     if (P->hnorm) (void)hipHostFree(P->hnorm);
     if (P->hflag) (void)hipHostFree(P->hflag);
@@ -190,9 +200,12 @@ int timing_flush(dmgs_plan P, int upto = -1) {
     return DMGS_OK;
 }
 
-int tbeg(dmgs_plan P, int k, hipStream_t st, int* slot) {
+// Launch of class cls on level k: times it (slot >= 0) when timing is on,
+// k is the finest level and it is the class's sampled launch.
+int tbeg(dmgs_plan P, int k, hipStream_t st, int* slot, int cls) {
     *slot = -1;
     if (!P->timing || k != 0) return DMGS_OK;
+    if (P->t_seen[cls]++ % P->tstride != 0) return DMGS_OK;
     if (P->tpending == kTimerSlots) TRY(timing_flush(P));
     *slot = P->tpending++;
     HIPCHK(hipEventRecord(P->tev[2 * *slot], st));
@@ -212,7 +225,7 @@ int tend(dmgs_plan P, int slot, int cls, double bytes, hipStream_t st) {
 #define TIMED(P, k, cls, bytes, st, launch)              \
     do {                                                 \
         int slot_;                                       \
-        TRY(tbeg((P), (k), (st), &slot_));               \
+        TRY(tbeg((P), (k), (st), &slot_, (cls)));        \
         launch;                                          \
         LAUNCHCHK();                                     \
         TRY(tend((P), slot_, (cls), (bytes), (st)));     \
@@ -333,7 +346,7 @@ int smooth_pass(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int ord
     // algorithmic bytes: read u (unless zero), q, D, w, (ec), write u
     double words = (zero ? 4.0 : 5.0) + (ec ? 0.125 : 0.0);
     int slot;
-    TRY(tbeg(P, k, st, &slot));
+    TRY(tbeg(P, k, st, &slot, DMGS_K_SMOOTH));
     if (harmonic(P)) TRY((launch_sweep_cfg<T, true>(P, a, l.N, mode, st)));
     else TRY((launch_sweep_cfg<T, false>(P, a, l.N, mode, st)));
     TRY(tend(P, slot, DMGS_K_SMOOTH, words * l.nv * sizeof(T), st));
@@ -416,7 +429,7 @@ int smooth_pass2(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int or
     // algorithmic bytes: read u (unless zero), q, D, w, (ec), write u, (r) -- once for both sweeps
     double words = (zero ? 4.0 : 5.0) + (ec ? 0.125 : 0.0) + (r ? 1.0 : 0.0);
     int slot;
-    TRY(tbeg(P, k, st, &slot));
+    TRY(tbeg(P, k, st, &slot, DMGS_K_SMOOTH));
     if constexpr (sizeof(T) == 4) {
         const bool h = harmonic(P);
         if (r) TRY(h ? (launch_sweep2<T, kSweep2TY, kSweep2TZ, true, true>(P, a, l.N, mode, st))
@@ -468,7 +481,7 @@ int defect_restrict(dmgs_plan P, int k, const T* u, const T* q, T* qc, hipStream
     a.st = l.stencil<T>(harmonic(P));
     constexpr int TYC = 8, TZC = sizeof(T) == 4 ? 32 : 16;
     int slot;
-    TRY(tbeg(P, k, st, &slot));
+    TRY(tbeg(P, k, st, &slot, DMGS_K_DEFECT_RESTRICT));
     if (from_r) TRY((launch_restrict<T, TYC, TZC, false, true>(P, a, c.N, st)));
     else if (harmonic(P)) TRY((launch_restrict<T, TYC, TZC, true, false>(P, a, c.N, st)));
     else TRY((launch_restrict<T, TYC, TZC, false, false>(P, a, c.N, st)));
@@ -564,7 +577,7 @@ int block_phase(dmgs_plan P, int k, T** cur, T** other, const T* q, T* qc, const
     const int mode = post ? kBlockPost : (zero ? kBlockPreZero : kBlockPre);
     const double words = (zero ? 4.0 : 5.0) + 0.125;
     int slot;
-    TRY(tbeg(P, k, st, &slot));
+    TRY(tbeg(P, k, st, &slot, DMGS_K_SMOOTH));
     if constexpr (sizeof(T) == 4) {
         const bool h = harmonic(P);
         if (mode == kBlockPost) TRY(h ? (launch_block_t<T, kBlockPost, true>(P, a, st)) : (launch_block_t<T, kBlockPost, false>(P, a, st)));
@@ -728,7 +741,7 @@ int ir_step(dmgs_plan P, const double* x, const float* e, double* x_out, const d
                    (r32 ? 4.0 * l.nv : 0.0);
     unsigned nb = 0;
     int tslot;
-    TRY(tbeg(P, 0, st, &tslot));
+    TRY(tbeg(P, 0, st, &tslot, DMGS_K_RESIDUAL));
     const bool h = harmonic(P);
     if (e) {
         if (x_zero) h ? launch_ir<true, true, true>(a, l.N, st, &nb) : launch_ir<true, true, false>(a, l.N, st, &nb);
@@ -1105,9 +1118,9 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     // and coarse corrections have homogeneous boundaries
     for (int k = 0; k < P->L && st == DMGS_OK; k++) {
         Level& l = P->lev[k];
-        void* ps[] = {l.u64, l.q64, l.t64, l.u32, l.q32, l.t32};
-        size_t sz[] = {8, 8, 8, 4, 4, 4};
-        for (int j = 0; j < 6 && st == DMGS_OK; j++)
+        void* ps[] = {l.u64, l.q64, l.t64, l.u32, l.q32, l.t32, l.r32};
+        size_t sz[] = {8, 8, 8, 4, 4, 4, 4};
+        for (int j = 0; j < 7 && st == DMGS_OK; j++)
             if (ps[j] && hipMemset(ps[j], 0, l.nv * sz[j]) != hipSuccess) { set_error("hipMemset failed"); st = DMGS_ERR_HIP; }
     }
     P->cfg_sweep = 0;
@@ -1219,6 +1232,122 @@ int dmgs_vjp(dmgs_plan P, const double* rho, const double* rhobar, double* qbar,
     return end_call(P, s, info, st);
 }
 
+namespace {
+// The twin of a plan: the same options, levels and coefficient hierarchy
+// (aliased, not owned) with work buffers, reductions, events and a stream of
+// its own, so that a second solve can run beside one on the plan.
+int make_twin(dmgs_plan P) {
+    if (P->twin) return DMGS_OK;
+    dmgs_plan T = new (std::nothrow) dmgs_plan_s();
+    if (!T) { set_error("host allocation failed"); return DMGS_ERR_OOM; }
+    T->opt = P->opt;
+    T->L = P->L;
+    T->device = P->device;
+    T->owns_coef = false;
+    T->cfg_sweep = P->cfg_sweep;
+    T->cfg_fuse_min = P->cfg_fuse_min;
+    T->cfg_sweep2_min = P->cfg_sweep2_min;
+    T->cfg_sweep2_wgs = P->cfg_sweep2_wgs;
+    T->cfg_block_max = P->cfg_block_max;
+    T->cfg_dr_wgs = P->cfg_dr_wgs;
+    T->cfg_defect = P->cfg_defect;
+    T->small32 = P->small32;
+    T->small64 = P->small64;
+    T->cinv = P->cinv;
+    const bool ir = is_ir(P);
+    int st = DMGS_OK;
+    for (int k = 0; k < P->L && st == DMGS_OK; k++) {
+        const Level& pl = P->lev[k];
+        Level& l = T->lev[k];
+        l = pl;   // geometry and coefficient arrays
+        l.u64 = l.q64 = l.t64 = nullptr;
+        l.u32 = l.q32 = l.t32 = l.r32 = nullptr;
+        if (ir) {
+            if (st == DMGS_OK) st = dalloc(T, &l.u32, l.nv);
+            if (st == DMGS_OK) st = dalloc(T, &l.q32, l.nv);
+            if (st == DMGS_OK) st = dalloc(T, &l.t32, l.nv);
+            if (k < P->L - 1 && st == DMGS_OK) st = dalloc(T, &l.r32, l.nv);
+        } else {
+            if (k > 0 && st == DMGS_OK) st = dalloc(T, &l.u64, l.nv);
+            if (k > 0 && st == DMGS_OK) st = dalloc(T, &l.q64, l.nv);
+            if (st == DMGS_OK) st = dalloc(T, &l.t64, l.nv);
+        }
+        void* ps[] = {l.u64, l.q64, l.t64, l.u32, l.q32, l.t32, l.r32};
+        size_t sz[] = {8, 8, 8, 4, 4, 4, 4};
+        for (int j = 0; j < 7 && st == DMGS_OK; j++)
+            if (ps[j] && hipMemset(ps[j], 0, l.nv * sz[j]) != hipSuccess) { set_error("hipMemset failed"); st = DMGS_ERR_HIP; }
+    }
+    if (st == DMGS_OK) st = dalloc(T, &T->scratch64, T->lev[0].nv);
+    if (ir && st == DMGS_OK) st = dalloc(T, &T->xalt64, T->lev[0].nv);
+    if (st == DMGS_OK) st = dalloc(T, &T->partial, kMaxPartials);
+    if (st == DMGS_OK && hipHostMalloc((void**)&T->hnorm, 4 * sizeof(double), hipHostMallocCoherent) != hipSuccess) {
+        set_error("hipHostMalloc failed");
+        st = DMGS_ERR_OOM;
+    }
+    if (st == DMGS_OK && (hipEventCreate(&T->ev_start) != hipSuccess || hipEventCreate(&T->ev_stop) != hipSuccess ||
+                          hipEventCreateWithFlags(&T->ev_norm, hipEventDisableTiming) != hipSuccess ||
+                          hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                          hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess ||
+                          hipStreamCreateWithFlags(&P->twin_stream, hipStreamNonBlocking) != hipSuccess)) {
+        set_error("hipEventCreate / hipStreamCreate failed");
+        st = DMGS_ERR_HIP;
+    }
+    if (st == DMGS_OK) st = hipDeviceSynchronize() == hipSuccess ? DMGS_OK : DMGS_ERR_HIP;
+    if (st != DMGS_OK) {
+        free_plan(T);
+        return st;
+    }
+    P->twin = T;
+    P->bytes += T->bytes;
+    return DMGS_OK;
+}
+}  // namespace
+
+int dmgs_forward_vjp(dmgs_plan P, const double* q, const double* rhobar, double* rho, double* qbar, double* logD_bar,
+                     double* logmua_bar, dmgs_info* info_fwd, dmgs_info* info_vjp, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    TRY(begin_call(P, st));
+    if (!q || !rhobar || !rho || !qbar) { set_error("NULL argument"); return DMGS_ERR_INVALID; }
+    TRY(make_twin(P));
+    dmgs_plan T = P->twin;
+    T->coef_set = true;
+    // the adjoint solve starts after the work already enqueued on `stream`
+    // (the coefficients) and runs on the twin's stream from a second host
+    // thread; `stream` waits for it before the gradients
+    HIPCHK(hipEventRecord(P->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(P->twin_stream, P->ev_fork, 0));
+    int sa = DMGS_OK;
+    std::string err_a;
+    std::thread adj([&] {
+        if (hipSetDevice(P->device) != hipSuccess) { sa = DMGS_ERR_HIP; err_a = "hipSetDevice failed"; return; }
+        sa = solve(T, rhobar, qbar, 0.0, 1, info_vjp, P->twin_stream);
+        if (sa != DMGS_OK) err_a = dmgs_last_error();
+    });
+    int sf = solve(P, q, rho, P->opt.bc_value, 0, info_fwd, st);
+    adj.join();
+    if (hipEventRecord(P->ev_join, P->twin_stream) != hipSuccess || hipStreamWaitEvent(st, P->ev_join, 0) != hipSuccess) {
+        set_error("event join failed");
+        return DMGS_ERR_HIP;
+    }
+    const bool ok_f = sf == DMGS_OK || sf == DMGS_ERR_NOT_CONVERGED;
+    const bool ok_a = sa == DMGS_OK || sa == DMGS_ERR_NOT_CONVERGED;
+    if (ok_f && ok_a && (logD_bar || logmua_bar)) {
+        const Level& l0 = P->lev[0];
+        TIMED(P, 0, DMGS_K_GRAD, 48.0 * l0.nv, st,
+              hipLaunchKernelGGL(k_coef_grads, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, (const double*)rho,
+                                 (const double*)qbar, (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2,
+                                 harmonic(P), logD_bar, logmua_bar));
+    }
+    int s = sf != DMGS_OK ? sf : sa;
+    if (sf == DMGS_OK && sa != DMGS_OK) set_error("adjoint solve: %s", err_a.c_str());
+    s = end_call(P, s, info_fwd, st);
+    if (info_vjp) {
+        info_vjp->status = sa;
+        if (info_fwd) info_vjp->device_ms = info_fwd->device_ms;
+    }
+    return s;
+}
+
 int dmgs_solve_once(const dmgs_options* o, const double* D, const double* mua, const double* q, double* rho,
                     dmgs_info* info, void* stream) {
     dmgs_plan P = nullptr;
@@ -1252,8 +1381,10 @@ int dmgs_timing_enable(dmgs_plan P, int enable) {
     if (enable && !P->tev[0])
         for (int i = 0; i < 2 * kTimerSlots; i++) HIPCHK(hipEventCreate(&P->tev[i]));
     P->timing = enable != 0;
+    P->tstride = enable > 1 ? enable : 1;
     for (int c = 0; c < DMGS_K_COUNT; c++) {
         P->t_count[c] = 0;
+        P->t_seen[c] = 0;
         P->t_ms[c] = 0.0;
         P->t_bytes[c] = 0.0;
     }
@@ -1263,9 +1394,11 @@ int dmgs_timing_enable(dmgs_plan P, int enable) {
 int dmgs_timing_read(dmgs_plan P, int cls, int64_t* launches, double* total_ms, double* bytes) {
     if (!P || cls < 0 || cls >= DMGS_K_COUNT) { set_error("bad plan or kernel class"); return DMGS_ERR_INVALID; }
     if (P->tpending) TRY(timing_flush(P));
-    if (launches) *launches = P->t_count[cls];
-    if (total_ms) *total_ms = P->t_ms[cls];
-    if (bytes) *bytes = P->t_bytes[cls];
+    // sampled classes: totals scaled from the timed launches to all of them
+    const double scale = P->t_count[cls] ? (double)P->t_seen[cls] / (double)P->t_count[cls] : 0.0;
+    if (launches) *launches = P->t_seen[cls];
+    if (total_ms) *total_ms = P->t_ms[cls] * scale;
+    if (bytes) *bytes = P->t_bytes[cls] * scale;
     return DMGS_OK;
 }
 

@@ -90,9 +90,18 @@ struct dmgs_plan_s {
     hipEvent_t tev[2 * dmgs::kTimerSlots] = {};
     dmgs::TimerRec trec[dmgs::kTimerSlots];
     int tpending = 0;
-    int64_t t_count[DMGS_K_COUNT] = {};
+    int64_t t_count[DMGS_K_COUNT] = {};   // timed launches
+    int64_t t_seen[DMGS_K_COUNT] = {};    // all finest-level launches
+    int tstride = 1;                      // one launch in tstride of each class is timed
     double t_ms[DMGS_K_COUNT] = {};
     double t_bytes[DMGS_K_COUNT] = {};
     size_t bytes = 0;
     int device = 0;
+    // concurrent forward + VJP: a second plan that shares this plan's
+    // coefficient hierarchy (not owned) and has its own work buffers, and
+    // the stream its solves run on
+    bool owns_coef = true;
+    dmgs_plan_s* twin = nullptr;
+    hipStream_t twin_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };

@@ -161,10 +161,32 @@ class Plan:
                    info=info, check=check)
         return (qbar, gD, gmu), info.as_dict()
 
+    def forward_vjp(self, q, rhobar, coef_grads=True, out=None, check=True):
+        """rho = S q and the VJP at rho with cotangent rhobar, the two solves
+        running concurrently (dmgs_forward_vjp).  Returns (rho, (qbar,
+        logD_bar, logmua_bar)), info_fwd, info_vjp."""
+        if out is None:
+            rho, qbar = self._empty(), self._empty()
+            gD = self._empty() if coef_grads else None
+            gmu = self._empty() if coef_grads else None
+        else:
+            rho, qbar, gD, gmu = out
+        info_f, info_a = _abi.Info(), _abi.Info()
+        st = self._call(_abi.lib().dmgs_forward_vjp, "dmgs_forward_vjp", self._arr(q, "q"),
+                        self._arr(rhobar, "rhobar"), self._arr(rho, "rho"), self._arr(qbar, "qbar"),
+                        self._arr(gD, "logD_bar", optional=True), self._arr(gmu, "logmua_bar", optional=True),
+                        C.byref(info_f), C.byref(info_a), _stream(self.device), check=False)
+        if check and st != _abi.DMGS_OK:
+            bad = info_f if info_f.status != _abi.DMGS_OK else info_a
+            raise _abi.DMGSError(st, "dmgs_forward_vjp", bad.as_dict())
+        return (rho, (qbar, gD, gmu)), info_f.as_dict(), info_a.as_dict()
+
     # ---- kernel timing ----------------------------------------------------------------
-    def timing(self, enable=True):
-        """Enable (and reset) or disable per-class timing of finest-level launches."""
-        self._call(_abi.lib().dmgs_timing_enable, "dmgs_timing_enable", int(bool(enable)))
+    def timing(self, enable=True, stride=1):
+        """Enable (and reset) or disable per-class timing of finest-level
+        launches; stride n times one launch in n of each class (totals are
+        scaled to all launches)."""
+        self._call(_abi.lib().dmgs_timing_enable, "dmgs_timing_enable", max(1, int(stride)) if enable else 0)
 
     def timing_read(self):
         """{class: {"launches", "ms", "bytes"}} accumulated since timing was enabled."""

@@ -199,3 +199,21 @@ def test_adaptive_refinement_steps():
     assert va["rel_residual"] <= 1e-10 and vf["rel_residual"] <= 1e-10
     assert va["vcycles"] <= vf["vcycles"] + 1 and va["cycles"] < vf["cycles"], (va, vf)
     assert rel_max(host(qa), host(qf)) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp32-in-fp64", "fp64"])
+def test_forward_vjp_concurrent_equals_separate_calls(precision):
+    """dmgs_forward_vjp (adjoint solve on a second stream) gives bitwise the
+    results of dmgs_forward followed by dmgs_vjp."""
+    say("forward_vjp %s" % precision)
+    N = 64
+    c = grf_inputs(N, 13)
+    P = plan_for(c["D"], c["mua"], precision=precision)
+    rho, inf = P.forward(dev(c["q"]))
+    (qb, gD, gmu), ina = P.vjp(rho, dev(c["rhobar"]))
+    for rep in range(2):
+        (rho2, (qb2, gD2, gmu2)), if2, ia2 = P.forward_vjp(dev(c["q"]), dev(c["rhobar"]))
+        assert if2["status"] == 0 and ia2["status"] == 0
+        assert if2["vcycles"] == inf["vcycles"] and ia2["vcycles"] == ina["vcycles"]
+        for a, b in ((rho, rho2), (qb, qb2), (gD, gD2), (gmu, gmu2)):
+            assert bool((a == b).all()), rep
