@@ -195,13 +195,36 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_r
     };
     const int cl0 = (ly >> 1) * Sh::CRZ + pz;   // this pair's coarse row (even y) and column in a plane
     const int cl1 = cl0 + hp * Sh::CRZ;         // the row below for odd y
+    // Even fine planes (one coarse plane) and even rows (waves with hp = 0:
+    // one coarse row) read fewer values; doubling is exact in floating point,
+    // so every case gives the bits of the general sum.
     auto add_coarse_lds = [&](int p, SweepPlane<T>& P) {
         const int X0 = p >> 1, X1 = X0 + (p & 1);
         const T* A = cring + (X0 & 3) * Sh::CPL;
         const T* B = cring + (X1 & 3) * Sh::CPL;
-        const T s0 = (A[cl0] + A[cl1]) + (B[cl0] + B[cl1]);
+        T s0, s1;
+        if (hp == 0) {
+            const T a0 = A[cl0], a1 = A[cl0 + 1];
+            if (p & 1) {
+                const T b0 = B[cl0], b1 = B[cl0 + 1];
+                s0 = (a0 + a0) + (b0 + b0);
+                s1 = (a1 + a1) + (b1 + b1);
+            } else {
+                s0 = (a0 + a0) + (a0 + a0);
+                s1 = (a1 + a1) + (a1 + a1);
+            }
+        } else {
+            if (p & 1) {
+                s0 = (A[cl0] + A[cl1]) + (B[cl0] + B[cl1]);
+                s1 = (A[cl0 + 1] + A[cl1 + 1]) + (B[cl0 + 1] + B[cl1 + 1]);
+            } else {
+                const T a0 = A[cl0] + A[cl1], a1 = A[cl0 + 1] + A[cl1 + 1];
+                s0 = a0 + a0;
+                s1 = a1 + a1;
+            }
+        }
         P.u0 += s0 * T(0.25);
-        P.u1 += (s0 + ((A[cl0 + 1] + A[cl1 + 1]) + (B[cl0 + 1] + B[cl1 + 1]))) * T(0.125);
+        P.u1 += (s0 + s1) * T(0.125);
     };
     T cg = T(0);   // loader: coarse value in flight
 
