@@ -268,8 +268,17 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_r
     };
 
     // stage j at unrolled step K updates element O of plane s - j (slot (K - j) mod 8)
+    // a wave none of whose lanes is in stage j's ring skips the stage (its
+    // slot entries already hold the values it would write)
+    bool wact0[4], wact1[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        wact0[j] = __builtin_amdgcn_ballot_w64(m0[j]) != 0;
+        wact1[j] = __builtin_amdgcn_ballot_w64(m1[j]) != 0;
+    }
     auto stage = [&](auto Oc, auto Jc, auto Kc, SweepPlane<T>& Pb, SweepPlane<T>& P, SweepPlane<T>& Pa) {
         constexpr int O = decltype(Oc)::value, J = decltype(Jc)::value, K = decltype(Kc)::value;
+        if (!(O ? wact1[J] : wact0[J])) return;
         UD<T>* S = ring + ((K - J + 8) & 7) * 2 * RA;
         // from a zero iterate every neighbour of the first colour is 0: the
         // update is w q (the same value the full formula gives)
