@@ -365,7 +365,8 @@ int launch_sweep2(dmgs_plan P, const SweepArgs<T>& a0, int N, int mode, hipStrea
     a.tiles_y = (N + TY - 1) / TY;
     a.tiles_z = (N + TZ - 1) / TZ;
     const int tiles = a.tiles_y * a.tiles_z;
-    const int nch = std::max(1, (P->cfg_sweep2_wgs + tiles - 1) / tiles);
+    const int wgs = N == P->lev[0].N ? P->cfg_sweep2_wgs : P->cfg_sweep2_wgs_coarse;
+    const int nch = std::max(1, (wgs + tiles - 1) / tiles);
     a.chunk = std::min(N - 1, std::max(8, (N - 1 + nch - 1) / nch));
     a.nchunks = (N - 1 + a.chunk - 1) / a.chunk;
     const int nb = tiles * a.nchunks;
@@ -1157,6 +1158,11 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     P->cfg_sweep2_wgs = 256;
     if (const char* e = std::getenv("DMGS_SWEEP2_MIN")) P->cfg_sweep2_min = std::max(16, std::atoi(e));
     if (const char* e = std::getenv("DMGS_SWEEP2_WGS")) P->cfg_sweep2_wgs = std::max(16, std::atoi(e));
+    // below the finest level the passes are latency-bound: longer chunks on
+    // half as many workgroups take less CU time, which the concurrent solves
+    // of dmgs_forward_vjp use
+    P->cfg_sweep2_wgs_coarse = std::max(16, P->cfg_sweep2_wgs / 2);
+    if (const char* e = std::getenv("DMGS_SWEEP2_WGS_COARSE")) P->cfg_sweep2_wgs_coarse = std::max(16, std::atoi(e));
     if (const char* e = std::getenv("DMGS_SWEEP_CFG")) P->cfg_sweep = std::min(2, std::max(0, std::atoi(e)));
     if (const char* e = std::getenv("DMGS_FUSE_MIN")) P->cfg_fuse_min = std::max(8, std::atoi(e));
     if (st != DMGS_OK) {
@@ -1248,6 +1254,7 @@ int make_twin(dmgs_plan P) {
     T->cfg_fuse_min = P->cfg_fuse_min;
     T->cfg_sweep2_min = P->cfg_sweep2_min;
     T->cfg_sweep2_wgs = P->cfg_sweep2_wgs;
+    T->cfg_sweep2_wgs_coarse = P->cfg_sweep2_wgs_coarse;
     T->cfg_block_max = P->cfg_block_max;
     T->cfg_dr_wgs = P->cfg_dr_wgs;
     T->cfg_defect = P->cfg_defect;

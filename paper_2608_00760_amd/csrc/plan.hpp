@@ -71,6 +71,7 @@ struct dmgs_plan_s {
     // fused-pass configuration
     int cfg_sweep = 0, cfg_fuse_min = 32;
     int cfg_sweep2_min = 64, cfg_sweep2_wgs = 256;   // two-sweep passes: smallest N, target workgroups
+    int cfg_sweep2_wgs_coarse = 128;                 // ... on levels below the finest
     int cfg_block_max = 64;                         // block passes: largest N
     int cfg_dr_wgs = 512;                           // defect-restriction passes: target workgroups
     int cfg_defect = 2;   // two-sweep pre-smoothing writes the defect: 0 never, 1 from a zero iterate, 2 always
