@@ -377,12 +377,13 @@ int launch_sweep2(dmgs_plan P, const SweepArgs<T>& a0, int N, int mode, hipStrea
     return DMGS_OK;
 }
 
-constexpr int kSweep2TY = 16, kSweep2TZ = 64;
+constexpr int kSweep2TY = 16, kSweep2TZ = 64;     // tiles of the two-sweep passes
+constexpr int kSweep2DTY = 16, kSweep2DTZ = 64;   // ... of the passes that also write the defect
 
 // Dynamic-LDS limits of the two-sweep kernels (set once per plan).
 int sweep2_attributes() {
     constexpr int lds = (int)sweep2_lds_bytes<float, kSweep2TY, kSweep2TZ>();
-    constexpr int ldsd = (int)sweep2_lds_bytes<float, kSweep2TY, kSweep2TZ, 5>();
+    constexpr int ldsd = (int)sweep2_lds_bytes<float, kSweep2DTY, kSweep2DTZ, 5>();
     const std::pair<const void*, int> fns[] = {
         {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepPlain, false>, lds},
         {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepZero, false>, lds},
@@ -390,10 +391,10 @@ int sweep2_attributes() {
         {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepPlain, true>, lds},
         {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepZero, true>, lds},
         {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepProlong, true>, lds},
-        {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepPlain, false, true>, ldsd},
-        {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepZero, false, true>, ldsd},
-        {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepPlain, true, true>, ldsd},
-        {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepZero, true, true>, ldsd}};
+        {(const void*)k_rb_sweep2_col<float, kSweep2DTY, kSweep2DTZ, kSweepPlain, false, true>, ldsd},
+        {(const void*)k_rb_sweep2_col<float, kSweep2DTY, kSweep2DTZ, kSweepZero, false, true>, ldsd},
+        {(const void*)k_rb_sweep2_col<float, kSweep2DTY, kSweep2DTZ, kSweepPlain, true, true>, ldsd},
+        {(const void*)k_rb_sweep2_col<float, kSweep2DTY, kSweep2DTZ, kSweepZero, true, true>, ldsd}};
     for (const auto& f : fns)
         if (hipFuncSetAttribute(f.first, hipFuncAttributeMaxDynamicSharedMemorySize, f.second) != hipSuccess) {
             set_error("hipFuncSetAttribute failed");
@@ -433,8 +434,8 @@ int smooth_pass2(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int or
     TRY(tbeg(P, k, st, &slot, DMGS_K_SMOOTH));
     if constexpr (sizeof(T) == 4) {
         const bool h = harmonic(P);
-        if (r) TRY(h ? (launch_sweep2<T, kSweep2TY, kSweep2TZ, true, true>(P, a, l.N, mode, st))
-                     : (launch_sweep2<T, kSweep2TY, kSweep2TZ, false, true>(P, a, l.N, mode, st)));
+        if (r) TRY(h ? (launch_sweep2<T, kSweep2DTY, kSweep2DTZ, true, true>(P, a, l.N, mode, st))
+                     : (launch_sweep2<T, kSweep2DTY, kSweep2DTZ, false, true>(P, a, l.N, mode, st)));
         else TRY(h ? (launch_sweep2<T, kSweep2TY, kSweep2TZ, true, false>(P, a, l.N, mode, st))
                    : (launch_sweep2<T, kSweep2TY, kSweep2TZ, false, false>(P, a, l.N, mode, st)));
     } else {
