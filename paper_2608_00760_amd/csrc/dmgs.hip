@@ -167,6 +167,7 @@ void free_plan(dmgs_plan P) {
     if (P->ev_start) (void)hipEventDestroy(P->ev_start);
     if (P->ev_stop) (void)hipEventDestroy(P->ev_stop);
     if (P->ev_norm) (void)hipEventDestroy(P->ev_norm);
+    if (P->ev_flag) (void)hipEventDestroy(P->ev_flag);
     for (int i = 0; i < 2 * kTimerSlots; i++)
         if (P->tev[i]) (void)hipEventDestroy(P->tev[i]);
     delete P;
@@ -947,12 +948,9 @@ int build_hierarchy(dmgs_plan P, hipStream_t st, const double* logD = nullptr, c
                                  (const double*)l0.mu64, l0.N, P->dflag));
     }
     HIPCHK(hipMemcpyAsync(P->hflag, P->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (*P->hflag) {
-        P->coef_set = false;
-        set_error("coefficients must satisfy D > 0, mua >= 0 and be finite");
-        return DMGS_ERR_INVALID;
-    }
+    HIPCHK(hipEventRecord(P->ev_flag, st));
+    // the hierarchy is built while the host waits for the flag (on invalid
+    // coefficients it is garbage, and the plan is marked unset)
     for (int k = 1; k < P->L; k++) {
         const Level& f = P->lev[k - 1];
         Level& c = P->lev[k];
@@ -977,6 +975,12 @@ int build_hierarchy(dmgs_plan P, hipStream_t st, const double* logD = nullptr, c
                                (float*)nullptr);
         }
         LAUNCHCHK();
+    }
+    HIPCHK(hipEventSynchronize(P->ev_flag));
+    if (*P->hflag) {
+        P->coef_set = false;
+        set_error("coefficients must satisfy D > 0, mua >= 0 and be finite");
+        return DMGS_ERR_INVALID;
     }
     P->coef_set = true;
     return DMGS_OK;
@@ -1112,7 +1116,8 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
         st = DMGS_ERR_OOM;
     }
     if (st == DMGS_OK && (hipEventCreate(&P->ev_start) != hipSuccess || hipEventCreate(&P->ev_stop) != hipSuccess ||
-                          hipEventCreateWithFlags(&P->ev_norm, hipEventDisableTiming) != hipSuccess)) {
+                          hipEventCreateWithFlags(&P->ev_norm, hipEventDisableTiming) != hipSuccess ||
+                          hipEventCreateWithFlags(&P->ev_flag, hipEventDisableTiming) != hipSuccess)) {
         set_error("hipEventCreate failed");
         st = DMGS_ERR_HIP;
     }

@@ -427,6 +427,19 @@ __global__ void k_coef_grads(const double* __restrict__ rho, const double* __res
     if (gmu) gmu[v] = vin ? -mu[v] * lv * rv : 0.0;
     if (!gD) return;
     double acc = 0.0;
+    if (x >= 2 && x <= N - 2 && y >= 2 && y <= N - 2 && z >= 2 && z <= N - 2 && !harmonic) {
+        // all six neighbours interior, arithmetic mean: straight-line code
+        // (the same terms in the same order as the general loop below)
+        const int off[6] = {sx, -sx, n, -n, 1, -1};
+        const double dcdv = 0.5 * Dv;
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            const int j = v + off[e];
+            acc += dcdv * (lv - lam[j]) * (rv - rho[j]);
+        }
+        gD[v] = -acc * inv_h2;
+        return;
+    }
     const int o[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
     for (int e = 0; e < 6; e++) {
         const int xa = x + o[e][0], ya = y + o[e][1], za = z + o[e][2];

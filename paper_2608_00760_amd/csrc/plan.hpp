@@ -83,6 +83,7 @@ struct dmgs_plan_s {
     int* hflag = nullptr;          // pinned host mirror
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     hipEvent_t ev_norm = nullptr;  // recorded after the last norm reduction
+    hipEvent_t ev_flag = nullptr;  // recorded after the validation flag's copy to the host
     int tmark = 0;                 // timer slots recorded before ev_norm
     int ir_steps[2] = {0, 0};      // refinement steps of the last solve, by cycle order
     bool coef_set = false;
