@@ -954,7 +954,7 @@ int build_hierarchy(dmgs_plan P, hipStream_t st, const double* logD = nullptr, c
     for (int k = 1; k < P->L; k++) {
         const Level& f = P->lev[k - 1];
         Level& c = P->lev[k];
-        hipLaunchKernelGGL(k_coarsen_coef, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)f.D64,
+        hipLaunchKernelGGL(k_coarsen_coef, dim3(vertex_grid(c.nv)), dim3(kBlock), 0, st, (const double*)f.D64,
                            (const double*)f.mu64, c.D64, c.mu64, f.N);
         LAUNCHCHK();
     }
@@ -967,10 +967,10 @@ int build_hierarchy(dmgs_plan P, hipStream_t st, const double* logD = nullptr, c
     for (int k = 0; k < P->L; k++) {
         Level& l = P->lev[k];
         if (is_ir(P)) {
-            hipLaunchKernelGGL(k_level_prep<float>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, (const double*)l.D64,
+            hipLaunchKernelGGL(k_level_prep<float>, dim3(vertex_grid(l.nv)), dim3(kBlock), 0, st, (const double*)l.D64,
                                (const double*)l.mu64, l.N, l.stencil<double>(harmonic(P)), l.w32, l.D32, l.mu32);
         } else {
-            hipLaunchKernelGGL(k_level_prep<double>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, (const double*)l.D64,
+            hipLaunchKernelGGL(k_level_prep<double>, dim3(vertex_grid(l.nv)), dim3(kBlock), 0, st, (const double*)l.D64,
                                (const double*)l.mu64, l.N, l.stencil<double>(harmonic(P)), l.w64, (float*)nullptr,
                                (float*)nullptr);
         }

@@ -64,6 +64,14 @@ __global__ void k_exp_validate(const double* __restrict__ logD, const double* __
     if (b) atomicOr(bad, 1);
 }
 
+// Kernels that read neighbours in the x +- 1 planes take one vertex per
+// thread over a grid of whole blocks rounded up to a multiple of 8, blocks
+// remapped so that each XCD walks a contiguous slab (the planes it reads
+// stay in its L2).
+__device__ __forceinline__ int vertex_of_thread() {
+    return xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+}
+
 // Coefficient transfer to the next coarser level: full weighting
 // (1/64)(1,2,1)^3 on coarse interior vertices, injection on coarse boundary
 // vertices.  D and mua in one pass.
@@ -82,11 +90,11 @@ __device__ __forceinline__ double coarsen_at(const double* __restrict__ f, int N
 __global__ void k_coarsen_coef(const double* __restrict__ fD, const double* __restrict__ fmu, double* __restrict__ cD,
                                double* __restrict__ cmu, int Nf) {
     const int Nc = Nf / 2, nf = Nf + 1, nc = Nc + 1, nv = nc * nc * nc;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
-        const int Z = v % nc, Y = (v / nc) % nc, X = v / (nc * nc);
-        cD[v] = coarsen_at(fD, Nc, nf, X, Y, Z);
-        cmu[v] = coarsen_at(fmu, Nc, nf, X, Y, Z);
-    }
+    const int v = vertex_of_thread();
+    if (v >= nv) return;
+    const int Z = v % nc, Y = (v / nc) % nc, X = v / (nc * nc);
+    cD[v] = coarsen_at(fD, Nc, nf, X, Y, Z);
+    cmu[v] = coarsen_at(fmu, Nc, nf, X, Y, Z);
 }
 
 // Smoother data of one level from its float64 coefficients: the inverse
@@ -97,21 +105,21 @@ template <class T>
 __global__ void k_level_prep(const double* __restrict__ D, const double* __restrict__ mu, int N, Stencil<double> st,
                              T* __restrict__ w, float* __restrict__ D32, float* __restrict__ mu32) {
     const int n = N + 1, sx = n * n, nv = sx * n;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
-        const int z = i % n, y = (i / n) % n, x = i / sx;
-        const double Di = D[i], mi = mu[i];
-        if (D32) {
-            D32[i] = (float)Di;
-            mu32[i] = (float)mi;
-        }
-        if (!is_interior(N, x, y, z)) {
-            w[i] = T(0);
-            continue;
-        }
-        const double d = mi + face_coef(Di, D[i + sx], st) + face_coef(Di, D[i - sx], st) + face_coef(Di, D[i + n], st) +
-                         face_coef(Di, D[i - n], st) + face_coef(Di, D[i + 1], st) + face_coef(Di, D[i - 1], st);
-        w[i] = (T)(1.0 / d);
+    const int i = vertex_of_thread();
+    if (i >= nv) return;
+    const int z = i % n, y = (i / n) % n, x = i / sx;
+    const double Di = D[i], mi = mu[i];
+    if (D32) {
+        D32[i] = (float)Di;
+        mu32[i] = (float)mi;
     }
+    if (!is_interior(N, x, y, z)) {
+        w[i] = T(0);
+        return;
+    }
+    const double d = mi + face_coef(Di, D[i + sx], st) + face_coef(Di, D[i - sx], st) + face_coef(Di, D[i + n], st) +
+                     face_coef(Di, D[i - n], st) + face_coef(Di, D[i + 1], st) + face_coef(Di, D[i - 1], st);
+    w[i] = (T)(1.0 / d);
 }
 
 // ---------------------------------------------------------------------------
@@ -371,13 +379,6 @@ __global__ void k_add_correction(double* __restrict__ u, const float* __restrict
 // Derivatives with respect to the coefficients (adjoint-state derivatives of
 // the discrete solution).
 
-// The two derivative kernels below take one vertex per thread over a grid of
-// whole blocks rounded up to a multiple of 8, blocks remapped so that each
-// XCD walks a contiguous slab (the x +- 1 planes stay in its L2).
-__device__ __forceinline__ int vertex_of_thread() {
-    return xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-}
-
 // rhs = dq - (dA) rho on interior vertices (0 on the boundary), where
 // (dA rho)_i = sum_j dD_f,ij/h^2 (rho_i - rho_j) + mua_i dlogmua_i rho_i and
 // dD_f is the derivative of the face mean along dlogD.  Null tangents are 0.
@@ -427,19 +428,6 @@ __global__ void k_coef_grads(const double* __restrict__ rho, const double* __res
     if (gmu) gmu[v] = vin ? -mu[v] * lv * rv : 0.0;
     if (!gD) return;
     double acc = 0.0;
-    if (x >= 2 && x <= N - 2 && y >= 2 && y <= N - 2 && z >= 2 && z <= N - 2 && !harmonic) {
-        // all six neighbours interior, arithmetic mean: straight-line code
-        // (the same terms in the same order as the general loop below)
-        const int off[6] = {sx, -sx, n, -n, 1, -1};
-        const double dcdv = 0.5 * Dv;
-#pragma unroll
-        for (int e = 0; e < 6; e++) {
-            const int j = v + off[e];
-            acc += dcdv * (lv - lam[j]) * (rv - rho[j]);
-        }
-        gD[v] = -acc * inv_h2;
-        return;
-    }
     const int o[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
     for (int e = 0; e < 6; e++) {
         const int xa = x + o[e][0], ya = y + o[e][1], za = z + o[e][2];
