@@ -33,13 +33,13 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(c, cycles_fwd, cycles_adj):
+def cpu_baseline(c, cycles_fwd, cycles_adj, smoother="rbgs"):
     """Time the oracle on a bounded sample: hierarchy set-up, 2 forward
     cycles, 2 adjoint cycles (with gradients); scale to a full fwd+VJP pair
     with the cycle counts the solve needs."""
     from oracle import ref
     t0 = time.perf_counter()
-    H = ref.Hierarchy(c["D"], c["mua"])
+    H = ref.Hierarchy(c["D"], c["mua"], smoother=smoother)
     t1 = time.perf_counter()
     rho, _ = H.forward(c["q"], fixed_cycles=2)
     t2 = time.perf_counter()
@@ -139,6 +139,8 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--inner", type=int, default=8, help="float32 V-cycles per refinement step (the most, when adaptive)")
     ap.add_argument("--no-adaptive", action="store_true", help="run --inner V-cycles in every refinement step")
+    ap.add_argument("--smoother", default="rbgs", choices=["rbgs", "wjacobi"],
+                    help="red-black Gauss-Seidel (the method's) or weighted Jacobi (the alternative)")
     ap.add_argument("--sequential", action="store_true",
                     help="run the forward solve and the VJP one after the other (default: concurrently)")
     ap.add_argument("--serving-requests", type=int, default=512, help="requests in the serving stream (0: skip)")
@@ -173,6 +175,7 @@ def main():
     bufs = [torch.empty(shape, dtype=torch.float64, device=dev) for _ in range(4)]
 
     P = Plan(Options(N, precision=args.precision, rtol=1e-10, max_cycles=100, ir_inner_cycles=args.inner,
+                     smoother=args.smoother,
                      ir_adaptive=not args.no_adaptive))
     log("plan: %d levels, %.2f GB" % (P.levels, P.bytes / 1e9))
     run_steps(P, t, bufs, args.warmup, args.sequential)
@@ -212,7 +215,7 @@ def main():
 
     fp64 = None
     if args.precision != "fp64" and not args.no_fp64_compare:
-        P64 = Plan(Options(N, precision="fp64", rtol=1e-10, max_cycles=100))
+        P64 = Plan(Options(N, precision="fp64", rtol=1e-10, max_cycles=100, smoother=args.smoother))
         run_steps(P64, t, bufs, 1, args.sequential)
         torch.cuda.synchronize()
         s0 = time.perf_counter()
@@ -236,7 +239,7 @@ def main():
         log("timing the oracle on a bounded sample")
         # the oracle runs plain V-cycles: scale by the V-cycles the solve needs
         # (refinement steps x float32 cycles per step in the mixed solver)
-        cpu = cpu_baseline(c, info_f["vcycles"], info_a["vcycles"])
+        cpu = cpu_baseline(c, info_f["vcycles"], info_a["vcycles"], args.smoother)
         log("oracle: %.4f pairs/s (%s)" % (cpu["value"], cpu["sample"]))
 
     # V-cycle time against the one-pass-per-operator byte model: 4 sweeps of 5
@@ -276,9 +279,10 @@ def main():
         "dtype": "f32-in-f64" if args.precision == "fp32-in-fp64" else "f64",
         "data": "synthetic",
         "config": {"workload": "diffusion-absorption multigrid solve + adjoint, %d^3 cells, GRF log-normal D (contrast "
-                               "<=1e4) and mua, 16-blob source, V(2,2) RB-GS, rtol 1e-10, set-up+forward+VJP per step"
-                               % N,
-                   "N": N, "precision": args.precision, "rtol": 1e-10, "ir_inner_cycles": args.inner,
+                               "<=1e4) and mua, 16-blob source, V(2,2) %s, rtol 1e-10, set-up+forward+VJP per step"
+                               % (N, "RB-GS" if args.smoother == "rbgs" else "weighted Jacobi (6/7)"),
+                   "N": N, "precision": args.precision, "rtol": 1e-10, "smoother": args.smoother,
+                   "ir_inner_cycles": args.inner,
                    "ir_adaptive": not args.no_adaptive,
                    "fwd_vjp_solves": "sequential" if args.sequential else "concurrent (two streams)",
                    "steps_fwd": info_f["cycles"], "steps_adj": info_a["cycles"],

@@ -65,13 +65,17 @@ enum dmgs_precision {
     DMGS_FP32_IN_FP64 = 1   /* float32 V-cycles inside float64 iterative refinement:
                                fine residual, solution update and coarsest solve in float64 */
 };
-enum dmgs_smoother { DMGS_RBGS = 0 };
+/* DMGS_RBGS: red-black Gauss-Seidel (Sec. 2.2, Sec. 2.3.1).  DMGS_WJACOBI:
+ * the alternative smoother, weighted Jacobi, u <- u + w (q - A u) / diag(A)
+ * with w = 6/7; its V-cycle is transposed by exchanging nu_pre and nu_post,
+ * which the pull-back does. */
+enum dmgs_smoother { DMGS_RBGS = 0, DMGS_WJACOBI = 1 };
 enum dmgs_face_mean { DMGS_FACE_ARITH = 0, DMGS_FACE_HARMONIC = 1 };
 
 typedef struct dmgs_options {
     int32_t n[3];          /* cells per axis; all three equal, N = c*2^m, c in {2,3}, 2 <= N <= 1024 */
     int32_t precision;     /* dmgs_precision */
-    int32_t smoother;      /* dmgs_smoother (red-black Gauss-Seidel, Sec. 2.3.1) */
+    int32_t smoother;      /* dmgs_smoother: red-black Gauss-Seidel (Sec. 2.3.1) or weighted Jacobi */
     int32_t nu_pre;        /* pre-smoothing sweeps (red-black pairs), 0..8; default 2 */
     int32_t nu_post;       /* post-smoothing sweeps, 0..8; default 2 */
     int32_t max_cycles;    /* tolerance mode: give up after this many cycles */

@@ -39,7 +39,9 @@
  *   - coarse coefficients: full weighting on coarse interior vertices,
  *     injection on coarse boundary vertices; coarse operators are
  *     rediscretised with h_k = 2^k h (Sec. 2.2);
- *   - coarse-level corrections start from zero (Sec. 2.3.1).
+ *   - coarse-level corrections start from zero (Sec. 2.3.1);
+ *   - the alternative smoother, weighted Jacobi, takes the weight
+ *     omega = 6/7 unless set: u <- u + omega (q - A u) / diag(A).
  *
  * Every function below is pinned by a test in tests/ (closed form, brute
  * force, transpose identities, invariants); none is "parity unpinned".
@@ -66,6 +68,8 @@ typedef struct ref_hier {
     double *mua[REF_MAXLEV];
     int face_mean;         /* 0 arithmetic, 1 harmonic */
     double g;              /* Dirichlet value on the fine level */
+    int smoother;          /* 0 red-black Gauss-Seidel, 1 weighted Jacobi */
+    double omega;          /* weighted-Jacobi weight */
 } ref_hier;
 
 typedef struct ref_opts {
@@ -152,6 +156,7 @@ ref_hier *ref_hier_create(int N, double h, double g, int face_mean,
     ref_hier *H = calloc(1, sizeof(ref_hier));
     if (!H) { *status = REF_ERR_OOM; return NULL; }
     H->L = L; H->face_mean = face_mean; H->g = g;
+    H->smoother = 0; H->omega = 6.0 / 7.0;
     int Nk = N; double hk = h;
     for (int k = 0; k < L; k++) {
         H->N[k] = Nk; H->h[k] = hk;
@@ -225,6 +230,35 @@ void ref_gs_half(const ref_hier *H, int k, int colour, double *u, const double *
                 }
                 u[i] = num / den;
             }
+}
+
+/* Select the smoother of every V-cycle: 0 red-black Gauss-Seidel, 1 weighted
+ * Jacobi with weight omega. */
+void ref_set_smoother(ref_hier *H, int smoother, double omega) {
+    H->smoother = smoother ? 1 : 0;
+    H->omega = omega;
+}
+
+/* One weighted-Jacobi sweep, every interior vertex from the old iterate:
+ * rho_i <- rho_i + omega (q_i - (A rho)_i) / (sum_j c_ij + lambda_i). */
+void ref_wj_sweep(const ref_hier *H, int k, double *u, const double *q) {
+    int N = H->N[k], n = N + 1, fm = H->face_mean;
+    double inv_h2 = 1.0 / (H->h[k] * H->h[k]);
+    const double *D = H->D[k], *mu = H->mua[k];
+    const long s[6] = { (long)n * n, -(long)n * n, n, -n, 1, -1 };
+    size_t nv = nvert(N);
+    double *Au = malloc(nv * sizeof(double));
+    ref_apply(H, k, u, Au);
+    #pragma omp parallel for
+    for (int x = 1; x < N; x++)
+        for (int y = 1; y < N; y++)
+            for (int z = 1; z < N; z++) {
+                size_t i = idx(n, x, y, z);
+                double d = mu[i];
+                for (int e = 0; e < 6; e++) d += face_coef(D, i, (size_t)((long)i + s[e]), inv_h2, fm);
+                u[i] += H->omega * (q[i] - Au[i]) / d;
+            }
+    free(Au);
 }
 
 /* Defect e = q - A rho on interior vertices, 0 on the boundary (Eq. (defect)). */
@@ -393,6 +427,7 @@ static void vcycle(const ref_hier *H, ref_work *W, int k, const ref_opts *o) {
     if (k == H->L - 1) { ref_exact_solve(H, k, W->q[k], W->u[k]); return; }
     int first = o->order ? 1 : 0, second = 1 - first;
     for (int s = 0; s < o->nu1; s++) {
+        if (H->smoother) { ref_wj_sweep(H, k, W->u[k], W->q[k]); continue; }
         ref_gs_half(H, k, first, W->u[k], W->q[k]);
         ref_gs_half(H, k, second, W->u[k], W->q[k]);
     }
@@ -402,6 +437,7 @@ static void vcycle(const ref_hier *H, ref_work *W, int k, const ref_opts *o) {
     vcycle(H, W, k + 1, o);
     ref_prolong_add(H->N[k], W->u[k + 1], W->u[k]);               /* Sec. 2.3.3 */
     for (int s = 0; s < o->nu2; s++) {
+        if (H->smoother) { ref_wj_sweep(H, k, W->u[k], W->q[k]); continue; }
         ref_gs_half(H, k, first, W->u[k], W->q[k]);
         ref_gs_half(H, k, second, W->u[k], W->q[k]);
     }
@@ -520,6 +556,30 @@ void ref_defect_adj(const ref_hier *H, int k, const double *rbar, double *ubar, 
     free(Ar); free(rb);
 }
 
+/* Adjoint of one weighted-Jacobi sweep rho' = rho + omega D^-1 (q - A rho)
+ * (D the diagonal, interior rows): with t = omega D^-1 ubar' on interior
+ * vertices, qbar += t and ubar = ubar' - A t -- the adjoint of a defect
+ * applied to t. */
+void ref_wj_sweep_adj(const ref_hier *H, int k, double *ubar, double *qbar) {
+    int N = H->N[k], n = N + 1, fm = H->face_mean;
+    double inv_h2 = 1.0 / (H->h[k] * H->h[k]);
+    const double *D = H->D[k], *mu = H->mua[k];
+    const long s[6] = { (long)n * n, -(long)n * n, n, -n, 1, -1 };
+    size_t nv = nvert(N);
+    double *t = calloc(nv, sizeof(double));
+    #pragma omp parallel for
+    for (int x = 1; x < N; x++)
+        for (int y = 1; y < N; y++)
+            for (int z = 1; z < N; z++) {
+                size_t i = idx(n, x, y, z);
+                double d = mu[i];
+                for (int e = 0; e < 6; e++) d += face_coef(D, i, (size_t)((long)i + s[e]), inv_h2, fm);
+                t[i] = H->omega * ubar[i] / d;
+            }
+    ref_defect_adj(H, k, t, ubar, qbar);
+    free(t);
+}
+
 /* Adjoint of the V-cycle on level k.  On entry ubar is the cotangent of the
  * cycle's output; on exit it is the cotangent of the cycle's input iterate,
  * and the cotangent of the right-hand side has been added to qbar. */
@@ -537,6 +597,7 @@ static void vcycle_adj(const ref_hier *H, ref_work *U, ref_work *Q, int k, const
     }
     int first = o->order ? 1 : 0, second = 1 - first;
     for (int s = 0; s < o->nu2; s++) {           /* post-smoothing, reversed */
+        if (H->smoother) { ref_wj_sweep_adj(H, k, ub, qb); continue; }
         ref_gs_half_adj(H, k, second, ub, qb);
         ref_gs_half_adj(H, k, first, ub, qb);
     }
@@ -553,6 +614,7 @@ static void vcycle_adj(const ref_hier *H, ref_work *U, ref_work *Q, int k, const
     for (size_t v = 0; v < nv; v++) rb[v] *= 0.125;
     ref_defect_adj(H, k, rb, ub, qb);            /* Sec. 2.3.2 */
     for (int s = 0; s < o->nu1; s++) {           /* pre-smoothing, reversed */
+        if (H->smoother) { ref_wj_sweep_adj(H, k, ub, qb); continue; }
         ref_gs_half_adj(H, k, second, ub, qb);
         ref_gs_half_adj(H, k, first, ub, qb);
     }
@@ -724,7 +786,9 @@ int ref_vjp(const ref_hier *H, const double *rho, const double *rhobar, double *
 
 /* Pull-back in q computed instead by black-before-red V-cycles on
  * A qbar = rhobar from qbar = 0 (used to check that this equals the literal
- * reversed composition). */
+ * reversed composition).  With weighted Jacobi the colour order has no
+ * meaning; the transposed cycle is the one with the pre- and
+ * post-smoothing counts exchanged. */
 int ref_pullback_br(const ref_hier *H, const double *rhobar, double *qbar, int nu1, int nu2,
                     double rtol, int max_cycles, int fixed_cycles, int *cycles, double *relres) {
     int N = H->N[0], n = N + 1;
@@ -737,6 +801,7 @@ int ref_pullback_br(const ref_hier *H, const double *rhobar, double *qbar, int n
                 w[i] = interior(N, x, y, z) ? rhobar[i] : 0.0;
             }
     ref_opts o = { 1, nu1, nu2, rtol, max_cycles, fixed_cycles };
+    if (H->smoother) { o.nu1 = nu2; o.nu2 = nu1; }
     int st = ref_solve(H, 0.0, w, qbar, &o, cycles, relres, NULL, 0);
     free(w);
     return st;

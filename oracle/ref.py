@@ -51,6 +51,9 @@ def lib():
             "ref_jvp": (i, [vp, _DP, _DP, _DP, _DP, _DP, i, i, d, i, i, ip, _DP]),
             "ref_vjp": (i, [vp, _DP, _DP, _DP, _DP, _DP, i, i, d, i, i, ip, _DP]),
             "ref_pullback_br": (i, [vp, _DP, _DP, i, i, d, i, i, ip, _DP]),
+            "ref_set_smoother": (None, [vp, i, d]),
+            "ref_wj_sweep": (None, [vp, i, _DP, _DP]),
+            "ref_wj_sweep_adj": (None, [vp, i, _DP, _DP]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -80,7 +83,7 @@ class OracleError(RuntimeError):
 class Hierarchy:
     """Coefficient hierarchy of rediscretised operators on all levels."""
 
-    def __init__(self, D, mua, h=1.0, bc=0.0, face_mean="arith"):
+    def __init__(self, D, mua, h=1.0, bc=0.0, face_mean="arith", smoother="rbgs", omega=6.0 / 7.0):
         D = np.ascontiguousarray(D, dtype=np.float64)
         mua = np.ascontiguousarray(mua, dtype=np.float64)
         assert D.ndim == 3 and D.shape[0] == D.shape[1] == D.shape[2] and D.shape == mua.shape
@@ -94,6 +97,9 @@ class Hierarchy:
             raise OracleError(st.value, "ref_hier_create")
         self.L = lib().ref_levels(self._h)
         self.Ns = [lib().ref_level_N(self._h, k) for k in range(self.L)]
+        assert smoother in ("rbgs", "wjacobi")
+        self.smoother, self.omega = smoother, float(omega)
+        lib().ref_set_smoother(self._h, 1 if smoother == "wjacobi" else 0, self.omega)
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -119,6 +125,17 @@ class Hierarchy:
         u = np.array(u, dtype=np.float64, copy=True)
         lib().ref_gs_half(self._h, k, int(colour), _p(u), _p(np.ascontiguousarray(q, np.float64)))
         return u
+
+    def wj_sweep(self, k, u, q):
+        u = np.array(u, dtype=np.float64, copy=True)
+        lib().ref_wj_sweep(self._h, k, _p(u), _p(np.ascontiguousarray(q, np.float64)))
+        return u
+
+    def wj_sweep_adj(self, k, ubar, qbar):
+        ubar = np.array(ubar, dtype=np.float64, copy=True)
+        qbar = np.array(qbar, dtype=np.float64, copy=True)
+        lib().ref_wj_sweep_adj(self._h, k, _p(ubar), _p(qbar))
+        return ubar, qbar
 
     def defect(self, k, u, q):
         r = self.zeros(k)

@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(HERE, "csrc", "libdmgs.so")
 DMGS_OK, DMGS_ERR_INVALID, DMGS_ERR_OOM, DMGS_ERR_NOT_CONVERGED = 0, 1, 2, 3
 DMGS_ERR_NONFINITE, DMGS_ERR_HIP, DMGS_ERR_BUDGET = 4, 5, 6
 DMGS_FP64, DMGS_FP32_IN_FP64 = 0, 1
-DMGS_RBGS = 0
+DMGS_RBGS, DMGS_WJACOBI = 0, 1
 DMGS_FACE_ARITH, DMGS_FACE_HARMONIC = 0, 1
 
 

@@ -84,7 +84,7 @@ int check_options(const dmgs_options* o) {
         return DMGS_ERR_INVALID;
     }
     if (o->precision != DMGS_FP64 && o->precision != DMGS_FP32_IN_FP64) { set_error("bad precision %d", o->precision); return DMGS_ERR_INVALID; }
-    if (o->smoother != DMGS_RBGS) { set_error("bad smoother %d", o->smoother); return DMGS_ERR_INVALID; }
+    if (o->smoother != DMGS_RBGS && o->smoother != DMGS_WJACOBI) { set_error("bad smoother %d", o->smoother); return DMGS_ERR_INVALID; }
     if (o->nu_pre < 0 || o->nu_pre > 8 || o->nu_post < 0 || o->nu_post > 8 || o->nu_pre + o->nu_post == 0) {
         set_error("bad smoothing counts %d,%d", o->nu_pre, o->nu_post);
         return DMGS_ERR_INVALID;
@@ -677,6 +677,48 @@ int launch_small_t(dmgs_plan P, int k, const T* q, T* u, int order, hipStream_t 
 template <class T>
 int small_level(dmgs_plan P) { return sizeof(T) == 4 ? P->small32 : P->small64; }
 
+// --- weighted-Jacobi cycles -----------------------------------------------------
+
+bool wjacobi(dmgs_plan P) { return P->opt.smoother == DMGS_WJACOBI; }
+constexpr double kWjOmega = 6.0 / 7.0;
+
+// count weighted-Jacobi sweeps on level k, ping-ponging *cur and *other;
+// zero: the first starts from a zero iterate
+template <class T>
+int wj_sweeps(dmgs_plan P, int k, T** cur, T** other, const T* q, int count, bool zero, hipStream_t st) {
+    const Level& l = P->lev[k];
+    for (int i = 0; i < count; i++) {
+        const bool z = zero && i == 0;
+        // reads u, q, D, mu, w and writes u (from zero: reads q, w)
+        TIMED(P, k, DMGS_K_SMOOTH, (z ? 3.0 : 6.0) * l.nv * sizeof(T), st,
+              hipLaunchKernelGGL(k_wj_sweep<T>, dim3(vertex_grid(l.nv)), dim3(kBlock), 0, st, (const T*)*cur, *other,
+                                 q, (const T*)Typed<T>::D(l), (const T*)Typed<T>::mu(l), (const T*)Typed<T>::w(l), l.N,
+                                 l.stencil<T>(harmonic(P)), (T)kWjOmega, z ? 1 : 0));
+        std::swap(*cur, *other);
+    }
+    return DMGS_OK;
+}
+
+// One V(nu_pre, nu_post)-cycle with weighted-Jacobi smoothing; order 1 (the
+// transposed cycle) exchanges the pre- and post-smoothing counts.
+template <class T>
+int vcycle_wj(dmgs_plan P, int k, T** cur, T** other, const T* q, int order, bool zero, hipStream_t st) {
+    const Level& l = P->lev[k];
+    const int nu1 = order ? P->opt.nu_post : P->opt.nu_pre, nu2 = order ? P->opt.nu_pre : P->opt.nu_post;
+    if (zero && (k == P->L - 1 || nu1 == 0)) TRY(fill<T>(*cur, l.nv, T(0), st));
+    if (k == P->L - 1) return coarsest<T>(P, q, *cur, st);
+    TRY(wj_sweeps<T>(P, k, cur, other, q, nu1, zero && nu1 > 0, st));
+    const Level& c = P->lev[k + 1];
+    T* qc = Typed<T>::q(c);
+    TRY(defect_restrict<T>(P, k, *cur, q, qc, st));
+    T* ccur = Typed<T>::u(c);
+    T* coth = Typed<T>::t(c);
+    TRY(vcycle_wj<T>(P, k + 1, &ccur, &coth, qc, order, true, st));
+    TIMED(P, k, DMGS_K_PROLONG, (double)(2 * l.nv + c.nv) * sizeof(T), st,
+          hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, (const T*)ccur, *cur, l.N));
+    return wj_sweeps<T>(P, k, cur, other, q, nu2, false, st);
+}
+
 // One V-cycle on level k with right-hand side q, iterate in *cur (the
 // level's other buffer is *other).  zero: the iterate starts from 0 (coarse
 // corrections, refinement corrections).  On return *cur holds the result.
@@ -686,6 +728,7 @@ int small_level(dmgs_plan P) { return sizeof(T) == 4 ? P->small32 : P->small64; 
 template <class T>
 int vcycle(dmgs_plan P, int k, T** cur, T** other, const T* q, int order, bool zero, hipStream_t st,
            bool smoothed = false, bool rdone = false) {
+    if (wjacobi(P)) return vcycle_wj<T>(P, k, cur, other, q, order, zero, st);
     if (k > 0 && k == small_level<T>(P) && zero) {
         if (harmonic(P)) return launch_small_t<T, true>(P, k, q, *cur, order, st);
         return launch_small_t<T, false>(P, k, q, *cur, order, st);
@@ -834,7 +877,7 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
         // discards it.  With ir_adaptive, a step after the first runs the
         // number of V-cycles the per-cycle contraction factor observed so
         // far predicts the tolerance needs (at most ir_inner_cycles).
-        const bool can_speculate = !fixed && P->L > 1 && fused_level(P, 0) && !block_level<float>(P, 0);
+        const bool can_speculate = !fixed && !wjacobi(P) && P->L > 1 && fused_level(P, 0) && !block_level<float>(P, 0);
         const bool adaptive = !fixed && o.ir_adaptive;
         double rel1 = 1.0;     // relative residual before the last step
         double rate = 0.0;     // per-V-cycle contraction factor (0: not known yet)

@@ -122,6 +122,30 @@ __global__ void k_level_prep(const double* __restrict__ D, const double* __restr
     w[i] = (T)(1.0 / d);
 }
 
+// Weighted-Jacobi sweep, out of place: on interior vertices
+//   u_out = u_in + omega w (q - A u_in),   w = 1 / (sum_j c_ij + mua_i),
+// and from a zero iterate (zero != 0) u_out = omega w q.  Boundary entries of
+// u_out are not written (the ping-pong partner holds the same values).
+template <class T>
+__global__ void k_wj_sweep(const T* __restrict__ u, T* __restrict__ u_out, const T* __restrict__ q,
+                           const T* __restrict__ D, const T* __restrict__ mu, const T* __restrict__ w, int N,
+                           Stencil<T> s, T omega, int zero) {
+    const int n = N + 1, sx = n * n, nv = sx * n;
+    const int i = vertex_of_thread();
+    if (i >= nv) return;
+    const int z = i % n, y = (i / n) % n, x = i / sx;
+    if (!is_interior(N, x, y, z)) return;
+    if (zero) {
+        u_out[i] = omega * w[i] * q[i];
+        return;
+    }
+    const T Di = D[i], ui = u[i];
+    const T Au = mu[i] * ui + face_coef(Di, D[i + sx], s) * (ui - u[i + sx]) + face_coef(Di, D[i - sx], s) * (ui - u[i - sx]) +
+                 face_coef(Di, D[i + n], s) * (ui - u[i + n]) + face_coef(Di, D[i - n], s) * (ui - u[i - n]) +
+                 face_coef(Di, D[i + 1], s) * (ui - u[i + 1]) + face_coef(Di, D[i - 1], s) * (ui - u[i - 1]);
+    u_out[i] = ui + omega * w[i] * (q[i] - Au);
+}
+
 // ---------------------------------------------------------------------------
 // Red-black Gauss-Seidel half-sweep on colour c (0 = red = (x+y+z) even), in
 // place: u_i <- (q_i + sum_j c_ij u_j) / (sum_j c_ij + mua_i).  Each thread

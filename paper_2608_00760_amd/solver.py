@@ -14,6 +14,7 @@ from . import _abi
 
 _PREC = {"fp64": _abi.DMGS_FP64, "fp32-in-fp64": _abi.DMGS_FP32_IN_FP64, "mixed": _abi.DMGS_FP32_IN_FP64}
 _FACE = {"arith": _abi.DMGS_FACE_ARITH, "harmonic": _abi.DMGS_FACE_HARMONIC}
+_SMOOTHER = {"rbgs": _abi.DMGS_RBGS, "wjacobi": _abi.DMGS_WJACOBI}
 
 
 @dataclass
@@ -30,6 +31,7 @@ class Options:
     bc_value: float = 0.0
     ir_inner_cycles: int = 8          # float32 V-cycles per refinement step (the most, when adaptive)
     ir_adaptive: bool = True          # later steps run the V-cycles the observed contraction predicts
+    smoother: str = "rbgs"            # "rbgs" (red-black Gauss-Seidel) | "wjacobi" (weighted Jacobi, 6/7)
 
     def to_c(self):
         o = _abi.default_options(self.N)
@@ -42,6 +44,7 @@ class Options:
         o.h, o.bc_value = float(self.h), float(self.bc_value)
         o.ir_inner_cycles = int(self.ir_inner_cycles)
         o.ir_adaptive = 1 if self.ir_adaptive else 0
+        o.smoother = _SMOOTHER[self.smoother]
         return o
 
 
