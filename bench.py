@@ -18,6 +18,7 @@ stretch its duration.  The CPU baseline is the FP64 oracle timed on a
 bounded sample of the same workload on the host cores.
 """
 import argparse
+import math
 import json
 import os
 import sys
@@ -128,6 +129,60 @@ def run_steps(P, t, bufs, steps, sequential=False):
     return info_f, info_a
 
 
+def paper_sweep(args):
+    """The paper's timing benchmark shape (Sec. 3.3) on this solver: fixed 15
+    V-cycles per solve, Solve / JVP / VJP timed separately over grid sizes,
+    with peak device memory.  Coefficients are seeded log-normal fields drawn
+    on the device (the timing of a fixed cycle count does not depend on their
+    values).  One JSON line per size and precision."""
+    import torch
+    from paper_2608_00760_amd.solver import Options, Plan
+    dev = torch.device("cuda:0")
+    sizes = [int(x) for x in args.sweep_sizes.split(",")]
+    for N in sizes:
+        for prec in ("fp64", "fp32-in-fp64"):
+            torch.cuda.empty_cache()
+            torch.cuda.reset_peak_memory_stats()
+            g = torch.Generator(device=dev)
+            g.manual_seed(7000 + N)
+            shape = (N + 1,) * 3
+            rnd = lambda: torch.randn(shape, generator=g, device=dev, dtype=torch.float64)
+            logD, logmu = 0.5 * rnd(), -3.0 + 0.5 * rnd()
+            q, w, dq, dd, dm = rnd(), rnd(), rnd(), rnd(), rnd()
+            for t in (q, w, dq, dm):   # boundary entries are ignored; keep them 0
+                t[0] = 0; t[-1] = 0; t[:, 0] = 0; t[:, -1] = 0; t[:, :, 0] = 0; t[:, :, -1] = 0
+            # 15 V-cycles: float64 cycles, or 15 refinement steps of one float32 cycle
+            P = Plan(Options(N, precision=prec, fixed_cycles=15, ir_inner_cycles=1, ir_adaptive=False))
+            P.set_log_coefficients(logD, logmu)
+            rho, qbar, drho = torch.empty_like(q), torch.empty_like(q), torch.empty_like(q)
+            gD, gmu = torch.empty_like(q), torch.empty_like(q)
+            ops = {"solve": lambda: P.forward(q, out=rho),
+                   "jvp": lambda: P.jvp(rho, dq, dd, dm, out=drho),
+                   "vjp": lambda: P.vjp(rho, w, out=(qbar, gD, gmu))}
+            res = {}
+            for name, f in ops.items():
+                f()
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(args.sweep_reps):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    f()
+                    e1.record()
+                    e1.synchronize()
+                    ts.append(e0.elapsed_time(e1))
+                ts.sort()
+                res[name + "_ms_median"] = ts[len(ts) // 2]
+                res[name + "_ms_min"] = ts[0]
+            torch.cuda.synchronize()
+            peak = torch.cuda.max_memory_allocated() + P.bytes
+            print(json.dumps({"sweep": "fixed 15 V-cycles", "N": N, "points": (N + 1) ** 3,
+                              "log2_points": round(math.log2((N + 1) ** 3), 2), "precision": prec,
+                              "reps": args.sweep_reps, **res, "peak_device_GB": peak / 1e9}), flush=True)
+            P.close()
+            del logD, logmu, q, w, dq, dd, dm, rho, qbar, drho, gD, gmu
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +196,10 @@ def main():
     ap.add_argument("--no-adaptive", action="store_true", help="run --inner V-cycles in every refinement step")
     ap.add_argument("--smoother", default="rbgs", choices=["rbgs", "wjacobi"],
                     help="red-black Gauss-Seidel (the method's) or weighted Jacobi (the alternative)")
+    ap.add_argument("--paper-sweep", action="store_true",
+                    help="only the fixed-15-cycle Solve/JVP/VJP timing sweep over --sweep-sizes (one JSON line each)")
+    ap.add_argument("--sweep-sizes", default="96,128,192,256,384,512,768")
+    ap.add_argument("--sweep-reps", type=int, default=20)
     ap.add_argument("--sequential", action="store_true",
                     help="run the forward solve and the VJP one after the other (default: concurrently)")
     ap.add_argument("--serving-requests", type=int, default=512, help="requests in the serving stream (0: skip)")
@@ -156,6 +215,10 @@ def main():
     import torch
     from paper_2608_00760_amd import synth
     from paper_2608_00760_amd.solver import Options, Plan, stream_copy
+
+    if args.paper_sweep:
+        paper_sweep(args)
+        return
 
     if args.copy_calibration:
         nbytes = 256 << 20
