@@ -111,6 +111,11 @@ void dmgs_default_options(int32_t n, dmgs_options *opt);
  * for invalid options.  Used for admission by memory footprint. */
 size_t dmgs_workspace_bytes(const dmgs_options *opt);
 
+/* Device bytes of a plan that has run dmgs_forward_vjp: dmgs_workspace_bytes
+ * plus the second set of work buffers that call allocates; 0 for invalid
+ * options. */
+size_t dmgs_forward_vjp_workspace_bytes(const dmgs_options *opt);
+
 /* Create a plan: validate options and allocate the level hierarchy on the
  * current device.  Errors: DMGS_ERR_INVALID, DMGS_ERR_OOM, DMGS_ERR_HIP. */
 int dmgs_plan_create(const dmgs_options *opt, dmgs_plan *out);
@@ -159,7 +164,7 @@ int dmgs_vjp(dmgs_plan plan, const double *rho, const double *rhobar, double *qb
  * driven from a second host thread, ordered after the work already on
  * `stream`; `stream` waits for it before the gradient pass.  The first call
  * allocates the second set of work buffers (dmgs_workspace_bytes does not
- * count them).  rho, qbar, logD_bar and logmua_bar must not alias each other
+ * count them; dmgs_forward_vjp_workspace_bytes does).  rho, qbar, logD_bar and logmua_bar must not alias each other
  * or the inputs; logD_bar / logmua_bar may be NULL.  info_fwd and info_vjp
  * describe the two solves (either may be NULL); the returned status is the
  * forward solve's, else the adjoint's. */

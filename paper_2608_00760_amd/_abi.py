@@ -38,6 +38,7 @@ _vp, _i, _d = C.c_void_p, C.c_int, C.c_double
 SIGNATURES = {
     "dmgs_default_options": (None, [C.c_int32, C.POINTER(Options)]),
     "dmgs_workspace_bytes": (C.c_size_t, [C.POINTER(Options)]),
+    "dmgs_forward_vjp_workspace_bytes": (C.c_size_t, [C.POINTER(Options)]),
     "dmgs_plan_create": (_i, [C.POINTER(Options), C.POINTER(_vp)]),
     "dmgs_plan_destroy": (_i, [_vp]),
     "dmgs_plan_levels": (_i, [_vp]),

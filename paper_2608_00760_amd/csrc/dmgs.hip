@@ -1106,6 +1106,24 @@ size_t dmgs_workspace_bytes(const dmgs_options* o) {
     return footprint(o);
 }
 
+size_t dmgs_forward_vjp_workspace_bytes(const dmgs_options* o) {
+    if (check_options(o) != DMGS_OK) return 0;
+    // the twin's work buffers (make_twin): per level the iterate, right-hand
+    // side and partner (+ the defect buffer below the coarsest) in IR plans,
+    // or partner (+ iterate and right-hand side below the finest) in float64
+    // plans; the float64 scratch (+ alternate iterate) and the partials
+    Sizes s = sizes_for(o);
+    const bool ir = o->precision == DMGS_FP32_IN_FP64;
+    size_t b = 0;
+    for (int k = 0; k < s.L; k++) {
+        if (ir) b += (k < s.L - 1 ? 4 : 3) * s.nv[k] * sizeof(float);
+        else b += (k > 0 ? 3 : 1) * s.nv[k] * sizeof(double);
+    }
+    b += (ir ? 2 : 1) * s.nv[0] * sizeof(double);
+    b += kMaxPartials * sizeof(double) + 4 * sizeof(double);
+    return footprint(o) + b;
+}
+
 int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     if (!out) { set_error("out is NULL"); return DMGS_ERR_INVALID; }
     *out = nullptr;

@@ -146,7 +146,9 @@ class Server:
         self.pool = collections.defaultdict(list)   # N -> idle plans
         self.pool_order = collections.deque()       # (N, plan) oldest first
         self.plan_bytes = {}
-        self._ws = lambda N: workspace_bytes(Options(N, **self.opts))
+        # every pooled plan may serve forward + VJP requests, whose two
+        # solves run concurrently on a second work set of the plan
+        self._ws = lambda N: workspace_bytes(Options(N, **self.opts), forward_vjp=True)
         self.lock = threading.Lock()
         self.cv = threading.Condition(self.lock)
 
@@ -183,13 +185,14 @@ class Server:
         with torch.cuda.device(self.device), torch.cuda.stream(stream):
             f = request_fields(req, self.device)
             plan.set_log_coefficients(f["logD"], f["logmua"])
-            rho, fi = plan.forward(f["q"])
             if req.mode == "jvp":
+                rho, fi = plan.forward(f["q"])
                 drho, ji = plan.jvp(rho, f["dq"], f["dlogD"], f["dlogmua"])
                 out = {"rho": rho, "drho": drho}
                 cyc = (fi["cycles"], ji["cycles"])
             else:
-                (qbar, gD, gmu), vi = plan.vjp(rho, f["rhobar"])
+                # the adjoint solve does not need rho: both solves at once
+                (rho, (qbar, gD, gmu)), fi, vi = plan.forward_vjp(f["q"], f["rhobar"])
                 out = {"rho": rho, "qbar": qbar, "logD_bar": gD, "logmua_bar": gmu}
                 cyc = (fi["cycles"], vi["cycles"])
             stream.synchronize()

@@ -48,9 +48,12 @@ class Options:
         return o
 
 
-def workspace_bytes(opts: Options) -> int:
+def workspace_bytes(opts: Options, forward_vjp=False) -> int:
+    """Device bytes of a plan; forward_vjp: including the second work set
+    that Plan.forward_vjp allocates on first use."""
     o = opts.to_c()
-    return int(_abi.lib().dmgs_workspace_bytes(C.byref(o)))
+    f = _abi.lib().dmgs_forward_vjp_workspace_bytes if forward_vjp else _abi.lib().dmgs_workspace_bytes
+    return int(f(C.byref(o)))
 
 
 def stream_copy(src, dst):

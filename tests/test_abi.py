@@ -54,6 +54,13 @@ def test_default_options_and_footprint(abi):
     assert lib.dmgs_workspace_bytes(C.byref(ob)) == 0
     for good in (2, 3, 6, 96, 192, 512):
         assert lib.dmgs_workspace_bytes(C.byref(abi.default_options(good))) > 0
+    # a plan that has run dmgs_forward_vjp also holds a second work set
+    for prec in (abi.DMGS_FP64, abi.DMGS_FP32_IN_FP64):
+        o = abi.default_options(256)
+        o.precision = prec
+        base, both = lib.dmgs_workspace_bytes(C.byref(o)), lib.dmgs_forward_vjp_workspace_bytes(C.byref(o))
+        assert base + nv * 8 <= both < 2 * base
+    assert lib.dmgs_forward_vjp_workspace_bytes(C.byref(abi.default_options(20))) == 0
 
 
 def test_status_strings(abi):

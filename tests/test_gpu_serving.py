@@ -22,7 +22,8 @@ def test_alone_equals_in_the_mix_and_budget_holds():
     from paper_2608_00760_amd.solver import Options, workspace_bytes
     say("serving: mixed stream")
     reqs = stream()
-    need = max(workspace_bytes(Options(r.N, precision="fp32-in-fp64")) + field_bytes(r.N, r.mode) for r in reqs)
+    need = max(workspace_bytes(Options(r.N, precision="fp32-in-fp64"), forward_vjp=True) + field_bytes(r.N, r.mode)
+               for r in reqs)
     budget = int(2.5 * need)         # tight: forces queueing
     srv = Server(budget_bytes=budget, max_slots=4)
     mixed = srv.run(copy.deepcopy(reqs), realtime=False)
