@@ -89,6 +89,11 @@ typedef struct dmgs_options {
     int32_t ir_adaptive;   /* DMGS_FP32_IN_FP64, tolerance mode: nonzero (default) = after the first step,
                               run as many V-cycles per step as the contraction factor observed so far
                               predicts the tolerance needs, at most ir_inner_cycles */
+    int32_t adjoint_schedule; /* tolerance mode: 0 (default) = a pull-back stops on its own residual;
+                                 1 = it repeats exactly the V-cycle schedule of the last dmgs_forward on
+                                 this plan (the count recorded in the forward pass; Sec. 2.4), so that
+                                 in float64 it is the exact transpose of that forward solve */
+    int32_t reserved;
 } dmgs_options;
 
 typedef struct dmgs_info {
@@ -152,7 +157,12 @@ int dmgs_jvp(dmgs_plan plan, const double *rho, const double *dq, const double *
  * with qbar = 0 and rho = g on boundary vertices.  logD_bar / logmua_bar may
  * be NULL (not computed).  Tolerance mode stops on ||rhobar - A qbar|| /
  * ||rhobar|| <= rtol; fixed mode applies exactly fixed_cycles cycles, making
- * the result the exact transpose of the fixed-cycle forward map. */
+ * the result the exact transpose of the fixed-cycle forward map.  With
+ * opt.adjoint_schedule the pull-back instead repeats the schedule of the last
+ * dmgs_forward (or dmgs_forward_vjp) on the plan, cycle for cycle (float64)
+ * or float32 V-cycles per refinement step (float32-in-float64), so that in
+ * float64 it is the exact transpose of that forward solve; DMGS_ERR_INVALID
+ * if no forward solve has run on the plan. */
 int dmgs_vjp(dmgs_plan plan, const double *rho, const double *rhobar, double *qbar,
              double *logD_bar, double *logmua_bar, dmgs_info *info, void *stream);
 
@@ -167,7 +177,9 @@ int dmgs_vjp(dmgs_plan plan, const double *rho, const double *rhobar, double *qb
  * count them; dmgs_forward_vjp_workspace_bytes does).  rho, qbar, logD_bar and logmua_bar must not alias each other
  * or the inputs; logD_bar / logmua_bar may be NULL.  info_fwd and info_vjp
  * describe the two solves (either may be NULL); the returned status is the
- * forward solve's, else the adjoint's. */
+ * forward solve's, else the adjoint's.  With opt.adjoint_schedule the adjoint
+ * solve repeats this call's forward schedule, so it is enqueued (still on the
+ * second stream) only after the forward solve has finished on the host. */
 int dmgs_forward_vjp(dmgs_plan plan, const double *q, const double *rhobar, double *rho, double *qbar,
                      double *logD_bar, double *logmua_bar, dmgs_info *info_fwd, dmgs_info *info_vjp, void *stream);
 

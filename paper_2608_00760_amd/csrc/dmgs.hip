@@ -13,6 +13,7 @@
 #include <new>
 #include <string>
 #include <thread>
+#include <vector>
 
 #include "kernels_basic.hpp"
 #include "kernels_stream.hpp"
@@ -85,6 +86,7 @@ int check_options(const dmgs_options* o) {
     }
     if (o->precision != DMGS_FP64 && o->precision != DMGS_FP32_IN_FP64) { set_error("bad precision %d", o->precision); return DMGS_ERR_INVALID; }
     if (o->smoother != DMGS_RBGS && o->smoother != DMGS_WJACOBI) { set_error("bad smoother %d", o->smoother); return DMGS_ERR_INVALID; }
+    if (o->adjoint_schedule != 0 && o->adjoint_schedule != 1) { set_error("bad adjoint_schedule %d", o->adjoint_schedule); return DMGS_ERR_INVALID; }
     if (o->nu_pre < 0 || o->nu_pre > 8 || o->nu_post < 0 || o->nu_post > 8 || o->nu_pre + o->nu_post == 0) {
         set_error("bad smoothing counts %d,%d", o->nu_pre, o->nu_post);
         return DMGS_ERR_INVALID;
@@ -818,10 +820,17 @@ int read_norms(dmgs_plan P, hipStream_t st) {
 
 // Solve A x = b on the finest level from x = 0 (interior) / bc (boundary).
 // order 0: red-first cycles (S); order 1: black-first cycles (S^T).
-int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_info* info, hipStream_t st) {
+// replay: run exactly this V-cycle schedule (float64 plans: one entry per
+// cycle; refinement plans: the float32 V-cycles of each step) with no
+// convergence test.  record: a tolerance-mode solve stores its schedule in
+// P->fwd_schedule.
+int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_info* info, hipStream_t st,
+          const std::vector<int>* replay = nullptr, bool record = false) {
     const dmgs_options& o = P->opt;
     const Level& l0 = P->lev[0];
-    const bool fixed = o.fixed_cycles > 0;
+    const bool fixed = o.fixed_cycles > 0 || replay;
+    const int nfix = replay ? (int)replay->size() : o.fixed_cycles;
+    std::vector<int> sched;
     // with a zero boundary value the refinement's first steps treat the
     // zero iterate implicitly (x is neither cleared nor read; only its
     // boundary is set, and it is cleared if no correction is applied)
@@ -845,10 +854,11 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
             if (!std::isfinite(r0)) { set_error("non-finite right-hand side"); status = DMGS_ERR_NONFINITE; goto done; }
             if (r0 == 0.0) goto done;
         }
-        for (cycles = 1;; cycles++) {
+        for (cycles = 1; !(fixed && nfix == 0); cycles++) {
             TRY(vcycle<double>(P, 0, &cur, &oth, b, order, false, st));
+            sched.push_back(1);
             if (fixed) {
-                if (cycles == o.fixed_cycles) break;
+                if (cycles == nfix) break;
                 continue;
             }
             TRY(ir_step(P, cur, nullptr, nullptr, b, nullptr, 1, st));
@@ -858,6 +868,7 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
             if (rel <= o.rtol) break;
             if (cycles >= o.max_cycles) { set_error("not converged after %d cycles (rel %.3e)", cycles, rel); status = DMGS_ERR_NOT_CONVERGED; break; }
         }
+        if (fixed && nfix == 0) cycles = 0;
         if (cur != x) HIPCHK(hipMemcpyAsync(x, cur, l0.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
         if (fixed && info) {
             TRY(ir_step(P, x, nullptr, nullptr, b, nullptr, 1, st));
@@ -913,16 +924,19 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
                     const double need = std::ceil(std::log(o.rtol / rel) / std::log(rate) - 1e-6);
                     inner = (int)std::min<double>(inner, std::max(1.0, need));
                 }
-            } else if (cycles == o.fixed_cycles) {
+            } else if (cycles == nfix) {
                 break;
             }
+            if (replay) inner = (*replay)[cycles];
+            sched.push_back(inner);
             for (int ic = 0; ic < inner; ic++)
                 TRY(vcycle<float>(P, 0, &e, &eo, l0.q32, order, ic == 0, st, ic == 0 && smoothed, rdone));
             vcycles += inner;
-            if (x_zero && cycles == 0 && (P->ir_steps[order] & 1)) {
+            if (x_zero && cycles == 0 && ((replay ? nfix : P->ir_steps[order]) & 1)) {
                 // the first update reads no iterate, so it may write x in
-                // place: with an odd number of steps (as the last solve of
-                // this kind took) the result then ends in x, not in xalt64
+                // place: with an odd number of steps (as a replayed schedule
+                // has, or the last solve of this kind took) the result then
+                // ends in x, not in xalt64
                 TRY(ir_step(P, xc, e, xc, b, l0.q32, 1, st, true));
             } else {
                 TRY(ir_step(P, xc, e, xo, b, l0.q32, 1, st, x_zero && cycles == 0));
@@ -938,10 +952,14 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
         if (fixed && info) {
             TRY(read_norms(P, st));
             r0 = std::sqrt(P->hnorm[0]);
-            rel = std::sqrt(P->hnorm[o.fixed_cycles > 0 ? 1 : 0]) / (r0 > 0.0 ? r0 : 1.0);
+            rel = std::sqrt(P->hnorm[nfix > 0 ? 1 : 0]) / (r0 > 0.0 ? r0 : 1.0);
         }
     }
 done:
+    if (record && !fixed) {
+        P->fwd_recorded = status == DMGS_OK || status == DMGS_ERR_NOT_CONVERGED;
+        P->fwd_schedule = sched;
+    }
     if (info) {
         info->cycles = cycles;
         info->vcycles = is_ir(P) ? vcycles : cycles;
@@ -1272,7 +1290,7 @@ int dmgs_forward(dmgs_plan P, const double* q, double* rho, dmgs_info* info, voi
     hipStream_t st = (hipStream_t)stream;
     TRY(begin_call(P, st));
     if (!q || !rho) { set_error("NULL argument"); return DMGS_ERR_INVALID; }
-    int s = solve(P, q, rho, P->opt.bc_value, 0, info, st);
+    int s = solve(P, q, rho, P->opt.bc_value, 0, info, st, nullptr, true);
     return end_call(P, s, info, st);
 }
 
@@ -1294,7 +1312,12 @@ int dmgs_vjp(dmgs_plan P, const double* rho, const double* rhobar, double* qbar,
     hipStream_t st = (hipStream_t)stream;
     TRY(begin_call(P, st));
     if (!rho || !rhobar || !qbar) { set_error("NULL argument"); return DMGS_ERR_INVALID; }
-    int s = solve(P, rhobar, qbar, 0.0, 1, info, st);
+    const std::vector<int>* replay = nullptr;
+    if (P->opt.adjoint_schedule && P->opt.fixed_cycles <= 0) {
+        if (!P->fwd_recorded) { set_error("adjoint_schedule: no forward solve recorded on this plan"); return DMGS_ERR_INVALID; }
+        replay = &P->fwd_schedule;
+    }
+    int s = solve(P, rhobar, qbar, 0.0, 1, info, st, replay);
     if ((s == DMGS_OK || s == DMGS_ERR_NOT_CONVERGED) && (logD_bar || logmua_bar)) {
         const Level& l0 = P->lev[0];
         TIMED(P, 0, DMGS_K_GRAD, 48.0 * l0.nv, st,
@@ -1388,17 +1411,31 @@ int dmgs_forward_vjp(dmgs_plan P, const double* q, const double* rhobar, double*
     // the adjoint solve starts after the work already enqueued on `stream`
     // (the coefficients) and runs on the twin's stream from a second host
     // thread; `stream` waits for it before the gradients
-    HIPCHK(hipEventRecord(P->ev_fork, st));
-    HIPCHK(hipStreamWaitEvent(P->twin_stream, P->ev_fork, 0));
-    int sa = DMGS_OK;
+    // With adjoint_schedule (tolerance mode) the adjoint solve repeats the
+    // forward solve's schedule, so it starts once the forward one has run
+    // on the host (its kernels may still be in flight).
+    const bool replay = P->opt.adjoint_schedule && P->opt.fixed_cycles <= 0;
+    int sa = DMGS_OK, sf = DMGS_OK;
     std::string err_a;
-    std::thread adj([&] {
+    auto adjoint = [&] {
         if (hipSetDevice(P->device) != hipSuccess) { sa = DMGS_ERR_HIP; err_a = "hipSetDevice failed"; return; }
-        sa = solve(T, rhobar, qbar, 0.0, 1, info_vjp, P->twin_stream);
+        sa = solve(T, rhobar, qbar, 0.0, 1, info_vjp, P->twin_stream, replay ? &T->fwd_schedule : nullptr);
         if (sa != DMGS_OK) err_a = dmgs_last_error();
-    });
-    int sf = solve(P, q, rho, P->opt.bc_value, 0, info_fwd, st);
-    adj.join();
+    };
+    if (replay) {
+        sf = solve(P, q, rho, P->opt.bc_value, 0, info_fwd, st, nullptr, true);
+        if (sf != DMGS_OK && sf != DMGS_ERR_NOT_CONVERGED) return end_call(P, sf, info_fwd, st);
+        T->fwd_schedule = P->fwd_schedule;
+        HIPCHK(hipEventRecord(P->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(P->twin_stream, P->ev_fork, 0));
+        adjoint();
+    } else {
+        HIPCHK(hipEventRecord(P->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(P->twin_stream, P->ev_fork, 0));
+        std::thread adj(adjoint);
+        sf = solve(P, q, rho, P->opt.bc_value, 0, info_fwd, st, nullptr, true);
+        adj.join();
+    }
     if (hipEventRecord(P->ev_join, P->twin_stream) != hipSuccess || hipStreamWaitEvent(st, P->ev_join, 0) != hipSuccess) {
         set_error("event join failed");
         return DMGS_ERR_HIP;

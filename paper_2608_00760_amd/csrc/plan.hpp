@@ -1,5 +1,6 @@
 // plan.hpp -- the resident level hierarchy of a solver plan.
 #pragma once
+#include <vector>
 #include <hip/hip_runtime.h>
 
 #include "../../include/dmgs.h"
@@ -86,6 +87,8 @@ struct dmgs_plan_s {
     hipEvent_t ev_flag = nullptr;  // recorded after the validation flag's copy to the host
     int tmark = 0;                 // timer slots recorded before ev_norm
     int ir_steps[2] = {0, 0};      // refinement steps of the last solve, by cycle order
+    std::vector<int> fwd_schedule; // V-cycle schedule of the last tolerance-mode forward solve
+    bool fwd_recorded = false;
     bool coef_set = false;
     // kernel timing (profiling aid)
     bool timing = false;

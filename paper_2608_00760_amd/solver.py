@@ -32,6 +32,7 @@ class Options:
     ir_inner_cycles: int = 8          # float32 V-cycles per refinement step (the most, when adaptive)
     ir_adaptive: bool = True          # later steps run the V-cycles the observed contraction predicts
     smoother: str = "rbgs"            # "rbgs" (red-black Gauss-Seidel) | "wjacobi" (weighted Jacobi, 6/7)
+    adjoint_schedule: bool = False    # pull-back repeats the last forward solve's V-cycle schedule
 
     def to_c(self):
         o = _abi.default_options(self.N)
@@ -45,6 +46,7 @@ class Options:
         o.ir_inner_cycles = int(self.ir_inner_cycles)
         o.ir_adaptive = 1 if self.ir_adaptive else 0
         o.smoother = _SMOOTHER[self.smoother]
+        o.adjoint_schedule = 1 if self.adjoint_schedule else 0
         return o
 
 

@@ -63,6 +63,21 @@ def test_default_options_and_footprint(abi):
     assert lib.dmgs_forward_vjp_workspace_bytes(C.byref(abi.default_options(20))) == 0
 
 
+def test_options_layout_matches_the_header(abi):
+    """dmgs_default_options clears sizeof(dmgs_options) bytes and then sets the
+    defaults; in a buffer pre-filled with a sentinel, the last byte it writes
+    (the zero `reserved` field) is the last byte of the binding's struct."""
+    size = C.sizeof(abi.Options)
+    buf = (C.c_uint8 * (size + 64))(*([0xAB] * (size + 64)))
+    abi.lib().dmgs_default_options(32, C.cast(buf, C.POINTER(abi.Options)))
+    written = [i for i in range(size + 64) if buf[i] != 0xAB]
+    assert written[-1] + 1 == size
+    o = abi.Options.from_buffer(buf)
+    assert o.adjoint_schedule == 0 and o.ir_adaptive == 1 and o.ir_inner_cycles == 8
+    o.adjoint_schedule = 2
+    assert abi.lib().dmgs_workspace_bytes(C.byref(o)) == 0
+
+
 def test_status_strings(abi):
     assert abi.status_string(0) == "ok"
     assert abi.status_string(3) == "not converged"
