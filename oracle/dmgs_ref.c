@@ -784,11 +784,12 @@ int ref_vjp(const ref_hier *H, const double *rho, const double *rhobar, double *
     return st;
 }
 
-/* Pull-back in q computed instead by black-before-red V-cycles on
+/* Pull-back in q computed instead by transposed V-cycles on
  * A qbar = rhobar from qbar = 0 (used to check that this equals the literal
- * reversed composition).  With weighted Jacobi the colour order has no
- * meaning; the transposed cycle is the one with the pre- and
- * post-smoothing counts exchanged. */
+ * reversed composition).  Reversing a cycle's steps (Eq. (EqcompT)) turns
+ * its post-smoothing into the pre-smoothing, so the transposed cycle has the
+ * pre- and post-smoothing counts exchanged; red-black sweeps also run black
+ * before red (with weighted Jacobi the colour order has no meaning). */
 int ref_pullback_br(const ref_hier *H, const double *rhobar, double *qbar, int nu1, int nu2,
                     double rtol, int max_cycles, int fixed_cycles, int *cycles, double *relres) {
     int N = H->N[0], n = N + 1;
@@ -800,8 +801,7 @@ int ref_pullback_br(const ref_hier *H, const double *rhobar, double *qbar, int n
                 size_t i = idx(n, x, y, z);
                 w[i] = interior(N, x, y, z) ? rhobar[i] : 0.0;
             }
-    ref_opts o = { 1, nu1, nu2, rtol, max_cycles, fixed_cycles };
-    if (H->smoother) { o.nu1 = nu2; o.nu2 = nu1; }
+    ref_opts o = { 1, nu2, nu1, rtol, max_cycles, fixed_cycles };
     int st = ref_solve(H, 0.0, w, qbar, &o, cycles, relres, NULL, 0);
     free(w);
     return st;

@@ -614,7 +614,13 @@ int block_attributes() {
     return DMGS_OK;
 }
 
-// Pre-smoothing pass on level k: nu_pre sweeps from *cur (or from 0), then
+// Smoothing counts of a cycle: the transposed cycle (order 1) reverses the
+// cycle's steps, so it pre-smooths with the forward cycle's post-smoothing
+// count and post-smooths with its pre-smoothing count.
+int nu_pre_of(dmgs_plan P, int order) { return order ? P->opt.nu_post : P->opt.nu_pre; }
+int nu_post_of(dmgs_plan P, int order) { return order ? P->opt.nu_pre : P->opt.nu_post; }
+
+// Pre-smoothing pass on level k: nu_pre_of sweeps from *cur (or from 0), then
 // qc = R (q - A u).  Simple levels work in place.
 template <class T>
 int pre_pass(dmgs_plan P, int k, T** cur, T** other, const T* q, T* qc, int order, bool zero, hipStream_t st) {
@@ -623,11 +629,11 @@ int pre_pass(dmgs_plan P, int k, T** cur, T** other, const T* q, T* qc, int orde
     if (fused_level(P, k)) {
         bool rdone;
         T* r = Typed<T>::r(l);
-        TRY(smooth_phase<T>(P, k, cur, other, q, P->opt.nu_pre, order, zero, (const T*)nullptr, st, r, &rdone));
+        TRY(smooth_phase<T>(P, k, cur, other, q, nu_pre_of(P, order), order, zero, (const T*)nullptr, st, r, &rdone));
         return rdone ? defect_restrict<T>(P, k, r, q, qc, st, true, order) : defect_restrict<T>(P, k, *cur, q, qc, st);
     }
     if (zero) TRY(fill<T>(*cur, l.nv, T(0), st));
-    TRY(sweeps<T>(P, k, *cur, q, P->opt.nu_pre, order, st));
+    TRY(sweeps<T>(P, k, *cur, q, nu_pre_of(P, order), order, st));
     T* r = *other;   // scratch for the defect
     TRY(apply_or_defect<T>(P, k, *cur, q, r, 0, st));
     hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(P->lev[k + 1].nv)), dim3(kBlock), 0, st, (const T*)r, qc, l.N);
@@ -636,15 +642,15 @@ int pre_pass(dmgs_plan P, int k, T** cur, T** other, const T* q, T* qc, int orde
     return DMGS_OK;
 }
 
-// Post-smoothing pass on level k: u = *cur + I ec, then nu_post sweeps.
+// Post-smoothing pass on level k: u = *cur + I ec, then nu_post_of sweeps.
 template <class T>
 int post_pass(dmgs_plan P, int k, T** cur, T** other, const T* ec, const T* q, int order, hipStream_t st) {
     const Level& l = P->lev[k];
     if (block_level<T>(P, k)) return block_phase<T>(P, k, cur, other, q, (T*)nullptr, ec, order, false, true, st);
-    if (fused_level(P, k)) return smooth_phase<T>(P, k, cur, other, q, P->opt.nu_post, order, false, ec, st);
+    if (fused_level(P, k)) return smooth_phase<T>(P, k, cur, other, q, nu_post_of(P, order), order, false, ec, st);
     TIMED(P, k, DMGS_K_PROLONG, (double)(2 * l.nv + P->lev[k + 1].nv) * sizeof(T), st,
           hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, ec, *cur, l.N));
-    return sweeps<T>(P, k, *cur, q, P->opt.nu_post, order, st);
+    return sweeps<T>(P, k, *cur, q, nu_post_of(P, order), order, st);
 }
 
 template <class T, bool HARM>
@@ -666,8 +672,8 @@ int launch_small_t(dmgs_plan P, int k, const T* q, T* u, int order, hipStream_t 
     a.q = q;
     a.u = u;
     a.cinv = P->cinv;
-    a.nu_pre = P->opt.nu_pre;
-    a.nu_post = P->opt.nu_post;
+    a.nu_pre = nu_pre_of(P, order);
+    a.nu_post = nu_post_of(P, order);
     a.order = order;
     a.roff = off;
     size_t bytes = small_lds_bytes<T>(Ns, a.nlev);
@@ -706,7 +712,7 @@ int wj_sweeps(dmgs_plan P, int k, T** cur, T** other, const T* q, int count, boo
 template <class T>
 int vcycle_wj(dmgs_plan P, int k, T** cur, T** other, const T* q, int order, bool zero, hipStream_t st) {
     const Level& l = P->lev[k];
-    const int nu1 = order ? P->opt.nu_post : P->opt.nu_pre, nu2 = order ? P->opt.nu_pre : P->opt.nu_post;
+    const int nu1 = nu_pre_of(P, order), nu2 = nu_post_of(P, order);
     if (zero && (k == P->L - 1 || nu1 == 0)) TRY(fill<T>(*cur, l.nv, T(0), st));
     if (k == P->L - 1) return coarsest<T>(P, q, *cur, st);
     TRY(wj_sweeps<T>(P, k, cur, other, q, nu1, zero && nu1 > 0, st));
@@ -901,7 +907,7 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
                 // residual the last step is expected to reach
                 const double pred = cycles == 0 ? 1.0 : rel1 * std::pow(rate > 0.0 ? rate : 0.5, inner);
                 if (can_speculate && cycles < o.max_cycles && pred > o.rtol) {
-                    TRY(smooth_phase<float>(P, 0, &e, &eo, l0.q32, o.nu_pre, order, true, (const float*)nullptr, st,
+                    TRY(smooth_phase<float>(P, 0, &e, &eo, l0.q32, nu_pre_of(P, order), order, true, (const float*)nullptr, st,
                                             l0.r32, &rdone));
                     smoothed = true;
                 }

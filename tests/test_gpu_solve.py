@@ -217,3 +217,27 @@ def test_forward_vjp_concurrent_equals_separate_calls(precision):
         assert if2["vcycles"] == inf["vcycles"] and ia2["vcycles"] == ina["vcycles"]
         for a, b in ((rho, rho2), (qb, qb2), (gD, gD2), (gmu, gmu2)):
             assert bool((a == b).all()), rep
+
+
+@pytest.mark.parametrize("nu1,nu2", [(2, 1), (1, 3), (0, 2)])
+def test_fixed_cycles_unequal_smoothing(nu1, nu2):
+    """V(nu1,nu2) with nu1 != nu2: the pull-back is the transposed cycle with
+    the smoothing counts exchanged, equal to the oracle's literal reversed
+    composition, and the dot-product identity holds on the GPU alone."""
+    from oracle import ref
+    say("fixed nu=%d,%d" % (nu1, nu2))
+    N, n = 48, 3
+    c = grf_inputs(N, 700 + nu1)
+    H = ref.Hierarchy(c["D"], c["mua"])
+    P = plan_for(c["D"], c["mua"], fixed_cycles=n, nu_pre=nu1, nu_post=nu2)
+    rho, _ = P.forward(dev(c["q"]))
+    rr, _ = H.forward(c["q"], fixed_cycles=n, nu1=nu1, nu2=nu2)
+    assert rel_max(host(rho), rr) <= 1e-12
+    (qb, gD, gmu), _ = P.vjp(rho, dev(c["rhobar"]))
+    (rqb, rgD, rgmu), _ = H.vjp(rr, c["rhobar"], fixed_cycles=n, nu1=nu1, nu2=nu2)
+    for g, r in ((qb, rqb), (gD, rgD), (gmu, rgmu)):
+        assert rel_max(host(g), r) <= 1e-12
+    drho, _ = P.jvp(rho, dev(c["dq"]), dev(c["dlogD"]), dev(c["dlogmua"]))
+    lhs = float((drho * dev(c["rhobar"])).sum())
+    rhs = float((dev(c["dq"]) * qb).sum() + (dev(c["dlogD"]) * gD).sum() + (dev(c["dlogmua"]) * gmu).sum())
+    assert abs(lhs - rhs) <= 1e-12 * float(drho.norm()) * float(np.linalg.norm(c["rhobar"]))

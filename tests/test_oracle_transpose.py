@@ -100,15 +100,20 @@ def test_full_dot_product_identity_all_inputs(N):
     assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(drho) * np.linalg.norm(t["rhobar"])
 
 
-@pytest.mark.parametrize("N,n", [(8, 4), (32, 9), (24, 6)])
-def test_literal_pullback_equals_black_red_cycles(N, n):
-    """The reversed composition of adjoint steps equals n black-before-red
-    V(2,2)-cycles on A qbar = rhobar from qbar = 0."""
+@pytest.mark.parametrize("N,n,nu1,nu2", [(8, 4, 2, 2), (32, 9, 2, 2), (24, 6, 2, 2), (16, 3, 2, 1), (16, 3, 1, 3),
+                                          (12, 2, 0, 2)])
+def test_literal_pullback_equals_black_red_cycles(N, n, nu1, nu2):
+    """The reversed composition of adjoint steps of n V(nu1,nu2)-cycles equals
+    n black-before-red V(nu2,nu1)-cycles on A qbar = rhobar from qbar = 0."""
     H = grf_hier(N, 300 + N)
     w = rnd(N, 30)
-    (lit, _, _), _ = H.vjp(np.zeros_like(w), w, fixed_cycles=n)
-    br, _ = H.pullback_br(w, fixed_cycles=n)
+    (lit, _, _), _ = H.vjp(np.zeros_like(w), w, fixed_cycles=n, nu1=nu1, nu2=nu2)
+    br, _ = H.pullback_br(w, fixed_cycles=n, nu1=nu1, nu2=nu2)
     assert np.abs(lit - br).max() <= 1e-13 * np.abs(lit).max()
+    if nu1 != nu2:
+        # the counts matter: black-first cycles with them in place differ
+        same = H.cycles(w, np.zeros_like(w), n, order=1, nu1=nu1, nu2=nu2)
+        assert np.abs(lit - same).max() > 1e-6 * np.abs(lit).max()
     # and, for comparison, one red-first cycle is a different map from one
     # black-first cycle (so the test above can tell the two orders apart)
     rb1 = H.cycles(w, np.zeros_like(w), 1, order=0)
