@@ -2,7 +2,9 @@
 
 This module draws fields only; it contains none of the solver's arithmetic.
 Every field is a float64 numpy array of shape (N+1, N+1, N+1) on the vertices
-of an N-cell grid with unit spacing, x slowest, z fastest.
+of an N-cell grid with unit spacing, x slowest, z fastest; with ndim=2 it is
+(N+1, N+1), x slowest, y fastest, and the recipes below hold with two
+coordinates in place of three.
 
 Recipes (the paper's Monte Carlo tissue data are not available; these stand
 in for coefficient fields and sources of the same kind):
@@ -30,24 +32,27 @@ except ImportError:  # numpy fallback
     _FFT_KW = {}
 
 
-def shape(N):
-    return (N + 1, N + 1, N + 1)
+def shape(N, ndim=3):
+    return (N + 1,) * ndim
 
 
-def grf(N, seed, slope=-3.0):
+def grf(N, seed, slope=-3.0, ndim=3):
     """Zero-mean unit-variance Gaussian random field with P(k) ~ k^slope."""
     rng = np.random.default_rng(seed)
     n = N + 1
-    w = rng.standard_normal(shape(N))
+    w = rng.standard_normal(shape(N, ndim))
     W = _fft.rfftn(w, **_FFT_KW)
     kx = np.fft.fftfreq(n) * n
     kz = np.fft.rfftfreq(n) * n
-    k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
-    k2[0, 0, 0] = 1.0
+    if ndim == 3:
+        k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
+    else:
+        k2 = kx[:, None] ** 2 + kz[None, :] ** 2
+    k2.flat[0] = 1.0
     amp = k2 ** (slope / 4.0)          # |k|^(slope/2)
-    amp[0, 0, 0] = 0.0
+    amp.flat[0] = 0.0
     W *= amp
-    f = _fft.irfftn(W, s=shape(N), **_FFT_KW)
+    f = _fft.irfftn(W, s=shape(N, ndim), **_FFT_KW)
     f -= f.mean()
     f /= f.std()
     return np.ascontiguousarray(f)
@@ -59,40 +64,46 @@ def coords(N):
 
 
 def blob(N, centre, sigma, amplitude=1.0):
-    """amplitude * exp(-|x - c|^2 / (2 sigma^2)), as a product of 1D factors."""
+    """amplitude * exp(-|x - c|^2 / (2 sigma^2)), as a product of 1D factors
+    (len(centre) = 3 or 2 coordinates)."""
     x = np.arange(N + 1, dtype=np.float64)
-    g = [np.exp(-(x - centre[a]) ** 2 / (2.0 * sigma * sigma)) for a in range(3)]
+    g = [np.exp(-(x - centre[a]) ** 2 / (2.0 * sigma * sigma)) for a in range(len(centre))]
+    if len(centre) == 2:
+        return amplitude * g[0][:, None] * g[1][None, :]
     return amplitude * (g[0][:, None, None] * g[1][None, :, None]) * g[2][None, None, :]
 
 
 def zero_boundary(f):
     f = f.copy()
-    f[0, :, :] = f[-1, :, :] = 0.0
-    f[:, 0, :] = f[:, -1, :] = 0.0
-    f[:, :, 0] = f[:, :, -1] = 0.0
+    for a in range(f.ndim):
+        idx = [slice(None)] * f.ndim
+        idx[a] = 0
+        f[tuple(idx)] = 0.0
+        idx[a] = -1
+        f[tuple(idx)] = 0.0
     return f
 
 
-def normal(N, seed, zero_bdry=True):
-    f = np.random.default_rng(seed).standard_normal(shape(N))
+def normal(N, seed, zero_bdry=True, ndim=3):
+    f = np.random.default_rng(seed).standard_normal(shape(N, ndim))
     return zero_boundary(f) if zero_bdry else f
 
 
-def log_coefficients(N, seed_D, seed_mu):
-    logD = np.clip(grf(N, seed_D), -math.log(100.0), math.log(100.0))
-    logmua = math.log(0.05) + grf(N, seed_mu)
+def log_coefficients(N, seed_D, seed_mu, ndim=3):
+    logD = np.clip(grf(N, seed_D, ndim=ndim), -math.log(100.0), math.log(100.0))
+    logmua = math.log(0.05) + grf(N, seed_mu, ndim=ndim)
     return logD, logmua
 
 
-def blob_source(N, seed, nblobs=16, noise=0.01):
+def blob_source(N, seed, nblobs=16, noise=0.01, ndim=3):
     rng = np.random.default_rng(seed)
-    q = np.zeros(shape(N))
+    q = np.zeros(shape(N, ndim))
     for _ in range(nblobs):
-        c = rng.uniform(0.15 * N, 0.85 * N, size=3)
+        c = rng.uniform(0.15 * N, 0.85 * N, size=ndim)
         s = rng.uniform(2.0, 6.0)
         a = rng.uniform(0.5, 1.5)
         q += blob(N, c, s, a)
-    q += noise * rng.standard_normal(shape(N))
+    q += noise * rng.standard_normal(shape(N, ndim))
     return q
 
 
@@ -104,19 +115,19 @@ def constant_case(N=32):
     return {"N": N, "logD": np.log(D), "logmua": np.log(mua), "D": D, "mua": mua, "q": q}
 
 
-def grf_case(N, base_seed):
+def grf_case(N, base_seed, ndim=3):
     """Log-normal GRF coefficients and a 16-blob source.  Seeds are
     base_seed+1 (log D), +2 (log mua), +3 (q), +4 (cotangent rhobar)."""
-    logD, logmua = log_coefficients(N, base_seed + 1, base_seed + 2)
-    q = blob_source(N, base_seed + 3)
+    logD, logmua = log_coefficients(N, base_seed + 1, base_seed + 2, ndim)
+    q = blob_source(N, base_seed + 3, ndim=ndim)
     return {"N": N, "logD": logD, "logmua": logmua, "D": np.exp(logD), "mua": np.exp(logmua), "q": q,
-            "rhobar": normal(N, base_seed + 4)}
+            "rhobar": normal(N, base_seed + 4, ndim=ndim)}
 
 
-def tangents(N, base_seed):
+def tangents(N, base_seed, ndim=3):
     """Tangents (dq, dlogD, dlogmua) and cotangent rhobar, seeds base_seed+1..+4."""
-    return {"dq": normal(N, base_seed + 1), "dlogD": normal(N, base_seed + 2, zero_bdry=False),
-            "dlogmua": normal(N, base_seed + 3), "rhobar": normal(N, base_seed + 4)}
+    return {"dq": normal(N, base_seed + 1, ndim=ndim), "dlogD": normal(N, base_seed + 2, zero_bdry=False, ndim=ndim),
+            "dlogmua": normal(N, base_seed + 3, ndim=ndim), "rhobar": normal(N, base_seed + 4, ndim=ndim)}
 
 
 # Named workloads (sizes and seeds).
