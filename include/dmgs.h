@@ -18,7 +18,8 @@
  *
  * Conventions for every entry point:
  *  - Field arrays are DEVICE pointers to dense C-order float64 arrays of
- *    (N+1)^3 entries, x slowest, z fastest: v = (x*(N+1) + y)*(N+1) + z.
+ *    (N+1)^3 entries, x slowest, z fastest: v = (x*(N+1) + y)*(N+1) + z
+ *    (plans with ndim = 2: (N+1)^2 entries, v = x*(N+1) + y).
  *    They are owned by the caller and must stay valid until the work enqueued
  *    on `stream` has finished.  Outputs must not alias inputs.
  *  - Boundary vertices (any coordinate 0 or N) of q, mua, tangents and
@@ -73,7 +74,8 @@ enum dmgs_smoother { DMGS_RBGS = 0, DMGS_WJACOBI = 1 };
 enum dmgs_face_mean { DMGS_FACE_ARITH = 0, DMGS_FACE_HARMONIC = 1 };
 
 typedef struct dmgs_options {
-    int32_t n[3];          /* cells per axis; all three equal, N = c*2^m, c in {2,3}, 2 <= N <= 1024 */
+    int32_t n[3];          /* cells per axis; all three equal, N = c*2^m, c in {2,3}, 2 <= N <= 1024
+                              (two-dimensional plans: see ndim) */
     int32_t precision;     /* dmgs_precision */
     int32_t smoother;      /* dmgs_smoother: red-black Gauss-Seidel (Sec. 2.3.1) or weighted Jacobi */
     int32_t nu_pre;        /* pre-smoothing sweeps (red-black pairs), 0..8; default 2 */
@@ -93,7 +95,11 @@ typedef struct dmgs_options {
                                  1 = it repeats exactly the V-cycle schedule of the last dmgs_forward on
                                  this plan (the count recorded in the forward pass; Sec. 2.4), so that
                                  in float64 it is the exact transpose of that forward solve */
-    int32_t reserved;
+    int32_t ndim;          /* 3 (default): (N+1)^3 grids, 7-point operator.  2: (N+1)^2 grids and the
+                              5-point operator of the same equation in two dimensions (the paper's
+                              benchmark setting, Sec. 3.3), with red = (x + y) even, restriction
+                              (1/16)(1,2,1) x (1,2,1) and bilinear prolongation I = 2^2 R^T; n[0] = n[1]
+                              = N (n[2] ignored), 2 <= N <= 16384; DMGS_FP64 and DMGS_RBGS only. */
 } dmgs_options;
 
 typedef struct dmgs_info {
@@ -107,7 +113,7 @@ typedef struct dmgs_info {
 
 /* Fill `opt` with the defaults: V(2,2), RB-GS, FP64, arithmetic face mean,
  * h = 1, g = 0, rtol = 1e-10, max_cycles = 200, fixed_cycles = 0,
- * ir_inner_cycles = 8, ir_adaptive = 1.  In DMGS_FP32_IN_FP64 plans a
+ * ir_inner_cycles = 8, ir_adaptive = 1, adjoint_schedule = 0, ndim = 3.  In DMGS_FP32_IN_FP64 plans a
  * "cycle" of max_cycles, fixed_cycles and info.cycles is one refinement
  * step. */
 void dmgs_default_options(int32_t n, dmgs_options *opt);

@@ -21,7 +21,7 @@ class Options(C.Structure):
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("max_cycles", C.c_int32),
                 ("fixed_cycles", C.c_int32), ("face_mean", C.c_int32), ("h", C.c_double),
                 ("bc_value", C.c_double), ("rtol", C.c_double), ("ir_inner_cycles", C.c_int32),
-                ("ir_adaptive", C.c_int32), ("adjoint_schedule", C.c_int32), ("reserved", C.c_int32)]
+                ("ir_adaptive", C.c_int32), ("adjoint_schedule", C.c_int32), ("ndim", C.c_int32)]
 
 
 class Info(C.Structure):

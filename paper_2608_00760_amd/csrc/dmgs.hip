@@ -20,6 +20,7 @@
 #include "kernels_sweep2.hpp"
 #include "kernels_block.hpp"
 #include "kernels_small.hpp"
+#include "kernels_2d.hpp"
 #include "plan.hpp"
 
 using namespace dmgs;
@@ -79,9 +80,18 @@ int levels_for(int N) {
 int check_options(const dmgs_options* o) {
     if (!o) { set_error("options is NULL"); return DMGS_ERR_INVALID; }
     int N = o->n[0];
-    if (o->n[1] != N || o->n[2] != N) { set_error("only cubic grids are supported (n = %d,%d,%d)", o->n[0], o->n[1], o->n[2]); return DMGS_ERR_INVALID; }
-    if (N < 2 || N > 1024 || levels_for(N) == 0 || levels_for(N) > kMaxLevels) {
-        set_error("N = %d is not c*2^m with c in {2,3}, 2 <= N <= 1024", N);
+    if (o->ndim != 2 && o->ndim != 3) { set_error("bad ndim %d", o->ndim); return DMGS_ERR_INVALID; }
+    const int nmax = o->ndim == 2 ? 16384 : 1024;
+    if (o->n[1] != N || (o->ndim == 3 && o->n[2] != N)) {
+        set_error("only square or cubic grids are supported (n = %d,%d,%d)", o->n[0], o->n[1], o->n[2]);
+        return DMGS_ERR_INVALID;
+    }
+    if (N < 2 || N > nmax || levels_for(N) == 0 || levels_for(N) > kMaxLevels) {
+        set_error("N = %d is not c*2^m with c in {2,3}, 2 <= N <= %d", N, nmax);
+        return DMGS_ERR_INVALID;
+    }
+    if (o->ndim == 2 && (o->precision != DMGS_FP64 || o->smoother != DMGS_RBGS)) {
+        set_error("two-dimensional plans take DMGS_FP64 and DMGS_RBGS");
         return DMGS_ERR_INVALID;
     }
     if (o->precision != DMGS_FP64 && o->precision != DMGS_FP32_IN_FP64) { set_error("bad precision %d", o->precision); return DMGS_ERR_INVALID; }
@@ -113,7 +123,8 @@ Sizes sizes_for(const dmgs_options* o) {
     Sizes s;
     s.L = levels_for(o->n[0]);
     int N = o->n[0];
-    for (int k = 0; k < s.L; k++, N /= 2) s.nv[k] = (int64_t)(N + 1) * (N + 1) * (N + 1);
+    for (int k = 0; k < s.L; k++, N /= 2)
+        s.nv[k] = (int64_t)(N + 1) * (N + 1) * (o->ndim == 2 ? 1 : (N + 1));
     return s;
 }
 
@@ -122,6 +133,10 @@ size_t footprint(const dmgs_options* o) {
     bool ir = o->precision == DMGS_FP32_IN_FP64;
     size_t b = 0;
     for (int k = 0; k < s.L; k++) {
+        if (o->ndim == 2) {   // D64, mu64, (u64, q64)
+            b += (k > 0 ? 4 : 2) * s.nv[k] * sizeof(double);
+            continue;
+        }
         b += 2 * s.nv[k] * sizeof(double);                            // D64, mu64
         if (ir) b += (k < s.L - 1 ? 7 : 6) * s.nv[k] * sizeof(float);  // D32, mu32, w32, u32, q32, t32, (r32)
         else b += (k > 0 ? 4 : 2) * s.nv[k] * sizeof(double);         // w64, (u64, q64), t64
@@ -176,6 +191,7 @@ void free_plan(dmgs_plan P) {
 }
 
 bool is_ir(dmgs_plan P) { return P->opt.precision == DMGS_FP32_IN_FP64; }
+bool is2d(dmgs_plan P) { return P->opt.ndim == 2; }
 int harmonic(dmgs_plan P) { return P->opt.face_mean == DMGS_FACE_HARMONIC; }
 
 // ---------------------------------------------------------------------------
@@ -824,6 +840,123 @@ int read_norms(dmgs_plan P, hipStream_t st) {
     return DMGS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Two-dimensional plans (ndim = 2): float64 V-cycles, in place, one launch
+// per half-sweep, the defect restricted as it is formed.
+
+template <bool HARM>
+int half_sweep2(dmgs_plan P, int k, double* u, const double* q, int colour, hipStream_t st) {
+    const Level& l = P->lev[k];
+    const int64_t items = (int64_t)(l.N - 1) * (l.N / 2);
+    // reads u and D on every vertex, q and mua on one colour; writes one colour
+    TIMED(P, k, DMGS_K_SMOOTH, 28.0 * l.nv, st,
+          hipLaunchKernelGGL(k2_half_sweep<HARM>, dim3(vertex_grid(items)), dim3(kBlock), 0, st, u, q,
+                             (const double*)l.D64, (const double*)l.mu64, l.N, l.stencil<double>(HARM), colour));
+    return DMGS_OK;
+}
+
+// One V-cycle on level k of a two-dimensional plan, in place on u (from 0
+// when zero); order 1 is the transposed cycle.
+template <bool HARM>
+int vcycle2(dmgs_plan P, int k, double* u, const double* q, int order, bool zero, hipStream_t st) {
+    const Level& l = P->lev[k];
+    if (zero) TRY(fill<double>(u, l.nv, 0.0, st));
+    if (k == P->L - 1) {
+        hipLaunchKernelGGL(k2_exact<HARM>, dim3(1), dim3(64), 0, st, q, u, (const double*)l.D64, (const double*)l.mu64,
+                           l.N, l.stencil<double>(HARM));
+        LAUNCHCHK();
+        return DMGS_OK;
+    }
+    const int first = order ? 1 : 0;
+    for (int i = 0; i < nu_pre_of(P, order); i++) {
+        TRY(half_sweep2<HARM>(P, k, u, q, first, st));
+        TRY(half_sweep2<HARM>(P, k, u, q, 1 - first, st));
+    }
+    const Level& c = P->lev[k + 1];
+    TIMED(P, k, DMGS_K_DEFECT_RESTRICT, 32.0 * l.nv + 8.0 * c.nv, st,
+          hipLaunchKernelGGL(k2_defect_restrict<HARM>, dim3(vertex_grid(c.nv)), dim3(kBlock), 0, st, (const double*)u, q,
+                             (const double*)l.D64, (const double*)l.mu64, l.N, l.stencil<double>(HARM), c.q64));
+    TRY(vcycle2<HARM>(P, k + 1, c.u64, c.q64, order, true, st));
+    TIMED(P, k, DMGS_K_PROLONG, 16.0 * l.nv + 8.0 * c.nv, st,
+          hipLaunchKernelGGL(k2_prolong_add, dim3(vertex_grid(l.nv)), dim3(kBlock), 0, st, (const double*)c.u64, u, l.N));
+    for (int i = 0; i < nu_post_of(P, order); i++) {
+        TRY(half_sweep2<HARM>(P, k, u, q, first, st));
+        TRY(half_sweep2<HARM>(P, k, u, q, 1 - first, st));
+    }
+    return DMGS_OK;
+}
+
+// ||b - A x||^2 of the finest level into the host norm slot `slot`.
+template <bool HARM>
+int resid2(dmgs_plan P, const double* x, const double* b, int slot, hipStream_t st) {
+    const Level& l = P->lev[0];
+    const unsigned nb = grid_for(l.nv, kMaxPartials);
+    TIMED(P, 0, DMGS_K_RESIDUAL, 32.0 * l.nv, st,
+          hipLaunchKernelGGL(k2_resid_sq<HARM>, dim3(nb), dim3(kBlock), 0, st, x, b, (const double*)l.D64,
+                             (const double*)l.mu64, l.N, l.stencil<double>(HARM), P->partial));
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, P->hnorm, slot);
+    LAUNCHCHK();
+    HIPCHK(hipEventRecord(P->ev_norm, st));
+    P->tmark = P->tpending;
+    return DMGS_OK;
+}
+
+// solve() for two-dimensional plans (same modes, schedule record and replay).
+template <bool HARM>
+int solve2d(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_info* info, hipStream_t st,
+            const std::vector<int>* replay, bool record) {
+    const dmgs_options& o = P->opt;
+    const Level& l0 = P->lev[0];
+    const bool fixed = o.fixed_cycles > 0 || replay;
+    const int nfix = replay ? (int)replay->size() : o.fixed_cycles;
+    std::vector<int> sched;
+    hipLaunchKernelGGL(k2_init_iterate, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, x, l0.N, bc);
+    LAUNCHCHK();
+    int cycles = 0, status = DMGS_OK;
+    double r0 = 0.0, rel = 0.0;
+    TRY(resid2<HARM>(P, x, b, 0, st));
+    do {
+        if (!fixed) {
+            TRY(read_norms(P, st));
+            r0 = std::sqrt(P->hnorm[0]);
+            if (!std::isfinite(r0)) { set_error("non-finite right-hand side"); status = DMGS_ERR_NONFINITE; break; }
+            if (r0 == 0.0) break;
+        }
+        for (cycles = 1; !(fixed && nfix == 0); cycles++) {
+            TRY(vcycle2<HARM>(P, 0, x, b, order, false, st));
+            sched.push_back(1);
+            if (fixed) {
+                if (cycles == nfix) break;
+                continue;
+            }
+            TRY(resid2<HARM>(P, x, b, 1, st));
+            TRY(read_norms(P, st));
+            rel = std::sqrt(P->hnorm[1]) / r0;
+            if (!std::isfinite(rel)) { set_error("non-finite residual after %d cycles", cycles); status = DMGS_ERR_NONFINITE; break; }
+            if (rel <= o.rtol) break;
+            if (cycles >= o.max_cycles) { set_error("not converged after %d cycles (rel %.3e)", cycles, rel); status = DMGS_ERR_NOT_CONVERGED; break; }
+        }
+        if (fixed && nfix == 0) cycles = 0;
+        if (fixed && info) {
+            TRY(resid2<HARM>(P, x, b, 1, st));
+            TRY(read_norms(P, st));
+            r0 = std::sqrt(P->hnorm[0]);
+            rel = std::sqrt(P->hnorm[1]) / (r0 > 0.0 ? r0 : 1.0);
+        }
+    } while (false);
+    if (record && !fixed) {
+        P->fwd_recorded = status == DMGS_OK || status == DMGS_ERR_NOT_CONVERGED;
+        P->fwd_schedule = sched;
+    }
+    if (info) {
+        info->cycles = cycles;
+        info->vcycles = cycles;
+        info->rel_residual = rel;
+        info->status = status;
+    }
+    return status;
+}
+
 // Solve A x = b on the finest level from x = 0 (interior) / bc (boundary).
 // order 0: red-first cycles (S); order 1: black-first cycles (S^T).
 // replay: run exactly this V-cycle schedule (float64 plans: one entry per
@@ -832,6 +965,9 @@ int read_norms(dmgs_plan P, hipStream_t st) {
 // P->fwd_schedule.
 int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_info* info, hipStream_t st,
           const std::vector<int>* replay = nullptr, bool record = false) {
+    if (is2d(P))
+        return harmonic(P) ? solve2d<true>(P, b, x, bc, order, info, st, replay, record)
+                           : solve2d<false>(P, b, x, bc, order, info, st, replay, record);
     const dmgs_options& o = P->opt;
     const Level& l0 = P->lev[0];
     const bool fixed = o.fixed_cycles > 0 || replay;
@@ -1005,7 +1141,17 @@ int build_hierarchy(dmgs_plan P, hipStream_t st, const double* logD = nullptr, c
     Level& l0 = P->lev[0];
     *P->hflag = 0;
     HIPCHK(hipMemsetAsync(P->dflag, 0, sizeof(int), st));
-    if (logD) {
+    if (is2d(P)) {
+        if (logD) {
+            TIMED(P, 0, DMGS_K_COEF, 32.0 * l0.nv, st,
+                  hipLaunchKernelGGL(k2_exp_validate, dim3(grid_for(l0.nv, 4096)), dim3(kBlock), 0, st, logD, logmu,
+                                     l0.D64, l0.mu64, l0.N, P->dflag));
+        } else {
+            TIMED(P, 0, DMGS_K_COEF, 16.0 * l0.nv, st,
+                  hipLaunchKernelGGL(k2_validate, dim3(grid_for(l0.nv, 4096)), dim3(kBlock), 0, st,
+                                     (const double*)l0.D64, (const double*)l0.mu64, l0.N, P->dflag));
+        }
+    } else if (logD) {
         TIMED(P, 0, DMGS_K_COEF, 32.0 * l0.nv, st,
               hipLaunchKernelGGL(k_exp_validate, dim3(grid_for(l0.nv, 4096)), dim3(kBlock), 0, st, logD, logmu, l0.D64,
                                  l0.mu64, l0.N, P->dflag));
@@ -1021,17 +1167,21 @@ int build_hierarchy(dmgs_plan P, hipStream_t st, const double* logD = nullptr, c
     for (int k = 1; k < P->L; k++) {
         const Level& f = P->lev[k - 1];
         Level& c = P->lev[k];
-        hipLaunchKernelGGL(k_coarsen_coef, dim3(vertex_grid(c.nv)), dim3(kBlock), 0, st, (const double*)f.D64,
-                           (const double*)f.mu64, c.D64, c.mu64, f.N);
+        if (is2d(P))
+            hipLaunchKernelGGL(k2_coarsen_coef, dim3(vertex_grid(c.nv)), dim3(kBlock), 0, st, (const double*)f.D64,
+                               (const double*)f.mu64, c.D64, c.mu64, f.N);
+        else
+            hipLaunchKernelGGL(k_coarsen_coef, dim3(vertex_grid(c.nv)), dim3(kBlock), 0, st, (const double*)f.D64,
+                               (const double*)f.mu64, c.D64, c.mu64, f.N);
         LAUNCHCHK();
     }
-    {
+    if (!is2d(P)) {
         const Level& c = P->lev[P->L - 1];
         hipLaunchKernelGGL(k_coarse_inverse, dim3(1), dim3(64), 0, st, (const double*)c.D64, (const double*)c.mu64, c.N,
                            c.stencil<double>(harmonic(P)), P->cinv);
         LAUNCHCHK();
     }
-    for (int k = 0; k < P->L; k++) {
+    for (int k = 0; k < P->L && !is2d(P); k++) {
         Level& l = P->lev[k];
         if (is_ir(P)) {
             hipLaunchKernelGGL(k_level_prep<float>, dim3(vertex_grid(l.nv)), dim3(kBlock), 0, st, (const double*)l.D64,
@@ -1055,6 +1205,7 @@ int build_hierarchy(dmgs_plan P, hipStream_t st, const double* logD = nullptr, c
 
 int debug_check(dmgs_plan P, int k, int fp32, bool need_coarse) {
     if (!P || !P->coef_set) { set_error("plan without coefficients"); return DMGS_ERR_INVALID; }
+    if (is2d(P)) { set_error("the diagnostic entry points take three-dimensional plans"); return DMGS_ERR_INVALID; }
     if (k < 0 || k >= P->L || (need_coarse && k >= P->L - 1)) { set_error("bad level %d", k); return DMGS_ERR_INVALID; }
     if (fp32 && !is_ir(P)) { set_error("float32 arrays need a DMGS_FP32_IN_FP64 plan"); return DMGS_ERR_INVALID; }
     if (hipSetDevice(P->device) != hipSuccess) { set_error("hipSetDevice failed"); return DMGS_ERR_HIP; }
@@ -1123,6 +1274,8 @@ void dmgs_default_options(int32_t n, dmgs_options* o) {
     o->rtol = 1e-10;
     o->ir_inner_cycles = 8;
     o->ir_adaptive = 1;
+    o->adjoint_schedule = 0;
+    o->ndim = 3;
 }
 
 size_t dmgs_workspace_bytes(const dmgs_options* o) {
@@ -1180,10 +1333,13 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
             if (st == DMGS_OK) st = dalloc(P, &l.t32, l.nv);
             if (k < s.L - 1 && st == DMGS_OK) st = dalloc(P, &l.r32, l.nv);
         } else {
-            if (st == DMGS_OK) st = dalloc(P, &l.w64, l.nv);
+            // two-dimensional cycles work in place and restrict the defect
+            // on the fly: no inverse diagonal and no scratch level buffer
+            const bool d3 = o->ndim != 2;
+            if (d3 && st == DMGS_OK) st = dalloc(P, &l.w64, l.nv);
             if (k > 0 && st == DMGS_OK) st = dalloc(P, &l.u64, l.nv);
             if (k > 0 && st == DMGS_OK) st = dalloc(P, &l.q64, l.nv);
-            if (st == DMGS_OK) st = dalloc(P, &l.t64, l.nv);
+            if (d3 && st == DMGS_OK) st = dalloc(P, &l.t64, l.nv);
         }
     }
     if (st == DMGS_OK) st = dalloc(P, &P->scratch64, P->lev[0].nv);
@@ -1220,7 +1376,7 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     // first level handled by the single-workgroup kernel (N <= 16 in float32,
     // N <= 8 in float64, all remaining levels within the LDS budget)
     P->small32 = P->small64 = -1;
-    for (int k = 1; k < P->L && st == DMGS_OK; k++) {
+    for (int k = 1; k < P->L && st == DMGS_OK && o->ndim != 2; k++) {
         int Ns[kSmallMaxLevels];
         int nl = P->L - k;
         if (nl > kSmallMaxLevels) continue;
@@ -1307,8 +1463,9 @@ int dmgs_jvp(dmgs_plan P, const double* rho, const double* dq, const double* dlo
     if (!rho || !drho) { set_error("NULL argument"); return DMGS_ERR_INVALID; }
     const Level& l0 = P->lev[0];
     TIMED(P, 0, DMGS_K_GRAD, 56.0 * l0.nv, st,
-          hipLaunchKernelGGL(k_tangent_rhs, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, rho, dq, dlogD, dlogmua,
-                             (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, harmonic(P), P->scratch64));
+          hipLaunchKernelGGL(is2d(P) ? k2_tangent_rhs : k_tangent_rhs, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, rho,
+                             dq, dlogD, dlogmua, (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2,
+                             harmonic(P), P->scratch64));
     int s = solve(P, P->scratch64, drho, 0.0, 0, info, st);
     return end_call(P, s, info, st);
 }
@@ -1327,7 +1484,7 @@ int dmgs_vjp(dmgs_plan P, const double* rho, const double* rhobar, double* qbar,
     if ((s == DMGS_OK || s == DMGS_ERR_NOT_CONVERGED) && (logD_bar || logmua_bar)) {
         const Level& l0 = P->lev[0];
         TIMED(P, 0, DMGS_K_GRAD, 48.0 * l0.nv, st,
-              hipLaunchKernelGGL(k_coef_grads, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, rho, (const double*)qbar,
+              hipLaunchKernelGGL(is2d(P) ? k2_coef_grads : k_coef_grads, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, rho, (const double*)qbar,
                                  (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, harmonic(P), logD_bar,
                                  logmua_bar));
     }
@@ -1451,7 +1608,7 @@ int dmgs_forward_vjp(dmgs_plan P, const double* q, const double* rhobar, double*
     if (ok_f && ok_a && (logD_bar || logmua_bar)) {
         const Level& l0 = P->lev[0];
         TIMED(P, 0, DMGS_K_GRAD, 48.0 * l0.nv, st,
-              hipLaunchKernelGGL(k_coef_grads, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, (const double*)rho,
+              hipLaunchKernelGGL(is2d(P) ? k2_coef_grads : k_coef_grads, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, (const double*)rho,
                                  (const double*)qbar, (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2,
                                  harmonic(P), logD_bar, logmua_bar));
     }

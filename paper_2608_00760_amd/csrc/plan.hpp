@@ -8,7 +8,7 @@
 
 namespace dmgs {
 
-constexpr int kMaxLevels = 12;
+constexpr int kMaxLevels = 16;
 constexpr int kMaxPartials = 2048;   // blocks of the first reduction stage
 
 struct Level {

@@ -1,7 +1,8 @@
 """Python face of the C ABI: a Plan holding the resident level hierarchy.
 
 Tensors are torch float64 (float32 for the float32 diagnostic passes) CUDA
-tensors of shape (N+1, N+1, N+1), C-contiguous, on the plan's device.  Every
+tensors of shape (N+1, N+1, N+1) (two-dimensional plans: (N+1, N+1)),
+C-contiguous, on the plan's device.  Every
 array argument is checked on the host (shape, dtype, device, layout) before
 anything is launched; PyTorch only supplies device memory and the stream.
 """
@@ -33,6 +34,7 @@ class Options:
     ir_adaptive: bool = True          # later steps run the V-cycles the observed contraction predicts
     smoother: str = "rbgs"            # "rbgs" (red-black Gauss-Seidel) | "wjacobi" (weighted Jacobi, 6/7)
     adjoint_schedule: bool = False    # pull-back repeats the last forward solve's V-cycle schedule
+    ndim: int = 3                     # 3: (N+1)^3 grids, 7-point operator; 2: (N+1)^2 grids, 5-point operator
 
     def to_c(self):
         o = _abi.default_options(self.N)
@@ -47,6 +49,7 @@ class Options:
         o.ir_adaptive = 1 if self.ir_adaptive else 0
         o.smoother = _SMOOTHER[self.smoother]
         o.adjoint_schedule = 1 if self.adjoint_schedule else 0
+        o.ndim = int(self.ndim)
         return o
 
 
@@ -106,8 +109,7 @@ class Plan:
 
     # ---- argument checks ------------------------------------------------------------
     def _shape(self, k=0):
-        n = self.level_N[k] + 1
-        return (n, n, n)
+        return (self.level_N[k] + 1,) * self.opts.ndim
 
     def _arr(self, t, name, k=0, dtype=torch.float64, optional=False):
         if t is None:

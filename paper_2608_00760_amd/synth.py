@@ -173,18 +173,21 @@ def serving_stream(nreq=512, sizes=(64, 96, 128, 192), seed=4999, rate=None):
 # a per-request seeded torch generator; same recipes as above, a different
 # random stream).
 
-def grf_torch(N, gen, device, slope=-3.0):
+def grf_torch(N, gen, device, slope=-3.0, ndim=3):
     import torch
     n = N + 1
-    w = torch.randn((n, n, n), generator=gen, device=device, dtype=torch.float64)
+    w = torch.randn((n,) * ndim, generator=gen, device=device, dtype=torch.float64)
     W = torch.fft.rfftn(w)
     kx = torch.fft.fftfreq(n, device=device, dtype=torch.float64) * n
     kz = torch.fft.rfftfreq(n, device=device, dtype=torch.float64) * n
-    k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
-    k2[0, 0, 0] = 1.0
+    if ndim == 3:
+        k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
+    else:
+        k2 = kx[:, None] ** 2 + kz[None, :] ** 2
+    k2.view(-1)[0] = 1.0
     amp = k2 ** (slope / 4.0)
-    amp[0, 0, 0] = 0.0
-    f = torch.fft.irfftn(W * amp, s=(n, n, n))
+    amp.view(-1)[0] = 0.0
+    f = torch.fft.irfftn(W * amp, s=(n,) * ndim)
     f = f - f.mean()
     f = f / f.std(correction=0)
     return f.contiguous()
@@ -213,6 +216,7 @@ def zero_boundary_torch(f):
     f[-1] = 0
     f[:, 0] = 0
     f[:, -1] = 0
-    f[:, :, 0] = 0
-    f[:, :, -1] = 0
+    if f.dim() == 3:
+        f[:, :, 0] = 0
+        f[:, :, -1] = 0
     return f

@@ -65,17 +65,42 @@ def test_default_options_and_footprint(abi):
 
 def test_options_layout_matches_the_header(abi):
     """dmgs_default_options clears sizeof(dmgs_options) bytes and then sets the
-    defaults; in a buffer pre-filled with a sentinel, the last byte it writes
-    (the zero `reserved` field) is the last byte of the binding's struct."""
+    defaults; in a buffer pre-filled with a sentinel, it writes up to the last
+    byte of the binding's struct (the zero high bytes of `ndim` = 3) and no
+    further."""
     size = C.sizeof(abi.Options)
     buf = (C.c_uint8 * (size + 64))(*([0xAB] * (size + 64)))
     abi.lib().dmgs_default_options(32, C.cast(buf, C.POINTER(abi.Options)))
     written = [i for i in range(size + 64) if buf[i] != 0xAB]
-    assert written[-1] + 1 == size
+    assert written[-1] + 1 <= size and all(buf[i] == 0 for i in range(written[-1] + 1, size))
+    assert buf[size] == 0xAB
     o = abi.Options.from_buffer(buf)
-    assert o.adjoint_schedule == 0 and o.ir_adaptive == 1 and o.ir_inner_cycles == 8
+    assert o.adjoint_schedule == 0 and o.ir_adaptive == 1 and o.ir_inner_cycles == 8 and o.ndim == 3
     o.adjoint_schedule = 2
     assert abi.lib().dmgs_workspace_bytes(C.byref(o)) == 0
+
+
+def test_two_dimensional_options(abi):
+    lib = abi.lib()
+    o = abi.default_options(8192)
+    o.ndim = 2
+    nv = 8193 ** 2
+    b = lib.dmgs_workspace_bytes(C.byref(o))
+    assert 4 * nv * 8 <= b < 6 * nv * 8           # D, mu, scratch (+ the coarse levels)
+    for field, value in (("ndim", 4), ("precision", abi.DMGS_FP32_IN_FP64), ("smoother", abi.DMGS_WJACOBI)):
+        ob = abi.default_options(64)
+        ob.ndim = 2
+        setattr(ob, field, value)
+        assert lib.dmgs_workspace_bytes(C.byref(ob)) == 0, field
+    for bad in (32768, 20, 1):
+        ob = abi.default_options(bad)
+        ob.ndim = 2
+        assert lib.dmgs_workspace_bytes(C.byref(ob)) == 0, bad
+    ob = abi.default_options(2048)
+    assert lib.dmgs_workspace_bytes(C.byref(ob)) == 0   # 3D stops at 1024
+    ob.ndim = 2
+    ob.n[2] = 7                                        # ignored in 2D
+    assert lib.dmgs_workspace_bytes(C.byref(ob)) > 0
 
 
 def test_status_strings(abi):
