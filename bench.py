@@ -136,23 +136,27 @@ def paper_sweep(args):
     on the device (the timing of a fixed cycle count does not depend on their
     values).  One JSON line per size and precision."""
     import torch
+    from paper_2608_00760_amd import synth
     from paper_2608_00760_amd.solver import Options, Plan
     dev = torch.device("cuda:0")
-    sizes = [int(x) for x in args.sweep_sizes.split(",")]
+    nd = args.sweep_ndim
+    sizes = [int(x) for x in (args.sweep_sizes or
+                              ("768,1024,1536,2048,3072,4096,6144,8192" if nd == 2 else
+                               "96,128,192,256,384,512,768")).split(",")]
     for N in sizes:
-        for prec in ("fp64", "fp32-in-fp64"):
+        for prec in (("fp64",) if nd == 2 else ("fp64", "fp32-in-fp64")):
             torch.cuda.empty_cache()
             torch.cuda.reset_peak_memory_stats()
             g = torch.Generator(device=dev)
             g.manual_seed(7000 + N)
-            shape = (N + 1,) * 3
+            shape = (N + 1,) * nd
             rnd = lambda: torch.randn(shape, generator=g, device=dev, dtype=torch.float64)
             logD, logmu = 0.5 * rnd(), -3.0 + 0.5 * rnd()
             q, w, dq, dd, dm = rnd(), rnd(), rnd(), rnd(), rnd()
             for t in (q, w, dq, dm):   # boundary entries are ignored; keep them 0
-                t[0] = 0; t[-1] = 0; t[:, 0] = 0; t[:, -1] = 0; t[:, :, 0] = 0; t[:, :, -1] = 0
+                synth.zero_boundary_torch(t)
             # 15 V-cycles: float64 cycles, or 15 refinement steps of one float32 cycle
-            P = Plan(Options(N, precision=prec, fixed_cycles=15, ir_inner_cycles=1, ir_adaptive=False))
+            P = Plan(Options(N, precision=prec, fixed_cycles=15, ir_inner_cycles=1, ir_adaptive=False, ndim=nd))
             P.set_log_coefficients(logD, logmu)
             rho, qbar, drho = torch.empty_like(q), torch.empty_like(q), torch.empty_like(q)
             gD, gmu = torch.empty_like(q), torch.empty_like(q)
@@ -176,9 +180,23 @@ def paper_sweep(args):
                 res[name + "_ms_min"] = ts[0]
             torch.cuda.synchronize()
             peak = torch.cuda.max_memory_allocated() + P.bytes
-            print(json.dumps({"sweep": "fixed 15 V-cycles", "N": N, "points": (N + 1) ** 3,
-                              "log2_points": round(math.log2((N + 1) ** 3), 2), "precision": prec,
-                              "reps": args.sweep_reps, **res, "peak_device_GB": peak / 1e9}), flush=True)
+            # one more solve with every finest-level launch timed: the
+            # smoothing kernel's achieved bandwidth against the HBM peak
+            P.timing(True, stride=1)
+            ops["solve"]()
+            torch.cuda.synchronize()
+            per_class = P.timing_read()
+            sm = per_class["smooth"]
+            P.timing(False)
+            gbps = sm["bytes"] / (sm["ms"] * 1e-3) / 1e9 if sm["ms"] > 0 else None
+            print(json.dumps({"sweep": "fixed 15 V-cycles", "ndim": nd, "N": N, "points": (N + 1) ** nd,
+                              "log2_points": round(math.log2((N + 1) ** nd), 2), "precision": prec,
+                              "reps": args.sweep_reps, **res, "peak_device_GB": peak / 1e9,
+                              "smooth_kernel": {"launches": sm["launches"],
+                                                "avg_us": 1e3 * sm["ms"] / max(sm["launches"], 1),
+                                                "GBps": gbps, "frac": gbps / HBM_PEAK_GBPS if gbps else None},
+                              "finest_level_ms_per_solve": {k: v["ms"] for k, v in per_class.items() if v["launches"]}}),
+                  flush=True)
             P.close()
             del logD, logmu, q, w, dq, dd, dm, rho, qbar, drho, gD, gmu
 
@@ -198,7 +216,10 @@ def main():
                     help="red-black Gauss-Seidel (the method's) or weighted Jacobi (the alternative)")
     ap.add_argument("--paper-sweep", action="store_true",
                     help="only the fixed-15-cycle Solve/JVP/VJP timing sweep over --sweep-sizes (one JSON line each)")
-    ap.add_argument("--sweep-sizes", default="96,128,192,256,384,512,768")
+    ap.add_argument("--sweep-sizes", default=None,
+                    help="comma-separated N (default 96..768 in 3D, 768..8192 in 2D)")
+    ap.add_argument("--sweep-ndim", type=int, default=3, choices=[2, 3],
+                    help="the sweep's grids: 3D (7-point) or 2D (5-point, the paper's comparison setting)")
     ap.add_argument("--sweep-reps", type=int, default=20)
     ap.add_argument("--sequential", action="store_true",
                     help="run the forward solve and the VJP one after the other (default: concurrently)")

@@ -133,8 +133,8 @@ size_t footprint(const dmgs_options* o) {
     bool ir = o->precision == DMGS_FP32_IN_FP64;
     size_t b = 0;
     for (int k = 0; k < s.L; k++) {
-        if (o->ndim == 2) {   // D64, mu64, (u64, q64)
-            b += (k > 0 ? 4 : 2) * s.nv[k] * sizeof(double);
+        if (o->ndim == 2) {   // D64, mu64, (u64, q64), t64
+            b += (k > 0 ? 5 : 3) * s.nv[k] * sizeof(double);
             continue;
         }
         b += 2 * s.nv[k] * sizeof(double);                            // D64, mu64
@@ -855,35 +855,91 @@ int half_sweep2(dmgs_plan P, int k, double* u, const double* q, int colour, hipS
     return DMGS_OK;
 }
 
-// One V-cycle on level k of a two-dimensional plan, in place on u (from 0
-// when zero); order 1 is the transposed cycle.
+// count red-black sweeps on level k (first colour `first`): pairs of sweeps
+// as out-of-place passes from *cur to *other (swapping them) on levels with
+// N >= cfg_2d_sweep2_min, the rest as in-place half-sweeps on *cur.  ec:
+// first add the prolongated coarse correction I ec to *cur (fused into the
+// first pass when there is one).
 template <bool HARM>
-int vcycle2(dmgs_plan P, int k, double* u, const double* q, int order, bool zero, hipStream_t st) {
+int sweeps2(dmgs_plan P, int k, double** cur, double** other, const double* q, int count, int first, hipStream_t st,
+            const double* ec = nullptr) {
     const Level& l = P->lev[k];
-    if (zero) TRY(fill<double>(u, l.nv, 0.0, st));
+    int i = 0;
+    const bool pass = l.N >= P->cfg_2d_sweep2_min;
+    if (ec && !(pass && count >= 2)) {
+        const Level& c = P->lev[k + 1];
+        TIMED(P, k, DMGS_K_PROLONG, 16.0 * l.nv + 8.0 * c.nv, st,
+              hipLaunchKernelGGL(k2_prolong_add, dim3(vertex_grid(l.nv)), dim3(kBlock), 0, st, ec, *cur, l.N));
+        ec = nullptr;
+    }
+    if (pass) {
+        const int ntiles = (l.N - 1 + kTile2 - 1) / kTile2;
+        // about 4096 waves on the largest grids; chunks of 32..512 rows, a
+        // multiple of 8 (the kernel's row ring); chunk 0 takes 2 more rows
+        int chunk = (int)std::min<int64_t>(512, std::max<int64_t>(32, ((int64_t)(l.N - 1) * ntiles / 4096 + 7) / 8 * 8));
+        if (P->cfg_2d_chunk > 0) chunk = P->cfg_2d_chunk;
+        const int nchunks = std::max(1, (l.N - 3 + chunk - 1) / chunk);
+        const unsigned blocks = (unsigned)((ntiles * nchunks + 3) / 4);
+        for (; count - i >= 2; i += 2) {
+            // reads u, q, D, mua (and the coarse correction); writes u
+            if (ec) {
+                TIMED(P, k, DMGS_K_SMOOTH, 40.0 * l.nv + 8.0 * P->lev[k + 1].nv, st,
+                      hipLaunchKernelGGL((k2_sweep2<HARM, true>), dim3(blocks), dim3(256), 0, st, (const double*)*cur,
+                                         *other, q, (const double*)l.D64, (const double*)l.mu64, ec, l.N,
+                                         l.stencil<double>(HARM), first, chunk, ntiles, nchunks));
+                ec = nullptr;
+            } else {
+                TIMED(P, k, DMGS_K_SMOOTH, 40.0 * l.nv, st,
+                      hipLaunchKernelGGL((k2_sweep2<HARM, false>), dim3(blocks), dim3(256), 0, st, (const double*)*cur,
+                                         *other, q, (const double*)l.D64, (const double*)l.mu64, (const double*)nullptr,
+                                         l.N, l.stencil<double>(HARM), first, chunk, ntiles, nchunks));
+            }
+            std::swap(*cur, *other);
+        }
+    }
+    for (; i < count; i++) {
+        TRY(half_sweep2<HARM>(P, k, *cur, q, first, st));
+        TRY(half_sweep2<HARM>(P, k, *cur, q, 1 - first, st));
+    }
+    return DMGS_OK;
+}
+
+// One V-cycle on level k of a two-dimensional plan with iterate *cur (from 0
+// when zero; the level's other buffer is *other, whose boundary holds the
+// same values); order 1 is the transposed cycle.  On return *cur holds the
+// result.
+template <bool HARM>
+int vcycle2(dmgs_plan P, int k, double** cur, double** other, const double* q, int order, bool zero, hipStream_t st) {
+    const Level& l = P->lev[k];
+    if (zero) TRY(fill<double>(*cur, l.nv, 0.0, st));
     if (k == P->L - 1) {
-        hipLaunchKernelGGL(k2_exact<HARM>, dim3(1), dim3(64), 0, st, q, u, (const double*)l.D64, (const double*)l.mu64,
-                           l.N, l.stencil<double>(HARM));
+        hipLaunchKernelGGL(k2_exact<HARM>, dim3(1), dim3(64), 0, st, q, *cur, (const double*)l.D64,
+                           (const double*)l.mu64, l.N, l.stencil<double>(HARM));
         LAUNCHCHK();
         return DMGS_OK;
     }
     const int first = order ? 1 : 0;
-    for (int i = 0; i < nu_pre_of(P, order); i++) {
-        TRY(half_sweep2<HARM>(P, k, u, q, first, st));
-        TRY(half_sweep2<HARM>(P, k, u, q, 1 - first, st));
-    }
+    TRY(sweeps2<HARM>(P, k, cur, other, q, nu_pre_of(P, order), first, st));
     const Level& c = P->lev[k + 1];
-    TIMED(P, k, DMGS_K_DEFECT_RESTRICT, 32.0 * l.nv + 8.0 * c.nv, st,
-          hipLaunchKernelGGL(k2_defect_restrict<HARM>, dim3(vertex_grid(c.nv)), dim3(kBlock), 0, st, (const double*)u, q,
-                             (const double*)l.D64, (const double*)l.mu64, l.N, l.stencil<double>(HARM), c.q64));
-    TRY(vcycle2<HARM>(P, k + 1, c.u64, c.q64, order, true, st));
-    TIMED(P, k, DMGS_K_PROLONG, 16.0 * l.nv + 8.0 * c.nv, st,
-          hipLaunchKernelGGL(k2_prolong_add, dim3(vertex_grid(l.nv)), dim3(kBlock), 0, st, (const double*)c.u64, u, l.N));
-    for (int i = 0; i < nu_post_of(P, order); i++) {
-        TRY(half_sweep2<HARM>(P, k, u, q, first, st));
-        TRY(half_sweep2<HARM>(P, k, u, q, 1 - first, st));
+    if (l.N >= P->cfg_2d_sweep2_min) {
+        // row-streaming form: coarse rows in chunks of cx (a multiple of 4)
+        const int ntiles = (c.N - 1 + kTileR - 1) / kTileR;
+        const int cx = (int)std::min<int64_t>(256, std::max<int64_t>(16, ((int64_t)(c.N - 1) * ntiles / 4096 + 3) / 4 * 4));
+        const int nchunks = (c.N - 1 + cx - 1) / cx;
+        TIMED(P, k, DMGS_K_DEFECT_RESTRICT, 32.0 * l.nv + 8.0 * c.nv, st,
+              hipLaunchKernelGGL(k2_defect_restrict_rows<HARM>, dim3((ntiles * nchunks + 3) / 4), dim3(256), 0, st,
+                                 (const double*)*cur, q, (const double*)l.D64, (const double*)l.mu64, l.N,
+                                 l.stencil<double>(HARM), c.q64, cx, ntiles, nchunks));
+    } else {
+        TIMED(P, k, DMGS_K_DEFECT_RESTRICT, 32.0 * l.nv + 8.0 * c.nv, st,
+              hipLaunchKernelGGL(k2_defect_restrict<HARM>, dim3(vertex_grid(c.nv)), dim3(kBlock), 0, st,
+                                 (const double*)*cur, q, (const double*)l.D64, (const double*)l.mu64, l.N,
+                                 l.stencil<double>(HARM), c.q64));
     }
-    return DMGS_OK;
+    double* ccur = c.u64;
+    double* coth = c.t64;
+    TRY(vcycle2<HARM>(P, k + 1, &ccur, &coth, c.q64, order, true, st));
+    return sweeps2<HARM>(P, k, cur, other, q, nu_post_of(P, order), first, st, ccur);
 }
 
 // ||b - A x||^2 of the finest level into the host norm slot `slot`.
@@ -910,7 +966,13 @@ int solve2d(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_
     const bool fixed = o.fixed_cycles > 0 || replay;
     const int nfix = replay ? (int)replay->size() : o.fixed_cycles;
     std::vector<int> sched;
+    // the iterate alternates between x and the level's other buffer; both
+    // hold the boundary value
+    double* cur = x;
+    double* oth = l0.t64;
     hipLaunchKernelGGL(k2_init_iterate, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, x, l0.N, bc);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k2_init_iterate, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, oth, l0.N, bc);
     LAUNCHCHK();
     int cycles = 0, status = DMGS_OK;
     double r0 = 0.0, rel = 0.0;
@@ -923,13 +985,13 @@ int solve2d(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_
             if (r0 == 0.0) break;
         }
         for (cycles = 1; !(fixed && nfix == 0); cycles++) {
-            TRY(vcycle2<HARM>(P, 0, x, b, order, false, st));
+            TRY(vcycle2<HARM>(P, 0, &cur, &oth, b, order, false, st));
             sched.push_back(1);
             if (fixed) {
                 if (cycles == nfix) break;
                 continue;
             }
-            TRY(resid2<HARM>(P, x, b, 1, st));
+            TRY(resid2<HARM>(P, cur, b, 1, st));
             TRY(read_norms(P, st));
             rel = std::sqrt(P->hnorm[1]) / r0;
             if (!std::isfinite(rel)) { set_error("non-finite residual after %d cycles", cycles); status = DMGS_ERR_NONFINITE; break; }
@@ -938,12 +1000,13 @@ int solve2d(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_
         }
         if (fixed && nfix == 0) cycles = 0;
         if (fixed && info) {
-            TRY(resid2<HARM>(P, x, b, 1, st));
+            TRY(resid2<HARM>(P, cur, b, 1, st));
             TRY(read_norms(P, st));
             r0 = std::sqrt(P->hnorm[0]);
             rel = std::sqrt(P->hnorm[1]) / (r0 > 0.0 ? r0 : 1.0);
         }
     } while (false);
+    if (cur != x) HIPCHK(hipMemcpyAsync(x, cur, l0.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (record && !fixed) {
         P->fwd_recorded = status == DMGS_OK || status == DMGS_ERR_NOT_CONVERGED;
         P->fwd_schedule = sched;
@@ -1333,13 +1396,12 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
             if (st == DMGS_OK) st = dalloc(P, &l.t32, l.nv);
             if (k < s.L - 1 && st == DMGS_OK) st = dalloc(P, &l.r32, l.nv);
         } else {
-            // two-dimensional cycles work in place and restrict the defect
-            // on the fly: no inverse diagonal and no scratch level buffer
-            const bool d3 = o->ndim != 2;
-            if (d3 && st == DMGS_OK) st = dalloc(P, &l.w64, l.nv);
+            // two-dimensional cycles take no inverse diagonal (t64 is the
+            // partner buffer of the out-of-place passes)
+            if (o->ndim != 2 && st == DMGS_OK) st = dalloc(P, &l.w64, l.nv);
             if (k > 0 && st == DMGS_OK) st = dalloc(P, &l.u64, l.nv);
             if (k > 0 && st == DMGS_OK) st = dalloc(P, &l.q64, l.nv);
-            if (d3 && st == DMGS_OK) st = dalloc(P, &l.t64, l.nv);
+            if (st == DMGS_OK) st = dalloc(P, &l.t64, l.nv);
         }
     }
     if (st == DMGS_OK) st = dalloc(P, &P->scratch64, P->lev[0].nv);
@@ -1412,6 +1474,8 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     if (const char* e = std::getenv("DMGS_SWEEP2_WGS_COARSE")) P->cfg_sweep2_wgs_coarse = std::max(16, std::atoi(e));
     if (const char* e = std::getenv("DMGS_SWEEP_CFG")) P->cfg_sweep = std::min(2, std::max(0, std::atoi(e)));
     if (const char* e = std::getenv("DMGS_FUSE_MIN")) P->cfg_fuse_min = std::max(8, std::atoi(e));
+    if (const char* e = std::getenv("DMGS_2D_SWEEP2_MIN")) P->cfg_2d_sweep2_min = std::max(4, std::atoi(e));
+    if (const char* e = std::getenv("DMGS_2D_CHUNK")) P->cfg_2d_chunk = std::max(8, std::atoi(e) / 8 * 8);
     if (st != DMGS_OK) {
         free_plan(P);
         return st;
@@ -1511,6 +1575,8 @@ int make_twin(dmgs_plan P) {
     T->cfg_block_max = P->cfg_block_max;
     T->cfg_dr_wgs = P->cfg_dr_wgs;
     T->cfg_defect = P->cfg_defect;
+    T->cfg_2d_sweep2_min = P->cfg_2d_sweep2_min;
+    T->cfg_2d_chunk = P->cfg_2d_chunk;
     T->small32 = P->small32;
     T->small64 = P->small64;
     T->cinv = P->cinv;

@@ -305,3 +305,235 @@ __global__ void k2_coef_grads(const double* __restrict__ rho, const double* __re
 }
 
 }  // namespace dmgs
+
+namespace dmgs {
+
+// ---------------------------------------------------------------------------
+// Two red-black sweeps per pass, out of place (u_in -> u_out).
+//
+// One wave per tile of kTile2 interior columns [ts, ts + kTile2); lane t
+// holds the column pair (yb + 2t, yb + 2t + 1), yb = ts - kRing2, so a wave
+// covers the tile and a ring of kRing2 = 4 columns on each side.  A chunk of
+// rows [xa, xb) is marched one row per step; the four colour updates of the
+// two sweeps run as a pipeline: at step s, stage j (j = 1..4) updates row
+// s - j + 1, which then sees its neighbours exactly as the sequential order
+// leaves them (a stage never changes the other colour).  Stage j is applied
+// on the tile plus a ring of 4 - j columns (neighbouring tiles recompute
+// these), and its rows reach 4 - j beyond the chunk, so the output rows
+// [xa, xb) depend only on rows [xa - 4, xb + 4) of u_in.  Each lane keeps
+// eight rows of its two columns (u, D, q, mua) in a register ring indexed by
+// row & 7 (the march is unrolled by 8, so ring slots are compile-time);
+// in-row neighbours of the other column come from the adjacent lane by a
+// shuffle.  A row is loaded three steps before the first stage reads it.
+// Only interior vertices of the tile are written; u_out's boundary keeps
+// its values.  Rows: chunk 0 is [1, 3 + chunk), chunk c > 0 is
+// [3 + c chunk, 3 + (c + 1) chunk), cut at N.
+constexpr int kTile2 = 120, kRing2 = 4;
+
+//
+// PROLONG (post-smoothing): the pass smooths u_in + I ec (Sec. 2.3.3,
+// bilinear, ec on the next coarser level with a zero boundary); the
+// correction of a row is added at the step before its first use, from
+// coarse values loaded with the row.
+template <bool HARM, bool PROLONG>
+__global__ __launch_bounds__(256) void k2_sweep2(const double* __restrict__ uin, double* __restrict__ uout,
+                                                 const double* __restrict__ q, const double* __restrict__ D,
+                                                 const double* __restrict__ mu, const double* __restrict__ ec, int N,
+                                                 Stencil<double> st, int first_colour, int chunk, int ntiles,
+                                                 int nchunks) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int tile = wave % ntiles, ch = wave / ntiles;
+    if (ch >= nchunks) return;   // whole waves exit
+    const int n = N + 1;
+    const int ts = 1 + tile * kTile2;
+    const int yb = ts - kRing2;
+    const int ya = yb + 2 * lane, yo = ya + 1;   // this lane's columns
+    // chunk 0 holds rows [1, 3 + chunk), chunk c > 0 rows [3 + c chunk,
+    // 3 + (c + 1) chunk): with chunk a multiple of 8 every march starts at
+    // a multiple of 8, which the unrolled ring needs
+    const int xa = ch == 0 ? 1 : 3 + ch * chunk, xb = min(N, 3 + (ch + 1) * chunk);
+    // rows and columns outside the grid are read clamped to its edge: no
+    // update that is kept reads them (an updated interior vertex has all its
+    // neighbours in the grid), and unconditional loads let the compiler wait
+    // for each row's loads alone
+    const int yca = min(max(ya, 0), N), yco = min(max(yo, 0), N);
+
+    double ua[8], uo[8], da[8], dd[8], qa[8], qo[8], ma[8], mo[8];
+    // coarse values of the correction: rows X0 = r >> 1 and X1 = (r + 1) >> 1,
+    // columns C0 = ya >> 1 and C0 + 1
+    double e00[8], e01[8], e10[8], e11[8];
+    const int Nc = N >> 1, nc = Nc + 1;
+    // (clamped separately: on the left edge the lane of columns (-1, 0) must
+    // take column 0 of ec, which is 0, for y = 0)
+    const int C0 = min(max(ya >> 1, 0), Nc), C1 = min(max((ya >> 1) + 1, 0), Nc);
+    // 32-bit element offsets (a grid has at most 16385^2 < 2^32 vertices)
+    auto load_row = [&](int r, int sl) __attribute__((always_inline)) {
+        const uint32_t b = (uint32_t)min(max(r, 0), N) * (uint32_t)n;
+        ua[sl] = uin[b + yca];
+        uo[sl] = uin[b + yco];
+        da[sl] = D[b + yca];
+        dd[sl] = D[b + yco];
+        qa[sl] = q[b + yca];
+        qo[sl] = q[b + yco];
+        ma[sl] = mu[b + yca];
+        mo[sl] = mu[b + yco];
+        if (PROLONG) {
+            const int rc = min(max(r, 0), N);
+            const uint32_t b0 = (uint32_t)(rc >> 1) * (uint32_t)nc, b1 = (uint32_t)min((rc + 1) >> 1, Nc) * (uint32_t)nc;
+            e00[sl] = ec[b0 + C0];
+            e01[sl] = ec[b0 + C1];
+            e10[sl] = ec[b1 + C0];
+            e11[sl] = ec[b1 + C1];
+        }
+    };
+    // u += I ec on row r (the bilinear weights of k2_prolong_add; the
+    // boundary gets 0, as ec vanishes there)
+    auto correct_row = [&](int r, int sl) __attribute__((always_inline)) {
+        if (!PROLONG) return;
+        const bool rodd = r & 1;
+        const double c0 = rodd ? 0.5 * (e00[sl] + e10[sl]) : e00[sl];
+        const double c1 = rodd ? 0.5 * (e01[sl] + e11[sl]) : e01[sl];
+        const double cm = rodd ? 0.25 * (e00[sl] + e10[sl] + e01[sl] + e11[sl]) : 0.5 * (e00[sl] + e01[sl]);
+        // ya even: ya on C0, yo between C0 and C1; ya odd: the reverse
+        const bool aodd = ya & 1;
+        ua[sl] += aodd ? cm : c0;
+        uo[sl] += aodd ? c1 : cm;
+    };
+    // colour c on row r (slot sl, rows r -1 / r + 1 in slots sm / sp), on the
+    // tile plus a ring of `ring` columns
+    auto stage = [&](int r, int sl, int sm, int sp, int c, int ring) __attribute__((always_inline)) {
+        // the pair column of the colour (wave-uniform): odd -> yo, else ya;
+        // every ring entry is updated through value selects, so the ring
+        // stays in registers
+        const bool odd = (c - r - yb) & 1;
+        const double su = odd ? ua[sl] : uo[sl], sd = odd ? da[sl] : dd[sl];   // the pair's other column
+        const int src = odd ? min(lane + 1, kWave - 1) : max(lane - 1, 0);
+        const double un = __shfl(su, src, kWave), dn = __shfl(sd, src, kWave);   // the adjacent lane's
+        const double ul = odd ? su : un, ur = odd ? un : su;
+        const double dl = odd ? sd : dn, dr = odd ? dn : sd;
+        const double Di = odd ? dd[sl] : da[sl];
+        const double cxm = face<HARM>(Di, odd ? dd[sm] : da[sm], st), cxp = face<HARM>(Di, odd ? dd[sp] : da[sp], st);
+        const double cym = face<HARM>(Di, dl, st), cyp = face<HARM>(Di, dr, st);
+        const double um = odd ? uo[sm] : ua[sm], up = odd ? uo[sp] : ua[sp];
+        const double qi = odd ? qo[sl] : qa[sl], mi = odd ? mo[sl] : ma[sl];
+        const double v = (qi + cxm * um + cxp * up + cym * ul + cyp * ur) / (cxm + cxp + cym + cyp + mi);
+        const int y = odd ? yo : ya;
+        const bool act = r >= 1 && r <= N - 1 && y >= max(1, ts - ring) && y <= min(N - 1, ts + kTile2 - 1 + ring);
+        ua[sl] = (act && !odd) ? v : ua[sl];
+        uo[sl] = (act && odd) ? v : uo[sl];
+    };
+    const int c1 = first_colour, c2 = 1 - first_colour;
+    const int sb = (xa - 3) & ~7;   // first step, a multiple of 8 (chunk 0 starts a few harmless steps early)
+    const int se = xb + 3;          // one past the last step
+    // rows sb - 4 .. sb + 2 before the first step
+#pragma unroll
+    for (int k = -4; k <= 2; k++) load_row(sb + k, k & 7);
+#pragma unroll
+    for (int k = -4; k <= 0; k++) correct_row(sb + k, k & 7);
+    for (int s8 = sb; s8 < se; s8 += 8) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int s = s8 + k;
+            load_row(s + 3, (k + 3) & 7);
+            correct_row(s + 1, (k + 1) & 7);   // first read by stage 1 below
+            stage(s, k & 7, (k - 1) & 7, (k + 1) & 7, c1, 3);
+            stage(s - 1, (k - 1) & 7, (k - 2) & 7, k & 7, c2, 2);
+            stage(s - 2, (k - 2) & 7, (k - 3) & 7, (k - 1) & 7, c1, 1);
+            stage(s - 3, (k - 3) & 7, (k - 4) & 7, (k - 2) & 7, c2, 0);
+            const int r = s - 3;
+            if (r >= xa && r < xb) {
+                const uint32_t b = (uint32_t)r * (uint32_t)n;
+                const int sl = (k - 3) & 7;
+                if (ya >= ts && ya < ts + kTile2 && ya <= N - 1) uout[b + ya] = ua[sl];
+                if (yo >= ts && yo < ts + kTile2 && yo <= N - 1) uout[b + yo] = uo[sl];
+            }
+        }
+    }
+}
+
+}  // namespace dmgs
+
+namespace dmgs {
+
+// qc = R (q - A u) streamed along fine rows (Sec. 2.3.2 and Eq. (rest)).
+// One wave per tile of kTileR = 62 coarse columns [Ys, Ys + 62): lane t
+// holds the fine column pair (2Y, 2Y + 1) of coarse column Y = Ys - 1 + t
+// (lanes 0 and 63 are halo lanes).  Each fine defect is formed once; a
+// fine row gives the horizontal sums h_x(Y) = r(x, 2Y-1) + 2 r(x, 2Y) +
+// r(x, 2Y+1) (one shuffle), and coarse row X is (h_{2X-1} + 2 h_{2X} +
+// h_{2X+1}) / 16, the order in which k2_defect_restrict sums.  A chunk of
+// coarse rows [Xa, Xb) (Xa = 1 + c cx, cx a multiple of 4) marches fine
+// rows 2Xa - 2 ... 2Xb - 1 in steps of 8 with rows in a register ring
+// (row x in slot x & 7), each loaded three steps before the step that
+// forms its defect.  Only coarse interior vertices are written.
+constexpr int kTileR = 62;
+
+template <bool HARM>
+__global__ __launch_bounds__(256) void k2_defect_restrict_rows(const double* __restrict__ u, const double* __restrict__ q,
+                                                               const double* __restrict__ D,
+                                                               const double* __restrict__ mu, int Nf,
+                                                               Stencil<double> st, double* __restrict__ qc, int cx,
+                                                               int ntiles, int nchunks) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int tile = wave % ntiles, ch = wave / ntiles;
+    if (ch >= nchunks) return;   // whole waves exit
+    const int Nc = Nf / 2, nf = Nf + 1, nc = Nc + 1;
+    const int Ys = 1 + tile * kTileR;
+    const int Y = Ys - 1 + lane;
+    const int ye = 2 * Y, yo = ye + 1;                     // this lane's fine columns
+    const int yce = min(max(ye, 0), Nf), yco = min(max(yo, 0), Nf);   // clamped reads (kept defects never need them)
+    const int Xa = 1 + ch * cx, Xb = min(Nc, Xa + cx);
+    const bool wr = lane >= 1 && lane <= kTileR && Y <= Nc - 1;
+
+    double ue[8], uo[8], de[8], dd[8], qe[8], qo[8], me[8], mo[8];
+    auto load_row = [&](int x, int sl) __attribute__((always_inline)) {
+        const uint32_t b = (uint32_t)min(max(x, 0), Nf) * (uint32_t)nf;
+        ue[sl] = u[b + yce];
+        uo[sl] = u[b + yco];
+        de[sl] = D[b + yce];
+        dd[sl] = D[b + yco];
+        qe[sl] = q[b + yce];
+        qo[sl] = q[b + yco];
+        me[sl] = mu[b + yce];
+        mo[sl] = mu[b + yco];
+    };
+    // h_x for row x (slot sl; rows x -1 / x + 1 in slots sm / sp)
+    auto hsum = [&](int sl, int sm, int sp) __attribute__((always_inline)) {
+        const double uoL = __shfl_up(uo[sl], 1, kWave), doL = __shfl_up(dd[sl], 1, kWave);     // column 2Y - 1
+        const double ueR = __shfl_down(ue[sl], 1, kWave), deR = __shfl_down(de[sl], 1, kWave); // column 2Y + 2
+        const double Dei = de[sl], uei = ue[sl];
+        const double re = qe[sl] - (me[sl] * uei + face<HARM>(Dei, de[sm], st) * (uei - ue[sm]) +
+                                    face<HARM>(Dei, de[sp], st) * (uei - ue[sp]) + face<HARM>(Dei, doL, st) * (uei - uoL) +
+                                    face<HARM>(Dei, dd[sl], st) * (uei - uo[sl]));
+        const double Doi = dd[sl], uoi = uo[sl];
+        const double ro = qo[sl] - (mo[sl] * uoi + face<HARM>(Doi, dd[sm], st) * (uoi - uo[sm]) +
+                                    face<HARM>(Doi, dd[sp], st) * (uoi - uo[sp]) + face<HARM>(Doi, de[sl], st) * (uoi - uei) +
+                                    face<HARM>(Doi, deR, st) * (uoi - ueR));
+        const double roL = __shfl_up(ro, 1, kWave);   // r(x, 2Y - 1)
+        return roL + 2.0 * re + ro;
+    };
+    const int x0 = 2 * Xa - 2;            // a multiple of 8
+    const int xe = 2 * Xb;                // one past the last fine row, 2 Xb - 1
+#pragma unroll
+    for (int k = -1; k <= 2; k++) load_row(x0 + k, k & 7);
+    double carry = 0.0, hmid = 0.0;
+    for (int x8 = x0; x8 < xe; x8 += 8) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int x = x8 + k;
+            load_row(x + 3, (k + 3) & 7);
+            const double h = hsum(k & 7, (k - 1) & 7, (k + 1) & 7);
+            if ((k & 1) == 0) {
+                hmid = h;                 // x = 2X
+            } else {                      // x = 2X + 1 closes coarse row X
+                const int X = x >> 1;
+                if (wr && X >= Xa && X < Xb) qc[(uint32_t)X * (uint32_t)nc + Y] = (carry + 2.0 * hmid + h) * (1.0 / 16.0);
+                carry = h;
+            }
+        }
+    }
+}
+
+}  // namespace dmgs

@@ -76,6 +76,8 @@ struct dmgs_plan_s {
     int cfg_block_max = 64;                         // block passes: largest N
     int cfg_dr_wgs = 512;                           // defect-restriction passes: target workgroups
     int cfg_defect = 2;   // two-sweep pre-smoothing writes the defect: 0 never, 1 from a zero iterate, 2 always
+    int cfg_2d_sweep2_min = 1536;  // two-dimensional plans: smallest N of the two-sweep passes
+    int cfg_2d_chunk = 0;          // ... rows per chunk (0: chosen from the grid size)
     int small32 = -1, small64 = -1;   // first level of the single-workgroup coarse kernel
     double* partial = nullptr;     // first-stage reduction partials
     double* cinv = nullptr;        // inverse of the coarsest operator (kCoarseMax^2 entries)

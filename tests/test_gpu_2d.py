@@ -66,6 +66,48 @@ def test_fixed_cycles_match_oracle(N, n, face_mean, nu):
     assert abs(lhs - rhs) <= 1e-12 * float(drho.norm()) * float(np.linalg.norm(c["rhobar"]))
 
 
+@pytest.mark.parametrize("N,chunk,nu,g", [(48, 8, (2, 2), 0.0), (128, 16, (2, 1), 0.3), (256, 0, (3, 2), 0.0),
+                                          (96, 24, (1, 3), 0.0)])
+def test_two_sweep_passes_on_every_level(monkeypatch, N, chunk, nu, g):
+    """The two-sweep passes (used on large levels) forced onto every level
+    that smooths, with short row chunks, odd sweep counts and g != 0."""
+    monkeypatch.setenv("DMGS_2D_SWEEP2_MIN", "4")
+    if chunk:
+        monkeypatch.setenv("DMGS_2D_CHUNK", str(chunk))
+    say("2d two-sweep passes N=%d chunk=%d nu=%s g=%g" % (N, chunk, nu, g))
+    c = case(N, 60 + N)
+    n = 3
+    P = plan_for(c, fixed_cycles=n, nu_pre=nu[0], nu_post=nu[1], bc_value=g)
+    H = oracle_for(c, g=g)
+    kw = dict(fixed_cycles=n, nu1=nu[0], nu2=nu[1])
+    rho, _ = P.forward(dev(c["q"]))
+    rr, _ = H.forward(c["q"], **kw)
+    assert rel_max(host(rho), rr) <= 1e-12
+    (qb, gD, gmu), _ = P.vjp(rho, dev(c["rhobar"]))
+    (rqb, rgD, rgmu), _ = H.vjp(rr, c["rhobar"], **kw)
+    for a, b in ((qb, rqb), (gD, rgD), (gmu, rgmu)):
+        assert rel_max(host(a), b) <= 1e-12
+    drho, _ = P.jvp(rho, dev(c["dq"]), dev(c["dlogD"]), dev(c["dlogmua"]))
+    dr, _ = H.jvp(rr, c["dq"], c["dlogD"], c["dlogmua"], **kw)
+    assert rel_max(host(drho), dr) <= 1e-12
+
+
+def test_large_grid_fixed_cycles_match_oracle():
+    """768^2 cells: the two-sweep passes on levels 0 (and the half-sweeps
+    below), against the oracle."""
+    say("2d fixed N=768")
+    N = 768
+    c = case(N, 768)
+    P = plan_for(c, fixed_cycles=2)
+    H = oracle_for(c)
+    rho, _ = P.forward(dev(c["q"]))
+    rr, _ = H.forward(c["q"], fixed_cycles=2)
+    assert rel_max(host(rho), rr) <= 1e-12
+    (qb, _, _), _ = P.vjp(rho, dev(c["rhobar"]), coef_grads=False)
+    rqb, _ = H.pullback(c["rhobar"], fixed_cycles=2)
+    assert rel_max(host(qb), rqb) <= 1e-12
+
+
 @pytest.mark.parametrize("N", [2, 3, 4, 6, 12])
 def test_small_grids_and_boundary_value(N):
     say("2d small N=%d" % N)
