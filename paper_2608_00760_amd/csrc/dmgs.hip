@@ -911,6 +911,27 @@ int sweeps2(dmgs_plan P, int k, double** cur, double** other, const double* q, i
 template <bool HARM>
 int vcycle2(dmgs_plan P, int k, double** cur, double** other, const double* q, int order, bool zero, hipStream_t st) {
     const Level& l = P->lev[k];
+    if (zero && k == P->small2) {
+        // this level and every coarser one in one LDS-resident workgroup
+        Small2Args a;
+        a.q = q;
+        a.u = *cur;
+        a.nl = P->L - k;
+        for (int i = 0; i < a.nl; i++) {
+            const Level& li = P->lev[k + i];
+            a.D[i] = li.D64;
+            a.mu[i] = li.mu64;
+            a.st[i] = li.stencil<double>(HARM);
+            a.N[i] = li.N;
+        }
+        a.nu_pre = nu_pre_of(P, order);
+        a.nu_post = nu_post_of(P, order);
+        a.first = order ? 1 : 0;
+        const size_t lds = (size_t)small2_words(a.N, a.nl) * sizeof(double);
+        hipLaunchKernelGGL(k2_small_vcycle<HARM>, dim3(1), dim3(1024), lds, st, a);
+        LAUNCHCHK();
+        return DMGS_OK;
+    }
     if (zero) TRY(fill<double>(*cur, l.nv, 0.0, st));
     if (k == P->L - 1) {
         hipLaunchKernelGGL(k2_exact<HARM>, dim3(1), dim3(64), 0, st, q, *cur, (const double*)l.D64,
@@ -1438,6 +1459,14 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     // first level handled by the single-workgroup kernel (N <= 16 in float32,
     // N <= 8 in float64, all remaining levels within the LDS budget)
     P->small32 = P->small64 = -1;
+    P->small2 = -1;
+    int small2_max = kSmall2MaxN;
+    if (const char* e = std::getenv("DMGS_2D_SMALL_MAX")) small2_max = std::min(kSmall2MaxN, std::atoi(e));
+    for (int k = 1; k < P->L - 1 && o->ndim == 2; k++)
+        if (P->lev[k].N <= small2_max && P->L - k <= kSmall2MaxLevels) {
+            P->small2 = k;
+            break;
+        }
     for (int k = 1; k < P->L && st == DMGS_OK && o->ndim != 2; k++) {
         int Ns[kSmallMaxLevels];
         int nl = P->L - k;
@@ -1576,6 +1605,7 @@ int make_twin(dmgs_plan P) {
     T->cfg_dr_wgs = P->cfg_dr_wgs;
     T->cfg_defect = P->cfg_defect;
     T->cfg_2d_sweep2_min = P->cfg_2d_sweep2_min;
+    T->small2 = P->small2;
     T->cfg_2d_chunk = P->cfg_2d_chunk;
     T->small32 = P->small32;
     T->small64 = P->small64;

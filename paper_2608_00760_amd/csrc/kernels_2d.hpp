@@ -537,3 +537,179 @@ __global__ __launch_bounds__(256) void k2_defect_restrict_rows(const double* __r
 }
 
 }  // namespace dmgs
+
+namespace dmgs {
+
+// ---------------------------------------------------------------------------
+// The coarse end of a two-dimensional V-cycle in one workgroup: levels
+// ks .. L-1 (N_ks <= kSmall2MaxN), every field LDS-resident.  The correction
+// of level ks starts from 0 with a zero boundary (a coarse correction), and
+// the same steps as the per-level kernels run in the same order: nu_pre
+// sweeps, defect and restriction, the next level, prolongation and
+// correction, nu_post sweeps; the coarsest level is solved exactly (one
+// thread, Cholesky).  Barriers separate the steps.
+constexpr int kSmall2MaxN = 32, kSmall2MaxLevels = 6;
+
+struct Small2Args {
+    const double* q;                          // right-hand side of level ks
+    double* u;                                // its correction (written on every vertex)
+    const double* D[kSmall2MaxLevels];
+    const double* mu[kSmall2MaxLevels];
+    Stencil<double> st[kSmall2MaxLevels];
+    int N[kSmall2MaxLevels];
+    int nl;                                   // levels ks .. L-1
+    int nu_pre, nu_post, first;               // first: colour of the first half-sweep
+};
+
+__host__ __device__ inline int small2_words(const int* Ns, int nl) {
+    int w = 0;
+    for (int i = 0; i < nl; i++) w += 4 * (Ns[i] + 1) * (Ns[i] + 1);
+    return w;
+}
+
+template <bool HARM>
+__global__ __launch_bounds__(1024) void k2_small_vcycle(Small2Args a) {
+    extern __shared__ double lds2[];
+    // level i holds u, q, D, mua (each (N_i + 1)^2) from lds2 + 4 sum_{j<i} (N_j + 1)^2
+    auto lvl = [&](int i) __attribute__((always_inline)) {
+        int off = 0;
+        for (int j = 0; j < i; j++) off += 4 * (a.N[j] + 1) * (a.N[j] + 1);
+        return lds2 + off;
+    };
+    auto nvl = [&](int i) __attribute__((always_inline)) { return (a.N[i] + 1) * (a.N[i] + 1); };
+#define U(i) (lvl(i))
+#define Q(i) (lvl(i) + nvl(i))
+#define DD(i) (lvl(i) + 2 * nvl(i))
+#define M(i) (lvl(i) + 3 * nvl(i))
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = 0; i < a.nl; i++) {
+        const int nv = (a.N[i] + 1) * (a.N[i] + 1);
+        for (int v = tid; v < nv; v += nt) {
+            U(i)[v] = 0.0;
+            Q(i)[v] = i == 0 ? a.q[v] : 0.0;
+            DD(i)[v] = a.D[i][v];
+            M(i)[v] = a.mu[i][v];
+        }
+    }
+    __syncthreads();
+    auto half = [&](int i, int colour) {
+        const int N = a.N[i], n = N + 1, S = N / 2;
+        const Stencil<double> s = a.st[i];
+        double* u = U(i);
+        for (int t = tid; t < (N - 1) * S; t += nt) {
+            const int x = 1 + t / S;
+            const int y = (((colour - x) & 1) ? 1 : 2) + 2 * (t % S);
+            if (y >= N) continue;
+            const int v = x * n + y;
+            const double Di = DD(i)[v];
+            const double cxm = face<HARM>(Di, DD(i)[v - n], s), cxp = face<HARM>(Di, DD(i)[v + n], s);
+            const double cym = face<HARM>(Di, DD(i)[v - 1], s), cyp = face<HARM>(Di, DD(i)[v + 1], s);
+            u[v] = (Q(i)[v] + cxm * u[v - n] + cxp * u[v + n] + cym * u[v - 1] + cyp * u[v + 1]) /
+                   (cxm + cxp + cym + cyp + M(i)[v]);
+        }
+        __syncthreads();
+    };
+    auto sweeps = [&](int i, int count) {
+        for (int c = 0; c < count; c++) {
+            half(i, a.first);
+            half(i, 1 - a.first);
+        }
+    };
+    for (int i = 0; i + 1 < a.nl; i++) {
+        sweeps(i, a.nu_pre);
+        // qc = R (q - A u)
+        const int Nf = a.N[i], nf = Nf + 1, Nc = a.N[i + 1], nc = Nc + 1;
+        const Stencil<double> s = a.st[i];
+        for (int v = tid; v < (Nc - 1) * (Nc - 1); v += nt) {
+            const int X = 1 + v / (Nc - 1), Y = 1 + v % (Nc - 1);
+            double acc = 0.0;
+            for (int da = -1; da <= 1; da++) {
+                double row = 0.0;
+                for (int db = -1; db <= 1; db++) {
+                    const int f = (2 * X + da) * nf + 2 * Y + db;
+                    const double Di = DD(i)[f], ui = U(i)[f];
+                    const double r = Q(i)[f] - (M(i)[f] * ui + face<HARM>(Di, DD(i)[f - nf], s) * (ui - U(i)[f - nf]) +
+                                                face<HARM>(Di, DD(i)[f + nf], s) * (ui - U(i)[f + nf]) +
+                                                face<HARM>(Di, DD(i)[f - 1], s) * (ui - U(i)[f - 1]) +
+                                                face<HARM>(Di, DD(i)[f + 1], s) * (ui - U(i)[f + 1]));
+                    row += (db == 0 ? 2.0 : 1.0) * r;
+                }
+                acc += (double)(2 - abs(da)) * row;
+            }
+            Q(i + 1)[X * nc + Y] = acc * (1.0 / 16.0);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        // exact solve on the coarsest level (N in {2, 3}), zero boundary
+        const int i = a.nl - 1, N = a.N[i], n = N + 1, m1 = N - 1, m = m1 * m1;
+        const Stencil<double> s = a.st[i];
+        double A[4][4], b[4];
+        for (int r = 0; r < m; r++)
+            for (int c = 0; c < m; c++) A[r][c] = 0.0;
+        for (int x = 1; x < N; x++)
+            for (int y = 1; y < N; y++) {
+                const int t = (x - 1) * m1 + (y - 1), v = x * n + y;
+                A[t][t] = M(i)[v];
+                b[t] = Q(i)[v];
+                const int nb[4][2] = {{x - 1, y}, {x + 1, y}, {x, y - 1}, {x, y + 1}};
+                for (int e = 0; e < 4; e++) {
+                    const int xa = nb[e][0], ya = nb[e][1];
+                    const double c = face<HARM>(DD(i)[v], DD(i)[xa * n + ya], s);
+                    A[t][t] += c;
+                    if (xa > 0 && xa < N && ya > 0 && ya < N) A[t][(xa - 1) * m1 + (ya - 1)] -= c;
+                }
+            }
+        for (int j = 0; j < m; j++) {
+            double d = A[j][j];
+            for (int p = 0; p < j; p++) d -= A[j][p] * A[j][p];
+            d = sqrt(d);
+            A[j][j] = d;
+            for (int r = j + 1; r < m; r++) {
+                double acc = A[r][j];
+                for (int p = 0; p < j; p++) acc -= A[r][p] * A[j][p];
+                A[r][j] = acc / d;
+            }
+        }
+        for (int r = 0; r < m; r++) {
+            double acc = b[r];
+            for (int p = 0; p < r; p++) acc -= A[r][p] * b[p];
+            b[r] = acc / A[r][r];
+        }
+        for (int r = m - 1; r >= 0; r--) {
+            double acc = b[r];
+            for (int p = r + 1; p < m; p++) acc -= A[p][r] * b[p];
+            b[r] = acc / A[r][r];
+        }
+        for (int x = 1; x < N; x++)
+            for (int y = 1; y < N; y++) U(i)[x * n + y] = b[(x - 1) * m1 + (y - 1)];
+    }
+    __syncthreads();
+    for (int i = a.nl - 2; i >= 0; i--) {
+        // u += I uc on fine interior vertices
+        const int Nf = a.N[i], nf = Nf + 1, nc = a.N[i + 1] + 1;
+        const double* ec = U(i + 1);
+        for (int v = tid; v < nf * nf; v += nt) {
+            const int x = v / nf, y = v % nf;
+            if (x == 0 || x == Nf || y == 0 || y == Nf) continue;
+            const int X0 = x >> 1, X1 = (x + 1) >> 1, Y0 = y >> 1, Y1 = (y + 1) >> 1;
+            const double* r0 = ec + X0 * nc;
+            const double* r1 = ec + X1 * nc;
+            double e;
+            if (X0 == X1) e = (Y0 == Y1) ? r0[Y0] : 0.5 * (r0[Y0] + r0[Y1]);
+            else if (Y0 == Y1) e = 0.5 * (r0[Y0] + r1[Y0]);
+            else e = 0.25 * (r0[Y0] + r1[Y0] + r0[Y1] + r1[Y1]);
+            U(i)[v] += e;
+        }
+        __syncthreads();
+        sweeps(i, a.nu_post);
+    }
+    const int nv0 = (a.N[0] + 1) * (a.N[0] + 1);
+    for (int v = tid; v < nv0; v += nt) a.u[v] = U(0)[v];
+#undef U
+#undef Q
+#undef DD
+#undef M
+}
+
+}  // namespace dmgs

@@ -79,6 +79,7 @@ struct dmgs_plan_s {
     int cfg_2d_sweep2_min = 1536;  // two-dimensional plans: smallest N of the two-sweep passes
     int cfg_2d_chunk = 0;          // ... rows per chunk (0: chosen from the grid size)
     int small32 = -1, small64 = -1;   // first level of the single-workgroup coarse kernel
+    int small2 = -1;                  // ... of two-dimensional plans
     double* partial = nullptr;     // first-stage reduction partials
     double* cinv = nullptr;        // inverse of the coarsest operator (kCoarseMax^2 entries)
     double* hnorm = nullptr;       // pinned host memory the reductions write their norms to (4 slots)
