@@ -85,13 +85,13 @@ def serving_leg(nreq):
 
 
 def kernel_source_hash():
-    """sha256 over the name and contents of the kernel sources (csrc/*.hpp and
-    csrc/dmgs.hip, sorted by path)."""
-    import glob
+    """sha256 over the name and contents of the sources that define the
+    dominant kernel's device code (the three-dimensional streaming passes:
+    csrc/grid.hpp, kernels_stream.hpp, kernels_sweep2.hpp, in that order)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2608_00760_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hpp")) + [os.path.join(csrc, "dmgs.hip")]):
+    for f in [os.path.join(csrc, n) for n in ("grid.hpp", "kernels_stream.hpp", "kernels_sweep2.hpp")]:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
