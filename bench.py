@@ -311,6 +311,29 @@ def main():
         P64.close()
         log("fp64 solver: %.3f ms/step" % fp64["ms_per_step"])
 
+    # likelihood gradient of one source (Sec. 2.5.3): forward solve, the
+    # fused epilogue, the pull-back and the gradients; data from the noise
+    # model with a 3-vertex edge mask
+    rho_l, _ = P.forward(t["q"])
+    Le = rho_l * torch.exp(t["logmua"])
+    w_l = P.noise_weights(Le, 3)
+    gl = torch.Generator(device=dev)
+    gl.manual_seed(3005)
+    sig = torch.maximum(0.05 * Le, 0.01 * Le.max())
+    d_l = Le + sig * torch.randn(Le.shape, generator=gl, device=dev, dtype=torch.float64)
+    P.likelihood_grad(t["q"], d_l, w_l)
+    torch.cuda.synchronize()
+    nl = max(3, args.steps // 2)
+    s0 = time.perf_counter()
+    for _ in range(nl):
+        (_, val_l, _), lf, la = P.likelihood_grad(t["q"], d_l, w_l)
+    torch.cuda.synchronize()
+    likelihood = {"ms_per_eval": (time.perf_counter() - s0) / nl * 1e3, "evals": nl, "chi2": val_l["chi2"],
+                  "nvox": val_l["nvox"], "vcycles_fwd": lf["vcycles"], "vcycles_adj": la["vcycles"],
+                  "what": "forward solve + epilogue (L_e = mua rho, H, chi2, dH/drho) + pull-back + gradients"}
+    log("likelihood gradient: %.3f ms per evaluation, chi2 %.4f" % (likelihood["ms_per_eval"], val_l["chi2"]))
+    del rho_l, Le, w_l, d_l, sig
+
     serving = None
     if args.serving_requests > 0:
         log("serving stream: %d requests" % args.serving_requests)
@@ -382,6 +405,7 @@ def main():
         "vcycle_sequential": vcycle_seq,
         "fp64_solver": fp64,
         "latency_p50_p99": serving,
+        "likelihood_grad": likelihood,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

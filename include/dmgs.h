@@ -189,6 +189,45 @@ int dmgs_vjp(dmgs_plan plan, const double *rho, const double *rhobar, double *qb
 int dmgs_forward_vjp(dmgs_plan plan, const double *q, const double *rhobar, double *rho, double *qbar,
                      double *logD_bar, double *logmua_bar, dmgs_info *info_fwd, dmgs_info *info_vjp, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Response and likelihood epilogue of the reconstruction (Sec. 2.5).  The
+ * response to a source q is the absorbed energy density L_e = mua rho with
+ * rho = S q (the paper's lambda is mua), compared with data d on the voxels
+ * the mask keeps, under Gaussian noise with diagonal covariance.
+ * ------------------------------------------------------------------------- */
+
+/* Inverse noise variances of the noise model (Sec. 2.5.1, Eq. (noise)):
+ * sigma_i = max(rel * Le_i, floor_frac * max_j Le_j) (the paper: rel = 0.05,
+ * floor_frac = 0.01, max over all vertices of Le), w_i = 1 / sigma_i^2 on
+ * vertices at least `mask` (>= 1) vertices from every face, 0 on the others
+ * and where sigma_i <= 0 (the paper masks 0.2 cm at every edge).  Le and w
+ * are finest-level device arrays of the plan; enqueued on `stream`, no
+ * wait.  Errors: DMGS_ERR_INVALID (NULL, mask < 1, negative or non-finite
+ * rel / floor_frac). */
+int dmgs_noise_weights(dmgs_plan plan, const double *Le, int32_t mask, double rel, double floor_frac, double *w,
+                       void *stream);
+
+/* Negative log-likelihood of data d and its gradient for one source q
+ * (Sec. 2.5.3, Eq. (chi2)):
+ *   rho = S q                                  (as dmgs_forward)
+ *   H = 1/2 sum_i w_i (d_i - mua_i rho_i)^2    over interior vertices
+ *   value[0] = H, value[1] = chi2 = 2 H / N_vox, value[2] = N_vox (number of
+ *   interior vertices with w_i > 0), written to HOST memory
+ *   qbar = dH/dq = S^dagger rhobar with rhobar_i = mua_i w_i (mua_i rho_i - d_i)
+ *   logD_bar = dH/dlogD and logmua_bar = dH/dlogmua: the pull-back's
+ *   coefficient gradients at rho (as dmgs_vjp) plus, for log mua, the direct
+ *   term w_i (mua_i rho_i - d_i) mua_i rho_i of L_e.
+ * w holds the inverse noise variances with the mask applied (0 = not compared;
+ * e.g. from dmgs_noise_weights); boundary entries of d and w are ignored.
+ * The pull-back follows opt.adjoint_schedule as dmgs_vjp does.  rho, qbar,
+ * logD_bar, logmua_bar must not alias each other or the inputs; logD_bar /
+ * logmua_bar may be NULL.  The call waits for the work it enqueued (value is
+ * ready on return).  info_fwd / info_vjp describe the two solves (either may
+ * be NULL); the status is the forward solve's, else the adjoint's. */
+int dmgs_likelihood_grad(dmgs_plan plan, const double *q, const double *d, const double *w, double *rho,
+                         double *qbar, double *logD_bar, double *logmua_bar, double *value, dmgs_info *info_fwd,
+                         dmgs_info *info_vjp, void *stream);
+
 /* One-shot convenience: create, set coefficients, forward, destroy. */
 int dmgs_solve_once(const dmgs_options *opt, const double *D, const double *mua, const double *q,
                     double *rho, dmgs_info *info, void *stream);

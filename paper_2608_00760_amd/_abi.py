@@ -50,6 +50,9 @@ SIGNATURES = {
     "dmgs_vjp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Info), _vp]),
     "dmgs_forward_vjp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Info), C.POINTER(Info), _vp]),
     "dmgs_solve_once": (_i, [C.POINTER(Options), _vp, _vp, _vp, _vp, C.POINTER(Info), _vp]),
+    "dmgs_noise_weights": (_i, [_vp, _vp, C.c_int32, C.c_double, C.c_double, _vp, _vp]),
+    "dmgs_likelihood_grad": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_double), C.POINTER(Info),
+                                  C.POINTER(Info), _vp]),
     "dmgs_status_string": (C.c_char_p, [_i]),
     "dmgs_last_error": (C.c_char_p, []),
     "dmgs_debug_apply": (_i, [_vp, _i, _i, _vp, _vp, _vp]),

@@ -21,6 +21,7 @@
 #include "kernels_block.hpp"
 #include "kernels_small.hpp"
 #include "kernels_2d.hpp"
+#include "kernels_epilogue.hpp"
 #include "plan.hpp"
 
 using namespace dmgs;
@@ -1715,6 +1716,70 @@ int dmgs_forward_vjp(dmgs_plan P, const double* q, const double* rhobar, double*
         info_vjp->status = sa;
         if (info_fwd) info_vjp->device_ms = info_fwd->device_ms;
     }
+    return s;
+}
+
+int dmgs_noise_weights(dmgs_plan P, const double* Le, int32_t mask, double rel, double floor_frac, double* w,
+                       void* stream) {
+    if (!P || !Le || !w) { set_error("NULL argument"); return DMGS_ERR_INVALID; }
+    if (mask < 1 || !(rel >= 0.0) || !(floor_frac >= 0.0) || !std::isfinite(rel) || !std::isfinite(floor_frac)) {
+        set_error("bad noise-model parameters (mask %d, rel %g, floor %g)", mask, rel, floor_frac);
+        return DMGS_ERR_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(P->device));
+    const Level& l0 = P->lev[0];
+    const unsigned nb = grid_for(l0.nv, kMaxPartials);
+    hipLaunchKernelGGL(k_max_partials, dim3(nb), dim3(kBlock), 0, st, Le, l0.nv, P->partial);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_noise_weights, dim3(grid_for(l0.nv, 4096)), dim3(kBlock), 0, st, Le, (const double*)P->partial,
+                       (int)nb, l0.nv, l0.N, P->opt.ndim, (int)mask, rel, floor_frac, w);
+    LAUNCHCHK();
+    return DMGS_OK;
+}
+
+int dmgs_likelihood_grad(dmgs_plan P, const double* q, const double* d, const double* w, double* rho, double* qbar,
+                         double* logD_bar, double* logmua_bar, double* value, dmgs_info* info_fwd, dmgs_info* info_vjp,
+                         void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    TRY(begin_call(P, st));
+    if (!q || !d || !w || !rho || !qbar || !value) { set_error("NULL argument"); return DMGS_ERR_INVALID; }
+    const Level& l0 = P->lev[0];
+    int sf = solve(P, q, rho, P->opt.bc_value, 0, info_fwd, st, nullptr, true);
+    if (sf != DMGS_OK && sf != DMGS_ERR_NOT_CONVERGED) return end_call(P, sf, info_fwd, st);
+    // epilogue: residual, sums of H and of the kept voxels, and the pull-back's
+    // cotangent (into the finest-level scratch)
+    const unsigned nb = grid_for(l0.nv, kMaxPartials / 2);
+    TIMED(P, 0, DMGS_K_GRAD, 40.0 * l0.nv, st,
+          hipLaunchKernelGGL(k_likelihood_epilogue, dim3(nb), dim3(kBlock), 0, st, (const double*)rho,
+                             (const double*)l0.mu64, d, w, l0.nv, l0.N, P->opt.ndim, P->scratch64, P->partial));
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, P->hnorm, 2);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial + nb, (int)nb, P->hnorm, 3);
+    LAUNCHCHK();
+    const std::vector<int>* replay = (P->opt.adjoint_schedule && P->opt.fixed_cycles <= 0) ? &P->fwd_schedule : nullptr;
+    const int sa = solve(P, P->scratch64, qbar, 0.0, 1, info_vjp, st, replay);
+    const bool ok_a = sa == DMGS_OK || sa == DMGS_ERR_NOT_CONVERGED;
+    if (ok_a && (logD_bar || logmua_bar)) {
+        TIMED(P, 0, DMGS_K_GRAD, 48.0 * l0.nv, st,
+              hipLaunchKernelGGL(is2d(P) ? k2_coef_grads : k_coef_grads, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st,
+                                 (const double*)rho, (const double*)qbar, (const double*)l0.D64, (const double*)l0.mu64,
+                                 l0.N, l0.inv_h2, harmonic(P), logD_bar, logmua_bar));
+    }
+    if (ok_a && logmua_bar) {
+        hipLaunchKernelGGL(k_likelihood_direct, dim3(grid_for(l0.nv, 4096)), dim3(kBlock), 0, st, (const double*)rho,
+                           (const double*)l0.mu64, d, w, l0.nv, l0.N, P->opt.ndim, logmua_bar);
+        LAUNCHCHK();
+    }
+    HIPCHK(hipEventRecord(P->ev_norm, st));
+    TRY(read_norms(P, st));
+    const double H = 0.5 * P->hnorm[2], nvox = P->hnorm[3];
+    value[0] = H;
+    value[1] = nvox > 0.0 ? 2.0 * H / nvox : 0.0;
+    value[2] = nvox;
+    int s = sf != DMGS_OK ? sf : sa;
+    s = end_call(P, s, info_fwd, st);
+    if (info_vjp) info_vjp->status = sa;
     return s;
 }
 

@@ -171,6 +171,33 @@ class Plan:
                    info=info, check=check)
         return (qbar, gD, gmu), info.as_dict()
 
+    def noise_weights(self, Le, mask, rel=0.05, floor=0.01):
+        """Inverse noise variances of the noise model with the edge mask
+        (dmgs_noise_weights)."""
+        w = self._empty()
+        self._call(_abi.lib().dmgs_noise_weights, "dmgs_noise_weights", self._arr(Le, "Le"), int(mask), float(rel),
+                   float(floor), self._arr(w, "w"), _stream(self.device))
+        return w
+
+    def likelihood_grad(self, q, d, w, coef_grads=True, check=True):
+        """rho = S q, {"H", "chi2", "nvox"} and (qbar, logD_bar, logmua_bar)
+        = the gradient of H (dmgs_likelihood_grad).  Returns (rho, value,
+        grads), info_fwd, info_vjp."""
+        rho, qbar = self._empty(), self._empty()
+        gD = self._empty() if coef_grads else None
+        gmu = self._empty() if coef_grads else None
+        value = (C.c_double * 3)()
+        info_f, info_a = _abi.Info(), _abi.Info()
+        st = self._call(_abi.lib().dmgs_likelihood_grad, "dmgs_likelihood_grad", self._arr(q, "q"), self._arr(d, "d"),
+                        self._arr(w, "w"), self._arr(rho, "rho"), self._arr(qbar, "qbar"),
+                        self._arr(gD, "logD_bar", optional=True), self._arr(gmu, "logmua_bar", optional=True),
+                        value, C.byref(info_f), C.byref(info_a), _stream(self.device), check=False)
+        if check and st != _abi.DMGS_OK:
+            bad = info_f if info_f.status != _abi.DMGS_OK else info_a
+            raise _abi.DMGSError(st, "dmgs_likelihood_grad", bad.as_dict())
+        val = {"H": value[0], "chi2": value[1], "nvox": int(value[2])}
+        return (rho, val, (qbar, gD, gmu)), info_f.as_dict(), info_a.as_dict()
+
     def forward_vjp(self, q, rhobar, coef_grads=True, out=None, check=True):
         """rho = S q and the VJP at rho with cotangent rhobar, the two solves
         running concurrently (dmgs_forward_vjp).  Returns (rho, (qbar,

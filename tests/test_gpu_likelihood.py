@@ -1,0 +1,85 @@
+"""Parity of the response and likelihood epilogue (dmgs_noise_weights,
+dmgs_likelihood_grad) with the oracle (oracle/likelihood.py on the solver
+oracles), through the C ABI.
+
+* The noise-model weights equal the oracle's to rounding (same operations).
+* Fixed-cycle mode (float64, 3D and 2D): rho, H, chi2, N_vox and the three
+  gradients equal the oracle's to 1e-12.
+* Tolerance mode (float32-in-float64, 3D): H and chi2 to 1e-9, gradients to
+  1e-8 against the oracle solved to 1e-13; data drawn from the noise model
+  give chi2 near 1.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, rel_max, say
+
+pytestmark = pytest.mark.gpu
+
+
+def setup(N, seed, ndim=3, mask=3, **opts):
+    from paper_2608_00760_amd import synth
+    from paper_2608_00760_amd.solver import Options, Plan
+    from oracle import likelihood
+    c = synth.grf_case(N, seed, ndim=ndim)
+    P = Plan(Options(N, ndim=ndim, **opts))
+    P.set_coefficients(dev(c["D"]), dev(c["mua"]))
+    rho, _ = P.forward(dev(c["q"]))
+    Le = host(rho) * c["mua"]
+    sigma = np.maximum(0.05 * Le, 0.01 * Le.max())
+    d = Le + sigma * np.random.default_rng(seed + 9).standard_normal(Le.shape)
+    w = likelihood.noise_weights(Le, mask)
+    return c, P, Le, d, w
+
+
+def oracle_hier(c, ndim):
+    from oracle import ref, ref2d
+    return ref.Hierarchy(c["D"], c["mua"]) if ndim == 3 else ref2d.Hierarchy2D(c["D"], c["mua"])
+
+
+def test_noise_weights_match_oracle():
+    from oracle import likelihood
+    say("noise weights")
+    for ndim, N, mask in ((3, 48, 3), (2, 96, 4)):
+        c, P, Le, d, w = setup(N, 40 + N, ndim=ndim, mask=mask)
+        wg = host(P.noise_weights(dev(Le), mask))
+        assert rel_max(wg, w) <= 1e-15
+        assert (wg[w == 0] == 0).all()
+
+
+@pytest.mark.parametrize("ndim,N,n", [(3, 32, 3), (3, 48, 2), (2, 128, 3)])
+def test_fixed_cycles_match_oracle(ndim, N, n):
+    from oracle import likelihood
+    say("likelihood fixed ndim=%d N=%d n=%d" % (ndim, N, n))
+    c, P0, Le, d, w = setup(N, 70 + N, ndim=ndim)
+    from paper_2608_00760_amd.solver import Options, Plan
+    P = Plan(Options(N, ndim=ndim, fixed_cycles=n))
+    P.set_coefficients(dev(c["D"]), dev(c["mua"]))
+    (rho, val, (qb, gD, gmu)), fi, vi = P.likelihood_grad(dev(c["q"]), dev(d), dev(w))
+    H = oracle_hier(c, ndim)
+    rr, (Hv, chi2), (rqb, rgD, rgmu) = likelihood.likelihood_grad(H, c["mua"], c["q"], d, w, fixed_cycles=n)
+    say("H %.6e chi2 %.4f nvox %d" % (val["H"], val["chi2"], val["nvox"]))
+    assert fi["cycles"] == n and vi["cycles"] == n
+    assert rel_max(host(rho), rr) <= 1e-12
+    assert abs(val["H"] - Hv) <= 1e-12 * Hv and abs(val["chi2"] - chi2) <= 1e-12 * chi2
+    assert val["nvox"] == int(np.count_nonzero(w > 0))
+    for g, r in ((qb, rqb), (gD, rgD), (gmu, rgmu)):
+        assert rel_max(host(g), r) <= 1e-12
+
+
+def test_tolerance_mode_matches_oracle():
+    from oracle import likelihood
+    say("likelihood tolerance fp32-in-fp64 N=64")
+    N = 64
+    c, P, Le, d, w = setup(N, 900, precision="fp32-in-fp64")
+    (rho, val, (qb, gD, gmu)), fi, vi = P.likelihood_grad(dev(c["q"]), dev(d), dev(w))
+    assert fi["status"] == 0 and vi["status"] == 0
+    H = oracle_hier(c, 3)
+    rr, (Hv, chi2), (rqb, rgD, rgmu) = likelihood.likelihood_grad(H, c["mua"], c["q"], d, w, rtol=1e-13,
+                                                                    max_cycles=300)
+    errs = {"H": abs(val["H"] - Hv) / Hv, "chi2": abs(val["chi2"] - chi2) / chi2, "q": rel_max(host(qb), rqb),
+            "logD": rel_max(host(gD), rgD), "logmua": rel_max(host(gmu), rgmu)}
+    say("chi2 %.4f" % val["chi2"], {k: "%.2e" % v for k, v in errs.items()})
+    assert errs["H"] <= 1e-9 and errs["chi2"] <= 1e-9
+    assert max(errs["q"], errs["logD"], errs["logmua"]) <= 1e-8
+    assert abs(val["chi2"] - 1.0) <= 4.0 * np.sqrt(2.0 / val["nvox"])
