@@ -386,7 +386,23 @@ int launch_sweep2(dmgs_plan P, const SweepArgs<T>& a0, int N, int mode, hipStrea
     a.tiles_z = (N + TZ - 1) / TZ;
     const int tiles = a.tiles_y * a.tiles_z;
     const int wgs = N == P->lev[0].N ? P->cfg_sweep2_wgs : P->cfg_sweep2_wgs_coarse;
-    const int nch = std::max(1, (wgs + tiles - 1) / tiles);
+    int nch = std::max(1, (wgs + tiles - 1) / tiles);
+    if (N == P->lev[0].N && P->cfg_sweep2_wgs == 256) {
+        // finest level: one workgroup per CU, so pick the chunk count whose
+        // workgroups fill the last round of CUs best, net of the 6 extra
+        // march steps a chunk costs
+        double best = 0.0;
+        for (int c = 1; c <= 32; c++) {
+            const int chunk = std::min(N - 1, std::max(8, (N - 1 + c - 1) / c));
+            const int nb = tiles * ((N - 1 + chunk - 1) / chunk);
+            const int rounds = (nb + P->ncu - 1) / P->ncu;
+            const double v = (double)nb / ((double)rounds * P->ncu) * chunk / (chunk + 6.0);
+            if (v > best + 1e-9) {
+                best = v;
+                nch = c;
+            }
+        }
+    }
     a.chunk = std::min(N - 1, std::max(8, (N - 1 + nch - 1) / nch));
     a.nchunks = (N - 1 + a.chunk - 1) / a.chunk;
     const int nb = tiles * a.nchunks;
@@ -399,11 +415,14 @@ int launch_sweep2(dmgs_plan P, const SweepArgs<T>& a0, int N, int mode, hipStrea
 
 constexpr int kSweep2TY = 16, kSweep2TZ = 64;     // tiles of the two-sweep passes
 constexpr int kSweep2DTY = 16, kSweep2DTZ = 64;   // ... of the passes that also write the defect
+constexpr int kSweep2TZ64 = 32;                   // float64 passes: tiles of 16 x 32
 
 // Dynamic-LDS limits of the two-sweep kernels (set once per plan).
 int sweep2_attributes() {
     constexpr int lds = (int)sweep2_lds_bytes<float, kSweep2TY, kSweep2TZ>();
     constexpr int ldsd = (int)sweep2_lds_bytes<float, kSweep2DTY, kSweep2DTZ, 5>();
+    constexpr int lds64 = (int)sweep2_lds_bytes<double, kSweep2TY, kSweep2TZ64>();
+    static_assert(lds64 <= 160 * 1024, "float64 two-sweep ring exceeds the LDS");
     const std::pair<const void*, int> fns[] = {
         {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepPlain, false>, lds},
         {(const void*)k_rb_sweep2_col<float, kSweep2TY, kSweep2TZ, kSweepZero, false>, lds},
@@ -414,7 +433,13 @@ int sweep2_attributes() {
         {(const void*)k_rb_sweep2_col<float, kSweep2DTY, kSweep2DTZ, kSweepPlain, false, true>, ldsd},
         {(const void*)k_rb_sweep2_col<float, kSweep2DTY, kSweep2DTZ, kSweepZero, false, true>, ldsd},
         {(const void*)k_rb_sweep2_col<float, kSweep2DTY, kSweep2DTZ, kSweepPlain, true, true>, ldsd},
-        {(const void*)k_rb_sweep2_col<float, kSweep2DTY, kSweep2DTZ, kSweepZero, true, true>, ldsd}};
+        {(const void*)k_rb_sweep2_col<float, kSweep2DTY, kSweep2DTZ, kSweepZero, true, true>, ldsd},
+        {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepPlain, false>, lds64},
+        {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepZero, false>, lds64},
+        {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepProlong, false>, lds64},
+        {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepPlain, true>, lds64},
+        {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepZero, true>, lds64},
+        {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepProlong, true>, lds64}};
     for (const auto& f : fns)
         if (hipFuncSetAttribute(f.first, hipFuncAttributeMaxDynamicSharedMemorySize, f.second) != hipSuccess) {
             set_error("hipFuncSetAttribute failed");
@@ -425,8 +450,13 @@ int sweep2_attributes() {
 
 // Two-sweep passes need a zero Dirichlet boundary (float32 corrections)
 // and whole-field buffer offsets below kOob.
+// The two-sweep pass needs a zero boundary: every float32 correction, every
+// coarse level, and the float64 finest level when the solve's boundary value
+// is 0 (the adjoint and tangent solves always; the forward solve when g = 0).
 bool use_sweep2(dmgs_plan P, int k, size_t tsize) {
-    return tsize == 4 && P->lev[k].N >= P->cfg_sweep2_min && sweep2_fits<float>(P->lev[k].N);
+    if (P->lev[k].N < P->cfg_sweep2_min) return false;
+    if (tsize == 4) return sweep2_fits<float>(P->lev[k].N);
+    return P->cfg_sweep2_fp64 && (k > 0 || P->bc_zero) && sweep2_fits<double>(P->lev[k].N);
 }
 
 // One two-sweep pass: u_out = two red-black sweeps applied to u_in (or to
@@ -459,8 +489,11 @@ int smooth_pass2(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int or
         else TRY(h ? (launch_sweep2<T, kSweep2TY, kSweep2TZ, true, false>(P, a, l.N, mode, st))
                    : (launch_sweep2<T, kSweep2TY, kSweep2TZ, false, false>(P, a, l.N, mode, st)));
     } else {
-        set_error("two-sweep pass is float32 only");
-        return DMGS_ERR_INVALID;
+        // float64: half-width tiles (the LDS ring holds twice the bytes);
+        // no defect-writing variant
+        if (r) { set_error("two-sweep pass: no defect output in float64"); return DMGS_ERR_INVALID; }
+        TRY(harmonic(P) ? (launch_sweep2<T, kSweep2TY, kSweep2TZ64, true, false>(P, a, l.N, mode, st))
+                        : (launch_sweep2<T, kSweep2TY, kSweep2TZ64, false, false>(P, a, l.N, mode, st)));
     }
     TRY(tend(P, slot, DMGS_K_SMOOTH, words * l.nv * sizeof(T), st));
     return DMGS_OK;
@@ -1053,6 +1086,7 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
     if (is2d(P))
         return harmonic(P) ? solve2d<true>(P, b, x, bc, order, info, st, replay, record)
                            : solve2d<false>(P, b, x, bc, order, info, st, replay, record);
+    P->bc_zero = bc == 0.0;
     const dmgs_options& o = P->opt;
     const Level& l0 = P->lev[0];
     const bool fixed = o.fixed_cycles > 0 || replay;
@@ -1394,6 +1428,11 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     if (!P) { set_error("host allocation failed"); return DMGS_ERR_OOM; }
     P->opt = *o;
     if (hipGetDevice(&P->device) != hipSuccess) { delete P; set_error("hipGetDevice failed"); return DMGS_ERR_HIP; }
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && ncu > 0)
+            P->ncu = ncu;
+    }
     Sizes s = sizes_for(o);
     P->L = s.L;
     bool ir = o->precision == DMGS_FP32_IN_FP64;
@@ -1505,6 +1544,7 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     if (const char* e = std::getenv("DMGS_SWEEP_CFG")) P->cfg_sweep = std::min(2, std::max(0, std::atoi(e)));
     if (const char* e = std::getenv("DMGS_FUSE_MIN")) P->cfg_fuse_min = std::max(8, std::atoi(e));
     if (const char* e = std::getenv("DMGS_2D_SWEEP2_MIN")) P->cfg_2d_sweep2_min = std::max(4, std::atoi(e));
+    if (const char* e = std::getenv("DMGS_SWEEP2_FP64")) P->cfg_sweep2_fp64 = std::atoi(e) != 0;
     if (const char* e = std::getenv("DMGS_2D_CHUNK")) P->cfg_2d_chunk = std::max(8, std::atoi(e) / 8 * 8);
     if (st != DMGS_OK) {
         free_plan(P);
@@ -1606,6 +1646,8 @@ int make_twin(dmgs_plan P) {
     T->cfg_dr_wgs = P->cfg_dr_wgs;
     T->cfg_defect = P->cfg_defect;
     T->cfg_2d_sweep2_min = P->cfg_2d_sweep2_min;
+    T->cfg_sweep2_fp64 = P->cfg_sweep2_fp64;
+    T->ncu = P->ncu;
     T->small2 = P->small2;
     T->cfg_2d_chunk = P->cfg_2d_chunk;
     T->small32 = P->small32;

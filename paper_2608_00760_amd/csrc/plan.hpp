@@ -77,6 +77,9 @@ struct dmgs_plan_s {
     int cfg_dr_wgs = 512;                           // defect-restriction passes: target workgroups
     int cfg_defect = 2;   // two-sweep pre-smoothing writes the defect: 0 never, 1 from a zero iterate, 2 always
     int cfg_2d_sweep2_min = 1536;  // two-dimensional plans: smallest N of the two-sweep passes
+    bool cfg_sweep2_fp64 = true;   // float64 levels use the two-sweep passes (zero boundaries only)
+    bool bc_zero = true;           // the current solve's boundary value is 0
+    int ncu = 256;                 // compute units of the plan's device
     int cfg_2d_chunk = 0;          // ... rows per chunk (0: chosen from the grid size)
     int small32 = -1, small64 = -1;   // first level of the single-workgroup coarse kernel
     int small2 = -1;                  // ... of two-dimensional plans
