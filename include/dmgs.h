@@ -228,6 +228,26 @@ int dmgs_likelihood_grad(dmgs_plan plan, const double *q, const double *d, const
                          double *qbar, double *logD_bar, double *logmua_bar, double *value, dmgs_info *info_fwd,
                          dmgs_info *info_vjp, void *stream);
 
+/* Unrolled adjoint of the fixed-cycle solver: the exact derivative of
+ * rho = S_n(q; log D, log mua), n = opt.fixed_cycles V(nu_pre, nu_post)-cycles
+ * from rho = 0 (interior) / g (boundary), through every step of every cycle
+ * -- smoothing, defect, restriction, prolongation, the coarsest solve and the
+ * coarse coefficients built from log D and log mua (Sec. 2.2 Eq. (Eqcomp)
+ * reversed as in Sec. 2.4 Eq. (EqcompT), with the coefficients as inputs of
+ * every step).  Writes rho = S_n q and the pull-back of rhobar: qbar (equal
+ * to dmgs_vjp's in fixed mode up to rounding), logD_bar and logmua_bar (the
+ * derivative of the n-cycle map itself, which differs from dmgs_vjp's
+ * adjoint-state gradients of the exact discrete solution by the iteration
+ * error; logD_bar / logmua_bar may be NULL).  The finest iterate is kept at
+ * the start of every cycle and each cycle is recomputed, recording its
+ * states, before its reverse pass: the call allocates n + about
+ * 1.14 (2 (nu_pre + nu_post) + 8) finest-level fields of device memory and
+ * frees them before it returns (it waits for its work).  Three-dimensional
+ * DMGS_FP64, DMGS_RBGS plans with fixed_cycles > 0 only, else
+ * DMGS_ERR_INVALID; DMGS_ERR_OOM if the work buffers do not fit. */
+int dmgs_vjp_unrolled(dmgs_plan plan, const double *q, const double *rhobar, double *rho, double *qbar,
+                      double *logD_bar, double *logmua_bar, dmgs_info *info, void *stream);
+
 /* One-shot convenience: create, set coefficients, forward, destroy. */
 int dmgs_solve_once(const dmgs_options *opt, const double *D, const double *mua, const double *q,
                     double *rho, dmgs_info *info, void *stream);

@@ -51,6 +51,7 @@ SIGNATURES = {
     "dmgs_forward_vjp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Info), C.POINTER(Info), _vp]),
     "dmgs_solve_once": (_i, [C.POINTER(Options), _vp, _vp, _vp, _vp, C.POINTER(Info), _vp]),
     "dmgs_noise_weights": (_i, [_vp, _vp, C.c_int32, C.c_double, C.c_double, _vp, _vp]),
+    "dmgs_vjp_unrolled": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Info), _vp]),
     "dmgs_likelihood_grad": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_double), C.POINTER(Info),
                                   C.POINTER(Info), _vp]),
     "dmgs_status_string": (C.c_char_p, [_i]),

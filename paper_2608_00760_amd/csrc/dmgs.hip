@@ -22,6 +22,7 @@
 #include "kernels_small.hpp"
 #include "kernels_2d.hpp"
 #include "kernels_epilogue.hpp"
+#include "kernels_unrolled.hpp"
 #include "plan.hpp"
 
 using namespace dmgs;
@@ -1759,6 +1760,208 @@ int dmgs_forward_vjp(dmgs_plan P, const double* q, const double* rhobar, double*
         if (info_fwd) info_vjp->device_ms = info_fwd->device_ms;
     }
     return s;
+}
+
+}  // extern "C"
+
+namespace {
+// Work buffers of one unrolled reverse pass (allocated per call).
+struct UnWork {
+    hipStream_t st = nullptr;   // the stream the buffers are used on (waited for before they are freed)
+    std::vector<void*> bufs;
+    double* ckpt = nullptr;                       // the finest iterate at the start of every cycle
+    double* u0 = nullptr;                         // the finest working iterate
+    double* tape[kMaxLevels][33] = {};            // per level: the state after each half-sweep (pre, then post)
+                                                  // and, last, the state the defect reads; the coarsest: its solution
+    double *uc[kMaxLevels] = {}, *qc[kMaxLevels] = {}, *r[kMaxLevels] = {};
+    double *ubar[kMaxLevels] = {}, *qbar[kMaxLevels] = {}, *Dbar[kMaxLevels] = {}, *mbar[kMaxLevels] = {},
+           *V[kMaxLevels] = {};
+    int alloc(double** p, int64_t n) {
+        if (hipMalloc((void**)p, (size_t)n * sizeof(double)) != hipSuccess) {
+            *p = nullptr;
+            set_error("hipMalloc of %lld bytes failed (unrolled reverse pass)", (long long)(n * sizeof(double)));
+            return DMGS_ERR_OOM;
+        }
+        bufs.push_back(*p);
+        return DMGS_OK;
+    }
+    ~UnWork() {
+        if (!bufs.empty()) (void)hipStreamSynchronize(st);
+        for (void* p : bufs) (void)hipFree(p);
+    }
+};
+
+unsigned un_grid(int64_t nv) { return (unsigned)((nv + kBlock - 1) / kBlock); }
+
+// One V-cycle of the fixed-cycle solver with the per-operator kernels, in
+// place on u; with record, the states the reverse pass needs are copied to
+// the tape.
+int vcycle_taped(dmgs_plan P, UnWork& W, int k, double* u, const double* q, bool record, hipStream_t st) {
+    const Level& l = P->lev[k];
+    const int nu1 = P->opt.nu_pre, nu2 = P->opt.nu_post;
+    const size_t bytes = l.nv * sizeof(double);
+    if (k == P->L - 1) {
+        hipLaunchKernelGGL(k_exact_solve<double>, dim3(1), dim3(64), 0, st, q, u, (const double*)l.D64,
+                           (const double*)l.mu64, l.N, l.stencil<double>(harmonic(P)));
+        LAUNCHCHK();
+        if (record) HIPCHK(hipMemcpyAsync(W.tape[k][0], u, bytes, hipMemcpyDeviceToDevice, st));
+        return DMGS_OK;
+    }
+    int h = 0;
+    for (int i = 0; i < nu1; i++)
+        for (int colour = 0; colour < 2; colour++, h++) {
+            TRY(half_sweep<double>(P, k, u, q, colour, st));
+            if (record) HIPCHK(hipMemcpyAsync(W.tape[k][h], u, bytes, hipMemcpyDeviceToDevice, st));
+        }
+    if (record) HIPCHK(hipMemcpyAsync(W.tape[k][2 * (nu1 + nu2)], u, bytes, hipMemcpyDeviceToDevice, st));
+    const Level& c = P->lev[k + 1];
+    TRY(apply_or_defect<double>(P, k, u, q, W.r[k], 0, st));
+    hipLaunchKernelGGL(k_restrict<double>, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)W.r[k], W.qc[k + 1], l.N);
+    LAUNCHCHK();
+    TRY(fill<double>(W.uc[k + 1], c.nv, 0.0, st));
+    TRY(vcycle_taped(P, W, k + 1, W.uc[k + 1], W.qc[k + 1], record, st));
+    hipLaunchKernelGGL(k_prolong_add<double>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, (const double*)W.uc[k + 1], u, l.N);
+    LAUNCHCHK();
+    for (int i = 0; i < nu2; i++)
+        for (int colour = 0; colour < 2; colour++, h++) {
+            TRY(half_sweep<double>(P, k, u, q, colour, st));
+            if (record) HIPCHK(hipMemcpyAsync(W.tape[k][h], u, bytes, hipMemcpyDeviceToDevice, st));
+        }
+    return DMGS_OK;
+}
+
+// Reverse of the recorded cycle on level k: W.ubar[k] holds the cotangent of
+// the level's iterate after the cycle and is left holding the one before it;
+// qbar, Dbar and mubar of the level accumulate.
+int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
+    const Level& l = P->lev[k];
+    const Stencil<double> s = l.stencil<double>(harmonic(P));
+    const int nu1 = P->opt.nu_pre, nu2 = P->opt.nu_post;
+    const unsigned g = un_grid(l.nv);
+    const double *D = l.D64, *mu = l.mu64;
+    if (k == P->L - 1) {
+        // lam = A^-1 ubar (zero boundary), then the solve's coefficient terms
+        TRY(fill<double>(W.V[k], l.nv, 0.0, st));
+        hipLaunchKernelGGL(k_exact_solve<double>, dim3(1), dim3(64), 0, st, (const double*)W.ubar[k], W.V[k], D, mu, l.N, s);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_un_defect, dim3(g), dim3(kBlock), 0, st, (double*)nullptr, (const double*)W.V[k], 1.0,
+                           (const double*)W.tape[k][0], D, mu, l.N, s, W.qbar[k], W.Dbar[k], W.mbar[k]);
+        LAUNCHCHK();
+        return DMGS_OK;
+    }
+    auto half_rev = [&](const double* state, int colour) -> int {
+        hipLaunchKernelGGL(k_un_half_v, dim3(g), dim3(kBlock), 0, st, (const double*)W.ubar[k], state, D, mu, l.N, s,
+                           colour, W.V[k], W.qbar[k], W.mbar[k]);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_un_half_gather, dim3(g), dim3(kBlock), 0, st, W.ubar[k], (const double*)W.V[k], state, D,
+                           l.N, s, colour, W.Dbar[k]);
+        LAUNCHCHK();
+        return DMGS_OK;
+    };
+    for (int h = 2 * nu2 - 1; h >= 0; h--) TRY(half_rev(W.tape[k][2 * nu1 + h], h & 1));
+    // prolongation u += I ec: ecbar = I^T ubar = 8 R ubar
+    const Level& c = P->lev[k + 1];
+    hipLaunchKernelGGL(k_restrict<double>, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)W.ubar[k],
+                       W.ubar[k + 1], l.N);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_un_scale, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, W.ubar[k + 1], c.nv, 8.0);
+    LAUNCHCHK();
+    TRY(fill<double>(W.qbar[k + 1], c.nv, 0.0, st));
+    TRY(vcycle_rev(P, W, k + 1, st));
+    // restriction qc = R r: rbar = R^T qcbar = I qcbar / 8; then the defect
+    TRY(fill<double>(W.r[k], l.nv, 0.0, st));
+    hipLaunchKernelGGL(k_prolong_add<double>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, (const double*)W.qbar[k + 1],
+                       W.r[k], l.N);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_un_defect, dim3(g), dim3(kBlock), 0, st, W.ubar[k], (const double*)W.r[k], 0.125,
+                       (const double*)W.tape[k][2 * (nu1 + nu2)], D, mu, l.N, s, W.qbar[k], W.Dbar[k], W.mbar[k]);
+    LAUNCHCHK();
+    for (int h = 2 * nu1 - 1; h >= 0; h--) TRY(half_rev(W.tape[k][h], h & 1));
+    return DMGS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int dmgs_vjp_unrolled(dmgs_plan P, const double* q, const double* rhobar, double* rho, double* qbar, double* logD_bar,
+                      double* logmua_bar, dmgs_info* info, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    TRY(begin_call(P, st));
+    if (!q || !rhobar || !rho || !qbar) { set_error("NULL argument"); return DMGS_ERR_INVALID; }
+    const dmgs_options& o = P->opt;
+    if (is2d(P) || o.precision != DMGS_FP64 || o.smoother != DMGS_RBGS || o.fixed_cycles <= 0) {
+        set_error("dmgs_vjp_unrolled takes three-dimensional DMGS_FP64, DMGS_RBGS plans with fixed_cycles > 0");
+        return DMGS_ERR_INVALID;
+    }
+    const int n = o.fixed_cycles, L = P->L, nstate = 2 * (o.nu_pre + o.nu_post) + 1;
+    const Level& l0 = P->lev[0];
+    UnWork W;
+    W.st = st;
+    TRY(W.alloc(&W.ckpt, (int64_t)n * l0.nv));
+    TRY(W.alloc(&W.u0, l0.nv));
+    for (int k = 0; k < L; k++) {
+        const int64_t nv = P->lev[k].nv;
+        const int ns = k == L - 1 ? 1 : nstate;
+        for (int h = 0; h < ns; h++) TRY(W.alloc(&W.tape[k][h], nv));
+        if (k < L - 1) TRY(W.alloc(&W.r[k], nv));
+        if (k > 0) {
+            TRY(W.alloc(&W.uc[k], nv));
+            TRY(W.alloc(&W.qc[k], nv));
+        }
+        TRY(W.alloc(&W.ubar[k], nv));
+        TRY(W.alloc(&W.qbar[k], nv));
+        TRY(W.alloc(&W.Dbar[k], nv));
+        TRY(W.alloc(&W.mbar[k], nv));
+        TRY(W.alloc(&W.V[k], nv));
+        TRY(fill<double>(W.Dbar[k], nv, 0.0, st));
+        TRY(fill<double>(W.mbar[k], nv, 0.0, st));
+        TRY(fill<double>(W.qbar[k], nv, 0.0, st));
+        TRY(fill<double>(W.ubar[k], nv, 0.0, st));
+    }
+    const size_t b0 = l0.nv * sizeof(double);
+    // forward: n cycles, keeping the iterate at the start of each
+    hipLaunchKernelGGL(k_init_iterate<double>, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, W.u0, l0.N, o.bc_value);
+    LAUNCHCHK();
+    for (int c = 0; c < n; c++) {
+        HIPCHK(hipMemcpyAsync(W.ckpt + (int64_t)c * l0.nv, W.u0, b0, hipMemcpyDeviceToDevice, st));
+        TRY(vcycle_taped(P, W, 0, W.u0, q, false, st));
+    }
+    HIPCHK(hipMemcpyAsync(rho, W.u0, b0, hipMemcpyDeviceToDevice, st));
+    // reverse: the cotangent of the last iterate is rhobar (interior)
+    HIPCHK(hipMemcpyAsync(W.ubar[0], rhobar, b0, hipMemcpyDeviceToDevice, st));
+    TRY(set_boundary<double>(W.ubar[0], l0.N, 0.0, st));
+    for (int c = n - 1; c >= 0; c--) {
+        HIPCHK(hipMemcpyAsync(W.u0, W.ckpt + (int64_t)c * l0.nv, b0, hipMemcpyDeviceToDevice, st));
+        TRY(vcycle_taped(P, W, 0, W.u0, q, true, st));
+        TRY(vcycle_rev(P, W, 0, st));
+    }
+    // coarse coefficient cotangents to the finest level
+    for (int k = L - 1; k >= 1; k--) {
+        const Level& f = P->lev[k - 1];
+        hipLaunchKernelGGL(k_un_coarsen_T, dim3(un_grid(f.nv)), dim3(kBlock), 0, st, (const double*)W.Dbar[k], W.Dbar[k - 1], f.N);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_un_coarsen_T, dim3(un_grid(f.nv)), dim3(kBlock), 0, st, (const double*)W.mbar[k], W.mbar[k - 1], f.N);
+        LAUNCHCHK();
+    }
+    HIPCHK(hipMemcpyAsync(qbar, W.qbar[0], b0, hipMemcpyDeviceToDevice, st));
+    if (logD_bar) {
+        hipLaunchKernelGGL(k_un_mul, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, (const double*)W.Dbar[0],
+                           (const double*)l0.D64, logD_bar, l0.nv);
+        LAUNCHCHK();
+    }
+    if (logmua_bar) {
+        hipLaunchKernelGGL(k_un_mul, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, (const double*)W.mbar[0],
+                           (const double*)l0.mu64, logmua_bar, l0.nv);
+        LAUNCHCHK();
+    }
+    // the work buffers are freed on return: wait for the work that uses them
+    HIPCHK(hipStreamSynchronize(st));
+    if (info) {
+        info->cycles = n;
+        info->vcycles = n;
+        info->rel_residual = 0.0;
+    }
+    return end_call(P, DMGS_OK, info, st);
 }
 
 int dmgs_noise_weights(dmgs_plan P, const double* Le, int32_t mask, double rel, double floor_frac, double* w,

@@ -171,6 +171,19 @@ class Plan:
                    info=info, check=check)
         return (qbar, gD, gmu), info.as_dict()
 
+    def vjp_unrolled(self, q, rhobar, coef_grads=True):
+        """rho = S_n q and the exact derivative of the n-cycle map pulled back
+        from rhobar: (rho, (qbar, logD_bar, logmua_bar)), info
+        (dmgs_vjp_unrolled; fixed-cycle float64 3D plans)."""
+        rho, qbar = self._empty(), self._empty()
+        gD = self._empty() if coef_grads else None
+        gmu = self._empty() if coef_grads else None
+        info = _abi.Info()
+        self._call(_abi.lib().dmgs_vjp_unrolled, "dmgs_vjp_unrolled", self._arr(q, "q"), self._arr(rhobar, "rhobar"),
+                   self._arr(rho, "rho"), self._arr(qbar, "qbar"), self._arr(gD, "logD_bar", optional=True),
+                   self._arr(gmu, "logmua_bar", optional=True), C.byref(info), _stream(self.device), info=info)
+        return (rho, (qbar, gD, gmu)), info.as_dict()
+
     def noise_weights(self, Le, mask, rel=0.05, floor=0.01):
         """Inverse noise variances of the noise model with the edge mask
         (dmgs_noise_weights)."""

@@ -66,9 +66,10 @@ def test_fixed_cycles_match_oracle(N, n, face_mean, nu):
     assert abs(lhs - rhs) <= 1e-12 * float(drho.norm()) * float(np.linalg.norm(c["rhobar"]))
 
 
-@pytest.mark.parametrize("N,chunk,nu,g", [(48, 8, (2, 2), 0.0), (128, 16, (2, 1), 0.3), (256, 0, (3, 2), 0.0),
-                                          (96, 24, (1, 3), 0.0)])
-def test_two_sweep_passes_on_every_level(monkeypatch, N, chunk, nu, g):
+@pytest.mark.parametrize("N,chunk,nu,g,face_mean", [(48, 8, (2, 2), 0.0, "arith"), (128, 16, (2, 1), 0.3, "arith"),
+                                                    (256, 0, (3, 2), 0.0, "arith"), (96, 24, (1, 3), 0.0, "arith"),
+                                                    (192, 32, (2, 2), 0.2, "harmonic")])
+def test_two_sweep_passes_on_every_level(monkeypatch, N, chunk, nu, g, face_mean):
     """The two-sweep passes (used on large levels) forced onto every level
     that smooths, with short row chunks, odd sweep counts and g != 0."""
     monkeypatch.setenv("DMGS_2D_SWEEP2_MIN", "4")
@@ -77,8 +78,8 @@ def test_two_sweep_passes_on_every_level(monkeypatch, N, chunk, nu, g):
     say("2d two-sweep passes N=%d chunk=%d nu=%s g=%g" % (N, chunk, nu, g))
     c = case(N, 60 + N)
     n = 3
-    P = plan_for(c, fixed_cycles=n, nu_pre=nu[0], nu_post=nu[1], bc_value=g)
-    H = oracle_for(c, g=g)
+    P = plan_for(c, fixed_cycles=n, nu_pre=nu[0], nu_post=nu[1], bc_value=g, face_mean=face_mean)
+    H = oracle_for(c, g=g, face_mean=face_mean)
     kw = dict(fixed_cycles=n, nu1=nu[0], nu2=nu[1])
     rho, _ = P.forward(dev(c["q"]))
     rr, _ = H.forward(c["q"], **kw)

@@ -1,0 +1,86 @@
+"""Parity of the unrolled adjoint (dmgs_vjp_unrolled) with its oracle
+(oracle/unrolled.py), through the C ABI.
+
+* rho, qbar, logD_bar and logmua_bar equal the oracle's to 1e-12 of the
+  largest entry (2 and 3 levels of recursion, ragged c = 3 sizes, both face
+  means, V(2,2) and V(2,1), g != 0).
+* qbar equals dmgs_vjp's fixed-cycle pull-back.
+* At 64^3, central differences of the library's own fixed-cycle forward map
+  along random log D and log mua directions match <grad, direction>.
+* Plans the entry point does not take are rejected.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, rel_max, say
+
+pytestmark = pytest.mark.gpu
+
+
+def case(N, seed):
+    from paper_2608_00760_amd import synth
+    logD, logmu = synth.log_coefficients(N, seed, seed + 1)
+    return logD, logmu, synth.normal(N, seed + 2), synth.normal(N, seed + 3)
+
+
+def plan_for(N, logD, logmu, **kw):
+    from paper_2608_00760_amd.solver import Options, Plan
+    P = Plan(Options(N, **kw))
+    P.set_log_coefficients(dev(logD), dev(logmu))
+    return P
+
+
+@pytest.mark.parametrize("N,n,nu,harmonic,g", [(8, 2, (2, 2), False, 0.0), (16, 3, (2, 1), True, 0.4),
+                                               (24, 2, (2, 2), False, 0.0), (48, 2, (1, 2), True, 0.0)])
+def test_matches_oracle(N, n, nu, harmonic, g):
+    from oracle import unrolled
+    say("unrolled N=%d n=%d nu=%s harmonic=%s g=%g" % (N, n, nu, harmonic, g))
+    logD, logmu, q, w = case(N, 200 + N)
+    fm = "harmonic" if harmonic else "arith"
+    P = plan_for(N, logD, logmu, fixed_cycles=n, nu_pre=nu[0], nu_post=nu[1], face_mean=fm, bc_value=g)
+    (rho, (qb, gD, gmu)), info = P.vjp_unrolled(dev(q), dev(w))
+    U = unrolled.Unrolled(np.exp(logD), np.exp(logmu), g=g, harmonic=harmonic)
+    rr, (rqb, rgD, rgmu) = U.vjp(q, w, n, nu[0], nu[1])
+    errs = {name: rel_max(host(a), b) for name, a, b in (("rho", rho, rr), ("qbar", qb, rqb), ("logD", gD, rgD),
+                                                         ("logmua", gmu, rgmu))}
+    say("errors", {k: "%.1e" % v for k, v in errs.items()})
+    assert max(errs.values()) <= 1e-12, errs
+    # the q-part is the fixed-cycle pull-back
+    (qb2, _, _), _ = P.vjp(rho, dev(w), coef_grads=False)
+    assert rel_max(host(qb), host(qb2)) <= 1e-12
+
+
+def test_central_differences_at_64():
+    import torch
+    say("unrolled 64^3 central differences")
+    N, n = 64, 3
+    logD, logmu, q, w = case(N, 64)
+    P = plan_for(N, logD, logmu, fixed_cycles=n)
+    (rho, (qb, gD, gmu)), _ = P.vjp_unrolled(dev(q), dev(w))
+    rng = np.random.default_rng(65)
+    eps = 1e-5
+    for which in ("logD", "logmua"):
+        v = rng.standard_normal(q.shape)
+        vals = []
+        for sgn in (1.0, -1.0):
+            lD = logD + sgn * eps * v if which == "logD" else logD
+            lm = logmu + sgn * eps * v if which == "logmua" else logmu
+            Pe = plan_for(N, lD, lm, fixed_cycles=n)
+            r, _ = Pe.forward(dev(q))
+            vals.append(float((r * dev(w)).sum()))
+            Pe.close()
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        g = float(np.sum(host(gD if which == "logD" else gmu) * v))
+        say(which, "fd %.10e grad %.10e" % (fd, g))
+        assert abs(fd - g) <= 1e-6 * abs(g), (which, fd, g)
+
+
+def test_rejects_other_plans():
+    from paper_2608_00760_amd import _abi
+    say("unrolled rejects")
+    logD, logmu, q, w = case(16, 7)
+    for kw in (dict(), dict(fixed_cycles=2, precision="fp32-in-fp64"), dict(fixed_cycles=2, smoother="wjacobi")):
+        P = plan_for(16, logD, logmu, **kw)
+        with pytest.raises(_abi.DMGSError) as e:
+            P.vjp_unrolled(dev(q), dev(w))
+        assert e.value.status == _abi.DMGS_ERR_INVALID
