@@ -188,6 +188,22 @@ def paper_sweep(args):
             per_class = P.timing_read()
             sm = per_class["smooth"]
             P.timing(False)
+            # the unrolled adjoint (exact derivative of the 15-cycle map in
+            # log D and log mua, through every step) for float64 3D plans
+            unrolled = None
+            if nd == 3 and prec == "fp64" and N <= args.sweep_unrolled_max:
+                P.vjp_unrolled(q, w)
+                torch.cuda.synchronize()
+                tu = []
+                for _ in range(3):
+                    t0u = time.perf_counter()
+                    P.vjp_unrolled(q, w)
+                    tu.append((time.perf_counter() - t0u) * 1e3)
+                tu.sort()
+                nvs = sum(((N >> k) + 1) ** 3 for k in range(P.levels))
+                work = 8 * (15 * (N + 1) ** 3 + (2 * 4 + 1 + 8) * nvs)
+                unrolled = {"ms_median": tu[1], "work_GB": work / 1e9,
+                            "vs_vjp": tu[1] / res["vjp_ms_median"]}
             gbps = sm["bytes"] / (sm["ms"] * 1e-3) / 1e9 if sm["ms"] > 0 else None
             print(json.dumps({"sweep": "fixed 15 V-cycles", "ndim": nd, "N": N, "points": (N + 1) ** nd,
                               "log2_points": round(math.log2((N + 1) ** nd), 2), "precision": prec,
@@ -195,7 +211,8 @@ def paper_sweep(args):
                               "smooth_kernel": {"launches": sm["launches"],
                                                 "avg_us": 1e3 * sm["ms"] / max(sm["launches"], 1),
                                                 "GBps": gbps, "frac": gbps / HBM_PEAK_GBPS if gbps else None},
-                              "finest_level_ms_per_solve": {k: v["ms"] for k, v in per_class.items() if v["launches"]}}),
+                              "finest_level_ms_per_solve": {k: v["ms"] for k, v in per_class.items() if v["launches"]},
+                              "vjp_unrolled": unrolled}),
                   flush=True)
             P.close()
             del logD, logmu, q, w, dq, dd, dm, rho, qbar, drho, gD, gmu
@@ -221,6 +238,8 @@ def main():
     ap.add_argument("--sweep-ndim", type=int, default=3, choices=[2, 3],
                     help="the sweep's grids: 3D (7-point) or 2D (5-point, the paper's comparison setting)")
     ap.add_argument("--sweep-reps", type=int, default=20)
+    ap.add_argument("--sweep-unrolled-max", type=int, default=512,
+                    help="largest N at which the sweep also times the unrolled adjoint (float64 3D)")
     ap.add_argument("--sequential", action="store_true",
                     help="run the forward solve and the VJP one after the other (default: concurrently)")
     ap.add_argument("--serving-requests", type=int, default=512, help="requests in the serving stream (0: skip)")
