@@ -73,6 +73,46 @@ def solve(q, logD, logmua, plan):
     return DMGSSolve.apply(q, logD, logmua, plan)
 
 
+class DMGSSolveUnrolled(torch.autograd.Function):
+    """rho = S_n(q; log D, log mua), the fixed-cycle map of a float64 3D plan
+    with fixed_cycles = n, differentiated exactly through every step
+    (backward = dmgs_vjp_unrolled, which recomputes the cycles from q, so q
+    is saved instead of per-level iterates).  Reverse mode only."""
+
+    @staticmethod
+    def forward(q, logD, logmua, plan):
+        token = next(_token)
+        _set_coefficients(plan, logD.detach().contiguous(), logmua.detach().contiguous(), token)
+        rho, info = plan.forward(q.detach().contiguous())
+        plan._last_forward = (token, info)
+        return rho
+
+    @staticmethod
+    def setup_context(ctx, inputs, output):
+        q, logD, logmua, plan = inputs
+        ctx.plan = plan
+        ctx.token, ctx.info = plan._last_forward
+        ctx.save_for_backward(q, logD, logmua)
+
+    @staticmethod
+    def backward(ctx, rhobar):
+        q, logD, logmua = ctx.saved_tensors
+        plan = ctx.plan
+        _set_coefficients(plan, logD.detach().contiguous(), logmua.detach().contiguous(), ctx.token)
+        need_coef = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+        (_, (qbar, gD, gmu)), _ = plan.vjp_unrolled(q.detach().contiguous(), rhobar.contiguous(), coef_grads=need_coef)
+        return (qbar if ctx.needs_input_grad[0] else None,
+                gD if ctx.needs_input_grad[1] else None,
+                gmu if ctx.needs_input_grad[2] else None,
+                None)
+
+
+def solve_unrolled(q, logD, logmua, plan):
+    """Forward solve on a fixed-cycle float64 3D `plan` whose backward is
+    the unrolled adjoint (see DMGSSolveUnrolled)."""
+    return DMGSSolveUnrolled.apply(q, logD, logmua, plan)
+
+
 class Solver:
     """A plan plus the differentiable call, for one grid size."""
 

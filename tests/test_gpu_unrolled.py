@@ -84,3 +84,20 @@ def test_rejects_other_plans():
         with pytest.raises(_abi.DMGSError) as e:
             P.vjp_unrolled(dev(q), dev(w))
         assert e.value.status == _abi.DMGS_ERR_INVALID
+
+
+def test_autograd_unrolled_backward():
+    """solve_unrolled's backward gives the bits of dmgs_vjp_unrolled."""
+    import torch
+    from paper_2608_00760_amd.autograd import solve_unrolled
+    say("unrolled autograd")
+    N, n = 24, 3
+    logD, logmu, q, w = case(N, 24)
+    P = plan_for(N, logD, logmu, fixed_cycles=n)
+    tq, tD, tm = (dev(a).requires_grad_(True) for a in (q, logD, logmu))
+    rho = solve_unrolled(tq, tD, tm, P)
+    (rho * dev(w)).sum().backward()
+    (rho2, (qb, gD, gmu)), _ = P.vjp_unrolled(dev(q), dev(w))
+    assert bool((rho.detach() == rho2).all()) or rel_max(host(rho.detach()), host(rho2)) <= 1e-14
+    for a, b in ((tq.grad, qb), (tD.grad, gD), (tm.grad, gmu)):
+        assert bool((a == b).all())
