@@ -14,7 +14,11 @@
  * (Sec. 2.3) and the pull-back S^dagger (Sec. 2.4, Eq. (EqcompT)) are exposed
  * with respect to q and, extending the paper (Sec. 4 lists it as future
  * work), with respect to log D and log mua as adjoint-state derivatives of
- * the discrete solution.
+ * the discrete solution.  Also exposed: the two-dimensional 5-point form of
+ * the same solver (opt.ndim = 2), the exact derivative of the fixed-cycle
+ * map through every step (dmgs_vjp_unrolled), and the response and
+ * likelihood epilogue of the reconstruction (Sec. 2.5: dmgs_noise_weights,
+ * dmgs_likelihood_grad).
  *
  * Conventions for every entry point:
  *  - Field arrays are DEVICE pointers to dense C-order float64 arrays of
