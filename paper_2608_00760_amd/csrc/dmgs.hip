@@ -967,6 +967,37 @@ int vcycle2(dmgs_plan P, int k, double** cur, double** other, const double* q, i
         LAUNCHCHK();
         return DMGS_OK;
     }
+    const int first = order ? 1 : 0;
+    // block passes run two workgroups per CU: take them where the tiles fill
+    // whole rounds (a nearly empty last round costs more than they save)
+    const int btiles = ((l.N + kB2 - 1) / kB2) * ((l.N + kB2 - 1) / kB2);
+    const bool bfits = btiles <= 2 * P->ncu || btiles % (2 * P->ncu) == 0;
+    if (k < P->L - 1 && l.N >= P->cfg_2d_block_min && l.N < P->cfg_2d_sweep2_min && bfits && nu_pre_of(P, order) == 2 &&
+        nu_post_of(P, order) == 2) {
+        // mid-size level: each smoothing phase in one launch of LDS tiles,
+        // the defect restricted by the pre-smoothing one
+        const Level& c = P->lev[k + 1];
+        const int ntx = (l.N + kB2 - 1) / kB2;
+        const dim3 grid(ntx * ntx), block(256);
+        const Stencil<double> s = l.stencil<double>(HARM);
+        TIMED(P, k, DMGS_K_SMOOTH, (zero ? 32.0 : 40.0) * l.nv + 8.0 * c.nv, st,
+              if (zero) hipLaunchKernelGGL((k2_block_pass<HARM, 1>), grid, block, 0, st, (const double*)*cur, *other,
+                                           q, (const double*)l.D64, (const double*)l.mu64, (const double*)nullptr,
+                                           c.q64, l.N, s, first, ntx);
+              else hipLaunchKernelGGL((k2_block_pass<HARM, 0>), grid, block, 0, st, (const double*)*cur, *other, q,
+                                      (const double*)l.D64, (const double*)l.mu64, (const double*)nullptr, c.q64, l.N,
+                                      s, first, ntx));
+        std::swap(*cur, *other);
+        double* ccur = c.u64;
+        double* coth = c.t64;
+        TRY(vcycle2<HARM>(P, k + 1, &ccur, &coth, c.q64, order, true, st));
+        TIMED(P, k, DMGS_K_SMOOTH, 40.0 * l.nv + 8.0 * c.nv, st,
+              hipLaunchKernelGGL((k2_block_pass<HARM, 2>), grid, block, 0, st, (const double*)*cur, *other, q,
+                                 (const double*)l.D64, (const double*)l.mu64, (const double*)ccur, (double*)nullptr,
+                                 l.N, s, first, ntx));
+        std::swap(*cur, *other);
+        return DMGS_OK;
+    }
     if (zero) TRY(fill<double>(*cur, l.nv, 0.0, st));
     if (k == P->L - 1) {
         hipLaunchKernelGGL(k2_exact<HARM>, dim3(1), dim3(64), 0, st, q, *cur, (const double*)l.D64,
@@ -974,7 +1005,6 @@ int vcycle2(dmgs_plan P, int k, double** cur, double** other, const double* q, i
         LAUNCHCHK();
         return DMGS_OK;
     }
-    const int first = order ? 1 : 0;
     TRY(sweeps2<HARM>(P, k, cur, other, q, nu_pre_of(P, order), first, st));
     const Level& c = P->lev[k + 1];
     if (l.N >= P->cfg_2d_sweep2_min) {
@@ -1546,6 +1576,7 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     if (const char* e = std::getenv("DMGS_FUSE_MIN")) P->cfg_fuse_min = std::max(8, std::atoi(e));
     if (const char* e = std::getenv("DMGS_2D_SWEEP2_MIN")) P->cfg_2d_sweep2_min = std::max(4, std::atoi(e));
     if (const char* e = std::getenv("DMGS_SWEEP2_FP64")) P->cfg_sweep2_fp64 = std::atoi(e) != 0;
+    if (const char* e = std::getenv("DMGS_2D_BLOCK_MIN")) P->cfg_2d_block_min = std::max(4, std::atoi(e));
     if (const char* e = std::getenv("DMGS_2D_CHUNK")) P->cfg_2d_chunk = std::max(8, std::atoi(e) / 8 * 8);
     if (st != DMGS_OK) {
         free_plan(P);
@@ -1648,6 +1679,7 @@ int make_twin(dmgs_plan P) {
     T->cfg_defect = P->cfg_defect;
     T->cfg_2d_sweep2_min = P->cfg_2d_sweep2_min;
     T->cfg_sweep2_fp64 = P->cfg_sweep2_fp64;
+    T->cfg_2d_block_min = P->cfg_2d_block_min;
     T->ncu = P->ncu;
     T->small2 = P->small2;
     T->cfg_2d_chunk = P->cfg_2d_chunk;

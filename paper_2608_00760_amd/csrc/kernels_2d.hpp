@@ -713,3 +713,100 @@ __global__ __launch_bounds__(1024) void k2_small_vcycle(Small2Args a) {
 }
 
 }  // namespace dmgs
+
+namespace dmgs {
+
+// ---------------------------------------------------------------------------
+// A whole smoothing phase of a mid-size level in one launch: one workgroup
+// per 32 x 32 tile, the tile and a ring of kH2 = 6 vertices staged in LDS
+// (u, q, D, mua), two red-black sweeps (four half-sweeps) with a barrier
+// after each, half-sweep j updating the tile plus a shrinking ring.
+//   MODE 0 / 1 (pre-smoothing from u_in / from zero): the sweeps leave u
+//     final on the tile plus a ring of 2; the pass writes u on the tile and
+//     the restricted defect qc = R (q - A u) of the tile's 16 x 16 coarse
+//     vertices (each forms its nine fine defects from LDS).
+//   MODE 2 (post-smoothing): u_in + I ec (bilinear, the bilinear weights of
+//     k2_prolong_add) is staged, then the sweeps; the pass writes u on the
+//     tile.
+// Only interior grid vertices are updated or written; staged vertices
+// outside the grid hold u = q = mua = 0, D = 1 and are never updated.
+constexpr int kB2 = 32, kH2 = 6, kW2 = kB2 + 2 * kH2;
+
+template <bool HARM, int MODE>
+__global__ __launch_bounds__(256) void k2_block_pass(const double* __restrict__ uin, double* __restrict__ uout,
+                                                     const double* __restrict__ q, const double* __restrict__ D,
+                                                     const double* __restrict__ mu, const double* __restrict__ ec,
+                                                     double* __restrict__ qc, int N, Stencil<double> st, int first,
+                                                     int ntx) {
+    __shared__ double su[kW2 * kW2], sq[kW2 * kW2], sd[kW2 * kW2], sm[kW2 * kW2];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+    const int x0 = tx * kB2 - kH2, y0 = ty * kB2 - kH2;   // grid coordinates of LDS entry (0, 0)
+    const int n = N + 1, Nc = N / 2, nc = Nc + 1;
+    for (int i = tid; i < kW2 * kW2; i += nt) {
+        const int gx = x0 + i / kW2, gy = y0 + i % kW2;
+        const bool in = gx >= 0 && gx <= N && gy >= 0 && gy <= N;
+        const int64_t g = (int64_t)gx * n + gy;
+        sd[i] = in ? D[g] : 1.0;
+        sm[i] = in ? mu[g] : 0.0;
+        sq[i] = in ? q[g] : 0.0;
+        double u = 0.0;
+        if (MODE == 0 || MODE == 2) u = in ? uin[g] : 0.0;
+        if (MODE == 2 && in && gx > 0 && gx < N && gy > 0 && gy < N) {
+            const int X0 = gx >> 1, X1 = (gx + 1) >> 1, Y0 = gy >> 1, Y1 = (gy + 1) >> 1;
+            const double* r0 = ec + (int64_t)X0 * nc;
+            const double* r1 = ec + (int64_t)X1 * nc;
+            double e;
+            if (X0 == X1) e = (Y0 == Y1) ? r0[Y0] : 0.5 * (r0[Y0] + r0[Y1]);
+            else if (Y0 == Y1) e = 0.5 * (r0[Y0] + r1[Y0]);
+            else e = 0.25 * (r0[Y0] + r1[Y0] + r0[Y1] + r1[Y1]);
+            u += e;
+        }
+        su[i] = u;
+    }
+    __syncthreads();
+    const int ring0 = MODE == 2 ? 3 : 5;   // ring of the first half-sweep
+    for (int j = 0; j < 4; j++) {
+        const int colour = (j & 1) ? 1 - first : first, ring = ring0 - j;
+        const int lo = kH2 - ring, hi = kH2 + kB2 + ring;   // local range [lo, hi)
+        for (int i = tid; i < kW2 * kW2; i += nt) {
+            const int lx = i / kW2, ly = i % kW2, gx = x0 + lx, gy = y0 + ly;
+            if (lx < lo || lx >= hi || ly < lo || ly >= hi || ((gx + gy) & 1) != colour) continue;
+            if (gx < 1 || gx > N - 1 || gy < 1 || gy > N - 1) continue;
+            const double Di = sd[i];
+            const double cxm = face<HARM>(Di, sd[i - kW2], st), cxp = face<HARM>(Di, sd[i + kW2], st);
+            const double cym = face<HARM>(Di, sd[i - 1], st), cyp = face<HARM>(Di, sd[i + 1], st);
+            su[i] = (sq[i] + cxm * su[i - kW2] + cxp * su[i + kW2] + cym * su[i - 1] + cyp * su[i + 1]) /
+                    (cxm + cxp + cym + cyp + sm[i]);
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < kB2 * kB2; i += nt) {
+        const int lx = kH2 + i / kB2, ly = kH2 + i % kB2, gx = x0 + lx, gy = y0 + ly;
+        if (gx < 1 || gx > N - 1 || gy < 1 || gy > N - 1) continue;
+        uout[(int64_t)gx * n + gy] = su[lx * kW2 + ly];
+    }
+    if (MODE == 2) return;
+    // restriction of the defect to the tile's coarse vertices (one per thread)
+    for (int c = tid; c < (kB2 / 2) * (kB2 / 2); c += nt) {
+        const int X = tx * (kB2 / 2) + c / (kB2 / 2), Y = ty * (kB2 / 2) + c % (kB2 / 2);
+        if (X < 1 || X > Nc - 1 || Y < 1 || Y > Nc - 1) continue;
+        double acc = 0.0;
+        for (int a = -1; a <= 1; a++) {
+            double row = 0.0;
+            for (int b = -1; b <= 1; b++) {
+                const int i = (2 * X + a - x0) * kW2 + (2 * Y + b - y0);
+                const double Di = sd[i], ui = su[i];
+                const double r = sq[i] - (sm[i] * ui + face<HARM>(Di, sd[i - kW2], st) * (ui - su[i - kW2]) +
+                                          face<HARM>(Di, sd[i + kW2], st) * (ui - su[i + kW2]) +
+                                          face<HARM>(Di, sd[i - 1], st) * (ui - su[i - 1]) +
+                                          face<HARM>(Di, sd[i + 1], st) * (ui - su[i + 1]));
+                row += (b == 0 ? 2.0 : 1.0) * r;
+            }
+            acc += (double)(2 - abs(a)) * row;
+        }
+        qc[(int64_t)X * nc + Y] = acc * (1.0 / 16.0);
+    }
+}
+
+}  // namespace dmgs

@@ -78,6 +78,7 @@ struct dmgs_plan_s {
     int cfg_defect = 2;   // two-sweep pre-smoothing writes the defect: 0 never, 1 from a zero iterate, 2 always
     int cfg_2d_sweep2_min = 1536;  // two-dimensional plans: smallest N of the two-sweep passes
     bool cfg_sweep2_fp64 = true;   // float64 levels use the two-sweep passes (zero boundaries only)
+    int cfg_2d_block_min = 64;     // two-dimensional plans: smallest N of the LDS block passes
     bool bc_zero = true;           // the current solve's boundary value is 0
     int ncu = 256;                 // compute units of the plan's device
     int cfg_2d_chunk = 0;          // ... rows per chunk (0: chosen from the grid size)

@@ -93,6 +93,28 @@ def test_two_sweep_passes_on_every_level(monkeypatch, N, chunk, nu, g, face_mean
     assert rel_max(host(drho), dr) <= 1e-12
 
 
+@pytest.mark.parametrize("N,nu,g,face_mean", [(48, (2, 2), 0.0, "arith"), (96, (2, 2), 0.3, "harmonic"),
+                                              (192, (2, 2), 0.0, "arith"), (96, (2, 1), 0.0, "arith")])
+def test_block_passes_on_every_level(monkeypatch, N, nu, g, face_mean):
+    """The LDS block passes (used on mid-size levels) forced onto every
+    level that smooths, the finest included (g != 0); V(2,1) takes the
+    per-operator path."""
+    monkeypatch.setenv("DMGS_2D_BLOCK_MIN", "4")
+    say("2d block passes N=%d nu=%s g=%g %s" % (N, nu, g, face_mean))
+    c = case(N, 80 + N)
+    n = 3
+    P = plan_for(c, fixed_cycles=n, nu_pre=nu[0], nu_post=nu[1], bc_value=g, face_mean=face_mean)
+    H = oracle_for(c, g=g, face_mean=face_mean)
+    kw = dict(fixed_cycles=n, nu1=nu[0], nu2=nu[1])
+    rho, _ = P.forward(dev(c["q"]))
+    rr, _ = H.forward(c["q"], **kw)
+    assert rel_max(host(rho), rr) <= 1e-12
+    (qb, gD, gmu), _ = P.vjp(rho, dev(c["rhobar"]))
+    (rqb, rgD, rgmu), _ = H.vjp(rr, c["rhobar"], **kw)
+    for a, b in ((qb, rqb), (gD, rgD), (gmu, rgmu)):
+        assert rel_max(host(a), b) <= 1e-12
+
+
 def test_large_grid_fixed_cycles_match_oracle():
     """768^2 cells: the two-sweep passes on levels 0 (and the half-sweeps
     below), against the oracle."""
