@@ -1951,14 +1951,22 @@ int dmgs_vjp_unrolled(dmgs_plan P, const double* q, const double* rhobar, double
         TRY(fill<double>(W.ubar[k], nv, 0.0, st));
     }
     const size_t b0 = l0.nv * sizeof(double);
-    // forward: n cycles, keeping the iterate at the start of each
-    hipLaunchKernelGGL(k_init_iterate<double>, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, W.u0, l0.N, o.bc_value);
-    LAUNCHCHK();
-    for (int c = 0; c < n; c++) {
-        HIPCHK(hipMemcpyAsync(W.ckpt + (int64_t)c * l0.nv, W.u0, b0, hipMemcpyDeviceToDevice, st));
-        TRY(vcycle_taped(P, W, 0, W.u0, q, false, st));
+    // forward: n cycles of the solver's own (fused) V-cycle, keeping the
+    // iterate at the start of each; the reverse pass recomputes each cycle
+    // with the per-operator kernels, whose states agree to rounding
+    {
+        double* cur = rho;
+        double* oth = l0.t64;
+        P->bc_zero = o.bc_value == 0.0;
+        hipLaunchKernelGGL(k_init_iterate<double>, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, cur, l0.N, o.bc_value);
+        LAUNCHCHK();
+        TRY(set_boundary<double>(oth, l0.N, o.bc_value, st));
+        for (int c = 0; c < n; c++) {
+            HIPCHK(hipMemcpyAsync(W.ckpt + (int64_t)c * l0.nv, cur, b0, hipMemcpyDeviceToDevice, st));
+            TRY(vcycle<double>(P, 0, &cur, &oth, q, 0, false, st));
+        }
+        if (cur != rho) HIPCHK(hipMemcpyAsync(rho, cur, b0, hipMemcpyDeviceToDevice, st));
     }
-    HIPCHK(hipMemcpyAsync(rho, W.u0, b0, hipMemcpyDeviceToDevice, st));
     // reverse: the cotangent of the last iterate is rhobar (interior)
     HIPCHK(hipMemcpyAsync(W.ubar[0], rhobar, b0, hipMemcpyDeviceToDevice, st));
     TRY(set_boundary<double>(W.ubar[0], l0.N, 0.0, st));
