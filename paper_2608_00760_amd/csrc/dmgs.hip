@@ -135,8 +135,8 @@ size_t footprint(const dmgs_options* o) {
     bool ir = o->precision == DMGS_FP32_IN_FP64;
     size_t b = 0;
     for (int k = 0; k < s.L; k++) {
-        if (o->ndim == 2) {   // D64, mu64, (u64, q64), t64
-            b += (k > 0 ? 5 : 3) * s.nv[k] * sizeof(double);
+        if (o->ndim == 2) {   // D64, mu64, (u64, q64), t64, (rd64)
+            b += ((k > 0 ? 5 : 3) + (k < s.L - 1 ? 1 : 0)) * s.nv[k] * sizeof(double);
             continue;
         }
         b += 2 * s.nv[k] * sizeof(double);                            // D64, mu64
@@ -168,7 +168,7 @@ void free_plan(dmgs_plan P) {
     if (P->ev_join) (void)hipEventDestroy(P->ev_join);
     for (int k = 0; k < P->L; k++) {
         Level& l = P->lev[k];
-        void* work[] = {l.u64, l.q64, l.t64, l.u32, l.q32, l.t32, l.r32};
+        void* work[] = {l.u64, l.q64, l.t64, l.u32, l.q32, l.t32, l.r32, l.rd64};
         for (void* p : work)
             if (p) (void)hipFree(p);
         if (!P->owns_coef) continue;
@@ -897,7 +897,8 @@ int half_sweep2(dmgs_plan P, int k, double* u, const double* q, int colour, hipS
 // first pass when there is one).
 template <bool HARM>
 int sweeps2(dmgs_plan P, int k, double** cur, double** other, const double* q, int count, int first, hipStream_t st,
-            const double* ec = nullptr) {
+            const double* ec = nullptr, double* rout = nullptr, bool* rdone = nullptr) {
+    if (rdone) *rdone = false;
     const Level& l = P->lev[k];
     int i = 0;
     const bool pass = l.N >= P->cfg_2d_sweep2_min;
@@ -917,17 +918,27 @@ int sweeps2(dmgs_plan P, int k, double** cur, double** other, const double* q, i
         const unsigned blocks = (unsigned)((ntiles * nchunks + 3) / 4);
         for (; count - i >= 2; i += 2) {
             // reads u, q, D, mua (and the coarse correction); writes u
-            if (ec) {
+            if (rout && count - i == 2 && !ec) {
+                // the phase's last pass also writes the defect of its result
+                const int ntd = (l.N - 1 + kTile2D - 1) / kTile2D;
+                const int ncd = std::max(1, (l.N - 4 + chunk - 1) / chunk);
+                TIMED(P, k, DMGS_K_SMOOTH, 48.0 * l.nv, st,
+                      hipLaunchKernelGGL((k2_sweep2<HARM, false, true>), dim3((unsigned)((ntd * ncd + 3) / 4)), dim3(256),
+                                         0, st, (const double*)*cur, *other, q, (const double*)l.D64,
+                                         (const double*)l.mu64, (const double*)nullptr, rout, l.N,
+                                         l.stencil<double>(HARM), first, chunk, ntd, ncd));
+                *rdone = true;
+            } else if (ec) {
                 TIMED(P, k, DMGS_K_SMOOTH, 40.0 * l.nv + 8.0 * P->lev[k + 1].nv, st,
                       hipLaunchKernelGGL((k2_sweep2<HARM, true>), dim3(blocks), dim3(256), 0, st, (const double*)*cur,
-                                         *other, q, (const double*)l.D64, (const double*)l.mu64, ec, l.N,
-                                         l.stencil<double>(HARM), first, chunk, ntiles, nchunks));
+                                         *other, q, (const double*)l.D64, (const double*)l.mu64, ec, (double*)nullptr,
+                                         l.N, l.stencil<double>(HARM), first, chunk, ntiles, nchunks));
                 ec = nullptr;
             } else {
                 TIMED(P, k, DMGS_K_SMOOTH, 40.0 * l.nv, st,
                       hipLaunchKernelGGL((k2_sweep2<HARM, false>), dim3(blocks), dim3(256), 0, st, (const double*)*cur,
                                          *other, q, (const double*)l.D64, (const double*)l.mu64, (const double*)nullptr,
-                                         l.N, l.stencil<double>(HARM), first, chunk, ntiles, nchunks));
+                                         (double*)nullptr, l.N, l.stencil<double>(HARM), first, chunk, ntiles, nchunks));
             }
             std::swap(*cur, *other);
         }
@@ -1005,9 +1016,16 @@ int vcycle2(dmgs_plan P, int k, double** cur, double** other, const double* q, i
         LAUNCHCHK();
         return DMGS_OK;
     }
-    TRY(sweeps2<HARM>(P, k, cur, other, q, nu_pre_of(P, order), first, st));
+    bool rdone = false;
+    TRY(sweeps2<HARM>(P, k, cur, other, q, nu_pre_of(P, order), first, st, nullptr,
+                      P->cfg_2d_defect ? l.rd64 : nullptr, &rdone));
     const Level& c = P->lev[k + 1];
-    if (l.N >= P->cfg_2d_sweep2_min) {
+    if (rdone) {
+        // restrict the defect the last pass wrote
+        TIMED(P, k, DMGS_K_DEFECT_RESTRICT, 8.0 * l.nv + 8.0 * c.nv, st,
+              hipLaunchKernelGGL(k2_restrict_r, dim3(vertex_grid(c.nv)), dim3(kBlock), 0, st, (const double*)l.rd64,
+                                 c.q64, l.N));
+    } else if (l.N >= P->cfg_2d_sweep2_min) {
         // row-streaming form: coarse rows in chunks of cx (a multiple of 4)
         const int ntiles = (c.N - 1 + kTileR - 1) / kTileR;
         const int cx = (int)std::min<int64_t>(256, std::max<int64_t>(16, ((int64_t)(c.N - 1) * ntiles / 4096 + 3) / 4 * 4));
@@ -1444,7 +1462,7 @@ size_t dmgs_forward_vjp_workspace_bytes(const dmgs_options* o) {
     size_t b = 0;
     for (int k = 0; k < s.L; k++) {
         if (ir) b += (k < s.L - 1 ? 4 : 3) * s.nv[k] * sizeof(float);
-        else b += (k > 0 ? 3 : 1) * s.nv[k] * sizeof(double);
+        else b += ((k > 0 ? 3 : 1) + (o->ndim == 2 && k < s.L - 1 ? 1 : 0)) * s.nv[k] * sizeof(double);
     }
     b += (ir ? 2 : 1) * s.nv[0] * sizeof(double);
     b += kMaxPartials * sizeof(double) + 4 * sizeof(double);
@@ -1494,6 +1512,7 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
             if (k > 0 && st == DMGS_OK) st = dalloc(P, &l.u64, l.nv);
             if (k > 0 && st == DMGS_OK) st = dalloc(P, &l.q64, l.nv);
             if (st == DMGS_OK) st = dalloc(P, &l.t64, l.nv);
+            if (o->ndim == 2 && k < s.L - 1 && st == DMGS_OK) st = dalloc(P, &l.rd64, l.nv);
         }
     }
     if (st == DMGS_OK) st = dalloc(P, &P->scratch64, P->lev[0].nv);
@@ -1577,6 +1596,7 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     if (const char* e = std::getenv("DMGS_2D_SWEEP2_MIN")) P->cfg_2d_sweep2_min = std::max(4, std::atoi(e));
     if (const char* e = std::getenv("DMGS_SWEEP2_FP64")) P->cfg_sweep2_fp64 = std::atoi(e) != 0;
     if (const char* e = std::getenv("DMGS_2D_BLOCK_MIN")) P->cfg_2d_block_min = std::max(4, std::atoi(e));
+    if (const char* e = std::getenv("DMGS_2D_DEFECT")) P->cfg_2d_defect = std::atoi(e) != 0;
     if (const char* e = std::getenv("DMGS_2D_CHUNK")) P->cfg_2d_chunk = std::max(8, std::atoi(e) / 8 * 8);
     if (st != DMGS_OK) {
         free_plan(P);
@@ -1680,6 +1700,7 @@ int make_twin(dmgs_plan P) {
     T->cfg_2d_sweep2_min = P->cfg_2d_sweep2_min;
     T->cfg_sweep2_fp64 = P->cfg_sweep2_fp64;
     T->cfg_2d_block_min = P->cfg_2d_block_min;
+    T->cfg_2d_defect = P->cfg_2d_defect;
     T->ncu = P->ncu;
     T->small2 = P->small2;
     T->cfg_2d_chunk = P->cfg_2d_chunk;
@@ -1692,7 +1713,7 @@ int make_twin(dmgs_plan P) {
         const Level& pl = P->lev[k];
         Level& l = T->lev[k];
         l = pl;   // geometry and coefficient arrays
-        l.u64 = l.q64 = l.t64 = nullptr;
+        l.u64 = l.q64 = l.t64 = l.rd64 = nullptr;
         l.u32 = l.q32 = l.t32 = l.r32 = nullptr;
         if (ir) {
             if (st == DMGS_OK) st = dalloc(T, &l.u32, l.nv);
@@ -1703,6 +1724,7 @@ int make_twin(dmgs_plan P) {
             if (k > 0 && st == DMGS_OK) st = dalloc(T, &l.u64, l.nv);
             if (k > 0 && st == DMGS_OK) st = dalloc(T, &l.q64, l.nv);
             if (st == DMGS_OK) st = dalloc(T, &l.t64, l.nv);
+            if (is2d(P) && k < P->L - 1 && st == DMGS_OK) st = dalloc(T, &l.rd64, l.nv);
         }
         void* ps[] = {l.u64, l.q64, l.t64, l.u32, l.q32, l.t32, l.r32};
         size_t sz[] = {8, 8, 8, 4, 4, 4, 4};

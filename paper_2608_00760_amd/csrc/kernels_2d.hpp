@@ -311,48 +311,57 @@ namespace dmgs {
 // ---------------------------------------------------------------------------
 // Two red-black sweeps per pass, out of place (u_in -> u_out).
 //
-// One wave per tile of kTile2 interior columns [ts, ts + kTile2); lane t
-// holds the column pair (yb + 2t, yb + 2t + 1), yb = ts - kRing2, so a wave
-// covers the tile and a ring of kRing2 = 4 columns on each side.  A chunk of
-// rows [xa, xb) is marched one row per step; the four colour updates of the
-// two sweeps run as a pipeline: at step s, stage j (j = 1..4) updates row
-// s - j + 1, which then sees its neighbours exactly as the sequential order
-// leaves them (a stage never changes the other colour).  Stage j is applied
-// on the tile plus a ring of 4 - j columns (neighbouring tiles recompute
-// these), and its rows reach 4 - j beyond the chunk, so the output rows
-// [xa, xb) depend only on rows [xa - 4, xb + 4) of u_in.  Each lane keeps
-// eight rows of its two columns (u, D, q, mua) in a register ring indexed by
-// row & 7 (the march is unrolled by 8, so ring slots are compile-time);
-// in-row neighbours of the other column come from the adjacent lane by a
-// shuffle.  A row is loaded three steps before the first stage reads it.
+// One wave per tile of TILE interior columns [ts, ts + TILE); lane t holds
+// the column pair (yb + 2t, yb + 2t + 1), yb = ts - RING, so a wave covers
+// the tile and a ring of RING columns on each side (TILE = 128 - 2 RING).
+// A chunk of rows [xa, xb) is marched one row per step; the four colour
+// updates of the two sweeps run as a pipeline: at step s, stage j (j =
+// 1..4) updates row s - j + 1, which then sees its neighbours exactly as the
+// sequential order leaves them (a stage never changes the other colour).
+// Stage j is applied on the tile plus a ring of RING - j columns
+// (neighbouring tiles recompute these), and its rows reach RING - j beyond
+// the chunk, so the output rows depend only on rows [xa - RING, xb + RING)
+// of u_in.  Each lane keeps eight rows of its two columns (u, D, q, mua) in
+// a register ring indexed by row & 7 (the march is unrolled by 8, so ring
+// slots are compile-time); in-row neighbours of the other column come from
+// the adjacent lane by a shuffle.  A row is loaded three steps before the
+// first stage reads it and enters its ring slot at the end of the step.
 // Only interior vertices of the tile are written; u_out's boundary keeps
-// its values.  Rows: chunk 0 is [1, 3 + chunk), chunk c > 0 is
-// [3 + c chunk, 3 + (c + 1) chunk), cut at N.
-constexpr int kTile2 = 120, kRing2 = 4;
-
+// its values.  Rows: with O = RING - 1, chunk 0 is [1, O + chunk) and chunk
+// c > 0 is [O + c chunk, O + (c + 1) chunk), cut at N (chunk a multiple of
+// 8, so that every march starts at a multiple of 8).
 //
 // PROLONG (post-smoothing): the pass smooths u_in + I ec (Sec. 2.3.3,
 // bilinear, ec on the next coarser level with a zero boundary); the
 // correction of a row is added at the step before its first use, from
 // coarse values loaded with the row.
-template <bool HARM, bool PROLONG>
+//
+// DEFECT (pre-smoothing): RING = 5, so the final values are known on the
+// tile plus a ring of 1 and on one row beyond the chunk; at step s, once
+// row s - 3 is final, the pass also writes the defect r = q - A u of row
+// s - 4 on the tile (Sec. 2.3.2), for the restriction to read.
+template <bool DEFECT> struct Sweep2Shape2 {
+    static constexpr int RING = DEFECT ? 5 : 4, TILE = 2 * kWave - 2 * RING;
+};
+constexpr int kTile2 = Sweep2Shape2<false>::TILE, kTile2D = Sweep2Shape2<true>::TILE;
+
+template <bool HARM, bool PROLONG, bool DEFECT = false>
 __global__ __launch_bounds__(256) void k2_sweep2(const double* __restrict__ uin, double* __restrict__ uout,
                                                  const double* __restrict__ q, const double* __restrict__ D,
-                                                 const double* __restrict__ mu, const double* __restrict__ ec, int N,
-                                                 Stencil<double> st, int first_colour, int chunk, int ntiles,
-                                                 int nchunks) {
+                                                 const double* __restrict__ mu, const double* __restrict__ ec,
+                                                 double* __restrict__ rout, int N, Stencil<double> st,
+                                                 int first_colour, int chunk, int ntiles, int nchunks) {
+    static_assert(!(PROLONG && DEFECT), "the defect is formed after pre-smoothing only");
+    constexpr int RING = Sweep2Shape2<DEFECT>::RING, TILE = Sweep2Shape2<DEFECT>::TILE, O = RING - 1;
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int tile = wave % ntiles, ch = wave / ntiles;
     if (ch >= nchunks) return;   // whole waves exit
     const int n = N + 1;
-    const int ts = 1 + tile * kTile2;
-    const int yb = ts - kRing2;
+    const int ts = 1 + tile * TILE;
+    const int yb = ts - RING;
     const int ya = yb + 2 * lane, yo = ya + 1;   // this lane's columns
-    // chunk 0 holds rows [1, 3 + chunk), chunk c > 0 rows [3 + c chunk,
-    // 3 + (c + 1) chunk): with chunk a multiple of 8 every march starts at
-    // a multiple of 8, which the unrolled ring needs
-    const int xa = ch == 0 ? 1 : 3 + ch * chunk, xb = min(N, 3 + (ch + 1) * chunk);
+    const int xa = ch == 0 ? 1 : O + ch * chunk, xb = min(N, O + (ch + 1) * chunk);
     // rows and columns outside the grid are read clamped to its edge: no
     // update that is kept reads them (an updated interior vertex has all its
     // neighbours in the grid), and unconditional loads let the compiler wait
@@ -367,25 +376,36 @@ __global__ __launch_bounds__(256) void k2_sweep2(const double* __restrict__ uin,
     // (clamped separately: on the left edge the lane of columns (-1, 0) must
     // take column 0 of ec, which is 0, for y = 0)
     const int C0 = min(max(ya >> 1, 0), Nc), C1 = min(max((ya >> 1) + 1, 0), Nc);
+    struct Row {
+        double ua, uo, da, dd, qa, qo, ma, mo, e00, e01, e10, e11;
+    };
     // 32-bit element offsets (a grid has at most 16385^2 < 2^32 vertices)
-    auto load_row = [&](int r, int sl) __attribute__((always_inline)) {
+    auto fetch_row = [&](int r) __attribute__((always_inline)) {
+        Row t;
         const uint32_t b = (uint32_t)min(max(r, 0), N) * (uint32_t)n;
-        ua[sl] = uin[b + yca];
-        uo[sl] = uin[b + yco];
-        da[sl] = D[b + yca];
-        dd[sl] = D[b + yco];
-        qa[sl] = q[b + yca];
-        qo[sl] = q[b + yco];
-        ma[sl] = mu[b + yca];
-        mo[sl] = mu[b + yco];
+        t.ua = uin[b + yca];
+        t.uo = uin[b + yco];
+        t.da = D[b + yca];
+        t.dd = D[b + yco];
+        t.qa = q[b + yca];
+        t.qo = q[b + yco];
+        t.ma = mu[b + yca];
+        t.mo = mu[b + yco];
+        t.e00 = t.e01 = t.e10 = t.e11 = 0.0;
         if (PROLONG) {
             const int rc = min(max(r, 0), N);
             const uint32_t b0 = (uint32_t)(rc >> 1) * (uint32_t)nc, b1 = (uint32_t)min((rc + 1) >> 1, Nc) * (uint32_t)nc;
-            e00[sl] = ec[b0 + C0];
-            e01[sl] = ec[b0 + C1];
-            e10[sl] = ec[b1 + C0];
-            e11[sl] = ec[b1 + C1];
+            t.e00 = ec[b0 + C0];
+            t.e01 = ec[b0 + C1];
+            t.e10 = ec[b1 + C0];
+            t.e11 = ec[b1 + C1];
         }
+        return t;
+    };
+    auto store_row = [&](const Row& t, int sl) __attribute__((always_inline)) {
+        ua[sl] = t.ua; uo[sl] = t.uo; da[sl] = t.da; dd[sl] = t.dd;
+        qa[sl] = t.qa; qo[sl] = t.qo; ma[sl] = t.ma; mo[sl] = t.mo;
+        if (PROLONG) { e00[sl] = t.e00; e01[sl] = t.e01; e10[sl] = t.e10; e11[sl] = t.e11; }
     };
     // u += I ec on row r (the bilinear weights of k2_prolong_add; the
     // boundary gets 0, as ec vanishes there)
@@ -419,37 +439,77 @@ __global__ __launch_bounds__(256) void k2_sweep2(const double* __restrict__ uin,
         const double qi = odd ? qo[sl] : qa[sl], mi = odd ? mo[sl] : ma[sl];
         const double v = (qi + cxm * um + cxp * up + cym * ul + cyp * ur) / (cxm + cxp + cym + cyp + mi);
         const int y = odd ? yo : ya;
-        const bool act = r >= 1 && r <= N - 1 && y >= max(1, ts - ring) && y <= min(N - 1, ts + kTile2 - 1 + ring);
+        const bool act = r >= 1 && r <= N - 1 && y >= max(1, ts - ring) && y <= min(N - 1, ts + TILE - 1 + ring);
         ua[sl] = (act && !odd) ? v : ua[sl];
         uo[sl] = (act && odd) ? v : uo[sl];
     };
+    // defect of row r (slot sl, final rows r -1 / r + 1 in slots sm / sp) on
+    // the tile, in the order of defect2_at
+    auto defect_row = [&](int r, int sl, int sm, int sp) __attribute__((always_inline)) {
+        const double uL = __shfl_up(uo[sl], 1, kWave), dL = __shfl_up(dd[sl], 1, kWave);       // column ya - 1
+        const double uR = __shfl_down(ua[sl], 1, kWave), dR = __shfl_down(da[sl], 1, kWave);   // column yo + 1
+        if (r < xa || r >= xb) return;
+        const uint32_t b = (uint32_t)r * (uint32_t)n;
+        const double Da = da[sl], u_a = ua[sl];
+        const double Do = dd[sl], u_o = uo[sl];
+        const double ra = qa[sl] - (ma[sl] * u_a + face<HARM>(Da, da[sm], st) * (u_a - ua[sm]) +
+                                    face<HARM>(Da, da[sp], st) * (u_a - ua[sp]) + face<HARM>(Da, dL, st) * (u_a - uL) +
+                                    face<HARM>(Da, Do, st) * (u_a - u_o));
+        const double ro = qo[sl] - (mo[sl] * u_o + face<HARM>(Do, dd[sm], st) * (u_o - uo[sm]) +
+                                    face<HARM>(Do, dd[sp], st) * (u_o - uo[sp]) + face<HARM>(Do, Da, st) * (u_o - u_a) +
+                                    face<HARM>(Do, dR, st) * (u_o - uR));
+        if (ya >= ts && ya < ts + TILE && ya <= N - 1) rout[b + ya] = ra;
+        if (yo >= ts && yo < ts + TILE && yo <= N - 1) rout[b + yo] = ro;
+    };
     const int c1 = first_colour, c2 = 1 - first_colour;
-    const int sb = (xa - 3) & ~7;   // first step, a multiple of 8 (chunk 0 starts a few harmless steps early)
-    const int se = xb + 3;          // one past the last step
+    const int sb = (xa - O) & ~7;   // first step, a multiple of 8 (chunk 0 starts a few harmless steps early)
+    const int se = xb + O;          // one past the last step
     // rows sb - 4 .. sb + 2 before the first step
 #pragma unroll
-    for (int k = -4; k <= 2; k++) load_row(sb + k, k & 7);
+    for (int k = -4; k <= 2; k++) store_row(fetch_row(sb + k), k & 7);
 #pragma unroll
     for (int k = -4; k <= 0; k++) correct_row(sb + k, k & 7);
     for (int s8 = sb; s8 < se; s8 += 8) {
 #pragma unroll
         for (int k = 0; k < 8; k++) {
             const int s = s8 + k;
-            load_row(s + 3, (k + 3) & 7);
+            const Row next = fetch_row(s + 3);   // enters slot (k + 3) & 7 (row s - 5's) at the end of the step
             correct_row(s + 1, (k + 1) & 7);   // first read by stage 1 below
-            stage(s, k & 7, (k - 1) & 7, (k + 1) & 7, c1, 3);
-            stage(s - 1, (k - 1) & 7, (k - 2) & 7, k & 7, c2, 2);
-            stage(s - 2, (k - 2) & 7, (k - 3) & 7, (k - 1) & 7, c1, 1);
-            stage(s - 3, (k - 3) & 7, (k - 4) & 7, (k - 2) & 7, c2, 0);
+            stage(s, k & 7, (k - 1) & 7, (k + 1) & 7, c1, RING - 1);
+            stage(s - 1, (k - 1) & 7, (k - 2) & 7, k & 7, c2, RING - 2);
+            stage(s - 2, (k - 2) & 7, (k - 3) & 7, (k - 1) & 7, c1, RING - 3);
+            stage(s - 3, (k - 3) & 7, (k - 4) & 7, (k - 2) & 7, c2, RING - 4);
             const int r = s - 3;
             if (r >= xa && r < xb) {
                 const uint32_t b = (uint32_t)r * (uint32_t)n;
                 const int sl = (k - 3) & 7;
-                if (ya >= ts && ya < ts + kTile2 && ya <= N - 1) uout[b + ya] = ua[sl];
-                if (yo >= ts && yo < ts + kTile2 && yo <= N - 1) uout[b + yo] = uo[sl];
+                if (ya >= ts && ya < ts + TILE && ya <= N - 1) uout[b + ya] = ua[sl];
+                if (yo >= ts && yo < ts + TILE && yo <= N - 1) uout[b + yo] = uo[sl];
             }
+            if (DEFECT) defect_row(s - 4, (k - 4) & 7, (k - 5) & 7, (k - 3) & 7);
+            store_row(next, (k + 3) & 7);
         }
     }
+}
+
+// qc = R r on coarse interior vertices from a fine defect r written by a
+// DEFECT pass (0 on the coarse boundary): (1/16)(1,2,1) x (1,2,1), summed
+// in the order of k2_defect_restrict.
+__global__ void k2_restrict_r(const double* __restrict__ r, double* __restrict__ qc, int Nf) {
+    const int Nc = Nf / 2, nf = Nf + 1, nc = Nc + 1;
+    const int64_t v = item_of_thread2();
+    if (v >= (int64_t)nc * nc) return;
+    const int X = (int)(v / nc), Y = (int)(v % nc);
+    if (!interior2(Nc, X, Y)) {
+        qc[v] = 0.0;
+        return;
+    }
+    double acc = 0.0;
+    for (int a = -1; a <= 1; a++) {
+        const double* row = r + (int64_t)(2 * X + a) * nf + 2 * Y;
+        acc += (double)(2 - abs(a)) * (row[-1] + 2.0 * row[0] + row[1]);
+    }
+    qc[v] = acc * (1.0 / 16.0);
 }
 
 }  // namespace dmgs

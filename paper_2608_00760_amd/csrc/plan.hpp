@@ -23,6 +23,7 @@ struct Level {
     double *u64 = nullptr, *q64 = nullptr, *t64 = nullptr;
     float *u32 = nullptr, *q32 = nullptr, *t32 = nullptr;
     float* r32 = nullptr;   // fine defect written by pre-smoothing passes (iterative-refinement plans, not the coarsest)
+    double* rd64 = nullptr; // ... two-dimensional plans (not the coarsest)
 
     template <class T> Stencil<T> stencil(int harmonic) const {
         Stencil<T> s;
@@ -79,6 +80,7 @@ struct dmgs_plan_s {
     int cfg_2d_sweep2_min = 1536;  // two-dimensional plans: smallest N of the two-sweep passes
     bool cfg_sweep2_fp64 = true;   // float64 levels use the two-sweep passes (zero boundaries only)
     int cfg_2d_block_min = 64;     // two-dimensional plans: smallest N of the LDS block passes
+    bool cfg_2d_defect = true;     // ... the last pre-smoothing pass writes the defect
     bool bc_zero = true;           // the current solve's boundary value is 0
     int ncu = 256;                 // compute units of the plan's device
     int cfg_2d_chunk = 0;          // ... rows per chunk (0: chosen from the grid size)

@@ -86,7 +86,7 @@ def test_two_dimensional_options(abi):
     o.ndim = 2
     nv = 8193 ** 2
     b = lib.dmgs_workspace_bytes(C.byref(o))
-    assert 4 * nv * 8 <= b < 6 * nv * 8           # D, mu, partner, scratch (+ the coarse levels)
+    assert 4 * nv * 8 <= b < 7 * nv * 8           # D, mu, partner, defect, scratch (+ the coarse levels)
     for field, value in (("ndim", 4), ("precision", abi.DMGS_FP32_IN_FP64), ("smoother", abi.DMGS_WJACOBI)):
         ob = abi.default_options(64)
         ob.ndim = 2
