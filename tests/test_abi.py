@@ -84,9 +84,14 @@ def test_two_dimensional_options(abi):
     lib = abi.lib()
     o = abi.default_options(8192)
     o.ndim = 2
-    nv = 8193 ** 2
     b = lib.dmgs_workspace_bytes(C.byref(o))
-    assert 4 * nv * 8 <= b < 7 * nv * 8           # D, mu, partner, defect, scratch (+ the coarse levels)
+    # per level D, mu, partner; below the finest u and q; above the coarsest
+    # the written defect; one float64 scratch field of the finest size; and
+    # under 1 MiB of partial sums and the coarsest inverse
+    nvs = [(8192 // 2 ** k + 1) ** 2 for k in range(13)]     # 8192 .. 2
+    L = len(nvs)
+    arrays = sum(((5 if k else 3) + (1 if k < L - 1 else 0)) * nv * 8 for k, nv in enumerate(nvs)) + nvs[0] * 8
+    assert arrays <= b < arrays + 2 ** 20
     for field, value in (("ndim", 4), ("precision", abi.DMGS_FP32_IN_FP64), ("smoother", abi.DMGS_WJACOBI)):
         ob = abi.default_options(64)
         ob.ndim = 2
