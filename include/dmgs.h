@@ -37,6 +37,12 @@
  *    still run when it returns).  With `info` given, every call waits at the
  *    end for all of its work, to fill in the final residual and the device
  *    time.  With fixed_cycles > 0 a solve does not wait otherwise.
+ *  - Graph capture: with fixed_cycles > 0, timing off and info == NULL,
+ *    dmgs_forward, dmgs_jvp and dmgs_vjp neither wait nor allocate, so a
+ *    caller may capture them into a HIP graph on its stream and replay it;
+ *    each replay repeats the captured pointers and gives the bits of the
+ *    eager calls.  Tolerance-mode solves read residual norms on the host
+ *    between cycles and cannot be captured.
  *  - A plan may be used by one host thread and one stream at a time; use
  *    several plans for concurrency.
  *  - Every function returns a dmgs_status; no C++ exception crosses the ABI.
