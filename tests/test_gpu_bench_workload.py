@@ -15,6 +15,8 @@ runs them one after the other, both to a relative residual of 1e-10.
   gradients match the oracle's gradient formula applied to the GPU's own u
   and lam to 1e-12 (the formula is pointwise, so this checks every vertex
   of the gradient pass at full size).
+* The likelihood gradient (forward solve, epilogue, pull-back, gradients)
+  matches the oracle's: H and chi2 to 1e-9, gradients to 1e-8.
 """
 import numpy as np
 import pytest
@@ -85,4 +87,33 @@ def test_float64_sequential(workload):
     (qb, gD, gmu), vinfo = P.vjp(rho, dev(c["rhobar"]))
     assert info["rel_residual"] <= 1e-10 and vinfo["rel_residual"] <= 1e-10
     check(H, c, oracle, host(rho), host(qb), host(gD), host(gmu), "fp64")
+    P.close()
+
+
+def test_likelihood_gradient(workload):
+    """The likelihood leg of the bench at 256^3: forward solve, epilogue,
+    pull-back and gradients (float32-in-float64 to 1e-10) against the
+    oracle's, with data drawn from the noise model around the oracle's
+    response and a 3-vertex edge mask."""
+    from oracle import likelihood
+    from paper_2608_00760_amd.solver import Options, Plan
+    c, H, (rr, _, _, _) = workload[0], workload[1], workload[2]
+    say("256^3 likelihood gradient")
+    Le = rr * c["mua"]
+    sigma = np.maximum(0.05 * Le, 0.01 * Le.max())
+    d = Le + sigma * np.random.default_rng(3005).standard_normal(Le.shape)
+    w = likelihood.noise_weights(Le, 3)
+    P = Plan(Options(N, precision="fp32-in-fp64", rtol=1e-10, max_cycles=100))
+    P.set_log_coefficients(dev(c["logD"]), dev(c["logmua"]))
+    (rho, val, (qb, gD, gmu)), fi, vi = P.likelihood_grad(dev(c["q"]), dev(d), dev(w))
+    assert fi["status"] == 0 and vi["status"] == 0
+    _, (Hv, chi2), (rqb, rgD, rgmu) = likelihood.likelihood_grad(H, c["mua"], c["q"], d, w, rtol=1e-13,
+                                                                 max_cycles=300)
+    errs = {"H": abs(val["H"] - Hv) / Hv, "chi2": abs(val["chi2"] - chi2) / chi2, "q": rel_max(host(qb), rqb),
+            "logD": rel_max(host(gD), rgD), "logmua": rel_max(host(gmu), rgmu)}
+    say("chi2 %.4f nvox %d" % (val["chi2"], val["nvox"]), {k: "%.2e" % v for k, v in errs.items()})
+    assert errs["H"] <= 1e-9 and errs["chi2"] <= 1e-9
+    assert max(errs["q"], errs["logD"], errs["logmua"]) <= 1e-8
+    assert val["nvox"] == int(np.count_nonzero(w > 0))
+    assert abs(val["chi2"] - 1.0) <= 4.0 * np.sqrt(2.0 / val["nvox"])
     P.close()

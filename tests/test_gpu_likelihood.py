@@ -17,31 +17,39 @@ from gpu_util import dev, host, rel_max, say
 pytestmark = pytest.mark.gpu
 
 
-def setup(N, seed, ndim=3, mask=3, **opts):
-    from paper_2608_00760_amd import synth
-    from paper_2608_00760_amd.solver import Options, Plan
-    from oracle import likelihood
-    c = synth.grf_case(N, seed, ndim=ndim)
-    P = Plan(Options(N, ndim=ndim, **opts))
-    P.set_coefficients(dev(c["D"]), dev(c["mua"]))
-    rho, _ = P.forward(dev(c["q"]))
-    Le = host(rho) * c["mua"]
-    sigma = np.maximum(0.05 * Le, 0.01 * Le.max())
-    d = Le + sigma * np.random.default_rng(seed + 9).standard_normal(Le.shape)
-    w = likelihood.noise_weights(Le, mask)
-    return c, P, Le, d, w
-
-
 def oracle_hier(c, ndim):
     from oracle import ref, ref2d
     return ref.Hierarchy(c["D"], c["mua"]) if ndim == 3 else ref2d.Hierarchy2D(c["D"], c["mua"])
+
+
+def setup(N, seed, ndim=3, mask=3):
+    """Inputs, the oracle hierarchy, and data drawn from the noise model
+    around the oracle's response (nothing here comes from the GPU)."""
+    from paper_2608_00760_amd import synth
+    from oracle import likelihood
+    c = synth.grf_case(N, seed, ndim=ndim)
+    H = oracle_hier(c, ndim)
+    rr, _ = H.forward(c["q"], rtol=1e-12, max_cycles=300)
+    Le = rr * c["mua"]
+    sigma = np.maximum(0.05 * Le, 0.01 * Le.max())
+    d = Le + sigma * np.random.default_rng(seed + 9).standard_normal(Le.shape)
+    w = likelihood.noise_weights(Le, mask)
+    return c, H, Le, d, w
+
+
+def plan_for(c, N, ndim=3, **opts):
+    from paper_2608_00760_amd.solver import Options, Plan
+    P = Plan(Options(N, ndim=ndim, **opts))
+    P.set_coefficients(dev(c["D"]), dev(c["mua"]))
+    return P
 
 
 def test_noise_weights_match_oracle():
     from oracle import likelihood
     say("noise weights")
     for ndim, N, mask in ((3, 48, 3), (2, 96, 4)):
-        c, P, Le, d, w = setup(N, 40 + N, ndim=ndim, mask=mask)
+        c, _, Le, d, w = setup(N, 40 + N, ndim=ndim, mask=mask)
+        P = plan_for(c, N, ndim)
         wg = host(P.noise_weights(dev(Le), mask))
         assert rel_max(wg, w) <= 1e-15
         assert (wg[w == 0] == 0).all()
@@ -51,12 +59,9 @@ def test_noise_weights_match_oracle():
 def test_fixed_cycles_match_oracle(ndim, N, n):
     from oracle import likelihood
     say("likelihood fixed ndim=%d N=%d n=%d" % (ndim, N, n))
-    c, P0, Le, d, w = setup(N, 70 + N, ndim=ndim)
-    from paper_2608_00760_amd.solver import Options, Plan
-    P = Plan(Options(N, ndim=ndim, fixed_cycles=n))
-    P.set_coefficients(dev(c["D"]), dev(c["mua"]))
+    c, H, Le, d, w = setup(N, 70 + N, ndim=ndim)
+    P = plan_for(c, N, ndim, fixed_cycles=n)
     (rho, val, (qb, gD, gmu)), fi, vi = P.likelihood_grad(dev(c["q"]), dev(d), dev(w))
-    H = oracle_hier(c, ndim)
     rr, (Hv, chi2), (rqb, rgD, rgmu) = likelihood.likelihood_grad(H, c["mua"], c["q"], d, w, fixed_cycles=n)
     say("H %.6e chi2 %.4f nvox %d" % (val["H"], val["chi2"], val["nvox"]))
     assert fi["cycles"] == n and vi["cycles"] == n
@@ -71,10 +76,10 @@ def test_tolerance_mode_matches_oracle():
     from oracle import likelihood
     say("likelihood tolerance fp32-in-fp64 N=64")
     N = 64
-    c, P, Le, d, w = setup(N, 900, precision="fp32-in-fp64")
+    c, H, Le, d, w = setup(N, 900)
+    P = plan_for(c, N, precision="fp32-in-fp64")
     (rho, val, (qb, gD, gmu)), fi, vi = P.likelihood_grad(dev(c["q"]), dev(d), dev(w))
     assert fi["status"] == 0 and vi["status"] == 0
-    H = oracle_hier(c, 3)
     rr, (Hv, chi2), (rqb, rgD, rgmu) = likelihood.likelihood_grad(H, c["mua"], c["q"], d, w, rtol=1e-13,
                                                                     max_cycles=300)
     errs = {"H": abs(val["H"] - Hv) / Hv, "chi2": abs(val["chi2"] - chi2) / chi2, "q": rel_max(host(qb), rqb),
