@@ -250,9 +250,11 @@ int dmgs_likelihood_grad(dmgs_plan plan, const double *q, const double *d, const
  * adjoint-state gradients of the exact discrete solution by the iteration
  * error; logD_bar / logmua_bar may be NULL).  The finest iterate is kept at
  * the start of every cycle and each cycle is recomputed, recording its
- * states, before its reverse pass: the call allocates n + about
- * 1.14 (2 (nu_pre + nu_post) + 8) finest-level fields of device memory and
- * frees them before it returns (it waits for its work).  Three-dimensional
+ * states, before its reverse pass.  The first call on a plan allocates n +
+ * about 1.14 (2 (nu_pre + nu_post) + 8) finest-level fields of device
+ * memory for this; the plan keeps them for later calls and counts them in
+ * its bytes, and dmgs_plan_destroy frees them.  The call waits for its work
+ * before it returns.  Three-dimensional
  * DMGS_FP64, DMGS_RBGS plans with fixed_cycles > 0 only, else
  * DMGS_ERR_INVALID; DMGS_ERR_OOM if the work buffers do not fit. */
 int dmgs_vjp_unrolled(dmgs_plan plan, const double *q, const double *rhobar, double *rho, double *qbar,

@@ -162,6 +162,7 @@ int dalloc(dmgs_plan P, T** p, int64_t count) {
 
 void free_plan(dmgs_plan P) {
     if (!P) return;
+    if (P->unwork && P->unwork_free) P->unwork_free(P->unwork);
     if (P->twin) free_plan(P->twin);
     if (P->twin_stream) (void)hipStreamDestroy(P->twin_stream);
     if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
@@ -1819,10 +1820,11 @@ int dmgs_forward_vjp(dmgs_plan P, const double* q, const double* rhobar, double*
 }  // extern "C"
 
 namespace {
-// Work buffers of one unrolled reverse pass (allocated per call).
+// Work buffers of the unrolled reverse pass, owned by the plan once its
+// first call has allocated them (hipFree waits for the device).
 struct UnWork {
-    hipStream_t st = nullptr;   // the stream the buffers are used on (waited for before they are freed)
     std::vector<void*> bufs;
+    size_t bytes = 0;
     double* ckpt = nullptr;                       // the finest iterate at the start of every cycle
     double* u0 = nullptr;                         // the finest working iterate
     double* tape[kMaxLevels][33] = {};            // per level: the state after each half-sweep (pre, then post)
@@ -1837,15 +1839,27 @@ struct UnWork {
             return DMGS_ERR_OOM;
         }
         bufs.push_back(*p);
+        bytes += (size_t)n * sizeof(double);
         return DMGS_OK;
     }
     ~UnWork() {
-        if (!bufs.empty()) (void)hipStreamSynchronize(st);
         for (void* p : bufs) (void)hipFree(p);
     }
 };
 
 unsigned un_grid(int64_t nv) { return (unsigned)((nv + kBlock - 1) / kBlock); }
+
+// Grid of the column-march kernels: blocks of kBlock threads over a plane
+// times chunks of planes, about 2048 blocks on large levels (each chunk
+// re-reads one plane on either side).
+dim3 un_col_grid(int N, int* chunk) {
+    const int n = N + 1;
+    const int64_t bx = ((int64_t)n * n + kBlock - 1) / kBlock;
+    int nch = (int)std::min<int64_t>(n, std::max<int64_t>(1, (2048 + bx - 1) / bx));
+    *chunk = (n + nch - 1) / nch;
+    nch = (n + *chunk - 1) / *chunk;
+    return dim3((unsigned)bx, (unsigned)nch);
+}
 
 // One V-cycle of the fixed-cycle solver with the per-operator kernels, in
 // place on u; with record, the states the reverse pass needs are copied to
@@ -1891,7 +1905,8 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
     const Level& l = P->lev[k];
     const Stencil<double> s = l.stencil<double>(harmonic(P));
     const int nu1 = P->opt.nu_pre, nu2 = P->opt.nu_post;
-    const unsigned g = un_grid(l.nv);
+    int chunk = 1;
+    const dim3 g = un_col_grid(l.N, &chunk);
     const double *D = l.D64, *mu = l.mu64;
     if (k == P->L - 1) {
         // lam = A^-1 ubar (zero boundary), then the solve's coefficient terms
@@ -1899,16 +1914,16 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
         hipLaunchKernelGGL(k_exact_solve<double>, dim3(1), dim3(64), 0, st, (const double*)W.ubar[k], W.V[k], D, mu, l.N, s);
         LAUNCHCHK();
         hipLaunchKernelGGL(k_un_defect, dim3(g), dim3(kBlock), 0, st, (double*)nullptr, (const double*)W.V[k], 1.0,
-                           (const double*)W.tape[k][0], D, mu, l.N, s, W.qbar[k], W.Dbar[k], W.mbar[k]);
+                           (const double*)W.tape[k][0], D, mu, l.N, s, W.qbar[k], W.Dbar[k], W.mbar[k], chunk);
         LAUNCHCHK();
         return DMGS_OK;
     }
     auto half_rev = [&](const double* state, int colour) -> int {
         hipLaunchKernelGGL(k_un_half_v, dim3(g), dim3(kBlock), 0, st, (const double*)W.ubar[k], state, D, mu, l.N, s,
-                           colour, W.V[k], W.qbar[k], W.mbar[k]);
+                           colour, W.V[k], W.qbar[k], W.mbar[k], chunk);
         LAUNCHCHK();
         hipLaunchKernelGGL(k_un_half_gather, dim3(g), dim3(kBlock), 0, st, W.ubar[k], (const double*)W.V[k], state, D,
-                           l.N, s, colour, W.Dbar[k]);
+                           l.N, s, colour, W.Dbar[k], chunk);
         LAUNCHCHK();
         return DMGS_OK;
     };
@@ -1928,7 +1943,7 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
                        W.r[k], l.N);
     LAUNCHCHK();
     hipLaunchKernelGGL(k_un_defect, dim3(g), dim3(kBlock), 0, st, W.ubar[k], (const double*)W.r[k], 0.125,
-                       (const double*)W.tape[k][2 * (nu1 + nu2)], D, mu, l.N, s, W.qbar[k], W.Dbar[k], W.mbar[k]);
+                       (const double*)W.tape[k][2 * (nu1 + nu2)], D, mu, l.N, s, W.qbar[k], W.Dbar[k], W.mbar[k], chunk);
     LAUNCHCHK();
     for (int h = 2 * nu1 - 1; h >= 0; h--) TRY(half_rev(W.tape[k][h], h & 1));
     return DMGS_OK;
@@ -1949,24 +1964,42 @@ int dmgs_vjp_unrolled(dmgs_plan P, const double* q, const double* rhobar, double
     }
     const int n = o.fixed_cycles, L = P->L, nstate = 2 * (o.nu_pre + o.nu_post) + 1;
     const Level& l0 = P->lev[0];
-    UnWork W;
-    W.st = st;
-    TRY(W.alloc(&W.ckpt, (int64_t)n * l0.nv));
-    TRY(W.alloc(&W.u0, l0.nv));
+    if (!P->unwork) {
+        // first call: allocate the work buffers; the plan keeps them
+        UnWork* w = new (std::nothrow) UnWork();
+        if (!w) { set_error("host allocation failed"); return DMGS_ERR_OOM; }
+        auto build = [&](UnWork& W) -> int {
+            TRY(W.alloc(&W.ckpt, (int64_t)n * l0.nv));
+            TRY(W.alloc(&W.u0, l0.nv));
+            for (int k = 0; k < L; k++) {
+                const int64_t nv = P->lev[k].nv;
+                const int ns = k == L - 1 ? 1 : nstate;
+                for (int h = 0; h < ns; h++) TRY(W.alloc(&W.tape[k][h], nv));
+                if (k < L - 1) TRY(W.alloc(&W.r[k], nv));
+                if (k > 0) {
+                    TRY(W.alloc(&W.uc[k], nv));
+                    TRY(W.alloc(&W.qc[k], nv));
+                }
+                TRY(W.alloc(&W.ubar[k], nv));
+                TRY(W.alloc(&W.qbar[k], nv));
+                TRY(W.alloc(&W.Dbar[k], nv));
+                TRY(W.alloc(&W.mbar[k], nv));
+                TRY(W.alloc(&W.V[k], nv));
+            }
+            return DMGS_OK;
+        };
+        const int sb = build(*w);
+        if (sb != DMGS_OK) {
+            delete w;
+            return sb;
+        }
+        P->unwork = w;
+        P->unwork_free = [](void* p) { delete static_cast<UnWork*>(p); };
+        P->bytes += w->bytes;
+    }
+    UnWork& W = *static_cast<UnWork*>(P->unwork);
     for (int k = 0; k < L; k++) {
         const int64_t nv = P->lev[k].nv;
-        const int ns = k == L - 1 ? 1 : nstate;
-        for (int h = 0; h < ns; h++) TRY(W.alloc(&W.tape[k][h], nv));
-        if (k < L - 1) TRY(W.alloc(&W.r[k], nv));
-        if (k > 0) {
-            TRY(W.alloc(&W.uc[k], nv));
-            TRY(W.alloc(&W.qc[k], nv));
-        }
-        TRY(W.alloc(&W.ubar[k], nv));
-        TRY(W.alloc(&W.qbar[k], nv));
-        TRY(W.alloc(&W.Dbar[k], nv));
-        TRY(W.alloc(&W.mbar[k], nv));
-        TRY(W.alloc(&W.V[k], nv));
         TRY(fill<double>(W.Dbar[k], nv, 0.0, st));
         TRY(fill<double>(W.mbar[k], nv, 0.0, st));
         TRY(fill<double>(W.qbar[k], nv, 0.0, st));
@@ -2016,7 +2049,8 @@ int dmgs_vjp_unrolled(dmgs_plan P, const double* q, const double* rhobar, double
                            (const double*)l0.mu64, logmua_bar, l0.nv);
         LAUNCHCHK();
     }
-    // the work buffers are freed on return: wait for the work that uses them
+    // the call returns with its work done (the plan's work buffers are then
+    // free for the next call, on any stream)
     HIPCHK(hipStreamSynchronize(st));
     if (info) {
         info->cycles = n;

@@ -15,8 +15,9 @@
 //   defect's coefficient terms with lam;
 //   coefficient coarsening (full weighting, injection on the boundary):
 //     its transpose carries a coarse level's Dbar, mubar to the finer one.
-// Every kernel takes one vertex per thread; cotangents are 0 on boundary
-// vertices except Dbar, which boundary faces reach.
+// The stencil kernels march along x (see UnCol); the others take one vertex
+// per thread.  Cotangents are 0 on boundary vertices except Dbar, which
+// boundary faces reach.
 #pragma once
 #include "kernels_basic.hpp"
 
@@ -31,63 +32,95 @@ __device__ __forceinline__ double dface_da(double Da, double Db, const Stencil<d
     return s.half_inv_h2;
 }
 
-__device__ __forceinline__ bool vertex3(int64_t i, int N, int& x, int& y, int& z) {
-    const int n = N + 1;
-    z = (int)(i % n);
-    y = (int)((i / n) % n);
-    x = (int)(i / ((int64_t)n * n));
-    return is_interior(N, x, y, z);
+// Column march: thread p of a plane (p = y (N+1) + z, so a plane is one
+// coalesced run) walks the planes [x0, x0 + chunk) of chunk blockIdx.y and
+// keeps the fields it needs at x - 1, x and x + 1 in registers; in-plane
+// neighbours are read at p +- (N+1) and p +- 1.  Each field is read from
+// memory about once, instead of three times for neighbours one plane away.
+struct UnCol {
+    int n, y, z, x0, x1;
+    int64_t sx, p;
+};
+
+__device__ __forceinline__ bool un_col(int N, int chunk, UnCol& c) {
+    c.n = N + 1;
+    c.sx = (int64_t)c.n * c.n;
+    c.p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    c.x0 = (int)blockIdx.y * chunk;
+    if (c.p >= c.sx || c.x0 >= c.n) return false;
+    c.y = (int)(c.p / c.n);
+    c.z = (int)(c.p % c.n);
+    c.x1 = min(c.n, c.x0 + chunk);
+    return true;
 }
 
 // half-sweep reverse, part 1: V = ubar / d on the colour's interior vertices
 // (0 elsewhere); qbar += V; mubar -= V u'
 __global__ void k_un_half_v(const double* __restrict__ ubar, const double* __restrict__ up,
                             const double* __restrict__ D, const double* __restrict__ mu, int N, Stencil<double> s,
-                            int colour, double* __restrict__ V, double* __restrict__ qbar, double* __restrict__ mubar) {
-    const int64_t nv = (int64_t)(N + 1) * (N + 1) * (N + 1);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nv) return;
-    int x, y, z;
-    if (!vertex3(i, N, x, y, z) || ((x + y + z) & 1) != colour) {
-        V[i] = 0.0;
-        return;
+                            int colour, double* __restrict__ V, double* __restrict__ qbar, double* __restrict__ mubar,
+                            int chunk) {
+    UnCol c;
+    if (!un_col(N, chunk, c)) return;
+    const int n = c.n;
+    const bool yz = c.y > 0 && c.y < N && c.z > 0 && c.z < N;
+    double Dm = c.x0 > 0 ? D[(c.x0 - 1) * c.sx + c.p] : 0.0, Dc = D[c.x0 * c.sx + c.p];
+    for (int x = c.x0; x < c.x1; x++) {
+        const int64_t i = x * c.sx + c.p;
+        const double Dp = x < N ? D[i + c.sx] : 0.0;
+        if (yz && x > 0 && x < N && ((x + c.y + c.z) & 1) == colour) {
+            const double d = mu[i] + face_coef(Dc, Dp, s) + face_coef(Dc, Dm, s) + face_coef(Dc, D[i + n], s) +
+                             face_coef(Dc, D[i - n], s) + face_coef(Dc, D[i + 1], s) + face_coef(Dc, D[i - 1], s);
+            const double v = ubar[i] / d;
+            V[i] = v;
+            qbar[i] += v;
+            mubar[i] -= v * up[i];
+        } else {
+            V[i] = 0.0;
+        }
+        Dm = Dc;
+        Dc = Dp;
     }
-    const int n = N + 1;
-    const int64_t sx = (int64_t)n * n;
-    const double Di = D[i];
-    const double d = mu[i] + face_coef(Di, D[i + sx], s) + face_coef(Di, D[i - sx], s) + face_coef(Di, D[i + n], s) +
-                     face_coef(Di, D[i - n], s) + face_coef(Di, D[i + 1], s) + face_coef(Di, D[i - 1], s);
-    const double v = ubar[i] / d;
-    V[i] = v;
-    qbar[i] += v;
-    mubar[i] -= v * up[i];
 }
 
 // half-sweep reverse, part 2: Dbar on every vertex, ubar on interior ones
 __global__ void k_un_half_gather(double* __restrict__ ubar, const double* __restrict__ V, const double* __restrict__ up,
                                  const double* __restrict__ D, int N, Stencil<double> s, int colour,
-                                 double* __restrict__ Dbar) {
-    const int64_t nv = (int64_t)(N + 1) * (N + 1) * (N + 1);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nv) return;
-    int x, y, z;
-    const bool in = vertex3(i, N, x, y, z);
-    const int n = N + 1;
-    const int64_t sx = (int64_t)n * n;
-    const int o[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
-    const int64_t off[6] = {sx, -sx, n, -n, 1, -1};
-    const double Di = D[i], Vi = V[i], ui = up[i];
-    double dacc = 0.0, gath = 0.0;
-    for (int e = 0; e < 6; e++) {
-        const int xa = x + o[e][0], ya = y + o[e][1], za = z + o[e][2];
-        if (xa < 0 || xa > N || ya < 0 || ya > N || za < 0 || za > N) continue;
-        const int64_t j = i + off[e];
-        const double Dj = D[j], Vj = V[j];
-        dacc += (Vi - Vj) * (ui - up[j]) * dface_da(Di, Dj, s);
-        gath += face_coef(Di, Dj, s) * Vj;
+                                 double* __restrict__ Dbar, int chunk) {
+    UnCol c;
+    if (!un_col(N, chunk, c)) return;
+    const int n = c.n;
+    const bool yz = c.y > 0 && c.y < N && c.z > 0 && c.z < N;
+    double Dm = 0.0, Vm = 0.0, um = 0.0;
+    if (c.x0 > 0) {
+        const int64_t j = (c.x0 - 1) * c.sx + c.p;
+        Dm = D[j]; Vm = V[j]; um = up[j];
     }
-    Dbar[i] -= dacc;
-    if (in) ubar[i] = ((x + y + z) & 1) == colour ? 0.0 : ubar[i] + gath;
+    const int64_t i0 = c.x0 * c.sx + c.p;
+    double Dc = D[i0], Vc = V[i0], uc = up[i0];
+    for (int x = c.x0; x < c.x1; x++) {
+        const int64_t i = x * c.sx + c.p;
+        double Dp = 0.0, Vp = 0.0, upp = 0.0;
+        if (x < N) {
+            Dp = D[i + c.sx]; Vp = V[i + c.sx]; upp = up[i + c.sx];
+        }
+        double dacc = 0.0, gath = 0.0;
+        // neighbours in the order +x, -x, +y, -y, +z, -z
+        auto nb = [&](double Dj, double Vj, double uj) {
+            dacc += (Vc - Vj) * (uc - uj) * dface_da(Dc, Dj, s);
+            gath += face_coef(Dc, Dj, s) * Vj;
+        };
+        if (x < N) nb(Dp, Vp, upp);
+        if (x > 0) nb(Dm, Vm, um);
+        if (c.y < N) nb(D[i + n], V[i + n], up[i + n]);
+        if (c.y > 0) nb(D[i - n], V[i - n], up[i - n]);
+        if (c.z < N) nb(D[i + 1], V[i + 1], up[i + 1]);
+        if (c.z > 0) nb(D[i - 1], V[i - 1], up[i - 1]);
+        Dbar[i] -= dacc;
+        if (yz && x > 0 && x < N) ubar[i] = ((x + c.y + c.z) & 1) == colour ? 0.0 : ubar[i] + gath;
+        Dm = Dc; Vm = Vc; um = uc;
+        Dc = Dp; Vc = Vp; uc = upp;
+    }
 }
 
 // defect (or coarsest-solve) reverse with cotangent rbar = scale * rb (rb
@@ -96,33 +129,49 @@ __global__ void k_un_half_gather(double* __restrict__ ubar, const double* __rest
 __global__ void k_un_defect(double* __restrict__ ubar, const double* __restrict__ rb, double scale,
                             const double* __restrict__ u, const double* __restrict__ D, const double* __restrict__ mu,
                             int N, Stencil<double> s, double* __restrict__ qbar, double* __restrict__ Dbar,
-                            double* __restrict__ mubar) {
-    const int64_t nv = (int64_t)(N + 1) * (N + 1) * (N + 1);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nv) return;
-    int x, y, z;
-    const bool in = vertex3(i, N, x, y, z);
-    const int n = N + 1;
-    const int64_t sx = (int64_t)n * n;
-    const int o[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
-    const int64_t off[6] = {sx, -sx, n, -n, 1, -1};
-    const double Di = D[i], ui = u[i];
-    const double ri = in ? scale * rb[i] : 0.0;
-    double dacc = 0.0, Ar = in ? mu[i] * ri : 0.0;
-    for (int e = 0; e < 6; e++) {
-        const int xa = x + o[e][0], ya = y + o[e][1], za = z + o[e][2];
-        if (xa < 0 || xa > N || ya < 0 || ya > N || za < 0 || za > N) continue;
-        const int64_t j = i + off[e];
-        const double rj = is_interior(N, xa, ya, za) ? scale * rb[j] : 0.0;
-        const double Dj = D[j];
-        dacc += (ri - rj) * (ui - u[j]) * dface_da(Di, Dj, s);
-        Ar += face_coef(Di, Dj, s) * (ri - rj);
+                            double* __restrict__ mubar, int chunk) {
+    UnCol c;
+    if (!un_col(N, chunk, c)) return;
+    const int n = c.n;
+    const bool yz = c.y > 0 && c.y < N && c.z > 0 && c.z < N;
+    auto rx = [&](int x, int64_t j) { return yz && x > 0 && x < N ? scale * rb[j] : 0.0; };
+    double Dm = 0.0, um = 0.0, rm = 0.0;
+    if (c.x0 > 0) {
+        const int64_t j = (c.x0 - 1) * c.sx + c.p;
+        Dm = D[j]; um = u[j]; rm = rx(c.x0 - 1, j);
     }
-    Dbar[i] -= dacc;
-    if (!in) return;
-    qbar[i] += ri;
-    mubar[i] -= ri * ui;
-    if (ubar) ubar[i] -= Ar;
+    const int64_t i0 = c.x0 * c.sx + c.p;
+    double Dc = D[i0], uc = u[i0], rc = rx(c.x0, i0);
+    for (int x = c.x0; x < c.x1; x++) {
+        const int64_t i = x * c.sx + c.p;
+        double Dp = 0.0, upp = 0.0, rp = 0.0;
+        if (x < N) {
+            Dp = D[i + c.sx]; upp = u[i + c.sx]; rp = rx(x + 1, i + c.sx);
+        }
+        const bool in = yz && x > 0 && x < N;
+        double dacc = 0.0, Ar = in ? mu[i] * rc : 0.0;
+        // neighbours in the order +x, -x, +y, -y, +z, -z; rb is read only
+        // on interior neighbours
+        auto nb = [&](double Dj, double uj, double rj) {
+            dacc += (rc - rj) * (uc - uj) * dface_da(Dc, Dj, s);
+            Ar += face_coef(Dc, Dj, s) * (rc - rj);
+        };
+        const bool zin = c.z > 0 && c.z < N, yin = c.y > 0 && c.y < N, xin = x > 0 && x < N;
+        if (x < N) nb(Dp, upp, rp);
+        if (x > 0) nb(Dm, um, rm);
+        if (c.y < N) nb(D[i + n], u[i + n], xin && zin && c.y + 1 < N ? scale * rb[i + n] : 0.0);
+        if (c.y > 0) nb(D[i - n], u[i - n], xin && zin && c.y - 1 > 0 ? scale * rb[i - n] : 0.0);
+        if (c.z < N) nb(D[i + 1], u[i + 1], xin && yin && c.z + 1 < N ? scale * rb[i + 1] : 0.0);
+        if (c.z > 0) nb(D[i - 1], u[i - 1], xin && yin && c.z - 1 > 0 ? scale * rb[i - 1] : 0.0);
+        Dbar[i] -= dacc;
+        if (in) {
+            qbar[i] += rc;
+            mubar[i] -= rc * uc;
+            if (ubar) ubar[i] -= Ar;
+        }
+        Dm = Dc; um = uc; rm = rc;
+        Dc = Dp; uc = upp; rc = rp;
+    }
 }
 
 // a *= f

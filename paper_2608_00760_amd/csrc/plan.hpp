@@ -118,4 +118,8 @@ struct dmgs_plan_s {
     dmgs_plan_s* twin = nullptr;
     hipStream_t twin_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // work buffers of the unrolled reverse pass, allocated by its first call
+    // and kept for later ones (freed with the plan through unwork_free)
+    void* unwork = nullptr;
+    void (*unwork_free)(void*) = nullptr;
 };
