@@ -1861,40 +1861,70 @@ dim3 un_col_grid(int N, int* chunk) {
     return dim3((unsigned)bx, (unsigned)nch);
 }
 
-// One V-cycle of the fixed-cycle solver with the per-operator kernels, in
-// place on u; with record, the states the reverse pass needs are copied to
-// the tape.
-int vcycle_taped(dmgs_plan P, UnWork& W, int k, double* u, const double* q, bool record, hipStream_t st) {
+// The state the defect of level k reads in a recorded cycle: the last
+// pre-smoothing half-sweep's slot, or (without pre-smoothing) the slot the
+// cycle's input is copied to.
+const double* pre_state(dmgs_plan P, UnWork& W, int k) {
+    const int nu1 = P->opt.nu_pre, nu2 = P->opt.nu_post;
+    return nu1 > 0 ? W.tape[k][2 * nu1 - 1] : W.tape[k][2 * (nu1 + nu2)];
+}
+
+// One V-cycle of the fixed-cycle solver with the per-operator kernels,
+// recording the states the reverse pass needs: each half-sweep writes its
+// result out of place into its tape slot and the next one reads it there.
+// u is the cycle's input (overwritten on levels below the finest: it holds
+// the input of the post-smoothing); *fin receives the cycle's result.
+int vcycle_taped(dmgs_plan P, UnWork& W, int k, double* u, const double* q, const double** fin, hipStream_t st) {
     const Level& l = P->lev[k];
     const int nu1 = P->opt.nu_pre, nu2 = P->opt.nu_post;
     const size_t bytes = l.nv * sizeof(double);
+    const Stencil<double> s = l.stencil<double>(harmonic(P));
     if (k == P->L - 1) {
         hipLaunchKernelGGL(k_exact_solve<double>, dim3(1), dim3(64), 0, st, q, u, (const double*)l.D64,
-                           (const double*)l.mu64, l.N, l.stencil<double>(harmonic(P)));
+                           (const double*)l.mu64, l.N, s);
         LAUNCHCHK();
-        if (record) HIPCHK(hipMemcpyAsync(W.tape[k][0], u, bytes, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(W.tape[k][0], u, bytes, hipMemcpyDeviceToDevice, st));
+        *fin = u;
         return DMGS_OK;
     }
+    int chunk = 1;
+    const dim3 g = un_col_grid(l.N, &chunk);
+    auto half = [&](const double* in, int h, int colour) -> int {
+        hipLaunchKernelGGL(k_un_gs_half, g, dim3(kBlock), 0, st, in, W.tape[k][h], q, (const double*)l.D64,
+                           (const double*)l.mu64, l.N, s, colour, chunk);
+        LAUNCHCHK();
+        return DMGS_OK;
+    };
+    const double* src = u;
     int h = 0;
     for (int i = 0; i < nu1; i++)
         for (int colour = 0; colour < 2; colour++, h++) {
-            TRY(half_sweep<double>(P, k, u, q, colour, st));
-            if (record) HIPCHK(hipMemcpyAsync(W.tape[k][h], u, bytes, hipMemcpyDeviceToDevice, st));
+            TRY(half(src, h, colour));
+            src = W.tape[k][h];
         }
-    if (record) HIPCHK(hipMemcpyAsync(W.tape[k][2 * (nu1 + nu2)], u, bytes, hipMemcpyDeviceToDevice, st));
+    if (nu1 == 0) {
+        // u itself becomes the post-smoothing input below: keep the state
+        HIPCHK(hipMemcpyAsync(W.tape[k][2 * (nu1 + nu2)], u, bytes, hipMemcpyDeviceToDevice, st));
+        src = W.tape[k][2 * (nu1 + nu2)];
+    }
     const Level& c = P->lev[k + 1];
-    TRY(apply_or_defect<double>(P, k, u, q, W.r[k], 0, st));
+    TRY(apply_or_defect<double>(P, k, src, q, W.r[k], 0, st));
     hipLaunchKernelGGL(k_restrict<double>, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)W.r[k], W.qc[k + 1], l.N);
     LAUNCHCHK();
     TRY(fill<double>(W.uc[k + 1], c.nv, 0.0, st));
-    TRY(vcycle_taped(P, W, k + 1, W.uc[k + 1], W.qc[k + 1], record, st));
-    hipLaunchKernelGGL(k_prolong_add<double>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, (const double*)W.uc[k + 1], u, l.N);
+    const double* ec = nullptr;
+    TRY(vcycle_taped(P, W, k + 1, W.uc[k + 1], W.qc[k + 1], &ec, st));
+    // the post-smoothing input: the pre-smoothed state plus the correction
+    if (src != u) HIPCHK(hipMemcpyAsync(u, src, bytes, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_prolong_add<double>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, ec, u, l.N);
     LAUNCHCHK();
+    src = u;
     for (int i = 0; i < nu2; i++)
         for (int colour = 0; colour < 2; colour++, h++) {
-            TRY(half_sweep<double>(P, k, u, q, colour, st));
-            if (record) HIPCHK(hipMemcpyAsync(W.tape[k][h], u, bytes, hipMemcpyDeviceToDevice, st));
+            TRY(half(src, h, colour));
+            src = W.tape[k][h];
         }
+    *fin = src;
     return DMGS_OK;
 }
 
@@ -1943,7 +1973,7 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
                        W.r[k], l.N);
     LAUNCHCHK();
     hipLaunchKernelGGL(k_un_defect, dim3(g), dim3(kBlock), 0, st, W.ubar[k], (const double*)W.r[k], 0.125,
-                       (const double*)W.tape[k][2 * (nu1 + nu2)], D, mu, l.N, s, W.qbar[k], W.Dbar[k], W.mbar[k], chunk);
+                       pre_state(P, W, k), D, mu, l.N, s, W.qbar[k], W.Dbar[k], W.mbar[k], chunk);
     LAUNCHCHK();
     for (int h = 2 * nu1 - 1; h >= 0; h--) TRY(half_rev(W.tape[k][h], h & 1));
     return DMGS_OK;
@@ -2027,7 +2057,8 @@ int dmgs_vjp_unrolled(dmgs_plan P, const double* q, const double* rhobar, double
     TRY(set_boundary<double>(W.ubar[0], l0.N, 0.0, st));
     for (int c = n - 1; c >= 0; c--) {
         HIPCHK(hipMemcpyAsync(W.u0, W.ckpt + (int64_t)c * l0.nv, b0, hipMemcpyDeviceToDevice, st));
-        TRY(vcycle_taped(P, W, 0, W.u0, q, true, st));
+        const double* fin = nullptr;
+        TRY(vcycle_taped(P, W, 0, W.u0, q, &fin, st));
         TRY(vcycle_rev(P, W, 0, st));
     }
     // coarse coefficient cotangents to the finest level

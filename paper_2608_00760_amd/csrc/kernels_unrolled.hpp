@@ -54,6 +54,46 @@ __device__ __forceinline__ bool un_col(int N, int chunk, UnCol& c) {
     return true;
 }
 
+// Recorded half-sweep of colour C, out of place: u_out = the Gauss-Seidel
+// value on C's interior vertices (it reads only the other colour, so it
+// equals the in-place sweep) and u_in elsewhere.  The recompute writes each
+// state straight into its tape slot.
+__global__ void k_un_gs_half(const double* __restrict__ u_in, double* __restrict__ u_out,
+                             const double* __restrict__ q, const double* __restrict__ D,
+                             const double* __restrict__ mu, int N, Stencil<double> s, int colour, int chunk) {
+    UnCol c;
+    if (!un_col(N, chunk, c)) return;
+    const int n = c.n;
+    const bool yz = c.y > 0 && c.y < N && c.z > 0 && c.z < N;
+    double Dm = 0.0, um = 0.0;
+    if (c.x0 > 0) {
+        const int64_t j = (c.x0 - 1) * c.sx + c.p;
+        Dm = D[j]; um = u_in[j];
+    }
+    const int64_t i0 = c.x0 * c.sx + c.p;
+    double Dc = D[i0], uc = u_in[i0];
+    for (int x = c.x0; x < c.x1; x++) {
+        const int64_t i = x * c.sx + c.p;
+        double Dp = 0.0, upp = 0.0;
+        if (x < N) {
+            Dp = D[i + c.sx]; upp = u_in[i + c.sx];
+        }
+        double v = uc;
+        if (yz && x > 0 && x < N && ((x + c.y + c.z) & 1) == colour) {
+            const double c0 = face_coef(Dc, Dp, s), c1 = face_coef(Dc, Dm, s);
+            const double c2 = face_coef(Dc, D[i + n], s), c3 = face_coef(Dc, D[i - n], s);
+            const double c4 = face_coef(Dc, D[i + 1], s), c5 = face_coef(Dc, D[i - 1], s);
+            const double num = q[i] + c0 * upp + c1 * um + c2 * u_in[i + n] + c3 * u_in[i - n] + c4 * u_in[i + 1] +
+                               c5 * u_in[i - 1];
+            const double den = mu[i] + c0 + c1 + c2 + c3 + c4 + c5;
+            v = num / den;
+        }
+        u_out[i] = v;
+        Dm = Dc; um = uc;
+        Dc = Dp; uc = upp;
+    }
+}
+
 // half-sweep reverse, part 1: V = ubar / d on the colour's interior vertices
 // (0 elsewhere); qbar += V; mubar -= V u'
 __global__ void k_un_half_v(const double* __restrict__ ubar, const double* __restrict__ up,
