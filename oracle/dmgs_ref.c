@@ -27,7 +27,7 @@
  * D the diffusion coefficient and lambda (here "mua", lambda_a of
  * Eq. (medimcoeffs)) the absorption coefficient.  Bars denote cotangents.
  *
- * Readings of passages the paper leaves open (all listed in the design doc):
+ * Readings of passages the paper leaves open:
  *   - sign convention: L is symmetric positive definite, Au = q, defect
  *     r = q - A rho (Eq. (maineq), Eq. (defect));
  *   - face diffusivity: arithmetic mean of the two vertex values (harmonic
