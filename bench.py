@@ -56,6 +56,29 @@ def cpu_baseline(c, cycles_fwd, cycles_adj, smoother="rbgs"):
                       % (c["N"], setup, fwd2, adj2, cycles_fwd, cycles_adj)}
 
 
+def sweep_cpu_baseline(nd, logD, logmu, q, w):
+    """The oracle beside one line of the benchmark sweep, on a bounded
+    sample: hierarchy set-up plus 2 fixed float64 V-cycles of the solve and 2
+    of the pull-back (with gradients), scaled to the sweep's 15 cycles."""
+    import numpy as np
+    from oracle import ref, ref2d
+    D, mu = np.exp(logD), np.exp(logmu)
+    t0 = time.perf_counter()
+    H = ref.Hierarchy(D, mu) if nd == 3 else ref2d.Hierarchy2D(D, mu)
+    t1 = time.perf_counter()
+    rho, _ = H.forward(q, fixed_cycles=2)
+    t2 = time.perf_counter()
+    H.vjp(rho, w, fixed_cycles=2)
+    t3 = time.perf_counter()
+    setup, fwd2, adj2 = t1 - t0, t2 - t1, t3 - t2
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)) if nd == 3 else 1
+    return {"solve_ms": 1e3 * (setup + fwd2 / 2 * 15), "vjp_ms": 1e3 * (setup + adj2 / 2 * 15),
+            "cores": min(cores, os.cpu_count() or cores), "kind": "oracle",
+            "sample": "hierarchy set-up %.2fs + 2 forward cycles %.2fs + 2 pull-back cycles with gradients %.2fs, "
+                      "scaled to 15 cycles (FP64, %s)" % (setup, fwd2, adj2,
+                                                          "C/OpenMP" if nd == 3 else "numpy")}
+
+
 def serving_leg(nreq):
     """The serving stream: nreq requests, grid sizes uniform over {64, 96, 128,
     192}^3, 50/50 forward+JVP / forward+VJP, each with its own seeded fields.
@@ -204,6 +227,9 @@ def paper_sweep(args):
                 work = 8 * (15 * (N + 1) ** 3 + (2 * 4 + 1 + 8) * nvs)
                 unrolled = {"ms_median": tu[1], "work_GB": work / 1e9,
                             "vs_vjp": tu[1] / res["vjp_ms_median"]}
+            cpu = None
+            if args.sweep_cpu_baseline and prec == "fp64" and N <= (256 if nd == 3 else 1024):
+                cpu = sweep_cpu_baseline(nd, *(t.cpu().numpy() for t in (logD, logmu, q, w)))
             gbps = sm["bytes"] / (sm["ms"] * 1e-3) / 1e9 if sm["ms"] > 0 else None
             print(json.dumps({"sweep": "fixed 15 V-cycles", "ndim": nd, "N": N, "points": (N + 1) ** nd,
                               "log2_points": round(math.log2((N + 1) ** nd), 2), "precision": prec,
@@ -212,7 +238,7 @@ def paper_sweep(args):
                                                 "avg_us": 1e3 * sm["ms"] / max(sm["launches"], 1),
                                                 "GBps": gbps, "frac": gbps / HBM_PEAK_GBPS if gbps else None},
                               "finest_level_ms_per_solve": {k: v["ms"] for k, v in per_class.items() if v["launches"]},
-                              "vjp_unrolled": unrolled}),
+                              "vjp_unrolled": unrolled, "cpu_baseline": cpu}),
                   flush=True)
             P.close()
             del logD, logmu, q, w, dq, dd, dm, rho, qbar, drho, gD, gmu
@@ -238,6 +264,8 @@ def main():
     ap.add_argument("--sweep-ndim", type=int, default=3, choices=[2, 3],
                     help="the sweep's grids: 3D (7-point) or 2D (5-point, the paper's comparison setting)")
     ap.add_argument("--sweep-reps", type=int, default=20)
+    ap.add_argument("--sweep-cpu-baseline", action="store_true",
+                    help="time the oracle beside the float64 sweep lines (3D N <= 256, 2D N <= 1024)")
     ap.add_argument("--sweep-unrolled-max", type=int, default=512,
                     help="largest N at which the sweep also times the unrolled adjoint (float64 3D)")
     ap.add_argument("--sequential", action="store_true",
