@@ -358,7 +358,7 @@ def main():
         P64.close()
         log("fp64 solver: %.3f ms/step" % fp64["ms_per_step"])
 
-    # likelihood gradient of one source (Sec. 2.5.3): forward solve, the
+    # likelihood gradient of one source (Sec. 2.5.4, Eq. (likelihood)): forward solve, the
     # fused epilogue, the pull-back and the gradients; data from the noise
     # model with a 3-vertex edge mask
     rho_l, _ = P.forward(t["q"])

@@ -218,7 +218,7 @@ int dmgs_noise_weights(dmgs_plan plan, const double *Le, int32_t mask, double re
                        void *stream);
 
 /* Negative log-likelihood of data d and its gradient for one source q
- * (Sec. 2.5.3, Eq. (chi2)):
+ * (Sec. 2.5.2 Eq. (response), Sec. 2.5.4 Eq. (likelihood) and Eq. (chi2)):
  *   rho = S q                                  (as dmgs_forward)
  *   H = 1/2 sum_i w_i (d_i - mua_i rho_i)^2    over interior vertices
  *   value[0] = H, value[1] = chi2 = 2 H / N_vox, value[2] = N_vox (number of

@@ -2,14 +2,14 @@
 (Sec. 2.5): test infrastructure, used only by the tests and the smoke check.
 Plain float64 numpy on the solver oracle's fields (3D or 2D arrays).
 
-* Response (Sec. 2.5.3): the absorbed energy density L_e = mua rho (the
+* Response (Sec. 2.5.2, Eq. (response)): the absorbed energy density L_e = mua rho (the
   paper writes lambda for mua), restricted by the mask M to the voxels that
   enter the comparison with data.
 * Noise model (Sec. 2.5.1, Eq. (noise)): sigma_i = max(rel L_e,i,
   floor max_j L_e,j) with rel = 0.05 and floor = 0.01; the mask keeps
   vertices at least `mask` vertices from every face (the paper masks 0.2 cm
   on all edges).  Weights w_i = 1 / sigma_i^2 on kept vertices, 0 elsewhere.
-* Likelihood (Sec. 2.5.3, Gaussian with diagonal covariance): the negative
+* Likelihood (Sec. 2.5.4, Eq. (likelihood), Gaussian with diagonal covariance): the negative
   log-likelihood up to a constant, H = 1/2 sum_i w_i (d_i - L_e,i)^2, and
   Eq. (chi2), chi2 = 2 H / N_vox with N_vox the number of kept voxels.
 * Gradient of H: with rho = S q, dH/drho = mua w (mua rho - d); the gradients
