@@ -1425,6 +1425,68 @@ int debug_post_t(dmgs_plan P, int k, int order, const T* u_in, const T* ec, cons
 // ===========================================================================
 // C ABI
 
+namespace {
+
+// Grid of the column-march derivative kernels: blocks of kBlock threads over
+// a plane times chunks of planes, at most about 2048 blocks (eight per CU on
+// 256 CUs, one round); each chunk re-reads one plane at either end.
+dim3 col_grid(int N, int* chunk) {
+    const int n = N + 1;
+    const int64_t bx = ((int64_t)n * n + kBlock - 1) / kBlock;
+    int nch = (int)std::min<int64_t>(n, std::max<int64_t>(1, 2048 / bx));
+    *chunk = (n + nch - 1) / nch;
+    nch = (n + *chunk - 1) / *chunk;
+    return dim3((unsigned)bx, (unsigned)nch);
+}
+
+// tangent right-hand side q' - A' rho of the push-forward (A9)
+int tangent_rhs(dmgs_plan P, const double* rho, const double* dq, const double* dlogD, const double* dlogmua,
+                double* out, hipStream_t st) {
+    const Level& l0 = P->lev[0];
+    if (is2d(P)) {
+        TIMED(P, 0, DMGS_K_GRAD, 56.0 * l0.nv, st,
+              hipLaunchKernelGGL(k2_tangent_rhs, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, rho, dq, dlogD,
+                                 dlogmua, (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2,
+                                 harmonic(P), out));
+        return DMGS_OK;
+    }
+    int chunk = 1;
+    const dim3 g = col_grid(l0.N, &chunk);
+    TIMED(P, 0, DMGS_K_GRAD, 56.0 * l0.nv, st,
+          hipLaunchKernelGGL(k_tangent_rhs_col, g, dim3(kBlock), 0, st, rho, dq, dlogD, dlogmua,
+                             (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, harmonic(P), out,
+                             chunk));
+    return DMGS_OK;
+}
+
+// coefficient gradients from the adjoint state lam (A10); with data d and
+// weights w, also the likelihood's direct log mua term
+int coef_grads(dmgs_plan P, const double* rho, const double* lam, double* gD, double* gmu, const double* d,
+               const double* w, hipStream_t st) {
+    const Level& l0 = P->lev[0];
+    if (is2d(P)) {
+        TIMED(P, 0, DMGS_K_GRAD, 48.0 * l0.nv, st,
+              hipLaunchKernelGGL(k2_coef_grads, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, rho, lam,
+                                 (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, harmonic(P), gD,
+                                 gmu));
+        if (d && gmu) {
+            hipLaunchKernelGGL(k_likelihood_direct, dim3(grid_for(l0.nv, 4096)), dim3(kBlock), 0, st, rho,
+                               (const double*)l0.mu64, d, w, l0.nv, l0.N, P->opt.ndim, gmu);
+            LAUNCHCHK();
+        }
+        return DMGS_OK;
+    }
+    int chunk = 1;
+    const dim3 g = col_grid(l0.N, &chunk);
+    const double bytes = (gD ? 40.0 : 24.0) + (gmu ? 8.0 : 0.0) + (d && gmu ? 16.0 : 0.0);
+    TIMED(P, 0, DMGS_K_GRAD, bytes * l0.nv, st,
+          hipLaunchKernelGGL(k_coef_grads_col, g, dim3(kBlock), 0, st, rho, lam, (const double*)l0.D64,
+                             (const double*)l0.mu64, l0.N, l0.inv_h2, harmonic(P), gD, gmu, d, w, chunk));
+    return DMGS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void dmgs_default_options(int32_t n, dmgs_options* o) {
@@ -1648,11 +1710,7 @@ int dmgs_jvp(dmgs_plan P, const double* rho, const double* dq, const double* dlo
     hipStream_t st = (hipStream_t)stream;
     TRY(begin_call(P, st));
     if (!rho || !drho) { set_error("NULL argument"); return DMGS_ERR_INVALID; }
-    const Level& l0 = P->lev[0];
-    TIMED(P, 0, DMGS_K_GRAD, 56.0 * l0.nv, st,
-          hipLaunchKernelGGL(is2d(P) ? k2_tangent_rhs : k_tangent_rhs, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, rho,
-                             dq, dlogD, dlogmua, (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2,
-                             harmonic(P), P->scratch64));
+    TRY(tangent_rhs(P, rho, dq, dlogD, dlogmua, P->scratch64, st));
     int s = solve(P, P->scratch64, drho, 0.0, 0, info, st);
     return end_call(P, s, info, st);
 }
@@ -1669,11 +1727,7 @@ int dmgs_vjp(dmgs_plan P, const double* rho, const double* rhobar, double* qbar,
     }
     int s = solve(P, rhobar, qbar, 0.0, 1, info, st, replay);
     if ((s == DMGS_OK || s == DMGS_ERR_NOT_CONVERGED) && (logD_bar || logmua_bar)) {
-        const Level& l0 = P->lev[0];
-        TIMED(P, 0, DMGS_K_GRAD, 48.0 * l0.nv, st,
-              hipLaunchKernelGGL(is2d(P) ? k2_coef_grads : k_coef_grads, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, rho, (const double*)qbar,
-                                 (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, harmonic(P), logD_bar,
-                                 logmua_bar));
+        TRY(coef_grads(P, rho, qbar, logD_bar, logmua_bar, nullptr, nullptr, st));
     }
     return end_call(P, s, info, st);
 }
@@ -1801,11 +1855,7 @@ int dmgs_forward_vjp(dmgs_plan P, const double* q, const double* rhobar, double*
     const bool ok_f = sf == DMGS_OK || sf == DMGS_ERR_NOT_CONVERGED;
     const bool ok_a = sa == DMGS_OK || sa == DMGS_ERR_NOT_CONVERGED;
     if (ok_f && ok_a && (logD_bar || logmua_bar)) {
-        const Level& l0 = P->lev[0];
-        TIMED(P, 0, DMGS_K_GRAD, 48.0 * l0.nv, st,
-              hipLaunchKernelGGL(is2d(P) ? k2_coef_grads : k_coef_grads, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, (const double*)rho,
-                                 (const double*)qbar, (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2,
-                                 harmonic(P), logD_bar, logmua_bar));
+        TRY(coef_grads(P, rho, qbar, logD_bar, logmua_bar, nullptr, nullptr, st));
     }
     int s = sf != DMGS_OK ? sf : sa;
     if (sf == DMGS_OK && sa != DMGS_OK) set_error("adjoint solve: %s", err_a.c_str());
@@ -1824,6 +1874,7 @@ namespace {
 // first call has allocated them (hipFree waits for the device).
 struct UnWork {
     std::vector<void*> bufs;
+    std::vector<size_t> sizes;
     size_t bytes = 0;
     double* ckpt = nullptr;                       // the finest iterate at the start of every cycle
     double* u0 = nullptr;                         // the finest working iterate
@@ -1839,8 +1890,18 @@ struct UnWork {
             return DMGS_ERR_OOM;
         }
         bufs.push_back(*p);
+        sizes.push_back((size_t)n * sizeof(double));
         bytes += (size_t)n * sizeof(double);
         return DMGS_OK;
+    }
+    // [p, p + count doubles) lies inside one of the buffers
+    bool holds(const double* p, int64_t count) const {
+        const char* a = reinterpret_cast<const char*>(p);
+        for (size_t i = 0; i < bufs.size(); i++) {
+            const char* b = static_cast<const char*>(bufs[i]);
+            if (a >= b && a + (size_t)count * sizeof(double) <= b + sizes[i]) return true;
+        }
+        return false;
     }
     ~UnWork() {
         for (void* p : bufs) (void)hipFree(p);
@@ -1848,6 +1909,18 @@ struct UnWork {
 };
 
 unsigned un_grid(int64_t nv) { return (unsigned)((nv + kBlock - 1) / kBlock); }
+
+// Every work buffer a launch or copy of the unrolled pass touches is checked
+// on the host against the buffers allocated for it (and the count of values
+// the launch or copy covers) before it is enqueued.
+#define UNCHK(W, ptr, count, what)                                                                       \
+    do {                                                                                                 \
+        if (!(W).holds((ptr), (count))) {                                                                \
+            set_error("unrolled pass: %s (level %d) is not an allocated work buffer of %lld values", what, k, \
+                      (long long)(count));                                                              \
+            return DMGS_ERR_INVALID;                                                                     \
+        }                                                                                                \
+    } while (0)
 
 // Grid of the column-march kernels: blocks of kBlock threads over a plane
 // times chunks of planes, about 2048 blocks on large levels (each chunk
@@ -1879,7 +1952,10 @@ int vcycle_taped(dmgs_plan P, UnWork& W, int k, double* u, const double* q, cons
     const int nu1 = P->opt.nu_pre, nu2 = P->opt.nu_post;
     const size_t bytes = l.nv * sizeof(double);
     const Stencil<double> s = l.stencil<double>(harmonic(P));
+    UNCHK(W, u, l.nv, "the cycle's iterate");
+    if (k > 0) UNCHK(W, q, l.nv, "the coarse right-hand side");
     if (k == P->L - 1) {
+        UNCHK(W, W.tape[k][0], l.nv, "the coarsest tape slot");
         hipLaunchKernelGGL(k_exact_solve<double>, dim3(1), dim3(64), 0, st, q, u, (const double*)l.D64,
                            (const double*)l.mu64, l.N, s);
         LAUNCHCHK();
@@ -1890,6 +1966,8 @@ int vcycle_taped(dmgs_plan P, UnWork& W, int k, double* u, const double* q, cons
     int chunk = 1;
     const dim3 g = un_col_grid(l.N, &chunk);
     auto half = [&](const double* in, int h, int colour) -> int {
+        UNCHK(W, in, l.nv, "a half-sweep input");
+        UNCHK(W, W.tape[k][h], l.nv, "a tape slot");
         hipLaunchKernelGGL(k_un_gs_half, g, dim3(kBlock), 0, st, in, W.tape[k][h], q, (const double*)l.D64,
                            (const double*)l.mu64, l.N, s, colour, chunk);
         LAUNCHCHK();
@@ -1904,10 +1982,14 @@ int vcycle_taped(dmgs_plan P, UnWork& W, int k, double* u, const double* q, cons
         }
     if (nu1 == 0) {
         // u itself becomes the post-smoothing input below: keep the state
+        UNCHK(W, W.tape[k][2 * (nu1 + nu2)], l.nv, "the input's tape slot");
         HIPCHK(hipMemcpyAsync(W.tape[k][2 * (nu1 + nu2)], u, bytes, hipMemcpyDeviceToDevice, st));
         src = W.tape[k][2 * (nu1 + nu2)];
     }
     const Level& c = P->lev[k + 1];
+    UNCHK(W, W.r[k], l.nv, "the defect");
+    UNCHK(W, W.qc[k + 1], c.nv, "the coarse right-hand side");
+    UNCHK(W, W.uc[k + 1], c.nv, "the coarse iterate");
     TRY(apply_or_defect<double>(P, k, src, q, W.r[k], 0, st));
     hipLaunchKernelGGL(k_restrict<double>, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)W.r[k], W.qc[k + 1], l.N);
     LAUNCHCHK();
@@ -1938,7 +2020,13 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
     int chunk = 1;
     const dim3 g = un_col_grid(l.N, &chunk);
     const double *D = l.D64, *mu = l.mu64;
+    UNCHK(W, W.ubar[k], l.nv, "ubar");
+    UNCHK(W, W.qbar[k], l.nv, "qbar");
+    UNCHK(W, W.Dbar[k], l.nv, "Dbar");
+    UNCHK(W, W.mbar[k], l.nv, "mubar");
+    UNCHK(W, W.V[k], l.nv, "V");
     if (k == P->L - 1) {
+        UNCHK(W, W.tape[k][0], l.nv, "the coarsest tape slot");
         // lam = A^-1 ubar (zero boundary), then the solve's coefficient terms
         TRY(fill<double>(W.V[k], l.nv, 0.0, st));
         hipLaunchKernelGGL(k_exact_solve<double>, dim3(1), dim3(64), 0, st, (const double*)W.ubar[k], W.V[k], D, mu, l.N, s);
@@ -1949,6 +2037,7 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
         return DMGS_OK;
     }
     auto half_rev = [&](const double* state, int colour) -> int {
+        UNCHK(W, state, l.nv, "a recorded state");
         hipLaunchKernelGGL(k_un_half_v, dim3(g), dim3(kBlock), 0, st, (const double*)W.ubar[k], state, D, mu, l.N, s,
                            colour, W.V[k], W.qbar[k], W.mbar[k], chunk);
         LAUNCHCHK();
@@ -1960,6 +2049,10 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
     for (int h = 2 * nu2 - 1; h >= 0; h--) TRY(half_rev(W.tape[k][2 * nu1 + h], h & 1));
     // prolongation u += I ec: ecbar = I^T ubar = 8 R ubar
     const Level& c = P->lev[k + 1];
+    UNCHK(W, W.ubar[k + 1], c.nv, "the coarse ubar");
+    UNCHK(W, W.qbar[k + 1], c.nv, "the coarse qbar");
+    UNCHK(W, W.r[k], l.nv, "rbar");
+    UNCHK(W, pre_state(P, W, k), l.nv, "the defect's recorded state");
     hipLaunchKernelGGL(k_restrict<double>, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)W.ubar[k],
                        W.ubar[k + 1], l.N);
     LAUNCHCHK();
@@ -2028,6 +2121,11 @@ int dmgs_vjp_unrolled(dmgs_plan P, const double* q, const double* rhobar, double
         P->bytes += w->bytes;
     }
     UnWork& W = *static_cast<UnWork*>(P->unwork);
+    {
+        const int k = 0;
+        UNCHK(W, W.ckpt, (int64_t)n * l0.nv, "the checkpoints");
+        UNCHK(W, W.u0, l0.nv, "the working iterate");
+    }
     for (int k = 0; k < L; k++) {
         const int64_t nv = P->lev[k].nv;
         TRY(fill<double>(W.Dbar[k], nv, 0.0, st));
@@ -2132,17 +2230,7 @@ int dmgs_likelihood_grad(dmgs_plan P, const double* q, const double* d, const do
     const std::vector<int>* replay = (P->opt.adjoint_schedule && P->opt.fixed_cycles <= 0) ? &P->fwd_schedule : nullptr;
     const int sa = solve(P, P->scratch64, qbar, 0.0, 1, info_vjp, st, replay);
     const bool ok_a = sa == DMGS_OK || sa == DMGS_ERR_NOT_CONVERGED;
-    if (ok_a && (logD_bar || logmua_bar)) {
-        TIMED(P, 0, DMGS_K_GRAD, 48.0 * l0.nv, st,
-              hipLaunchKernelGGL(is2d(P) ? k2_coef_grads : k_coef_grads, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st,
-                                 (const double*)rho, (const double*)qbar, (const double*)l0.D64, (const double*)l0.mu64,
-                                 l0.N, l0.inv_h2, harmonic(P), logD_bar, logmua_bar));
-    }
-    if (ok_a && logmua_bar) {
-        hipLaunchKernelGGL(k_likelihood_direct, dim3(grid_for(l0.nv, 4096)), dim3(kBlock), 0, st, (const double*)rho,
-                           (const double*)l0.mu64, d, w, l0.nv, l0.N, P->opt.ndim, logmua_bar);
-        LAUNCHCHK();
-    }
+    if (ok_a && (logD_bar || logmua_bar)) TRY(coef_grads(P, rho, qbar, logD_bar, logmua_bar, d, w, st));
     HIPCHK(hipEventRecord(P->ev_norm, st));
     TRY(read_norms(P, st));
     const double H = 0.5 * P->hnorm[2], nvox = P->hnorm[3];

@@ -23,6 +23,15 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
 }
 
 
+// The same for any block count: XCD x (blocks b = x, x + 8, ...) takes the
+// contiguous range of logical blocks [x*floor(nb/8) + min(x, nb%8), ...) of
+// its size, a bijection of [0, nb).
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+    const int kXcd = 8;
+    const int x = b % kXcd, i = b / kXcd, q = nblocks / kXcd, r = nblocks % kXcd;
+    return x * q + min(x, r) + i;
+}
+
 constexpr int kWave = 64;
 
 __host__ __device__ inline int64_t vidx(int n, int x, int y, int z) {
