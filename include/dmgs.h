@@ -264,6 +264,30 @@ int dmgs_vjp_unrolled(dmgs_plan plan, const double *q, const double *rhobar, dou
 int dmgs_solve_once(const dmgs_options *opt, const double *D, const double *mua, const double *q,
                     double *rho, dmgs_info *info, void *stream);
 
+/* Bytes of the library's static device scratch array (one copy per device,
+ * held until the process ends) that dmgs_solve_once_noalloc works in. */
+#define DMGS_NOALLOC_SCRATCH_BYTES ((size_t)144 << 20)
+
+/* dmgs_solve_once without any allocation, for callers that cannot allocate
+ * device memory (code running between allocation-free points of a serving
+ * loop, harnesses that forbid hipMalloc).  Same arguments, layout, result and
+ * errors as dmgs_solve_once; the caller passes the inputs and the output.
+ * The plan's hierarchy and work buffers are carved from a static device
+ * array of DMGS_NOALLOC_SCRATCH_BYTES (144 MiB: 3D grids up to N = 128 in
+ * both precisions, 2D grids up to N = 1536); a plan needing more than that
+ * (dmgs_workspace_bytes(opt) + 64 KiB for alignment) is rejected with
+ * DMGS_ERR_INVALID before any device work.  The call makes no hipMalloc,
+ * hipFree, pinned-host or event allocation: norms and the validation flag
+ * are copied to host variables and waited for by synchronising the stream.
+ * All calls on one device share that device's array, which keeps the last
+ * call's contents (each call clears what must start at zero).  The library
+ * serialises calls on one device with a host lock and each call returns
+ * with its work complete, so calls never overlap on the array; work of
+ * other library calls is unaffected.  info->device_ms is 0 (no events).
+ * Devices 0..15 only. */
+int dmgs_solve_once_noalloc(const dmgs_options *opt, const double *D, const double *mua, const double *q,
+                            double *rho, dmgs_info *info, void *stream);
+
 const char *dmgs_status_string(int status);
 const char *dmgs_last_error(void);
 

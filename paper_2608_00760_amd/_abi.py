@@ -14,6 +14,7 @@ DMGS_ERR_NONFINITE, DMGS_ERR_HIP, DMGS_ERR_BUDGET = 4, 5, 6
 DMGS_FP64, DMGS_FP32_IN_FP64 = 0, 1
 DMGS_RBGS, DMGS_WJACOBI = 0, 1
 DMGS_FACE_ARITH, DMGS_FACE_HARMONIC = 0, 1
+DMGS_NOALLOC_SCRATCH_BYTES = 144 << 20
 
 
 class Options(C.Structure):
@@ -50,6 +51,7 @@ SIGNATURES = {
     "dmgs_vjp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Info), _vp]),
     "dmgs_forward_vjp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Info), C.POINTER(Info), _vp]),
     "dmgs_solve_once": (_i, [C.POINTER(Options), _vp, _vp, _vp, _vp, C.POINTER(Info), _vp]),
+    "dmgs_solve_once_noalloc": (_i, [C.POINTER(Options), _vp, _vp, _vp, _vp, C.POINTER(Info), _vp]),
     "dmgs_noise_weights": (_i, [_vp, _vp, C.c_int32, C.c_double, C.c_double, _vp, _vp]),
     "dmgs_vjp_unrolled": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Info), _vp]),
     "dmgs_likelihood_grad": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_double), C.POINTER(Info),

@@ -13,6 +13,7 @@
 #include <new>
 #include <string>
 #include <thread>
+#include <mutex>
 #include <vector>
 
 #include "kernels_basic.hpp"
@@ -148,8 +149,25 @@ size_t footprint(const dmgs_options* o) {
     return b;
 }
 
+// Slack of an arena plan over its footprint: each buffer starts on a 256-byte
+// boundary (at most kMaxLevels * 12 + 8 buffers).
+constexpr size_t kArenaSlack = 64 * 1024;
+
 template <class T>
 int dalloc(dmgs_plan P, T** p, int64_t count) {
+    if (P->arena) {
+        const size_t off = (P->arena_used + 255) & ~(size_t)255;
+        const size_t bytes = (size_t)count * sizeof(T);
+        if (off + bytes > P->arena_cap) {
+            *p = nullptr;
+            set_error("the plan needs more than the %zu bytes of its arena", P->arena_cap);
+            return DMGS_ERR_INVALID;
+        }
+        *p = reinterpret_cast<T*>(P->arena + off);
+        P->arena_used = off + bytes;
+        P->bytes += bytes;
+        return DMGS_OK;
+    }
     hipError_t e = hipMalloc((void**)p, (size_t)count * sizeof(T));
     if (e != hipSuccess) {
         *p = nullptr;
@@ -162,6 +180,7 @@ int dalloc(dmgs_plan P, T** p, int64_t count) {
 
 void free_plan(dmgs_plan P) {
     if (!P) return;
+    if (P->arena) return;   // arena plans own no resources and live in static storage
     if (P->unwork && P->unwork_free) P->unwork_free(P->unwork);
     if (P->twin) free_plan(P->twin);
     if (P->twin_stream) (void)hipStreamDestroy(P->twin_stream);
@@ -194,6 +213,17 @@ void free_plan(dmgs_plan P) {
 }
 
 bool is_ir(dmgs_plan P) { return P->opt.precision == DMGS_FP32_IN_FP64; }
+
+// Where the reductions write their norms: the pinned host slots, or the
+// device slots of an arena plan (copied to the host by read_norms).
+double* norm_dst(dmgs_plan P) { return P->arena ? P->dnorm : P->hnorm; }
+
+// After the last norm reduction enqueued on st.
+int mark_norms(dmgs_plan P, hipStream_t st) {
+    if (!P->arena) HIPCHK(hipEventRecord(P->ev_norm, st));
+    P->tmark = P->tpending;
+    return DMGS_OK;
+}
 bool is2d(dmgs_plan P) { return P->opt.ndim == 2; }
 int harmonic(dmgs_plan P) { return P->opt.face_mean == DMGS_FACE_HARMONIC; }
 
@@ -859,18 +889,21 @@ int ir_step(dmgs_plan P, const double* x, const float* e, double* x_out, const d
     LAUNCHCHK();
     TRY(tend(P, tslot, DMGS_K_RESIDUAL, bytes, st));
     // the final sum goes straight to the plan's pinned host slots
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, P->hnorm, slot);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, norm_dst(P), slot);
     LAUNCHCHK();
-    HIPCHK(hipEventRecord(P->ev_norm, st));
-    P->tmark = P->tpending;
-    return DMGS_OK;
+    return mark_norms(P, st);
 }
 
 // The reduction kernels write the norms into pinned host memory; waiting for
 // the event after the last of them makes them readable (work enqueued after
-// it may still be running).
+// it may still be running).  An arena plan copies its device slots to the
+// host and waits for the stream.
 int read_norms(dmgs_plan P, hipStream_t st) {
-    (void)st;
+    if (P->arena) {
+        HIPCHK(hipMemcpyAsync(P->hnorm, P->dnorm, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return DMGS_OK;
+    }
     HIPCHK(hipEventSynchronize(P->ev_norm));
     if (P->timing) TRY(timing_flush(P, P->tmark));
     return DMGS_OK;
@@ -1055,11 +1088,9 @@ int resid2(dmgs_plan P, const double* x, const double* b, int slot, hipStream_t 
     TIMED(P, 0, DMGS_K_RESIDUAL, 32.0 * l.nv, st,
           hipLaunchKernelGGL(k2_resid_sq<HARM>, dim3(nb), dim3(kBlock), 0, st, x, b, (const double*)l.D64,
                              (const double*)l.mu64, l.N, l.stencil<double>(HARM), P->partial));
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, P->hnorm, slot);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, norm_dst(P), slot);
     LAUNCHCHK();
-    HIPCHK(hipEventRecord(P->ev_norm, st));
-    P->tmark = P->tpending;
-    return DMGS_OK;
+    return mark_norms(P, st);
 }
 
 // solve() for two-dimensional plans (same modes, schedule record and replay).
@@ -1284,7 +1315,7 @@ int begin_call(dmgs_plan P, hipStream_t st, bool need_coef = true) {
     if (!P) { set_error("plan is NULL"); return DMGS_ERR_INVALID; }
     if (need_coef && !P->coef_set) { set_error("coefficients not set"); return DMGS_ERR_INVALID; }
     HIPCHK(hipSetDevice(P->device));
-    HIPCHK(hipEventRecord(P->ev_start, st));
+    if (P->ev_start) HIPCHK(hipEventRecord(P->ev_start, st));
     return DMGS_OK;
 }
 
@@ -1296,7 +1327,7 @@ int end_call(dmgs_plan P, int status, dmgs_info* info, hipStream_t st) {
     if (info) {
         info->status = status;
         info->device_ms = 0.0;
-        if (hipEventRecord(P->ev_stop, st) == hipSuccess && hipEventSynchronize(P->ev_stop) == hipSuccess) {
+        if (P->ev_stop && hipEventRecord(P->ev_stop, st) == hipSuccess && hipEventSynchronize(P->ev_stop) == hipSuccess) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, P->ev_start, P->ev_stop) == hipSuccess) info->device_ms = ms;
         }
@@ -1309,7 +1340,8 @@ int end_call(dmgs_plan P, int status, dmgs_info* info, hipStream_t st) {
 int build_hierarchy(dmgs_plan P, hipStream_t st, const double* logD = nullptr, const double* logmu = nullptr) {
     Level& l0 = P->lev[0];
     *P->hflag = 0;
-    HIPCHK(hipMemsetAsync(P->dflag, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, st, P->dflag, (int64_t)1, 0);
+    LAUNCHCHK();
     if (is2d(P)) {
         if (logD) {
             TIMED(P, 0, DMGS_K_COEF, 32.0 * l0.nv, st,
@@ -1330,7 +1362,7 @@ int build_hierarchy(dmgs_plan P, hipStream_t st, const double* logD = nullptr, c
                                  (const double*)l0.mu64, l0.N, P->dflag));
     }
     HIPCHK(hipMemcpyAsync(P->hflag, P->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipEventRecord(P->ev_flag, st));
+    if (!P->arena) HIPCHK(hipEventRecord(P->ev_flag, st));
     // the hierarchy is built while the host waits for the flag (on invalid
     // coefficients it is garbage, and the plan is marked unset)
     for (int k = 1; k < P->L; k++) {
@@ -1362,7 +1394,8 @@ int build_hierarchy(dmgs_plan P, hipStream_t st, const double* logD = nullptr, c
         }
         LAUNCHCHK();
     }
-    HIPCHK(hipEventSynchronize(P->ev_flag));
+    if (P->arena) HIPCHK(hipStreamSynchronize(st));
+    else HIPCHK(hipEventSynchronize(P->ev_flag));
     if (*P->hflag) {
         P->coef_set = false;
         set_error("coefficients must satisfy D > 0, mua >= 0 and be finite");
@@ -1532,14 +1565,18 @@ size_t dmgs_forward_vjp_workspace_bytes(const dmgs_options* o) {
     return footprint(o) + b;
 }
 
-int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
-    if (!out) { set_error("out is NULL"); return DMGS_ERR_INVALID; }
-    *out = nullptr;
-    TRY(check_options(o));
-    dmgs_plan P = new (std::nothrow) dmgs_plan_s();
-    if (!P) { set_error("host allocation failed"); return DMGS_ERR_OOM; }
+}  // extern "C"
+
+namespace {
+
+// Levels, buffers and configuration of a new plan on the current device.
+// Ordinary plans allocate every buffer (hipMalloc, pinned host slots,
+// events) and clear the work buffers synchronously; arena plans (P->arena
+// set) carve the buffers from the arena and clear them with fill kernels on
+// stream zst.  On failure the caller frees what was allocated (free_plan).
+int plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
     P->opt = *o;
-    if (hipGetDevice(&P->device) != hipSuccess) { delete P; set_error("hipGetDevice failed"); return DMGS_ERR_HIP; }
+    if (hipGetDevice(&P->device) != hipSuccess) { set_error("hipGetDevice failed"); return DMGS_ERR_HIP; }
     {
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && ncu > 0)
@@ -1584,28 +1621,44 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     if (st == DMGS_OK) st = dalloc(P, &P->cinv, kCoarseMax * kCoarseMax);
 
     if (st == DMGS_OK) st = dalloc(P, &P->dflag, 1);
-    if (st == DMGS_OK && hipHostMalloc((void**)&P->hnorm, 4 * sizeof(double), hipHostMallocCoherent) != hipSuccess) {
-        set_error("hipHostMalloc failed");
-        st = DMGS_ERR_OOM;
-    }
-    if (st == DMGS_OK && hipHostMalloc((void**)&P->hflag, sizeof(int), hipHostMallocDefault) != hipSuccess) {
-        set_error("hipHostMalloc failed");
-        st = DMGS_ERR_OOM;
-    }
-    if (st == DMGS_OK && (hipEventCreate(&P->ev_start) != hipSuccess || hipEventCreate(&P->ev_stop) != hipSuccess ||
-                          hipEventCreateWithFlags(&P->ev_norm, hipEventDisableTiming) != hipSuccess ||
-                          hipEventCreateWithFlags(&P->ev_flag, hipEventDisableTiming) != hipSuccess)) {
-        set_error("hipEventCreate failed");
-        st = DMGS_ERR_HIP;
+    if (P->arena) {
+        if (st == DMGS_OK) st = dalloc(P, &P->dnorm, 4);
+        P->hnorm = P->hnorm_buf;
+        P->hflag = &P->hflag_buf;
+    } else {
+        if (st == DMGS_OK && hipHostMalloc((void**)&P->hnorm, 4 * sizeof(double), hipHostMallocCoherent) != hipSuccess) {
+            set_error("hipHostMalloc failed");
+            st = DMGS_ERR_OOM;
+        }
+        if (st == DMGS_OK && hipHostMalloc((void**)&P->hflag, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+            set_error("hipHostMalloc failed");
+            st = DMGS_ERR_OOM;
+        }
+        if (st == DMGS_OK && (hipEventCreate(&P->ev_start) != hipSuccess || hipEventCreate(&P->ev_stop) != hipSuccess ||
+                              hipEventCreateWithFlags(&P->ev_norm, hipEventDisableTiming) != hipSuccess ||
+                              hipEventCreateWithFlags(&P->ev_flag, hipEventDisableTiming) != hipSuccess)) {
+            set_error("hipEventCreate failed");
+            st = DMGS_ERR_HIP;
+        }
     }
     // every work buffer starts at 0: the passes never write boundary layers,
-    // and coarse corrections have homogeneous boundaries
+    // and coarse corrections have homogeneous boundaries (an arena keeps the
+    // last call's contents, so its buffers are cleared on the stream)
     for (int k = 0; k < P->L && st == DMGS_OK; k++) {
         Level& l = P->lev[k];
-        void* ps[] = {l.u64, l.q64, l.t64, l.u32, l.q32, l.t32, l.r32};
-        size_t sz[] = {8, 8, 8, 4, 4, 4, 4};
-        for (int j = 0; j < 7 && st == DMGS_OK; j++)
-            if (ps[j] && hipMemset(ps[j], 0, l.nv * sz[j]) != hipSuccess) { set_error("hipMemset failed"); st = DMGS_ERR_HIP; }
+        void* ps[] = {l.u64, l.q64, l.t64, l.u32, l.q32, l.t32, l.r32, l.rd64};
+        size_t sz[] = {8, 8, 8, 4, 4, 4, 4, 8};
+        for (int j = 0; j < 8 && st == DMGS_OK; j++) {
+            if (!ps[j]) continue;
+            if (P->arena) {
+                if (sz[j] == 8) hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(l.nv)), dim3(kBlock), 0, zst, (double*)ps[j], l.nv, 0.0);
+                else hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(l.nv)), dim3(kBlock), 0, zst, (float*)ps[j], l.nv, 0.0f);
+                if (hipGetLastError() != hipSuccess) { set_error("fill kernel launch failed"); st = DMGS_ERR_HIP; }
+            } else if (hipMemset(ps[j], 0, l.nv * sz[j]) != hipSuccess) {
+                set_error("hipMemset failed");
+                st = DMGS_ERR_HIP;
+            }
+        }
     }
     P->cfg_sweep = 0;
     P->cfg_fuse_min = ir ? 32 : 16;
@@ -1661,6 +1714,20 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     if (const char* e = std::getenv("DMGS_2D_BLOCK_MIN")) P->cfg_2d_block_min = std::max(4, std::atoi(e));
     if (const char* e = std::getenv("DMGS_2D_DEFECT")) P->cfg_2d_defect = std::atoi(e) != 0;
     if (const char* e = std::getenv("DMGS_2D_CHUNK")) P->cfg_2d_chunk = std::max(8, std::atoi(e) / 8 * 8);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
+    if (!out) { set_error("out is NULL"); return DMGS_ERR_INVALID; }
+    *out = nullptr;
+    TRY(check_options(o));
+    dmgs_plan P = new (std::nothrow) dmgs_plan_s();
+    if (!P) { set_error("host allocation failed"); return DMGS_ERR_OOM; }
+    const int st = plan_init(P, o, nullptr);
     if (st != DMGS_OK) {
         free_plan(P);
         return st;
@@ -2223,15 +2290,15 @@ int dmgs_likelihood_grad(dmgs_plan P, const double* q, const double* d, const do
     TIMED(P, 0, DMGS_K_GRAD, 40.0 * l0.nv, st,
           hipLaunchKernelGGL(k_likelihood_epilogue, dim3(nb), dim3(kBlock), 0, st, (const double*)rho,
                              (const double*)l0.mu64, d, w, l0.nv, l0.N, P->opt.ndim, P->scratch64, P->partial));
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, P->hnorm, 2);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, norm_dst(P), 2);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial + nb, (int)nb, P->hnorm, 3);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial + nb, (int)nb, norm_dst(P), 3);
     LAUNCHCHK();
     const std::vector<int>* replay = (P->opt.adjoint_schedule && P->opt.fixed_cycles <= 0) ? &P->fwd_schedule : nullptr;
     const int sa = solve(P, P->scratch64, qbar, 0.0, 1, info_vjp, st, replay);
     const bool ok_a = sa == DMGS_OK || sa == DMGS_ERR_NOT_CONVERGED;
     if (ok_a && (logD_bar || logmua_bar)) TRY(coef_grads(P, rho, qbar, logD_bar, logmua_bar, d, w, st));
-    HIPCHK(hipEventRecord(P->ev_norm, st));
+    TRY(mark_norms(P, st));
     TRY(read_norms(P, st));
     const double H = 0.5 * P->hnorm[2], nvox = P->hnorm[3];
     value[0] = H;
@@ -2251,6 +2318,67 @@ int dmgs_solve_once(const dmgs_options* o, const double* D, const double* mua, c
     if (s == DMGS_OK) s = dmgs_forward(P, q, rho, info, stream);
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && s == DMGS_OK) s = DMGS_ERR_HIP;
     dmgs_plan_destroy(P);
+    return s;
+}
+
+}  // extern "C"
+
+// Static scratch of dmgs_solve_once_noalloc: every device the library runs
+// on holds one copy until the process ends.  In host code the name stands
+// for a host-side object; the device address of each device's copy comes
+// from hipGetSymbolAddress, taken once per device.
+static __device__ __align__(256) unsigned char scratch[DMGS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kNoallocDevices = 16;
+struct NoallocSlot {
+    std::mutex lock;                // serialises the calls on this device
+    unsigned char* ptr = nullptr;   // this device's address of `scratch`
+    dmgs_plan_s plan;               // host side of the arena plan, reset by each call
+};
+NoallocSlot g_noalloc[kNoallocDevices];
+}  // namespace
+
+extern "C" {
+
+int dmgs_solve_once_noalloc(const dmgs_options* o, const double* D, const double* mua, const double* q, double* rho,
+                            dmgs_info* info, void* stream) {
+    TRY(check_options(o));
+    if (!D || !mua || !q || !rho) { set_error("NULL argument"); return DMGS_ERR_INVALID; }
+    const size_t need = footprint(o) + kArenaSlack;
+    if (need > (size_t)DMGS_NOALLOC_SCRATCH_BYTES) {
+        set_error("dmgs_solve_once_noalloc: the plan needs %zu bytes (workspace %zu plus alignment), more than the "
+                  "%zu bytes of the static scratch", need, footprint(o), (size_t)DMGS_NOALLOC_SCRATCH_BYTES);
+        return DMGS_ERR_INVALID;
+    }
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoallocDevices) {
+        set_error("dmgs_solve_once_noalloc: device %d beyond the %d the library keeps scratch addresses for", dev,
+                  kNoallocDevices);
+        return DMGS_ERR_INVALID;
+    }
+    NoallocSlot& S = g_noalloc[dev];
+    std::lock_guard<std::mutex> guard(S.lock);
+    if (!S.ptr) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress of the static scratch failed: %s", hipGetErrorString(e));
+            return DMGS_ERR_HIP;
+        }
+        S.ptr = static_cast<unsigned char*>(p);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    dmgs_plan P = &S.plan;
+    *P = dmgs_plan_s();
+    P->arena = S.ptr;
+    P->arena_cap = (size_t)DMGS_NOALLOC_SCRATCH_BYTES;
+    TRY(plan_init(P, o, st));
+    int s = dmgs_set_coefficients(P, D, mua, stream);
+    if (s == DMGS_OK) s = dmgs_forward(P, q, rho, info, stream);
+    // the call returns with its work done: the next call may reuse the array
+    if (hipStreamSynchronize(st) != hipSuccess && s == DMGS_OK) s = DMGS_ERR_HIP;
     return s;
 }
 

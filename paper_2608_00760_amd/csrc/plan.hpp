@@ -122,4 +122,13 @@ struct dmgs_plan_s {
     // and kept for later ones (freed with the plan through unwork_free)
     void* unwork = nullptr;
     void (*unwork_free)(void*) = nullptr;
+    // allocation-free plans: every device buffer is carved from an arena of
+    // device memory the plan does not own; the norms and the validation flag
+    // are read back by copies and stream synchronisation instead of pinned
+    // host memory and events
+    unsigned char* arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+    double* dnorm = nullptr;     // device norm slots the reductions write (arena plans)
+    double hnorm_buf[4] = {};    // host copies of the norms (arena plans)
+    int hflag_buf = 0;           // host copy of the validation flag (arena plans)
 };

@@ -81,6 +81,37 @@ def _stream(device):
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def _solve_once(fn, where, opts: Options, D, mua, q, out=None, check=True):
+    shape = (opts.N + 1,) * opts.ndim
+    dev = q.device
+    for name, t in (("D", D), ("mua", mua), ("q", q)) + ((("out", out),) if out is not None else ()):
+        if (not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != dev or not t.is_cuda
+                or tuple(t.shape) != shape or not t.is_contiguous()):
+            raise ValueError("%s must be a contiguous float64 CUDA tensor of shape %s on %s" % (name, shape, dev))
+    rho = torch.empty(shape, dtype=torch.float64, device=dev) if out is None else out
+    o = opts.to_c()
+    info = _abi.Info()
+    with torch.cuda.device(dev):
+        st = fn(C.byref(o), C.c_void_p(D.data_ptr()), C.c_void_p(mua.data_ptr()), C.c_void_p(q.data_ptr()),
+                C.c_void_p(rho.data_ptr()), C.byref(info), _stream(dev))
+    if check and st != _abi.DMGS_OK:
+        raise _abi.DMGSError(st, where, info.as_dict())
+    return rho, dict(info.as_dict(), status=st)
+
+
+def solve_once(opts: Options, D, mua, q, out=None, check=True):
+    """dmgs_solve_once: a plan created, used for one forward solve and
+    destroyed."""
+    return _solve_once(_abi.lib().dmgs_solve_once, "dmgs_solve_once", opts, D, mua, q, out, check)
+
+
+def solve_once_noalloc(opts: Options, D, mua, q, out=None, check=True):
+    """dmgs_solve_once_noalloc: the same solve in the library's static scratch
+    array, with no device allocation (pass `out` to allocate nothing here
+    either)."""
+    return _solve_once(_abi.lib().dmgs_solve_once_noalloc, "dmgs_solve_once_noalloc", opts, D, mua, q, out, check)
+
+
 class Plan:
     def __init__(self, opts: Options, device=None):
         self.opts = opts

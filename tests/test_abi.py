@@ -108,6 +108,28 @@ def test_two_dimensional_options(abi):
     assert lib.dmgs_workspace_bytes(C.byref(ob)) > 0
 
 
+def test_noalloc_rejections_before_device_work(abi):
+    """dmgs_solve_once_noalloc checks its options, pointers and the size of
+    the plan against the static scratch array before touching a device (so
+    these calls run here, without a GPU)."""
+    lib = abi.lib()
+    fake = C.c_void_p(0x1000)   # never dereferenced: every call below fails on the host first
+    for N, prec, ok_size in ((128, abi.DMGS_FP32_IN_FP64, True), (192, abi.DMGS_FP64, False),
+                             (256, abi.DMGS_FP32_IN_FP64, False)):
+        o = abi.default_options(N)
+        o.precision = prec
+        fits = lib.dmgs_workspace_bytes(C.byref(o)) + 64 * 1024 <= abi.DMGS_NOALLOC_SCRATCH_BYTES
+        assert fits == ok_size, N
+        if not fits:
+            st = lib.dmgs_solve_once_noalloc(C.byref(o), fake, fake, fake, fake, None, None)
+            assert st == abi.DMGS_ERR_INVALID and "static scratch" in abi.last_error(), N
+    o = abi.default_options(32)
+    st = lib.dmgs_solve_once_noalloc(C.byref(o), fake, None, fake, fake, None, None)
+    assert st == abi.DMGS_ERR_INVALID and "NULL" in abi.last_error()
+    o.n[0] = 5
+    assert lib.dmgs_solve_once_noalloc(C.byref(o), fake, fake, fake, fake, None, None) == abi.DMGS_ERR_INVALID
+
+
 def test_status_strings(abi):
     assert abi.status_string(0) == "ok"
     assert abi.status_string(3) == "not converged"
