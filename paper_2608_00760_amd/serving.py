@@ -5,9 +5,11 @@ variational inference run do).  A dispatcher admits them in arrival order
 whenever a slot is free and their device-memory footprint (the plan's
 hierarchy and workspace, from dmgs_workspace_bytes, plus the request's
 fields) fits in the HBM budget; idle pooled plans are evicted to make room.
-Admitted requests run on worker threads, each driving the native library on
-its own HIP stream, so the work of requests that arrived while others were
-running overlaps on the device.  Hierarchies stay resident: plans are pooled
+Freed blocks that torch's caching allocator keeps count against the budget
+too: when they would take the resident total past it, they are released
+before the next admission.  Admitted requests run on worker threads, each
+driving the native library on its own HIP stream, so the work of requests
+that arrived while others were running overlaps on the device.  Hierarchies stay resident: plans are pooled
 per grid size and reused.  Per-request arithmetic does not depend on what
 else is running (every kernel and reduction is deterministic), so a result
 is bitwise the same alone and in the mix.
@@ -125,10 +127,15 @@ def request_fields(req, device):
 
 
 def field_bytes(N, mode):
+    """Device bytes a request's own tensors take while it runs: inputs (log D,
+    log mua, q, and the tangent's three fields or the cotangent), outputs
+    (rho and rho', or rho and three gradients) and the generator's
+    transient FFT fields (at most 5), each rounded up to the caching
+    allocator's 2 MiB granularity."""
     nv = (N + 1) ** 3
-    # inputs (logD, logmua, q, tangent/cotangent) + outputs + generator temporaries
-    nfields = (6 + 1 + 3) if mode == "jvp" else (4 + 1 + 3)
-    return nfields * nv * 8 + 4 * nv * 8
+    field = -(-nv * 8 // (2 << 20)) * (2 << 20)
+    nfields = (6 + 2) if mode == "jvp" else (4 + 4)
+    return (nfields + 5) * field
 
 
 class Server:
@@ -151,6 +158,12 @@ class Server:
         self._ws = lambda N: workspace_bytes(Options(N, **self.opts), forward_vjp=True)
         self.lock = threading.Lock()
         self.cv = threading.Condition(self.lock)
+        # device bytes of the plans that exist (running or pooled) and their
+        # peak, each counted as dmgs_forward_vjp_workspace_bytes (exact once
+        # the plan has run a forward + VJP request, an upper bound before)
+        self.plan_live = 0
+        self.plan_peak = 0
+        self.cache_releases = 0
 
     # -- plan pool (called with the lock held) ---------------------------------
     def _need_of(self, req):
@@ -164,8 +177,25 @@ class Server:
             N, plan = self.pool_order.popleft()
             self.pool[N].remove(plan)
             plan.close()
+            self.plan_live -= self.plan_bytes[N]
             freed += self.plan_bytes[N]
         return freed
+
+    def _release_cache_if_needed(self):
+        """Freed blocks that torch's caching allocator keeps are device memory
+        the accounting does not see.  When they and the next request's need
+        would take the resident total past the budget, return them to the
+        device (torch.cuda.empty_cache) before admitting it."""
+        import torch
+        if not self.adm.queue or self.adm.active >= self.adm.max_slots:
+            return
+        cached = torch.cuda.memory_reserved(self.device) - torch.cuda.memory_allocated(self.device)
+        if cached <= 0:
+            return
+        need, reuse = self._need_of(self.adm.queue[0])
+        if self.adm.resident() + (need - reuse) + cached > self.adm.budget:
+            torch.cuda.empty_cache()
+            self.cache_releases += 1
 
     def _take_plan(self, N):
         from .solver import Options, Plan
@@ -223,6 +253,9 @@ class Server:
                     req, need, plan = work.popleft()
                 try:
                     if plan is None:
+                        with self.cv:
+                            self.plan_live += self.plan_bytes[req.N]
+                            self.plan_peak = max(self.plan_peak, self.plan_live)
                         plan = self._new_plan(req.N)
                     out, cyc = self._execute(req, plan, stream)
                     req.cycles = cyc
@@ -231,6 +264,8 @@ class Server:
                 except Exception as e:     # a failed request is retired with its status
                     req.status = "error"
                     req.error = str(e)
+                    with self.cv:
+                        self.plan_live -= self.plan_bytes[req.N]
                     if plan is not None:
                         plan.close()
                         plan = None
@@ -256,6 +291,7 @@ class Server:
                     self.adm.offer(reqs[i])
                     i += 1
                 while True:
+                    self._release_cache_if_needed()
                     got = self.adm.next_admissible(self._need_of, self._evict)
                     if got is None:
                         break

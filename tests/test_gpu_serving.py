@@ -1,11 +1,23 @@
-"""Continuous-batching serving loop: every result is bitwise the same alone
-and in the mix, the memory budget is never exceeded, and requests queue when
-it is tight."""
+"""Continuous-batching serving loop (GPU):
+
+* every result is bitwise the same alone and in the mix;
+* the memory budget holds for measured device memory: torch's peak reserved
+  memory (the requests' fields and results) plus the bytes of the plans that
+  existed at the peak stays within the budget;
+* requests queue when the budget is tight, and one that can never fit is
+  rejected;
+* every served result of a mixed stream over the four serving grid sizes
+  (64^3, 96^3, 128^3, 192^3) and both request kinds matches the oracle's
+  1e-13 solves: rho and rho' (forward + JVP) or rho and the three
+  gradients (forward + VJP), to 1e-8 of the largest entry (Sec. 2.4
+  stopping rule at rtol 1e-10).
+"""
 import copy
 
+import numpy as np
 import pytest
 
-from gpu_util import say
+from gpu_util import rel_max, say
 
 pytestmark = pytest.mark.gpu
 
@@ -25,13 +37,27 @@ def test_alone_equals_in_the_mix_and_budget_holds():
     need = max(workspace_bytes(Options(r.N, precision="fp32-in-fp64"), forward_vjp=True) + field_bytes(r.N, r.mode)
                for r in reqs)
     budget = int(2.5 * need)         # tight: forces queueing
-    srv = Server(budget_bytes=budget, max_slots=4)
-    mixed = srv.run(copy.deepcopy(reqs), realtime=False)
-    s = summarize(mixed)
-    say("serving summary", s, "peak", srv.adm.peak, "budget", budget, "max queue", srv.adm.max_queue)
+    # measured device memory of the server itself (results are dropped as
+    # they are produced: results a caller keeps are its own memory)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    base = torch.cuda.memory_reserved()
+    srv = Server(budget_bytes=budget, max_slots=4, keep_results=False)
+    s = summarize(srv.run(copy.deepcopy(reqs), realtime=False))
+    measured = torch.cuda.max_memory_reserved() - base + srv.plan_peak
+    say("serving summary", s, "accounted peak", srv.adm.peak, "measured peak", measured, "(torch reserved",
+        torch.cuda.max_memory_reserved() - base, "+ plans", srv.plan_peak, ") budget", budget,
+        "max queue", srv.adm.max_queue, "cache releases", srv.cache_releases)
     assert s["done"] == len(reqs)
     assert srv.adm.peak <= budget
+    assert measured <= budget
     assert srv.adm.max_queue > 1
+    srv.close()
+    # the same stream keeping its results, for the comparison below
+    srv = Server(budget_bytes=budget, max_slots=4)
+    mixed = srv.run(copy.deepcopy(reqs), realtime=False)
+    assert summarize(mixed)["done"] == len(reqs) and srv.adm.peak <= budget
     srv.close()
     say("serving: each request alone")
     for r in reqs:
@@ -40,6 +66,32 @@ def test_alone_equals_in_the_mix_and_budget_holds():
         assert alone.status == "done" and alone.cycles == m.cycles
         for k, v in alone.result.items():
             assert torch.equal(v, m.result[k]), (r.id, k)
+
+
+def test_served_results_match_the_oracle():
+    import torch
+    from oracle import ref
+    from paper_2608_00760_amd.serving import Request, Server, request_fields, summarize
+    sizes = (64, 96, 128, 192)
+    reqs = [Request(id=i, N=sizes[i // 2], mode=("jvp", "vjp")[i % 2], seed=7300 + i) for i in range(8)]
+    say("serving: mixed stream over", sizes, "both modes")
+    srv = Server(budget_bytes=32 << 30, max_slots=4)
+    out = srv.run(copy.deepcopy(reqs), realtime=False)
+    assert summarize(out)["done"] == len(reqs)
+    srv.close()
+    for r in sorted(out, key=lambda r: r.id):
+        f = {k: v.cpu().numpy() for k, v in request_fields(r, torch.device("cuda:0")).items()}
+        H = ref.Hierarchy(np.exp(f["logD"]), np.exp(f["logmua"]))
+        rho, _ = H.forward(f["q"], rtol=1e-13)
+        want = {"rho": rho}
+        if r.mode == "jvp":
+            want["drho"], _ = H.jvp(rho, f["dq"], f["dlogD"], f["dlogmua"], rtol=1e-13)
+        else:
+            (want["qbar"], want["logD_bar"], want["logmua_bar"]), _ = H.vjp(rho, f["rhobar"], rtol=1e-13)
+        errs = {k: rel_max(r.result[k].cpu().numpy(), v) for k, v in want.items()}
+        say("served N=%d %s cycles %s: max rel err %s" % (r.N, r.mode, r.cycles,
+                                                           {k: "%.1e" % e for k, e in errs.items()}))
+        assert max(errs.values()) <= 1e-8, (r.N, r.mode, errs)
 
 
 def test_poisson_arrivals_and_rejection():
