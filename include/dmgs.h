@@ -104,7 +104,14 @@ typedef struct dmgs_options {
     int32_t adjoint_schedule; /* tolerance mode: 0 (default) = a pull-back stops on its own residual;
                                  1 = it repeats exactly the V-cycle schedule of the last dmgs_forward on
                                  this plan (the count recorded in the forward pass; Sec. 2.4), so that
-                                 in float64 it is the exact transpose of that forward solve */
+                                 in float64 it is the exact transpose of that forward solve.  Its
+                                 accuracy then follows from that count, not from rtol: the adjoint
+                                 residual is whatever the forward's schedule reaches on the adjoint
+                                 system (reported in info).  In DMGS_FP32_IN_FP64 plans, where the
+                                 replay repeats the refinement steps and their float32 V-cycle
+                                 counts, the contract is a relative gradient error of at most 1e-7
+                                 against the converged adjoint (checked at 64^3; 1e-8 needs
+                                 adjoint_schedule = 0) */
     int32_t ndim;          /* 3 (default): (N+1)^3 grids, 7-point operator.  2: (N+1)^2 grids and the
                               5-point operator of the same equation in two dimensions (the paper's
                               benchmark setting, Sec. 3.3), with red = (x + y) even, restriction

@@ -74,15 +74,17 @@ def test_backward_resets_coefficients_changed_in_between():
     assert torch.equal(gq, eq) and torch.equal(gD, eD) and torch.equal(gmu, emu)
 
 
-def test_central_differences_128_32_directions():
-    """Gradients of <w, u> against central differences, 32 seeded directions."""
+@pytest.mark.parametrize("precision", ["fp64", "fp32-in-fp64"])
+def test_central_differences_128_32_directions(precision):
+    """Gradients of <w, u> against central differences, 32 seeded directions
+    (the 128^3 workload: float64, as it is named, and the mixed mode)."""
     import torch
     from paper_2608_00760_amd import synth
     from paper_2608_00760_amd.autograd import Solver
-    say("central differences 128^3")
+    say("central differences 128^3 %s" % precision)
     N = 128
     c = synth.grf_128()
-    S = Solver(N, precision="fp32-in-fp64", rtol=1e-12)
+    S = Solver(N, precision=precision, rtol=1e-12)
     q, logD, logmua = (dev(c[k]).requires_grad_(True) for k in ("q", "logD", "logmua"))
     w = dev(c["rhobar"])
     rho = S(q, logD, logmua)
@@ -97,7 +99,7 @@ def test_central_differences_128_32_directions():
             fd = (f(eps) - f(-eps)) / (2 * eps)
             ad = float((gq * vq).sum() + (gD * vD).sum() + (gmu * vm).sum())
             worst = max(worst, abs(fd - ad) / abs(ad))
-    say("worst relative FD error", worst)
+    say("worst relative FD error (%s)" % precision, worst)
     assert worst <= 1e-6
 
 

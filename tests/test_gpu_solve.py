@@ -93,7 +93,7 @@ def test_small_constant_workload_closed_form():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32-in-fp64"])
-@pytest.mark.parametrize("N", [64, 96, 128])
+@pytest.mark.parametrize("N", [64, 96, 128, 192])
 def test_tolerance_mode_forward_vjp_against_oracle(precision, N):
     """Forward + VJP to 1e-10 on GRF coefficients; gradients within 1e-8."""
     from oracle import ref
