@@ -21,15 +21,15 @@ import numpy as np
 
 
 def kept(shape, mask):
-    """Boolean array: vertices at least `mask` vertices from every face."""
-    N = shape[0] - 1
-    idx = np.arange(N + 1)
-    ok1 = (idx >= mask) & (idx <= N - mask)
+    """Boolean array: vertices at least `mask` vertices from every face
+    (each axis with its own number of vertices)."""
     out = np.ones(shape, dtype=bool)
-    for a in range(len(shape)):
+    for a, n in enumerate(shape):
+        idx = np.arange(n)
+        ok = (idx >= mask) & (idx <= n - 1 - mask)
         sh = [1] * len(shape)
-        sh[a] = N + 1
-        out &= ok1.reshape(sh)
+        sh[a] = n
+        out &= ok.reshape(sh)
     return out
 
 
