@@ -24,7 +24,10 @@
 //
 // Threads own a column pair (y; z, z+1), z even, of the tile plus a ring of
 // 4, and keep eight planes of their pair in a register ring (planes s-4 ..
-// s+3; s+2 and s+3 are loads in flight).  In-plane neighbours go through an
+// s+3; s+2 and s+3 are loads in flight).  Plane s+3 is loaded right after
+// step s's barrier into the registers of plane s-5 (dead since step s-1), so
+// the load is in flight while the step computes; it is first used at step
+// s+2.  In-plane neighbours go through an
 // eight-slot LDS ring of planes holding {u, D}, laid out by pair element so
 // that consecutive lanes read consecutive 8-byte words; with eight slots
 // and the march unrolled by eight, every slot address is a compile-time
@@ -323,12 +326,13 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_r
     const int s0 = xa - 3 - (DEFECT ? 1 : 0), s_end = xb + 2 + (DEFECT ? 1 : 0);
     const int par0 = __builtin_amdgcn_readfirstlane((s0 + hp + a.order) & 1);   // element updated at step s0
     auto step = [&](auto Kc, int s, SweepPlane<T>& Pm4, SweepPlane<T>& Pm3, SweepPlane<T>& Pm2, SweepPlane<T>& Pm1,
-                    SweepPlane<T>& P0, SweepPlane<T>& Pp1) {
+                    SweepPlane<T>& P0, SweepPlane<T>& Pp1, SweepPlane<T>& Pp3) {
         constexpr int K = decltype(Kc)::value;
         UD<T>* S = ring + K * 2 * RA;
         S[pe] = UD<T>{P0.u0, P0.D0};
         S[RA + pe] = UD<T>{P0.u1, P0.D1};
         lds_barrier();
+        load(s + 3, Pp3);   // into the registers of plane s-5
         if (PROLONG) {
             add_coarse_lds(s + 1, Pp1);   // plane s+1, first used now
             if (cloader) {
@@ -351,8 +355,8 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_r
     };
 
     // register ring of eight planes, the march unrolled by eight so planes
-    // never move between registers; after step s, plane s-4 is dead and its
-    // registers take plane s+4 (first used at step s+3).
+    // never move between registers; plane p lives in R(p - s0 + 4 mod 8),
+    // and step s loads plane s+3 into the registers plane s-5 held.
     SweepPlane<T> R0, R1, R2, R3, R4, R5, R6, R7;
     load(s0 - 4, R0);
     load(s0 - 3, R1);
@@ -361,7 +365,6 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_r
     load(s0, R4);
     load(s0 + 1, R5);
     load(s0 + 2, R6);
-    load(s0 + 3, R7);
     if (PROLONG) {   // planes up to s0 from memory; coarse planes of steps s0 and s0+1 into LDS
         SweepPlane<T>* Ps[] = {&R0, &R1, &R2, &R3, &R4};
         for (int i = 0; i < 5; i++) {
@@ -383,21 +386,21 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_r
     using I6 = std::integral_constant<int, 6>;
     using I7 = std::integral_constant<int, 7>;
     for (int s = s0; s <= s_end; s += 8) {
-        step(I0(), s, R0, R1, R2, R3, R4, R5); load(s + 4, R0);
+        step(I0(), s, R0, R1, R2, R3, R4, R5, R7);
         if (s + 1 > s_end) break;
-        step(I1(), s + 1, R1, R2, R3, R4, R5, R6); load(s + 5, R1);
+        step(I1(), s + 1, R1, R2, R3, R4, R5, R6, R0);
         if (s + 2 > s_end) break;
-        step(I2(), s + 2, R2, R3, R4, R5, R6, R7); load(s + 6, R2);
+        step(I2(), s + 2, R2, R3, R4, R5, R6, R7, R1);
         if (s + 3 > s_end) break;
-        step(I3(), s + 3, R3, R4, R5, R6, R7, R0); load(s + 7, R3);
+        step(I3(), s + 3, R3, R4, R5, R6, R7, R0, R2);
         if (s + 4 > s_end) break;
-        step(I4(), s + 4, R4, R5, R6, R7, R0, R1); load(s + 8, R4);
+        step(I4(), s + 4, R4, R5, R6, R7, R0, R1, R3);
         if (s + 5 > s_end) break;
-        step(I5(), s + 5, R5, R6, R7, R0, R1, R2); load(s + 9, R5);
+        step(I5(), s + 5, R5, R6, R7, R0, R1, R2, R4);
         if (s + 6 > s_end) break;
-        step(I6(), s + 6, R6, R7, R0, R1, R2, R3); load(s + 10, R6);
+        step(I6(), s + 6, R6, R7, R0, R1, R2, R3, R5);
         if (s + 7 > s_end) break;
-        step(I7(), s + 7, R7, R0, R1, R2, R3, R4); load(s + 11, R7);
+        step(I7(), s + 7, R7, R0, R1, R2, R3, R4, R6);
     }
 }
 
