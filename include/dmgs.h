@@ -84,8 +84,12 @@ enum dmgs_smoother { DMGS_RBGS = 0, DMGS_WJACOBI = 1 };
 enum dmgs_face_mean { DMGS_FACE_ARITH = 0, DMGS_FACE_HARMONIC = 1 };
 
 typedef struct dmgs_options {
-    int32_t n[3];          /* cells per axis; all three equal, N = c*2^m, c in {2,3}, 2 <= N <= 1024
-                              (two-dimensional plans: see ndim) */
+    int32_t n[3];          /* cells per axis (x, y, z); all three equal, N = c*2^m, c in {2,3}, 2 <= N <= 1024
+                              (two-dimensional plans: see ndim).  Three-dimensional plans may also take
+                              different counts per axis (a general grid, as the paper's (128, 64, 64)
+                              data grid of Sec. 2.5.1): every axis halves from one level to the next
+                              until the smallest count is 2 or 3, each count 2..1024, and the coarsest
+                              level has at most 64 interior vertices; see h_axis */
     int32_t precision;     /* dmgs_precision */
     int32_t smoother;      /* dmgs_smoother: red-black Gauss-Seidel (Sec. 2.3.1) or weighted Jacobi */
     int32_t nu_pre;        /* pre-smoothing sweeps (red-black pairs), 0..8; default 2 */
@@ -117,6 +121,13 @@ typedef struct dmgs_options {
                               benchmark setting, Sec. 3.3), with red = (x + y) even, restriction
                               (1/16)(1,2,1) x (1,2,1) and bilinear prolongation I = 2^2 R^T; n[0] = n[1]
                               = N (n[2] ignored), 2 <= N <= 16384; DMGS_FP64 and DMGS_RBGS only. */
+    double h_axis[3];      /* three-dimensional plans: spacing per axis (x, y, z); 0 (default) = h.  Unequal
+                              counts in n or unequal spacings make a general-grid plan: the face
+                              coefficient of each axis is D_f / h_a^2, on level k with 2^k h_a (Sec. 2.2
+                              rediscretised per axis); DMGS_FP64 and DMGS_RBGS only, one operation per
+                              launch; every solve, push-forward, pull-back and likelihood entry point
+                              takes them (dmgs_forward_vjp runs its two solves one after the other);
+                              the diagnostic entry points and dmgs_vjp_unrolled do not. */
 } dmgs_options;
 
 typedef struct dmgs_info {
@@ -145,13 +156,38 @@ size_t dmgs_workspace_bytes(const dmgs_options *opt);
 size_t dmgs_forward_vjp_workspace_bytes(const dmgs_options *opt);
 
 /* Create a plan: validate options and allocate the level hierarchy on the
- * current device.  Errors: DMGS_ERR_INVALID, DMGS_ERR_OOM, DMGS_ERR_HIP. */
+ * current device.  Errors: DMGS_ERR_INVALID, DMGS_ERR_OOM, DMGS_ERR_HIP.
+ *
+ * Tuning knobs.  Plan creation reads these environment variables, which
+ * choose which kernel runs on which level and how a launch is cut up; they
+ * change no option's meaning, and every choice they allow computes the same
+ * operators (the tests force several of them to cover every kernel on every
+ * level).  Unset, the tuned defaults apply:
+ *   DMGS_SWEEP2_MIN (64)        smallest N of the two-sweep streaming passes
+ *   DMGS_SWEEP2_WGS (256)       target workgroups of a finest-level two-sweep pass
+ *   DMGS_SWEEP2_WGS_COARSE      ... below the finest level (half of the above)
+ *   DMGS_SWEEP2_DEFECT (2)      pre-smoothing pass writes the defect: 0 never, 1 from a zero iterate, 2 always
+ *   DMGS_SWEEP2_FP64 (1)        float64 levels with a zero boundary use the two-sweep pass
+ *   DMGS_SWEEP_CFG (0)          float32 one-sweep pass tiles: 0 16x64, 1 8x64, 2 16x32
+ *   DMGS_FUSE_MIN (32 / 16)     smallest N of the fused passes (float32 / float64 plans)
+ *   DMGS_BLOCK_MAX (64)         largest N of the LDS block passes
+ *   DMGS_DR_WGS (512)           target workgroups of the defect-restriction pass
+ *   DMGS_2D_SWEEP2_MIN (1536)   two-dimensional plans: smallest N of the two-sweep passes
+ *   DMGS_2D_BLOCK_MIN (64)      ... smallest N of the LDS block passes
+ *   DMGS_2D_DEFECT (1)          ... the last pre-smoothing pass writes the defect
+ *   DMGS_2D_CHUNK (0)           ... rows per chunk of the two-sweep passes (0: from the grid size)
+ *   DMGS_2D_SMALL_MAX (32)      ... largest N of the single-workgroup coarse kernel */
 int dmgs_plan_create(const dmgs_options *opt, dmgs_plan *out);
 int dmgs_plan_destroy(dmgs_plan plan);
 
-/* Number of levels and cells per axis on level k (k = 0 finest). */
+/* Number of levels and cells per axis on level k (k = 0 finest); for a
+ * general grid dmgs_plan_level_n gives the x count.  dmgs_plan_level_shape
+ * writes the cells of level k per axis (x, y, z; a two-dimensional plan
+ * writes N, N, 0) to n3 and returns DMGS_OK, or DMGS_ERR_INVALID for a NULL
+ * plan or pointer or a level out of range. */
 int dmgs_plan_levels(dmgs_plan plan);
 int dmgs_plan_level_n(dmgs_plan plan, int k);
+int dmgs_plan_level_shape(dmgs_plan plan, int k, int32_t *n3);
 
 /* Coefficient set-up (Sec. 2.2: operators rediscretised on every level):
  * copy D and mua, check D > 0, mua >= 0 (interior) and finiteness

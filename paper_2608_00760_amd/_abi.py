@@ -22,7 +22,8 @@ class Options(C.Structure):
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("max_cycles", C.c_int32),
                 ("fixed_cycles", C.c_int32), ("face_mean", C.c_int32), ("h", C.c_double),
                 ("bc_value", C.c_double), ("rtol", C.c_double), ("ir_inner_cycles", C.c_int32),
-                ("ir_adaptive", C.c_int32), ("adjoint_schedule", C.c_int32), ("ndim", C.c_int32)]
+                ("ir_adaptive", C.c_int32), ("adjoint_schedule", C.c_int32), ("ndim", C.c_int32),
+                ("h_axis", C.c_double * 3)]
 
 
 class Info(C.Structure):
@@ -44,6 +45,7 @@ SIGNATURES = {
     "dmgs_plan_destroy": (_i, [_vp]),
     "dmgs_plan_levels": (_i, [_vp]),
     "dmgs_plan_level_n": (_i, [_vp, _i]),
+    "dmgs_plan_level_shape": (_i, [_vp, _i, C.POINTER(C.c_int32)]),
     "dmgs_set_coefficients": (_i, [_vp, _vp, _vp, _vp]),
     "dmgs_set_log_coefficients": (_i, [_vp, _vp, _vp, _vp]),
     "dmgs_forward": (_i, [_vp, _vp, _vp, C.POINTER(Info), _vp]),

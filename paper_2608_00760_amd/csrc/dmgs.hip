@@ -24,6 +24,7 @@
 #include "kernels_2d.hpp"
 #include "kernels_epilogue.hpp"
 #include "kernels_unrolled.hpp"
+#include "kernels_grid.hpp"
 #include "plan.hpp"
 
 using namespace dmgs;
@@ -80,16 +81,64 @@ int levels_for(int N) {
     return L;
 }
 
+// Spacing of axis a (h_axis[a], or h when it is 0).
+double axis_h(const dmgs_options* o, int a) { return o->h_axis[a] > 0.0 ? o->h_axis[a] : o->h; }
+
+// A three-dimensional plan with different cell counts or spacings per axis.
+bool general_grid(const dmgs_options* o) {
+    if (o->ndim != 3) return false;
+    return o->n[0] != o->n[1] || o->n[1] != o->n[2] || axis_h(o, 0) != axis_h(o, 1) || axis_h(o, 1) != axis_h(o, 2);
+}
+
+// Levels of a general grid: every axis halves until the smallest count is 2
+// or 3 (cn receives the counts of each level); 0 when the counts do not
+// halve down so.
+int grid_levels(const int32_t* n, int cn[][3]) {
+    int c[3] = {n[0], n[1], n[2]};
+    for (int a = 0; a < 3; a++)
+        if (c[a] < 2) return 0;
+    int L = 0;
+    while (true) {
+        if (L >= kMaxLevels) return 0;
+        for (int a = 0; a < 3; a++) cn[L][a] = c[a];
+        L++;
+        const int m = std::min(c[0], std::min(c[1], c[2]));
+        if (m <= 3) return (m == 2 || m == 3) ? L : 0;
+        for (int a = 0; a < 3; a++) {
+            if (c[a] % 2) return 0;
+            c[a] /= 2;
+        }
+    }
+}
+
 int check_options(const dmgs_options* o) {
     if (!o) { set_error("options is NULL"); return DMGS_ERR_INVALID; }
     int N = o->n[0];
     if (o->ndim != 2 && o->ndim != 3) { set_error("bad ndim %d", o->ndim); return DMGS_ERR_INVALID; }
     const int nmax = o->ndim == 2 ? 16384 : 1024;
-    if (o->n[1] != N || (o->ndim == 3 && o->n[2] != N)) {
-        set_error("only square or cubic grids are supported (n = %d,%d,%d)", o->n[0], o->n[1], o->n[2]);
+    for (int a = 0; a < 3 && o->ndim == 3; a++)
+        if (!(o->h_axis[a] >= 0.0) || !std::isfinite(o->h_axis[a])) { set_error("bad h_axis"); return DMGS_ERR_INVALID; }
+    if (general_grid(o)) {
+        int cn[kMaxLevels][3];
+        const int L = grid_levels(o->n, cn);
+        if (L == 0 || std::max(o->n[0], std::max(o->n[1], o->n[2])) > nmax) {
+            set_error("cell counts %d,%d,%d do not halve down to a smallest count of 2 or 3 (each 2..%d)", o->n[0],
+                      o->n[1], o->n[2], nmax);
+            return DMGS_ERR_INVALID;
+        }
+        if ((cn[L - 1][0] - 1) * (cn[L - 1][1] - 1) * (cn[L - 1][2] - 1) > kGridCoarseMax) {
+            set_error("the coarsest level (%d,%d,%d cells) has more than %d interior vertices", cn[L - 1][0],
+                      cn[L - 1][1], cn[L - 1][2], kGridCoarseMax);
+            return DMGS_ERR_INVALID;
+        }
+        if (o->precision != DMGS_FP64 || o->smoother != DMGS_RBGS) {
+            set_error("general-grid plans take DMGS_FP64 and DMGS_RBGS");
+            return DMGS_ERR_INVALID;
+        }
+    } else if (o->n[1] != N || (o->ndim == 3 && o->n[2] != N)) {
+        set_error("two-dimensional plans are square (n = %d,%d)", o->n[0], o->n[1]);
         return DMGS_ERR_INVALID;
-    }
-    if (N < 2 || N > nmax || levels_for(N) == 0 || levels_for(N) > kMaxLevels) {
+    } else if (N < 2 || N > nmax || levels_for(N) == 0 || levels_for(N) > kMaxLevels) {
         set_error("N = %d is not c*2^m with c in {2,3}, 2 <= N <= %d", N, nmax);
         return DMGS_ERR_INVALID;
     }
@@ -124,6 +173,12 @@ struct Sizes {
 
 Sizes sizes_for(const dmgs_options* o) {
     Sizes s;
+    if (general_grid(o)) {
+        int cn[kMaxLevels][3];
+        s.L = grid_levels(o->n, cn);
+        for (int k = 0; k < s.L; k++) s.nv[k] = (int64_t)(cn[k][0] + 1) * (cn[k][1] + 1) * (cn[k][2] + 1);
+        return s;
+    }
     s.L = levels_for(o->n[0]);
     int N = o->n[0];
     for (int k = 0; k < s.L; k++, N /= 2)
@@ -135,6 +190,17 @@ size_t footprint(const dmgs_options* o) {
     Sizes s = sizes_for(o);
     bool ir = o->precision == DMGS_FP32_IN_FP64;
     size_t b = 0;
+    if (general_grid(o)) {
+        // per level D64, mu64, (u64, q64 below the finest), (t64: the defect,
+        // above the coarsest); the finest scratch; partials, the coarsest
+        // inverse, norm slots and the flag
+        for (int k = 0; k < s.L; k++)
+            b += (2 + (k > 0 ? 2 : 0) + (k < s.L - 1 ? 1 : 0)) * s.nv[k] * sizeof(double);
+        b += s.nv[0] * sizeof(double);
+        b += kMaxPartials * sizeof(double) + kGridCoarseMax * kGridCoarseMax * sizeof(double) + 4 * sizeof(double) +
+             sizeof(int);
+        return b;
+    }
     for (int k = 0; k < s.L; k++) {
         if (o->ndim == 2) {   // D64, mu64, (u64, q64), t64, (rd64)
             b += ((k > 0 ? 5 : 3) + (k < s.L - 1 ? 1 : 0)) * s.nv[k] * sizeof(double);
@@ -1162,8 +1228,122 @@ int solve2d(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_
 // cycle; refinement plans: the float32 V-cycles of each step) with no
 // convergence test.  record: a tolerance-mode solve stores its schedule in
 // P->fwd_schedule.
+// ---------------------------------------------------------------------------
+// General-grid plans: float64 V-cycles, in place, one operation per launch.
+
+GridDims gdims(dmgs_plan P, int k);
+
+// One V(nu1, nu2)-cycle on level k (order 0: red before black; order 1, the
+// transposed cycle: black before red with the counts exchanged); u on the
+// coarser levels starts at 0.
+int vcycle_grid(dmgs_plan P, int k, double* u, const double* q, int order, hipStream_t st) {
+    const Level& l = P->lev[k];
+    const GridDims G = gdims(P, k);
+    if (k == P->L - 1) {
+        hipLaunchKernelGGL(k_g_exact, dim3(1), dim3(kGridCoarseMax), 0, st, q, u, (const double*)l.D64,
+                           (const double*)P->cinv, G);
+        LAUNCHCHK();
+        return DMGS_OK;
+    }
+    const int first = order ? 1 : 0;
+    const unsigned g = grid_for(l.nv);
+    auto sweeps = [&](int count) -> int {
+        for (int i = 0; i < count; i++)
+            for (int c = 0; c < 2; c++) {
+                TIMED(P, k, DMGS_K_SMOOTH, 40.0 * l.nv, st,
+                      hipLaunchKernelGGL(k_g_half, dim3(g), dim3(kBlock), 0, st, u, q, (const double*)l.D64,
+                                         (const double*)l.mu64, G, c ? 1 - first : first));
+            }
+        return DMGS_OK;
+    };
+    TRY(sweeps(nu_pre_of(P, order)));
+    const Level& c = P->lev[k + 1];
+    TIMED(P, k, DMGS_K_DEFECT_RESTRICT, 40.0 * l.nv, st,
+          hipLaunchKernelGGL(k_g_defect, dim3(g), dim3(kBlock), 0, st, (const double*)u, q, (const double*)l.D64,
+                             (const double*)l.mu64, G, l.t64));
+    hipLaunchKernelGGL(k_g_restrict, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)l.t64, G, c.q64);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_g_fill<double>, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, c.u64, gdims(P, k + 1), 0.0);
+    LAUNCHCHK();
+    TRY(vcycle_grid(P, k + 1, c.u64, c.q64, order, st));
+    TIMED(P, k, DMGS_K_PROLONG, 17.0 * l.nv, st,
+          hipLaunchKernelGGL(k_g_prolong_add, dim3(g), dim3(kBlock), 0, st, (const double*)c.u64, G, u));
+    return sweeps(nu_post_of(P, order));
+}
+
+// ||b - A x||^2 of the finest level into the norm slot `slot`.
+int resid_grid(dmgs_plan P, const double* x, const double* b, int slot, hipStream_t st) {
+    const Level& l = P->lev[0];
+    const unsigned nb = grid_for(l.nv, kMaxPartials);
+    TIMED(P, 0, DMGS_K_RESIDUAL, 32.0 * l.nv, st,
+          hipLaunchKernelGGL(k_g_resid_sq, dim3(nb), dim3(kBlock), 0, st, x, b, (const double*)l.D64,
+                             (const double*)l.mu64, gdims(P, 0), P->partial));
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, norm_dst(P), slot);
+    LAUNCHCHK();
+    return mark_norms(P, st);
+}
+
+// solve() for general-grid plans (same modes, schedule record and replay).
+int solve_grid(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_info* info, hipStream_t st,
+               const std::vector<int>* replay, bool record) {
+    const dmgs_options& o = P->opt;
+    const Level& l0 = P->lev[0];
+    const bool fixed = o.fixed_cycles > 0 || replay;
+    const int nfix = replay ? (int)replay->size() : o.fixed_cycles;
+    hipLaunchKernelGGL(k_g_init, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, x, gdims(P, 0), bc);
+    LAUNCHCHK();
+    int cycles = 0, status = DMGS_OK;
+    double r0 = 0.0, rel = 0.0;
+    // the initial residual into slot 0 (read in fixed mode only with info)
+    TRY(resid_grid(P, x, b, 0, st));
+    if (!fixed) {
+        TRY(read_norms(P, st));
+        r0 = std::sqrt(P->hnorm[0]);
+        if (!std::isfinite(r0)) {
+            set_error("non-finite right-hand side");
+            status = DMGS_ERR_NONFINITE;
+        }
+    }
+    if (status == DMGS_OK && (fixed || r0 > 0.0)) {
+        for (cycles = 1; !(fixed && nfix == 0); cycles++) {
+            TRY(vcycle_grid(P, 0, x, b, order, st));
+            if (fixed) {
+                if (cycles == nfix) break;
+                continue;
+            }
+            TRY(resid_grid(P, x, b, 1, st));
+            TRY(read_norms(P, st));
+            rel = std::sqrt(P->hnorm[1]) / r0;
+            if (!std::isfinite(rel)) { set_error("non-finite residual after %d cycles", cycles); status = DMGS_ERR_NONFINITE; break; }
+            if (rel <= o.rtol) break;
+            if (cycles >= o.max_cycles) { set_error("not converged after %d cycles (rel %.3e)", cycles, rel); status = DMGS_ERR_NOT_CONVERGED; break; }
+        }
+        if (fixed && nfix == 0) cycles = 0;
+    } else {
+        cycles = 0;
+    }
+    if (fixed && info) {
+        TRY(resid_grid(P, x, b, 1, st));
+        TRY(read_norms(P, st));
+        r0 = std::sqrt(P->hnorm[0]);
+        rel = std::sqrt(P->hnorm[1]) / (r0 > 0.0 ? r0 : 1.0);
+    }
+    if (record && !fixed) {
+        P->fwd_recorded = status == DMGS_OK || status == DMGS_ERR_NOT_CONVERGED;
+        P->fwd_schedule.assign(cycles, 1);
+    }
+    if (info) {
+        info->cycles = cycles;
+        info->vcycles = cycles;
+        info->rel_residual = rel;
+        info->status = status;
+    }
+    return status;
+}
+
 int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_info* info, hipStream_t st,
           const std::vector<int>* replay = nullptr, bool record = false) {
+    if (P->grid) return solve_grid(P, b, x, bc, order, info, st, replay, record);
     if (is2d(P))
         return harmonic(P) ? solve2d<true>(P, b, x, bc, order, info, st, replay, record)
                            : solve2d<false>(P, b, x, bc, order, info, st, replay, record);
@@ -1337,7 +1517,68 @@ int end_call(dmgs_plan P, int status, dmgs_info* info, hipStream_t st) {
 
 // Coefficient hierarchy from the finest level's D64 and mu64.  from_log:
 // they are formed here from logD and logmu (exp and validation in one pass).
+GridDims gdims(dmgs_plan P, int k) {
+    const Level& l = P->lev[k];
+    GridDims g;
+    g.nx = l.nc[0];
+    g.ny = l.nc[1];
+    g.nz = l.nc[2];
+    for (int a = 0; a < 3; a++) g.ih2[a] = 1.0 / (l.h3[a] * l.h3[a]);
+    g.harmonic = harmonic(P);
+    return g;
+}
+
+// Vertex counts per axis, fastest first, of a plan's finest level.
+VertDims vdims(dmgs_plan P) {
+    const Level& l = P->lev[0];
+    VertDims d;
+    if (P->grid) {
+        d.n[0] = l.nc[2] + 1;
+        d.n[1] = l.nc[1] + 1;
+        d.n[2] = l.nc[0] + 1;
+    } else {
+        d.n[0] = d.n[1] = l.N + 1;
+        d.n[2] = P->opt.ndim == 2 ? 1 : l.N + 1;
+    }
+    return d;
+}
+
+// Coefficient hierarchy of a general-grid plan (see build_hierarchy).
+int build_hierarchy_grid(dmgs_plan P, hipStream_t st, const double* logD, const double* logmu) {
+    Level& l0 = P->lev[0];
+    *P->hflag = 0;
+    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, st, P->dflag, (int64_t)1, 0);
+    LAUNCHCHK();
+    TIMED(P, 0, DMGS_K_COEF, (logD ? 32.0 : 16.0) * l0.nv, st,
+          hipLaunchKernelGGL(k_g_coef_in, dim3(grid_for(l0.nv, 4096)), dim3(kBlock), 0, st, logD, logmu, l0.D64,
+                             l0.mu64, gdims(P, 0), P->dflag));
+    HIPCHK(hipMemcpyAsync(P->hflag, P->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (!P->arena) HIPCHK(hipEventRecord(P->ev_flag, st));
+    for (int k = 1; k < P->L; k++) {
+        const Level& f = P->lev[k - 1];
+        Level& c = P->lev[k];
+        hipLaunchKernelGGL(k_g_coarsen, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)f.D64,
+                           (const double*)f.mu64, gdims(P, k - 1), c.D64, c.mu64);
+        LAUNCHCHK();
+    }
+    const Level& c = P->lev[P->L - 1];
+    const int m = (c.nc[0] - 1) * (c.nc[1] - 1) * (c.nc[2] - 1);
+    hipLaunchKernelGGL(k_g_inverse, dim3(1), dim3(64), (size_t)(2 * m * m * sizeof(double)), st, (const double*)c.D64,
+                       (const double*)c.mu64, gdims(P, P->L - 1), P->cinv);
+    LAUNCHCHK();
+    if (P->arena) HIPCHK(hipStreamSynchronize(st));
+    else HIPCHK(hipEventSynchronize(P->ev_flag));
+    if (*P->hflag) {
+        P->coef_set = false;
+        set_error("coefficients must satisfy D > 0, mua >= 0 and be finite");
+        return DMGS_ERR_INVALID;
+    }
+    P->coef_set = true;
+    return DMGS_OK;
+}
+
 int build_hierarchy(dmgs_plan P, hipStream_t st, const double* logD = nullptr, const double* logmu = nullptr) {
+    if (P->grid) return build_hierarchy_grid(P, st, logD, logmu);
     Level& l0 = P->lev[0];
     *P->hflag = 0;
     hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, st, P->dflag, (int64_t)1, 0);
@@ -1407,7 +1648,7 @@ int build_hierarchy(dmgs_plan P, hipStream_t st, const double* logD = nullptr, c
 
 int debug_check(dmgs_plan P, int k, int fp32, bool need_coarse) {
     if (!P || !P->coef_set) { set_error("plan without coefficients"); return DMGS_ERR_INVALID; }
-    if (is2d(P)) { set_error("the diagnostic entry points take three-dimensional plans"); return DMGS_ERR_INVALID; }
+    if (is2d(P) || P->grid) { set_error("the diagnostic entry points take cubic three-dimensional plans"); return DMGS_ERR_INVALID; }
     if (k < 0 || k >= P->L || (need_coarse && k >= P->L - 1)) { set_error("bad level %d", k); return DMGS_ERR_INVALID; }
     if (fp32 && !is_ir(P)) { set_error("float32 arrays need a DMGS_FP32_IN_FP64 plan"); return DMGS_ERR_INVALID; }
     if (hipSetDevice(P->device) != hipSuccess) { set_error("hipSetDevice failed"); return DMGS_ERR_HIP; }
@@ -1476,6 +1717,12 @@ dim3 col_grid(int N, int* chunk) {
 int tangent_rhs(dmgs_plan P, const double* rho, const double* dq, const double* dlogD, const double* dlogmua,
                 double* out, hipStream_t st) {
     const Level& l0 = P->lev[0];
+    if (P->grid) {
+        TIMED(P, 0, DMGS_K_GRAD, 56.0 * l0.nv, st,
+              hipLaunchKernelGGL(k_g_tangent_rhs, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, rho, dq, dlogD, dlogmua,
+                                 (const double*)l0.D64, (const double*)l0.mu64, gdims(P, 0), out));
+        return DMGS_OK;
+    }
     if (is2d(P)) {
         TIMED(P, 0, DMGS_K_GRAD, 56.0 * l0.nv, st,
               hipLaunchKernelGGL(k2_tangent_rhs, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, rho, dq, dlogD,
@@ -1497,6 +1744,12 @@ int tangent_rhs(dmgs_plan P, const double* rho, const double* dq, const double* 
 int coef_grads(dmgs_plan P, const double* rho, const double* lam, double* gD, double* gmu, const double* d,
                const double* w, hipStream_t st) {
     const Level& l0 = P->lev[0];
+    if (P->grid) {
+        TIMED(P, 0, DMGS_K_GRAD, 48.0 * l0.nv, st,
+              hipLaunchKernelGGL(k_g_coef_grads, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, rho, lam,
+                                 (const double*)l0.D64, (const double*)l0.mu64, gdims(P, 0), gD, gmu, d, w));
+        return DMGS_OK;
+    }
     if (is2d(P)) {
         TIMED(P, 0, DMGS_K_GRAD, 48.0 * l0.nv, st,
               hipLaunchKernelGGL(k2_coef_grads, dim3(vertex_grid(l0.nv)), dim3(kBlock), 0, st, rho, lam,
@@ -1504,7 +1757,7 @@ int coef_grads(dmgs_plan P, const double* rho, const double* lam, double* gD, do
                                  gmu));
         if (d && gmu) {
             hipLaunchKernelGGL(k_likelihood_direct, dim3(grid_for(l0.nv, 4096)), dim3(kBlock), 0, st, rho,
-                               (const double*)l0.mu64, d, w, l0.nv, l0.N, P->opt.ndim, gmu);
+                               (const double*)l0.mu64, d, w, l0.nv, vdims(P), gmu);
             LAUNCHCHK();
         }
         return DMGS_OK;
@@ -1549,6 +1802,7 @@ size_t dmgs_workspace_bytes(const dmgs_options* o) {
 
 size_t dmgs_forward_vjp_workspace_bytes(const dmgs_options* o) {
     if (check_options(o) != DMGS_OK) return 0;
+    if (general_grid(o)) return footprint(o);   // the two solves share the plan's buffers
     // the twin's work buffers (make_twin): per level the iterate, right-hand
     // side and partner (+ the defect buffer below the coarsest) in IR plans,
     // or partner (+ iterate and right-hand side below the finest) in float64
@@ -1574,9 +1828,85 @@ namespace {
 // events) and clear the work buffers synchronously; arena plans (P->arena
 // set) carve the buffers from the arena and clear them with fill kernels on
 // stream zst.  On failure the caller frees what was allocated (free_plan).
+// Levels and buffers of a general-grid plan (see plan_init): per level
+// D64, mu64, below the finest u64 and q64, above the coarsest t64 (the
+// defect); the finest scratch, partials, the coarsest inverse, the flag.
+int grid_plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
+    P->grid = true;
+    int cn[kMaxLevels][3];
+    P->L = grid_levels(o->n, cn);
+    int st = DMGS_OK;
+    for (int k = 0; k < P->L && st == DMGS_OK; k++) {
+        Level& l = P->lev[k];
+        for (int a = 0; a < 3; a++) {
+            l.nc[a] = cn[k][a];
+            l.h3[a] = axis_h(o, a) * (double)(1 << k);
+        }
+        l.N = cn[k][0];
+        l.n = l.N + 1;
+        l.nv = (int64_t)(cn[k][0] + 1) * (cn[k][1] + 1) * (cn[k][2] + 1);
+        l.h = l.h3[0];
+        l.inv_h2 = 1.0 / (l.h * l.h);
+        if (st == DMGS_OK) st = dalloc(P, &l.D64, l.nv);
+        if (st == DMGS_OK) st = dalloc(P, &l.mu64, l.nv);
+        if (k > 0 && st == DMGS_OK) st = dalloc(P, &l.u64, l.nv);
+        if (k > 0 && st == DMGS_OK) st = dalloc(P, &l.q64, l.nv);
+        if (k < P->L - 1 && st == DMGS_OK) st = dalloc(P, &l.t64, l.nv);
+    }
+    if (st == DMGS_OK) st = dalloc(P, &P->scratch64, P->lev[0].nv);
+    if (st == DMGS_OK) st = dalloc(P, &P->partial, kMaxPartials);
+    if (st == DMGS_OK) st = dalloc(P, &P->cinv, kGridCoarseMax * kGridCoarseMax);
+    if (st == DMGS_OK) st = dalloc(P, &P->dflag, 1);
+    if (P->arena) {
+        if (st == DMGS_OK) st = dalloc(P, &P->dnorm, 4);
+        P->hnorm = P->hnorm_buf;
+        P->hflag = &P->hflag_buf;
+    } else {
+        if (st == DMGS_OK && hipHostMalloc((void**)&P->hnorm, 4 * sizeof(double), hipHostMallocCoherent) != hipSuccess) {
+            set_error("hipHostMalloc failed");
+            st = DMGS_ERR_OOM;
+        }
+        if (st == DMGS_OK && hipHostMalloc((void**)&P->hflag, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+            set_error("hipHostMalloc failed");
+            st = DMGS_ERR_OOM;
+        }
+        if (st == DMGS_OK && (hipEventCreate(&P->ev_start) != hipSuccess || hipEventCreate(&P->ev_stop) != hipSuccess ||
+                              hipEventCreateWithFlags(&P->ev_norm, hipEventDisableTiming) != hipSuccess ||
+                              hipEventCreateWithFlags(&P->ev_flag, hipEventDisableTiming) != hipSuccess)) {
+            set_error("hipEventCreate failed");
+            st = DMGS_ERR_HIP;
+        }
+    }
+    // the coarse iterates and right-hand sides start at 0 (their boundaries
+    // stay 0), and so do the defects' boundaries
+    for (int k = 0; k < P->L && st == DMGS_OK; k++) {
+        Level& l = P->lev[k];
+        for (double* p : {l.u64, l.q64, l.t64}) {
+            if (!p) continue;
+            hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(l.nv)), dim3(kBlock), 0, zst, p, l.nv, 0.0);
+            if (hipGetLastError() != hipSuccess) { set_error("fill kernel launch failed"); st = DMGS_ERR_HIP; }
+        }
+    }
+    if (st == DMGS_OK && !P->arena && hipStreamSynchronize(zst) != hipSuccess) {
+        set_error("stream synchronisation failed");
+        st = DMGS_ERR_HIP;
+    }
+    const int m = (P->lev[P->L - 1].nc[0] - 1) * (P->lev[P->L - 1].nc[1] - 1) * (P->lev[P->L - 1].nc[2] - 1);
+    if (st == DMGS_OK && hipFuncSetAttribute((const void*)k_g_inverse, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)(2 * m * m * sizeof(double))) != hipSuccess) {
+        set_error("hipFuncSetAttribute failed");
+        st = DMGS_ERR_HIP;
+    }
+    return st;
+}
+
 int plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
     P->opt = *o;
     if (hipGetDevice(&P->device) != hipSuccess) { set_error("hipGetDevice failed"); return DMGS_ERR_HIP; }
+    if (general_grid(o)) return grid_plan_init(P, o, zst);
+    // cubic and square plans: one spacing (h_axis, when all three are given and equal, is it)
+    if (o->ndim == 3) P->opt.h = axis_h(o, 0);
+    o = &P->opt;
     {
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && ncu > 0)
@@ -1747,6 +2077,13 @@ int dmgs_plan_destroy(dmgs_plan P) {
 int dmgs_plan_levels(dmgs_plan P) { return P ? P->L : 0; }
 int dmgs_plan_level_n(dmgs_plan P, int k) { return (P && k >= 0 && k < P->L) ? P->lev[k].N : 0; }
 
+int dmgs_plan_level_shape(dmgs_plan P, int k, int32_t* n3) {
+    if (!P || !n3 || k < 0 || k >= P->L) { set_error("bad plan, pointer or level"); return DMGS_ERR_INVALID; }
+    const Level& l = P->lev[k];
+    for (int a = 0; a < 3; a++) n3[a] = P->grid ? l.nc[a] : (a == 2 && is2d(P) ? 0 : l.N);
+    return DMGS_OK;
+}
+
 int dmgs_set_coefficients(dmgs_plan P, const double* D, const double* mua, void* stream) {
     if (!P || !D || !mua) { set_error("NULL argument"); return DMGS_ERR_INVALID; }
     hipStream_t st = (hipStream_t)stream;
@@ -1884,6 +2221,18 @@ int dmgs_forward_vjp(dmgs_plan P, const double* q, const double* rhobar, double*
     hipStream_t st = (hipStream_t)stream;
     TRY(begin_call(P, st));
     if (!q || !rhobar || !rho || !qbar) { set_error("NULL argument"); return DMGS_ERR_INVALID; }
+    if (P->grid) {
+        // general grids: the two solves one after the other on `stream`
+        const bool replay = P->opt.adjoint_schedule && P->opt.fixed_cycles <= 0;
+        const int sf = solve(P, q, rho, P->opt.bc_value, 0, info_fwd, st, nullptr, true);
+        if (sf != DMGS_OK && sf != DMGS_ERR_NOT_CONVERGED) return end_call(P, sf, info_fwd, st);
+        const int sa = solve(P, rhobar, qbar, 0.0, 1, info_vjp, st, replay ? &P->fwd_schedule : nullptr);
+        if ((sa == DMGS_OK || sa == DMGS_ERR_NOT_CONVERGED) && (logD_bar || logmua_bar))
+            TRY(coef_grads(P, rho, qbar, logD_bar, logmua_bar, nullptr, nullptr, st));
+        const int s = end_call(P, sf != DMGS_OK ? sf : sa, info_fwd, st);
+        if (info_vjp) info_vjp->status = sa;
+        return s;
+    }
     TRY(make_twin(P));
     dmgs_plan T = P->twin;
     T->coef_set = true;
@@ -2148,7 +2497,7 @@ int dmgs_vjp_unrolled(dmgs_plan P, const double* q, const double* rhobar, double
     TRY(begin_call(P, st));
     if (!q || !rhobar || !rho || !qbar) { set_error("NULL argument"); return DMGS_ERR_INVALID; }
     const dmgs_options& o = P->opt;
-    if (is2d(P) || o.precision != DMGS_FP64 || o.smoother != DMGS_RBGS || o.fixed_cycles <= 0) {
+    if (is2d(P) || P->grid || o.precision != DMGS_FP64 || o.smoother != DMGS_RBGS || o.fixed_cycles <= 0) {
         set_error("dmgs_vjp_unrolled takes three-dimensional DMGS_FP64, DMGS_RBGS plans with fixed_cycles > 0");
         return DMGS_ERR_INVALID;
     }
@@ -2270,7 +2619,7 @@ int dmgs_noise_weights(dmgs_plan P, const double* Le, int32_t mask, double rel, 
     hipLaunchKernelGGL(k_max_partials, dim3(nb), dim3(kBlock), 0, st, Le, l0.nv, P->partial);
     LAUNCHCHK();
     hipLaunchKernelGGL(k_noise_weights, dim3(grid_for(l0.nv, 4096)), dim3(kBlock), 0, st, Le, (const double*)P->partial,
-                       (int)nb, l0.nv, l0.N, P->opt.ndim, (int)mask, rel, floor_frac, w);
+                       (int)nb, l0.nv, vdims(P), (int)mask, rel, floor_frac, w);
     LAUNCHCHK();
     return DMGS_OK;
 }
@@ -2289,7 +2638,7 @@ int dmgs_likelihood_grad(dmgs_plan P, const double* q, const double* d, const do
     const unsigned nb = grid_for(l0.nv, kMaxPartials / 2);
     TIMED(P, 0, DMGS_K_GRAD, 40.0 * l0.nv, st,
           hipLaunchKernelGGL(k_likelihood_epilogue, dim3(nb), dim3(kBlock), 0, st, (const double*)rho,
-                             (const double*)l0.mu64, d, w, l0.nv, l0.N, P->opt.ndim, P->scratch64, P->partial));
+                             (const double*)l0.mu64, d, w, l0.nv, vdims(P), P->scratch64, P->partial));
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, norm_dst(P), 2);
     LAUNCHCHK();
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial + nb, (int)nb, norm_dst(P), 3);

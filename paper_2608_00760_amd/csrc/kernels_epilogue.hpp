@@ -12,14 +12,21 @@
 
 namespace dmgs {
 
-// distance of vertex v of an (N+1)^ndim grid to the nearest face
-__device__ __forceinline__ int face_depth(int64_t v, int N, int ndim) {
-    const int n = N + 1;
-    int d = N;
-    for (int a = 0; a < ndim; a++) {
+// vertex counts per axis, fastest axis first (an axis of count 1 is absent:
+// two-dimensional grids)
+struct VertDims {
+    int n[3];
+};
+
+// distance of vertex v to the nearest face of the grid
+__device__ __forceinline__ int face_depth(int64_t v, const VertDims& g) {
+    int d = 1 << 30;
+    for (int a = 0; a < 3; a++) {
+        const int n = g.n[a];
+        if (n <= 1) continue;
         const int c = (int)(v % n);
         v /= n;
-        d = min(d, min(c, N - c));
+        d = min(d, min(c, n - 1 - c));
     }
     return d;
 }
@@ -51,7 +58,7 @@ __global__ void k_max_partials(const double* __restrict__ a, int64_t nv, double*
 // least `mask` from every face (0 elsewhere, and where sigma <= 0).  Every
 // block reduces the npart partial maxima itself.
 __global__ void k_noise_weights(const double* __restrict__ Le, const double* __restrict__ partial, int npart,
-                                int64_t nv, int N, int ndim, int mask, double rel, double floor_frac,
+                                int64_t nv, VertDims g, int mask, double rel, double floor_frac,
                                 double* __restrict__ w) {
     __shared__ double smax;
     double m = -DBL_MAX;
@@ -62,7 +69,7 @@ __global__ void k_noise_weights(const double* __restrict__ Le, const double* __r
     const double floor_sigma = floor_frac * smax;
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
         const double sigma = fmax(rel * Le[v], floor_sigma);
-        w[v] = (face_depth(v, N, ndim) >= mask && sigma > 0.0) ? 1.0 / (sigma * sigma) : 0.0;
+        w[v] = (face_depth(v, g) >= mask && sigma > 0.0) ? 1.0 / (sigma * sigma) : 0.0;
     }
 }
 
@@ -70,11 +77,11 @@ __global__ void k_noise_weights(const double* __restrict__ Le, const double* __r
 // partial[b] = sum of w (d - mua rho)^2 and partial[nblocks + b] = number of
 // vertices with w > 0 over the block's interior vertices.
 __global__ void k_likelihood_epilogue(const double* __restrict__ rho, const double* __restrict__ mu,
-                                      const double* __restrict__ d, const double* __restrict__ w, int64_t nv, int N,
-                                      int ndim, double* __restrict__ rhobar, double* __restrict__ partial) {
+                                      const double* __restrict__ d, const double* __restrict__ w, int64_t nv,
+                                      VertDims g, double* __restrict__ rhobar, double* __restrict__ partial) {
     double acc = 0.0, cnt = 0.0;
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
-        if (face_depth(v, N, ndim) < 1) {
+        if (face_depth(v, g) < 1) {
             rhobar[v] = 0.0;
             continue;
         }
@@ -95,10 +102,10 @@ __global__ void k_likelihood_epilogue(const double* __restrict__ rho, const doub
 // gmu += w (mua rho - d) mua rho on interior vertices: log mua enters L_e
 // directly as well as through the operator
 __global__ void k_likelihood_direct(const double* __restrict__ rho, const double* __restrict__ mu,
-                                    const double* __restrict__ d, const double* __restrict__ w, int64_t nv, int N,
-                                    int ndim, double* __restrict__ gmu) {
+                                    const double* __restrict__ d, const double* __restrict__ w, int64_t nv,
+                                    VertDims g, double* __restrict__ gmu) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
-        if (face_depth(v, N, ndim) < 1) continue;
+        if (face_depth(v, g) < 1) continue;
         const double l = mu[v] * rho[v];
         gmu[v] += w[v] * (l - d[v]) * l;
     }

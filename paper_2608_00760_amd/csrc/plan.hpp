@@ -15,6 +15,8 @@ struct Level {
     int N = 0, n = 0;
     int64_t nv = 0;
     double h = 1.0, inv_h2 = 1.0;
+    int nc[3] = {0, 0, 0};        // cells per axis (general grids; N, N, N on cubic levels)
+    double h3[3] = {1.0, 1.0, 1.0};   // spacing per axis
     // coefficient hierarchy (float64 on every level; float32 copies in
     // iterative-refinement plans)
     double *D64 = nullptr, *mu64 = nullptr, *w64 = nullptr;   // w: inverse diagonal
@@ -111,6 +113,7 @@ struct dmgs_plan_s {
     double t_bytes[DMGS_K_COUNT] = {};
     size_t bytes = 0;
     int device = 0;
+    bool grid = false;             // general grid: per-axis cell counts and spacings
     // concurrent forward + VJP: a second plan that shares this plan's
     // coefficient hierarchy (not owned) and has its own work buffers, and
     // the stream its solves run on

@@ -35,6 +35,8 @@ class Options:
     smoother: str = "rbgs"            # "rbgs" (red-black Gauss-Seidel) | "wjacobi" (weighted Jacobi, 6/7)
     adjoint_schedule: bool = False    # pull-back repeats the last forward solve's V-cycle schedule
     ndim: int = 3                     # 3: (N+1)^3 grids, 7-point operator; 2: (N+1)^2 grids, 5-point operator
+    shape: tuple = None               # 3D: cells per axis (nx, ny, nz) of a general grid (default (N, N, N))
+    spacing: tuple = None             # 3D: spacing per axis (hx, hy, hz) (default h on every axis)
 
     def to_c(self):
         o = _abi.default_options(self.N)
@@ -50,7 +52,18 @@ class Options:
         o.smoother = _SMOOTHER[self.smoother]
         o.adjoint_schedule = 1 if self.adjoint_schedule else 0
         o.ndim = int(self.ndim)
+        if self.shape is not None:
+            o.n[0], o.n[1], o.n[2] = (int(c) for c in self.shape)
+        if self.spacing is not None:
+            o.h_axis[0], o.h_axis[1], o.h_axis[2] = (float(v) for v in self.spacing)
         return o
+
+    @property
+    def cells(self):
+        """Cells per axis of the finest level."""
+        if self.shape is not None:
+            return tuple(int(c) for c in self.shape)
+        return (self.N,) * self.ndim
 
 
 def workspace_bytes(opts: Options, forward_vjp=False) -> int:
@@ -82,7 +95,7 @@ def _stream(device):
 
 
 def _solve_once(fn, where, opts: Options, D, mua, q, out=None, check=True):
-    shape = (opts.N + 1,) * opts.ndim
+    shape = tuple(c + 1 for c in opts.cells)
     dev = q.device
     for name, t in (("D", D), ("mua", mua), ("q", q)) + ((("out", out),) if out is not None else ()):
         if (not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != dev or not t.is_cuda
@@ -125,6 +138,11 @@ class Plan:
             raise _abi.DMGSError(st, "dmgs_plan_create")
         self.levels = _abi.lib().dmgs_plan_levels(self._h)
         self.level_N = [_abi.lib().dmgs_plan_level_n(self._h, k) for k in range(self.levels)]
+        self.level_shape = []
+        for k in range(self.levels):
+            n3 = (C.c_int32 * 3)()
+            _abi.lib().dmgs_plan_level_shape(self._h, k, n3)
+            self.level_shape.append(tuple(int(n3[a]) for a in range(opts.ndim)))
         self.bytes = workspace_bytes(opts)
 
     def close(self):
@@ -140,7 +158,7 @@ class Plan:
 
     # ---- argument checks ------------------------------------------------------------
     def _shape(self, k=0):
-        return (self.level_N[k] + 1,) * self.opts.ndim
+        return tuple(c + 1 for c in self.level_shape[k])
 
     def _arr(self, t, name, k=0, dtype=torch.float64, optional=False):
         if t is None:

@@ -130,6 +130,56 @@ def tangents(N, base_seed, ndim=3):
             "dlogmua": normal(N, base_seed + 3, ndim=ndim), "rhobar": normal(N, base_seed + 4, ndim=ndim)}
 
 
+# ---------------------------------------------------------------------------
+# Grids with different cell counts per axis (the paper's data grid has
+# (128, 64, 64) cells over 7.5 x 3.5 x 3.5 cm).  The same recipes on the
+# vertex index grid: integer wavenumbers per axis for the GRF, blob centres
+# ~ U[0.15 n_a, 0.85 n_a] per axis and sigma ~ U[2, 6] vertices.
+
+def grf_shape(cells, seed, slope=-3.0):
+    """grf on (nx+1, ny+1, nz+1) vertices."""
+    rng = np.random.default_rng(seed)
+    shp = tuple(c + 1 for c in cells)
+    w = rng.standard_normal(shp)
+    W = _fft.rfftn(w, **_FFT_KW)
+    k0 = np.fft.fftfreq(shp[0]) * shp[0]
+    k1 = np.fft.fftfreq(shp[1]) * shp[1]
+    k2r = np.fft.rfftfreq(shp[2]) * shp[2]
+    k2 = k0[:, None, None] ** 2 + k1[None, :, None] ** 2 + k2r[None, None, :] ** 2
+    k2.flat[0] = 1.0
+    amp = k2 ** (slope / 4.0)
+    amp.flat[0] = 0.0
+    W *= amp
+    f = _fft.irfftn(W, s=shp, **_FFT_KW)
+    f -= f.mean()
+    f /= f.std()
+    return np.ascontiguousarray(f)
+
+
+def grid_case(cells, base_seed, nblobs=16, noise=0.01):
+    """grf_case on a grid of `cells` = (nx, ny, nz): log D, log mua, a
+    16-blob source and a cotangent (seeds base_seed+1..+4), plus tangents
+    dq, dlogD, dlogmua (seeds base_seed+5..+7)."""
+    shp = tuple(c + 1 for c in cells)
+    logD = np.clip(grf_shape(cells, base_seed + 1), -math.log(100.0), math.log(100.0))
+    logmua = math.log(0.05) + grf_shape(cells, base_seed + 2)
+    rng = np.random.default_rng(base_seed + 3)
+    idx = [np.arange(c, dtype=np.float64) for c in shp]
+    q = np.zeros(shp)
+    for _ in range(nblobs):
+        c = [rng.uniform(0.15 * n, 0.85 * n) for n in cells]
+        sg = rng.uniform(2.0, 6.0)
+        a = rng.uniform(0.5, 1.5)
+        g = [np.exp(-(idx[k] - c[k]) ** 2 / (2.0 * sg * sg)) for k in range(3)]
+        q += a * (g[0][:, None, None] * g[1][None, :, None]) * g[2][None, None, :]
+    q += noise * rng.standard_normal(shp)
+    out = {"cells": tuple(cells), "logD": logD, "logmua": logmua, "D": np.exp(logD), "mua": np.exp(logmua), "q": q}
+    for name, sd, zb in (("rhobar", 4, True), ("dq", 5, True), ("dlogD", 6, False), ("dlogmua", 7, True)):
+        f = np.random.default_rng(base_seed + sd).standard_normal(shp)
+        out[name] = zero_boundary(f) if zb else f
+    return out
+
+
 # Named workloads (sizes and seeds).
 def small_constant():
     """32^3 cells, D = 1, mua = 0.1, centred blob; tangents seeds 1001-1004."""

@@ -46,8 +46,28 @@ def test_default_options_and_footprint(abi):
     for bad in (5, 20, 1, 0, 2048):
         ob = abi.default_options(bad)
         assert lib.dmgs_workspace_bytes(C.byref(ob)) == 0, bad
+    # general grids (different counts or spacings per axis): valid when every
+    # axis halves down to a smallest count of 2 or 3, float64 RB-GS only
     ob = abi.default_options(64)
     ob.n[2] = 32
+    assert lib.dmgs_workspace_bytes(C.byref(ob)) > 0
+    for n3, ok in (((128, 64, 64), True), ((96, 64, 48), True), ((10, 8, 8), False), ((64, 64, 1), False),
+                   ((512, 16, 16), True), ((1024, 16, 16), False), ((2048, 1024, 1024), False)):
+        ob = abi.default_options(8)
+        ob.n[0], ob.n[1], ob.n[2] = n3
+        assert (lib.dmgs_workspace_bytes(C.byref(ob)) > 0) == ok, n3
+    ob = abi.default_options(128)
+    ob.n[1] = ob.n[2] = 64
+    ob.precision = abi.DMGS_FP32_IN_FP64
+    assert lib.dmgs_workspace_bytes(C.byref(ob)) == 0
+    ob = abi.default_options(64)
+    ob.h_axis[0], ob.h_axis[1], ob.h_axis[2] = 1.0, 2.0, 1.0   # unequal spacing alone makes a general grid
+    assert lib.dmgs_workspace_bytes(C.byref(ob)) > 0
+    ob.precision = abi.DMGS_FP32_IN_FP64
+    assert lib.dmgs_workspace_bytes(C.byref(ob)) == 0
+    ob.h_axis[1] = 1.0                                          # equal spacings: a cubic plan again
+    assert lib.dmgs_workspace_bytes(C.byref(ob)) > 0
+    ob.h_axis[1] = -1.0
     assert lib.dmgs_workspace_bytes(C.byref(ob)) == 0
     ob = abi.default_options(64)
     ob.nu_pre = ob.nu_post = 0
