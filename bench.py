@@ -34,26 +34,46 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(c, cycles_fwd, cycles_adj, smoother="rbgs"):
-    """Time the oracle on a bounded sample: hierarchy set-up, 2 forward
-    cycles, 2 adjoint cycles (with gradients); scale to a full fwd+VJP pair
-    with the cycle counts the solve needs."""
+def host_cpu():
+    """The host's CPU model, its logical CPU count and the ones this process
+    may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return model, os.cpu_count() or avail, avail
+
+
+def cpu_baseline(c, smoother="rbgs", reps=3):
+    """Time the oracle on whole fwd+VJP pairs of the benchmark's own workload:
+    hierarchy set-up, forward solve to the benchmark's tolerance, pull-back
+    to the same tolerance with the three gradients; the median of `reps`
+    pairs (each pair is timed whole, so one-off costs count once per pair)."""
     from oracle import ref
-    t0 = time.perf_counter()
-    H = ref.Hierarchy(c["D"], c["mua"], smoother=smoother)
-    t1 = time.perf_counter()
-    rho, _ = H.forward(c["q"], fixed_cycles=2)
-    t2 = time.perf_counter()
-    H.vjp(rho, c["rhobar"], fixed_cycles=2)
-    t3 = time.perf_counter()
-    setup, fwd2, adj2 = t1 - t0, t2 - t1, t3 - t2
-    pair_s = setup + fwd2 / 2 * cycles_fwd + adj2 / 2 * cycles_adj
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / pair_s, "unit": "fwd+VJP pairs/s", "cores": min(cores, os.cpu_count() or cores),
-            "kind": "oracle",
-            "sample": "N=%d: hierarchy set-up %.2fs + 2 forward V-cycles %.2fs + 2 adjoint V-cycles with gradients "
-                      "%.2fs, scaled to %d forward + %d adjoint cycles (FP64, C/OpenMP)"
-                      % (c["N"], setup, fwd2, adj2, cycles_fwd, cycles_adj)}
+    times, cyc = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        H = ref.Hierarchy(c["D"], c["mua"], smoother=smoother)
+        rho, fi = H.forward(c["q"], rtol=1e-10)
+        _, ai = H.vjp(rho, c["rhobar"], rtol=1e-10)
+        times.append(time.perf_counter() - t0)
+        cyc = (fi["cycles"], ai["cycles"])
+        del H, rho
+    times.sort()
+    pair_s = times[len(times) // 2]
+    model, nlog, avail = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", avail))
+    return {"value": 1.0 / pair_s, "unit": "fwd+VJP pairs/s", "cores": min(threads, avail), "kind": "oracle",
+            "cpu_model": model, "nproc": avail, "logical_cpus": nlog,
+            "sample": "median of %d whole fwd+VJP pairs at N=%d (set-up, forward to 1e-10 in %d V-cycles, pull-back "
+                      "to 1e-10 in %d V-cycles with gradients; FP64, C/OpenMP): %s s"
+                      % (reps, c["N"], cyc[0], cyc[1], ", ".join("%.2f" % t for t in times))}
 
 
 def sweep_cpu_baseline(nd, logD, logmu, q, w):
@@ -68,15 +88,23 @@ def sweep_cpu_baseline(nd, logD, logmu, q, w):
     t1 = time.perf_counter()
     rho, _ = H.forward(q, fixed_cycles=2)
     t2 = time.perf_counter()
-    H.vjp(rho, w, fixed_cycles=2)
+    H.forward(q, fixed_cycles=4)
     t3 = time.perf_counter()
-    setup, fwd2, adj2 = t1 - t0, t2 - t1, t3 - t2
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)) if nd == 3 else 1
-    return {"solve_ms": 1e3 * (setup + fwd2 / 2 * 15), "vjp_ms": 1e3 * (setup + adj2 / 2 * 15),
-            "cores": min(cores, os.cpu_count() or cores), "kind": "oracle",
-            "sample": "hierarchy set-up %.2fs + 2 forward cycles %.2fs + 2 pull-back cycles with gradients %.2fs, "
-                      "scaled to 15 cycles (FP64, %s)" % (setup, fwd2, adj2,
-                                                          "C/OpenMP" if nd == 3 else "numpy")}
+    H.vjp(rho, w, fixed_cycles=2)
+    t4 = time.perf_counter()
+    H.vjp(rho, w, fixed_cycles=4)
+    t5 = time.perf_counter()
+    # per-cycle costs from the differences (4 - 2 cycles), so the calls'
+    # one-off work (iterate set-up, gradients) is counted once
+    setup, f2, f4, a2, a4 = t1 - t0, t2 - t1, t3 - t2, t4 - t3, t5 - t4
+    fc, ac = max(f4 - f2, 0.0) / 2, max(a4 - a2, 0.0) / 2
+    _, _, avail = host_cpu()
+    cores = min(int(os.environ.get("OMP_NUM_THREADS", avail)), avail) if nd == 3 else 1
+    return {"solve_ms": 1e3 * (setup + f2 + 13 * fc), "vjp_ms": 1e3 * (setup + a2 + 13 * ac),
+            "cores": cores, "kind": "oracle",
+            "sample": "set-up %.2fs; 2 and 4 forward cycles %.2fs / %.2fs; 2 and 4 pull-back cycles with gradients "
+                      "%.2fs / %.2fs; per-cycle cost from the difference, extended to 15 cycles (FP64, %s)"
+                      % (setup, f2, f4, a2, a4, "C/OpenMP" if nd == 3 else "numpy")}
 
 
 def serving_leg(nreq):
@@ -105,6 +133,71 @@ def serving_leg(nreq):
             "requests_per_s": pois["requests_per_s"], "solves_per_s": pois["solves_per_s"],
             "errors": pois["errors"] + burst["errors"], "budget_GB": budget / 1e9, "peak_accounted_GB": peak / 1e9,
             "max_slots": 8}
+
+
+def config5_leg(reps=3):
+    """512^3 (134M cells) forward + VJP through the torch.autograd.Function:
+    GRF log-normal coefficients (clipped to a D contrast <= 1e4) and a
+    16-blob source drawn on the device, float32 V-cycles inside float64
+    refinement to 1e-10.  One untimed pair, then `reps` timed pairs (each
+    the differentiable forward solve and torch.autograd.grad of <w, rho>
+    with respect to q, log D and log mua); peak device memory = torch's peak
+    allocation + the plan's bytes."""
+    import torch
+    from paper_2608_00760_amd import synth
+    from paper_2608_00760_amd.autograd import Solver
+    N = 512
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(5000)
+    logD = synth.grf_torch(N, g, dev).clamp_(-math.log(100.0), math.log(100.0))
+    logmua = math.log(0.05) + synth.grf_torch(N, g, dev)
+    q = synth.blob_source_torch(N, g, dev)
+    w = synth.zero_boundary_torch(torch.randn(q.shape, generator=g, device=dev, dtype=torch.float64))
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    S = Solver(N, precision="fp32-in-fp64")
+    qv, lD, lm = (t.requires_grad_(True) for t in (q, logD, logmua))
+
+    def pair():
+        rho = S(qv, lD, lm)
+        grads = torch.autograd.grad((rho * w).sum(), (qv, lD, lm))
+        return rho, grads
+    pair()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rho, grads = pair()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+        del rho, grads
+    times.sort()
+    ms = times[len(times) // 2]
+    fi = S.plan._last_forward[1]
+    rho = S(qv, lD, lm)
+    (qb, _, _), vi = S.plan.vjp(rho.detach(), w, coef_grads=False)
+    torch.cuda.synchronize()
+    peak = torch.cuda.max_memory_allocated() + S.plan.bytes
+    nv = (N + 1) ** 3
+    levels = sum(((N >> k) + 1) ** 3 for k in range(S.plan.levels)) / nv
+    vc = fi["vcycles"] + vi["vcycles"]
+    model = 26.25 * 4 * nv * levels * vc
+    out = {"workload": "512^3 cells, GRF log-normal D (contrast <= 1e4) and mua, 16-blob source, fp32-in-fp64, "
+                       "rtol 1e-10, forward + VJP through torch.autograd.Function",
+           "ms_per_pair": ms, "ms_reps": times, "pairs_per_s": 1e3 / ms,
+           "peak_device_GB": peak / 1e9, "torch_peak_GB": torch.cuda.max_memory_allocated() / 1e9,
+           "plan_GB": S.plan.bytes / 1e9, "vcycles_fwd": fi["vcycles"], "vcycles_adj": vi["vcycles"],
+           "rel_residual_fwd": fi["rel_residual"], "rel_residual_adj": vi["rel_residual"],
+           "vcycle_model_GBps": model / (ms * 1e-3) / 1e9,
+           "vcycle_model_frac": model / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+           "note": "model GB/s = the one-pass V-cycle byte model (26.25 words per fine vertex, all levels) times "
+                   "the pair's V-cycles over the whole pair's time (refinement, set-up and gradient passes "
+                   "included, so a lower bound)"}
+    S.close()
+    return out
 
 
 def kernel_source_hash():
@@ -271,6 +364,7 @@ def main():
     ap.add_argument("--sequential", action="store_true",
                     help="run the forward solve and the VJP one after the other (default: concurrently)")
     ap.add_argument("--serving-requests", type=int, default=512, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--no-512", action="store_true", help="skip the 512^3 autograd forward + VJP record")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the library's plain streaming copy (256 MiB, 3 times): HBM counter calibration")
     args = ap.parse_args()
@@ -340,6 +434,16 @@ def main():
     avg_ms = d["ms"] / max(d["launches"], 1)
     bytes_per_launch = d["bytes"] / max(d["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    # the same launches on the one-pass-per-sweep unit (5 words per
+    # red-black sweep: read u, q, D, mua or w, write u); a level-0 pass of
+    # the V(2,2) red-black cycle applies two sweeps
+    sweep_unit = None
+    if dom == "smooth" and args.smoother == "rbgs":
+        word_b = 4 if args.precision == "fp32-in-fp64" else 8
+        su = 2 * 5 * word_b * (N + 1) ** 3
+        sweep_unit = {"bytes_per_launch": su, "achieved": su / (avg_ms * 1e-3) / 1e9,
+                      "frac": su / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                      "what": "two red-black sweeps per level-0 launch at 5 words per sweep"}
     kernels = {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / max(v["launches"], 1),
                    "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None,
                    "share": v["ms"] / (elapsed * 1e3)} for k, v in stats.items() if v["launches"]}
@@ -388,12 +492,17 @@ def main():
         log("serving: p50 %.2f ms p99 %.2f ms, %.1f requests/s (saturation %.1f)" % (
             serving["p50_ms"], serving["p99_ms"], serving["requests_per_s"], serving["saturation_requests_per_s"]))
 
+    big = None
+    if not args.no_512 and not args.sequential:
+        log("512^3 forward + VJP through the autograd Function")
+        big = config5_leg()
+        log("512^3: %.1f ms per pair, peak %.1f GB, %d + %d V-cycles" % (
+            big["ms_per_pair"], big["peak_device_GB"], big["vcycles_fwd"], big["vcycles_adj"]))
+
     cpu = None
     if not args.no_cpu_baseline:
-        log("timing the oracle on a bounded sample")
-        # the oracle runs plain V-cycles: scale by the V-cycles the solve needs
-        # (refinement steps x float32 cycles per step in the mixed solver)
-        cpu = cpu_baseline(c, info_f["vcycles"], info_a["vcycles"], args.smoother)
+        log("timing the oracle on whole fwd+VJP pairs")
+        cpu = cpu_baseline(c, args.smoother)
         log("oracle: %.4f pairs/s (%s)" % (cpu["value"], cpu["sample"]))
 
     # V-cycle time against the one-pass-per-operator byte model: 4 sweeps of 5
@@ -446,13 +555,15 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "measured_in": "sequential timed region",
                      "traffic": measured_traffic(dom) if N == 256 and args.precision == "fp32-in-fp64" else None,
-                     "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "per_sweep_unit": sweep_unit},
         "kernels": kernels,
         "vcycle": vcycle,
         "vcycle_sequential": vcycle_seq,
         "fp64_solver": fp64,
         "latency_p50_p99": serving,
         "likelihood_grad": likelihood,
+        "autograd_512": big,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
