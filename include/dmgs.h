@@ -176,7 +176,9 @@ size_t dmgs_forward_vjp_workspace_bytes(const dmgs_options *opt);
  *   DMGS_2D_BLOCK_MIN (64)      ... smallest N of the LDS block passes
  *   DMGS_2D_DEFECT (1)          ... the last pre-smoothing pass writes the defect
  *   DMGS_2D_CHUNK (0)           ... rows per chunk of the two-sweep passes (0: from the grid size)
- *   DMGS_2D_SMALL_MAX (32)      ... largest N of the single-workgroup coarse kernel */
+ *   DMGS_2D_SMALL_MAX (32)      ... largest N of the single-workgroup coarse kernel
+ *   DMGS_EPI_FUSE (1)           dmgs_likelihood_grad computes its epilogue in the
+ *                               forward solve's last refinement step (0: separate pass) */
 int dmgs_plan_create(const dmgs_options *opt, dmgs_plan *out);
 int dmgs_plan_destroy(dmgs_plan plan);
 

@@ -906,27 +906,48 @@ int vcycle(dmgs_plan P, int k, T** cur, T** other, const T* q, int order, bool z
 
 // ||b - A x||^2 into the plan's host norm slot `slot` (fused float64 kernel); with e, also
 // x_out = x + e and r32 = float(b - A x_out).
-template <bool HAS_E, bool X_ZERO, bool HARM>
-void launch_ir(const IrArgs& a0, int N, hipStream_t st, unsigned* nb_out) {
-    constexpr int TY = 16, TZ = 64;
-    IrArgs a = a0;
-    a.tiles_y = (N + TY - 1) / TY;
-    a.tiles_z = (N + TZ - 1) / TZ;
+constexpr int kIrTY = 16, kIrTZ = 64;
+
+// Blocks of the refinement kernel at level size N when each block leaves
+// `sums` partial sums (kMaxPartials bounds them all); 0 if no chunking fits.
+IrArgs ir_shape(int N, int sums) {
+    IrArgs a;
+    a.tiles_y = (N + kIrTY - 1) / kIrTY;
+    a.tiles_z = (N + kIrTZ - 1) / kIrTZ;
     a.chunk = choose_chunk(N - 1, a.tiles_y * a.tiles_z);
     a.nchunks = (N - 1 + a.chunk - 1) / a.chunk;
-    while (a.tiles_y * a.tiles_z * a.nchunks > kMaxPartials) {
+    while (a.nchunks > 1 && a.tiles_y * a.tiles_z * a.nchunks * sums > kMaxPartials) {
         a.chunk *= 2;
         a.nchunks = (N - 1 + a.chunk - 1) / a.chunk;
     }
+    if (a.tiles_y * a.tiles_z * a.nchunks * sums > kMaxPartials) a.nchunks = 0;
+    return a;
+}
+
+template <bool HAS_E, bool X_ZERO, bool HARM, bool EPI>
+void launch_ir(const IrArgs& a0, int N, hipStream_t st, unsigned* nb_out) {
+    IrArgs a = a0;
+    const IrArgs sh = ir_shape(N, EPI ? 3 : 1);
+    a.tiles_y = sh.tiles_y;
+    a.tiles_z = sh.tiles_z;
+    a.chunk = sh.chunk;
+    a.nchunks = sh.nchunks;
     unsigned nb = (unsigned)(a.tiles_y * a.tiles_z * a.nchunks);
-    hipLaunchKernelGGL((k_ir_residual_col<TY, TZ, HAS_E, X_ZERO, HARM>), dim3(nb), dim3(IrShape<TY, TZ>::NT), 0, st, a);
+    hipLaunchKernelGGL((k_ir_residual_col<kIrTY, kIrTZ, HAS_E, X_ZERO, HARM, EPI>), dim3(nb),
+                       dim3(IrShape<kIrTY, kIrTZ>::NT), 0, st, a);
     *nb_out = nb;
 }
 
+template <bool HAS_E, bool X_ZERO, bool EPI>
+void launch_ir_h(const IrArgs& a, int N, bool h, hipStream_t st, unsigned* nb) {
+    h ? launch_ir<HAS_E, X_ZERO, true, EPI>(a, N, st, nb) : launch_ir<HAS_E, X_ZERO, false, EPI>(a, N, st, nb);
+}
+
 // x_zero: x is 0 everywhere (the boundary value is 0 and nothing has been
-// added yet); x is not read.
+// added yet); x is not read.  epi: also the likelihood epilogue of x + e
+// (the plan's epi_* buffers), its sums into norm slots 2 and 3.
 int ir_step(dmgs_plan P, const double* x, const float* e, double* x_out, const double* b, float* r32, int slot,
-            hipStream_t st, bool x_zero = false) {
+            hipStream_t st, bool x_zero = false, bool epi = false) {
     const Level& l = P->lev[0];
     IrArgs a;
     a.x = x;
@@ -939,24 +960,44 @@ int ir_step(dmgs_plan P, const double* x, const float* e, double* x_out, const d
     a.partial = P->partial;
     a.N = l.N;
     a.st = l.stencil<double>(harmonic(P));
+    if (epi) {
+        if (!e || !x_out || !P->epi_d || !P->epi_w || !P->epi_rhobar || ir_shape(l.N, 3).nchunks == 0) {
+            set_error("internal: refinement step cannot take the likelihood epilogue");
+            return DMGS_ERR_INVALID;
+        }
+        a.ed = P->epi_d;
+        a.ew = P->epi_w;
+        a.erhobar = P->epi_rhobar;
+    }
     double bytes = (x_zero ? (e ? 24.0 : 8.0) : 32.0) * l.nv + (e ? 4.0 * l.nv : 0.0) + (x_out ? 8.0 * l.nv : 0.0) +
-                   (r32 ? 4.0 * l.nv : 0.0);
+                   (r32 ? 4.0 * l.nv : 0.0) + (epi ? 24.0 * l.nv : 0.0);
     unsigned nb = 0;
     int tslot;
     TRY(tbeg(P, 0, st, &tslot, DMGS_K_RESIDUAL));
     const bool h = harmonic(P);
-    if (e) {
-        if (x_zero) h ? launch_ir<true, true, true>(a, l.N, st, &nb) : launch_ir<true, true, false>(a, l.N, st, &nb);
-        else h ? launch_ir<true, false, true>(a, l.N, st, &nb) : launch_ir<true, false, false>(a, l.N, st, &nb);
+    if (epi) {
+        if (x_zero) launch_ir_h<true, true, true>(a, l.N, h, st, &nb);
+        else launch_ir_h<true, false, true>(a, l.N, h, st, &nb);
+    } else if (e) {
+        if (x_zero) launch_ir_h<true, true, false>(a, l.N, h, st, &nb);
+        else launch_ir_h<true, false, false>(a, l.N, h, st, &nb);
     } else {
-        if (x_zero) h ? launch_ir<false, true, true>(a, l.N, st, &nb) : launch_ir<false, true, false>(a, l.N, st, &nb);
-        else h ? launch_ir<false, false, true>(a, l.N, st, &nb) : launch_ir<false, false, false>(a, l.N, st, &nb);
+        if (x_zero) launch_ir_h<false, true, false>(a, l.N, h, st, &nb);
+        else launch_ir_h<false, false, false>(a, l.N, h, st, &nb);
     }
     LAUNCHCHK();
     TRY(tend(P, tslot, DMGS_K_RESIDUAL, bytes, st));
-    // the final sum goes straight to the plan's pinned host slots
+    // the final sums go straight to the plan's pinned host slots
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, norm_dst(P), slot);
     LAUNCHCHK();
+    if (epi) {
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial + nb, (int)nb,
+                           norm_dst(P), 2);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial + 2 * nb, (int)nb,
+                           norm_dst(P), 3);
+        LAUNCHCHK();
+    }
     return mark_norms(P, st);
 }
 
@@ -1415,6 +1456,13 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
         double rel1 = 1.0;     // relative residual before the last step
         double rate = 0.0;     // per-V-cycle contraction factor (0: not known yet)
         int inner = o.ir_inner_cycles;
+        // A requested likelihood epilogue rides on the refinement step that
+        // is expected to be the last (in tolerance mode: the contraction
+        // seen so far predicts the tolerance met); epi_step names the step
+        // whose iterate it was computed for.
+        const bool want_epi = P->epi_d && order == 0 && ir_shape(l0.N, 3).nchunks > 0;
+        int epi_step = -1;
+        P->epi_fused = false;
         for (cycles = 0;; cycles++) {
             float* e = l0.u32;
             float* eo = l0.t32;
@@ -1454,18 +1502,25 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
             for (int ic = 0; ic < inner; ic++)
                 TRY(vcycle<float>(P, 0, &e, &eo, l0.q32, order, ic == 0, st, ic == 0 && smoothed, rdone));
             vcycles += inner;
+            bool epi = false;
+            if (want_epi) {
+                epi = fixed ? cycles == nfix - 1
+                            : rate > 0.0 && rel * std::pow(rate, inner) <= o.rtol * (1.0 + 1e-6);
+                if (epi) epi_step = cycles + 1;
+            }
             if (x_zero && cycles == 0 && ((replay ? nfix : P->ir_steps[order]) & 1)) {
                 // the first update reads no iterate, so it may write x in
                 // place: with an odd number of steps (as a replayed schedule
                 // has, or the last solve of this kind took) the result then
                 // ends in x, not in xalt64
-                TRY(ir_step(P, xc, e, xc, b, l0.q32, 1, st, true));
+                TRY(ir_step(P, xc, e, xc, b, l0.q32, 1, st, true, epi));
             } else {
-                TRY(ir_step(P, xc, e, xo, b, l0.q32, 1, st, x_zero && cycles == 0));
+                TRY(ir_step(P, xc, e, xo, b, l0.q32, 1, st, x_zero && cycles == 0, epi));
                 std::swap(xc, xo);
             }
         }
         P->ir_steps[order] = cycles;
+        P->epi_fused = want_epi && epi_step == cycles && cycles > 0;
         if (x_zero && cycles == 0) {
             hipLaunchKernelGGL(k_init_iterate<double>, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, x, l0.N, 0.0);
             LAUNCHCHK();
@@ -2043,6 +2098,7 @@ int plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
     if (const char* e = std::getenv("DMGS_SWEEP2_FP64")) P->cfg_sweep2_fp64 = std::atoi(e) != 0;
     if (const char* e = std::getenv("DMGS_2D_BLOCK_MIN")) P->cfg_2d_block_min = std::max(4, std::atoi(e));
     if (const char* e = std::getenv("DMGS_2D_DEFECT")) P->cfg_2d_defect = std::atoi(e) != 0;
+    if (const char* e = std::getenv("DMGS_EPI_FUSE")) P->cfg_epi_fuse = std::atoi(e) != 0;
     if (const char* e = std::getenv("DMGS_2D_CHUNK")) P->cfg_2d_chunk = std::max(8, std::atoi(e) / 8 * 8);
     return st;
 }
@@ -2631,18 +2687,32 @@ int dmgs_likelihood_grad(dmgs_plan P, const double* q, const double* d, const do
     TRY(begin_call(P, st));
     if (!q || !d || !w || !rho || !qbar || !value) { set_error("NULL argument"); return DMGS_ERR_INVALID; }
     const Level& l0 = P->lev[0];
+    // the epilogue (residual, sums of H and of the kept voxels, and the
+    // pull-back's cotangent into the finest-level scratch) is fused into the
+    // forward solve's last refinement step where the plan refines; the
+    // cotangent's boundary is 0
+    const bool fuse = is_ir(P) && !P->grid && !is2d(P) && P->cfg_epi_fuse;
+    if (fuse) {
+        TRY(set_boundary<double>(P->scratch64, l0.N, 0.0, st));
+        P->epi_d = d;
+        P->epi_w = w;
+        P->epi_rhobar = P->scratch64;
+    }
     int sf = solve(P, q, rho, P->opt.bc_value, 0, info_fwd, st, nullptr, true);
+    P->epi_d = P->epi_w = nullptr;
+    P->epi_rhobar = nullptr;
     if (sf != DMGS_OK && sf != DMGS_ERR_NOT_CONVERGED) return end_call(P, sf, info_fwd, st);
-    // epilogue: residual, sums of H and of the kept voxels, and the pull-back's
-    // cotangent (into the finest-level scratch)
-    const unsigned nb = grid_for(l0.nv, kMaxPartials / 2);
-    TIMED(P, 0, DMGS_K_GRAD, 40.0 * l0.nv, st,
-          hipLaunchKernelGGL(k_likelihood_epilogue, dim3(nb), dim3(kBlock), 0, st, (const double*)rho,
-                             (const double*)l0.mu64, d, w, l0.nv, vdims(P), P->scratch64, P->partial));
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, norm_dst(P), 2);
-    LAUNCHCHK();
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial + nb, (int)nb, norm_dst(P), 3);
-    LAUNCHCHK();
+    if (!(fuse && P->epi_fused)) {
+        const unsigned nb = grid_for(l0.nv, kMaxPartials / 2);
+        TIMED(P, 0, DMGS_K_GRAD, 40.0 * l0.nv, st,
+              hipLaunchKernelGGL(k_likelihood_epilogue, dim3(nb), dim3(kBlock), 0, st, (const double*)rho,
+                                 (const double*)l0.mu64, d, w, l0.nv, vdims(P), P->scratch64, P->partial));
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, norm_dst(P), 2);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial + nb, (int)nb,
+                           norm_dst(P), 3);
+        LAUNCHCHK();
+    }
     const std::vector<int>* replay = (P->opt.adjoint_schedule && P->opt.fixed_cycles <= 0) ? &P->fwd_schedule : nullptr;
     const int sa = solve(P, P->scratch64, qbar, 0.0, 1, info_vjp, st, replay);
     const bool ok_a = sa == DMGS_OK || sa == DMGS_ERR_NOT_CONVERGED;

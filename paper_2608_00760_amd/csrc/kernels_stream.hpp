@@ -13,7 +13,8 @@
 //  k_rb_sweep_col      one red-black Gauss-Seidel sweep, out of place.
 //  k_defect_restrict_col  r = q - A u and full-weighting restriction.
 //  k_ir_residual_col   float64 refinement step: x_out = x + e,
-//                      r32 = float(b - A x_out), ||b - A x_out||^2.
+//                      r32 = float(b - A x_out), ||b - A x_out||^2;
+//                      optionally the likelihood epilogue of x_out.
 #pragma once
 #include <type_traits>
 
@@ -423,6 +424,13 @@ struct IrArgs {
     const double* mu;
     float* r32;
     double* partial;
+    // likelihood epilogue of the refined iterate rho = x_out (EPI): data d,
+    // weights w; rhobar = mua w (mua rho - d) on tile vertices, and block
+    // sums of w (d - mua rho)^2 and of w > 0 at partial[gridDim + b] and
+    // partial[2 gridDim + b]
+    const double* ed = nullptr;
+    const double* ew = nullptr;
+    double* erhobar = nullptr;
     int N;
     int tiles_y, tiles_z, chunk, nchunks;
     Stencil<double> st;
@@ -431,6 +439,7 @@ struct IrArgs {
 struct IrPlane {
     double x0, x1, D0, D1, b0, b1, m0, m1;
     float e0, e1;
+    double d0, d1, w0, w1;   // likelihood data and weights (EPI)
 };
 
 template <int TY, int TZ>
@@ -441,7 +450,7 @@ struct IrShape {
 
 // X_ZERO: the iterate x is 0 everywhere (not read): with e, x_out = e;
 // without e, the residual is b itself.
-template <int TY, int TZ, bool HAS_E, bool X_ZERO, bool HARM>
+template <int TY, int TZ, bool HAS_E, bool X_ZERO, bool HARM, bool EPI = false>
 __global__ __launch_bounds__((IrShape<TY, TZ>::NT)) void k_ir_residual_col(IrArgs a) {
     using Sh = IrShape<TY, TZ>;
     constexpr int NP = Sh::NP, RY = Sh::RY, RZ = Sh::RZ, RA = Sh::RA;
@@ -497,11 +506,17 @@ __global__ __launch_bounds__((IrShape<TY, TZ>::NT)) void k_ir_residual_col(IrArg
         } else {
             P.e0 = P.e1 = 0.0f;
         }
+        if (EPI) {
+            const auto rDd = plane_rsrc(a.ed, pb8, p, pv);
+            const auto rW = plane_rsrc(a.ew, pb8, p, pv);
+            P.d0 = buf_load<double>(rDd, o8_0); P.d1 = buf_load<double>(rDd, o8_1);
+            P.w0 = buf_load<double>(rW, o8_0); P.w1 = buf_load<double>(rW, o8_1);
+        }
     };
     auto u0of = [&](const IrPlane& P) { return HAS_E ? P.x0 + (double)P.e0 : P.x0; };
     auto u1of = [&](const IrPlane& P) { return HAS_E ? P.x1 + (double)P.e1 : P.x1; };
 
-    double acc = 0.0;
+    double acc = 0.0, accH = 0.0, accN = 0.0;
     auto step = [&](int p, IrPlane& Pm1, IrPlane& P0, IrPlane& Pp1) {
         const int sl = p & 1;
         double* U = sU[sl];
@@ -534,6 +549,24 @@ __global__ __launch_bounds__((IrShape<TY, TZ>::NT)) void k_ir_residual_col(IrArg
         const auto rR = plane_rsrc(a.r32, pb4, p, pin && a.r32 != nullptr);
         buf_store<float>((float)r0, rR, s4_0);
         buf_store<float>((float)r1, rR, s4_1);
+        if (EPI) {
+            // L_e = mua rho, the data residual and the pull-back's cotangent
+            // on the tile's interior vertices (the boundary of rhobar is 0)
+            auto epi = [&](double u, double m, double d, double w, bool on, double& rb) {
+                const double res = m * u - d;
+                rb = m * w * res;
+                if (on) {
+                    accH += w * res * res;
+                    accN += w > 0.0 ? 1.0 : 0.0;
+                }
+            };
+            double rb0, rb1;
+            epi(u0, P0.m0, P0.d0, P0.w0, pin && t0, rb0);
+            epi(u1, P0.m1, P0.d1, P0.w1, pin && t1, rb1);
+            const auto rRb = plane_rsrc(a.erhobar, pb8, p, pin);
+            buf_store<double>(rb0, rRb, s8_0);
+            buf_store<double>(rb1, rRb, s8_1);
+        }
     };
 
     IrPlane R0, R1, R2, R3;
@@ -550,15 +583,29 @@ __global__ __launch_bounds__((IrShape<TY, TZ>::NT)) void k_ir_residual_col(IrArg
         if (p0 + 3 >= xb) break;
         step(p0 + 3, R3, R0, R1); load(p0 + 6, R3);
     }
-    // deterministic block sum (fixed order over waves)
-    __shared__ double wsum[Sh::NT / 64];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    if (tid % 64 == 0) wsum[tid / 64] = acc;
+    // deterministic block sums (fixed order over waves)
+    __shared__ double wsum[3][Sh::NT / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        acc += __shfl_down(acc, off, 64);
+        if (EPI) {
+            accH += __shfl_down(accH, off, 64);
+            accN += __shfl_down(accN, off, 64);
+        }
+    }
+    if (tid % 64 == 0) {
+        wsum[0][tid / 64] = acc;
+        if (EPI) {
+            wsum[1][tid / 64] = accH;
+            wsum[2][tid / 64] = accN;
+        }
+    }
     __syncthreads();
     if (tid == 0) {
-        double s = 0.0;
-        for (int i = 0; i < Sh::NT / 64; i++) s += wsum[i];
-        a.partial[blockIdx.x] = s;
+        for (int k = 0; k < (EPI ? 3 : 1); k++) {
+            double s = 0.0;
+            for (int i = 0; i < Sh::NT / 64; i++) s += wsum[k][i];
+            a.partial[k * gridDim.x + blockIdx.x] = s;
+        }
     }
 }
 

@@ -88,3 +88,35 @@ def test_tolerance_mode_matches_oracle():
     assert errs["H"] <= 1e-9 and errs["chi2"] <= 1e-9
     assert max(errs["q"], errs["logD"], errs["logmua"]) <= 1e-8
     assert abs(val["chi2"] - 1.0) <= 4.0 * np.sqrt(2.0 / val["nvox"])
+
+
+@pytest.mark.parametrize("N,fixed,g", [(64, 0, 0.0), (96, 0, 0.3), (64, 3, 0.0), (48, 2, 0.3)])
+def test_fused_epilogue_matches_separate_pass(N, fixed, g, monkeypatch):
+    """A refining plan computes the epilogue (rhobar, the sums of H and of
+    the kept voxels) inside the forward solve's last refinement step.  With
+    and without that fusion (DMGS_EPI_FUSE) the solves are the same: rho is
+    bitwise equal, H and chi2 agree to 1e-13, the gradients to 1e-13 in
+    fixed-cycle mode (1e-9 with tolerances, where a last-bit change of
+    rhobar may move the adjoint's stopping point); the timing counts show
+    that the separate epilogue pass ran only without fusion."""
+    import torch
+    say("fused epilogue N=%d fixed=%d g=%g" % (N, fixed, g))
+    c, H, Le, d, w = setup(N, 950 + N + fixed)
+    res = {}
+    for fuse in (1, 0):
+        monkeypatch.setenv("DMGS_EPI_FUSE", str(fuse))
+        P = plan_for(c, N, precision="fp32-in-fp64", fixed_cycles=fixed, bc_value=g)
+        P.timing(True)
+        (rho, val, grads), fi, vi = P.likelihood_grad(dev(c["q"]), dev(d), dev(w))
+        torch.cuda.synchronize()
+        res[fuse] = (host(rho), val, [host(x) for x in grads], P.timing_read()["grad"]["launches"], fi)
+    (r1, v1, g1, n1, f1), (r0, v0, g0, n0, f0) = res[1], res[0]
+    say("  cycles %d, grad-class launches fused %d separate %d, chi2 %.4f" % (f1["cycles"], n1, n0, v1["chi2"]))
+    assert f1["cycles"] == f0["cycles"] and f1["cycles"] >= 1
+    assert n1 == n0 - 1
+    assert np.array_equal(r1, r0)
+    assert abs(v1["H"] - v0["H"]) <= 1e-13 * v0["H"] and abs(v1["chi2"] - v0["chi2"]) <= 1e-13 * v0["chi2"]
+    assert v1["nvox"] == v0["nvox"] == int(np.count_nonzero(w > 0))
+    tol = 1e-13 if fixed else 1e-9
+    for a, b in zip(g1, g0):
+        assert rel_max(a, b) <= tol
