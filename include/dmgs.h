@@ -278,7 +278,15 @@ int dmgs_noise_weights(dmgs_plan plan, const double *Le, int32_t mask, double re
  * logD_bar, logmua_bar must not alias each other or the inputs; logD_bar /
  * logmua_bar may be NULL.  The call waits for the work it enqueued (value is
  * ready on return).  info_fwd / info_vjp describe the two solves (either may
- * be NULL); the status is the forward solve's, else the adjoint's. */
+ * be NULL); the status is the forward solve's, else the adjoint's.
+ * The epilogue (L_e, the sums of H and N_vox, rhobar) is computed in the
+ * forward solve's last pass over rho where one exists: a refining plan's
+ * last refinement step, a general grid's last half-sweep, a float64 cubic
+ * plan's last residual pass (in fixed-cycle mode only when info_fwd is
+ * given); in tolerance mode that is the step the observed contraction
+ * predicts to be the last.  Otherwise, and on two-dimensional plans, it is
+ * a separate pass over rho; both give the same values (the sums up to
+ * rounding order). */
 int dmgs_likelihood_grad(dmgs_plan plan, const double *q, const double *d, const double *w, double *rho,
                          double *qbar, double *logD_bar, double *logmua_bar, double *value, dmgs_info *info_fwd,
                          dmgs_info *info_vjp, void *stream);

@@ -961,7 +961,7 @@ int ir_step(dmgs_plan P, const double* x, const float* e, double* x_out, const d
     a.N = l.N;
     a.st = l.stencil<double>(harmonic(P));
     if (epi) {
-        if (!e || !x_out || !P->epi_d || !P->epi_w || !P->epi_rhobar || ir_shape(l.N, 3).nchunks == 0) {
+        if ((x_zero && !e) || !P->epi_d || !P->epi_w || !P->epi_rhobar || ir_shape(l.N, 3).nchunks == 0) {
             set_error("internal: refinement step cannot take the likelihood epilogue");
             return DMGS_ERR_INVALID;
         }
@@ -976,7 +976,8 @@ int ir_step(dmgs_plan P, const double* x, const float* e, double* x_out, const d
     TRY(tbeg(P, 0, st, &tslot, DMGS_K_RESIDUAL));
     const bool h = harmonic(P);
     if (epi) {
-        if (x_zero) launch_ir_h<true, true, true>(a, l.N, h, st, &nb);
+        if (!e) launch_ir_h<false, false, true>(a, l.N, h, st, &nb);
+        else if (x_zero) launch_ir_h<true, true, true>(a, l.N, h, st, &nb);
         else launch_ir_h<true, false, true>(a, l.N, h, st, &nb);
     } else if (e) {
         if (x_zero) launch_ir_h<true, true, false>(a, l.N, h, st, &nb);
@@ -1277,7 +1278,11 @@ GridDims gdims(dmgs_plan P, int k);
 // One V(nu1, nu2)-cycle on level k (order 0: red before black; order 1, the
 // transposed cycle: black before red with the counts exchanged); u on the
 // coarser levels starts at 0.
-int vcycle_grid(dmgs_plan P, int k, double* u, const double* q, int order, hipStream_t st) {
+// epi (finest level): the last post-smoothing half-sweep also takes the
+// likelihood epilogue of the cycle's result (the plan's epi_* buffers, sums
+// into norm slots 2 and 3); *epi_done reports whether it ran.
+int vcycle_grid(dmgs_plan P, int k, double* u, const double* q, int order, hipStream_t st, bool epi = false,
+                bool* epi_done = nullptr) {
     const Level& l = P->lev[k];
     const GridDims G = gdims(P, k);
     if (k == P->L - 1) {
@@ -1309,7 +1314,23 @@ int vcycle_grid(dmgs_plan P, int k, double* u, const double* q, int order, hipSt
     TRY(vcycle_grid(P, k + 1, c.u64, c.q64, order, st));
     TIMED(P, k, DMGS_K_PROLONG, 17.0 * l.nv, st,
           hipLaunchKernelGGL(k_g_prolong_add, dim3(g), dim3(kBlock), 0, st, (const double*)c.u64, G, u));
-    return sweeps(nu_post_of(P, order));
+    const int npost = nu_post_of(P, order);
+    if (!(epi && k == 0 && npost > 0 && P->epi_d)) return sweeps(npost);
+    TRY(sweeps(npost - 1));
+    TIMED(P, k, DMGS_K_SMOOTH, 40.0 * l.nv, st,
+          hipLaunchKernelGGL(k_g_half, dim3(g), dim3(kBlock), 0, st, u, q, (const double*)l.D64,
+                             (const double*)l.mu64, G, first));
+    const unsigned ge = grid_for(l.nv, kMaxPartials / 2);
+    TIMED(P, k, DMGS_K_SMOOTH, 72.0 * l.nv, st,
+          hipLaunchKernelGGL(k_g_half_epi, dim3(ge), dim3(kBlock), 0, st, u, q, (const double*)l.D64,
+                             (const double*)l.mu64, G, 1 - first, P->epi_d, P->epi_w, P->epi_rhobar, P->partial));
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)ge, norm_dst(P), 2);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial + ge, (int)ge, norm_dst(P),
+                       3);
+    LAUNCHCHK();
+    if (epi_done) *epi_done = true;
+    return mark_norms(P, st);
 }
 
 // ||b - A x||^2 of the finest level into the norm slot `slot`.
@@ -1345,16 +1366,28 @@ int solve_grid(dmgs_plan P, const double* b, double* x, double bc, int order, dm
             status = DMGS_ERR_NONFINITE;
         }
     }
+    // A requested likelihood epilogue rides on the last half-sweep of the
+    // cycle expected to be the last (in tolerance mode: the one the
+    // contraction of the last cycle predicts to come within 4 rtol; a cycle
+    // that takes it and is not the last costs one more read of d and w).
+    const bool want_epi = P->epi_d && order == 0;
+    P->epi_fused = false;
+    double rel_prev = 1.0;
+    bool epi_next = false;
     if (status == DMGS_OK && (fixed || r0 > 0.0)) {
         for (cycles = 1; !(fixed && nfix == 0); cycles++) {
-            TRY(vcycle_grid(P, 0, x, b, order, st));
+            bool done = false;
+            TRY(vcycle_grid(P, 0, x, b, order, st, want_epi && (fixed ? cycles == nfix : epi_next), &done));
+            P->epi_fused = done;
             if (fixed) {
                 if (cycles == nfix) break;
                 continue;
             }
             TRY(resid_grid(P, x, b, 1, st));
             TRY(read_norms(P, st));
+            rel_prev = cycles == 1 ? 1.0 : rel;
             rel = std::sqrt(P->hnorm[1]) / r0;
+            epi_next = rel < rel_prev && rel * (rel / rel_prev) <= 4.0 * o.rtol;
             if (!std::isfinite(rel)) { set_error("non-finite residual after %d cycles", cycles); status = DMGS_ERR_NONFINITE; break; }
             if (rel <= o.rtol) break;
             if (cycles >= o.max_cycles) { set_error("not converged after %d cycles (rel %.3e)", cycles, rel); status = DMGS_ERR_NOT_CONVERGED; break; }
@@ -1417,6 +1450,13 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
             if (!std::isfinite(r0)) { set_error("non-finite right-hand side"); status = DMGS_ERR_NONFINITE; goto done; }
             if (r0 == 0.0) goto done;
         }
+        // A requested likelihood epilogue rides on the residual pass after
+        // the cycle expected to be the last (the contraction of the last
+        // cycle predicts a residual within 4 rtol), or on the final residual
+        // pass of fixed-cycle mode.
+        const bool want_epi = P->epi_d && order == 0 && ir_shape(l0.N, 3).nchunks > 0;
+        P->epi_fused = false;
+        double rel_prev = 1.0;
         for (cycles = 1; !(fixed && nfix == 0); cycles++) {
             TRY(vcycle<double>(P, 0, &cur, &oth, b, order, false, st));
             sched.push_back(1);
@@ -1424,8 +1464,11 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
                 if (cycles == nfix) break;
                 continue;
             }
-            TRY(ir_step(P, cur, nullptr, nullptr, b, nullptr, 1, st));
+            const bool epi = want_epi && cycles > 1 && rel < rel_prev && rel * (rel / rel_prev) <= 4.0 * o.rtol;
+            TRY(ir_step(P, cur, nullptr, nullptr, b, nullptr, 1, st, false, epi));
+            P->epi_fused = epi;
             TRY(read_norms(P, st));
+            rel_prev = cycles == 1 ? 1.0 : rel;
             rel = std::sqrt(P->hnorm[1]) / r0;
             if (!std::isfinite(rel)) { set_error("non-finite residual after %d cycles", cycles); status = DMGS_ERR_NONFINITE; break; }
             if (rel <= o.rtol) break;
@@ -1434,7 +1477,8 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
         if (fixed && nfix == 0) cycles = 0;
         if (cur != x) HIPCHK(hipMemcpyAsync(x, cur, l0.nv * sizeof(double), hipMemcpyDeviceToDevice, st));
         if (fixed && info) {
-            TRY(ir_step(P, x, nullptr, nullptr, b, nullptr, 1, st));
+            TRY(ir_step(P, x, nullptr, nullptr, b, nullptr, 1, st, false, want_epi));
+            P->epi_fused = want_epi;
             TRY(read_norms(P, st));
             r0 = std::sqrt(P->hnorm[0]);
             rel = std::sqrt(P->hnorm[1]) / (r0 > 0.0 ? r0 : 1.0);
@@ -1888,6 +1932,8 @@ namespace {
 // defect); the finest scratch, partials, the coarsest inverse, the flag.
 int grid_plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
     P->grid = true;
+    // the one tuning knob that applies to general grids
+    if (const char* e = std::getenv("DMGS_EPI_FUSE")) P->cfg_epi_fuse = std::atoi(e) != 0;
     int cn[kMaxLevels][3];
     P->L = grid_levels(o->n, cn);
     int st = DMGS_OK;
@@ -2691,13 +2737,14 @@ int dmgs_likelihood_grad(dmgs_plan P, const double* q, const double* d, const do
     // pull-back's cotangent into the finest-level scratch) is fused into the
     // forward solve's last refinement step where the plan refines; the
     // cotangent's boundary is 0
-    const bool fuse = is_ir(P) && !P->grid && !is2d(P) && P->cfg_epi_fuse;
+    const bool fuse = !is2d(P) && P->cfg_epi_fuse;
     if (fuse) {
-        TRY(set_boundary<double>(P->scratch64, l0.N, 0.0, st));
+        if (!P->grid) TRY(set_boundary<double>(P->scratch64, l0.N, 0.0, st));
         P->epi_d = d;
         P->epi_w = w;
         P->epi_rhobar = P->scratch64;
     }
+    P->epi_fused = false;
     int sf = solve(P, q, rho, P->opt.bc_value, 0, info_fwd, st, nullptr, true);
     P->epi_d = P->epi_w = nullptr;
     P->epi_rhobar = nullptr;

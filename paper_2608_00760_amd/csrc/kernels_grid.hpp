@@ -139,6 +139,45 @@ __global__ void k_g_half(double* __restrict__ u, const double* __restrict__ q, c
     }
 }
 
+// The last half-sweep of a solve, with the likelihood epilogue of its
+// result: the swept colour is updated as in k_g_half, and every vertex, its
+// value now final, gets rhobar = mua w (mua u - d) (0 on the boundary) and
+// adds w (mua u - d)^2 and [w > 0] to its block's sums at partial[block]
+// and partial[gridDim + block].  The other colour is only read.
+__global__ void k_g_half_epi(double* __restrict__ u, const double* __restrict__ q, const double* __restrict__ D,
+                             const double* __restrict__ mu, GridDims G, int colour, const double* __restrict__ d,
+                             const double* __restrict__ w, double* __restrict__ rhobar, double* __restrict__ partial) {
+    double acc = 0.0, cnt = 0.0;
+    GRID_LOOP(G, v) {
+        int x, y, z;
+        G.coords(v, x, y, z);
+        if (!G.interior(x, y, z)) {
+            rhobar[v] = 0.0;
+            continue;
+        }
+        double uv;
+        if (((x + y + z) & 1) == colour) {
+            double num, diag;
+            g_stencil(u, D, G, x, y, z, v, num, diag);
+            uv = (q[v] + num) / (diag + mu[v]);
+            u[v] = uv;
+        } else {
+            uv = u[v];
+        }
+        const double m = mu[v], wv = w[v];
+        const double res = m * uv - d[v];
+        rhobar[v] = m * wv * res;
+        acc += wv * res * res;
+        cnt += wv > 0.0 ? 1.0 : 0.0;
+    }
+    const double s = block_sum(acc);
+    const double c = block_sum(cnt);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = s;
+        partial[gridDim.x + blockIdx.x] = c;
+    }
+}
+
 // r = q - A u on interior vertices, 0 on the boundary
 __global__ void k_g_defect(const double* __restrict__ u, const double* __restrict__ q, const double* __restrict__ D,
                            const double* __restrict__ mu, GridDims G, double* __restrict__ r) {

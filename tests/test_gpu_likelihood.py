@@ -90,24 +90,59 @@ def test_tolerance_mode_matches_oracle():
     assert abs(val["chi2"] - 1.0) <= 4.0 * np.sqrt(2.0 / val["nvox"])
 
 
-@pytest.mark.parametrize("N,fixed,g", [(64, 0, 0.0), (96, 0, 0.3), (64, 3, 0.0), (48, 2, 0.3)])
-def test_fused_epilogue_matches_separate_pass(N, fixed, g, monkeypatch):
-    """A refining plan computes the epilogue (rhobar, the sums of H and of
-    the kept voxels) inside the forward solve's last refinement step.  With
-    and without that fusion (DMGS_EPI_FUSE) the solves are the same: rho is
-    bitwise equal, H and chi2 agree to 1e-13, the gradients to 1e-13 in
-    fixed-cycle mode (1e-9 with tolerances, where a last-bit change of
-    rhobar may move the adjoint's stopping point); the timing counts show
-    that the separate epilogue pass ran only without fusion."""
-    import torch
-    say("fused epilogue N=%d fixed=%d g=%g" % (N, fixed, g))
+
+@pytest.mark.parametrize("precision,N,fixed,g", [
+    ("fp32-in-fp64", 64, 0, 0.0), ("fp32-in-fp64", 96, 0, 0.3), ("fp32-in-fp64", 64, 3, 0.0),
+    ("fp32-in-fp64", 48, 2, 0.3), ("fp64", 64, 0, 0.0), ("fp64", 48, 3, 0.3)])
+def test_fused_epilogue_matches_separate_pass(precision, N, fixed, g, monkeypatch):
+    """The epilogue (rhobar, the sums of H and of the kept voxels) rides on
+    the forward solve's last pass over the iterate: a refining plan's last
+    refinement step, a float64 plan's last residual pass.  With and without
+    that fusion (DMGS_EPI_FUSE) the solves are the same: rho is bitwise
+    equal, H and chi2 agree to 1e-13, the gradients to 1e-13 in fixed-cycle
+    mode (1e-9 with tolerances, where a last-bit change of rhobar may move
+    the adjoint's stopping point); the timing counts show that the separate
+    epilogue pass ran only without fusion."""
+    say("fused epilogue %s N=%d fixed=%d g=%g" % (precision, N, fixed, g))
     c, H, Le, d, w = setup(N, 950 + N + fixed)
+    fused_vs_separate(lambda: plan_for(c, N, precision=precision, fixed_cycles=fixed, bc_value=g),
+                      c["q"], d, w, fixed, monkeypatch)
+
+
+@pytest.mark.parametrize("fixed", [0, 4])
+def test_fused_epilogue_general_grid(fixed, monkeypatch):
+    """General grids take the epilogue in the last half-sweep of the last
+    V-cycle (in tolerance mode: of the cycle the last contraction predicts to
+    be the last); the same comparison with the separate pass."""
+    from oracle import likelihood
+    from paper_2608_00760_amd import synth
+    from paper_2608_00760_amd.solver import Options, Plan
+    cells, h = (64, 32, 32), (7.5 / 64, 3.5 / 32, 3.5 / 32)
+    say("fused epilogue grid", cells, "fixed", fixed)
+    c = synth.grid_case(cells, 960 + fixed)
+    from oracle import refgrid
+    Hg = refgrid.HierarchyGrid(c["D"], c["mua"], h=h)
+    rr, _ = Hg.forward(c["q"], rtol=1e-12)
+    Le = c["mua"] * rr
+    w = likelihood.noise_weights(Le, 2)
+    sigma = np.sqrt(np.where(w > 0, 1.0 / np.where(w > 0, w, 1.0), 0.0))
+    d = Le + sigma * np.random.default_rng(961).standard_normal(Le.shape)
+
+    def make():
+        P = Plan(Options(cells[0], shape=cells, spacing=h, fixed_cycles=fixed))
+        P.set_log_coefficients(dev(c["logD"]), dev(c["logmua"]))
+        return P
+    fused_vs_separate(make, c["q"], d, w, fixed, monkeypatch)
+
+
+def fused_vs_separate(make, q, d, w, fixed, monkeypatch):
+    import torch
     res = {}
     for fuse in (1, 0):
         monkeypatch.setenv("DMGS_EPI_FUSE", str(fuse))
-        P = plan_for(c, N, precision="fp32-in-fp64", fixed_cycles=fixed, bc_value=g)
+        P = make()
         P.timing(True)
-        (rho, val, grads), fi, vi = P.likelihood_grad(dev(c["q"]), dev(d), dev(w))
+        (rho, val, grads), fi, vi = P.likelihood_grad(dev(q), dev(d), dev(w))
         torch.cuda.synchronize()
         res[fuse] = (host(rho), val, [host(x) for x in grads], P.timing_read()["grad"]["launches"], fi)
     (r1, v1, g1, n1, f1), (r0, v0, g0, n0, f0) = res[1], res[0]
