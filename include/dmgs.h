@@ -133,7 +133,10 @@ typedef struct dmgs_options {
 typedef struct dmgs_info {
     int32_t cycles;        /* V-cycles (or refinement steps) applied */
     int32_t status;        /* dmgs_status of the call */
-    double rel_residual;   /* final ||r|| / ||r_0|| of the solve (adjoint: ||rhobar - A qbar|| / ||rhobar||) */
+    double rel_residual;   /* final ||r|| / ||r_0|| of the solve (adjoint: ||rhobar - A qbar|| / ||rhobar||);
+                              float64 red-black plans in tolerance mode form ||r|| after the first cycle
+                              in the next cycle's first smoothing pass, where the residual of the colour
+                              a cycle updates last is 0 up to rounding and is taken as 0 */
     double device_ms;      /* device time of the call, from events on `stream` */
     int32_t vcycles;       /* V-cycles applied (float32 V-cycles over all refinement steps) */
     int32_t reserved;

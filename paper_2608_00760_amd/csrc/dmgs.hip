@@ -471,15 +471,11 @@ int smooth_pass(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int ord
     return DMGS_OK;
 }
 
-// Two-sweep passes (float32): tiles of 16 x 64; chunks of x-planes sized
-// for about cfg_sweep2_wgs workgroups, at least 8 planes (a chunk
-// recomputes 3 planes at each end).
-template <class T, int TY, int TZ, bool HARM, bool DEFECT>
-int launch_sweep2(dmgs_plan P, const SweepArgs<T>& a0, int N, int mode, hipStream_t st) {
-    SweepArgs<T> a = a0;
-    constexpr int RING = DEFECT ? 5 : 4;
-    constexpr int NT = Sweep2Shape<TY, TZ, RING>::NT;
-    constexpr size_t lds = sweep2_lds_bytes<T, TY, TZ, RING>();
+// Grid of a two-sweep pass over level size N with TY x TZ tiles: chunks of
+// x-planes sized for about cfg_sweep2_wgs workgroups, at least 8 planes (a
+// chunk recomputes 3 planes at each end).  Returns the number of workgroups.
+template <class T>
+int sweep2_grid(dmgs_plan P, SweepArgs<T>& a, int N, int TY, int TZ) {
     a.tiles_y = (N + TY - 1) / TY;
     a.tiles_z = (N + TZ - 1) / TZ;
     const int tiles = a.tiles_y * a.tiles_z;
@@ -503,7 +499,28 @@ int launch_sweep2(dmgs_plan P, const SweepArgs<T>& a0, int N, int mode, hipStrea
     }
     a.chunk = std::min(N - 1, std::max(8, (N - 1 + nch - 1) / nch));
     a.nchunks = (N - 1 + a.chunk - 1) / a.chunk;
-    const int nb = tiles * a.nchunks;
+    return tiles * a.nchunks;
+}
+
+// NORM: a plain pass that also leaves the per-block sums of its input's
+// squared residual in a.partial (*nb_out blocks).
+template <class T, int TY, int TZ, bool HARM, bool DEFECT, bool NORM = false>
+int launch_sweep2(dmgs_plan P, const SweepArgs<T>& a0, int N, int mode, hipStream_t st, unsigned* nb_out = nullptr) {
+    SweepArgs<T> a = a0;
+    constexpr int RING = DEFECT ? 5 : 4;
+    constexpr int NT = Sweep2Shape<TY, TZ, RING>::NT;
+    constexpr size_t lds = sweep2_lds_bytes<T, TY, TZ, RING>();
+    const int nb = sweep2_grid<T>(P, a, N, TY, TZ);
+    if (nb_out) *nb_out = (unsigned)nb;
+    if constexpr (NORM) {
+        if (mode != kSweepPlain || nb > kMaxPartials || !a.partial) {
+            set_error("internal: two-sweep norm pass needs a plain pass of at most %d workgroups", kMaxPartials);
+            return DMGS_ERR_INVALID;
+        }
+        hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepPlain, HARM, false, true>), dim3(nb), dim3(NT), lds, st, a);
+        LAUNCHCHK();
+        return DMGS_OK;
+    }
     if (mode == kSweepZero) hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepZero, HARM, DEFECT>), dim3(nb), dim3(NT), lds, st, a);
     else if (mode == kSweepPlain) hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepPlain, HARM, DEFECT>), dim3(nb), dim3(NT), lds, st, a);
     else if constexpr (!DEFECT) hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepProlong, HARM>), dim3(nb), dim3(NT), lds, st, a);
@@ -537,7 +554,9 @@ int sweep2_attributes() {
         {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepProlong, false>, lds64},
         {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepPlain, true>, lds64},
         {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepZero, true>, lds64},
-        {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepProlong, true>, lds64}};
+        {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepProlong, true>, lds64},
+        {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepPlain, false, false, true>, lds64},
+        {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepPlain, true, false, true>, lds64}};
     for (const auto& f : fns)
         if (hipFuncSetAttribute(f.first, hipFuncAttributeMaxDynamicSharedMemorySize, f.second) != hipSuccess) {
             set_error("hipFuncSetAttribute failed");
@@ -559,9 +578,11 @@ bool use_sweep2(dmgs_plan P, int k, size_t tsize) {
 
 // One two-sweep pass: u_out = two red-black sweeps applied to u_in (or to
 // 0, or to u_in + I ec).
+// norm_partial (float64, plain passes): also the per-block sums of the
+// input's squared residual there (*nb_out blocks).
 template <class T>
 int smooth_pass2(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int order, bool zero, const T* ec,
-                 hipStream_t st, T* r = nullptr) {
+                 hipStream_t st, T* r = nullptr, double* norm_partial = nullptr, unsigned* nb_out = nullptr) {
     const Level& l = P->lev[k];
     SweepArgs<T> a;
     a.u_in = u_in;
@@ -576,6 +597,10 @@ int smooth_pass2(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int or
     a.st = l.stencil<T>(harmonic(P));
     const int mode = zero ? kSweepZero : (ec ? kSweepProlong : kSweepPlain);
     if (r && ec) { set_error("two-sweep pass: defect only after pre-smoothing"); return DMGS_ERR_INVALID; }
+    if (norm_partial && (sizeof(T) != 8 || zero || ec || r)) {
+        set_error("internal: the two-sweep norm pass is a plain float64 pass");
+        return DMGS_ERR_INVALID;
+    }
     // algorithmic bytes: read u (unless zero), q, D, w, (ec), write u, (r) -- once for both sweeps
     double words = (zero ? 4.0 : 5.0) + (ec ? 0.125 : 0.0) + (r ? 1.0 : 0.0);
     int slot;
@@ -590,8 +615,14 @@ int smooth_pass2(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int or
         // float64: half-width tiles (the LDS ring holds twice the bytes);
         // no defect-writing variant
         if (r) { set_error("two-sweep pass: no defect output in float64"); return DMGS_ERR_INVALID; }
-        TRY(harmonic(P) ? (launch_sweep2<T, kSweep2TY, kSweep2TZ64, true, false>(P, a, l.N, mode, st))
-                        : (launch_sweep2<T, kSweep2TY, kSweep2TZ64, false, false>(P, a, l.N, mode, st)));
+        if (norm_partial) {
+            a.partial = norm_partial;
+            TRY(harmonic(P) ? (launch_sweep2<T, kSweep2TY, kSweep2TZ64, true, false, true>(P, a, l.N, mode, st, nb_out))
+                            : (launch_sweep2<T, kSweep2TY, kSweep2TZ64, false, false, true>(P, a, l.N, mode, st, nb_out)));
+        } else {
+            TRY(harmonic(P) ? (launch_sweep2<T, kSweep2TY, kSweep2TZ64, true, false>(P, a, l.N, mode, st))
+                            : (launch_sweep2<T, kSweep2TY, kSweep2TZ64, false, false>(P, a, l.N, mode, st)));
+        }
     }
     TRY(tend(P, slot, DMGS_K_SMOOTH, words * l.nv * sizeof(T), st));
     return DMGS_OK;
@@ -1457,13 +1488,62 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
         const bool want_epi = P->epi_d && order == 0 && ir_shape(l0.N, 3).nchunks > 0;
         P->epi_fused = false;
         double rel_prev = 1.0;
+        // In tolerance mode the residual norm of each iterate comes with the
+        // first pre-smoothing pass of the next cycle (free_norm): after a
+        // cycle whose post-smoothing ended with the second colour, the
+        // second colour's residual is 0 and the first colour's is what that
+        // pass's first stage forms anyway.  The pass, the defect and the
+        // coarse levels of the next cycle are enqueued before the host reads
+        // the norm; when it meets the tolerance, the iterate (still in the
+        // pass's input buffer) is returned and the rest of that cycle is
+        // dropped.
+        SweepArgs<double> probe;
+        const bool free_norm = !fixed && !want_epi && !wjacobi(P) && P->L > 1 && fused_level(P, 0) &&
+                               use_sweep2(P, 0, sizeof(double)) && nu_pre_of(P, order) >= 2 &&
+                               nu_post_of(P, order) >= 1 && sweep2_grid<double>(P, probe, l0.N, kSweep2TY, kSweep2TZ64) <= kMaxPartials;
         for (cycles = 1; !(fixed && nfix == 0); cycles++) {
+            if (free_norm && cycles >= 2) {
+                // cycle `cycles` from u_{cycles-1} (in cur)
+                double* prev = cur;
+                unsigned nb = 0;
+                TRY(smooth_pass2<double>(P, 0, cur, oth, b, order, false, nullptr, st, nullptr, P->partial, &nb));
+                std::swap(cur, oth);
+                hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb,
+                                   norm_dst(P), 1);
+                LAUNCHCHK();
+                TRY(mark_norms(P, st));
+                if (nu_pre_of(P, order) > 2)
+                    TRY(smooth_phase<double>(P, 0, &cur, &oth, b, nu_pre_of(P, order) - 2, order, false, (const double*)nullptr, st));
+                const Level& c1 = P->lev[1];
+                TRY(defect_restrict<double>(P, 0, cur, b, c1.q64, st));
+                double* ccur = c1.u64;
+                double* coth = c1.t64;
+                TRY(vcycle<double>(P, 1, &ccur, &coth, c1.q64, order, true, st));
+                TRY(read_norms(P, st));
+                rel_prev = cycles == 2 ? 1.0 : rel;
+                rel = std::sqrt(P->hnorm[1]) / r0;
+                bool stop = false;
+                if (!std::isfinite(rel)) { set_error("non-finite residual after %d cycles", cycles - 1); status = DMGS_ERR_NONFINITE; stop = true; }
+                else if (rel <= o.rtol) stop = true;
+                else if (cycles - 1 >= o.max_cycles) { set_error("not converged after %d cycles (rel %.3e)", cycles - 1, rel); status = DMGS_ERR_NOT_CONVERGED; stop = true; }
+                if (stop) {
+                    // the result is the cycle's input; prev may be x itself
+                    cur = prev;
+                    oth = prev == x ? l0.t64 : x;
+                    cycles--;
+                    break;
+                }
+                TRY(post_pass<double>(P, 0, &cur, &oth, ccur, b, order, st));
+                sched.push_back(1);
+                continue;
+            }
             TRY(vcycle<double>(P, 0, &cur, &oth, b, order, false, st));
             sched.push_back(1);
             if (fixed) {
                 if (cycles == nfix) break;
                 continue;
             }
+            if (free_norm) continue;   // the norm of this iterate comes with the next cycle
             const bool epi = want_epi && cycles > 1 && rel < rel_prev && rel * (rel / rel_prev) <= 4.0 * o.rtol;
             TRY(ir_step(P, cur, nullptr, nullptr, b, nullptr, 1, st, false, epi));
             P->epi_fused = epi;

@@ -80,6 +80,7 @@ struct SweepArgs {
     const T* w;      // inverse diagonal
     const T* ec;     // coarse correction added by prolongation (MODE 2)
     T* r;            // defect of the result (two-sweep passes with DEFECT)
+    double* partial = nullptr;   // per-block sums of the input's squared residual (two-sweep passes with NORM)
     int N;
     int order;       // colour of the first stage: 0 red, 1 black
     int tiles_y, tiles_z, chunk, nchunks;

@@ -51,6 +51,13 @@
 // equation with its neighbours' final values), so only the first colour's
 // residual is computed and stored; the reader takes the second colour's as
 // 0.  Waves with no tile vertex skip the defect.
+//
+// With NORM (plain passes) the pass also sums the squared residual of its
+// input over the tile's first-colour vertices: stage 0 forms q + sum_j c_ij
+// u_j from the input, and the residual is that minus u_i / w_i.  When the
+// input ended a red-black sweep whose last colour is this pass's second,
+// the second colour's residual is 0 (up to rounding), so the block sums
+// (one per workgroup, in a.partial) add up to ||q - A u||^2 of the input.
 #pragma once
 #include "kernels_stream.hpp"
 
@@ -91,10 +98,11 @@ __host__ __device__ constexpr bool sweep2_fits(int N) {
     return ((int64_t)(N + 1) * (N + 1) * (N + 20) + 64) * (int64_t)sizeof(T) < (int64_t)kOob;
 }
 
-template <class T, int TY, int TZ, int MODE, bool HARM, bool DEFECT = false>
+template <class T, int TY, int TZ, int MODE, bool HARM, bool DEFECT = false, bool NORM = false>
 __global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_rb_sweep2_col(SweepArgs<T> a) {
     constexpr bool ZERO_INIT = MODE == kSweepZero, PROLONG = MODE == kSweepProlong;
     static_assert(!(DEFECT && PROLONG), "the defect is formed after pre-smoothing only");
+    static_assert(!NORM || (MODE == kSweepPlain && !DEFECT), "the input's residual norm needs a plain pass");
     using Sh = Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>;
     constexpr int R = Sh::R, NP = Sh::NP, RA = Sh::RA, HALF = Sh::HALF;
     // slot k, element O: ring[(k * 2 + O) * RA + ly * NP + pz]
@@ -279,13 +287,25 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_r
         wact0[j] = __builtin_amdgcn_ballot_w64(m0[j]) != 0;
         wact1[j] = __builtin_amdgcn_ballot_w64(m1[j]) != 0;
     }
+    double nacc = 0.0;   // NORM: this lane's squared residuals of the input
+    bool step_in = false;   // NORM: the current step's plane is one of the chunk's
     auto stage = [&](auto Oc, auto Jc, auto Kc, SweepPlane<T>& Pb, SweepPlane<T>& P, SweepPlane<T>& Pa) {
         constexpr int O = decltype(Oc)::value, J = decltype(Jc)::value, K = decltype(Kc)::value;
         if (!(O ? wact1[J] : wact0[J])) return;
         UD<T>* S = ring + ((K - J + 8) & 7) * 2 * RA;
-        // from a zero iterate every neighbour of the first colour is 0: the
-        // update is w q (the same value the full formula gives)
-        const T v = (ZERO_INIT && J == 0) ? (O ? P.q1 * P.w1 : P.q0 * P.w0) : update(Oc, S, Pb, P, Pa);
+        T v;
+        if constexpr (NORM && J == 0) {
+            const T num = gs_num(Oc, S, Pb, P, Pa);
+            const T wi = O ? P.w1 : P.w0;
+            const bool on = step_in && (O ? soff1 : soff0) != kOob;
+            const T r = num - (O ? P.u1 : P.u0) / (on ? wi : T(1));
+            nacc += on ? (double)r * (double)r : 0.0;
+            v = num * wi;
+        } else {
+            // from a zero iterate every neighbour of the first colour is 0: the
+            // update is w q (the same value the full formula gives)
+            v = (ZERO_INIT && J == 0) ? (O ? P.q1 * P.w1 : P.q0 * P.w0) : update(Oc, S, Pb, P, Pa);
+        }
         if (O) {
             P.u1 = m1[J] ? v : P.u1;
             if (J < 3 || DEFECT) S[RA + pe].u = P.u1;
@@ -331,6 +351,7 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_r
         UD<T>* S = ring + K * 2 * RA;
         S[pe] = UD<T>{P0.u0, P0.D0};
         S[RA + pe] = UD<T>{P0.u1, P0.D1};
+        if (NORM) step_in = s >= xa && s < xb;
         lds_barrier();
         load(s + 3, Pp3);   // into the registers of plane s-5
         if (PROLONG) {
@@ -401,6 +422,10 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_r
         step(I6(), s + 6, R6, R7, R0, R1, R2, R3, R5);
         if (s + 7 > s_end) break;
         step(I7(), s + 7, R7, R0, R1, R2, R3, R4, R6);
+    }
+    if constexpr (NORM) {
+        const double b = block_sum(nacc);
+        if (tid == 0) a.partial[blockIdx.x] = b;
     }
 }
 
