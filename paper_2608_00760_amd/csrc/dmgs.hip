@@ -19,6 +19,7 @@
 #include "kernels_basic.hpp"
 #include "kernels_stream.hpp"
 #include "kernels_sweep2.hpp"
+#include "kernels_deriv.hpp"
 #include "kernels_block.hpp"
 #include "kernels_small.hpp"
 #include "kernels_2d.hpp"
@@ -1883,13 +1884,30 @@ namespace {
 // Grid of the column-march derivative kernels: blocks of kBlock threads over
 // a plane times chunks of planes, at most about 2048 blocks (eight per CU on
 // 256 CUs, one round); each chunk re-reads one plane at either end.
-dim3 col_grid(int N, int* chunk) {
+// Grid of the derivative kernels: (tile, chunk) blocks of kDerThreads; the
+// chunk count is chosen so that the blocks, one per CU, fill the last round
+// of CUs best, net of the two extra planes each chunk reads.  Chunks are
+// whole multiples of the kernels' unrolled march.
+dim3 der_grid(dmgs_plan P, int N, int* chunk) {
     const int n = N + 1;
-    const int64_t bx = ((int64_t)n * n + kBlock - 1) / kBlock;
-    int nch = (int)std::min<int64_t>(n, std::max<int64_t>(1, 2048 / bx));
-    *chunk = (n + nch - 1) / nch;
-    nch = (n + *chunk - 1) / *chunk;
-    return dim3((unsigned)bx, (unsigned)nch);
+    const int tiles = ((n + kDerTY - 1) / kDerTY) * ((n + kDerTZ - 1) / kDerTZ);
+    int best_c = 1;
+    double best = 0.0;
+    auto chunk_of = [&](int c) { return ((n + c - 1) / c + kDerRing - 1) / kDerRing * kDerRing; };
+    const int64_t pb = (int64_t)n * n * 8;
+    for (int c = 1; c <= 64 && c <= n; c++) {
+        const int ch = chunk_of(c);
+        if ((int64_t)(ch + 3) * pb >= (int64_t)kOob) continue;   // the kernels' 32-bit span of planes
+        const int nb = tiles * ((n + ch - 1) / ch);
+        const int rounds = (nb + P->ncu - 1) / P->ncu;
+        const double v = (double)nb / ((double)rounds * P->ncu) * ch / (ch + 2.0);
+        if (v > best + 1e-9) {
+            best = v;
+            best_c = c;
+        }
+    }
+    *chunk = chunk_of(best_c);
+    return dim3((unsigned)tiles, (unsigned)((n + *chunk - 1) / *chunk));
 }
 
 // tangent right-hand side q' - A' rho of the push-forward (A9)
@@ -1910,11 +1928,13 @@ int tangent_rhs(dmgs_plan P, const double* rho, const double* dq, const double* 
         return DMGS_OK;
     }
     int chunk = 1;
-    const dim3 g = col_grid(l0.N, &chunk);
+    const dim3 g = der_grid(P, l0.N, &chunk);
+    auto launch = [&](auto harm) {
+        hipLaunchKernelGGL(k_tangent_rhs_col<decltype(harm)::value>, g, dim3(kDerThreads), 0, st, rho, dq, dlogD,
+                           dlogmua, (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, out, chunk);
+    };
     TIMED(P, 0, DMGS_K_GRAD, 56.0 * l0.nv, st,
-          hipLaunchKernelGGL(k_tangent_rhs_col, g, dim3(kBlock), 0, st, rho, dq, dlogD, dlogmua,
-                             (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, harmonic(P), out,
-                             chunk));
+          (harmonic(P) ? launch(std::true_type()) : launch(std::false_type())));
     return DMGS_OK;
 }
 
@@ -1942,11 +1962,18 @@ int coef_grads(dmgs_plan P, const double* rho, const double* lam, double* gD, do
         return DMGS_OK;
     }
     int chunk = 1;
-    const dim3 g = col_grid(l0.N, &chunk);
+    const dim3 g = der_grid(P, l0.N, &chunk);
     const double bytes = (gD ? 40.0 : 24.0) + (gmu ? 8.0 : 0.0) + (d && gmu ? 16.0 : 0.0);
+    const bool data = d && w && gmu;
+    auto launch = [&](auto harm, auto dat) {
+        hipLaunchKernelGGL((k_coef_grads_col<decltype(harm)::value, decltype(dat)::value>), g, dim3(kDerThreads), 0, st,
+                           rho, lam, (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, gD, gmu, d, w,
+                           chunk);
+    };
+    using T_ = std::true_type;
+    using F_ = std::false_type;
     TIMED(P, 0, DMGS_K_GRAD, bytes * l0.nv, st,
-          hipLaunchKernelGGL(k_coef_grads_col, g, dim3(kBlock), 0, st, rho, lam, (const double*)l0.D64,
-                             (const double*)l0.mu64, l0.N, l0.inv_h2, harmonic(P), gD, gmu, d, w, chunk));
+          (harmonic(P) ? (data ? launch(T_(), T_()) : launch(T_(), F_())) : (data ? launch(F_(), T_()) : launch(F_(), F_()))));
     return DMGS_OK;
 }
 

@@ -399,157 +399,4 @@ __global__ void k_add_correction(double* __restrict__ u, const float* __restrict
         u[v] += (double)e[v];
 }
 
-// ---------------------------------------------------------------------------
-// Derivatives with respect to the coefficients (adjoint-state derivatives of
-// the discrete solution).
-
-// Column march of the derivative kernels: thread p = y (N+1) + z of a plane
-// walks the planes [x0, x1) of chunk c and keeps its own values at x - 1, x
-// and x + 1 in registers, so each field is read from memory about once
-// (plus one plane at each end of a chunk).  In-plane neighbours p +- 1 and
-// p +- (N+1) are loaded: the block itself or blocks running beside it load
-// them at about the same time.  The flattened (plane block, chunk) index is
-// remapped so that each XCD runs a contiguous range of it (whole chunks of
-// consecutive rows), which keeps those neighbours in one L2.
-struct ColMarch {
-    int n, y, z, x0, x1;
-    int64_t sx, p;
-};
-
-__device__ __forceinline__ bool col_march(int N, int chunk, ColMarch& c) {
-    const int nb = (int)(gridDim.x * gridDim.y);
-    const int L = xcd_remap((int)(blockIdx.y * gridDim.x + blockIdx.x), nb);
-    const int bx = L % (int)gridDim.x, by = L / (int)gridDim.x;
-    c.n = N + 1;
-    c.sx = (int64_t)c.n * c.n;
-    c.p = (int64_t)bx * blockDim.x + threadIdx.x;
-    c.x0 = by * chunk;
-    if (c.p >= c.sx || c.x0 >= c.n) return false;
-    c.y = (int)(c.p / c.n);
-    c.z = (int)(c.p % c.n);
-    c.x1 = min(c.n, c.x0 + chunk);
-    return true;
-}
-
-// d D_f along the tangent: D_f = (D_a + D_b)/2 or 2 D_a D_b / (D_a + D_b),
-// with dD = D dlogD at both ends
-__device__ __forceinline__ double dface(double Da, double dDa, double Db, double dDb, int harmonic) {
-    if (harmonic) {
-        const double sum = Da + Db;
-        return 2.0 * (Db * Db * dDa + Da * Da * dDb) / (sum * sum);
-    }
-    return 0.5 * (dDa + dDb);
-}
-
-// rhs = dq - (dA) rho on interior vertices (0 on the boundary), where
-// (dA rho)_i = sum_j dD_f,ij/h^2 (rho_i - rho_j) + mua_i dlogmua_i rho_i and
-// dD_f is the derivative of the face mean along dlogD.  Null tangents are 0.
-// Neighbours in the order +x, -x, +y, -y, +z, -z.
-__global__ void k_tangent_rhs_col(const double* __restrict__ rho, const double* __restrict__ dq,
-                                  const double* __restrict__ dlogD, const double* __restrict__ dlogmu,
-                                  const double* __restrict__ D, const double* __restrict__ mu, int N, double inv_h2,
-                                  int harmonic, double* __restrict__ rhs, int chunk) {
-    ColMarch c;
-    if (!col_march(N, chunk, c)) return;
-    const int n = c.n;
-    const bool yz = c.y > 0 && c.y < N && c.z > 0 && c.z < N;
-    auto dD_at = [&](int64_t j) { return dlogD ? D[j] * dlogD[j] : 0.0; };
-    double rm = 0.0, Dm = 0.0, dDm = 0.0;
-    if (c.x0 > 0 && yz) {
-        const int64_t j = (c.x0 - 1) * c.sx + c.p;
-        rm = rho[j]; Dm = D[j]; dDm = dD_at(j);
-    }
-    const int64_t i0 = c.x0 * c.sx + c.p;
-    double rc = rho[i0], Dc = D[i0], dDc = dD_at(i0);
-    for (int x = c.x0; x < c.x1; x++) {
-        const int64_t i = x * c.sx + c.p;
-        double rp = 0.0, Dp = 0.0, dDp = 0.0;
-        if (x < N && yz) {
-            rp = rho[i + c.sx]; Dp = D[i + c.sx]; dDp = dD_at(i + c.sx);
-        }
-        double out = 0.0;
-        if (yz && x > 0 && x < N) {
-            double acc = dlogmu ? mu[i] * dlogmu[i] * rc : 0.0;
-            if (dlogD) {
-                auto nb = [&](double Dj, double dDj, double rj) { acc += dface(Dc, dDc, Dj, dDj, harmonic) * inv_h2 * (rc - rj); };
-                nb(Dp, dDp, rp);
-                nb(Dm, dDm, rm);
-                nb(D[i + n], dD_at(i + n), rho[i + n]);
-                nb(D[i - n], dD_at(i - n), rho[i - n]);
-                nb(D[i + 1], dD_at(i + 1), rho[i + 1]);
-                nb(D[i - 1], dD_at(i - 1), rho[i - 1]);
-            }
-            out = (dq ? dq[i] : 0.0) - acc;
-        }
-        rhs[i] = out;
-        rm = rc; Dm = Dc; dDm = dDc;
-        rc = rp; Dc = Dp; dDc = dDp;
-    }
-}
-
-// Coefficient gradients from the adjoint state lam = qbar:
-//   logmua_bar_i = -mua_i lam_i rho_i (interior, 0 on the boundary)
-//   logD_bar_v   = -sum_{faces (v,j), v or j interior} dD_f/dlogD_v (lam_v - lam_j)(rho_v - rho_j) / h^2
-// with lam = 0 on boundary vertices.  With data d and weights w (the
-// likelihood's gradient) logmua_bar also takes the direct term of L_e =
-// mua rho: w_i (mua_i rho_i - d_i) mua_i rho_i.  Neighbours in the order
-// +x, -x, +y, -y, +z, -z.
-__global__ void k_coef_grads_col(const double* __restrict__ rho, const double* __restrict__ lam,
-                                 const double* __restrict__ D, const double* __restrict__ mu, int N, double inv_h2,
-                                 int harmonic, double* __restrict__ gD, double* __restrict__ gmu,
-                                 const double* __restrict__ d, const double* __restrict__ w, int chunk) {
-    ColMarch c;
-    if (!col_march(N, chunk, c)) return;
-    const int n = c.n;
-    const bool yz = c.y > 0 && c.y < N && c.z > 0 && c.z < N;
-    auto lam_at = [&](int x, int y, int z, int64_t j) { return is_interior(N, x, y, z) ? lam[j] : 0.0; };
-    double lm = 0.0, rm = 0.0, Dm = 0.0;
-    if (c.x0 > 0) {
-        const int64_t j = (c.x0 - 1) * c.sx + c.p;
-        lm = lam_at(c.x0 - 1, c.y, c.z, j); rm = rho[j]; Dm = D[j];
-    }
-    const int64_t i0 = c.x0 * c.sx + c.p;
-    double lc = lam_at(c.x0, c.y, c.z, i0), rc = rho[i0], Dc = D[i0];
-    for (int x = c.x0; x < c.x1; x++) {
-        const int64_t i = x * c.sx + c.p;
-        double lp = 0.0, rp = 0.0, Dp = 0.0;
-        if (x < N) {
-            lp = lam_at(x + 1, c.y, c.z, i + c.sx); rp = rho[i + c.sx]; Dp = D[i + c.sx];
-        }
-        const bool vin = yz && x > 0 && x < N;
-        if (gmu) {
-            double g = vin ? -mu[i] * lc * rc : 0.0;
-            if (d && vin) {
-                const double Le = mu[i] * rc;
-                g += w[i] * (Le - d[i]) * Le;
-            }
-            gmu[i] = g;
-        }
-        if (gD) {
-            double acc = 0.0;
-            auto nb = [&](bool jin, double lj, double rj, double Dj) {
-                if (!vin && !jin) return;
-                double dcdv;
-                if (harmonic) {
-                    const double sum = Dc + Dj;
-                    dcdv = 2.0 * Dj * Dj * Dc / (sum * sum);
-                } else {
-                    dcdv = 0.5 * Dc;
-                }
-                acc += dcdv * (lc - lj) * (rc - rj);
-            };
-            if (x < N) nb(yz && x + 1 < N, lp, rp, Dp);
-            if (x > 0) nb(yz && x - 1 > 0, lm, rm, Dm);
-            const bool xin = x > 0 && x < N, zin = c.z > 0 && c.z < N, yin = c.y > 0 && c.y < N;
-            if (c.y < N) nb(xin && zin && c.y + 1 < N, xin && zin && c.y + 1 < N ? lam[i + n] : 0.0, rho[i + n], D[i + n]);
-            if (c.y > 0) nb(xin && zin && c.y - 1 > 0, xin && zin && c.y - 1 > 0 ? lam[i - n] : 0.0, rho[i - n], D[i - n]);
-            if (c.z < N) nb(xin && yin && c.z + 1 < N, xin && yin && c.z + 1 < N ? lam[i + 1] : 0.0, rho[i + 1], D[i + 1]);
-            if (c.z > 0) nb(xin && yin && c.z - 1 > 0, xin && yin && c.z - 1 > 0 ? lam[i - 1] : 0.0, rho[i - 1], D[i - 1]);
-            gD[i] = -acc * inv_h2;
-        }
-        lm = lc; rm = rc; Dm = Dc;
-        lc = lp; rc = rp; Dc = Dp;
-    }
-}
-
 }  // namespace dmgs

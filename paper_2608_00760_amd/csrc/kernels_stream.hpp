@@ -48,6 +48,11 @@ template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsr
 template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int off) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
+// ... with a wave-uniform offset `soff` added to the lane's `off` (the range
+// check applies to their sum, so kOob in either reads 0)
+__device__ __forceinline__ double buf_load_s(__amdgpu_buffer_rsrc_t r, int off, int soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
+}
 template <class T> __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, int off);
 template <> __device__ __forceinline__ void buf_store<float>(float v, __amdgpu_buffer_rsrc_t r, int off) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);

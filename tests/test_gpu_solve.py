@@ -241,3 +241,43 @@ def test_fixed_cycles_unequal_smoothing(nu1, nu2):
     lhs = float((drho * dev(c["rhobar"])).sum())
     rhs = float((dev(c["dq"]) * qb).sum() + (dev(c["dlogD"]) * gD).sum() + (dev(c["dlogmua"]) * gmu).sum())
     assert abs(lhs - rhs) <= 1e-12 * float(drho.norm()) * float(np.linalg.norm(c["rhobar"]))
+
+
+@pytest.mark.parametrize("N,face_mean,max_cycles", [(64, "arith", 200), (96, "harmonic", 200), (128, "arith", 4)])
+def test_fp64_norm_from_next_pass_matches_explicit_residual(N, face_mean, max_cycles, monkeypatch):
+    """Float64 tolerance mode takes each iterate's residual norm from the
+    next cycle's first two-sweep pass.  Against the same plan with that pass
+    switched off for float64 levels (DMGS_SWEEP2_FP64=0: one-sweep passes and
+    an explicit residual pass after every cycle): the same number of cycles
+    and the same stopping status (also when max_cycles ends the solve, where
+    the returned iterate is the last complete cycle's).  The two smooth with
+    different kernels, so their iterates differ in the last bits and their
+    residuals near 1e-10 agree to about 1e-5; the check is 1e-3, against
+    which a norm from the wrong iterate or a missing colour (factors of 2 and
+    more) fails.  Each reported residual equals the oracle operator's residual
+    of the returned iterate to 1e-3."""
+    from oracle import ref
+    say("fp64 norm from the next pass N=%d %s max_cycles=%d" % (N, face_mean, max_cycles))
+    c = grf_inputs(N, 7000 + N)
+    H = ref.Hierarchy(c["D"], c["mua"], face_mean=face_mean)
+    res = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("DMGS_SWEEP2_FP64", flag)
+        P = plan_for(c["D"], c["mua"], face_mean=face_mean, max_cycles=max_cycles)
+        rho, fi = P.forward(dev(c["q"]), check=False)
+        (qb, _, _), vi = P.vjp(rho, dev(c["rhobar"]), check=False)
+        res[flag] = (host(rho), fi, host(qb), vi)
+        say("  DMGS_SWEEP2_FP64=%s fwd %d cycles %.3e status %d, adj %d cycles %.3e" % (
+            flag, fi["cycles"], fi["rel_residual"], fi["status"], vi["cycles"], vi["rel_residual"]))
+    (r1, f1, l1, v1), (r0, f0, l0, v0) = res["1"], res["0"]
+    for a, b in ((f1, f0), (v1, v0)):
+        assert a["cycles"] == b["cycles"] and a["status"] == b["status"]
+        assert abs(a["rel_residual"] - b["rel_residual"]) <= 1e-3 * b["rel_residual"]
+    for rho, fi, lam, vi in (res["1"], res["0"]):
+        assert abs(rel_residual(H, rho, c["q"]) - fi["rel_residual"]) <= 1e-3 * fi["rel_residual"]
+        lam_res = np.linalg.norm(c["rhobar"] - H.apply(0, lam)) / np.linalg.norm(c["rhobar"])
+        assert abs(lam_res - vi["rel_residual"]) <= 1e-3 * vi["rel_residual"]
+    if max_cycles == 200:
+        assert f1["status"] == 0 and f1["rel_residual"] <= 1e-10
+    else:
+        assert f1["status"] == 3 and f1["cycles"] == max_cycles
