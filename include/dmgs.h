@@ -181,7 +181,9 @@ size_t dmgs_forward_vjp_workspace_bytes(const dmgs_options *opt);
  *   DMGS_2D_CHUNK (0)           ... rows per chunk of the two-sweep passes (0: from the grid size)
  *   DMGS_2D_SMALL_MAX (32)      ... largest N of the single-workgroup coarse kernel
  *   DMGS_EPI_FUSE (1)           dmgs_likelihood_grad computes its epilogue in the
- *                               forward solve's last refinement step (0: separate pass) */
+ *                               forward solve's last refinement step (0: separate pass)
+ * DMGS_TRACE (0) is not a tuning knob: 1 records residual histories and
+ * kernel times (dmgs_trace_read). */
 int dmgs_plan_create(const dmgs_options *opt, dmgs_plan *out);
 int dmgs_plan_destroy(dmgs_plan plan);
 
@@ -370,6 +372,24 @@ enum dmgs_kernel_class {
     DMGS_K_COUNT = 7
 };
 int dmgs_timing_enable(dmgs_plan plan, int enable);
+
+/* Residual history (tracing aid).  With DMGS_TRACE=1
+ * in the environment when the plan is created, every solve records the
+ * relative residual ||b - A u|| / ||b - A u_0|| of the iterate after each
+ * V-cycle (float64 plans) or refinement step (DMGS_FP32_IN_FP64), and the
+ * plan times every finest-level launch (dmgs_timing_read; as
+ * dmgs_timing_enable(plan, 1)).  In tolerance mode the history costs
+ * nothing extra; in fixed-cycle mode it adds one residual pass and one host
+ * wait per cycle.  order 0: the last forward or push-forward solve
+ * (dmgs_likelihood_grad: its forward solve); 1: the last pull-back.  Writes
+ * up to cap entries (cycles or steps applied so far, V-cycles applied so
+ * far, relative residual) to steps, vcycles, rel (host arrays) and the
+ * number of entries to *count.  Float64 tolerance mode records each
+ * iterate's residual when the next cycle's first pass has formed it, so the
+ * last entry is the returned iterate's.  Errors: DMGS_ERR_INVALID (NULL,
+ * order not 0 or 1, negative cap, tracing off). */
+int dmgs_trace_read(dmgs_plan plan, int32_t order, int32_t cap, int32_t *steps, int32_t *vcycles, double *rel,
+                    int32_t *count);
 int dmgs_timing_read(dmgs_plan plan, int kernel_class, int64_t *launches, double *total_ms,
                      double *algorithmic_bytes);
 

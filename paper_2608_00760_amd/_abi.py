@@ -69,6 +69,8 @@ SIGNATURES = {
     "dmgs_debug_stream_copy": (_i, [_vp, _vp, C.c_size_t, _vp]),
     "dmgs_timing_enable": (_i, [_vp, _i]),
     "dmgs_timing_read": (_i, [_vp, _i, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "dmgs_trace_read": (_i, [_vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                             C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
 }
 
 KERNEL_CLASSES = ["smooth", "defect_restrict", "prolong", "residual", "update", "coef", "grad"]

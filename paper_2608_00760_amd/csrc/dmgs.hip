@@ -1234,6 +1234,11 @@ int resid2(dmgs_plan P, const double* x, const double* b, int slot, hipStream_t 
 }
 
 // solve() for two-dimensional plans (same modes, schedule record and replay).
+// DMGS_TRACE: one point of a solve's residual history
+void trace_point(dmgs_plan P, int order, int steps, int vcycles, double rel) {
+    if (P->cfg_trace) P->trace[order].push_back({steps, vcycles, rel});
+}
+
 template <bool HARM>
 int solve2d(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_info* info, hipStream_t st,
             const std::vector<int>* replay, bool record) {
@@ -1259,17 +1264,26 @@ int solve2d(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_
             r0 = std::sqrt(P->hnorm[0]);
             if (!std::isfinite(r0)) { set_error("non-finite right-hand side"); status = DMGS_ERR_NONFINITE; break; }
             if (r0 == 0.0) break;
+        } else if (P->cfg_trace) {
+            TRY(read_norms(P, st));
+            r0 = std::sqrt(P->hnorm[0]);
         }
         for (cycles = 1; !(fixed && nfix == 0); cycles++) {
             TRY(vcycle2<HARM>(P, 0, &cur, &oth, b, order, false, st));
             sched.push_back(1);
             if (fixed) {
+                if (P->cfg_trace) {
+                    TRY(resid2<HARM>(P, cur, b, 1, st));
+                    TRY(read_norms(P, st));
+                    trace_point(P, order, cycles, cycles, std::sqrt(P->hnorm[1]) / (r0 > 0.0 ? r0 : 1.0));
+                }
                 if (cycles == nfix) break;
                 continue;
             }
             TRY(resid2<HARM>(P, cur, b, 1, st));
             TRY(read_norms(P, st));
             rel = std::sqrt(P->hnorm[1]) / r0;
+            trace_point(P, order, cycles, cycles, rel);
             if (!std::isfinite(rel)) { set_error("non-finite residual after %d cycles", cycles); status = DMGS_ERR_NONFINITE; break; }
             if (rel <= o.rtol) break;
             if (cycles >= o.max_cycles) { set_error("not converged after %d cycles (rel %.3e)", cycles, rel); status = DMGS_ERR_NOT_CONVERGED; break; }
@@ -1397,6 +1411,9 @@ int solve_grid(dmgs_plan P, const double* b, double* x, double bc, int order, dm
             set_error("non-finite right-hand side");
             status = DMGS_ERR_NONFINITE;
         }
+    } else if (P->cfg_trace) {
+        TRY(read_norms(P, st));
+        r0 = std::sqrt(P->hnorm[0]);
     }
     // A requested likelihood epilogue rides on the last half-sweep of the
     // cycle expected to be the last (in tolerance mode: the one the
@@ -1412,6 +1429,11 @@ int solve_grid(dmgs_plan P, const double* b, double* x, double bc, int order, dm
             TRY(vcycle_grid(P, 0, x, b, order, st, want_epi && (fixed ? cycles == nfix : epi_next), &done));
             P->epi_fused = done;
             if (fixed) {
+                if (P->cfg_trace) {
+                    TRY(resid_grid(P, x, b, 1, st));
+                    TRY(read_norms(P, st));
+                    trace_point(P, order, cycles, cycles, std::sqrt(P->hnorm[1]) / (r0 > 0.0 ? r0 : 1.0));
+                }
                 if (cycles == nfix) break;
                 continue;
             }
@@ -1419,6 +1441,7 @@ int solve_grid(dmgs_plan P, const double* b, double* x, double bc, int order, dm
             TRY(read_norms(P, st));
             rel_prev = cycles == 1 ? 1.0 : rel;
             rel = std::sqrt(P->hnorm[1]) / r0;
+            trace_point(P, order, cycles, cycles, rel);
             epi_next = rel < rel_prev && rel * (rel / rel_prev) <= 4.0 * o.rtol;
             if (!std::isfinite(rel)) { set_error("non-finite residual after %d cycles", cycles); status = DMGS_ERR_NONFINITE; break; }
             if (rel <= o.rtol) break;
@@ -1449,6 +1472,7 @@ int solve_grid(dmgs_plan P, const double* b, double* x, double bc, int order, dm
 
 int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_info* info, hipStream_t st,
           const std::vector<int>* replay = nullptr, bool record = false) {
+    P->trace[order].clear();
     if (P->grid) return solve_grid(P, b, x, bc, order, info, st, replay, record);
     if (is2d(P))
         return harmonic(P) ? solve2d<true>(P, b, x, bc, order, info, st, replay, record)
@@ -1481,6 +1505,9 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
             r0 = std::sqrt(P->hnorm[0]);
             if (!std::isfinite(r0)) { set_error("non-finite right-hand side"); status = DMGS_ERR_NONFINITE; goto done; }
             if (r0 == 0.0) goto done;
+        } else if (P->cfg_trace) {
+            TRY(read_norms(P, st));
+            r0 = std::sqrt(P->hnorm[0]);
         }
         // A requested likelihood epilogue rides on the residual pass after
         // the cycle expected to be the last (the contraction of the last
@@ -1523,6 +1550,7 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
                 TRY(read_norms(P, st));
                 rel_prev = cycles == 2 ? 1.0 : rel;
                 rel = std::sqrt(P->hnorm[1]) / r0;
+                trace_point(P, order, cycles - 1, cycles - 1, rel);
                 bool stop = false;
                 if (!std::isfinite(rel)) { set_error("non-finite residual after %d cycles", cycles - 1); status = DMGS_ERR_NONFINITE; stop = true; }
                 else if (rel <= o.rtol) stop = true;
@@ -1541,6 +1569,11 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
             TRY(vcycle<double>(P, 0, &cur, &oth, b, order, false, st));
             sched.push_back(1);
             if (fixed) {
+                if (P->cfg_trace) {
+                    TRY(ir_step(P, cur, nullptr, nullptr, b, nullptr, 1, st));
+                    TRY(read_norms(P, st));
+                    trace_point(P, order, cycles, cycles, std::sqrt(P->hnorm[1]) / (r0 > 0.0 ? r0 : 1.0));
+                }
                 if (cycles == nfix) break;
                 continue;
             }
@@ -1551,6 +1584,7 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
             TRY(read_norms(P, st));
             rel_prev = cycles == 1 ? 1.0 : rel;
             rel = std::sqrt(P->hnorm[1]) / r0;
+            trace_point(P, order, cycles, cycles, rel);
             if (!std::isfinite(rel)) { set_error("non-finite residual after %d cycles", cycles); status = DMGS_ERR_NONFINITE; break; }
             if (rel <= o.rtol) break;
             if (cycles >= o.max_cycles) { set_error("not converged after %d cycles (rel %.3e)", cycles, rel); status = DMGS_ERR_NOT_CONVERGED; break; }
@@ -1569,6 +1603,11 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
         double* xo = P->xalt64;
         TRY(set_boundary<double>(xo, l0.N, bc, st));
         TRY(ir_step(P, xc, nullptr, nullptr, b, l0.q32, 0, st, x_zero));
+        double r0t = 0.0;   // DMGS_TRACE in fixed mode: the initial residual norm
+        if (fixed && P->cfg_trace) {
+            TRY(read_norms(P, st));
+            r0t = std::sqrt(P->hnorm[0]);
+        }
         // While the host waits for a step's residual norm, the first
         // smoothing pass of the next step is already enqueued when the
         // residual is not expected to meet the tolerance yet.  The pass
@@ -1608,6 +1647,7 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
                     rel = 1.0;
                 } else {
                     rel = std::sqrt(P->hnorm[1]) / r0;
+                    trace_point(P, order, cycles, vcycles, rel);
                     if (!std::isfinite(rel)) { set_error("non-finite residual after %d steps", cycles); status = DMGS_ERR_NONFINITE; break; }
                     if (rel <= o.rtol) break;
                     rate = rel < rel1 ? std::pow(rel / rel1, 1.0 / inner) : 0.0;
@@ -1642,6 +1682,10 @@ int solve(dmgs_plan P, const double* b, double* x, double bc, int order, dmgs_in
             } else {
                 TRY(ir_step(P, xc, e, xo, b, l0.q32, 1, st, x_zero && cycles == 0, epi));
                 std::swap(xc, xo);
+            }
+            if (fixed && P->cfg_trace) {
+                TRY(read_norms(P, st));
+                trace_point(P, order, cycles + 1, vcycles, std::sqrt(P->hnorm[1]) / (r0t > 0.0 ? r0t : 1.0));
             }
         }
         P->ir_steps[order] = cycles;
@@ -2266,7 +2310,13 @@ int dmgs_plan_create(const dmgs_options* o, dmgs_plan* out) {
     TRY(check_options(o));
     dmgs_plan P = new (std::nothrow) dmgs_plan_s();
     if (!P) { set_error("host allocation failed"); return DMGS_ERR_OOM; }
-    const int st = plan_init(P, o, nullptr);
+    int st = plan_init(P, o, nullptr);
+    if (st == DMGS_OK) {
+        // tracing aid: residual history of every solve (dmgs_trace_read) and
+        // per-class kernel timing of every finest-level launch
+        if (const char* e = std::getenv("DMGS_TRACE")) P->cfg_trace = std::atoi(e) != 0;
+        if (P->cfg_trace) st = dmgs_timing_enable(P, 1);
+    }
     if (st != DMGS_OK) {
         free_plan(P);
         return st;
@@ -2368,6 +2418,7 @@ int make_twin(dmgs_plan P) {
     T->cfg_2d_sweep2_min = P->cfg_2d_sweep2_min;
     T->cfg_sweep2_fp64 = P->cfg_sweep2_fp64;
     T->cfg_2d_block_min = P->cfg_2d_block_min;
+    T->cfg_trace = P->cfg_trace;
     T->cfg_2d_defect = P->cfg_2d_defect;
     T->ncu = P->ncu;
     T->small2 = P->small2;
@@ -2477,6 +2528,7 @@ int dmgs_forward_vjp(dmgs_plan P, const double* q, const double* rhobar, double*
         set_error("event join failed");
         return DMGS_ERR_HIP;
     }
+    P->trace[1] = T->trace[1];   // the pull-back ran on the twin
     const bool ok_f = sf == DMGS_OK || sf == DMGS_ERR_NOT_CONVERGED;
     const bool ok_a = sa == DMGS_OK || sa == DMGS_ERR_NOT_CONVERGED;
     if (ok_f && ok_a && (logD_bar || logmua_bar)) {
@@ -2983,6 +3035,26 @@ int dmgs_timing_enable(dmgs_plan P, int enable) {
         P->t_seen[c] = 0;
         P->t_ms[c] = 0.0;
         P->t_bytes[c] = 0.0;
+    }
+    return DMGS_OK;
+}
+
+int dmgs_trace_read(dmgs_plan P, int32_t order, int32_t cap, int32_t* steps, int32_t* vcycles, double* rel,
+                    int32_t* count) {
+    if (!P || !count || (order != 0 && order != 1) || cap < 0 || (cap > 0 && (!steps || !vcycles || !rel))) {
+        set_error("bad plan, order or buffers");
+        return DMGS_ERR_INVALID;
+    }
+    if (!P->cfg_trace) {
+        set_error("tracing is off (set DMGS_TRACE=1 before creating the plan)");
+        return DMGS_ERR_INVALID;
+    }
+    const auto& tr = P->trace[order];
+    *count = (int32_t)tr.size();
+    for (int32_t i = 0; i < cap && i < (int32_t)tr.size(); i++) {
+        steps[i] = tr[i].steps;
+        vcycles[i] = tr[i].vcycles;
+        rel[i] = tr[i].rel;
     }
     return DMGS_OK;
 }

@@ -84,6 +84,7 @@ struct dmgs_plan_s {
     int cfg_2d_block_min = 64;     // two-dimensional plans: smallest N of the LDS block passes
     bool cfg_2d_defect = true;     // ... the last pre-smoothing pass writes the defect
     bool cfg_epi_fuse = true;      // the likelihood epilogue rides on the last refinement step
+    bool cfg_trace = false;        // DMGS_TRACE: record each solve's residual history
     bool bc_zero = true;           // the current solve's boundary value is 0
     int ncu = 256;                 // compute units of the plan's device
     int cfg_2d_chunk = 0;          // ... rows per chunk (0: chosen from the grid size)
@@ -100,6 +101,11 @@ struct dmgs_plan_s {
     int tmark = 0;                 // timer slots recorded before ev_norm
     int ir_steps[2] = {0, 0};      // refinement steps of the last solve, by cycle order
     std::vector<int> fwd_schedule; // V-cycle schedule of the last tolerance-mode forward solve
+    struct TracePoint {
+        int32_t steps, vcycles;    // cycles (refinement steps) and V-cycles applied so far
+        double rel;                // relative residual of the iterate then
+    };
+    std::vector<TracePoint> trace[2];   // residual history of the last solve of each cycle order
     // likelihood epilogue requested from the next forward solve (data, weights,
     // cotangent output); epi_fused reports whether its last refinement step
     // computed it for the returned iterate

@@ -287,6 +287,17 @@ class Plan:
         scaled to all launches)."""
         self._call(_abi.lib().dmgs_timing_enable, "dmgs_timing_enable", max(1, int(stride)) if enable else 0)
 
+    def trace(self, order=0):
+        """Residual history of the last solve of this cycle order (0: forward
+        or push-forward, 1: pull-back) as [(cycles, vcycles, rel_residual)];
+        the plan must have been created with DMGS_TRACE=1."""
+        count = C.c_int32(0)
+        self._call(_abi.lib().dmgs_trace_read, "dmgs_trace_read", int(order), 0, None, None, None, C.byref(count))
+        n = count.value
+        steps, vc, rel = (C.c_int32 * max(n, 1))(), (C.c_int32 * max(n, 1))(), (C.c_double * max(n, 1))()
+        self._call(_abi.lib().dmgs_trace_read, "dmgs_trace_read", int(order), n, steps, vc, rel, C.byref(count))
+        return [(steps[i], vc[i], rel[i]) for i in range(n)]
+
     def timing_read(self):
         """{class: {"launches", "ms", "bytes"}} accumulated since timing was enabled."""
         out = {}
