@@ -337,6 +337,62 @@ def paper_sweep(args):
             del logD, logmu, q, w, dq, dd, dm, rho, qbar, drho, gD, gmu
 
 
+def graph_replay(args):
+    """The fixed-cycle forward solve (15 V-cycles, NULL info: no host waits)
+    launched eagerly and replayed from a captured HIP graph, on the same
+    stream; median of --sweep-reps calls each, one JSON line per case."""
+    import ctypes as C
+    import torch
+    from paper_2608_00760_amd import _abi, synth
+    from paper_2608_00760_amd.solver import Options, Plan
+    lib = _abi.lib()
+    dev = torch.device("cuda:0")
+    cases = [(3, 96, "fp64"), (3, 96, "fp32-in-fp64"), (3, 128, "fp64"), (2, 768, "fp64"), (2, 1024, "fp64")]
+    for nd, N, prec in cases:
+        g = torch.Generator(device=dev)
+        g.manual_seed(4000 + N)
+        shape = (N + 1,) * nd
+        logD = synth.grf_torch(N, g, dev, ndim=nd).clamp_(-math.log(100.0), math.log(100.0))
+        logmua = math.log(0.05) + synth.grf_torch(N, g, dev, ndim=nd)
+        q = synth.zero_boundary_torch(torch.randn(shape, generator=g, device=dev, dtype=torch.float64))
+        rho_e, rho_g = torch.empty_like(q), torch.empty_like(q)
+        P = Plan(Options(N, precision=prec, fixed_cycles=15, ir_inner_cycles=1, ir_adaptive=False, ndim=nd))
+        P.set_log_coefficients(logD, logmua)
+        s = torch.cuda.Stream()
+
+        def call(out):
+            st = lib.dmgs_forward(P._h, C.c_void_p(q.data_ptr()), C.c_void_p(out.data_ptr()), None,
+                                  C.c_void_p(s.cuda_stream))
+            if st != 0:
+                raise RuntimeError("dmgs_forward: %s" % lib.dmgs_last_error().decode())
+
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            call(rho_e)
+            s.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=s):
+                call(rho_g)
+            graph.replay()
+            s.synchronize()
+            bitwise = bool(torch.equal(rho_e, rho_g))
+            times = {"eager": [], "graph": []}
+            for _ in range(args.sweep_reps):
+                for kind in ("eager", "graph"):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record(s)
+                    call(rho_e) if kind == "eager" else graph.replay()
+                    b.record(s)
+                    s.synchronize()
+                    times[kind].append(a.elapsed_time(b))
+        med = {k: sorted(v)[len(v) // 2] for k, v in times.items()}
+        print(json.dumps({"graph_replay": "fixed 15 V-cycles, forward", "ndim": nd, "N": N, "precision": prec,
+                          "reps": args.sweep_reps, "eager_ms_median": med["eager"], "graph_ms_median": med["graph"],
+                          "replay_bitwise_equal": bitwise}), flush=True)
+        del graph
+        P.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,6 +421,8 @@ def main():
                     help="run the forward solve and the VJP one after the other (default: concurrently)")
     ap.add_argument("--serving-requests", type=int, default=512, help="requests in the serving stream (0: skip)")
     ap.add_argument("--no-512", action="store_true", help="skip the 512^3 autograd forward + VJP record")
+    ap.add_argument("--graph-replay", action="store_true",
+                    help="only time the fixed-cycle forward launched eagerly against its captured HIP graph")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the library's plain streaming copy (256 MiB, 3 times): HBM counter calibration")
     args = ap.parse_args()
@@ -380,6 +438,10 @@ def main():
 
     if args.paper_sweep:
         paper_sweep(args)
+        return
+
+    if args.graph_replay:
+        graph_replay(args)
         return
 
     if args.copy_calibration:

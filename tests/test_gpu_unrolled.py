@@ -76,6 +76,56 @@ def test_central_differences_at_64():
         assert abs(fd - g) <= 1e-6 * abs(g), (which, fd, g)
 
 
+@pytest.mark.parametrize("N", [256, 512])
+def test_paper_mode_at_full_size(N):
+    """The paper's mode, 15 fixed V(2,2)-cycles, at 256^3 and 512^3 (inputs
+    drawn on the device): qbar equals the fixed-cycle pull-back dmgs_vjp to
+    1e-12, and central differences of the fixed-cycle forward map along one
+    random log D and one random log mua direction match <grad, direction> to
+    1e-6 (properties that hold at any size; the oracle pins the map at the
+    small sizes above)."""
+    import math
+    import torch
+    from paper_2608_00760_amd import synth
+    from paper_2608_00760_amd.solver import Options, Plan
+    say("unrolled %d^3, 15 cycles" % N)
+    n = 15
+    d = torch.device("cuda:0")
+    g = torch.Generator(device=d)
+    g.manual_seed(7000 + N)
+    logD = synth.grf_torch(N, g, d).clamp_(-math.log(100.0), math.log(100.0))
+    logmu = math.log(0.05) + synth.grf_torch(N, g, d)
+    q = synth.zero_boundary_torch(torch.randn(logD.shape, generator=g, device=d, dtype=torch.float64))
+    w = synth.zero_boundary_torch(torch.randn(logD.shape, generator=g, device=d, dtype=torch.float64))
+
+    def plan(lD, lm):
+        P = Plan(Options(N, fixed_cycles=n))
+        P.set_log_coefficients(lD, lm)
+        return P
+    P = plan(logD, logmu)
+    (rho, (qb, gD, gmu)), _ = P.vjp_unrolled(q, w)
+    (qb2, _, _), _ = P.vjp(rho, w)
+    torch.cuda.synchronize()
+    err = float((qb - qb2).abs().max() / qb2.abs().max())
+    say("  qbar vs dmgs_vjp %.1e" % err)
+    assert err <= 1e-12
+    P.close()
+    eps = 1e-5
+    for which in ("logD", "logmua"):
+        v = torch.randn(logD.shape, generator=g, device=d, dtype=torch.float64)
+        vals = []
+        for sgn in (1.0, -1.0):
+            Pe = plan(logD + sgn * eps * v if which == "logD" else logD,
+                      logmu + sgn * eps * v if which == "logmua" else logmu)
+            r, _ = Pe.forward(q)
+            vals.append(float((r * w).sum()))
+            Pe.close()
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        gr = float(((gD if which == "logD" else gmu) * v).sum())
+        say("  %s fd %.10e grad %.10e" % (which, fd, gr))
+        assert abs(fd - gr) <= 1e-6 * abs(gr), (which, fd, gr)
+
+
 def test_rejects_other_plans():
     from paper_2608_00760_amd import _abi
     say("unrolled rejects")
