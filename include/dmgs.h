@@ -166,7 +166,7 @@ size_t dmgs_forward_vjp_workspace_bytes(const dmgs_options *opt);
  * change no option's meaning, and every choice they allow computes the same
  * operators (the tests force several of them to cover every kernel on every
  * level).  Unset, the tuned defaults apply:
- *   DMGS_SWEEP2_MIN (64)        smallest N of the two-sweep streaming passes
+ *   DMGS_SWEEP2_MIN (64 / 16)   smallest N of the two-sweep streaming passes (float32 / float64 plans)
  *   DMGS_SWEEP2_WGS (256)       target workgroups of a finest-level two-sweep pass
  *   DMGS_SWEEP2_WGS_COARSE      ... below the finest level (half of the above)
  *   DMGS_SWEEP2_DEFECT (2)      pre-smoothing pass writes the defect: 0 never, 1 from a zero iterate, 2 always

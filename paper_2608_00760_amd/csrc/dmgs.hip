@@ -2280,7 +2280,10 @@ int plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
     if (const char* e = std::getenv("DMGS_DR_WGS")) P->cfg_dr_wgs = std::max(16, std::atoi(e));
     if (const char* e = std::getenv("DMGS_SWEEP2_DEFECT")) P->cfg_defect = std::min(2, std::max(0, std::atoi(e)));
     if (const char* e = std::getenv("DMGS_BLOCK_MAX")) P->cfg_block_max = std::atoi(e);
-    P->cfg_sweep2_min = 64;
+    // float64 plans have no block passes: their two-sweep passes reach down
+    // to the levels the small-level kernel leaves (one launch per phase
+    // instead of two)
+    P->cfg_sweep2_min = is_ir(P) ? 64 : 16;
     P->cfg_sweep2_wgs = 256;
     if (const char* e = std::getenv("DMGS_SWEEP2_MIN")) P->cfg_sweep2_min = std::max(16, std::atoi(e));
     if (const char* e = std::getenv("DMGS_SWEEP2_WGS")) P->cfg_sweep2_wgs = std::max(16, std::atoi(e));

@@ -81,12 +81,20 @@ def test_operator_apply(N):
         assert rel_max(host(P.debug_apply(k, dev(u))), H.apply(k, u)) <= 1e-13
 
 
+# Float64 pass variants: the plan's default (two-sweep passes from N = 16)
+# and one-sweep streaming passes on every level.
+FP64_VARIANTS = {"default": {}, "one_sweep": {"DMGS_SWEEP2_MIN": "100000"}}
+
+
 @pytest.mark.parametrize("N", SIZES)
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("face_mean", ["arith", "harmonic"])
-def test_pre_and_post_passes_fp64(N, order, face_mean):
+@pytest.mark.parametrize("variant", list(FP64_VARIANTS))
+def test_pre_and_post_passes_fp64(N, order, face_mean, variant, monkeypatch):
     from paper_2608_00760_amd import synth
-    say("passes fp64 N=%d order=%d %s" % (N, order, face_mean))
+    say("passes fp64 N=%d order=%d %s %s" % (N, order, face_mean, variant))
+    for key, val in FP64_VARIANTS[variant].items():
+        monkeypatch.setenv(key, val)
     P, H = make(N, 30 + N, face_mean=face_mean)
     for k in range(P.levels - 1):
         Nk = H.Ns[k]
