@@ -182,6 +182,12 @@ size_t dmgs_forward_vjp_workspace_bytes(const dmgs_options *opt);
  *   DMGS_2D_SMALL_MAX (32)      ... largest N of the single-workgroup coarse kernel
  *   DMGS_EPI_FUSE (1)           dmgs_likelihood_grad computes its epilogue in the
  *                               forward solve's last refinement step (0: separate pass)
+ *   DMGS_PAD (1)                refinement plans pad the rows of the finest level's
+ *                               float32 arrays to a multiple of four elements when
+ *                               every pass there takes a pitch (even smoothing
+ *                               counts, red-black smoothing, N above the block
+ *                               passes' range); 0: dense rows.  The footprint
+ *                               (dmgs_workspace_bytes) counts the padding.
  * DMGS_TRACE (0) is not a tuning knob: 1 records residual histories and
  * kernel times (dmgs_trace_read). */
 int dmgs_plan_create(const dmgs_options *opt, dmgs_plan *out);
@@ -400,7 +406,10 @@ int dmgs_timing_read(dmgs_plan plan, int kernel_class, int64_t *launches, double
  * float32 instantiation used inside iterative refinement (arrays are then
  * float32, coefficients the plan's float32 copies).  order 0 = red half-sweep
  * first (forward), 1 = black first (transposed cycle).  Used by the parity
- * tests; not needed to solve.
+ * tests; not needed to solve.  When the float32 arrays of level k have padded
+ * rows (DMGS_PAD), dmgs_debug_pre and dmgs_debug_post copy the caller's
+ * arrays into the level's own work buffers, run the pass there and copy the
+ * result out (the work buffers' contents are overwritten).
  * ------------------------------------------------------------------------- */
 
 /* out = A_k u on interior vertices, 0 on the boundary. */

@@ -187,6 +187,51 @@ Sizes sizes_for(const dmgs_options* o) {
     return s;
 }
 
+// Tuning knobs of cubic plans that decide which kernels run on the finest
+// level (environment variables; plan_init keeps them in the plan).
+struct Knobs {
+    int fuse_min, sweep2_min, block_max, defect;
+    bool pad;
+};
+
+Knobs read_knobs(const dmgs_options* o) {
+    const bool ir = o->precision == DMGS_FP32_IN_FP64;
+    // float64 plans have no block passes: their two-sweep passes reach down
+    // to the levels the small-level kernel leaves (one launch per phase
+    // instead of two)
+    Knobs k{ir ? 32 : 16, ir ? 64 : 16, 64, 2, true};
+    if (const char* e = std::getenv("DMGS_FUSE_MIN")) k.fuse_min = std::max(8, std::atoi(e));
+    if (const char* e = std::getenv("DMGS_SWEEP2_MIN")) k.sweep2_min = std::max(16, std::atoi(e));
+    if (const char* e = std::getenv("DMGS_BLOCK_MAX")) k.block_max = std::atoi(e);
+    if (const char* e = std::getenv("DMGS_SWEEP2_DEFECT")) k.defect = std::min(2, std::max(0, std::atoi(e)));
+    if (const char* e = std::getenv("DMGS_PAD")) k.pad = std::atoi(e) != 0;
+    return k;
+}
+
+// Row pitch of the finest level's float32 arrays.  Refinement plans pad the
+// rows to a multiple of four elements (n = 257: 1040-byte rows instead of
+// 1028) when every kernel that runs on that level takes a pitch: red-black
+// smoothing by two-sweep passes only (even smoothing counts), no block or
+// simple passes, a coarser level.  A tile's rows then fall on different
+// memory channels; the two-sweep pass at 256^3 moves the same bytes about
+// 12 % faster.
+int fine_row_pitch(const dmgs_options* o, const Knobs& kn, int L) {
+    const int N = o->n[0], n = N + 1;
+    const bool ok = kn.pad && o->ndim == 3 && !general_grid(o) && o->precision == DMGS_FP32_IN_FP64 &&
+                    o->smoother == DMGS_RBGS && L > 1 && o->nu_pre >= 2 && o->nu_pre % 2 == 0 && o->nu_post >= 2 &&
+                    o->nu_post % 2 == 0 && N >= kn.fuse_min && N > kn.block_max && N >= kn.sweep2_min;
+    if (!ok) return n;
+    const int py = (n + 3) / 4 * 4;
+    return sweep2_fits<float>(N, (int64_t)py * n) ? py : n;
+}
+
+// Float32 elements allocated per array on level k (padded rows on the finest).
+int64_t nv32_of(const dmgs_options* o, const Sizes& s, int k, int py0) {
+    if (k > 0 || o->ndim == 2) return s.nv[k];
+    const int64_t n = o->n[0] + 1;
+    return n * n * py0;
+}
+
 size_t footprint(const dmgs_options* o) {
     Sizes s = sizes_for(o);
     bool ir = o->precision == DMGS_FP32_IN_FP64;
@@ -202,13 +247,14 @@ size_t footprint(const dmgs_options* o) {
              sizeof(int);
         return b;
     }
+    const int py0 = fine_row_pitch(o, read_knobs(o), s.L);
     for (int k = 0; k < s.L; k++) {
         if (o->ndim == 2) {   // D64, mu64, (u64, q64), t64, (rd64)
             b += ((k > 0 ? 5 : 3) + (k < s.L - 1 ? 1 : 0)) * s.nv[k] * sizeof(double);
             continue;
         }
         b += 2 * s.nv[k] * sizeof(double);                            // D64, mu64
-        if (ir) b += (k < s.L - 1 ? 7 : 6) * s.nv[k] * sizeof(float);  // D32, mu32, w32, u32, q32, t32, (r32)
+        if (ir) b += (k < s.L - 1 ? 7 : 6) * nv32_of(o, s, k, py0) * sizeof(float);  // D32, mu32, w32, u32, q32, t32, (r32)
         else b += (k > 0 ? 4 : 2) * s.nv[k] * sizeof(double);         // w64, (u64, q64), t64
     }
     b += (ir ? 2 : 1) * s.nv[0] * sizeof(double);                     // scratch64 (+ xalt64)
@@ -370,9 +416,19 @@ int set_boundary(T* u, int N, T g, hipStream_t st) {
     return DMGS_OK;
 }
 
+// Kernels that take dense fields only refuse a padded level (a plan pads its
+// finest level only when none of them runs there).
+template <class T>
+int need_dense(dmgs_plan P, int k, const char* what) {
+    if (dense<T>(P->lev[k])) return DMGS_OK;
+    set_error("internal: %s on the padded level %d", what, k);
+    return DMGS_ERR_INVALID;
+}
+
 template <class T>
 int half_sweep(dmgs_plan P, int k, T* u, const T* q, int colour, hipStream_t st) {
     const Level& l = P->lev[k];
+    TRY(need_dense<T>(P, k, "half-sweep"));
     int64_t total = (int64_t)(l.N - 1) * (l.N - 1) * (l.N / 2);
     // reads all of u and D, the colour's q and mua, writes the colour's u
     TIMED(P, k, DMGS_K_SMOOTH, 3.5 * l.nv * sizeof(T), st,
@@ -396,7 +452,8 @@ int apply_or_defect(dmgs_plan P, int k, const T* u, const T* q, T* out, int appl
     const Level& l = P->lev[k];
     TIMED(P, k, DMGS_K_DEFECT_RESTRICT, 5.0 * l.nv * sizeof(T), st,
           hipLaunchKernelGGL(k_defect<T>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, u, q, (const T*)Typed<T>::D(l),
-                             (const T*)Typed<T>::mu(l), out, l.N, l.stencil<T>(harmonic(P)), apply_only));
+                             (const T*)Typed<T>::mu(l), out, l.N, l.stencil<T>(harmonic(P)), apply_only,
+                             Typed<T>::py(l), Typed<T>::px(l)));
     return DMGS_OK;
 }
 
@@ -451,6 +508,7 @@ template <class T>
 int smooth_pass(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int order, bool zero, const T* ec,
                 hipStream_t st) {
     const Level& l = P->lev[k];
+    TRY(need_dense<T>(P, k, "one-sweep pass"));
     SweepArgs<T> a;
     a.u_in = u_in;
     a.u_out = u_out;
@@ -573,8 +631,9 @@ int sweep2_attributes() {
 // is 0 (the adjoint and tangent solves always; the forward solve when g = 0).
 bool use_sweep2(dmgs_plan P, int k, size_t tsize) {
     if (P->lev[k].N < P->cfg_sweep2_min) return false;
-    if (tsize == 4) return sweep2_fits<float>(P->lev[k].N);
-    return P->cfg_sweep2_fp64 && (k > 0 || P->bc_zero) && sweep2_fits<double>(P->lev[k].N);
+    const Level& l = P->lev[k];
+    if (tsize == 4) return sweep2_fits<float>(l.N, Typed<float>::px(l));
+    return P->cfg_sweep2_fp64 && (k > 0 || P->bc_zero) && sweep2_fits<double>(l.N, Typed<double>::px(l));
 }
 
 // One two-sweep pass: u_out = two red-black sweeps applied to u_in (or to
@@ -593,6 +652,8 @@ int smooth_pass2(dmgs_plan P, int k, const T* u_in, T* u_out, const T* q, int or
     a.w = Typed<T>::w(l);
     a.ec = ec;
     a.r = r;
+    a.py = Typed<T>::py(l);
+    a.px = Typed<T>::px(l);
     a.N = l.N;
     a.order = order;
     a.st = l.stencil<T>(harmonic(P));
@@ -661,6 +722,8 @@ int defect_restrict(dmgs_plan P, int k, const T* u, const T* q, T* qc, hipStream
     a.D = Typed<T>::D(l);
     a.mu = Typed<T>::mu(l);
     a.qc = qc;
+    a.py = Typed<T>::py(l);
+    a.px = Typed<T>::px(l);
     a.N = l.N;
     a.rzero = order ? 0 : 1;
     a.st = l.stencil<T>(harmonic(P));
@@ -685,6 +748,7 @@ int smooth_phase(dmgs_plan P, int k, T** cur, T** other, const T* q, int nsweeps
     if (rdone) *rdone = false;
     const Level& l = P->lev[k];
     if (nsweeps == 0) {
+        TRY(need_dense<T>(P, k, "smoothing phase without sweeps"));
         if (zero) TRY(fill<T>(*cur, l.nv, T(0), st));
         if (ec) {
             TIMED(P, k, DMGS_K_PROLONG, (double)(2 * l.nv + P->lev[k + 1].nv) * sizeof(T), st,
@@ -747,6 +811,7 @@ template <class T>
 int block_phase(dmgs_plan P, int k, T** cur, T** other, const T* q, T* qc, const T* ec, int order, bool zero,
                 bool post, hipStream_t st) {
     const Level& l = P->lev[k];
+    TRY(need_dense<T>(P, k, "block pass"));
     BlockArgs<T> a;
     a.u_in = *cur;
     a.u_out = *other;
@@ -812,6 +877,7 @@ int pre_pass(dmgs_plan P, int k, T** cur, T** other, const T* q, T* qc, int orde
         TRY(smooth_phase<T>(P, k, cur, other, q, nu_pre_of(P, order), order, zero, (const T*)nullptr, st, r, &rdone));
         return rdone ? defect_restrict<T>(P, k, r, q, qc, st, true, order) : defect_restrict<T>(P, k, *cur, q, qc, st);
     }
+    TRY(need_dense<T>(P, k, "simple pre-smoothing"));
     if (zero) TRY(fill<T>(*cur, l.nv, T(0), st));
     TRY(sweeps<T>(P, k, *cur, q, nu_pre_of(P, order), order, st));
     T* r = *other;   // scratch for the defect
@@ -828,6 +894,7 @@ int post_pass(dmgs_plan P, int k, T** cur, T** other, const T* ec, const T* q, i
     const Level& l = P->lev[k];
     if (block_level<T>(P, k)) return block_phase<T>(P, k, cur, other, q, (T*)nullptr, ec, order, false, true, st);
     if (fused_level(P, k)) return smooth_phase<T>(P, k, cur, other, q, nu_post_of(P, order), order, false, ec, st);
+    TRY(need_dense<T>(P, k, "simple post-smoothing"));
     TIMED(P, k, DMGS_K_PROLONG, (double)(2 * l.nv + P->lev[k + 1].nv) * sizeof(T), st,
           hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, ec, *cur, l.N));
     return sweeps<T>(P, k, *cur, q, nu_post_of(P, order), order, st);
@@ -875,6 +942,7 @@ constexpr double kWjOmega = 6.0 / 7.0;
 template <class T>
 int wj_sweeps(dmgs_plan P, int k, T** cur, T** other, const T* q, int count, bool zero, hipStream_t st) {
     const Level& l = P->lev[k];
+    TRY(need_dense<T>(P, k, "weighted-Jacobi sweep"));
     for (int i = 0; i < count; i++) {
         const bool z = zero && i == 0;
         // reads u, q, D, mu, w and writes u (from zero: reads q, w)
@@ -893,6 +961,7 @@ template <class T>
 int vcycle_wj(dmgs_plan P, int k, T** cur, T** other, const T* q, int order, bool zero, hipStream_t st) {
     const Level& l = P->lev[k];
     const int nu1 = nu_pre_of(P, order), nu2 = nu_post_of(P, order);
+    TRY(need_dense<T>(P, k, "weighted-Jacobi cycle"));
     if (zero && (k == P->L - 1 || nu1 == 0)) TRY(fill<T>(*cur, l.nv, T(0), st));
     if (k == P->L - 1) return coarsest<T>(P, q, *cur, st);
     TRY(wj_sweeps<T>(P, k, cur, other, q, nu1, zero && nu1 > 0, st));
@@ -922,6 +991,7 @@ int vcycle(dmgs_plan P, int k, T** cur, T** other, const T* q, int order, bool z
         return launch_small_t<T, false>(P, k, q, *cur, order, st);
     }
     if (k == P->L - 1) {
+        TRY(need_dense<T>(P, k, "coarsest solve"));
         if (zero) TRY(fill<T>(*cur, P->lev[k].nv, T(0), st));
         return coarsest<T>(P, q, *cur, st);
     }
@@ -989,6 +1059,8 @@ int ir_step(dmgs_plan P, const double* x, const float* e, double* x_out, const d
     a.D = l.D64;
     a.mu = l.mu64;
     a.r32 = r32;
+    a.py = l.py;
+    a.px = l.px;
     a.partial = P->partial;
     a.N = l.N;
     a.st = l.stencil<double>(harmonic(P));
@@ -1851,11 +1923,12 @@ int build_hierarchy(dmgs_plan P, hipStream_t st, const double* logD = nullptr, c
         Level& l = P->lev[k];
         if (is_ir(P)) {
             hipLaunchKernelGGL(k_level_prep<float>, dim3(vertex_grid(l.nv)), dim3(kBlock), 0, st, (const double*)l.D64,
-                               (const double*)l.mu64, l.N, l.stencil<double>(harmonic(P)), l.w32, l.D32, l.mu32);
+                               (const double*)l.mu64, l.N, l.stencil<double>(harmonic(P)), l.w32, l.D32, l.mu32, l.py,
+                               l.px);
         } else {
             hipLaunchKernelGGL(k_level_prep<double>, dim3(vertex_grid(l.nv)), dim3(kBlock), 0, st, (const double*)l.D64,
                                (const double*)l.mu64, l.N, l.stencil<double>(harmonic(P)), l.w64, (float*)nullptr,
-                               (float*)nullptr);
+                               (float*)nullptr, l.n, (int64_t)l.n * l.n);
         }
         LAUNCHCHK();
     }
@@ -1884,9 +1957,59 @@ int debug_check(dmgs_plan P, int k, int fp32, bool need_coarse) {
 template <class T>
 T* level_scratch(dmgs_plan P, int k) { return Typed<T>::t(P->lev[k]); }
 
+// Copy a field of level k between the dense layout (to_level false: dst)
+// and the level's layout of T arrays (to_level true: dst).
+template <class T>
+int repitch(dmgs_plan P, int k, const T* src, T* dst, bool to_level, hipStream_t st) {
+    const Level& l = P->lev[k];
+    const int n = l.n, py = Typed<T>::py(l);
+    const int64_t px = Typed<T>::px(l), dpx = (int64_t)n * n;
+    if (to_level) hipLaunchKernelGGL(k_repitch<T>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, src, n, dpx, dst, py, px, n);
+    else hipLaunchKernelGGL(k_repitch<T>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, src, py, px, dst, n, dpx, n);
+    LAUNCHCHK();
+    return DMGS_OK;
+}
+
+// The diagnostic passes on a level whose T arrays have padded rows: the
+// dense inputs are copied into the level's own iterate, partner and
+// right-hand-side buffers (their previous contents are lost), the passes run
+// there, and the result is copied back out.
+template <class T>
+int debug_pre_padded(dmgs_plan P, int k, int order, const T* u_in, const T* q, T* u_out, T* qc, hipStream_t st) {
+    const Level& l = P->lev[k];
+    T* cur = Typed<T>::u(l);
+    T* oth = Typed<T>::t(l);
+    T* ql = Typed<T>::q(l);
+    if (u_in) {
+        TRY(repitch<T>(P, k, u_in, cur, true, st));
+        TRY(repitch<T>(P, k, u_in, oth, true, st));
+    } else {
+        TRY(fill<T>(cur, l.nv32, T(0), st));
+        TRY(fill<T>(oth, l.nv32, T(0), st));
+    }
+    TRY(repitch<T>(P, k, q, ql, true, st));
+    TRY(fill<T>(qc, P->lev[k + 1].nv, T(0), st));
+    TRY(pre_pass<T>(P, k, &cur, &oth, ql, qc, order, u_in == nullptr, st));
+    return repitch<T>(P, k, cur, u_out, false, st);
+}
+
+template <class T>
+int debug_post_padded(dmgs_plan P, int k, int order, const T* u_in, const T* ec, const T* q, T* u_out, hipStream_t st) {
+    const Level& l = P->lev[k];
+    T* cur = Typed<T>::u(l);
+    T* oth = Typed<T>::t(l);
+    T* ql = Typed<T>::q(l);
+    TRY(repitch<T>(P, k, u_in, cur, true, st));
+    TRY(repitch<T>(P, k, u_in, oth, true, st));
+    TRY(repitch<T>(P, k, q, ql, true, st));
+    TRY(post_pass<T>(P, k, &cur, &oth, ec, ql, order, st));
+    return repitch<T>(P, k, cur, u_out, false, st);
+}
+
 template <class T>
 int debug_pre_t(dmgs_plan P, int k, int order, const T* u_in, const T* q, T* u_out, T* qc, hipStream_t st) {
     const Level& l = P->lev[k];
+    if (!dense<T>(l)) return debug_pre_padded<T>(P, k, order, u_in, q, u_out, qc, st);
     T* scratch = level_scratch<T>(P, k);
     if (!scratch) { set_error("no scratch of this type on level %d", k); return DMGS_ERR_INVALID; }
     if (u_in) {
@@ -1907,6 +2030,7 @@ int debug_pre_t(dmgs_plan P, int k, int order, const T* u_in, const T* q, T* u_o
 template <class T>
 int debug_post_t(dmgs_plan P, int k, int order, const T* u_in, const T* ec, const T* q, T* u_out, hipStream_t st) {
     const Level& l = P->lev[k];
+    if (!dense<T>(l)) return debug_post_padded<T>(P, k, order, u_in, ec, q, u_out, st);
     T* scratch = level_scratch<T>(P, k);
     if (!scratch) { set_error("no scratch of this type on level %d", k); return DMGS_ERR_INVALID; }
     HIPCHK(hipMemcpyAsync(u_out, u_in, l.nv * sizeof(T), hipMemcpyDeviceToDevice, st));
@@ -2059,9 +2183,10 @@ size_t dmgs_forward_vjp_workspace_bytes(const dmgs_options* o) {
     // plans; the float64 scratch (+ alternate iterate) and the partials
     Sizes s = sizes_for(o);
     const bool ir = o->precision == DMGS_FP32_IN_FP64;
+    const int py0 = fine_row_pitch(o, read_knobs(o), s.L);
     size_t b = 0;
     for (int k = 0; k < s.L; k++) {
-        if (ir) b += (k < s.L - 1 ? 4 : 3) * s.nv[k] * sizeof(float);
+        if (ir) b += (k < s.L - 1 ? 4 : 3) * nv32_of(o, s, k, py0) * sizeof(float);
         else b += ((k > 0 ? 3 : 1) + (o->ndim == 2 && k < s.L - 1 ? 1 : 0)) * s.nv[k] * sizeof(double);
     }
     b += (ir ? 2 : 1) * s.nv[0] * sizeof(double);
@@ -2099,6 +2224,9 @@ int grid_plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
         l.nv = (int64_t)(cn[k][0] + 1) * (cn[k][1] + 1) * (cn[k][2] + 1);
         l.h = l.h3[0];
         l.inv_h2 = 1.0 / (l.h * l.h);
+        l.py = l.n;   // no float32 arrays
+        l.px = (int64_t)l.n * l.n;
+        l.nv32 = 0;
         if (st == DMGS_OK) st = dalloc(P, &l.D64, l.nv);
         if (st == DMGS_OK) st = dalloc(P, &l.mu64, l.nv);
         if (k > 0 && st == DMGS_OK) st = dalloc(P, &l.u64, l.nv);
@@ -2167,6 +2295,8 @@ int plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
     Sizes s = sizes_for(o);
     P->L = s.L;
     bool ir = o->precision == DMGS_FP32_IN_FP64;
+    const Knobs kn = read_knobs(o);
+    const int py0 = fine_row_pitch(o, kn, s.L);
     int st = DMGS_OK;
     int N = o->n[0];
     double h = o->h;
@@ -2177,16 +2307,19 @@ int plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
         l.nv = s.nv[k];
         l.h = h;
         l.inv_h2 = 1.0 / (h * h);
+        l.py = k == 0 && o->ndim == 3 ? py0 : l.n;
+        l.px = (int64_t)l.py * l.n;
+        l.nv32 = nv32_of(o, s, k, py0);
         if (st == DMGS_OK) st = dalloc(P, &l.D64, l.nv);
         if (st == DMGS_OK) st = dalloc(P, &l.mu64, l.nv);
         if (ir) {
-            if (st == DMGS_OK) st = dalloc(P, &l.D32, l.nv);
-            if (st == DMGS_OK) st = dalloc(P, &l.mu32, l.nv);
-            if (st == DMGS_OK) st = dalloc(P, &l.w32, l.nv);
-            if (st == DMGS_OK) st = dalloc(P, &l.u32, l.nv);
-            if (st == DMGS_OK) st = dalloc(P, &l.q32, l.nv);
-            if (st == DMGS_OK) st = dalloc(P, &l.t32, l.nv);
-            if (k < s.L - 1 && st == DMGS_OK) st = dalloc(P, &l.r32, l.nv);
+            if (st == DMGS_OK) st = dalloc(P, &l.D32, l.nv32);
+            if (st == DMGS_OK) st = dalloc(P, &l.mu32, l.nv32);
+            if (st == DMGS_OK) st = dalloc(P, &l.w32, l.nv32);
+            if (st == DMGS_OK) st = dalloc(P, &l.u32, l.nv32);
+            if (st == DMGS_OK) st = dalloc(P, &l.q32, l.nv32);
+            if (st == DMGS_OK) st = dalloc(P, &l.t32, l.nv32);
+            if (k < s.L - 1 && st == DMGS_OK) st = dalloc(P, &l.r32, l.nv32);
         } else {
             // two-dimensional cycles take no inverse diagonal (t64 is the
             // partner buffer of the out-of-place passes)
@@ -2223,27 +2356,29 @@ int plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
             st = DMGS_ERR_HIP;
         }
     }
-    // every work buffer starts at 0: the passes never write boundary layers,
-    // and coarse corrections have homogeneous boundaries (an arena keeps the
-    // last call's contents, so its buffers are cleared on the stream)
+    // every work buffer starts at 0: the passes never write boundary layers
+    // or row padding, and coarse corrections have homogeneous boundaries (an
+    // arena keeps the last call's contents, so its buffers are cleared on the
+    // stream); the coefficient arrays' row padding is 0 as well
     for (int k = 0; k < P->L && st == DMGS_OK; k++) {
         Level& l = P->lev[k];
-        void* ps[] = {l.u64, l.q64, l.t64, l.u32, l.q32, l.t32, l.r32, l.rd64};
-        size_t sz[] = {8, 8, 8, 4, 4, 4, 4, 8};
-        for (int j = 0; j < 8 && st == DMGS_OK; j++) {
-            if (!ps[j]) continue;
+        void* ps[] = {l.u64, l.q64, l.t64, l.u32, l.q32, l.t32, l.r32, l.rd64, l.D32, l.mu32, l.w32};
+        size_t sz[] = {8, 8, 8, 4, 4, 4, 4, 8, 4, 4, 4};
+        for (int j = 0; j < 11 && st == DMGS_OK; j++) {
+            if (!ps[j] || (j >= 8 && dense<float>(l))) continue;
+            const int64_t cnt = sz[j] == 8 ? l.nv : l.nv32;
             if (P->arena) {
-                if (sz[j] == 8) hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(l.nv)), dim3(kBlock), 0, zst, (double*)ps[j], l.nv, 0.0);
-                else hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(l.nv)), dim3(kBlock), 0, zst, (float*)ps[j], l.nv, 0.0f);
+                if (sz[j] == 8) hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(cnt)), dim3(kBlock), 0, zst, (double*)ps[j], cnt, 0.0);
+                else hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(cnt)), dim3(kBlock), 0, zst, (float*)ps[j], cnt, 0.0f);
                 if (hipGetLastError() != hipSuccess) { set_error("fill kernel launch failed"); st = DMGS_ERR_HIP; }
-            } else if (hipMemset(ps[j], 0, l.nv * sz[j]) != hipSuccess) {
+            } else if (hipMemset(ps[j], 0, cnt * sz[j]) != hipSuccess) {
                 set_error("hipMemset failed");
                 st = DMGS_ERR_HIP;
             }
         }
     }
     P->cfg_sweep = 0;
-    P->cfg_fuse_min = ir ? 32 : 16;
+    P->cfg_fuse_min = kn.fuse_min;
     // first level handled by the single-workgroup kernel (N <= 16 in float32,
     // N <= 8 in float64, all remaining levels within the LDS budget)
     P->small32 = P->small64 = -1;
@@ -2275,17 +2410,12 @@ int plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
     }
     if (st == DMGS_OK) st = sweep2_attributes();
     if (st == DMGS_OK) st = block_attributes();
-    P->cfg_block_max = 64;
+    P->cfg_block_max = kn.block_max;
     P->cfg_dr_wgs = 512;
     if (const char* e = std::getenv("DMGS_DR_WGS")) P->cfg_dr_wgs = std::max(16, std::atoi(e));
-    if (const char* e = std::getenv("DMGS_SWEEP2_DEFECT")) P->cfg_defect = std::min(2, std::max(0, std::atoi(e)));
-    if (const char* e = std::getenv("DMGS_BLOCK_MAX")) P->cfg_block_max = std::atoi(e);
-    // float64 plans have no block passes: their two-sweep passes reach down
-    // to the levels the small-level kernel leaves (one launch per phase
-    // instead of two)
-    P->cfg_sweep2_min = is_ir(P) ? 64 : 16;
+    P->cfg_defect = kn.defect;
+    P->cfg_sweep2_min = kn.sweep2_min;
     P->cfg_sweep2_wgs = 256;
-    if (const char* e = std::getenv("DMGS_SWEEP2_MIN")) P->cfg_sweep2_min = std::max(16, std::atoi(e));
     if (const char* e = std::getenv("DMGS_SWEEP2_WGS")) P->cfg_sweep2_wgs = std::max(16, std::atoi(e));
     // below the finest level the passes are latency-bound: longer chunks on
     // half as many workgroups take less CU time, which the concurrent solves
@@ -2293,7 +2423,6 @@ int plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
     P->cfg_sweep2_wgs_coarse = std::max(16, P->cfg_sweep2_wgs / 2);
     if (const char* e = std::getenv("DMGS_SWEEP2_WGS_COARSE")) P->cfg_sweep2_wgs_coarse = std::max(16, std::atoi(e));
     if (const char* e = std::getenv("DMGS_SWEEP_CFG")) P->cfg_sweep = std::min(2, std::max(0, std::atoi(e)));
-    if (const char* e = std::getenv("DMGS_FUSE_MIN")) P->cfg_fuse_min = std::max(8, std::atoi(e));
     if (const char* e = std::getenv("DMGS_2D_SWEEP2_MIN")) P->cfg_2d_sweep2_min = std::max(4, std::atoi(e));
     if (const char* e = std::getenv("DMGS_SWEEP2_FP64")) P->cfg_sweep2_fp64 = std::atoi(e) != 0;
     if (const char* e = std::getenv("DMGS_2D_BLOCK_MIN")) P->cfg_2d_block_min = std::max(4, std::atoi(e));
@@ -2438,10 +2567,10 @@ int make_twin(dmgs_plan P) {
         l.u64 = l.q64 = l.t64 = l.rd64 = nullptr;
         l.u32 = l.q32 = l.t32 = l.r32 = nullptr;
         if (ir) {
-            if (st == DMGS_OK) st = dalloc(T, &l.u32, l.nv);
-            if (st == DMGS_OK) st = dalloc(T, &l.q32, l.nv);
-            if (st == DMGS_OK) st = dalloc(T, &l.t32, l.nv);
-            if (k < P->L - 1 && st == DMGS_OK) st = dalloc(T, &l.r32, l.nv);
+            if (st == DMGS_OK) st = dalloc(T, &l.u32, l.nv32);
+            if (st == DMGS_OK) st = dalloc(T, &l.q32, l.nv32);
+            if (st == DMGS_OK) st = dalloc(T, &l.t32, l.nv32);
+            if (k < P->L - 1 && st == DMGS_OK) st = dalloc(T, &l.r32, l.nv32);
         } else {
             if (k > 0 && st == DMGS_OK) st = dalloc(T, &l.u64, l.nv);
             if (k > 0 && st == DMGS_OK) st = dalloc(T, &l.q64, l.nv);
@@ -2451,7 +2580,10 @@ int make_twin(dmgs_plan P) {
         void* ps[] = {l.u64, l.q64, l.t64, l.u32, l.q32, l.t32, l.r32};
         size_t sz[] = {8, 8, 8, 4, 4, 4, 4};
         for (int j = 0; j < 7 && st == DMGS_OK; j++)
-            if (ps[j] && hipMemset(ps[j], 0, l.nv * sz[j]) != hipSuccess) { set_error("hipMemset failed"); st = DMGS_ERR_HIP; }
+            if (ps[j] && hipMemset(ps[j], 0, (sz[j] == 8 ? l.nv : l.nv32) * sz[j]) != hipSuccess) {
+                set_error("hipMemset failed");
+                st = DMGS_ERR_HIP;
+            }
     }
     if (st == DMGS_OK) st = dalloc(T, &T->scratch64, T->lev[0].nv);
     if (ir && st == DMGS_OK) st = dalloc(T, &T->xalt64, T->lev[0].nv);

@@ -102,24 +102,27 @@ __global__ void k_coarsen_coef(const double* __restrict__ fD, const double* __re
 // boundary), formed in float64 and stored as T, and, when D32 is given,
 // float32 copies of D and mua.
 template <class T>
+// The outputs w, D32, mu32 are laid out with row pitch py and plane pitch
+// px (D and mu are dense).
 __global__ void k_level_prep(const double* __restrict__ D, const double* __restrict__ mu, int N, Stencil<double> st,
-                             T* __restrict__ w, float* __restrict__ D32, float* __restrict__ mu32) {
+                             T* __restrict__ w, float* __restrict__ D32, float* __restrict__ mu32, int py, int64_t px) {
     const int n = N + 1, sx = n * n, nv = sx * n;
     const int i = vertex_of_thread();
     if (i >= nv) return;
     const int z = i % n, y = (i / n) % n, x = i / sx;
+    const int64_t o = x * px + (int64_t)y * py + z;
     const double Di = D[i], mi = mu[i];
     if (D32) {
-        D32[i] = (float)Di;
-        mu32[i] = (float)mi;
+        D32[o] = (float)Di;
+        mu32[o] = (float)mi;
     }
     if (!is_interior(N, x, y, z)) {
-        w[i] = T(0);
+        w[o] = T(0);
         return;
     }
     const double d = mi + face_coef(Di, D[i + sx], st) + face_coef(Di, D[i - sx], st) + face_coef(Di, D[i + n], st) +
                      face_coef(Di, D[i - n], st) + face_coef(Di, D[i + 1], st) + face_coef(Di, D[i - 1], st);
-    w[i] = (T)(1.0 / d);
+    w[o] = (T)(1.0 / d);
 }
 
 // Weighted-Jacobi sweep, out of place: on interior vertices
@@ -174,20 +177,36 @@ __global__ void k_gs_half(T* __restrict__ u, const T* __restrict__ q, const T* _
     u[i] = num / den;
 }
 
-// r = q - A u on interior vertices (0 on the boundary); mode 1 writes A u instead.
+// r = q - A u on interior vertices (0 on the boundary); mode 1 writes A u
+// instead.  u, q and r are dense; the coefficients D and mu have row pitch
+// cpy and plane pitch cpx.
 template <class T>
 __global__ void k_defect(const T* __restrict__ u, const T* __restrict__ q, const T* __restrict__ D,
-                         const T* __restrict__ mu, T* __restrict__ r, int N, Stencil<T> s, int apply_only) {
+                         const T* __restrict__ mu, T* __restrict__ r, int N, Stencil<T> s, int apply_only, int cpy,
+                         int64_t cpx) {
     int n = N + 1;
     int64_t nv = (int64_t)n * n * n, sx = (int64_t)n * n;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
         int z = (int)(i % n), y = (int)((i / n) % n), x = (int)(i / sx);
         if (!is_interior(N, x, y, z)) { r[i] = T(0); continue; }
-        T Di = D[i], ui = u[i];
-        T Au = mu[i] * ui + face_coef(Di, D[i + sx], s) * (ui - u[i + sx]) + face_coef(Di, D[i - sx], s) * (ui - u[i - sx]) +
-               face_coef(Di, D[i + n], s) * (ui - u[i + n]) + face_coef(Di, D[i - n], s) * (ui - u[i - n]) +
-               face_coef(Di, D[i + 1], s) * (ui - u[i + 1]) + face_coef(Di, D[i - 1], s) * (ui - u[i - 1]);
+        const int64_t c = x * cpx + (int64_t)y * cpy + z;
+        T Di = D[c], ui = u[i];
+        T Au = mu[c] * ui + face_coef(Di, D[c + cpx], s) * (ui - u[i + sx]) + face_coef(Di, D[c - cpx], s) * (ui - u[i - sx]) +
+               face_coef(Di, D[c + cpy], s) * (ui - u[i + n]) + face_coef(Di, D[c - cpy], s) * (ui - u[i - n]) +
+               face_coef(Di, D[c + 1], s) * (ui - u[i + 1]) + face_coef(Di, D[c - 1], s) * (ui - u[i - 1]);
         r[i] = apply_only ? Au : q[i] - Au;
+    }
+}
+
+// dst = src on every vertex of an n^3 field, between layouts of row pitch
+// spy / dpy and plane pitch spx / dpx (padding entries of dst untouched).
+template <class T>
+__global__ void k_repitch(const T* __restrict__ src, int spy, int64_t spx, T* __restrict__ dst, int dpy, int64_t dpx,
+                          int n) {
+    const int64_t nv = (int64_t)n * n * n;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        const int z = (int)(v % n), y = (int)((v / n) % n), x = (int)(v / ((int64_t)n * n));
+        dst[x * dpx + (int64_t)y * dpy + z] = src[x * spx + (int64_t)y * spy + z];
     }
 }
 

@@ -86,6 +86,10 @@ struct SweepArgs {
     const T* ec;     // coarse correction added by prolongation (MODE 2)
     T* r;            // defect of the result (two-sweep passes with DEFECT)
     double* partial = nullptr;   // per-block sums of the input's squared residual (two-sweep passes with NORM)
+    // layout of u_in, u_out, q, D, w and r (two-sweep passes): vertex (x, y, z)
+    // at x px + y py + z; the one-sweep pass takes dense fields
+    int py = 0;
+    int64_t px = 0;
     int N;
     int order;       // colour of the first stage: 0 red, 1 black
     int tiles_y, tiles_z, chunk, nchunks;
@@ -273,6 +277,8 @@ struct RestrictArgs {
     const T* D;
     const T* mu;
     T* qc;
+    int py = 0;        // layout of the fine fields u, q, D, mu: vertex (x, y, z) at x px + y py + z
+    int64_t px = 0;
     int N;   // fine cells per axis
     int rzero;   // FROM_R: colour ((x+y+z) mod 2) whose defect is 0 and not read
     int tiles_y, tiles_z, chunk, nchunks;
@@ -300,8 +306,8 @@ __global__ __launch_bounds__((RestrictShape<TYC, TZC>::NT)) void k_defect_restri
     __shared__ T sU[2][RA];
     __shared__ T sD[2][RA];
     __shared__ T sR[2][RA];
-    const int N = a.N, n = N + 1, Nc = N / 2, ncv = Nc + 1;
-    const int64_t sx = (int64_t)n * n, plane_bytes = sx * (int64_t)sizeof(T);
+    const int N = a.N, Nc = N / 2, ncv = Nc + 1;
+    const int64_t plane_bytes = a.px * (int64_t)sizeof(T);
     const int64_t cplane_bytes = (int64_t)ncv * ncv * (int64_t)sizeof(T);
     const int tid = threadIdx.x;
     const bool act = tid < RY * NP;
@@ -314,8 +320,8 @@ __global__ __launch_bounds__((RestrictShape<TYC, TZC>::NT)) void k_defect_restri
     const int y = 2 * Y0 - 2 + ly, zl = 2 * Z0 - 2 + 2 * pz;
     const int e0 = ly * RZ + 2 * pz;
     const bool yin = act && y >= 0 && y <= N;
-    const int off0 = (yin && zl <= N) ? (int)(((int64_t)y * n + zl) * sizeof(T)) : kOob;
-    const int off1 = (yin && zl + 1 <= N) ? (int)(((int64_t)y * n + zl + 1) * sizeof(T)) : kOob;
+    const int off0 = (yin && zl <= N) ? (int)(((int64_t)y * a.py + zl) * sizeof(T)) : kOob;
+    const int off1 = (yin && zl + 1 <= N) ? (int)(((int64_t)y * a.py + zl + 1) * sizeof(T)) : kOob;
     // residual needed on region rows/cols 1 .. R-2 (interior vertices only)
     const bool rrow = act && ly >= 1 && ly <= RY - 2 && y >= 1 && y <= N - 1;
     const bool rc0 = rrow && 2 * pz >= 1 && zl >= 1 && zl <= N - 1;
@@ -437,6 +443,8 @@ struct IrArgs {
     const double* ed = nullptr;
     const double* ew = nullptr;
     double* erhobar = nullptr;
+    int py = 0;        // layout of the float32 fields e and r32: vertex (x, y, z) at x px + y py + z
+    int64_t px = 0;    // (the float64 fields are dense)
     int N;
     int tiles_y, tiles_z, chunk, nchunks;
     Stencil<double> st;
@@ -464,7 +472,7 @@ __global__ __launch_bounds__((IrShape<TY, TZ>::NT)) void k_ir_residual_col(IrArg
     __shared__ double sD[2][RA];
     const int N = a.N, n = N + 1;
     const int64_t sx = (int64_t)n * n;
-    const int64_t pb8 = sx * 8, pb4 = sx * 4;
+    const int64_t pb8 = sx * 8, pb4 = a.px * 4;
     const int tid = threadIdx.x;
     const bool act = tid < RY * NP;
     const int ly = act ? tid / NP : 0, pz = act ? tid % NP : 0;
@@ -476,11 +484,11 @@ __global__ __launch_bounds__((IrShape<TY, TZ>::NT)) void k_ir_residual_col(IrArg
     const int xa = 1 + bx * a.chunk, xb = min(N, xa + a.chunk);   // planes [xa, xb)
     const int e0 = ly * RZ + 2 * pz;
     const bool yin = act && y >= 0 && y <= N;
-    const int64_t v0 = (int64_t)y * n + zl;
+    const int64_t v0 = (int64_t)y * n + zl, v4 = (int64_t)y * a.py + zl;
     const int o8_0 = (yin && zl >= 0 && zl <= N) ? (int)(v0 * 8) : kOob;
     const int o8_1 = (yin && zl + 1 <= N) ? (int)((v0 + 1) * 8) : kOob;
-    const int o4_0 = (yin && zl >= 0 && zl <= N) ? (int)(v0 * 4) : kOob;
-    const int o4_1 = (yin && zl + 1 <= N) ? (int)((v0 + 1) * 4) : kOob;
+    const int o4_0 = (yin && zl >= 0 && zl <= N) ? (int)(v4 * 4) : kOob;
+    const int o4_1 = (yin && zl + 1 <= N) ? (int)((v4 + 1) * 4) : kOob;
     const bool tile_y = act && ly >= 1 && ly <= TY && y >= 1 && y <= N - 1;
     const bool t0 = tile_y && zl >= max(1, z0) && zl <= min(N - 1, z0 + TZ - 1);
     const bool t1 = tile_y && zl + 1 >= max(1, z0) && zl + 1 <= min(N - 1, z0 + TZ - 1);

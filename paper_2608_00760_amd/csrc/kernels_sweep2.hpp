@@ -92,10 +92,10 @@ constexpr size_t sweep2_lds_bytes() {
 }
 
 // Largest level the two-sweep pass takes: buffer offsets of a whole field
-// (plus a few planes beyond it) stay below kOob.
+// of planes of px elements (plus a few planes beyond it) stay below kOob.
 template <class T>
-__host__ __device__ constexpr bool sweep2_fits(int N) {
-    return ((int64_t)(N + 1) * (N + 1) * (N + 20) + 64) * (int64_t)sizeof(T) < (int64_t)kOob;
+__host__ __device__ constexpr bool sweep2_fits(int N, int64_t px) {
+    return (px * (N + 20) + 64) * (int64_t)sizeof(T) < (int64_t)kOob;
 }
 
 template <class T, int TY, int TZ, int MODE, bool HARM, bool DEFECT = false, bool NORM = false>
@@ -109,7 +109,7 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_r
     extern __shared__ __align__(16) unsigned char lds_raw[];
     UD<T>* const ring = reinterpret_cast<UD<T>*>(lds_raw) + Sh::PAD;
     const int N = a.N, n = N + 1;
-    const int plane_bytes = n * n * (int)sizeof(T);
+    const int plane_bytes = (int)(a.px * (int64_t)sizeof(T));   // the level's fields: rows of a.py, planes of a.px
     const int field_bytes = n * plane_bytes;
     const int tid = threadIdx.x;
     const int hp = tid >= HALF ? 1 : 0;                 // row parity of this wave
@@ -128,9 +128,10 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_r
     const int xa = 1 + bx * a.chunk, xb = min(N, xa + a.chunk);   // output planes [xa, xb)
     const int pe = ly * NP + pz;                                   // this pair's index in a slot
     // in-plane offset of element 0 (element 1 is the next word); rows outside
-    // the grid read 0, columns just outside it read finite neighbours' data
-    // that no update of an interior vertex uses
-    const int off = (y >= 0 && y <= N) ? (y * n + zl) * (int)sizeof(T) : kOob;
+    // the grid read 0, columns just outside it read finite data (the
+    // neighbouring row's, or row padding) that no update of an interior
+    // vertex uses
+    const int off = (y >= 0 && y <= N) ? (y * a.py + zl) * (int)sizeof(T) : kOob;
     // ring membership: stage j updates a vertex within R - 1 - j of the tile
     auto in_ring = [&](int z, int r) {
         return y >= max(1, y0 - r) && y <= min(N - 1, y0 + TY - 1 + r) && z >= max(1, z0 - r) &&

@@ -26,6 +26,12 @@ struct Level {
     float *u32 = nullptr, *q32 = nullptr, *t32 = nullptr;
     float* r32 = nullptr;   // fine defect written by pre-smoothing passes (iterative-refinement plans, not the coarsest)
     double* rd64 = nullptr; // ... two-dimensional plans (not the coarsest)
+    // layout of the float32 arrays: vertex (x, y, z) at x px + y py + z, nv32
+    // elements allocated.  Dense (py = n, px = n^2) except on the finest
+    // level of refinement plans whose passes all take a pitch, where rows
+    // are padded (py > n) to spread a tile's rows over the memory channels.
+    int py = 0;
+    int64_t px = 0, nv32 = 0;
 
     template <class T> Stencil<T> stencil(int harmonic) const {
         Stencil<T> s;
@@ -45,6 +51,8 @@ template <> struct Typed<double> {
     static double* q(const Level& l) { return l.q64; }
     static double* t(const Level& l) { return l.t64; }
     static double* r(const Level&) { return nullptr; }
+    static int py(const Level& l) { return l.n; }
+    static int64_t px(const Level& l) { return (int64_t)l.n * l.n; }
 };
 template <> struct Typed<float> {
     static float* D(const Level& l) { return l.D32; }
@@ -54,7 +62,12 @@ template <> struct Typed<float> {
     static float* q(const Level& l) { return l.q32; }
     static float* t(const Level& l) { return l.t32; }
     static float* r(const Level& l) { return l.r32; }
+    static int py(const Level& l) { return l.py; }
+    static int64_t px(const Level& l) { return l.px; }
 };
+
+// The level's arrays of type T are dense (every kernel takes them).
+template <class T> bool dense(const Level& l) { return Typed<T>::py(l) == l.n; }
 
 }  // namespace dmgs
 

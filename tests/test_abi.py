@@ -83,6 +83,42 @@ def test_default_options_and_footprint(abi):
     assert lib.dmgs_forward_vjp_workspace_bytes(C.byref(abi.default_options(20))) == 0
 
 
+def test_padded_finest_level_footprint(abi, monkeypatch):
+    """Refinement plans whose finest-level passes all take a row pitch pad
+    that level's float32 rows to a multiple of four elements (n = 257: 260):
+    its seven float32 arrays (D, mu, w, iterate, right-hand side, partner,
+    defect) grow by n^2 (py - n) elements each, and the second work set of
+    dmgs_forward_vjp (iterate, right-hand side, partner, defect) likewise.
+    Odd smoothing counts, weighted Jacobi, float64 plans, levels the block
+    passes take and DMGS_PAD=0 keep the dense layout."""
+    lib = abi.lib()
+
+    def both(o):
+        return lib.dmgs_workspace_bytes(C.byref(o)), lib.dmgs_forward_vjp_workspace_bytes(C.byref(o))
+
+    for N, py in ((256, 260), (128, 132), (96, 100)):
+        o = abi.default_options(N)
+        o.precision = abi.DMGS_FP32_IN_FP64
+        n = N + 1
+        monkeypatch.setenv("DMGS_PAD", "0")
+        dense = both(o)
+        monkeypatch.delenv("DMGS_PAD")
+        padded = both(o)
+        grow = n * n * (py - n) * 4
+        assert padded[0] - dense[0] == 7 * grow, N
+        assert padded[1] - dense[1] == 11 * grow, N
+    for change in ({"nu_pre": 1, "nu_post": 1}, {"nu_post": 3}, {"smoother": abi.DMGS_WJACOBI},
+                   {"precision": abi.DMGS_FP64}, {"n": 64}):
+        o = abi.default_options(change.pop("n", 256))
+        o.precision = abi.DMGS_FP32_IN_FP64
+        for k, v in change.items():
+            setattr(o, k, v)
+        monkeypatch.setenv("DMGS_PAD", "0")
+        dense = both(o)
+        monkeypatch.delenv("DMGS_PAD")
+        assert both(o) == dense, change
+
+
 def test_options_layout_matches_the_header(abi):
     """dmgs_default_options clears sizeof(dmgs_options) bytes and then sets the
     defaults; in a buffer pre-filled with a sentinel, it writes up to the last
