@@ -352,6 +352,66 @@ int dmgs_solve_once(const dmgs_options *opt, const double *D, const double *mua,
 int dmgs_solve_once_noalloc(const dmgs_options *opt, const double *D, const double *mua, const double *q,
                             double *rho, dmgs_info *info, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Grouped execution (continuous batching).  A sampling loop over the
+ * posterior (Sec. 2.1, Sec. 2.5.4) asks for many forward solves, each followed
+ * by a push-forward (Sec. 2.3) or a pull-back (Sec. 2.4, Eq. (EqcompT)), on grids of
+ * several sizes.  A batch advances all its requests together.  Each
+ * dmgs_batch_tick runs one refinement step for every active request, with the
+ * kernels of all requests merged into grouped launches (one launch serves
+ * the same pass of several requests, each on its own arrays), and
+ * synchronises the stream once.  Requests may be added between ticks.  A
+ * request's arithmetic does not depend on the batch: its results, cycle
+ * counts and residuals are bitwise those of dmgs_forward followed by
+ * dmgs_jvp or dmgs_vjp on its plan.
+ *
+ * Plans: DMGS_FP32_IN_FP64, cubic 3D, V(2,2) red-black cycles (nu_pre =
+ * nu_post = 2), adjoint_schedule 0, a coarse end of at most 16 cells per axis
+ * (N = c 2^m with m >= 2), coefficients set.  A plan serves at most one
+ * request of a batch at a time and must not be used by other calls while it
+ * does.  Its coefficient set-up must be ordered before the ticks (the same
+ * stream, or a synchronisation).
+ * ------------------------------------------------------------------------- */
+typedef struct dmgs_batch_s *dmgs_batch;
+
+enum { DMGS_BATCH_JVP = 0, DMGS_BATCH_VJP = 1 };
+
+/* Create an empty batch on the current device.  Errors: DMGS_ERR_INVALID,
+ * DMGS_ERR_OOM, DMGS_ERR_HIP. */
+int dmgs_batch_create(dmgs_batch *out);
+/* Destroy a batch; requests not yet reported are dropped (no device work of
+ * the batch is pending between ticks).  The plans are the caller's. */
+int dmgs_batch_destroy(dmgs_batch batch);
+/* Add a request (device arrays of (N+1)^3 float64, owned by the caller and
+ * untouched by it until the request is reported):
+ *   DMGS_BATCH_JVP: rho = S q, then out0 = drho = S (dq - A' rho) with
+ *                   in0 = dq, in1 = dlogD, in2 = dlogmua (each may be NULL);
+ *   DMGS_BATCH_VJP: rho = S q, then out0 = qbar = S^T rhobar with in0 =
+ *                   rhobar, and out1 = logD_bar, out2 = logmua_bar (each may
+ *                   be NULL).
+ * tag is returned with the request's results.  Errors: DMGS_ERR_INVALID (an
+ * ineligible plan, a plan already serving a request of the batch, NULL
+ * arrays), DMGS_ERR_OOM. */
+int dmgs_batch_add(dmgs_batch batch, dmgs_plan plan, int32_t mode, const double *q, const double *in0,
+                   const double *in1, const double *in2, double *rho, double *out0, double *out1, double *out2,
+                   int64_t tag);
+/* Requests added and not yet reported. */
+int dmgs_batch_pending(dmgs_batch batch);
+/* One tick on `stream`: one refinement step for every active request (a new
+ * request's first tick forms its initial residual), in grouped launches,
+ * then one synchronisation of the stream.  Up to `cap` requests that
+ * finished are reported: tags[i], status[i] (DMGS_OK, or the status that
+ * ended the request: a forward solve that fails ends it), and the forward
+ * and second solve's infos (info_fwd, info_second may be NULL; a skipped
+ * second solve reports zeros).  *count = number reported; later finishers wait
+ * for the next tick.  Returns DMGS_OK unless the tick itself failed (then the
+ * batch should be destroyed). */
+int dmgs_batch_tick(dmgs_batch batch, void *stream, int32_t cap, int64_t *tags, int32_t *status,
+                    dmgs_info *info_fwd, dmgs_info *info_second, int32_t *count);
+/* Ticks run, grouped launches issued, and the single-request launches they
+ * replaced, since the batch was created. */
+int dmgs_batch_stats(dmgs_batch batch, int64_t *ticks, int64_t *launches, int64_t *recorded);
+
 const char *dmgs_status_string(int status);
 const char *dmgs_last_error(void);
 

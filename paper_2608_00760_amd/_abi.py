@@ -71,7 +71,16 @@ SIGNATURES = {
     "dmgs_timing_read": (_i, [_vp, _i, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "dmgs_trace_read": (_i, [_vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                              C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "dmgs_batch_create": (_i, [C.POINTER(_vp)]),
+    "dmgs_batch_destroy": (_i, [_vp]),
+    "dmgs_batch_add": (_i, [_vp, _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int64]),
+    "dmgs_batch_pending": (_i, [_vp]),
+    "dmgs_batch_tick": (_i, [_vp, _vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(Info),
+                             C.POINTER(Info), C.POINTER(C.c_int32)]),
+    "dmgs_batch_stats": (_i, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
 }
+
+DMGS_BATCH_JVP, DMGS_BATCH_VJP = 0, 1
 
 KERNEL_CLASSES = ["smooth", "defect_restrict", "prolong", "residual", "update", "coef", "grad"]
 

@@ -333,6 +333,7 @@ double* norm_dst(dmgs_plan P) { return P->arena ? P->dnorm : P->hnorm; }
 
 // After the last norm reduction enqueued on st.
 int mark_norms(dmgs_plan P, hipStream_t st) {
+    if (P->rec) return DMGS_OK;   // a batch tick synchronises itself
     if (!P->arena) HIPCHK(hipEventRecord(P->ev_norm, st));
     P->tmark = P->tpending;
     return DMGS_OK;
@@ -369,7 +370,7 @@ int timing_flush(dmgs_plan P, int upto = -1) {
 // k is the finest level and it is the class's sampled launch.
 int tbeg(dmgs_plan P, int k, hipStream_t st, int* slot, int cls) {
     *slot = -1;
-    if (!P->timing || k != 0) return DMGS_OK;
+    if (!P->timing || k != 0 || P->rec) return DMGS_OK;
     if (P->t_seen[cls]++ % P->tstride != 0) return DMGS_OK;
     if (P->tpending == kTimerSlots) TRY(timing_flush(P));
     *slot = P->tpending++;
@@ -400,6 +401,43 @@ int tend(dmgs_plan P, int slot, int cls, double bytes, hipStream_t st) {
 // Cycle building blocks.  Levels with N >= kFuseMin use the fused streaming
 // passes (out of place, ping-pong between the level's two buffers); smaller
 // levels use one launch per operation, in place.
+
+// Lay `count` recorded launches of one grouped kernel out as its Group table.
+template <class Args>
+void write_group(unsigned char* dst, const RecOp* const* ops, int count, const int* start) {
+    Group<Args>* g = reinterpret_cast<Group<Args>*>(dst);
+    std::memset(g, 0, sizeof(Group<Args>));
+    g->count = count;
+    for (int i = 0; i <= count; i++) g->start[i] = start[i];
+    for (int i = 0; i < count; i++) {
+        g->nblk[i] = (int)ops[i]->nblk;
+        std::memcpy(&g->a[i], ops[i]->args, sizeof(Args));
+    }
+}
+
+// Launch kernel `solo` with the one argument a, or, while the plan records
+// (grouped execution), append the launch of its grouped form `grp` instead.
+template <class Args>
+int launch_rec(dmgs_plan P, const void* solo, const void* grp, unsigned nb, unsigned threads, size_t lds, const Args& a,
+               hipStream_t st) {
+    if (P->rec) {
+        static_assert(sizeof(Args) <= sizeof(RecOp::args), "kernel arguments exceed a recorded launch");
+        if (!grp) { set_error("internal: a launch without a grouped form in grouped execution"); return DMGS_ERR_INVALID; }
+        RecOp op;
+        op.fn = grp;
+        op.nblk = nb;
+        op.threads = threads;
+        op.lds = lds;
+        op.table_bytes = sizeof(Group<Args>);
+        op.write = write_group<Args>;
+        std::memcpy(op.args, &a, sizeof(Args));
+        P->rec->push_back(op);
+        return DMGS_OK;
+    }
+    void* kargs[] = {const_cast<Args*>(&a)};
+    HIPCHK(hipLaunchKernel(solo, dim3(nb), dim3(threads), kargs, lds, st));
+    return DMGS_OK;
+}
 
 template <class T>
 int fill(T* a, int64_t nv, T val, hipStream_t st) {
@@ -576,15 +614,23 @@ int launch_sweep2(dmgs_plan P, const SweepArgs<T>& a0, int N, int mode, hipStrea
             set_error("internal: two-sweep norm pass needs a plain pass of at most %d workgroups", kMaxPartials);
             return DMGS_ERR_INVALID;
         }
+        if (P->rec) { set_error("internal: the float64 norm pass in grouped execution"); return DMGS_ERR_INVALID; }
         hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepPlain, HARM, false, true>), dim3(nb), dim3(NT), lds, st, a);
         LAUNCHCHK();
         return DMGS_OK;
     }
-    if (mode == kSweepZero) hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepZero, HARM, DEFECT>), dim3(nb), dim3(NT), lds, st, a);
-    else if (mode == kSweepPlain) hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepPlain, HARM, DEFECT>), dim3(nb), dim3(NT), lds, st, a);
-    else if constexpr (!DEFECT) hipLaunchKernelGGL((k_rb_sweep2_col<T, TY, TZ, kSweepProlong, HARM>), dim3(nb), dim3(NT), lds, st, a);
-    LAUNCHCHK();
-    return DMGS_OK;
+    // grouped forms exist for the float32 passes (refinement plans)
+    auto go = [&](auto Mc) {
+        constexpr int M = decltype(Mc)::value;
+        const void* grp = nullptr;
+        if constexpr (sizeof(T) == 4) grp = (const void*)k_rb_sweep2_grp<T, TY, TZ, M, HARM, DEFECT>;
+        return launch_rec(P, (const void*)k_rb_sweep2_col<T, TY, TZ, M, HARM, DEFECT>, grp, (unsigned)nb, NT, lds, a, st);
+    };
+    if (mode == kSweepZero) return go(std::integral_constant<int, kSweepZero>());
+    if (mode == kSweepPlain) return go(std::integral_constant<int, kSweepPlain>());
+    if constexpr (!DEFECT) return go(std::integral_constant<int, kSweepProlong>());
+    set_error("internal: no defect output after prolongation");
+    return DMGS_ERR_INVALID;
 }
 
 constexpr int kSweep2TY = 16, kSweep2TZ = 64;     // tiles of the two-sweep passes
@@ -608,6 +654,16 @@ int sweep2_attributes() {
         {(const void*)k_rb_sweep2_col<float, kSweep2DTY, kSweep2DTZ, kSweepZero, false, true>, ldsd},
         {(const void*)k_rb_sweep2_col<float, kSweep2DTY, kSweep2DTZ, kSweepPlain, true, true>, ldsd},
         {(const void*)k_rb_sweep2_col<float, kSweep2DTY, kSweep2DTZ, kSweepZero, true, true>, ldsd},
+        {(const void*)k_rb_sweep2_grp<float, kSweep2TY, kSweep2TZ, kSweepPlain, false>, lds},
+        {(const void*)k_rb_sweep2_grp<float, kSweep2TY, kSweep2TZ, kSweepZero, false>, lds},
+        {(const void*)k_rb_sweep2_grp<float, kSweep2TY, kSweep2TZ, kSweepProlong, false>, lds},
+        {(const void*)k_rb_sweep2_grp<float, kSweep2TY, kSweep2TZ, kSweepPlain, true>, lds},
+        {(const void*)k_rb_sweep2_grp<float, kSweep2TY, kSweep2TZ, kSweepZero, true>, lds},
+        {(const void*)k_rb_sweep2_grp<float, kSweep2TY, kSweep2TZ, kSweepProlong, true>, lds},
+        {(const void*)k_rb_sweep2_grp<float, kSweep2DTY, kSweep2DTZ, kSweepPlain, false, true>, ldsd},
+        {(const void*)k_rb_sweep2_grp<float, kSweep2DTY, kSweep2DTZ, kSweepZero, false, true>, ldsd},
+        {(const void*)k_rb_sweep2_grp<float, kSweep2DTY, kSweep2DTZ, kSweepPlain, true, true>, ldsd},
+        {(const void*)k_rb_sweep2_grp<float, kSweep2DTY, kSweep2DTZ, kSweepZero, true, true>, ldsd},
         {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepPlain, false>, lds64},
         {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepZero, false>, lds64},
         {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepProlong, false>, lds64},
@@ -704,9 +760,9 @@ int launch_restrict(dmgs_plan P, const RestrictArgs<T>& a0, int Nc, hipStream_t 
     if (a.chunk > Nc - 1) a.chunk = Nc - 1;
     a.nchunks = (Nc - 1 + a.chunk - 1) / a.chunk;
     int nb = a.tiles_y * a.tiles_z * a.nchunks;
-    hipLaunchKernelGGL((k_defect_restrict_col<T, TYC, TZC, HARM, FROM_R>), dim3(nb), dim3(NT), 0, st, a);
-    LAUNCHCHK();
-    return DMGS_OK;
+    const void* grp = nullptr;
+    if constexpr (sizeof(T) == 4) grp = (const void*)k_defect_restrict_grp<T, TYC, TZC, HARM, FROM_R>;
+    return launch_rec(P, (const void*)k_defect_restrict_col<T, TYC, TZC, HARM, FROM_R>, grp, (unsigned)nb, NT, 0, a, st);
 }
 
 // qc = R (q - A u); from_r: u holds the defect itself after pre-smoothing
@@ -800,9 +856,8 @@ template <class T, int MODE, bool HARM>
 int launch_block_t(dmgs_plan P, const BlockArgs<T>& a, hipStream_t st) {
     const int nb3 = a.nb * a.nb * a.nb;
     const size_t lds = BlockShape<kBlockB, MODE>::lds_bytes(sizeof(T));
-    hipLaunchKernelGGL((k_block_pass<T, kBlockB, MODE, HARM>), dim3(nb3), dim3(kBlockThreads), lds, st, a);
-    LAUNCHCHK();
-    return DMGS_OK;
+    return launch_rec(P, (const void*)k_block_pass<T, kBlockB, MODE, HARM>, (const void*)k_block_grp<T, kBlockB, MODE, HARM>,
+                      (unsigned)nb3, kBlockThreads, lds, a, st);
 }
 
 // One block phase on level k: pre (from *cur or from zero; qc written) or
@@ -847,12 +902,15 @@ int block_attributes() {
     const void* fns[] = {
         (const void*)k_block_pass<float, kBlockB, kBlockPreZero, false>, (const void*)k_block_pass<float, kBlockB, kBlockPreZero, true>,
         (const void*)k_block_pass<float, kBlockB, kBlockPre, false>, (const void*)k_block_pass<float, kBlockB, kBlockPre, true>,
-        (const void*)k_block_pass<float, kBlockB, kBlockPost, false>, (const void*)k_block_pass<float, kBlockB, kBlockPost, true>};
+        (const void*)k_block_pass<float, kBlockB, kBlockPost, false>, (const void*)k_block_pass<float, kBlockB, kBlockPost, true>,
+        (const void*)k_block_grp<float, kBlockB, kBlockPreZero, false>, (const void*)k_block_grp<float, kBlockB, kBlockPreZero, true>,
+        (const void*)k_block_grp<float, kBlockB, kBlockPre, false>, (const void*)k_block_grp<float, kBlockB, kBlockPre, true>,
+        (const void*)k_block_grp<float, kBlockB, kBlockPost, false>, (const void*)k_block_grp<float, kBlockB, kBlockPost, true>};
     const int lims[] = {(int)BlockShape<kBlockB, kBlockPreZero>::lds_bytes(4), (int)BlockShape<kBlockB, kBlockPreZero>::lds_bytes(4),
                         (int)BlockShape<kBlockB, kBlockPre>::lds_bytes(4), (int)BlockShape<kBlockB, kBlockPre>::lds_bytes(4),
                         (int)BlockShape<kBlockB, kBlockPost>::lds_bytes(4), (int)BlockShape<kBlockB, kBlockPost>::lds_bytes(4)};
-    for (int i = 0; i < 6; i++)
-        if (hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, lims[i]) != hipSuccess) {
+    for (int i = 0; i < 12; i++)
+        if (hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, lims[i % 6]) != hipSuccess) {
             set_error("hipFuncSetAttribute failed");
             return DMGS_ERR_HIP;
         }
@@ -924,9 +982,9 @@ int launch_small_t(dmgs_plan P, int k, const T* q, T* u, int order, hipStream_t 
     a.order = order;
     a.roff = off;
     size_t bytes = small_lds_bytes<T>(Ns, a.nlev);
-    hipLaunchKernelGGL((k_small_vcycle<T, HARM>), dim3(1), dim3(kSmallThreads), bytes, st, a);
-    LAUNCHCHK();
-    return DMGS_OK;
+    const void* grp = nullptr;
+    if constexpr (sizeof(T) == 4) grp = (const void*)k_small_grp<T, HARM>;
+    return launch_rec(P, (const void*)k_small_vcycle<T, HARM>, grp, 1u, kSmallThreads, bytes, a, st);
 }
 
 template <class T>
@@ -1027,7 +1085,7 @@ IrArgs ir_shape(int N, int sums) {
 }
 
 template <bool HAS_E, bool X_ZERO, bool HARM, bool EPI>
-void launch_ir(const IrArgs& a0, int N, hipStream_t st, unsigned* nb_out) {
+int launch_ir(dmgs_plan P, const IrArgs& a0, int N, hipStream_t st, unsigned* nb_out) {
     IrArgs a = a0;
     const IrArgs sh = ir_shape(N, EPI ? 3 : 1);
     a.tiles_y = sh.tiles_y;
@@ -1035,14 +1093,27 @@ void launch_ir(const IrArgs& a0, int N, hipStream_t st, unsigned* nb_out) {
     a.chunk = sh.chunk;
     a.nchunks = sh.nchunks;
     unsigned nb = (unsigned)(a.tiles_y * a.tiles_z * a.nchunks);
-    hipLaunchKernelGGL((k_ir_residual_col<kIrTY, kIrTZ, HAS_E, X_ZERO, HARM, EPI>), dim3(nb),
-                       dim3(IrShape<kIrTY, kIrTZ>::NT), 0, st, a);
     *nb_out = nb;
+    const void* grp = nullptr;   // the epilogue does not run in grouped execution
+    if constexpr (!EPI) grp = (const void*)k_ir_residual_grp<kIrTY, kIrTZ, HAS_E, X_ZERO, HARM>;
+    return launch_rec(P, (const void*)k_ir_residual_col<kIrTY, kIrTZ, HAS_E, X_ZERO, HARM, EPI>, grp, nb,
+                      IrShape<kIrTY, kIrTZ>::NT, 0, a, st);
 }
 
 template <bool HAS_E, bool X_ZERO, bool EPI>
-void launch_ir_h(const IrArgs& a, int N, bool h, hipStream_t st, unsigned* nb) {
-    h ? launch_ir<HAS_E, X_ZERO, true, EPI>(a, N, st, nb) : launch_ir<HAS_E, X_ZERO, false, EPI>(a, N, st, nb);
+int launch_ir_h(dmgs_plan P, const IrArgs& a, int N, bool h, hipStream_t st, unsigned* nb) {
+    return h ? launch_ir<HAS_E, X_ZERO, true, EPI>(P, a, N, st, nb) : launch_ir<HAS_E, X_ZERO, false, EPI>(P, a, N, st, nb);
+}
+
+// Sum `count` partials into norm slot `slot` (recorded in grouped execution).
+int sum_partials(dmgs_plan P, const double* partial, int count, int slot, hipStream_t st) {
+    if (P->rec) {
+        SumArgs s{partial, count, norm_dst(P), slot};
+        return launch_rec(P, nullptr, (const void*)k_sum_grp, 1u, 1024u, 0, s, st);
+    }
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, partial, count, norm_dst(P), slot);
+    LAUNCHCHK();
+    return DMGS_OK;
 }
 
 // x_zero: x is 0 everywhere (the boundary value is 0 and nothing has been
@@ -1079,29 +1150,24 @@ int ir_step(dmgs_plan P, const double* x, const float* e, double* x_out, const d
     int tslot;
     TRY(tbeg(P, 0, st, &tslot, DMGS_K_RESIDUAL));
     const bool h = harmonic(P);
+    if (epi && P->rec) { set_error("internal: the likelihood epilogue in grouped execution"); return DMGS_ERR_INVALID; }
     if (epi) {
-        if (!e) launch_ir_h<false, false, true>(a, l.N, h, st, &nb);
-        else if (x_zero) launch_ir_h<true, true, true>(a, l.N, h, st, &nb);
-        else launch_ir_h<true, false, true>(a, l.N, h, st, &nb);
+        if (!e) TRY((launch_ir_h<false, false, true>(P, a, l.N, h, st, &nb)));
+        else if (x_zero) TRY((launch_ir_h<true, true, true>(P, a, l.N, h, st, &nb)));
+        else TRY((launch_ir_h<true, false, true>(P, a, l.N, h, st, &nb)));
     } else if (e) {
-        if (x_zero) launch_ir_h<true, true, false>(a, l.N, h, st, &nb);
-        else launch_ir_h<true, false, false>(a, l.N, h, st, &nb);
+        if (x_zero) TRY((launch_ir_h<true, true, false>(P, a, l.N, h, st, &nb)));
+        else TRY((launch_ir_h<true, false, false>(P, a, l.N, h, st, &nb)));
     } else {
-        if (x_zero) launch_ir_h<false, true, false>(a, l.N, h, st, &nb);
-        else launch_ir_h<false, false, false>(a, l.N, h, st, &nb);
+        if (x_zero) TRY((launch_ir_h<false, true, false>(P, a, l.N, h, st, &nb)));
+        else TRY((launch_ir_h<false, false, false>(P, a, l.N, h, st, &nb)));
     }
-    LAUNCHCHK();
     TRY(tend(P, tslot, DMGS_K_RESIDUAL, bytes, st));
     // the final sums go straight to the plan's pinned host slots
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial, (int)nb, norm_dst(P), slot);
-    LAUNCHCHK();
+    TRY(sum_partials(P, (const double*)P->partial, (int)nb, slot, st));
     if (epi) {
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial + nb, (int)nb,
-                           norm_dst(P), 2);
-        LAUNCHCHK();
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, (const double*)P->partial + 2 * nb, (int)nb,
-                           norm_dst(P), 3);
-        LAUNCHCHK();
+        TRY(sum_partials(P, (const double*)P->partial + nb, (int)nb, 2, st));
+        TRY(sum_partials(P, (const double*)P->partial + 2 * nb, (int)nb, 3, st));
     }
     return mark_norms(P, st);
 }
@@ -2401,7 +2467,8 @@ int plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
     if (st == DMGS_OK) {
         const int lim = (int)kSmallLdsLimit;
         const void* fns[] = {(const void*)k_small_vcycle<float, false>, (const void*)k_small_vcycle<float, true>,
-                             (const void*)k_small_vcycle<double, false>, (const void*)k_small_vcycle<double, true>};
+                             (const void*)k_small_vcycle<double, false>, (const void*)k_small_vcycle<double, true>,
+                             (const void*)k_small_grp<float, false>, (const void*)k_small_grp<float, true>};
         for (const void* f : fns)
             if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) {
                 set_error("hipFuncSetAttribute failed");
@@ -3276,3 +3343,5 @@ int dmgs_debug_cycles(dmgs_plan P, int order, int ncycles, const double* q, doub
 }
 
 }  // extern "C"
+
+#include "batch.hpp"

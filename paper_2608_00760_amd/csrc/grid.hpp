@@ -34,6 +34,34 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
 
 constexpr int kWave = 64;
 
+// Grouped launches: one launch runs the same kernel for several requests.
+// Member m owns the grid's blocks [start[m], start[m+1]) and runs with its
+// own arguments a[m] on the first nblk[m] of them (block index within the
+// member bid = blockIdx.x - start[m]); the host starts every member at a
+// multiple of 8 blocks, so a member's blocks fall on the XCDs as in a
+// launch of its own, and the blocks past nblk[m] exit at once.
+constexpr int kGroupMax = 16;
+
+template <class Args>
+struct Group {
+    int count;
+    int start[kGroupMax + 1];
+    int nblk[kGroupMax];
+    Args a[kGroupMax];
+};
+
+// This block's member, and its block index within the member (-1: a
+// padding block, which does nothing).
+template <class Args>
+__device__ __forceinline__ int group_member(const Group<Args>* g, int* bid) {
+    const int b = blockIdx.x;
+    int m = 0;
+    while (m + 1 < g->count && b >= g->start[m + 1]) m++;
+    const int i = b - g->start[m];
+    *bid = i < g->nblk[m] ? i : -1;
+    return m;
+}
+
 __host__ __device__ inline int64_t vidx(int n, int x, int y, int z) {
     return ((int64_t)x * n + y) * n + z;
 }

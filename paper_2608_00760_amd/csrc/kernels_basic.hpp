@@ -390,6 +390,26 @@ __global__ void k_sum_partials(const double* __restrict__ partial, int count, do
     if (threadIdx.x == 0) out[slot] = b;
 }
 
+// Arguments of k_sum_partials; grouped form, one workgroup per member (the
+// same sums, in the same order).
+struct SumArgs {
+    const double* partial;
+    int count;
+    double* out;
+    int slot;
+};
+
+__global__ void k_sum_grp(const Group<SumArgs>* g) {
+    int bid;
+    const int m = group_member(g, &bid);
+    if (bid < 0) return;
+    const SumArgs a = g->a[m];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < a.count; i += blockDim.x) acc += a.partial[i];
+    double b = block_sum(acc);
+    if (threadIdx.x == 0) a.out[a.slot] = b;
+}
+
 // Iterative refinement, float64 step: r32 = float(q - A u) on interior
 // vertices (0 on the boundary), partial[block] = sum of (q - A u)^2.
 __global__ void k_resid_cast(const double* __restrict__ u, const double* __restrict__ q, const double* __restrict__ D,

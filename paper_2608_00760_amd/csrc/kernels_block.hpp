@@ -54,7 +54,7 @@ struct BlockShape {
 constexpr int kBlockThreads = 1024;
 
 template <class T, int B, int MODE, bool HARM>
-__global__ __launch_bounds__(kBlockThreads) void k_block_pass(BlockArgs<T> a) {
+__device__ __forceinline__ void block_pass_body(const BlockArgs<T>& a, const int bid) {
     using Sh = BlockShape<B, MODE>;
     constexpr int R = Sh::R, S = Sh::S, V = Sh::V, S0 = Sh::S0;
     extern __shared__ __align__(16) unsigned char block_smem[];
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_pass(BlockArgs<T> a) {
     T* const lw = lu + 3 * V;
     T* const lr = lu + 4 * V;   // defect (pre)
     const int N = a.N, n = N + 1, tid = threadIdx.x;
-    const int bx = blockIdx.x / (a.nb * a.nb), by = (blockIdx.x / a.nb) % a.nb, bz = blockIdx.x % a.nb;
+    const int bx = bid / (a.nb * a.nb), by = (bid / a.nb) % a.nb, bz = bid % a.nb;
     const int ox = 1 + bx * B, oy = 1 + by * B, oz = 1 + bz * B;   // block origin (grid coordinates)
     const int bxg = ox - R, byg = oy - R, bzg = oz - R;             // box origin
     const int first = a.order;
@@ -191,6 +191,20 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_pass(BlockArgs<T> a) {
             a.qc[((int64_t)X * ncv + Y) * ncv + Z] = sacc * T(1.0 / 64.0);
         }
     }
+}
+
+template <class T, int B, int MODE, bool HARM>
+__global__ __launch_bounds__(kBlockThreads) void k_block_pass(BlockArgs<T> a) {
+    block_pass_body<T, B, MODE, HARM>(a, blockIdx.x);
+}
+
+template <class T, int B, int MODE, bool HARM>
+__global__ __launch_bounds__(kBlockThreads) void k_block_grp(const Group<BlockArgs<T>>* g) {
+    int bid;
+    const int m = group_member(g, &bid);
+    if (bid < 0) return;
+    const BlockArgs<T> a = g->a[m];
+    block_pass_body<T, B, MODE, HARM>(a, bid);
 }
 
 }  // namespace dmgs

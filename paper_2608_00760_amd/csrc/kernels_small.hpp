@@ -65,7 +65,7 @@ __host__ __device__ inline size_t small_lds_bytes(const int* Ns, int nlev) {
 __device__ __forceinline__ int ilog2_ceil(int v) { return v <= 1 ? 0 : 32 - __builtin_clz(v - 1); }
 
 template <class T, bool HARM>
-__global__ __launch_bounds__(kSmallThreads) void k_small_vcycle(SmallArgs<T> a) {
+__device__ __forceinline__ void small_vcycle_body(const SmallArgs<T>& a) {
     extern __shared__ __align__(16) unsigned char small_smem[];
     T* const base = reinterpret_cast<T*>(small_smem);
     // level arrays addressed from the LDS base (no pointer tables: they
@@ -252,6 +252,21 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_vcycle(SmallArgs<T> a) 
     }
     const int n0 = a.lev[0].N + 1, nv0 = n0 * n0 * n0;
     for (int v = tid; v < nv0; v += kSmallThreads) a.u[v] = U(0)[v];
+}
+
+template <class T, bool HARM>
+__global__ __launch_bounds__(kSmallThreads) void k_small_vcycle(SmallArgs<T> a) {
+    small_vcycle_body<T, HARM>(a);
+}
+
+// Grouped form: one workgroup per member.
+template <class T, bool HARM>
+__global__ __launch_bounds__(kSmallThreads) void k_small_grp(const Group<SmallArgs<T>>* g) {
+    int bid;
+    const int m = group_member(g, &bid);
+    if (bid < 0) return;
+    const SmallArgs<T> a = g->a[m];
+    small_vcycle_body<T, HARM>(a);
 }
 
 }  // namespace dmgs

@@ -299,8 +299,8 @@ struct RestrictShape {
 
 // FROM_R: the fine defect is given (in a.u, 0 off the interior; the colour
 // a.rzero is taken as 0 and not read) and only restricted.
-template <class T, int TYC, int TZC, bool HARM, bool FROM_R = false>
-__global__ __launch_bounds__((RestrictShape<TYC, TZC>::NT)) void k_defect_restrict_col(RestrictArgs<T> a) {
+template <class T, int TYC, int TZC, bool HARM, bool FROM_R>
+__device__ __forceinline__ void defect_restrict_body(const RestrictArgs<T>& a, const int bid) {
     using Sh = RestrictShape<TYC, TZC>;
     constexpr int NP = Sh::NP, RY = Sh::RY, RZ = Sh::RZ, RA = Sh::RA;
     __shared__ T sU[2][RA];
@@ -313,7 +313,7 @@ __global__ __launch_bounds__((RestrictShape<TYC, TZC>::NT)) void k_defect_restri
     const bool act = tid < RY * NP;
     const int ly = act ? tid / NP : 0, pz = act ? tid % NP : 0;
     const int nb = a.tiles_y * a.tiles_z * a.nchunks;
-    const int b = xcd_tile(blockIdx.x, nb);
+    const int b = xcd_tile(bid, nb);
     const int bz = b % a.tiles_z, by = (b / a.tiles_z) % a.tiles_y, bx = b / (a.tiles_z * a.tiles_y);
     const int Y0 = 1 + by * TYC, Z0 = 1 + bz * TZC;
     const int Xa = 1 + bx * a.chunk, Xb = min(Nc, Xa + a.chunk);   // coarse planes [Xa, Xb)
@@ -419,6 +419,20 @@ __global__ __launch_bounds__((RestrictShape<TYC, TZC>::NT)) void k_defect_restri
     if (cown) restrict_plane(p_last);
 }
 
+template <class T, int TYC, int TZC, bool HARM, bool FROM_R = false>
+__global__ __launch_bounds__((RestrictShape<TYC, TZC>::NT)) void k_defect_restrict_col(RestrictArgs<T> a) {
+    defect_restrict_body<T, TYC, TZC, HARM, FROM_R>(a, blockIdx.x);
+}
+
+template <class T, int TYC, int TZC, bool HARM, bool FROM_R = false>
+__global__ __launch_bounds__((RestrictShape<TYC, TZC>::NT)) void k_defect_restrict_grp(const Group<RestrictArgs<T>>* g) {
+    int bid;
+    const int m = group_member(g, &bid);
+    if (bid < 0) return;
+    const RestrictArgs<T> a = g->a[m];
+    defect_restrict_body<T, TYC, TZC, HARM, FROM_R>(a, bid);
+}
+
 // ---------------------------------------------------------------------------
 // Float64 refinement step (and the plain float64 residual norm): threads own
 // column pairs of the tile plus a ring of 1 in y and one pair in z.
@@ -464,8 +478,9 @@ struct IrShape {
 
 // X_ZERO: the iterate x is 0 everywhere (not read): with e, x_out = e;
 // without e, the residual is b itself.
-template <int TY, int TZ, bool HAS_E, bool X_ZERO, bool HARM, bool EPI = false>
-__global__ __launch_bounds__((IrShape<TY, TZ>::NT)) void k_ir_residual_col(IrArgs a) {
+// One workgroup (bid of nblk) of the refinement step.
+template <int TY, int TZ, bool HAS_E, bool X_ZERO, bool HARM, bool EPI>
+__device__ __forceinline__ void ir_residual_body(const IrArgs& a, const int bid, const int nblk) {
     using Sh = IrShape<TY, TZ>;
     constexpr int NP = Sh::NP, RY = Sh::RY, RZ = Sh::RZ, RA = Sh::RA;
     __shared__ double sU[2][RA];
@@ -477,8 +492,8 @@ __global__ __launch_bounds__((IrShape<TY, TZ>::NT)) void k_ir_residual_col(IrArg
     const bool act = tid < RY * NP;
     const int ly = act ? tid / NP : 0, pz = act ? tid % NP : 0;
     const int nb = a.tiles_y * a.tiles_z * a.nchunks;
-    const int bid = xcd_tile(blockIdx.x, nb);
-    const int bz = bid % a.tiles_z, by = (bid / a.tiles_z) % a.tiles_y, bx = bid / (a.tiles_z * a.tiles_y);
+    const int tb = xcd_tile(bid, nb);
+    const int bz = tb % a.tiles_z, by = (tb / a.tiles_z) % a.tiles_y, bx = tb / (a.tiles_z * a.tiles_y);
     const int y0 = by * TY, z0 = bz * TZ;
     const int y = y0 - 1 + ly, zl = z0 - 2 + 2 * pz;
     const int xa = 1 + bx * a.chunk, xb = min(N, xa + a.chunk);   // planes [xa, xb)
@@ -618,9 +633,23 @@ __global__ __launch_bounds__((IrShape<TY, TZ>::NT)) void k_ir_residual_col(IrArg
         for (int k = 0; k < (EPI ? 3 : 1); k++) {
             double s = 0.0;
             for (int i = 0; i < Sh::NT / 64; i++) s += wsum[k][i];
-            a.partial[k * gridDim.x + blockIdx.x] = s;
+            a.partial[k * nblk + bid] = s;
         }
     }
+}
+
+template <int TY, int TZ, bool HAS_E, bool X_ZERO, bool HARM, bool EPI = false>
+__global__ __launch_bounds__((IrShape<TY, TZ>::NT)) void k_ir_residual_col(IrArgs a) {
+    ir_residual_body<TY, TZ, HAS_E, X_ZERO, HARM, EPI>(a, blockIdx.x, gridDim.x);
+}
+
+template <int TY, int TZ, bool HAS_E, bool X_ZERO, bool HARM, bool EPI = false>
+__global__ __launch_bounds__((IrShape<TY, TZ>::NT)) void k_ir_residual_grp(const Group<IrArgs>* g) {
+    int bid;
+    const int m = group_member(g, &bid);
+    if (bid < 0) return;
+    const IrArgs a = g->a[m];
+    ir_residual_body<TY, TZ, HAS_E, X_ZERO, HARM, EPI>(a, bid, g->nblk[m]);
 }
 
 // Set the boundary layer of an iterate to g (interior untouched).

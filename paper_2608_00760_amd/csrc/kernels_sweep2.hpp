@@ -98,8 +98,9 @@ __host__ __device__ constexpr bool sweep2_fits(int N, int64_t px) {
     return (px * (N + 20) + 64) * (int64_t)sizeof(T) < (int64_t)kOob;
 }
 
-template <class T, int TY, int TZ, int MODE, bool HARM, bool DEFECT = false, bool NORM = false>
-__global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_rb_sweep2_col(SweepArgs<T> a) {
+// One workgroup of the pass: tile and chunk bid of the level's grid.
+template <class T, int TY, int TZ, int MODE, bool HARM, bool DEFECT, bool NORM>
+__device__ __forceinline__ void rb_sweep2_body(const SweepArgs<T>& a, const int bid) {
     constexpr bool ZERO_INIT = MODE == kSweepZero, PROLONG = MODE == kSweepProlong;
     static_assert(!(DEFECT && PROLONG), "the defect is formed after pre-smoothing only");
     static_assert(!NORM || (MODE == kSweepPlain && !DEFECT), "the input's residual norm needs a plain pass");
@@ -121,7 +122,7 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_r
     const int th = own ? th0 : th0 - Sh::ROWS_HALF * NP;
     const int ly = 2 * (th / NP) + hp, pz = th % NP;
     const int nb = a.tiles_y * a.tiles_z * a.nchunks;
-    const int b = xcd_tile(blockIdx.x, nb);
+    const int b = xcd_tile(bid, nb);
     const int bz = b % a.tiles_z, by = (b / a.tiles_z) % a.tiles_y, bx = b / (a.tiles_z * a.tiles_y);
     const int y0 = by * TY, z0 = bz * TZ;
     const int y = y0 - R + ly, zl = z0 - R + 2 * pz;
@@ -426,8 +427,23 @@ __global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_r
     }
     if constexpr (NORM) {
         const double b = block_sum(nacc);
-        if (tid == 0) a.partial[blockIdx.x] = b;
+        if (tid == 0) a.partial[bid] = b;
     }
+}
+
+template <class T, int TY, int TZ, int MODE, bool HARM, bool DEFECT = false, bool NORM = false>
+__global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_rb_sweep2_col(SweepArgs<T> a) {
+    rb_sweep2_body<T, TY, TZ, MODE, HARM, DEFECT, NORM>(a, blockIdx.x);
+}
+
+// Grouped form (one launch for several requests' passes).
+template <class T, int TY, int TZ, int MODE, bool HARM, bool DEFECT = false, bool NORM = false>
+__global__ __launch_bounds__((Sweep2Shape<TY, TZ, DEFECT ? 5 : 4>::NT)) void k_rb_sweep2_grp(const Group<SweepArgs<T>>* g) {
+    int bid;
+    const int m = group_member(g, &bid);
+    if (bid < 0) return;
+    const SweepArgs<T> a = g->a[m];
+    rb_sweep2_body<T, TY, TZ, MODE, HARM, DEFECT, NORM>(a, bid);
 }
 
 }  // namespace dmgs

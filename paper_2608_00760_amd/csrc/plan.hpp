@@ -72,6 +72,20 @@ template <class T> bool dense(const Level& l) { return Typed<T>::py(l) == l.n; }
 }  // namespace dmgs
 
 namespace dmgs {
+// A launch recorded for grouped execution (a plan records instead of
+// launching while it takes part in a batch tick): the grouped kernel, the
+// member's block count, block size and dynamic LDS, and its arguments;
+// write() lays a group of such launches of one kernel out as that kernel's
+// Group table (start[] holds count + 1 block offsets).
+struct RecOp {
+    const void* fn;
+    unsigned nblk, threads;
+    size_t lds;
+    size_t table_bytes;
+    void (*write)(unsigned char* dst, const RecOp* const* ops, int count, const int* start);
+    alignas(16) unsigned char args[512];
+};
+
 constexpr int kTimerSlots = 512;
 struct TimerRec {
     int cls;
@@ -156,6 +170,9 @@ struct dmgs_plan_s {
     // device memory the plan does not own; the norms and the validation flag
     // are read back by copies and stream synchronisation instead of pinned
     // host memory and events
+    // grouped execution: while set, the launches of the refinement cycle are
+    // appended here instead of being issued
+    std::vector<dmgs::RecOp>* rec = nullptr;
     unsigned char* arena = nullptr;
     size_t arena_cap = 0, arena_used = 0;
     double* dnorm = nullptr;     // device norm slots the reductions write (arena plans)

@@ -351,3 +351,105 @@ class Plan:
         self._call(_abi.lib().dmgs_debug_cycles, "dmgs_debug_cycles", int(order), int(ncycles),
                    self._arr(q, "q"), self._arr(u, "u"), _stream(self.device))
         return u
+
+
+class Batch:
+    """Grouped execution of forward + push-forward / pull-back requests
+    (dmgs_batch_*): each tick() advances every active request by one
+    refinement step in grouped launches and synchronises the stream once.
+
+    add(plan, mode, q, ...) enqueues a request on a plan that serves no other
+    request of the batch; tick() returns the requests that finished, as
+    dicts with the request's tag, status, infos and output tensors.  The
+    batch keeps every request's tensors alive until it is reported.  Results
+    are bitwise those of Plan.forward followed by Plan.jvp / Plan.vjp."""
+
+    def __init__(self, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else torch.device(device).index or 0)
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = _abi.lib().dmgs_batch_create(C.byref(self._h))
+        if st != _abi.DMGS_OK:
+            raise _abi.DMGSError(st, "dmgs_batch_create")
+        self._live = {}
+        self._next_tag = 0
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _abi.lib().dmgs_batch_destroy(self._h)
+            self._h = C.c_void_p()
+        self._live = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, plan, mode, q, dq=None, dlogD=None, dlogmua=None, rhobar=None, coef_grads=True, tag=None):
+        """mode "jvp": rho = S q and drho = S(dq - A' rho); mode "vjp": rho = S q,
+        qbar = S^T rhobar and, with coef_grads, the log-coefficient gradients."""
+        if plan.device != self.device:
+            raise ValueError("the plan lives on another device")
+        tag = self._next_tag if tag is None else int(tag)
+        self._next_tag = max(self._next_tag, tag) + 1
+        rho = plan._empty()
+        out = {"rho": rho}
+        if mode == "jvp":
+            out["drho"] = plan._empty()
+            ins = (plan._arr(dq, "dq", optional=True), plan._arr(dlogD, "dlogD", optional=True),
+                   plan._arr(dlogmua, "dlogmua", optional=True))
+            outs = (plan._arr(out["drho"], "drho"), None, None)
+            m = _abi.DMGS_BATCH_JVP
+        elif mode == "vjp":
+            out["qbar"] = plan._empty()
+            if coef_grads:
+                out["logD_bar"], out["logmua_bar"] = plan._empty(), plan._empty()
+            ins = (plan._arr(rhobar, "rhobar"), None, None)
+            outs = (plan._arr(out["qbar"], "qbar"), plan._arr(out.get("logD_bar"), "logD_bar", optional=True),
+                    plan._arr(out.get("logmua_bar"), "logmua_bar", optional=True))
+            m = _abi.DMGS_BATCH_VJP
+        else:
+            raise ValueError("mode must be 'jvp' or 'vjp'")
+        with torch.cuda.device(self.device):
+            st = _abi.lib().dmgs_batch_add(self._h, plan._h, m, plan._arr(q, "q"), *ins, plan._arr(rho, "rho"), *outs,
+                                           C.c_int64(tag))
+        if st != _abi.DMGS_OK:
+            raise _abi.DMGSError(st, "dmgs_batch_add")
+        # inputs and outputs stay referenced until the request is reported
+        self._live[tag] = {"plan": plan, "mode": mode, "keep": (q, dq, dlogD, dlogmua, rhobar), "out": out}
+        return tag
+
+    def pending(self):
+        return _abi.lib().dmgs_batch_pending(self._h)
+
+    def tick(self, stream=None):
+        n = max(1, len(self._live))
+        tags = (C.c_int64 * n)()
+        status = (C.c_int32 * n)()
+        inf = (_abi.Info * n)()
+        ins = (_abi.Info * n)()
+        count = C.c_int32(0)
+        st_ptr = _stream(self.device) if stream is None else C.c_void_p(stream.cuda_stream)
+        with torch.cuda.device(self.device):
+            st = _abi.lib().dmgs_batch_tick(self._h, st_ptr, n, tags, status, inf, ins, C.byref(count))
+        if st != _abi.DMGS_OK:
+            raise _abi.DMGSError(st, "dmgs_batch_tick")
+        done = []
+        for i in range(count.value):
+            rec = self._live.pop(int(tags[i]))
+            done.append({"tag": int(tags[i]), "status": int(status[i]), "info_fwd": inf[i].as_dict(),
+                         "info_second": ins[i].as_dict(), "mode": rec["mode"], **rec["out"]})
+        return done
+
+    def stats(self):
+        t, l, r = C.c_int64(), C.c_int64(), C.c_int64()
+        _abi.lib().dmgs_batch_stats(self._h, C.byref(t), C.byref(l), C.byref(r))
+        return {"ticks": t.value, "launches": l.value, "recorded": r.value}
+
+    def run(self, stream=None):
+        """Tick until every request has been reported; returns them all."""
+        out = []
+        while self.pending():
+            out.extend(self.tick(stream))
+        return out
