@@ -113,26 +113,41 @@ def serving_leg(nreq):
     First all at t = 0 (saturation throughput), then Poisson arrivals at 0.8 x
     that rate for p50/p99 latency."""
     from paper_2608_00760_amd import synth
-    from paper_2608_00760_amd.serving import Request, Server, summarize
+    from paper_2608_00760_amd.serving import Request, Server, TickServer, summarize
     budget = 96 << 30
 
     def reqs(rate):
         return [Request(id=d["id"], N=d["N"], mode=d["mode"], seed=d["seed"], arrival=d["arrival"])
                 for d in synth.serving_stream(nreq=nreq, rate=rate)]
 
-    srv = Server(budget_bytes=budget, max_slots=8, keep_results=False)
-    srv.run(reqs(None)[:16], realtime=False)      # warm-up: plans for every size
-    burst = summarize(srv.run(reqs(None), realtime=False))
-    rate = 0.8 * burst["requests_per_s"]
-    pois = summarize(srv.run(reqs(rate), realtime=True))
-    peak = srv.adm.peak
-    srv.close()
-    return {"requests": nreq, "sizes": [64, 96, 128, 192], "modes": "50/50 fwd+JVP / fwd+VJP",
-            "saturation_requests_per_s": burst["requests_per_s"], "saturation_solves_per_s": burst["solves_per_s"],
-            "poisson_rate_per_s": rate, "p50_ms": pois["p50_ms"], "p99_ms": pois["p99_ms"],
-            "requests_per_s": pois["requests_per_s"], "solves_per_s": pois["solves_per_s"],
-            "errors": pois["errors"] + burst["errors"], "budget_GB": budget / 1e9, "peak_accounted_GB": peak / 1e9,
-            "max_slots": 8}
+    def measure(srv, other_rate=None):
+        srv.run(reqs(None)[:16], realtime=False)      # warm-up: plans for every size
+        burst = summarize(srv.run(reqs(None), realtime=False))
+        rate = 0.8 * burst["requests_per_s"]
+        pois = summarize(srv.run(reqs(rate), realtime=True))
+        out = {"saturation_requests_per_s": burst["requests_per_s"], "saturation_solves_per_s": burst["solves_per_s"],
+               "poisson_rate_per_s": rate, "p50_ms": pois["p50_ms"], "p99_ms": pois["p99_ms"],
+               "requests_per_s": pois["requests_per_s"], "solves_per_s": pois["solves_per_s"],
+               "errors": pois["errors"] + burst["errors"]}
+        if other_rate:   # latency at the other server's arrival rate
+            same = summarize(srv.run(reqs(other_rate), realtime=True))
+            out["at_thread_rate"] = {"poisson_rate_per_s": other_rate, "p50_ms": same["p50_ms"],
+                                     "p99_ms": same["p99_ms"], "errors": same["errors"]}
+        out["peak_accounted_GB"] = srv.adm.peak / 1e9
+        srv.close()
+        return out
+
+    out = {"requests": nreq, "sizes": [64, 96, 128, 192], "modes": "50/50 fwd+JVP / fwd+VJP", "budget_GB": budget / 1e9,
+           "max_slots": 8, "server": "one HIP stream per admitted request (threads)"}
+    out.update(measure(Server(budget_bytes=budget, max_slots=8, keep_results=False)))
+    # the same streams through grouped ticks (dmgs_batch_*)
+    tick = TickServer(budget_bytes=budget, max_slots=8, keep_results=False)
+    g = measure(tick, out["poisson_rate_per_s"])
+    g["grouped_launches"], g["recorded_launches"] = tick.batch_stats["launches"], tick.batch_stats["recorded"]
+    g["server"] = ("grouped ticks (dmgs_batch_*): a batch per grid size, each ticked on its own stream; a tick runs "
+                   "one refinement step of every request of the batch and synchronises once")
+    out["grouped_ticks"] = g
+    return out
 
 
 def config5_leg(reps=3):
@@ -553,6 +568,12 @@ def main():
         serving = serving_leg(args.serving_requests)
         log("serving: p50 %.2f ms p99 %.2f ms, %.1f requests/s (saturation %.1f)" % (
             serving["p50_ms"], serving["p99_ms"], serving["requests_per_s"], serving["saturation_requests_per_s"]))
+        g = serving["grouped_ticks"]
+        log("serving, grouped ticks: p50 %.2f ms p99 %.2f ms, %.1f requests/s (saturation %.1f); at the thread "
+            "server's rate p50 %.2f ms p99 %.2f ms; %d grouped launches for %d" % (
+                g["p50_ms"], g["p99_ms"], g["requests_per_s"], g["saturation_requests_per_s"],
+                g["at_thread_rate"]["p50_ms"], g["at_thread_rate"]["p99_ms"], g["grouped_launches"],
+                g["recorded_launches"]))
 
     big = None
     if not args.no_512 and not args.sequential:

@@ -320,6 +320,143 @@ class Server:
             self._evict(1 << 62)
 
 
+class TickServer(Server):
+    """The same admission, plan pool and request fields as Server, executed
+    as grouped ticks (dmgs_batch_*).  Admitted requests join the batch of
+    their size class (the classes are split at the bounds in `split`), and
+    each class's batch is ticked by its own host thread on its own HIP
+    stream.  A tick advances every request of the batch by one refinement
+    step in grouped launches and synchronises that stream once.  The classes
+    tick concurrently, so a small request's steps do not wait for a large
+    request's.  A forward +
+    VJP request runs its two solves one after the other (plans need no
+    second work set), so plans are accounted with dmgs_workspace_bytes.
+    Results are bitwise those of Server."""
+
+    def __init__(self, *args, split=(64, 96, 128), **kw):
+        super().__init__(*args, **kw)
+        from .solver import Options, workspace_bytes
+        self._ws = lambda N: workspace_bytes(Options(N, **self.opts))
+        self.split = tuple(split)
+        self.ticks = 0
+        self.batch_stats = None
+
+    def run(self, requests, realtime=True):
+        import torch
+        from .solver import Batch
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.id))
+        if not realtime:
+            for r in reqs:
+                r.arrival = 0.0
+        by_id = {r.id: r for r in reqs}
+        t0 = time.perf_counter()
+        clock = lambda: time.perf_counter() - t0
+        classes = []
+        for _ in range(len(self.split) + 1):
+            classes.append({"stream": torch.cuda.Stream(device=self.device), "batch": Batch(self.device),
+                            "lock": threading.Lock(), "running": {}})
+        state = {"done": 0, "stop": False}
+
+        def retire(cls, d):   # called with self.cv held
+            req = by_id[d["tag"]]
+            need, plan = cls["running"].pop(req.id)
+            req.t_done = clock()
+            req.cycles = (d["info_fwd"]["cycles"], d["info_second"]["cycles"])
+            if d["status"] == 0:
+                req.status = "done"
+                keys = ("rho", "drho") if d["mode"] == "jvp" else ("rho", "qbar", "logD_bar", "logmua_bar")
+                req.result = {k: d[k] for k in keys} if self.keep else {}
+                self.pool[req.N].append(plan)
+                self.pool_order.append((req.N, plan))
+                self.adm.finish(need, self.plan_bytes[req.N])
+            else:   # a failed request is retired with its status, and its plan closed
+                req.status = "error"
+                req.error = "status %d" % d["status"]
+                plan.close()
+                self.plan_live -= self.plan_bytes[req.N]
+                self.adm.finish(need, 0)
+            state["done"] += 1
+
+        def pending(cls):
+            with cls["lock"]:
+                return cls["batch"].pending()
+
+        def worker(cls):
+            with torch.cuda.device(self.device):
+                while True:
+                    with self.cv:
+                        while not state["stop"] and not pending(cls):
+                            self.cv.wait()
+                        if state["stop"]:
+                            return
+                    with cls["lock"]:
+                        finished = cls["batch"].tick(cls["stream"])
+                    with self.cv:
+                        self.ticks += 1
+                        for d in finished:
+                            retire(cls, d)
+                        self.cv.notify_all()
+
+        threads = [threading.Thread(target=worker, args=(c,), daemon=True) for c in classes]
+        for th in threads:
+            th.start()
+        i = 0
+        try:
+            with torch.cuda.device(self.device), self.cv:
+                while state["done"] < len(reqs):
+                    now = clock()
+                    while i < len(reqs) and reqs[i].arrival <= now:
+                        self.adm.offer(reqs[i])
+                        i += 1
+                    while True:
+                        self._release_cache_if_needed()
+                        got = self.adm.next_admissible(self._need_of, self._evict)
+                        if got is None:
+                            break
+                        kind, req, need = got
+                        if kind == "reject":
+                            req.status = "rejected"
+                            req.error = "footprint %d bytes exceeds the budget %d" % (need, self.adm.budget)
+                            req.t_done = clock()
+                            state["done"] += 1
+                            continue
+                        req.t_admit = clock()
+                        plan = self._take_plan(req.N)
+                        if plan is None:
+                            self.plan_live += self.plan_bytes[req.N]
+                            self.plan_peak = max(self.plan_peak, self.plan_live)
+                            plan = self._new_plan(req.N)
+                        cls = classes[sum(req.N > b for b in self.split)]
+                        with torch.cuda.stream(cls["stream"]):
+                            f = request_fields(req, self.device)
+                            plan.set_log_coefficients(f["logD"], f["logmua"])
+                        with cls["lock"]:
+                            if req.mode == "jvp":
+                                cls["batch"].add(plan, "jvp", f["q"], dq=f["dq"], dlogD=f["dlogD"],
+                                                 dlogmua=f["dlogmua"], tag=req.id)
+                            else:
+                                cls["batch"].add(plan, "vjp", f["q"], rhobar=f["rhobar"], tag=req.id)
+                        cls["running"][req.id] = (need, plan)
+                        self.cv.notify_all()
+                    timeout = 0.05
+                    if i < len(reqs):
+                        timeout = max(0.0, min(timeout, reqs[i].arrival - clock()))
+                    self.cv.wait(timeout=timeout)
+                state["stop"] = True
+                self.cv.notify_all()
+        finally:
+            with self.cv:
+                state["stop"] = True
+                self.cv.notify_all()
+            for th in threads:
+                th.join()
+            st = [c["batch"].stats() for c in classes]
+            self.batch_stats = {k: sum(x[k] for x in st) for k in st[0]}
+            for c in classes:
+                c["batch"].close()
+        return reqs
+
+
 def summarize(reqs, wall=None):
     done = [r for r in reqs if r.status == "done"]
     lat = np.array([r.latency for r in done]) if done else np.zeros(1)

@@ -10,7 +10,10 @@
   (64^3, 96^3, 128^3, 192^3) and both request kinds matches the oracle's
   1e-13 solves: rho and rho' (forward + JVP) or rho and the three
   gradients (forward + VJP), to 1e-8 of the largest entry (Sec. 2.4
-  stopping rule at rtol 1e-10).
+  stopping rule at rtol 1e-10);
+* the grouped-tick server (TickServer) returns bitwise the thread server's
+  results and refinement counts, with fewer launches than the requests
+  recorded, and keeps its budget.
 """
 import copy
 
@@ -92,6 +95,42 @@ def test_served_results_match_the_oracle():
         say("served N=%d %s cycles %s: max rel err %s" % (r.N, r.mode, r.cycles,
                                                            {k: "%.1e" % e for k, e in errs.items()}))
         assert max(errs.values()) <= 1e-8, (r.N, r.mode, errs)
+
+
+def test_tick_server_matches_server():
+    """The grouped-tick server returns bitwise the thread server's results
+    (and so meets the oracle as above), within its budget, with fewer
+    launches than the requests' own."""
+    import torch
+    from paper_2608_00760_amd.serving import Request, Server, TickServer, summarize
+    sizes = (64, 96, 128, 192)
+    reqs = [Request(id=i, N=sizes[i % 4], mode=("jvp", "vjp")[(i // 4) % 2], seed=7600 + i, arrival=0.003 * i)
+            for i in range(12)]
+    say("serving: tick server against the thread server")
+    ref_srv = Server(budget_bytes=32 << 30, max_slots=4)
+    want = {r.id: r for r in ref_srv.run(copy.deepcopy(reqs), realtime=False)}
+    ref_srv.close()
+    tick = TickServer(budget_bytes=32 << 30, max_slots=6)
+    got = tick.run(copy.deepcopy(reqs), realtime=True)
+    s = summarize(got)
+    say("  tick server", s, "ticks", tick.ticks, "batch", tick.batch_stats, "peak", tick.adm.peak)
+    assert s["done"] == len(reqs) and tick.adm.peak <= 32 << 30
+    assert tick.batch_stats["launches"] < tick.batch_stats["recorded"]
+    for r in got:
+        w = want[r.id]
+        assert r.cycles == w.cycles, (r.id, r.cycles, w.cycles)
+        assert sorted(r.result) == sorted(w.result)
+        for k, v in r.result.items():
+            assert torch.equal(v, w.result[k]), (r.id, k)
+    tick.close()
+    # a tight budget queues requests; one that can never fit is rejected
+    small = [Request(id=i, N=(32, 64)[i % 2], mode=("jvp", "vjp")[i % 2], seed=7700 + i) for i in range(6)]
+    big = Request(id=99, N=192, mode="vjp", seed=1)
+    tick = TickServer(budget_bytes=400 << 20, max_slots=3, keep_results=False)
+    out = tick.run(small + [big], realtime=False)
+    s = summarize(out)
+    assert s["done"] == 6 and s["rejected"] == 1 and tick.adm.peak <= 400 << 20
+    tick.close()
 
 
 def test_poisson_arrivals_and_rejection():
