@@ -2915,14 +2915,21 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
         LAUNCHCHK();
         return DMGS_OK;
     }
+    // one pass per half-sweep, ubar ping-ponging between W.ubar[k] and W.V[k]
+    // (an even number of half-sweeps per phase leaves it in W.ubar[k])
+    int dchunk = 1;
+    const dim3 dg = der_grid(P, l.N, &dchunk);
     auto half_rev = [&](const double* state, int colour) -> int {
         UNCHK(W, state, l.nv, "a recorded state");
-        hipLaunchKernelGGL(k_un_half_v, dim3(g), dim3(kBlock), 0, st, (const double*)W.ubar[k], state, D, mu, l.N, s,
-                           colour, W.V[k], W.qbar[k], W.mbar[k], chunk);
+        auto launch = [&](auto harm) {
+            hipLaunchKernelGGL(k_un_half_rev<decltype(harm)::value>, dg, dim3(kDerThreads), 0, st,
+                               (const double*)W.ubar[k], W.V[k], state, D, (const double*)l.w64, l.N, s, colour,
+                               W.qbar[k], W.mbar[k], W.Dbar[k], dchunk);
+        };
+        if (s.harmonic) launch(std::true_type());
+        else launch(std::false_type());
         LAUNCHCHK();
-        hipLaunchKernelGGL(k_un_half_gather, dim3(g), dim3(kBlock), 0, st, W.ubar[k], (const double*)W.V[k], state, D,
-                           l.N, s, colour, W.Dbar[k], chunk);
-        LAUNCHCHK();
+        std::swap(W.ubar[k], W.V[k]);
         return DMGS_OK;
     };
     for (int h = 2 * nu2 - 1; h >= 0; h--) TRY(half_rev(W.tape[k][2 * nu1 + h], h & 1));
@@ -3011,6 +3018,7 @@ int dmgs_vjp_unrolled(dmgs_plan P, const double* q, const double* rhobar, double
         TRY(fill<double>(W.mbar[k], nv, 0.0, st));
         TRY(fill<double>(W.qbar[k], nv, 0.0, st));
         TRY(fill<double>(W.ubar[k], nv, 0.0, st));
+        TRY(fill<double>(W.V[k], nv, 0.0, st));   // the partner of ubar in the reverse half-sweeps
     }
     const size_t b0 = l0.nv * sizeof(double);
     // forward: n cycles of the solver's own (fused) V-cycle, keeping the

@@ -15,11 +15,13 @@
 //   defect's coefficient terms with lam;
 //   coefficient coarsening (full weighting, injection on the boundary):
 //     its transpose carries a coarse level's Dbar, mubar to the finer one.
-// The stencil kernels march along x (see UnCol); the others take one vertex
-// per thread.  Cotangents are 0 on boundary vertices except Dbar, which
+// The reverse half-sweep (k_un_half_rev) marches the column tiles of
+// kernels_deriv.hpp; the other stencil kernels march along x (see UnCol);
+// the rest take one vertex per thread.  Cotangents are 0 on boundary vertices except Dbar, which
 // boundary faces reach.
 #pragma once
 #include "kernels_basic.hpp"
+#include "kernels_deriv.hpp"
 
 namespace dmgs {
 
@@ -94,72 +96,110 @@ __global__ void k_un_gs_half(const double* __restrict__ u_in, double* __restrict
     }
 }
 
-// half-sweep reverse, part 1: V = ubar / d on the colour's interior vertices
-// (0 elsewhere); qbar += V; mubar -= V u'
-__global__ void k_un_half_v(const double* __restrict__ ubar, const double* __restrict__ up,
-                            const double* __restrict__ D, const double* __restrict__ mu, int N, Stencil<double> s,
-                            int colour, double* __restrict__ V, double* __restrict__ qbar, double* __restrict__ mubar,
-                            int chunk) {
-    UnCol c;
-    if (!un_col(N, chunk, c)) return;
-    const int n = c.n;
-    const bool yz = c.y > 0 && c.y < N && c.z > 0 && c.z < N;
-    double Dm = c.x0 > 0 ? D[(c.x0 - 1) * c.sx + c.p] : 0.0, Dc = D[c.x0 * c.sx + c.p];
-    for (int x = c.x0; x < c.x1; x++) {
-        const int64_t i = x * c.sx + c.p;
-        const double Dp = x < N ? D[i + c.sx] : 0.0;
-        if (yz && x > 0 && x < N && ((x + c.y + c.z) & 1) == colour) {
-            const double d = mu[i] + face_coef(Dc, Dp, s) + face_coef(Dc, Dm, s) + face_coef(Dc, D[i + n], s) +
-                             face_coef(Dc, D[i - n], s) + face_coef(Dc, D[i + 1], s) + face_coef(Dc, D[i - 1], s);
-            const double v = ubar[i] / d;
-            V[i] = v;
-            qbar[i] += v;
-            mubar[i] -= v * up[i];
-        } else {
-            V[i] = 0.0;
+// The whole reverse of one half-sweep of colour C in one pass (levels the
+// column tiles of kernels_deriv.hpp cover), with V_i = ubar_i w_i (w the
+// inverse diagonal 1 / d_i) formed where it is needed instead of stored:
+//   qbar_i += V_i, mubar_i -= V_i u'_i                      (C's interior)
+//   Dbar_i -= sum over faces of (V_i - V_j)(u'_i - u'_j) dc/dD_i   (every vertex)
+//   ubar_out_i = 0 (C's interior), ubar_in_i + sum_j c_ij V_j (other interior)
+// ubar is read from one buffer and written to another: a workgroup's ring
+// reads ubar of vertices that neighbouring workgroups update.  Boundary
+// entries of ubar_out are not written.  The march, tiles and ring are those
+// of k_coef_grads_col: own column's fields at x - 1, x, x + 1 in registers,
+// the plane's V, u' and D over the tile plus a ring of one in LDS.
+// Neighbours in the order +x, -x, +y, -y, +z, -z, as the two-kernel form.
+template <bool HARM>
+__global__ __launch_bounds__(kDerThreads) void k_un_half_rev(const double* __restrict__ ubar_in,
+                                                            double* __restrict__ ubar_out,
+                                                            const double* __restrict__ up,
+                                                            const double* __restrict__ D,
+                                                            const double* __restrict__ w, int N, Stencil<double> s,
+                                                            int colour, double* __restrict__ qbar,
+                                                            double* __restrict__ mubar, double* __restrict__ Dbar,
+                                                            int chunk) {
+    __shared__ double sV[2][kDerCells], sU[2][kDerCells], sD[2][kDerCells];
+    DerTile t;
+    der_tile(N, chunk, t);
+    const int n = t.n;
+    struct H {
+        double b, w, u, D;   // ubar_in, w, u', D
+    };
+    struct Vp : H {
+        double qb, mb, Db;   // own column only: qbar, mubar, Dbar
+    };
+    const DerSpan sp(t, n);
+    const auto rB = sp.rsrc(ubar_in), rW = sp.rsrc(w), rU = sp.rsrc(up), rD = sp.rsrc(D);
+    const auto rQ = sp.rsrc(qbar), rM = sp.rsrc(mubar), rDb = sp.rsrc(Dbar);
+    auto load_h = [&](int x, bool valid, int64_t p) -> H {
+        const int o = valid ? (int)(p * 8) : kOob, so = sp.off(x);
+        return H{buf_load_s(rB, o, so), buf_load_s(rW, o, so), buf_load_s(rU, o, so), buf_load_s(rD, o, so)};
+    };
+    auto load_v = [&](int x) -> Vp {
+        Vp v;
+        static_cast<H&>(v) = load_h(x, t.own, t.p);
+        const int oo = (t.own && x < t.x1) ? (int)(t.p * 8) : kOob, so = sp.off(x);
+        v.qb = buf_load_s(rQ, oo, so);
+        v.mb = buf_load_s(rM, oo, so);
+        v.Db = buf_load_s(rDb, oo, so);
+        return v;
+    };
+    // V of a vertex from its own fields (0 off C's interior)
+    auto vof = [&](const H& h, int x, int y, int z) {
+        return (is_interior(N, x, y, z) && ((x + y + z) & 1) == colour) ? h.b * h.w : 0.0;
+    };
+    auto fc = [&](double Da, double Db) { return face<HARM>(Da, Db, s); };
+    auto dda = [&](double Da, double Db) {
+        if (HARM) {
+            const double u = Da + Db;
+            return Db * Db / (u * u) * s.two_inv_h2;
         }
-        Dm = Dc;
-        Dc = Dp;
-    }
-}
-
-// half-sweep reverse, part 2: Dbar on every vertex, ubar on interior ones
-__global__ void k_un_half_gather(double* __restrict__ ubar, const double* __restrict__ V, const double* __restrict__ up,
-                                 const double* __restrict__ D, int N, Stencil<double> s, int colour,
-                                 double* __restrict__ Dbar, int chunk) {
-    UnCol c;
-    if (!un_col(N, chunk, c)) return;
-    const int n = c.n;
-    const bool yz = c.y > 0 && c.y < N && c.z > 0 && c.z < N;
-    double Dm = 0.0, Vm = 0.0, um = 0.0;
-    if (c.x0 > 0) {
-        const int64_t j = (c.x0 - 1) * c.sx + c.p;
-        Dm = D[j]; Vm = V[j]; um = up[j];
-    }
-    const int64_t i0 = c.x0 * c.sx + c.p;
-    double Dc = D[i0], Vc = V[i0], uc = up[i0];
-    for (int x = c.x0; x < c.x1; x++) {
-        const int64_t i = x * c.sx + c.p;
-        double Dp = 0.0, Vp = 0.0, upp = 0.0;
-        if (x < N) {
-            Dp = D[i + c.sx]; Vp = V[i + c.sx]; upp = up[i + c.sx];
+        return s.half_inv_h2;
+    };
+    const bool halo = threadIdx.x < kDerHalo;
+    const bool yz = t.y > 0 && t.y < N && t.z > 0 && t.z < N;
+    auto step = [&](int x, Vp& Rm, Vp& Rc, Vp& Rp, Vp& Rl, H& Hc, H& Hl) {
+        const int b = x & 1;
+        const double Vc = vof(Rc, x, t.y, t.z);
+        sV[b][t.cell] = Vc; sU[b][t.cell] = Rc.u; sD[b][t.cell] = Rc.D;
+        if (halo) { sV[b][t.hcell] = vof(Hc, x, t.hy, t.hz); sU[b][t.hcell] = Hc.u; sD[b][t.hcell] = Hc.D; }
+        lds_barrier();
+        Rl = load_v(x + 3);
+        Hl = load_h(x + 2, t.hv, t.hp);
+        if (t.own && x < t.x1) {
+            const int64_t i = x * t.sx + t.p;
+            double dacc = 0.0, gath = 0.0;
+            auto nb = [&](double Dj, double Vj, double uj) {
+                dacc += (Vc - Vj) * (Rc.u - uj) * dda(Rc.D, Dj);
+                gath += fc(Rc.D, Dj) * Vj;
+            };
+            if (x < N) nb(Rp.D, vof(Rp, x + 1, t.y, t.z), Rp.u);
+            if (x > 0) nb(Rm.D, vof(Rm, x - 1, t.y, t.z), Rm.u);
+            auto cell = [&](int e) { nb(sD[b][e], sV[b][e], sU[b][e]); };
+            if (t.y < N) cell(t.cell + kDerRZ);
+            if (t.y > 0) cell(t.cell - kDerRZ);
+            if (t.z < N) cell(t.cell + 1);
+            if (t.z > 0) cell(t.cell - 1);
+            Dbar[i] = Rc.Db - dacc;
+            if (yz && x > 0 && x < N) {
+                if (((x + t.y + t.z) & 1) == colour) {
+                    qbar[i] = Rc.qb + Vc;
+                    mubar[i] = Rc.mb - Vc * Rc.u;
+                    ubar_out[i] = 0.0;
+                } else {
+                    ubar_out[i] = Rc.b + gath;
+                }
+            }
         }
-        double dacc = 0.0, gath = 0.0;
-        // neighbours in the order +x, -x, +y, -y, +z, -z
-        auto nb = [&](double Dj, double Vj, double uj) {
-            dacc += (Vc - Vj) * (uc - uj) * dface_da(Dc, Dj, s);
-            gath += face_coef(Dc, Dj, s) * Vj;
-        };
-        if (x < N) nb(Dp, Vp, upp);
-        if (x > 0) nb(Dm, Vm, um);
-        if (c.y < N) nb(D[i + n], V[i + n], up[i + n]);
-        if (c.y > 0) nb(D[i - n], V[i - n], up[i - n]);
-        if (c.z < N) nb(D[i + 1], V[i + 1], up[i + 1]);
-        if (c.z > 0) nb(D[i - 1], V[i - 1], up[i - 1]);
-        Dbar[i] -= dacc;
-        if (yz && x > 0 && x < N) ubar[i] = ((x + c.y + c.z) & 1) == colour ? 0.0 : ubar[i] + gath;
-        Dm = Dc; Vm = Vc; um = uc;
-        Dc = Dp; Vc = Vp; uc = upp;
+    };
+    const int x0 = t.x0;
+    Vp R0 = load_v(x0 - 1), R1 = load_v(x0), R2 = load_v(x0 + 1), R3 = load_v(x0 + 2), R4;
+    H H0 = load_h(x0, t.hv, t.hp), H1 = load_h(x0 + 1, t.hv, t.hp), H2, H3, H4;
+    for (int x = x0; x < t.x1; x += kDerRing) {
+        step(x, R0, R1, R2, R4, H0, H2);
+        step(x + 1, R1, R2, R3, R0, H1, H3);
+        step(x + 2, R2, R3, R4, R1, H2, H4);
+        step(x + 3, R3, R4, R0, R2, H3, H0);
+        step(x + 4, R4, R0, R1, R3, H4, H1);
     }
 }
 
