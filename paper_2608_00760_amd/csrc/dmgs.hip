@@ -2115,10 +2115,7 @@ int debug_post_t(dmgs_plan P, int k, int order, const T* u_in, const T* ec, cons
 
 namespace {
 
-// Grid of the column-march derivative kernels: blocks of kBlock threads over
-// a plane times chunks of planes, at most about 2048 blocks (eight per CU on
-// 256 CUs, one round); each chunk re-reads one plane at either end.
-// Grid of the derivative kernels: (tile, chunk) blocks of kDerThreads; the
+// Grid of the column-tile kernels (derivatives, unrolled adjoint): (tile, chunk) blocks of kDerThreads; the
 // chunk count is chosen so that the blocks, one per CU, fill the last round
 // of CUs best, net of the two extra planes each chunk reads.  Chunks are
 // whole multiples of the kernels' unrolled march.
@@ -2801,18 +2798,6 @@ unsigned un_grid(int64_t nv) { return (unsigned)((nv + kBlock - 1) / kBlock); }
         }                                                                                                \
     } while (0)
 
-// Grid of the column-march kernels: blocks of kBlock threads over a plane
-// times chunks of planes, about 2048 blocks on large levels (each chunk
-// re-reads one plane on either side).
-dim3 un_col_grid(int N, int* chunk) {
-    const int n = N + 1;
-    const int64_t bx = ((int64_t)n * n + kBlock - 1) / kBlock;
-    int nch = (int)std::min<int64_t>(n, std::max<int64_t>(1, (2048 + bx - 1) / bx));
-    *chunk = (n + nch - 1) / nch;
-    nch = (n + *chunk - 1) / *chunk;
-    return dim3((unsigned)bx, (unsigned)nch);
-}
-
 // The state the defect of level k reads in a recorded cycle: the last
 // pre-smoothing half-sweep's slot, or (without pre-smoothing) the slot the
 // cycle's input is copied to.
@@ -2843,12 +2828,16 @@ int vcycle_taped(dmgs_plan P, UnWork& W, int k, double* u, const double* q, cons
         return DMGS_OK;
     }
     int chunk = 1;
-    const dim3 g = un_col_grid(l.N, &chunk);
+    const dim3 g = der_grid(P, l.N, &chunk);
     auto half = [&](const double* in, int h, int colour) -> int {
         UNCHK(W, in, l.nv, "a half-sweep input");
         UNCHK(W, W.tape[k][h], l.nv, "a tape slot");
-        hipLaunchKernelGGL(k_un_gs_half, g, dim3(kBlock), 0, st, in, W.tape[k][h], q, (const double*)l.D64,
-                           (const double*)l.mu64, l.N, s, colour, chunk);
+        auto launch = [&](auto harm) {
+            hipLaunchKernelGGL(k_un_gs_half_t<decltype(harm)::value>, g, dim3(kDerThreads), 0, st, in, W.tape[k][h],
+                               q, (const double*)l.D64, (const double*)l.w64, l.N, s, colour, chunk);
+        };
+        if (s.harmonic) launch(std::true_type());
+        else launch(std::false_type());
         LAUNCHCHK();
         return DMGS_OK;
     };
@@ -2897,8 +2886,17 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
     const Stencil<double> s = l.stencil<double>(harmonic(P));
     const int nu1 = P->opt.nu_pre, nu2 = P->opt.nu_post;
     int chunk = 1;
-    const dim3 g = un_col_grid(l.N, &chunk);
+    const dim3 g = der_grid(P, l.N, &chunk);
     const double *D = l.D64, *mu = l.mu64;
+    // the defect's (or the coarsest solve's) reverse
+    auto defect_rev = [&](double* ubar, const double* rb, double scale, const double* u) {
+        auto launch = [&](auto harm) {
+            hipLaunchKernelGGL(k_un_defect_t<decltype(harm)::value>, g, dim3(kDerThreads), 0, st, ubar, rb, scale, u,
+                               D, mu, l.N, s, W.qbar[k], W.Dbar[k], W.mbar[k], chunk);
+        };
+        if (s.harmonic) launch(std::true_type());
+        else launch(std::false_type());
+    };
     UNCHK(W, W.ubar[k], l.nv, "ubar");
     UNCHK(W, W.qbar[k], l.nv, "qbar");
     UNCHK(W, W.Dbar[k], l.nv, "Dbar");
@@ -2910,21 +2908,18 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
         TRY(fill<double>(W.V[k], l.nv, 0.0, st));
         hipLaunchKernelGGL(k_exact_solve<double>, dim3(1), dim3(64), 0, st, (const double*)W.ubar[k], W.V[k], D, mu, l.N, s);
         LAUNCHCHK();
-        hipLaunchKernelGGL(k_un_defect, dim3(g), dim3(kBlock), 0, st, (double*)nullptr, (const double*)W.V[k], 1.0,
-                           (const double*)W.tape[k][0], D, mu, l.N, s, W.qbar[k], W.Dbar[k], W.mbar[k], chunk);
+        defect_rev(nullptr, (const double*)W.V[k], 1.0, (const double*)W.tape[k][0]);
         LAUNCHCHK();
         return DMGS_OK;
     }
     // one pass per half-sweep, ubar ping-ponging between W.ubar[k] and W.V[k]
     // (an even number of half-sweeps per phase leaves it in W.ubar[k])
-    int dchunk = 1;
-    const dim3 dg = der_grid(P, l.N, &dchunk);
     auto half_rev = [&](const double* state, int colour) -> int {
         UNCHK(W, state, l.nv, "a recorded state");
         auto launch = [&](auto harm) {
-            hipLaunchKernelGGL(k_un_half_rev<decltype(harm)::value>, dg, dim3(kDerThreads), 0, st,
+            hipLaunchKernelGGL(k_un_half_rev<decltype(harm)::value>, g, dim3(kDerThreads), 0, st,
                                (const double*)W.ubar[k], W.V[k], state, D, (const double*)l.w64, l.N, s, colour,
-                               W.qbar[k], W.mbar[k], W.Dbar[k], dchunk);
+                               W.qbar[k], W.mbar[k], W.Dbar[k], chunk);
         };
         if (s.harmonic) launch(std::true_type());
         else launch(std::false_type());
@@ -2951,8 +2946,7 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
     hipLaunchKernelGGL(k_prolong_add<double>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, (const double*)W.qbar[k + 1],
                        W.r[k], l.N);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_un_defect, dim3(g), dim3(kBlock), 0, st, W.ubar[k], (const double*)W.r[k], 0.125,
-                       pre_state(P, W, k), D, mu, l.N, s, W.qbar[k], W.Dbar[k], W.mbar[k], chunk);
+    defect_rev(W.ubar[k], (const double*)W.r[k], 0.125, pre_state(P, W, k));
     LAUNCHCHK();
     for (int h = 2 * nu1 - 1; h >= 0; h--) TRY(half_rev(W.tape[k][h], h & 1));
     return DMGS_OK;

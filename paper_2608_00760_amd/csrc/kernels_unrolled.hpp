@@ -15,9 +15,10 @@
 //   defect's coefficient terms with lam;
 //   coefficient coarsening (full weighting, injection on the boundary):
 //     its transpose carries a coarse level's Dbar, mubar to the finer one.
-// The reverse half-sweep (k_un_half_rev) marches the column tiles of
-// kernels_deriv.hpp; the other stencil kernels march along x (see UnCol);
-// the rest take one vertex per thread.  Cotangents are 0 on boundary vertices except Dbar, which
+// The stencil kernels (the recorded half-sweep, the reverse of a half-sweep
+// and of the defect) march the column tiles of kernels_deriv.hpp: a
+// thread's own column in registers, each plane's neighbours over the tile
+// plus a ring of one in LDS.  The rest take one vertex per thread.  Cotangents are 0 on boundary vertices except Dbar, which
 // boundary faces reach.
 #pragma once
 #include "kernels_basic.hpp"
@@ -32,68 +33,6 @@ __device__ __forceinline__ double dface_da(double Da, double Db, const Stencil<d
         return Db * Db / (t * t) * s.two_inv_h2;
     }
     return s.half_inv_h2;
-}
-
-// Column march: thread p of a plane (p = y (N+1) + z, so a plane is one
-// coalesced run) walks the planes [x0, x0 + chunk) of chunk blockIdx.y and
-// keeps the fields it needs at x - 1, x and x + 1 in registers; in-plane
-// neighbours are read at p +- (N+1) and p +- 1.  Each field is read from
-// memory about once, instead of three times for neighbours one plane away.
-struct UnCol {
-    int n, y, z, x0, x1;
-    int64_t sx, p;
-};
-
-__device__ __forceinline__ bool un_col(int N, int chunk, UnCol& c) {
-    c.n = N + 1;
-    c.sx = (int64_t)c.n * c.n;
-    c.p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    c.x0 = (int)blockIdx.y * chunk;
-    if (c.p >= c.sx || c.x0 >= c.n) return false;
-    c.y = (int)(c.p / c.n);
-    c.z = (int)(c.p % c.n);
-    c.x1 = min(c.n, c.x0 + chunk);
-    return true;
-}
-
-// Recorded half-sweep of colour C, out of place: u_out = the Gauss-Seidel
-// value on C's interior vertices (it reads only the other colour, so it
-// equals the in-place sweep) and u_in elsewhere.  The recompute writes each
-// state straight into its tape slot.
-__global__ void k_un_gs_half(const double* __restrict__ u_in, double* __restrict__ u_out,
-                             const double* __restrict__ q, const double* __restrict__ D,
-                             const double* __restrict__ mu, int N, Stencil<double> s, int colour, int chunk) {
-    UnCol c;
-    if (!un_col(N, chunk, c)) return;
-    const int n = c.n;
-    const bool yz = c.y > 0 && c.y < N && c.z > 0 && c.z < N;
-    double Dm = 0.0, um = 0.0;
-    if (c.x0 > 0) {
-        const int64_t j = (c.x0 - 1) * c.sx + c.p;
-        Dm = D[j]; um = u_in[j];
-    }
-    const int64_t i0 = c.x0 * c.sx + c.p;
-    double Dc = D[i0], uc = u_in[i0];
-    for (int x = c.x0; x < c.x1; x++) {
-        const int64_t i = x * c.sx + c.p;
-        double Dp = 0.0, upp = 0.0;
-        if (x < N) {
-            Dp = D[i + c.sx]; upp = u_in[i + c.sx];
-        }
-        double v = uc;
-        if (yz && x > 0 && x < N && ((x + c.y + c.z) & 1) == colour) {
-            const double c0 = face_coef(Dc, Dp, s), c1 = face_coef(Dc, Dm, s);
-            const double c2 = face_coef(Dc, D[i + n], s), c3 = face_coef(Dc, D[i - n], s);
-            const double c4 = face_coef(Dc, D[i + 1], s), c5 = face_coef(Dc, D[i - 1], s);
-            const double num = q[i] + c0 * upp + c1 * um + c2 * u_in[i + n] + c3 * u_in[i - n] + c4 * u_in[i + 1] +
-                               c5 * u_in[i - 1];
-            const double den = mu[i] + c0 + c1 + c2 + c3 + c4 + c5;
-            v = num / den;
-        }
-        u_out[i] = v;
-        Dm = Dc; um = uc;
-        Dc = Dp; uc = upp;
-    }
 }
 
 // The whole reverse of one half-sweep of colour C in one pass (levels the
@@ -203,54 +142,164 @@ __global__ __launch_bounds__(kDerThreads) void k_un_half_rev(const double* __res
     }
 }
 
-// defect (or coarsest-solve) reverse with cotangent rbar = scale * rb (rb
-// read on interior vertices only): qbar += rbar, ubar -= A rbar (unless
-// ubar is null), mubar -= rbar u, Dbar -= the face terms
-__global__ void k_un_defect(double* __restrict__ ubar, const double* __restrict__ rb, double scale,
-                            const double* __restrict__ u, const double* __restrict__ D, const double* __restrict__ mu,
-                            int N, Stencil<double> s, double* __restrict__ qbar, double* __restrict__ Dbar,
-                            double* __restrict__ mubar, int chunk) {
-    UnCol c;
-    if (!un_col(N, chunk, c)) return;
-    const int n = c.n;
-    const bool yz = c.y > 0 && c.y < N && c.z > 0 && c.z < N;
-    auto rx = [&](int x, int64_t j) { return yz && x > 0 && x < N ? scale * rb[j] : 0.0; };
-    double Dm = 0.0, um = 0.0, rm = 0.0;
-    if (c.x0 > 0) {
-        const int64_t j = (c.x0 - 1) * c.sx + c.p;
-        Dm = D[j]; um = u[j]; rm = rx(c.x0 - 1, j);
+// Recorded half-sweep of colour C, out of place: u_out = the Gauss-Seidel
+// value (q + sum_j c_ij u_j) w on C's interior vertices, with the stored
+// inverse diagonal w, and u_in elsewhere (it reads only the other colour, so
+// it equals the in-place sweep).  The recompute writes each state straight
+// into its tape slot.
+template <bool HARM>
+__global__ __launch_bounds__(kDerThreads) void k_un_gs_half_t(const double* __restrict__ u_in,
+                                                             double* __restrict__ u_out, const double* __restrict__ q,
+                                                             const double* __restrict__ D,
+                                                             const double* __restrict__ w, int N, Stencil<double> s,
+                                                             int colour, int chunk) {
+    __shared__ double sU[2][kDerCells], sD[2][kDerCells];
+    DerTile t;
+    der_tile(N, chunk, t);
+    const int n = t.n;
+    struct H {
+        double u, D;
+    };
+    struct Vp : H {
+        double q, w;   // own column only
+    };
+    const DerSpan sp(t, n);
+    const auto rU = sp.rsrc(u_in), rD = sp.rsrc(D), rQ = sp.rsrc(q), rW = sp.rsrc(w);
+    auto load_h = [&](int x, bool valid, int64_t p) -> H {
+        const int o = valid ? (int)(p * 8) : kOob, so = sp.off(x);
+        return H{buf_load_s(rU, o, so), buf_load_s(rD, o, so)};
+    };
+    auto load_v = [&](int x) -> Vp {
+        Vp v;
+        static_cast<H&>(v) = load_h(x, t.own, t.p);
+        const int oo = (t.own && x < t.x1) ? (int)(t.p * 8) : kOob, so = sp.off(x);
+        v.q = buf_load_s(rQ, oo, so);
+        v.w = buf_load_s(rW, oo, so);
+        return v;
+    };
+    const bool halo = threadIdx.x < kDerHalo;
+    const bool yz = t.y > 0 && t.y < N && t.z > 0 && t.z < N;
+    auto step = [&](int x, Vp& Rm, Vp& Rc, Vp& Rp, Vp& Rl, H& Hc, H& Hl) {
+        const int b = x & 1;
+        sU[b][t.cell] = Rc.u; sD[b][t.cell] = Rc.D;
+        if (halo) { sU[b][t.hcell] = Hc.u; sD[b][t.hcell] = Hc.D; }
+        lds_barrier();
+        Rl = load_v(x + 3);
+        Hl = load_h(x + 2, t.hv, t.hp);
+        if (t.own && x < t.x1) {
+            double v = Rc.u;
+            if (yz && x > 0 && x < N && ((x + t.y + t.z) & 1) == colour) {
+                const int e[4] = {t.cell + kDerRZ, t.cell - kDerRZ, t.cell + 1, t.cell - 1};
+                double num = Rc.q + face<HARM>(Rc.D, Rp.D, s) * Rp.u + face<HARM>(Rc.D, Rm.D, s) * Rm.u;
+                for (int k = 0; k < 4; k++) num += face<HARM>(Rc.D, sD[b][e[k]], s) * sU[b][e[k]];
+                v = num * Rc.w;
+            }
+            u_out[x * t.sx + t.p] = v;
+        }
+    };
+    const int x0 = t.x0;
+    Vp R0 = load_v(x0 - 1), R1 = load_v(x0), R2 = load_v(x0 + 1), R3 = load_v(x0 + 2), R4;
+    H H0 = load_h(x0, t.hv, t.hp), H1 = load_h(x0 + 1, t.hv, t.hp), H2, H3, H4;
+    for (int x = x0; x < t.x1; x += kDerRing) {
+        step(x, R0, R1, R2, R4, H0, H2);
+        step(x + 1, R1, R2, R3, R0, H1, H3);
+        step(x + 2, R2, R3, R4, R1, H2, H4);
+        step(x + 3, R3, R4, R0, R2, H3, H0);
+        step(x + 4, R4, R0, R1, R3, H4, H1);
     }
-    const int64_t i0 = c.x0 * c.sx + c.p;
-    double Dc = D[i0], uc = u[i0], rc = rx(c.x0, i0);
-    for (int x = c.x0; x < c.x1; x++) {
-        const int64_t i = x * c.sx + c.p;
-        double Dp = 0.0, upp = 0.0, rp = 0.0;
-        if (x < N) {
-            Dp = D[i + c.sx]; upp = u[i + c.sx]; rp = rx(x + 1, i + c.sx);
+}
+
+// Defect (or coarsest-solve) reverse with cotangent rbar = scale * rb on
+// interior vertices (0 elsewhere; rb is read there only): qbar += rbar,
+// ubar -= A rbar (unless ubar is null), mubar -= rbar u on interior vertices,
+// and Dbar -= the face terms on every vertex.  Only the own vertex's ubar is
+// read and written.
+template <bool HARM>
+__global__ __launch_bounds__(kDerThreads) void k_un_defect_t(double* __restrict__ ubar, const double* __restrict__ rb,
+                                                            double scale, const double* __restrict__ u,
+                                                            const double* __restrict__ D,
+                                                            const double* __restrict__ mu, int N, Stencil<double> s,
+                                                            double* __restrict__ qbar, double* __restrict__ Dbar,
+                                                            double* __restrict__ mubar, int chunk) {
+    __shared__ double sR[2][kDerCells], sU[2][kDerCells], sD[2][kDerCells];
+    DerTile t;
+    der_tile(N, chunk, t);
+    const int n = t.n;
+    struct H {
+        double r, u, D;   // rb (scaled where used), u, D
+    };
+    struct Vp : H {
+        double m, qb, mb, Db, ub;   // own column only
+    };
+    const DerSpan sp(t, n);
+    const auto rR = sp.rsrc(rb), rU = sp.rsrc(u), rD = sp.rsrc(D), rM = sp.rsrc(mu);
+    const auto rQ = sp.rsrc(qbar), rMb = sp.rsrc(mubar), rDb = sp.rsrc(Dbar), rUb = sp.rsrc(ubar);
+    // rb is read on interior vertices only
+    auto load_h = [&](int x, bool valid, int y, int z, int64_t p) -> H {
+        const int o = valid ? (int)(p * 8) : kOob, so = sp.off(x);
+        const int orb = (valid && is_interior(N, x, y, z)) ? o : kOob;
+        return H{buf_load_s(rR, orb, so), buf_load_s(rU, o, so), buf_load_s(rD, o, so)};
+    };
+    auto load_v = [&](int x) -> Vp {
+        Vp v;
+        static_cast<H&>(v) = load_h(x, t.own, t.y, t.z, t.p);
+        const int oo = (t.own && x < t.x1) ? (int)(t.p * 8) : kOob, so = sp.off(x);
+        v.m = buf_load_s(rM, oo, so);
+        v.qb = buf_load_s(rQ, oo, so);
+        v.mb = buf_load_s(rMb, oo, so);
+        v.Db = buf_load_s(rDb, oo, so);
+        v.ub = buf_load_s(rUb, oo, so);
+        return v;
+    };
+    auto dda = [&](double Da, double Db) {
+        if (HARM) {
+            const double w = Da + Db;
+            return Db * Db / (w * w) * s.two_inv_h2;
         }
-        const bool in = yz && x > 0 && x < N;
-        double dacc = 0.0, Ar = in ? mu[i] * rc : 0.0;
-        // neighbours in the order +x, -x, +y, -y, +z, -z; rb is read only
-        // on interior neighbours
-        auto nb = [&](double Dj, double uj, double rj) {
-            dacc += (rc - rj) * (uc - uj) * dface_da(Dc, Dj, s);
-            Ar += face_coef(Dc, Dj, s) * (rc - rj);
-        };
-        const bool zin = c.z > 0 && c.z < N, yin = c.y > 0 && c.y < N, xin = x > 0 && x < N;
-        if (x < N) nb(Dp, upp, rp);
-        if (x > 0) nb(Dm, um, rm);
-        if (c.y < N) nb(D[i + n], u[i + n], xin && zin && c.y + 1 < N ? scale * rb[i + n] : 0.0);
-        if (c.y > 0) nb(D[i - n], u[i - n], xin && zin && c.y - 1 > 0 ? scale * rb[i - n] : 0.0);
-        if (c.z < N) nb(D[i + 1], u[i + 1], xin && yin && c.z + 1 < N ? scale * rb[i + 1] : 0.0);
-        if (c.z > 0) nb(D[i - 1], u[i - 1], xin && yin && c.z - 1 > 0 ? scale * rb[i - 1] : 0.0);
-        Dbar[i] -= dacc;
-        if (in) {
-            qbar[i] += rc;
-            mubar[i] -= rc * uc;
-            if (ubar) ubar[i] -= Ar;
+        return s.half_inv_h2;
+    };
+    const bool halo = threadIdx.x < kDerHalo;
+    const bool yz = t.y > 0 && t.y < N && t.z > 0 && t.z < N;
+    auto step = [&](int x, Vp& Rm, Vp& Rc, Vp& Rp, Vp& Rl, H& Hc, H& Hl) {
+        const int b = x & 1;
+        sR[b][t.cell] = scale * Rc.r; sU[b][t.cell] = Rc.u; sD[b][t.cell] = Rc.D;
+        if (halo) { sR[b][t.hcell] = scale * Hc.r; sU[b][t.hcell] = Hc.u; sD[b][t.hcell] = Hc.D; }
+        lds_barrier();
+        Rl = load_v(x + 3);
+        Hl = load_h(x + 2, t.hv, t.hy, t.hz, t.hp);
+        if (t.own && x < t.x1) {
+            const int64_t i = x * t.sx + t.p;
+            const bool in = yz && x > 0 && x < N;
+            const double rc = scale * Rc.r;
+            double dacc = 0.0, Ar = in ? Rc.m * rc : 0.0;
+            auto nb = [&](double Dj, double uj, double rj) {
+                dacc += (rc - rj) * (Rc.u - uj) * dda(Rc.D, Dj);
+                Ar += face<HARM>(Rc.D, Dj, s) * (rc - rj);
+            };
+            if (x < N) nb(Rp.D, Rp.u, scale * Rp.r);
+            if (x > 0) nb(Rm.D, Rm.u, scale * Rm.r);
+            auto cell = [&](int e) { nb(sD[b][e], sU[b][e], sR[b][e]); };
+            if (t.y < N) cell(t.cell + kDerRZ);
+            if (t.y > 0) cell(t.cell - kDerRZ);
+            if (t.z < N) cell(t.cell + 1);
+            if (t.z > 0) cell(t.cell - 1);
+            Dbar[i] = Rc.Db - dacc;
+            if (in) {
+                qbar[i] = Rc.qb + rc;
+                mubar[i] = Rc.mb - rc * Rc.u;
+                if (ubar) ubar[i] = Rc.ub - Ar;
+            }
         }
-        Dm = Dc; um = uc; rm = rc;
-        Dc = Dp; uc = upp; rc = rp;
+    };
+    const int x0 = t.x0;
+    Vp R0 = load_v(x0 - 1), R1 = load_v(x0), R2 = load_v(x0 + 1), R3 = load_v(x0 + 2), R4;
+    H H0 = load_h(x0, t.hv, t.hy, t.hz, t.hp), H1 = load_h(x0 + 1, t.hv, t.hy, t.hz, t.hp), H2, H3, H4;
+    for (int x = x0; x < t.x1; x += kDerRing) {
+        step(x, R0, R1, R2, R4, H0, H2);
+        step(x + 1, R1, R2, R3, R0, H1, H3);
+        step(x + 2, R2, R3, R4, R1, H2, H4);
+        step(x + 3, R3, R4, R0, R2, H3, H0);
+        step(x + 4, R4, R0, R1, R3, H4, H1);
     }
 }
 
