@@ -20,6 +20,7 @@ it can be exercised without a GPU.
 import collections
 import threading
 import time
+import traceback
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -261,9 +262,9 @@ class Server:
                     req.cycles = cyc
                     req.result = out if self.keep else {}
                     req.status = "done"
-                except Exception as e:     # a failed request is retired with its status
+                except Exception:     # a failed request is retired with its status and traceback
                     req.status = "error"
-                    req.error = str(e)
+                    req.error = traceback.format_exc()
                     with self.cv:
                         self.plan_live -= self.plan_bytes[req.N]
                     if plan is not None:

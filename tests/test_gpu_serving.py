@@ -110,11 +110,12 @@ def test_tick_server_matches_server():
     ref_srv = Server(budget_bytes=32 << 30, max_slots=4)
     want = {r.id: r for r in ref_srv.run(copy.deepcopy(reqs), realtime=False)}
     ref_srv.close()
+    assert all(w.status == "done" for w in want.values()), [(w.id, w.status, w.error) for w in want.values()]
     tick = TickServer(budget_bytes=32 << 30, max_slots=6)
     got = tick.run(copy.deepcopy(reqs), realtime=True)
     s = summarize(got)
     say("  tick server", s, "ticks", tick.ticks, "batch", tick.batch_stats, "peak", tick.adm.peak)
-    assert s["done"] == len(reqs) and tick.adm.peak <= 32 << 30
+    assert s["done"] == len(reqs) and tick.adm.peak <= 32 << 30, [(r.id, r.status, r.error) for r in got]
     assert tick.batch_stats["launches"] < tick.batch_stats["recorded"]
     for r in got:
         w = want[r.id]
