@@ -2261,6 +2261,37 @@ size_t dmgs_forward_vjp_workspace_bytes(const dmgs_options* o) {
 
 namespace {
 
+// Dynamic-LDS limits of the kernels that take more than the default, set
+// once per device (the attributes are process-wide, and plans may be created
+// by several host threads while others launch those kernels).
+int kernel_attributes(int device) {
+    constexpr int kDevices = 64;
+    static std::mutex lock;
+    static bool done[kDevices] = {};
+    std::lock_guard<std::mutex> guard(lock);
+    if (device >= 0 && device < kDevices && done[device]) return DMGS_OK;
+    const int lim = (int)kSmallLdsLimit;
+    const void* fns[] = {(const void*)k_small_vcycle<float, false>, (const void*)k_small_vcycle<float, true>,
+                         (const void*)k_small_vcycle<double, false>, (const void*)k_small_vcycle<double, true>,
+                         (const void*)k_small_grp<float, false>, (const void*)k_small_grp<float, true>};
+    for (const void* f : fns)
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) {
+            set_error("hipFuncSetAttribute failed");
+            return DMGS_ERR_HIP;
+        }
+    // the general-grid coarsest inverse: a plan's own size would lower the
+    // limit for plans with a larger coarsest level, so the largest is set
+    if (hipFuncSetAttribute((const void*)k_g_inverse, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(2 * kGridCoarseMax * kGridCoarseMax * sizeof(double))) != hipSuccess) {
+        set_error("hipFuncSetAttribute failed");
+        return DMGS_ERR_HIP;
+    }
+    TRY(sweep2_attributes());
+    TRY(block_attributes());
+    if (device >= 0 && device < kDevices) done[device] = true;
+    return DMGS_OK;
+}
+
 // Levels, buffers and configuration of a new plan on the current device.
 // Ordinary plans allocate every buffer (hipMalloc, pinned host slots,
 // events) and clear the work buffers synchronously; arena plans (P->arena
@@ -2334,12 +2365,7 @@ int grid_plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
         set_error("stream synchronisation failed");
         st = DMGS_ERR_HIP;
     }
-    const int m = (P->lev[P->L - 1].nc[0] - 1) * (P->lev[P->L - 1].nc[1] - 1) * (P->lev[P->L - 1].nc[2] - 1);
-    if (st == DMGS_OK && hipFuncSetAttribute((const void*)k_g_inverse, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)(2 * m * m * sizeof(double))) != hipSuccess) {
-        set_error("hipFuncSetAttribute failed");
-        st = DMGS_ERR_HIP;
-    }
+    if (st == DMGS_OK) st = kernel_attributes(P->device);
     return st;
 }
 
@@ -2461,19 +2487,7 @@ int plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
         if (P->small32 < 0 && P->lev[k].N <= 16 && small_lds_bytes<float>(Ns, nl) <= kSmallLdsLimit) P->small32 = k;
         if (P->small64 < 0 && P->lev[k].N <= 8 && small_lds_bytes<double>(Ns, nl) <= kSmallLdsLimit) P->small64 = k;
     }
-    if (st == DMGS_OK) {
-        const int lim = (int)kSmallLdsLimit;
-        const void* fns[] = {(const void*)k_small_vcycle<float, false>, (const void*)k_small_vcycle<float, true>,
-                             (const void*)k_small_vcycle<double, false>, (const void*)k_small_vcycle<double, true>,
-                             (const void*)k_small_grp<float, false>, (const void*)k_small_grp<float, true>};
-        for (const void* f : fns)
-            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) {
-                set_error("hipFuncSetAttribute failed");
-                st = DMGS_ERR_HIP;
-            }
-    }
-    if (st == DMGS_OK) st = sweep2_attributes();
-    if (st == DMGS_OK) st = block_attributes();
+    if (st == DMGS_OK) st = kernel_attributes(P->device);
     P->cfg_block_max = kn.block_max;
     P->cfg_dr_wgs = 512;
     if (const char* e = std::getenv("DMGS_DR_WGS")) P->cfg_dr_wgs = std::max(16, std::atoi(e));

@@ -15,6 +15,8 @@ the oracle for such grids (oracle/refgrid.py), through the C ABI.
   against the oracle.
 * dmgs_forward_vjp equals the separate calls; the diagnostic entry points
   and the unrolled adjoint reject general grids.
+* A plan keeps working after a plan with a smaller coarsest level is created
+  (the coarsest inverse's LDS limit is process-wide).
 """
 import math
 
@@ -131,3 +133,26 @@ def test_forward_vjp_and_rejections():
     Q.set_log_coefficients(dev(c["logD"]), dev(c["logmua"]))
     with pytest.raises(_abi.DMGSError):
         Q.vjp_unrolled(dev(c["q"]), dev(c["rhobar"]))
+
+
+def test_plans_with_different_coarsest_levels():
+    """(60, 12, 12) cells coarsen to (15, 3, 3): 56 coarsest unknowns, whose
+    inverse takes 50 KB of LDS; (16, 8, 8) coarsens to 3 unknowns.  The first
+    plan's coefficient set-up and solve still run after the second exists,
+    and match the oracle."""
+    from oracle import refgrid
+    from paper_2608_00760_amd import synth
+    from paper_2608_00760_amd.solver import Options, Plan
+    say("grid plans with different coarsest levels")
+    big, small = (60, 12, 12), (16, 8, 8)
+    h = (0.5, 1.0, 1.0)
+    A = Plan(Options(big[0], shape=big, spacing=h, fixed_cycles=3))
+    B = Plan(Options(small[0], shape=small, spacing=h, fixed_cycles=3))
+    cb = synth.grid_case(small, 8600)
+    B.set_log_coefficients(dev(cb["logD"]), dev(cb["logmua"]))
+    c = synth.grid_case(big, 8601)
+    A.set_log_coefficients(dev(c["logD"]), dev(c["logmua"]))
+    rho, _ = A.forward(dev(c["q"]))
+    rr, _ = refgrid.HierarchyGrid(c["D"], c["mua"], h=h).forward(c["q"], fixed_cycles=3)
+    assert A.level_shape[-1] == (15, 3, 3)
+    assert rel_max(host(rho), rr) <= 1e-12
