@@ -366,8 +366,10 @@ int dmgs_solve_once_noalloc(const dmgs_options *opt, const double *D, const doub
  * dmgs_jvp or dmgs_vjp on its plan.
  *
  * Plans: DMGS_FP32_IN_FP64, cubic 3D, V(2,2) red-black cycles (nu_pre =
- * nu_post = 2), adjoint_schedule 0, a coarse end of at most 16 cells per axis
- * (N = c 2^m with m >= 2), coefficients set.  A plan serves at most one
+ * nu_post = 2), adjoint_schedule 0, coefficients set, and every level above
+ * the single-workgroup coarse end (N <= 16) run by the block passes (16 < N
+ * <= 64) or the two-sweep passes (N >= 64): in practice N >= 24 with the
+ * default tuning knobs.  A plan serves at most one
  * request of a batch at a time and must not be used by other calls while it
  * does.  Its coefficient set-up must be ordered before the ticks (the same
  * stream, or a synchronisation).
