@@ -10,9 +10,13 @@
   rule at rtol 1e-10).
 * Requests of one size run their passes in shared launches: the batch
   issues fewer launches than the requests recorded.
-* A request whose source is not finite ends with DMGS_ERR_NONFINITE and
-  leaves the others unchanged; ineligible plans and a plan serving two
-  requests at once are rejected.
+* More requests of one kernel than a grouped launch takes (16) are split
+  over several launches; the smallest eligible grid (24^3) takes part.
+* A request whose source is not finite ends with DMGS_ERR_NONFINITE, and one
+  whose forward solve reaches max_cycles with DMGS_ERR_NOT_CONVERGED after
+  the single call's steps; neither runs a second solve, and the others are
+  unchanged.  Ineligible plans and a plan serving two requests at once are
+  rejected.
 """
 import numpy as np
 import pytest
@@ -157,3 +161,42 @@ def test_nonfinite_request_and_rejections():
         with pytest.raises(_abi.DMGSError):
             B.add(R, "jvp", dev(cc["q"]))
     torch.cuda.synchronize()
+
+
+def test_more_requests_than_a_group_holds():
+    """18 requests of one size (more than the 16 members a grouped launch
+    takes) and the smallest grid grouped execution takes (24^3): every
+    request still equals its single-request calls."""
+    from paper_2608_00760_amd.solver import Batch
+    say("batch: 18 requests of 32^3 and two of 24^3")
+    B = Batch()
+    reqs = {}
+    for i in range(20):
+        N = 32 if i < 18 else 24
+        P, c, t = make_plan(N, 13000 + i, face_mean=("arith", "harmonic")[i % 2])
+        mode = ("jvp", "vjp")[(i // 2) % 2]
+        reqs[i] = (P, c, t, mode)
+        add(B, P, c, t, mode, i)
+    done = B.run()
+    st = B.stats()
+    say("  ticks %d, grouped launches %d for %d recorded" % (st["ticks"], st["launches"], st["recorded"]))
+    assert st["launches"] * 4 < st["recorded"]
+    check_against_solo(reqs, done)
+
+
+def test_forward_that_does_not_converge():
+    """A forward solve that reaches max_cycles ends its request with
+    DMGS_ERR_NOT_CONVERGED after as many refinement steps as the single call
+    takes, and no second solve runs."""
+    from paper_2608_00760_amd import _abi
+    from paper_2608_00760_amd.solver import Batch
+    say("batch: max_cycles reached")
+    B = Batch()
+    P, c, t = make_plan(64, 13100, max_cycles=1)
+    add(B, P, c, t, "vjp", 1)
+    done = B.run()
+    assert len(done) == 1 and done[0]["status"] == _abi.DMGS_ERR_NOT_CONVERGED
+    assert done[0]["info_second"]["cycles"] == 0
+    _, fi = P.forward(dev(c["q"]), check=False)
+    assert fi["status"] == _abi.DMGS_ERR_NOT_CONVERGED
+    assert done[0]["info_fwd"]["cycles"] == fi["cycles"] and done[0]["info_fwd"]["rel_residual"] == fi["rel_residual"]
