@@ -374,6 +374,7 @@ int dmgs_solve_once_noalloc(const dmgs_options *opt, const double *D, const doub
  * does.  Its coefficient set-up must be ordered before the ticks (the same
  * stream, or a synchronisation).
  * ------------------------------------------------------------------------- */
+/* A batch is driven by one host thread at a time. */
 typedef struct dmgs_batch_s *dmgs_batch;
 
 enum { DMGS_BATCH_JVP = 0, DMGS_BATCH_VJP = 1 };

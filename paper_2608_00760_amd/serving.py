@@ -382,6 +382,22 @@ class TickServer(Server):
             with cls["lock"]:
                 return cls["batch"].pending()
 
+        def fail_all(cls, err):   # called with self.cv and cls["lock"] held
+            # a tick that fails ends every request of its batch, whose plans
+            # are closed, and the batch is replaced
+            for rid, (need, plan) in list(cls["running"].items()):
+                req = by_id[rid]
+                req.status = "error"
+                req.error = err
+                req.t_done = clock()
+                plan.close()
+                self.plan_live -= self.plan_bytes[req.N]
+                self.adm.finish(need, 0)
+                state["done"] += 1
+            cls["running"].clear()
+            cls["batch"].close()
+            cls["batch"] = Batch(self.device)
+
         def worker(cls):
             with torch.cuda.device(self.device):
                 while True:
@@ -390,12 +406,19 @@ class TickServer(Server):
                             self.cv.wait()
                         if state["stop"]:
                             return
+                    err = None
                     with cls["lock"]:
-                        finished = cls["batch"].tick(cls["stream"])
+                        try:
+                            finished = cls["batch"].tick(cls["stream"])
+                        except Exception:
+                            finished, err = [], traceback.format_exc()
                     with self.cv:
                         self.ticks += 1
                         for d in finished:
                             retire(cls, d)
+                        if err is not None:
+                            with cls["lock"]:
+                                fail_all(cls, err)
                         self.cv.notify_all()
 
         threads = [threading.Thread(target=worker, args=(c,), daemon=True) for c in classes]

@@ -13,7 +13,8 @@
   stopping rule at rtol 1e-10);
 * the grouped-tick server (TickServer) returns bitwise the thread server's
   results and refinement counts, with fewer launches than the requests
-  recorded, and keeps its budget.
+  recorded, and keeps its budget; a tick that fails (forced from the host)
+  ends its batch's requests with the error, and the rest are served.
 """
 import copy
 
@@ -148,3 +149,32 @@ def test_poisson_arrivals_and_rejection():
     assert next(r for r in out if r.id == 99).status == "rejected"
     assert srv.adm.peak <= 600 << 20
     srv.close()
+
+
+def test_tick_server_survives_a_failed_tick(monkeypatch):
+    """A tick that raises (forced from the host: the binding's tick raises
+    once) ends the requests of its batch with the error and closes their
+    plans; the server goes on with a new batch and serves the rest."""
+    from paper_2608_00760_amd import solver
+    from paper_2608_00760_amd.serving import Request, TickServer, summarize
+    say("serving: a failed tick")
+    real_tick = solver.Batch.tick
+    calls = {"n": 0}
+
+    def flaky_tick(self, stream=None):
+        calls["n"] += 1
+        if calls["n"] == 2:
+            raise RuntimeError("forced tick failure")
+        return real_tick(self, stream)
+
+    monkeypatch.setattr(solver.Batch, "tick", flaky_tick)
+    reqs = [Request(id=i, N=32, mode=("jvp", "vjp")[i % 2], seed=7800 + i) for i in range(8)]
+    tick = TickServer(budget_bytes=8 << 30, max_slots=3, keep_results=False)
+    out = tick.run(reqs, realtime=False)
+    s = summarize(out)
+    failed = [r for r in out if r.status == "error"]
+    say("  ", s, [(r.id, r.error.splitlines()[-1]) for r in failed])
+    assert s["done"] + s["errors"] == len(reqs) and 1 <= s["errors"] <= 3
+    assert all("forced tick failure" in r.error for r in failed)
+    assert tick.plan_live >= 0 and tick.adm.active == 0
+    tick.close()
