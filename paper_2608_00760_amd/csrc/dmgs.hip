@@ -2121,7 +2121,7 @@ namespace {
 // whole multiples of the kernels' unrolled march.
 dim3 der_grid(dmgs_plan P, int N, int* chunk) {
     const int n = N + 1;
-    const int tiles = ((n + kDerTY - 1) / kDerTY) * ((n + kDerTZ - 1) / kDerTZ);
+    const int tiles = ((N + kDerTY - 1) / kDerTY) * ((N + kDerTZ - 1) / kDerTZ);   // y, z < N
     int best_c = 1;
     double best = 0.0;
     auto chunk_of = [&](int c) { return ((n + c - 1) / c + kDerRing - 1) / kDerRing * kDerRing; };
@@ -2163,6 +2163,7 @@ int tangent_rhs(dmgs_plan P, const double* rho, const double* dq, const double* 
     auto launch = [&](auto harm) {
         hipLaunchKernelGGL(k_tangent_rhs_col<decltype(harm)::value>, g, dim3(kDerThreads), 0, st, rho, dq, dlogD,
                            dlogmua, (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, out, chunk);
+        hipLaunchKernelGGL(k_tangent_rhs_edge, dim3(grid_for(der_edge_count(l0.N))), dim3(kBlock), 0, st, out, l0.N);
     };
     TIMED(P, 0, DMGS_K_GRAD, 56.0 * l0.nv, st,
           (harmonic(P) ? launch(std::true_type()) : launch(std::false_type())));
@@ -2200,6 +2201,8 @@ int coef_grads(dmgs_plan P, const double* rho, const double* lam, double* gD, do
         hipLaunchKernelGGL((k_coef_grads_col<decltype(harm)::value, decltype(dat)::value>), g, dim3(kDerThreads), 0, st,
                            rho, lam, (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, gD, gmu, d, w,
                            chunk);
+        hipLaunchKernelGGL(k_coef_grads_edge<decltype(harm)::value>, dim3(grid_for(der_edge_count(l0.N))), dim3(kBlock),
+                           0, st, rho, lam, (const double*)l0.D64, l0.N, l0.inv_h2, gD, gmu);
     };
     using T_ = std::true_type;
     using F_ = std::false_type;
@@ -2849,6 +2852,8 @@ int vcycle_taped(dmgs_plan P, UnWork& W, int k, double* u, const double* q, cons
         auto launch = [&](auto harm) {
             hipLaunchKernelGGL(k_un_gs_half_t<decltype(harm)::value>, g, dim3(kDerThreads), 0, st, in, W.tape[k][h],
                                q, (const double*)l.D64, (const double*)l.w64, l.N, s, colour, chunk);
+            hipLaunchKernelGGL(k_un_gs_half_edge, dim3(grid_for(der_edge_count(l.N))), dim3(kBlock), 0, st, in,
+                               W.tape[k][h], l.N);
         };
         if (s.harmonic) launch(std::true_type());
         else launch(std::false_type());
@@ -2907,6 +2912,8 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
         auto launch = [&](auto harm) {
             hipLaunchKernelGGL(k_un_defect_t<decltype(harm)::value>, g, dim3(kDerThreads), 0, st, ubar, rb, scale, u,
                                D, mu, l.N, s, W.qbar[k], W.Dbar[k], W.mbar[k], chunk);
+            hipLaunchKernelGGL(k_un_defect_edge<decltype(harm)::value>, dim3(grid_for(der_edge_count(l.N))),
+                               dim3(kBlock), 0, st, rb, scale, u, D, l.N, s, W.Dbar[k]);
         };
         if (s.harmonic) launch(std::true_type());
         else launch(std::false_type());
@@ -2934,6 +2941,9 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
             hipLaunchKernelGGL(k_un_half_rev<decltype(harm)::value>, g, dim3(kDerThreads), 0, st,
                                (const double*)W.ubar[k], W.V[k], state, D, (const double*)l.w64, l.N, s, colour,
                                W.qbar[k], W.mbar[k], W.Dbar[k], chunk);
+            hipLaunchKernelGGL(k_un_half_rev_edge<decltype(harm)::value>, dim3(grid_for(der_edge_count(l.N))),
+                               dim3(kBlock), 0, st, (const double*)W.ubar[k], state, D, (const double*)l.w64, l.N, s,
+                               colour, W.Dbar[k]);
         };
         if (s.harmonic) launch(std::true_type());
         else launch(std::false_type());

@@ -4,7 +4,11 @@
 // pull-back's coefficient gradients.
 //
 // A workgroup owns a tile of kDerTY x kDerTZ vertex columns (y, z), one
-// thread each, and marches them along x over a chunk of planes.  Each
+// thread each, and marches them along x over a chunk of planes.  The tiles
+// cover y, z < N: the boundary planes y = N and z = N (a single row or
+// column beyond whole tiles when N is a multiple of the tile) are left to a
+// one-vertex-per-thread companion kernel, so no workgroup holds a nearly
+// empty tile.  Each
 // thread keeps its own column's values at x - 1, x and x + 1 in registers
 // (and the planes after them in flight).  The in-plane neighbours come from
 // an LDS copy of plane x over the tile plus a ring of one vertex: the
@@ -27,7 +31,8 @@ constexpr int kDerHalo = 2 * kDerRZ + 2 * kDerTY;   // ring cells
 struct DerTile {
     int n, x0, x1;       // vertices per axis; chunk of planes [x0, x1)
     int y, z, cell;      // this thread's column and its LDS cell
-    bool own;            // the column lies inside the grid
+    bool inb;            // the column lies inside the grid (its values are loaded)
+    bool own;            // ... and below y = N, z = N (its outputs are formed here)
     int hy, hz, hcell;   // this thread's ring cell (tid < kDerHalo)
     bool hv;             // ... inside the grid
     int64_t sx, p, hp;   // plane stride; in-plane offsets of the column and the ring cell
@@ -39,16 +44,20 @@ __device__ __forceinline__ void der_tile(int N, int chunk, DerTile& t) {
     const int tile = L % (int)gridDim.x, ch = L / (int)gridDim.x;
     t.n = N + 1;
     t.sx = (int64_t)t.n * t.n;
-    const int tiles_z = (t.n + kDerTZ - 1) / kDerTZ;
+    const int tiles_z = (N + kDerTZ - 1) / kDerTZ;
     const int y0 = (tile / tiles_z) * kDerTY, z0 = (tile % tiles_z) * kDerTZ;
     t.x0 = ch * chunk;
     t.x1 = min(t.n, t.x0 + chunk);
     const int tid = (int)threadIdx.x, ty = tid / kDerTZ, tz = tid % kDerTZ;
     t.y = y0 + ty;
     t.z = z0 + tz;
-    t.own = t.y < t.n && t.z < t.n;
+    // a column at y = N or z = N inside the tile (N not a multiple of the
+    // tile) is loaded for its neighbours; its outputs are the companion
+    // kernel's
+    t.inb = t.y < t.n && t.z < t.n;
+    t.own = t.y < N && t.z < N;
     t.cell = (ty + 1) * kDerRZ + tz + 1;
-    t.p = t.own ? (int64_t)t.y * t.n + t.z : 0;
+    t.p = t.inb ? (int64_t)t.y * t.n + t.z : 0;
     // ring: the row above, the row below, then the left and right columns
     int ly = -1, lz = -1;
     if (tid < kDerRZ) {
@@ -66,6 +75,36 @@ __device__ __forceinline__ void der_tile(int N, int chunk, DerTile& t) {
     t.hcell = (ly + 1) * kDerRZ + lz + 1;
     t.hp = t.hv ? (int64_t)t.hy * t.n + t.hz : 0;
 }
+
+// Vertices the tiles leave out: the boundary planes y = N (index t < n^2:
+// (x, N, z)) and z = N (t >= n^2: (x, y, N), y < N), every x.  Each has at
+// most one interior neighbour j: (x, N - 1, z), or (x, y, N - 1).
+struct DerEdge {
+    int64_t i, j;   // the vertex and its neighbour
+    bool jin;       // the neighbour is interior
+};
+
+__device__ __forceinline__ bool der_edge(int N, DerEdge& e) {
+    const int n = N + 1;
+    const int64_t nn = (int64_t)n * n, t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nn + (int64_t)n * N) return false;
+    int x, y, z;
+    if (t < nn) {
+        x = (int)(t / n); y = N; z = (int)(t % n);
+        e.jin = x > 0 && x < N && z > 0 && z < N;
+        e.j = ((int64_t)x * n + (N - 1)) * n + z;
+    } else {
+        const int64_t u = t - nn;
+        x = (int)(u / N); y = (int)(u % N); z = N;
+        e.jin = x > 0 && x < N && y > 0 && y < N;
+        e.j = ((int64_t)x * n + y) * n + (N - 1);
+    }
+    e.i = ((int64_t)x * n + y) * n + z;
+    return true;
+}
+
+// Vertices of the boundary planes y = N and z = N (all 2 n^2 - n of them).
+__host__ __device__ inline int64_t der_edge_count(int N) { return (int64_t)(N + 1) * (2 * N + 1); }
 
 // d D_f along the tangent: D_f = (D_a + D_b)/2 or 2 D_a D_b / (D_a + D_b),
 // with dD = D dlogD at both ends
@@ -133,7 +172,7 @@ __global__ __launch_bounds__(kDerThreads) void k_tangent_rhs_col(const double* _
     };
     auto load_v = [&](int x) -> V {
         V v;
-        static_cast<H&>(v) = load_h(x, t.own, t.p);
+        static_cast<H&>(v) = load_h(x, t.inb, t.p);
         const int oo = (t.own && x < t.x1) ? (int)(t.p * 8) : kOob, so = sp.off(x);
         v.m = buf_load_s(rM, oo, so);
         v.gm = buf_load_s(rGm, oo, so);
@@ -181,6 +220,12 @@ __global__ __launch_bounds__(kDerThreads) void k_tangent_rhs_col(const double* _
     }
 }
 
+// The tangent right-hand side on the planes y = N and z = N: 0 (boundary).
+__global__ void k_tangent_rhs_edge(double* __restrict__ rhs, int N) {
+    DerEdge e;
+    if (der_edge(N, e)) rhs[e.i] = 0.0;
+}
+
 // Coefficient gradients from the adjoint state lam = qbar:
 //   logmua_bar_i = -mua_i lam_i rho_i (interior, 0 on the boundary)
 //   logD_bar_v   = -sum_{faces (v,j), v or j interior} dD_f/dlogD_v (lam_v - lam_j)(rho_v - rho_j) / h^2
@@ -217,7 +262,7 @@ __global__ __launch_bounds__(kDerThreads) void k_coef_grads_col(const double* __
     };
     auto load_v = [&](int x) -> V {
         V v;
-        static_cast<H&>(v) = load_h(x, t.own, t.y, t.z, t.p);
+        static_cast<H&>(v) = load_h(x, t.inb, t.y, t.z, t.p);
         const int oo = (t.own && x < t.x1) ? (int)(t.p * 8) : kOob, so = sp.off(x);
         v.m = buf_load_s(rM, oo, so);
         if (DATA) {
@@ -288,6 +333,33 @@ __global__ __launch_bounds__(kDerThreads) void k_coef_grads_col(const double* __
         step(x + 3, R3, R4, R0, R2, H3, H0);
         step(x + 4, R4, R0, R1, R3, H4, H1);
     }
+}
+
+// The coefficient gradients on the planes y = N and z = N: logmua_bar = 0
+// (boundary); logD_bar from the one face to an interior neighbour j, with
+// lam = 0 at the vertex itself (the other faces join boundary vertices and
+// count for nothing in k_coef_grads_col either).
+template <bool HARM>
+__global__ void k_coef_grads_edge(const double* __restrict__ rho, const double* __restrict__ lam,
+                                  const double* __restrict__ D, int N, double inv_h2, double* __restrict__ gD,
+                                  double* __restrict__ gmu) {
+    DerEdge e;
+    if (!der_edge(N, e)) return;
+    if (gmu) gmu[e.i] = 0.0;
+    if (!gD) return;
+    double acc = 0.0;
+    if (e.jin) {
+        const double Dv = D[e.i], Dj = D[e.j];
+        double dcdv;
+        if (HARM) {
+            const double sum = Dv + Dj;
+            dcdv = 2.0 * Dj * Dj * Dv / (sum * sum);
+        } else {
+            dcdv = 0.5 * Dv;
+        }
+        acc += dcdv * (0.0 - lam[e.j]) * (rho[e.i] - rho[e.j]);
+    }
+    gD[e.i] = -acc * inv_h2;
 }
 
 }  // namespace dmgs

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kDerThreads) void k_un_half_rev(const double* __res
     };
     auto load_v = [&](int x) -> Vp {
         Vp v;
-        static_cast<H&>(v) = load_h(x, t.own, t.p);
+        static_cast<H&>(v) = load_h(x, t.inb, t.p);
         const int oo = (t.own && x < t.x1) ? (int)(t.p * 8) : kOob, so = sp.off(x);
         v.qb = buf_load_s(rQ, oo, so);
         v.mb = buf_load_s(rM, oo, so);
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kDerThreads) void k_un_gs_half_t(const double* __re
     };
     auto load_v = [&](int x) -> Vp {
         Vp v;
-        static_cast<H&>(v) = load_h(x, t.own, t.p);
+        static_cast<H&>(v) = load_h(x, t.inb, t.p);
         const int oo = (t.own && x < t.x1) ? (int)(t.p * 8) : kOob, so = sp.off(x);
         v.q = buf_load_s(rQ, oo, so);
         v.w = buf_load_s(rW, oo, so);
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kDerThreads) void k_un_defect_t(double* __restrict_
     };
     auto load_v = [&](int x) -> Vp {
         Vp v;
-        static_cast<H&>(v) = load_h(x, t.own, t.y, t.z, t.p);
+        static_cast<H&>(v) = load_h(x, t.inb, t.y, t.z, t.p);
         const int oo = (t.own && x < t.x1) ? (int)(t.p * 8) : kOob, so = sp.off(x);
         v.m = buf_load_s(rM, oo, so);
         v.qb = buf_load_s(rQ, oo, so);
@@ -301,6 +301,64 @@ __global__ __launch_bounds__(kDerThreads) void k_un_defect_t(double* __restrict_
         step(x + 3, R3, R4, R0, R2, H3, H0);
         step(x + 4, R4, R0, R1, R3, H4, H1);
     }
+}
+
+// The planes y = N and z = N that the column tiles leave out (see
+// der_edge): boundary vertices, where only Dbar changes, by the one face to
+// an interior neighbour j (the other faces join boundary vertices, whose
+// cotangent terms are 0).
+
+// recorded half-sweep: boundary values are kept
+__global__ void k_un_gs_half_edge(const double* __restrict__ u_in, double* __restrict__ u_out, int N) {
+    DerEdge e;
+    if (der_edge(N, e)) u_out[e.i] = u_in[e.i];
+}
+
+// reverse half-sweep: V = 0 at the vertex, V_j = ubar_j w_j if j is of colour C
+template <bool HARM>
+__global__ void k_un_half_rev_edge(const double* __restrict__ ubar_in, const double* __restrict__ up,
+                                   const double* __restrict__ D, const double* __restrict__ w, int N, Stencil<double> s,
+                                   int colour, double* __restrict__ Dbar) {
+    DerEdge e;
+    if (!der_edge(N, e)) return;
+    const int n = N + 1;
+    double dacc = 0.0;
+    if (e.jin) {
+        const int jx = (int)(e.j / ((int64_t)n * n)), jy = (int)((e.j / n) % n), jz = (int)(e.j % n);
+        const double Vj = ((jx + jy + jz) & 1) == colour ? ubar_in[e.j] * w[e.j] : 0.0;
+        const double Dv = D[e.i], Dj = D[e.j];
+        double dda;
+        if (HARM) {
+            const double t = Dv + Dj;
+            dda = Dj * Dj / (t * t) * s.two_inv_h2;
+        } else {
+            dda = s.half_inv_h2;
+        }
+        dacc += (0.0 - Vj) * (up[e.i] - up[e.j]) * dda;
+    }
+    Dbar[e.i] = Dbar[e.i] - dacc;
+}
+
+// defect reverse: rbar = 0 at the vertex, scale * rb_j at the interior neighbour
+template <bool HARM>
+__global__ void k_un_defect_edge(const double* __restrict__ rb, double scale, const double* __restrict__ u,
+                                 const double* __restrict__ D, int N, Stencil<double> s, double* __restrict__ Dbar) {
+    DerEdge e;
+    if (!der_edge(N, e)) return;
+    double dacc = 0.0;
+    if (e.jin) {
+        const double rj = scale * rb[e.j];
+        const double Dv = D[e.i], Dj = D[e.j];
+        double dda;
+        if (HARM) {
+            const double t = Dv + Dj;
+            dda = Dj * Dj / (t * t) * s.two_inv_h2;
+        } else {
+            dda = s.half_inv_h2;
+        }
+        dacc += (0.0 - rj) * (u[e.i] - u[e.j]) * dda;
+    }
+    Dbar[e.i] = Dbar[e.i] - dacc;
 }
 
 // a *= f
