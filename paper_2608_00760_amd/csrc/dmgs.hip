@@ -2119,9 +2119,14 @@ namespace {
 // chunk count is chosen so that the blocks, one per CU, fill the last round
 // of CUs best, net of the two extra planes each chunk reads.  Chunks are
 // whole multiples of the kernels' unrolled march.
-dim3 der_grid(dmgs_plan P, int N, int* chunk) {
+// Levels from this size on leave the boundary planes y = N, z = N to the
+// companion kernels; smaller ones tile every vertex (one launch).
+constexpr int kDerSplitMin = 128;
+
+dim3 der_grid(dmgs_plan P, int N, int* chunk, int* cover) {
     const int n = N + 1;
-    const int tiles = ((N + kDerTY - 1) / kDerTY) * ((N + kDerTZ - 1) / kDerTZ);   // y, z < N
+    *cover = N >= kDerSplitMin ? N : n;
+    const int tiles = ((*cover + kDerTY - 1) / kDerTY) * ((*cover + kDerTZ - 1) / kDerTZ);   // y, z < cover
     int best_c = 1;
     double best = 0.0;
     auto chunk_of = [&](int c) { return ((n + c - 1) / c + kDerRing - 1) / kDerRing * kDerRing; };
@@ -2158,12 +2163,13 @@ int tangent_rhs(dmgs_plan P, const double* rho, const double* dq, const double* 
                                  harmonic(P), out));
         return DMGS_OK;
     }
-    int chunk = 1;
-    const dim3 g = der_grid(P, l0.N, &chunk);
+    int chunk = 1, cover = 0;
+    const dim3 g = der_grid(P, l0.N, &chunk, &cover);
     auto launch = [&](auto harm) {
         hipLaunchKernelGGL(k_tangent_rhs_col<decltype(harm)::value>, g, dim3(kDerThreads), 0, st, rho, dq, dlogD,
-                           dlogmua, (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, out, chunk);
-        hipLaunchKernelGGL(k_tangent_rhs_edge, dim3(grid_for(der_edge_count(l0.N))), dim3(kBlock), 0, st, out, l0.N);
+                           dlogmua, (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, out, chunk, cover);
+        if (cover == l0.N)
+            hipLaunchKernelGGL(k_tangent_rhs_edge, dim3(grid_for(der_edge_count(l0.N))), dim3(kBlock), 0, st, out, l0.N);
     };
     TIMED(P, 0, DMGS_K_GRAD, 56.0 * l0.nv, st,
           (harmonic(P) ? launch(std::true_type()) : launch(std::false_type())));
@@ -2193,16 +2199,17 @@ int coef_grads(dmgs_plan P, const double* rho, const double* lam, double* gD, do
         }
         return DMGS_OK;
     }
-    int chunk = 1;
-    const dim3 g = der_grid(P, l0.N, &chunk);
+    int chunk = 1, cover = 0;
+    const dim3 g = der_grid(P, l0.N, &chunk, &cover);
     const double bytes = (gD ? 40.0 : 24.0) + (gmu ? 8.0 : 0.0) + (d && gmu ? 16.0 : 0.0);
     const bool data = d && w && gmu;
     auto launch = [&](auto harm, auto dat) {
         hipLaunchKernelGGL((k_coef_grads_col<decltype(harm)::value, decltype(dat)::value>), g, dim3(kDerThreads), 0, st,
                            rho, lam, (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, gD, gmu, d, w,
-                           chunk);
-        hipLaunchKernelGGL(k_coef_grads_edge<decltype(harm)::value>, dim3(grid_for(der_edge_count(l0.N))), dim3(kBlock),
-                           0, st, rho, lam, (const double*)l0.D64, l0.N, l0.inv_h2, gD, gmu);
+                           chunk, cover);
+        if (cover == l0.N)
+            hipLaunchKernelGGL(k_coef_grads_edge<decltype(harm)::value>, dim3(grid_for(der_edge_count(l0.N))),
+                               dim3(kBlock), 0, st, rho, lam, (const double*)l0.D64, l0.N, l0.inv_h2, gD, gmu);
     };
     using T_ = std::true_type;
     using F_ = std::false_type;
@@ -2765,6 +2772,18 @@ int dmgs_forward_vjp(dmgs_plan P, const double* q, const double* rhobar, double*
 namespace {
 // Work buffers of the unrolled reverse pass, owned by the plan once its
 // first call has allocated them (hipFree waits for the device).
+// Grid of the column-march kernels: blocks of kBlock threads over a plane
+// times chunks of planes, about 2048 blocks on large levels (each chunk
+// re-reads one plane on either side).
+dim3 un_col_grid(int N, int* chunk) {
+    const int n = N + 1;
+    const int64_t bx = ((int64_t)n * n + kBlock - 1) / kBlock;
+    int nch = (int)std::min<int64_t>(n, std::max<int64_t>(1, (2048 + bx - 1) / bx));
+    *chunk = (n + nch - 1) / nch;
+    nch = (n + *chunk - 1) / *chunk;
+    return dim3((unsigned)bx, (unsigned)nch);
+}
+
 struct UnWork {
     std::vector<void*> bufs;
     std::vector<size_t> sizes;
@@ -2844,16 +2863,26 @@ int vcycle_taped(dmgs_plan P, UnWork& W, int k, double* u, const double* q, cons
         *fin = u;
         return DMGS_OK;
     }
-    int chunk = 1;
-    const dim3 g = der_grid(P, l.N, &chunk);
+    int chunk = 1, cover = 0;
+    const dim3 g = der_grid(P, l.N, &chunk, &cover);
+    const bool tiled = l.N >= kDerSplitMin;   // smaller levels: the x-march forms
+    int uchunk = 1;
+    const dim3 ug = un_col_grid(l.N, &uchunk);
     auto half = [&](const double* in, int h, int colour) -> int {
         UNCHK(W, in, l.nv, "a half-sweep input");
         UNCHK(W, W.tape[k][h], l.nv, "a tape slot");
+        if (!tiled) {
+            hipLaunchKernelGGL(k_un_gs_half, ug, dim3(kBlock), 0, st, in, W.tape[k][h], q, (const double*)l.D64,
+                               (const double*)l.mu64, l.N, s, colour, uchunk);
+            LAUNCHCHK();
+            return DMGS_OK;
+        }
         auto launch = [&](auto harm) {
             hipLaunchKernelGGL(k_un_gs_half_t<decltype(harm)::value>, g, dim3(kDerThreads), 0, st, in, W.tape[k][h],
-                               q, (const double*)l.D64, (const double*)l.w64, l.N, s, colour, chunk);
-            hipLaunchKernelGGL(k_un_gs_half_edge, dim3(grid_for(der_edge_count(l.N))), dim3(kBlock), 0, st, in,
-                               W.tape[k][h], l.N);
+                               q, (const double*)l.D64, (const double*)l.w64, l.N, s, colour, chunk, cover);
+            if (cover == l.N)
+                hipLaunchKernelGGL(k_un_gs_half_edge, dim3(grid_for(der_edge_count(l.N))), dim3(kBlock), 0, st, in,
+                                   W.tape[k][h], l.N);
         };
         if (s.harmonic) launch(std::true_type());
         else launch(std::false_type());
@@ -2904,16 +2933,25 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
     const Level& l = P->lev[k];
     const Stencil<double> s = l.stencil<double>(harmonic(P));
     const int nu1 = P->opt.nu_pre, nu2 = P->opt.nu_post;
-    int chunk = 1;
-    const dim3 g = der_grid(P, l.N, &chunk);
+    int chunk = 1, cover = 0;
+    const dim3 g = der_grid(P, l.N, &chunk, &cover);
+    const bool tiled = l.N >= kDerSplitMin;   // smaller levels: the x-march forms
+    int uchunk = 1;
+    const dim3 ug = un_col_grid(l.N, &uchunk);
     const double *D = l.D64, *mu = l.mu64;
     // the defect's (or the coarsest solve's) reverse
     auto defect_rev = [&](double* ubar, const double* rb, double scale, const double* u) {
+        if (!tiled) {
+            hipLaunchKernelGGL(k_un_defect, ug, dim3(kBlock), 0, st, ubar, rb, scale, u, D, mu, l.N, s, W.qbar[k],
+                               W.Dbar[k], W.mbar[k], uchunk);
+            return;
+        }
         auto launch = [&](auto harm) {
             hipLaunchKernelGGL(k_un_defect_t<decltype(harm)::value>, g, dim3(kDerThreads), 0, st, ubar, rb, scale, u,
-                               D, mu, l.N, s, W.qbar[k], W.Dbar[k], W.mbar[k], chunk);
-            hipLaunchKernelGGL(k_un_defect_edge<decltype(harm)::value>, dim3(grid_for(der_edge_count(l.N))),
-                               dim3(kBlock), 0, st, rb, scale, u, D, l.N, s, W.Dbar[k]);
+                               D, mu, l.N, s, W.qbar[k], W.Dbar[k], W.mbar[k], chunk, cover);
+            if (cover == l.N)
+                hipLaunchKernelGGL(k_un_defect_edge<decltype(harm)::value>, dim3(grid_for(der_edge_count(l.N))),
+                                   dim3(kBlock), 0, st, rb, scale, u, D, l.N, s, W.Dbar[k]);
         };
         if (s.harmonic) launch(std::true_type());
         else launch(std::false_type());
@@ -2933,17 +2971,29 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
         LAUNCHCHK();
         return DMGS_OK;
     }
-    // one pass per half-sweep, ubar ping-ponging between W.ubar[k] and W.V[k]
-    // (an even number of half-sweeps per phase leaves it in W.ubar[k])
+    // tiled levels: one pass per half-sweep, ubar ping-ponging between
+    // W.ubar[k] and W.V[k] (an even number of half-sweeps per phase leaves it
+    // in W.ubar[k]); x-march levels: V = ubar / d into W.V[k], then the gather
+    // updates ubar in place
     auto half_rev = [&](const double* state, int colour) -> int {
         UNCHK(W, state, l.nv, "a recorded state");
+        if (!tiled) {
+            hipLaunchKernelGGL(k_un_half_v, ug, dim3(kBlock), 0, st, (const double*)W.ubar[k], state, D, mu, l.N, s,
+                               colour, W.V[k], W.qbar[k], W.mbar[k], uchunk);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_un_half_gather, ug, dim3(kBlock), 0, st, W.ubar[k], (const double*)W.V[k], state, D,
+                               l.N, s, colour, W.Dbar[k], uchunk);
+            LAUNCHCHK();
+            return DMGS_OK;
+        }
         auto launch = [&](auto harm) {
             hipLaunchKernelGGL(k_un_half_rev<decltype(harm)::value>, g, dim3(kDerThreads), 0, st,
                                (const double*)W.ubar[k], W.V[k], state, D, (const double*)l.w64, l.N, s, colour,
-                               W.qbar[k], W.mbar[k], W.Dbar[k], chunk);
-            hipLaunchKernelGGL(k_un_half_rev_edge<decltype(harm)::value>, dim3(grid_for(der_edge_count(l.N))),
-                               dim3(kBlock), 0, st, (const double*)W.ubar[k], state, D, (const double*)l.w64, l.N, s,
-                               colour, W.Dbar[k]);
+                               W.qbar[k], W.mbar[k], W.Dbar[k], chunk, cover);
+            if (cover == l.N)
+                hipLaunchKernelGGL(k_un_half_rev_edge<decltype(harm)::value>, dim3(grid_for(der_edge_count(l.N))),
+                                   dim3(kBlock), 0, st, (const double*)W.ubar[k], state, D, (const double*)l.w64, l.N,
+                                   s, colour, W.Dbar[k]);
         };
         if (s.harmonic) launch(std::true_type());
         else launch(std::false_type());

@@ -5,10 +5,12 @@
 //
 // A workgroup owns a tile of kDerTY x kDerTZ vertex columns (y, z), one
 // thread each, and marches them along x over a chunk of planes.  The tiles
-// cover y, z < N: the boundary planes y = N and z = N (a single row or
-// column beyond whole tiles when N is a multiple of the tile) are left to a
-// one-vertex-per-thread companion kernel, so no workgroup holds a nearly
-// empty tile.  Each
+// cover y, z < cover.  On large levels cover = N: the boundary planes
+// y = N and z = N (a single row or column beyond whole tiles when N is a
+// multiple of the tile) are left to a one-vertex-per-thread companion
+// kernel, so no workgroup holds a nearly empty tile.  On small levels, where
+// launches cost more than idle lanes, cover = N + 1 and the tiles take every
+// vertex.  Each
 // thread keeps its own column's values at x - 1, x and x + 1 in registers
 // (and the planes after them in flight).  The in-plane neighbours come from
 // an LDS copy of plane x over the tile plus a ring of one vertex: the
@@ -38,24 +40,24 @@ struct DerTile {
     int64_t sx, p, hp;   // plane stride; in-plane offsets of the column and the ring cell
 };
 
-__device__ __forceinline__ void der_tile(int N, int chunk, DerTile& t) {
+__device__ __forceinline__ void der_tile(int N, int chunk, int cover, DerTile& t) {
     const int nb = (int)(gridDim.x * gridDim.y);
     const int L = xcd_remap((int)(blockIdx.y * gridDim.x + blockIdx.x), nb);
     const int tile = L % (int)gridDim.x, ch = L / (int)gridDim.x;
     t.n = N + 1;
     t.sx = (int64_t)t.n * t.n;
-    const int tiles_z = (N + kDerTZ - 1) / kDerTZ;
+    const int tiles_z = (cover + kDerTZ - 1) / kDerTZ;
     const int y0 = (tile / tiles_z) * kDerTY, z0 = (tile % tiles_z) * kDerTZ;
     t.x0 = ch * chunk;
     t.x1 = min(t.n, t.x0 + chunk);
     const int tid = (int)threadIdx.x, ty = tid / kDerTZ, tz = tid % kDerTZ;
     t.y = y0 + ty;
     t.z = z0 + tz;
-    // a column at y = N or z = N inside the tile (N not a multiple of the
-    // tile) is loaded for its neighbours; its outputs are the companion
-    // kernel's
+    // with cover = N, a column at y = N or z = N inside the tile (N not a
+    // multiple of the tile) is loaded for its neighbours; its outputs are the
+    // companion kernel's
     t.inb = t.y < t.n && t.z < t.n;
-    t.own = t.y < N && t.z < N;
+    t.own = t.y < cover && t.z < cover;
     t.cell = (ty + 1) * kDerRZ + tz + 1;
     t.p = t.inb ? (int64_t)t.y * t.n + t.z : 0;
     // ring: the row above, the row below, then the left and right columns
@@ -152,10 +154,10 @@ __global__ __launch_bounds__(kDerThreads) void k_tangent_rhs_col(const double* _
                                                                 const double* __restrict__ dlogmu,
                                                                 const double* __restrict__ D,
                                                                 const double* __restrict__ mu, int N, double inv_h2,
-                                                                double* __restrict__ rhs, int chunk) {
+                                                                double* __restrict__ rhs, int chunk, int cover) {
     __shared__ double sR[2][kDerCells], sD[2][kDerCells], sT[2][kDerCells];
     DerTile t;
-    der_tile(N, chunk, t);
+    der_tile(N, chunk, cover, t);
     const int n = t.n;
     struct H {
         double r, D, g;   // rho, D, dlogD (products formed when used, so loads stay in flight)
@@ -241,10 +243,10 @@ __global__ __launch_bounds__(kDerThreads) void k_coef_grads_col(const double* __
                                                                const double* __restrict__ mu, int N, double inv_h2,
                                                                double* __restrict__ gD, double* __restrict__ gmu,
                                                                const double* __restrict__ d,
-                                                               const double* __restrict__ w, int chunk) {
+                                                               const double* __restrict__ w, int chunk, int cover) {
     __shared__ double sL[2][kDerCells], sR[2][kDerCells], sD[2][kDerCells];
     DerTile t;
-    der_tile(N, chunk, t);
+    der_tile(N, chunk, cover, t);
     const int n = t.n;
     struct H {
         double l, r, D;   // lam (0 on boundary vertices), rho, D

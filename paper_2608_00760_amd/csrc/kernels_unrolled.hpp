@@ -16,9 +16,10 @@
 //   coefficient coarsening (full weighting, injection on the boundary):
 //     its transpose carries a coarse level's Dbar, mubar to the finer one.
 // The stencil kernels (the recorded half-sweep, the reverse of a half-sweep
-// and of the defect) march the column tiles of kernels_deriv.hpp: a
-// thread's own column in registers, each plane's neighbours over the tile
-// plus a ring of one in LDS.  The rest take one vertex per thread.  Cotangents are 0 on boundary vertices except Dbar, which
+// and of the defect) march the column tiles of kernels_deriv.hpp on levels
+// N >= 128 (a thread's own column in registers, each plane's neighbours over
+// the tile plus a ring of one in LDS), and march one thread per plane vertex
+// (UnCol) on smaller levels.  The rest take one vertex per thread.  Cotangents are 0 on boundary vertices except Dbar, which
 // boundary faces reach.
 #pragma once
 #include "kernels_basic.hpp"
@@ -33,6 +34,192 @@ __device__ __forceinline__ double dface_da(double Da, double Db, const Stencil<d
         return Db * Db / (t * t) * s.two_inv_h2;
     }
     return s.half_inv_h2;
+}
+
+// Levels below kDerSplitMin-sized grids (N < 128) run these x-march forms
+// instead of the column tiles: a thread per vertex column of the plane gives
+// small levels many more workgroups than whole 16 x 64 tiles would.
+//
+// Column march: thread p of a plane (p = y (N+1) + z, so a plane is one
+// coalesced run) walks the planes [x0, x0 + chunk) of chunk blockIdx.y and
+// keeps the fields it needs at x - 1, x and x + 1 in registers; in-plane
+// neighbours are read at p +- (N+1) and p +- 1.  Each field is read from
+// memory about once, instead of three times for neighbours one plane away.
+struct UnCol {
+    int n, y, z, x0, x1;
+    int64_t sx, p;
+};
+
+__device__ __forceinline__ bool un_col(int N, int chunk, UnCol& c) {
+    c.n = N + 1;
+    c.sx = (int64_t)c.n * c.n;
+    c.p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    c.x0 = (int)blockIdx.y * chunk;
+    if (c.p >= c.sx || c.x0 >= c.n) return false;
+    c.y = (int)(c.p / c.n);
+    c.z = (int)(c.p % c.n);
+    c.x1 = min(c.n, c.x0 + chunk);
+    return true;
+}
+
+// Recorded half-sweep of colour C, out of place: u_out = the Gauss-Seidel
+// value on C's interior vertices (it reads only the other colour, so it
+// equals the in-place sweep) and u_in elsewhere.  The recompute writes each
+// state straight into its tape slot.
+__global__ void k_un_gs_half(const double* __restrict__ u_in, double* __restrict__ u_out,
+                             const double* __restrict__ q, const double* __restrict__ D,
+                             const double* __restrict__ mu, int N, Stencil<double> s, int colour, int chunk) {
+    UnCol c;
+    if (!un_col(N, chunk, c)) return;
+    const int n = c.n;
+    const bool yz = c.y > 0 && c.y < N && c.z > 0 && c.z < N;
+    double Dm = 0.0, um = 0.0;
+    if (c.x0 > 0) {
+        const int64_t j = (c.x0 - 1) * c.sx + c.p;
+        Dm = D[j]; um = u_in[j];
+    }
+    const int64_t i0 = c.x0 * c.sx + c.p;
+    double Dc = D[i0], uc = u_in[i0];
+    for (int x = c.x0; x < c.x1; x++) {
+        const int64_t i = x * c.sx + c.p;
+        double Dp = 0.0, upp = 0.0;
+        if (x < N) {
+            Dp = D[i + c.sx]; upp = u_in[i + c.sx];
+        }
+        double v = uc;
+        if (yz && x > 0 && x < N && ((x + c.y + c.z) & 1) == colour) {
+            const double c0 = face_coef(Dc, Dp, s), c1 = face_coef(Dc, Dm, s);
+            const double c2 = face_coef(Dc, D[i + n], s), c3 = face_coef(Dc, D[i - n], s);
+            const double c4 = face_coef(Dc, D[i + 1], s), c5 = face_coef(Dc, D[i - 1], s);
+            const double num = q[i] + c0 * upp + c1 * um + c2 * u_in[i + n] + c3 * u_in[i - n] + c4 * u_in[i + 1] +
+                               c5 * u_in[i - 1];
+            const double den = mu[i] + c0 + c1 + c2 + c3 + c4 + c5;
+            v = num / den;
+        }
+        u_out[i] = v;
+        Dm = Dc; um = uc;
+        Dc = Dp; uc = upp;
+    }
+}
+
+// half-sweep reverse, part 1: V = ubar / d on the colour's interior vertices
+// (0 elsewhere); qbar += V; mubar -= V u'
+__global__ void k_un_half_v(const double* __restrict__ ubar, const double* __restrict__ up,
+                            const double* __restrict__ D, const double* __restrict__ mu, int N, Stencil<double> s,
+                            int colour, double* __restrict__ V, double* __restrict__ qbar, double* __restrict__ mubar,
+                            int chunk) {
+    UnCol c;
+    if (!un_col(N, chunk, c)) return;
+    const int n = c.n;
+    const bool yz = c.y > 0 && c.y < N && c.z > 0 && c.z < N;
+    double Dm = c.x0 > 0 ? D[(c.x0 - 1) * c.sx + c.p] : 0.0, Dc = D[c.x0 * c.sx + c.p];
+    for (int x = c.x0; x < c.x1; x++) {
+        const int64_t i = x * c.sx + c.p;
+        const double Dp = x < N ? D[i + c.sx] : 0.0;
+        if (yz && x > 0 && x < N && ((x + c.y + c.z) & 1) == colour) {
+            const double d = mu[i] + face_coef(Dc, Dp, s) + face_coef(Dc, Dm, s) + face_coef(Dc, D[i + n], s) +
+                             face_coef(Dc, D[i - n], s) + face_coef(Dc, D[i + 1], s) + face_coef(Dc, D[i - 1], s);
+            const double v = ubar[i] / d;
+            V[i] = v;
+            qbar[i] += v;
+            mubar[i] -= v * up[i];
+        } else {
+            V[i] = 0.0;
+        }
+        Dm = Dc;
+        Dc = Dp;
+    }
+}
+
+// half-sweep reverse, part 2: Dbar on every vertex, ubar on interior ones
+__global__ void k_un_half_gather(double* __restrict__ ubar, const double* __restrict__ V, const double* __restrict__ up,
+                                 const double* __restrict__ D, int N, Stencil<double> s, int colour,
+                                 double* __restrict__ Dbar, int chunk) {
+    UnCol c;
+    if (!un_col(N, chunk, c)) return;
+    const int n = c.n;
+    const bool yz = c.y > 0 && c.y < N && c.z > 0 && c.z < N;
+    double Dm = 0.0, Vm = 0.0, um = 0.0;
+    if (c.x0 > 0) {
+        const int64_t j = (c.x0 - 1) * c.sx + c.p;
+        Dm = D[j]; Vm = V[j]; um = up[j];
+    }
+    const int64_t i0 = c.x0 * c.sx + c.p;
+    double Dc = D[i0], Vc = V[i0], uc = up[i0];
+    for (int x = c.x0; x < c.x1; x++) {
+        const int64_t i = x * c.sx + c.p;
+        double Dp = 0.0, Vp = 0.0, upp = 0.0;
+        if (x < N) {
+            Dp = D[i + c.sx]; Vp = V[i + c.sx]; upp = up[i + c.sx];
+        }
+        double dacc = 0.0, gath = 0.0;
+        // neighbours in the order +x, -x, +y, -y, +z, -z
+        auto nb = [&](double Dj, double Vj, double uj) {
+            dacc += (Vc - Vj) * (uc - uj) * dface_da(Dc, Dj, s);
+            gath += face_coef(Dc, Dj, s) * Vj;
+        };
+        if (x < N) nb(Dp, Vp, upp);
+        if (x > 0) nb(Dm, Vm, um);
+        if (c.y < N) nb(D[i + n], V[i + n], up[i + n]);
+        if (c.y > 0) nb(D[i - n], V[i - n], up[i - n]);
+        if (c.z < N) nb(D[i + 1], V[i + 1], up[i + 1]);
+        if (c.z > 0) nb(D[i - 1], V[i - 1], up[i - 1]);
+        Dbar[i] -= dacc;
+        if (yz && x > 0 && x < N) ubar[i] = ((x + c.y + c.z) & 1) == colour ? 0.0 : ubar[i] + gath;
+        Dm = Dc; Vm = Vc; um = uc;
+        Dc = Dp; Vc = Vp; uc = upp;
+    }
+}
+
+// defect (or coarsest-solve) reverse with cotangent rbar = scale * rb (rb
+// read on interior vertices only): qbar += rbar, ubar -= A rbar (unless
+// ubar is null), mubar -= rbar u, Dbar -= the face terms
+__global__ void k_un_defect(double* __restrict__ ubar, const double* __restrict__ rb, double scale,
+                            const double* __restrict__ u, const double* __restrict__ D, const double* __restrict__ mu,
+                            int N, Stencil<double> s, double* __restrict__ qbar, double* __restrict__ Dbar,
+                            double* __restrict__ mubar, int chunk) {
+    UnCol c;
+    if (!un_col(N, chunk, c)) return;
+    const int n = c.n;
+    const bool yz = c.y > 0 && c.y < N && c.z > 0 && c.z < N;
+    auto rx = [&](int x, int64_t j) { return yz && x > 0 && x < N ? scale * rb[j] : 0.0; };
+    double Dm = 0.0, um = 0.0, rm = 0.0;
+    if (c.x0 > 0) {
+        const int64_t j = (c.x0 - 1) * c.sx + c.p;
+        Dm = D[j]; um = u[j]; rm = rx(c.x0 - 1, j);
+    }
+    const int64_t i0 = c.x0 * c.sx + c.p;
+    double Dc = D[i0], uc = u[i0], rc = rx(c.x0, i0);
+    for (int x = c.x0; x < c.x1; x++) {
+        const int64_t i = x * c.sx + c.p;
+        double Dp = 0.0, upp = 0.0, rp = 0.0;
+        if (x < N) {
+            Dp = D[i + c.sx]; upp = u[i + c.sx]; rp = rx(x + 1, i + c.sx);
+        }
+        const bool in = yz && x > 0 && x < N;
+        double dacc = 0.0, Ar = in ? mu[i] * rc : 0.0;
+        // neighbours in the order +x, -x, +y, -y, +z, -z; rb is read only
+        // on interior neighbours
+        auto nb = [&](double Dj, double uj, double rj) {
+            dacc += (rc - rj) * (uc - uj) * dface_da(Dc, Dj, s);
+            Ar += face_coef(Dc, Dj, s) * (rc - rj);
+        };
+        const bool zin = c.z > 0 && c.z < N, yin = c.y > 0 && c.y < N, xin = x > 0 && x < N;
+        if (x < N) nb(Dp, upp, rp);
+        if (x > 0) nb(Dm, um, rm);
+        if (c.y < N) nb(D[i + n], u[i + n], xin && zin && c.y + 1 < N ? scale * rb[i + n] : 0.0);
+        if (c.y > 0) nb(D[i - n], u[i - n], xin && zin && c.y - 1 > 0 ? scale * rb[i - n] : 0.0);
+        if (c.z < N) nb(D[i + 1], u[i + 1], xin && yin && c.z + 1 < N ? scale * rb[i + 1] : 0.0);
+        if (c.z > 0) nb(D[i - 1], u[i - 1], xin && yin && c.z - 1 > 0 ? scale * rb[i - 1] : 0.0);
+        Dbar[i] -= dacc;
+        if (in) {
+            qbar[i] += rc;
+            mubar[i] -= rc * uc;
+            if (ubar) ubar[i] -= Ar;
+        }
+        Dm = Dc; um = uc; rm = rc;
+        Dc = Dp; uc = upp; rc = rp;
+    }
 }
 
 // The whole reverse of one half-sweep of colour C in one pass (levels the
@@ -55,10 +242,10 @@ __global__ __launch_bounds__(kDerThreads) void k_un_half_rev(const double* __res
                                                             const double* __restrict__ w, int N, Stencil<double> s,
                                                             int colour, double* __restrict__ qbar,
                                                             double* __restrict__ mubar, double* __restrict__ Dbar,
-                                                            int chunk) {
+                                                            int chunk, int cover) {
     __shared__ double sV[2][kDerCells], sU[2][kDerCells], sD[2][kDerCells];
     DerTile t;
-    der_tile(N, chunk, t);
+    der_tile(N, chunk, cover, t);
     const int n = t.n;
     struct H {
         double b, w, u, D;   // ubar_in, w, u', D
@@ -152,10 +339,10 @@ __global__ __launch_bounds__(kDerThreads) void k_un_gs_half_t(const double* __re
                                                              double* __restrict__ u_out, const double* __restrict__ q,
                                                              const double* __restrict__ D,
                                                              const double* __restrict__ w, int N, Stencil<double> s,
-                                                             int colour, int chunk) {
+                                                             int colour, int chunk, int cover) {
     __shared__ double sU[2][kDerCells], sD[2][kDerCells];
     DerTile t;
-    der_tile(N, chunk, t);
+    der_tile(N, chunk, cover, t);
     const int n = t.n;
     struct H {
         double u, D;
@@ -220,10 +407,10 @@ __global__ __launch_bounds__(kDerThreads) void k_un_defect_t(double* __restrict_
                                                             const double* __restrict__ D,
                                                             const double* __restrict__ mu, int N, Stencil<double> s,
                                                             double* __restrict__ qbar, double* __restrict__ Dbar,
-                                                            double* __restrict__ mubar, int chunk) {
+                                                            double* __restrict__ mubar, int chunk, int cover) {
     __shared__ double sR[2][kDerCells], sU[2][kDerCells], sD[2][kDerCells];
     DerTile t;
-    der_tile(N, chunk, t);
+    der_tile(N, chunk, cover, t);
     const int n = t.n;
     struct H {
         double r, u, D;   // rb (scaled where used), u, D
