@@ -3,7 +3,9 @@
 
 * rho, qbar, logD_bar and logmua_bar equal the oracle's to 1e-12 of the
   largest entry (2 and 3 levels of recursion, ragged c = 3 sizes, both face
-  means, V(2,2), V(2,1), V(1,2) and V(0,2), g != 0).
+  means, V(2,2), V(2,1), V(1,2) and V(0,2), g != 0).  At 128^3 and 192^3 the
+  finest level runs the column-tile kernels with their boundary-plane
+  companions and the coarser levels the x-march kernels.
 * qbar equals dmgs_vjp's fixed-cycle pull-back.
 * At 64^3, central differences of the library's own fixed-cycle forward map
   along random log D and log mua directions match <grad, direction>.
@@ -32,7 +34,8 @@ def plan_for(N, logD, logmu, **kw):
 
 @pytest.mark.parametrize("N,n,nu,harmonic,g", [(8, 2, (2, 2), False, 0.0), (16, 3, (2, 1), True, 0.4),
                                                (24, 2, (2, 2), False, 0.0), (48, 2, (1, 2), True, 0.0),
-                                               (16, 2, (0, 2), False, 0.3)])
+                                               (16, 2, (0, 2), False, 0.3), (128, 2, (2, 2), True, 0.3),
+                                               (192, 1, (2, 1), False, 0.0)])
 def test_matches_oracle(N, n, nu, harmonic, g):
     from oracle import unrolled
     say("unrolled N=%d n=%d nu=%s harmonic=%s g=%g" % (N, n, nu, harmonic, g))
