@@ -2119,8 +2119,9 @@ namespace {
 // chunk count is chosen so that the blocks, one per CU, fill the last round
 // of CUs best, net of the two extra planes each chunk reads.  Chunks are
 // whole multiples of the kernels' unrolled march.
-// Levels from this size on leave the boundary planes y = N, z = N to the
-// companion kernels; smaller ones tile every vertex (one launch).
+// Levels from this size on leave the boundary planes y = N, z = N to extra
+// grid rows of the same launch (at most two vertices per thread); smaller
+// ones tile every vertex.
 constexpr int kDerSplitMin = 128;
 
 dim3 der_grid(dmgs_plan P, int N, int* chunk, int* cover) {
@@ -2143,7 +2144,10 @@ dim3 der_grid(dmgs_plan P, int N, int* chunk, int* cover) {
         }
     }
     *chunk = chunk_of(best_c);
-    return dim3((unsigned)tiles, (unsigned)((n + *chunk - 1) / *chunk));
+    const int nch = (n + *chunk - 1) / *chunk;
+    const int64_t per_row = (int64_t)tiles * kDerThreads * 2;
+    const int erows = *cover == N ? (int)((der_edge_count(N) + per_row - 1) / per_row) : 0;
+    return dim3((unsigned)tiles, (unsigned)(nch + erows));
 }
 
 // tangent right-hand side q' - A' rho of the push-forward (A9)
@@ -2168,8 +2172,6 @@ int tangent_rhs(dmgs_plan P, const double* rho, const double* dq, const double* 
     auto launch = [&](auto harm) {
         hipLaunchKernelGGL(k_tangent_rhs_col<decltype(harm)::value>, g, dim3(kDerThreads), 0, st, rho, dq, dlogD,
                            dlogmua, (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, out, chunk, cover);
-        if (cover == l0.N)
-            hipLaunchKernelGGL(k_tangent_rhs_edge, dim3(grid_for(der_edge_count(l0.N))), dim3(kBlock), 0, st, out, l0.N);
     };
     TIMED(P, 0, DMGS_K_GRAD, 56.0 * l0.nv, st,
           (harmonic(P) ? launch(std::true_type()) : launch(std::false_type())));
@@ -2207,9 +2209,6 @@ int coef_grads(dmgs_plan P, const double* rho, const double* lam, double* gD, do
         hipLaunchKernelGGL((k_coef_grads_col<decltype(harm)::value, decltype(dat)::value>), g, dim3(kDerThreads), 0, st,
                            rho, lam, (const double*)l0.D64, (const double*)l0.mu64, l0.N, l0.inv_h2, gD, gmu, d, w,
                            chunk, cover);
-        if (cover == l0.N)
-            hipLaunchKernelGGL(k_coef_grads_edge<decltype(harm)::value>, dim3(grid_for(der_edge_count(l0.N))),
-                               dim3(kBlock), 0, st, rho, lam, (const double*)l0.D64, l0.N, l0.inv_h2, gD, gmu);
     };
     using T_ = std::true_type;
     using F_ = std::false_type;
@@ -2880,9 +2879,6 @@ int vcycle_taped(dmgs_plan P, UnWork& W, int k, double* u, const double* q, cons
         auto launch = [&](auto harm) {
             hipLaunchKernelGGL(k_un_gs_half_t<decltype(harm)::value>, g, dim3(kDerThreads), 0, st, in, W.tape[k][h],
                                q, (const double*)l.D64, (const double*)l.w64, l.N, s, colour, chunk, cover);
-            if (cover == l.N)
-                hipLaunchKernelGGL(k_un_gs_half_edge, dim3(grid_for(der_edge_count(l.N))), dim3(kBlock), 0, st, in,
-                                   W.tape[k][h], l.N);
         };
         if (s.harmonic) launch(std::true_type());
         else launch(std::false_type());
@@ -2949,9 +2945,6 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
         auto launch = [&](auto harm) {
             hipLaunchKernelGGL(k_un_defect_t<decltype(harm)::value>, g, dim3(kDerThreads), 0, st, ubar, rb, scale, u,
                                D, mu, l.N, s, W.qbar[k], W.Dbar[k], W.mbar[k], chunk, cover);
-            if (cover == l.N)
-                hipLaunchKernelGGL(k_un_defect_edge<decltype(harm)::value>, dim3(grid_for(der_edge_count(l.N))),
-                                   dim3(kBlock), 0, st, rb, scale, u, D, l.N, s, W.Dbar[k]);
         };
         if (s.harmonic) launch(std::true_type());
         else launch(std::false_type());
@@ -2990,10 +2983,6 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
             hipLaunchKernelGGL(k_un_half_rev<decltype(harm)::value>, g, dim3(kDerThreads), 0, st,
                                (const double*)W.ubar[k], W.V[k], state, D, (const double*)l.w64, l.N, s, colour,
                                W.qbar[k], W.mbar[k], W.Dbar[k], chunk, cover);
-            if (cover == l.N)
-                hipLaunchKernelGGL(k_un_half_rev_edge<decltype(harm)::value>, dim3(grid_for(der_edge_count(l.N))),
-                                   dim3(kBlock), 0, st, (const double*)W.ubar[k], state, D, (const double*)l.w64, l.N,
-                                   s, colour, W.Dbar[k]);
         };
         if (s.harmonic) launch(std::true_type());
         else launch(std::false_type());

@@ -7,10 +7,11 @@
 // thread each, and marches them along x over a chunk of planes.  The tiles
 // cover y, z < cover.  On large levels cover = N: the boundary planes
 // y = N and z = N (a single row or column beyond whole tiles when N is a
-// multiple of the tile) are left to a one-vertex-per-thread companion
-// kernel, so no workgroup holds a nearly empty tile.  On small levels, where
-// launches cost more than idle lanes, cover = N + 1 and the tiles take every
-// vertex.  Each
+// multiple of the tile) are left to extra workgroups of the same launch,
+// one vertex per thread (grid rows past the chunks), so no workgroup holds
+// a nearly empty tile.  Their outputs are disjoint from the tiles' and they
+// read nothing the tiles write.  On small levels, where idle lanes cost
+// little, cover = N + 1 and the tiles take every vertex.  Each
 // thread keeps its own column's values at x - 1, x and x + 1 in registers
 // (and the planes after them in flight).  The in-plane neighbours come from
 // an LDS copy of plane x over the tile plus a ring of one vertex: the
@@ -40,8 +41,12 @@ struct DerTile {
     int64_t sx, p, hp;   // plane stride; in-plane offsets of the column and the ring cell
 };
 
+// Chunks of planes along x (grid rows of tiles); rows past them take the
+// boundary planes.
+__device__ __forceinline__ int der_chunks(int N, int chunk) { return (N + chunk) / chunk; }
+
 __device__ __forceinline__ void der_tile(int N, int chunk, int cover, DerTile& t) {
-    const int nb = (int)(gridDim.x * gridDim.y);
+    const int nb = (int)gridDim.x * der_chunks(N, chunk);
     const int L = xcd_remap((int)(blockIdx.y * gridDim.x + blockIdx.x), nb);
     const int tile = L % (int)gridDim.x, ch = L / (int)gridDim.x;
     t.n = N + 1;
@@ -86,10 +91,9 @@ struct DerEdge {
     bool jin;       // the neighbour is interior
 };
 
-__device__ __forceinline__ bool der_edge(int N, DerEdge& e) {
+__device__ __forceinline__ void der_edge_at(int N, int64_t t, DerEdge& e) {
     const int n = N + 1;
-    const int64_t nn = (int64_t)n * n, t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nn + (int64_t)n * N) return false;
+    const int64_t nn = (int64_t)n * n;
     int x, y, z;
     if (t < nn) {
         x = (int)(t / n); y = N; z = (int)(t % n);
@@ -102,11 +106,28 @@ __device__ __forceinline__ bool der_edge(int N, DerEdge& e) {
         e.j = ((int64_t)x * n + y) * n + (N - 1);
     }
     e.i = ((int64_t)x * n + y) * n + z;
-    return true;
 }
 
 // Vertices of the boundary planes y = N and z = N (all 2 n^2 - n of them).
 __host__ __device__ inline int64_t der_edge_count(int N) { return (int64_t)(N + 1) * (2 * N + 1); }
+
+// In a workgroup of the grid rows past the chunks, runs f(e) for this
+// thread's share of the boundary-plane vertices and returns true (the whole
+// workgroup then leaves before the march and its barriers).
+template <class F>
+__device__ __forceinline__ bool der_edge_block(int N, int chunk, F&& f) {
+    const int nch = der_chunks(N, chunk);
+    if ((int)blockIdx.y < nch) return false;
+    const int64_t cnt = der_edge_count(N);
+    const int64_t stride = (int64_t)(gridDim.y - nch) * gridDim.x * blockDim.x;
+    for (int64_t t = ((int64_t)(blockIdx.y - nch) * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x; t < cnt;
+         t += stride) {
+        DerEdge e;
+        der_edge_at(N, t, e);
+        f(e);
+    }
+    return true;
+}
 
 // d D_f along the tangent: D_f = (D_a + D_b)/2 or 2 D_a D_b / (D_a + D_b),
 // with dD = D dlogD at both ends
@@ -155,6 +176,8 @@ __global__ __launch_bounds__(kDerThreads) void k_tangent_rhs_col(const double* _
                                                                 const double* __restrict__ D,
                                                                 const double* __restrict__ mu, int N, double inv_h2,
                                                                 double* __restrict__ rhs, int chunk, int cover) {
+    // the planes y = N and z = N: 0 (boundary)
+    if (der_edge_block(N, chunk, [&](const DerEdge& e) { rhs[e.i] = 0.0; })) return;
     __shared__ double sR[2][kDerCells], sD[2][kDerCells], sT[2][kDerCells];
     DerTile t;
     der_tile(N, chunk, cover, t);
@@ -222,10 +245,29 @@ __global__ __launch_bounds__(kDerThreads) void k_tangent_rhs_col(const double* _
     }
 }
 
-// The tangent right-hand side on the planes y = N and z = N: 0 (boundary).
-__global__ void k_tangent_rhs_edge(double* __restrict__ rhs, int N) {
-    DerEdge e;
-    if (der_edge(N, e)) rhs[e.i] = 0.0;
+// The coefficient gradients on the planes y = N and z = N: logmua_bar = 0
+// (boundary); logD_bar from the one face to an interior neighbour j, with
+// lam = 0 at the vertex itself (the other faces join boundary vertices and
+// count for nothing on the tiles either).
+template <bool HARM>
+__device__ __forceinline__ void coef_grads_edge(const DerEdge& e, const double* __restrict__ rho,
+                                                const double* __restrict__ lam, const double* __restrict__ D,
+                                                double inv_h2, double* __restrict__ gD, double* __restrict__ gmu) {
+    if (gmu) gmu[e.i] = 0.0;
+    if (!gD) return;
+    double acc = 0.0;
+    if (e.jin) {
+        const double Dv = D[e.i], Dj = D[e.j];
+        double dcdv;
+        if (HARM) {
+            const double sum = Dv + Dj;
+            dcdv = 2.0 * Dj * Dj * Dv / (sum * sum);
+        } else {
+            dcdv = 0.5 * Dv;
+        }
+        acc += dcdv * (0.0 - lam[e.j]) * (rho[e.i] - rho[e.j]);
+    }
+    gD[e.i] = -acc * inv_h2;
 }
 
 // Coefficient gradients from the adjoint state lam = qbar:
@@ -244,6 +286,8 @@ __global__ __launch_bounds__(kDerThreads) void k_coef_grads_col(const double* __
                                                                double* __restrict__ gD, double* __restrict__ gmu,
                                                                const double* __restrict__ d,
                                                                const double* __restrict__ w, int chunk, int cover) {
+    if (der_edge_block(N, chunk, [&](const DerEdge& e) { coef_grads_edge<HARM>(e, rho, lam, D, inv_h2, gD, gmu); }))
+        return;
     __shared__ double sL[2][kDerCells], sR[2][kDerCells], sD[2][kDerCells];
     DerTile t;
     der_tile(N, chunk, cover, t);
@@ -335,33 +379,6 @@ __global__ __launch_bounds__(kDerThreads) void k_coef_grads_col(const double* __
         step(x + 3, R3, R4, R0, R2, H3, H0);
         step(x + 4, R4, R0, R1, R3, H4, H1);
     }
-}
-
-// The coefficient gradients on the planes y = N and z = N: logmua_bar = 0
-// (boundary); logD_bar from the one face to an interior neighbour j, with
-// lam = 0 at the vertex itself (the other faces join boundary vertices and
-// count for nothing in k_coef_grads_col either).
-template <bool HARM>
-__global__ void k_coef_grads_edge(const double* __restrict__ rho, const double* __restrict__ lam,
-                                  const double* __restrict__ D, int N, double inv_h2, double* __restrict__ gD,
-                                  double* __restrict__ gmu) {
-    DerEdge e;
-    if (!der_edge(N, e)) return;
-    if (gmu) gmu[e.i] = 0.0;
-    if (!gD) return;
-    double acc = 0.0;
-    if (e.jin) {
-        const double Dv = D[e.i], Dj = D[e.j];
-        double dcdv;
-        if (HARM) {
-            const double sum = Dv + Dj;
-            dcdv = 2.0 * Dj * Dj * Dv / (sum * sum);
-        } else {
-            dcdv = 0.5 * Dv;
-        }
-        acc += dcdv * (0.0 - lam[e.j]) * (rho[e.i] - rho[e.j]);
-    }
-    gD[e.i] = -acc * inv_h2;
 }
 
 }  // namespace dmgs

@@ -222,6 +222,57 @@ __global__ void k_un_defect(double* __restrict__ ubar, const double* __restrict_
     }
 }
 
+// The planes y = N and z = N that the column tiles leave out (taken by the
+// extra workgroups of the same launches, see der_edge_block): boundary
+// vertices, where only Dbar changes, by the one face to an interior
+// neighbour j (the other faces join boundary vertices, whose cotangent terms
+// are 0).
+
+// reverse half-sweep: V = 0 at the vertex, V_j = ubar_j w_j if j is of colour C
+template <bool HARM>
+__device__ __forceinline__ void un_half_rev_edge(const DerEdge& e, const double* __restrict__ ubar_in,
+                                                 const double* __restrict__ up, const double* __restrict__ D,
+                                                 const double* __restrict__ w, int N, const Stencil<double>& s,
+                                                 int colour, double* __restrict__ Dbar) {
+    const int n = N + 1;
+    double dacc = 0.0;
+    if (e.jin) {
+        const int jx = (int)(e.j / ((int64_t)n * n)), jy = (int)((e.j / n) % n), jz = (int)(e.j % n);
+        const double Vj = ((jx + jy + jz) & 1) == colour ? ubar_in[e.j] * w[e.j] : 0.0;
+        const double Dv = D[e.i], Dj = D[e.j];
+        double dda;
+        if (HARM) {
+            const double t = Dv + Dj;
+            dda = Dj * Dj / (t * t) * s.two_inv_h2;
+        } else {
+            dda = s.half_inv_h2;
+        }
+        dacc += (0.0 - Vj) * (up[e.i] - up[e.j]) * dda;
+    }
+    Dbar[e.i] = Dbar[e.i] - dacc;
+}
+
+// defect reverse: rbar = 0 at the vertex, scale * rb_j at the interior neighbour
+template <bool HARM>
+__device__ __forceinline__ void un_defect_edge(const DerEdge& e, const double* __restrict__ rb, double scale,
+                                               const double* __restrict__ u, const double* __restrict__ D,
+                                               const Stencil<double>& s, double* __restrict__ Dbar) {
+    double dacc = 0.0;
+    if (e.jin) {
+        const double rj = scale * rb[e.j];
+        const double Dv = D[e.i], Dj = D[e.j];
+        double dda;
+        if (HARM) {
+            const double t = Dv + Dj;
+            dda = Dj * Dj / (t * t) * s.two_inv_h2;
+        } else {
+            dda = s.half_inv_h2;
+        }
+        dacc += (0.0 - rj) * (u[e.i] - u[e.j]) * dda;
+    }
+    Dbar[e.i] = Dbar[e.i] - dacc;
+}
+
 // The whole reverse of one half-sweep of colour C in one pass (levels the
 // column tiles of kernels_deriv.hpp cover), with V_i = ubar_i w_i (w the
 // inverse diagonal 1 / d_i) formed where it is needed instead of stored:
@@ -243,6 +294,10 @@ __global__ __launch_bounds__(kDerThreads) void k_un_half_rev(const double* __res
                                                             int colour, double* __restrict__ qbar,
                                                             double* __restrict__ mubar, double* __restrict__ Dbar,
                                                             int chunk, int cover) {
+    if (der_edge_block(N, chunk, [&](const DerEdge& e) {
+            un_half_rev_edge<HARM>(e, ubar_in, up, D, w, N, s, colour, Dbar);
+        }))
+        return;
     __shared__ double sV[2][kDerCells], sU[2][kDerCells], sD[2][kDerCells];
     DerTile t;
     der_tile(N, chunk, cover, t);
@@ -340,6 +395,8 @@ __global__ __launch_bounds__(kDerThreads) void k_un_gs_half_t(const double* __re
                                                              const double* __restrict__ D,
                                                              const double* __restrict__ w, int N, Stencil<double> s,
                                                              int colour, int chunk, int cover) {
+    // the planes y = N and z = N: boundary values are kept
+    if (der_edge_block(N, chunk, [&](const DerEdge& e) { u_out[e.i] = u_in[e.i]; })) return;
     __shared__ double sU[2][kDerCells], sD[2][kDerCells];
     DerTile t;
     der_tile(N, chunk, cover, t);
@@ -408,6 +465,8 @@ __global__ __launch_bounds__(kDerThreads) void k_un_defect_t(double* __restrict_
                                                             const double* __restrict__ mu, int N, Stencil<double> s,
                                                             double* __restrict__ qbar, double* __restrict__ Dbar,
                                                             double* __restrict__ mubar, int chunk, int cover) {
+    if (der_edge_block(N, chunk, [&](const DerEdge& e) { un_defect_edge<HARM>(e, rb, scale, u, D, s, Dbar); }))
+        return;
     __shared__ double sR[2][kDerCells], sU[2][kDerCells], sD[2][kDerCells];
     DerTile t;
     der_tile(N, chunk, cover, t);
@@ -488,64 +547,6 @@ __global__ __launch_bounds__(kDerThreads) void k_un_defect_t(double* __restrict_
         step(x + 3, R3, R4, R0, R2, H3, H0);
         step(x + 4, R4, R0, R1, R3, H4, H1);
     }
-}
-
-// The planes y = N and z = N that the column tiles leave out (see
-// der_edge): boundary vertices, where only Dbar changes, by the one face to
-// an interior neighbour j (the other faces join boundary vertices, whose
-// cotangent terms are 0).
-
-// recorded half-sweep: boundary values are kept
-__global__ void k_un_gs_half_edge(const double* __restrict__ u_in, double* __restrict__ u_out, int N) {
-    DerEdge e;
-    if (der_edge(N, e)) u_out[e.i] = u_in[e.i];
-}
-
-// reverse half-sweep: V = 0 at the vertex, V_j = ubar_j w_j if j is of colour C
-template <bool HARM>
-__global__ void k_un_half_rev_edge(const double* __restrict__ ubar_in, const double* __restrict__ up,
-                                   const double* __restrict__ D, const double* __restrict__ w, int N, Stencil<double> s,
-                                   int colour, double* __restrict__ Dbar) {
-    DerEdge e;
-    if (!der_edge(N, e)) return;
-    const int n = N + 1;
-    double dacc = 0.0;
-    if (e.jin) {
-        const int jx = (int)(e.j / ((int64_t)n * n)), jy = (int)((e.j / n) % n), jz = (int)(e.j % n);
-        const double Vj = ((jx + jy + jz) & 1) == colour ? ubar_in[e.j] * w[e.j] : 0.0;
-        const double Dv = D[e.i], Dj = D[e.j];
-        double dda;
-        if (HARM) {
-            const double t = Dv + Dj;
-            dda = Dj * Dj / (t * t) * s.two_inv_h2;
-        } else {
-            dda = s.half_inv_h2;
-        }
-        dacc += (0.0 - Vj) * (up[e.i] - up[e.j]) * dda;
-    }
-    Dbar[e.i] = Dbar[e.i] - dacc;
-}
-
-// defect reverse: rbar = 0 at the vertex, scale * rb_j at the interior neighbour
-template <bool HARM>
-__global__ void k_un_defect_edge(const double* __restrict__ rb, double scale, const double* __restrict__ u,
-                                 const double* __restrict__ D, int N, Stencil<double> s, double* __restrict__ Dbar) {
-    DerEdge e;
-    if (!der_edge(N, e)) return;
-    double dacc = 0.0;
-    if (e.jin) {
-        const double rj = scale * rb[e.j];
-        const double Dv = D[e.i], Dj = D[e.j];
-        double dda;
-        if (HARM) {
-            const double t = Dv + Dj;
-            dda = Dj * Dj / (t * t) * s.two_inv_h2;
-        } else {
-            dda = s.half_inv_h2;
-        }
-        dacc += (0.0 - rj) * (u[e.i] - u[e.j]) * dda;
-    }
-    Dbar[e.i] = Dbar[e.i] - dacc;
 }
 
 // a *= f
