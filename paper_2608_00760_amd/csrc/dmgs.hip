@@ -2134,7 +2134,7 @@ dim3 der_grid(dmgs_plan P, int N, int* chunk, int* cover) {
     const int64_t pb = (int64_t)n * n * 8;
     for (int c = 1; c <= 64 && c <= n; c++) {
         const int ch = chunk_of(c);
-        if ((int64_t)(ch + 3) * pb >= (int64_t)kOob) continue;   // the kernels' 32-bit span of planes
+        if ((int64_t)(ch + 5) * pb >= (int64_t)kOob) continue;   // the kernels' 32-bit span of planes
         const int nb = tiles * ((n + ch - 1) / ch);
         const int rounds = (nb + P->ncu - 1) / P->ncu;
         const double v = (double)nb / ((double)rounds * P->ncu) * ch / (ch + 2.0);
@@ -2867,18 +2867,29 @@ int vcycle_taped(dmgs_plan P, UnWork& W, int k, double* u, const double* q, cons
     const bool tiled = l.N >= kDerSplitMin;   // smaller levels: the x-march forms
     int uchunk = 1;
     const dim3 ug = un_col_grid(l.N, &uchunk);
+    // one recorded half-sweep on an x-march level
     auto half = [&](const double* in, int h, int colour) -> int {
         UNCHK(W, in, l.nv, "a half-sweep input");
         UNCHK(W, W.tape[k][h], l.nv, "a tape slot");
+        hipLaunchKernelGGL(k_un_gs_half, ug, dim3(kBlock), 0, st, in, W.tape[k][h], q, (const double*)l.D64,
+                           (const double*)l.mu64, l.N, s, colour, uchunk);
+        LAUNCHCHK();
+        return DMGS_OK;
+    };
+    // a whole sweep (first colour, then second): on tiled levels one pass
+    // writing both tape slots
+    auto sweep = [&](const double* in, int h) -> int {
         if (!tiled) {
-            hipLaunchKernelGGL(k_un_gs_half, ug, dim3(kBlock), 0, st, in, W.tape[k][h], q, (const double*)l.D64,
-                               (const double*)l.mu64, l.N, s, colour, uchunk);
-            LAUNCHCHK();
-            return DMGS_OK;
+            TRY(half(in, h, 0));
+            return half(W.tape[k][h], h + 1, 1);
         }
+        UNCHK(W, in, l.nv, "a sweep input");
+        UNCHK(W, W.tape[k][h], l.nv, "a tape slot");
+        UNCHK(W, W.tape[k][h + 1], l.nv, "a tape slot");
         auto launch = [&](auto harm) {
-            hipLaunchKernelGGL(k_un_gs_half_t<decltype(harm)::value>, g, dim3(kDerThreads), 0, st, in, W.tape[k][h],
-                               q, (const double*)l.D64, (const double*)l.w64, l.N, s, colour, chunk, cover);
+            hipLaunchKernelGGL(k_un_gs_sweep_t<decltype(harm)::value>, g, dim3(kDerThreads), 0, st, in, W.tape[k][h],
+                               W.tape[k][h + 1], q, (const double*)l.D64, (const double*)l.w64, l.N, s, 0, chunk,
+                               cover);
         };
         if (s.harmonic) launch(std::true_type());
         else launch(std::false_type());
@@ -2887,11 +2898,10 @@ int vcycle_taped(dmgs_plan P, UnWork& W, int k, double* u, const double* q, cons
     };
     const double* src = u;
     int h = 0;
-    for (int i = 0; i < nu1; i++)
-        for (int colour = 0; colour < 2; colour++, h++) {
-            TRY(half(src, h, colour));
-            src = W.tape[k][h];
-        }
+    for (int i = 0; i < nu1; i++, h += 2) {
+        TRY(sweep(src, h));
+        src = W.tape[k][h + 1];
+    }
     if (nu1 == 0) {
         // u itself becomes the post-smoothing input below: keep the state
         UNCHK(W, W.tape[k][2 * (nu1 + nu2)], l.nv, "the input's tape slot");
@@ -2913,11 +2923,10 @@ int vcycle_taped(dmgs_plan P, UnWork& W, int k, double* u, const double* q, cons
     hipLaunchKernelGGL(k_prolong_add<double>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, ec, u, l.N);
     LAUNCHCHK();
     src = u;
-    for (int i = 0; i < nu2; i++)
-        for (int colour = 0; colour < 2; colour++, h++) {
-            TRY(half(src, h, colour));
-            src = W.tape[k][h];
-        }
+    for (int i = 0; i < nu2; i++, h += 2) {
+        TRY(sweep(src, h));
+        src = W.tape[k][h + 1];
+    }
     *fin = src;
     return DMGS_OK;
 }

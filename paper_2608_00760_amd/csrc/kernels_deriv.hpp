@@ -147,16 +147,17 @@ __device__ __forceinline__ double dface(double Da, double dDa, double Db, double
 // nothing, store nothing and keep the barriers uniform.
 constexpr int kDerRing = 5;
 
-// The planes a block reads, [x0 - 1, x1] within the grid, through one buffer
-// resource per field; a plane is selected by a wave-uniform offset, and
-// planes outside the span, null fields and lanes without a column read 0.
-// The host keeps (chunk + 3) planes below 2^31 bytes.
+// The planes a block reads, [x0 - m, x1 + m - 1] within the grid (m = 1, or
+// 2 for the two-stage sweep), through one buffer resource per field; a plane
+// is selected by a wave-uniform offset, and planes outside the span, null
+// fields and lanes without a column read 0.  The host keeps (chunk + 5)
+// planes below 2^31 bytes.
 struct DerSpan {
     int xb, xe;        // planes [xb, xe)
     int pb;            // bytes per plane
     int64_t base;      // byte offset of plane xb
-    __device__ DerSpan(const DerTile& t, int n)
-        : xb(max(0, t.x0 - 1)), xe(min(n, t.x1 + 1)), pb((int)(t.sx * 8)), base((int64_t)xb * t.sx * 8) {}
+    __device__ DerSpan(const DerTile& t, int n, int m = 1)
+        : xb(max(0, t.x0 - m)), xe(min(n, t.x1 + m)), pb((int)(t.sx * 8)), base((int64_t)xb * t.sx * 8) {}
     __device__ __amdgpu_buffer_rsrc_t rsrc(const double* f) const {
         const char* b = reinterpret_cast<const char*>(f) + (f ? base : 0);
         return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(b), 0, f ? (xe - xb) * pb : 0, 0x00020000);

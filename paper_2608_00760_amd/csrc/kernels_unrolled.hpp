@@ -384,72 +384,130 @@ __global__ __launch_bounds__(kDerThreads) void k_un_half_rev(const double* __res
     }
 }
 
-// Recorded half-sweep of colour C, out of place: u_out = the Gauss-Seidel
-// value (q + sum_j c_ij u_j) w on C's interior vertices, with the stored
-// inverse diagonal w, and u_in elsewhere (it reads only the other colour, so
-// it equals the in-place sweep).  The recompute writes each state straight
-// into its tape slot.
+// A whole recorded sweep, out of place: u_mid = u_in after the half-sweep
+// of colour c1 (the Gauss-Seidel value (q + sum_j c_ij u_j) w on c1's
+// interior vertices, with the stored inverse diagonal w), u_out = u_mid
+// after the half-sweep of the other colour c2; the recompute writes both
+// states straight into their tape slots (each half-sweep reads only the
+// other colour, so it equals the in-place sweep).  Each field is read once
+// for the two half-sweeps.  The column tiles march along x with two stages:
+// at step x, stage 1 forms u_mid on plane x over the tile plus a ring of
+// one (the ring recomputed from u_in and D over a ring of two in LDS), and
+// stage 2 forms u_out on plane x - 1 from u_mid of plane x - 1 in LDS and of
+// planes x - 2 and x in registers.  One barrier per step orders all LDS
+// traffic: u and u_mid are double-buffered by plane parity, D (which stage 2
+// reads one step later) is kept for three planes.  Neighbours in the order
+// +x, -x, +y, -y, +z, -z.
+constexpr int kSwRY = kDerTY + 4, kSwRZ = kDerTZ + 4, kSwCells = kSwRY * kSwRZ;
+constexpr int kSwHalo = kSwCells - kDerThreads;   // ring-2 cells (336)
+
 template <bool HARM>
-__global__ __launch_bounds__(kDerThreads) void k_un_gs_half_t(const double* __restrict__ u_in,
-                                                             double* __restrict__ u_out, const double* __restrict__ q,
-                                                             const double* __restrict__ D,
-                                                             const double* __restrict__ w, int N, Stencil<double> s,
-                                                             int colour, int chunk, int cover) {
+__global__ __launch_bounds__(kDerThreads) void k_un_gs_sweep_t(const double* __restrict__ u_in,
+                                                              double* __restrict__ u_mid, double* __restrict__ u_out,
+                                                              const double* __restrict__ q,
+                                                              const double* __restrict__ D,
+                                                              const double* __restrict__ w, int N, Stencil<double> s,
+                                                              int c1, int chunk, int cover) {
     // the planes y = N and z = N: boundary values are kept
-    if (der_edge_block(N, chunk, [&](const DerEdge& e) { u_out[e.i] = u_in[e.i]; })) return;
-    __shared__ double sU[2][kDerCells], sD[2][kDerCells];
+    if (der_edge_block(N, chunk, [&](const DerEdge& e) {
+            const double v = u_in[e.i];
+            u_mid[e.i] = v;
+            u_out[e.i] = v;
+        }))
+        return;
+    __shared__ double sU[2][kSwCells], sD[3][kSwCells], sM[2][kDerCells];
     DerTile t;
     der_tile(N, chunk, cover, t);
     const int n = t.n;
-    struct H {
-        double u, D;
+    const int tid = (int)threadIdx.x;
+    const int c2 = 1 - c1;
+    // this thread's cell in the ring-2 arrays, and its ring cell (tid <
+    // kSwHalo): rows y0 - 2, y0 - 1 and y0 + 16, y0 + 17 whole, then columns
+    // z0 - 2, z0 - 1, z0 + 64, z0 + 65 of the tile's rows
+    const int y0 = t.y - tid / kDerTZ, z0 = t.z - tid % kDerTZ;
+    const int cell2 = (tid / kDerTZ + 2) * kSwRZ + tid % kDerTZ + 2;
+    int ly, lz;
+    if (tid < 2 * kSwRZ) {
+        ly = tid / kSwRZ - 2; lz = tid % kSwRZ - 2;
+    } else if (tid < 4 * kSwRZ) {
+        ly = kDerTY + (tid - 2 * kSwRZ) / kSwRZ; lz = (tid - 2 * kSwRZ) % kSwRZ - 2;
+    } else {
+        const int u = tid - 4 * kSwRZ;   // < 4 * kDerTY for ring threads
+        ly = u / 4;
+        const int c = u % 4;
+        lz = c < 2 ? c - 2 : kDerTZ + c - 2;
+    }
+    const bool halo = tid < kSwHalo;
+    const int hy = y0 + ly, hz = z0 + lz;
+    const bool hv = halo && hy >= 0 && hy < n && hz >= 0 && hz < n;
+    const bool r1 = halo && ly >= -1 && ly <= kDerTY && lz >= -1 && lz <= kDerTZ;   // ring of one
+    const int hcell2 = (ly + 2) * kSwRZ + lz + 2, hcell1 = (ly + 1) * kDerRZ + lz + 1;
+    const int64_t hp = hv ? (int64_t)hy * n + hz : 0;
+    struct F {
+        double u, D, q, w;
     };
-    struct Vp : H {
-        double q, w;   // own column only
-    };
-    const DerSpan sp(t, n);
+    const DerSpan sp(t, n, 2);
     const auto rU = sp.rsrc(u_in), rD = sp.rsrc(D), rQ = sp.rsrc(q), rW = sp.rsrc(w);
-    auto load_h = [&](int x, bool valid, int64_t p) -> H {
+    const int xs = t.x0 - 1, xlast = t.x1;   // stage 1 runs on planes [xs, xlast]
+    auto load = [&](int x, bool valid, bool full, int64_t p) -> F {
         const int o = valid ? (int)(p * 8) : kOob, so = sp.off(x);
-        return H{buf_load_s(rU, o, so), buf_load_s(rD, o, so)};
+        const int of = (full && x >= xs && x <= xlast) ? o : kOob;
+        return F{buf_load_s(rU, o, so), buf_load_s(rD, o, so), buf_load_s(rQ, of, so), buf_load_s(rW, of, so)};
     };
-    auto load_v = [&](int x) -> Vp {
-        Vp v;
-        static_cast<H&>(v) = load_h(x, t.inb, t.p);
-        const int oo = (t.own && x < t.x1) ? (int)(t.p * 8) : kOob, so = sp.off(x);
-        v.q = buf_load_s(rQ, oo, so);
-        v.w = buf_load_s(rW, oo, so);
-        return v;
+    auto load_v = [&](int x) { return load(x, t.inb, true, t.p); };
+    auto load_h = [&](int x) { return load(x, hv, r1 && hv, hp); };
+    auto fc = [&](double Da, double Db) { return face<HARM>(Da, Db, s); };
+    // stage 1 at one vertex of plane x: its value after the c1 half-sweep
+    auto stage1 = [&](int b, int b3, int x, int y, int z, int c, const F& Fm, const F& Fc, const F& Fp) {
+        if (!is_interior(N, x, y, z) || ((x + y + z) & 1) != c1) return Fc.u;
+        const int e[4] = {c + kSwRZ, c - kSwRZ, c + 1, c - 1};
+        double num = Fc.q + fc(Fc.D, Fp.D) * Fp.u + fc(Fc.D, Fm.D) * Fm.u;
+        for (int k = 0; k < 4; k++) num += fc(Fc.D, sD[b3][e[k]]) * sU[b][e[k]];
+        return num * Fc.w;
     };
-    const bool halo = threadIdx.x < kDerHalo;
     const bool yz = t.y > 0 && t.y < N && t.z > 0 && t.z < N;
-    auto step = [&](int x, Vp& Rm, Vp& Rc, Vp& Rp, Vp& Rl, H& Hc, H& Hl) {
-        const int b = x & 1;
-        sU[b][t.cell] = Rc.u; sD[b][t.cell] = Rc.D;
-        if (halo) { sU[b][t.hcell] = Hc.u; sD[b][t.hcell] = Hc.D; }
+    double m2 = 0.0, m1 = 0.0;   // own u_mid at planes x - 2, x - 1
+    auto step = [&](int x, F& Rm, F& Rc, F& Rp, F& Rl, F& Hm, F& Hc, F& Hp, F& Hl) {
+        const int b = x & 1, b3 = (x + 3) % 3;   // x >= -1
+        sU[b][cell2] = Rc.u; sD[b3][cell2] = Rc.D;
+        if (halo) { sU[b][hcell2] = Hc.u; sD[b3][hcell2] = Hc.D; }
         lds_barrier();
-        Rl = load_v(x + 3);
-        Hl = load_h(x + 2, t.hv, t.hp);
-        if (t.own && x < t.x1) {
-            double v = Rc.u;
-            if (yz && x > 0 && x < N && ((x + t.y + t.z) & 1) == colour) {
+        // stage 2's -x coefficient needs D of plane x - 2, whose registers
+        // take plane x + 2 now (first used at the next step)
+        const double fm = fc(Rm.D, Rl.D);
+        Rl = load_v(x + 2);
+        Hl = load_h(x + 2);
+        const double m0 = stage1(b, b3, x, t.y, t.z, cell2, Rm, Rc, Rp);
+        sM[b][t.cell] = m0;
+        if (r1) sM[b][hcell1] = stage1(b, b3, x, hy, hz, hcell2, Hm, Hc, Hp);
+        if (t.own && x >= t.x0 && x < t.x1) u_mid[x * t.sx + t.p] = m0;
+        // stage 2 on plane x - 1 (its u_mid and D in-plane from the previous step's slots)
+        const int xm = x - 1;
+        if (t.own && xm >= t.x0 && xm < t.x1) {
+            double v = m1;
+            if (yz && xm > 0 && xm < N && ((xm + t.y + t.z) & 1) == c2) {
+                const int bm = b ^ 1, bm3 = (x + 2) % 3;
+                const int c = (t.cell / kDerRZ + 1) * kSwRZ + t.cell % kDerRZ + 1;   // = cell2
                 const int e[4] = {t.cell + kDerRZ, t.cell - kDerRZ, t.cell + 1, t.cell - 1};
-                double num = Rc.q + face<HARM>(Rc.D, Rp.D, s) * Rp.u + face<HARM>(Rc.D, Rm.D, s) * Rm.u;
-                for (int k = 0; k < 4; k++) num += face<HARM>(Rc.D, sD[b][e[k]], s) * sU[b][e[k]];
-                v = num * Rc.w;
+                const int e2[4] = {c + kSwRZ, c - kSwRZ, c + 1, c - 1};
+                double num = Rm.q + fc(Rm.D, Rc.D) * m0 + fm * m2;
+                for (int k = 0; k < 4; k++) num += fc(Rm.D, sD[bm3][e2[k]]) * sM[bm][e[k]];
+                v = num * Rm.w;
             }
-            u_out[x * t.sx + t.p] = v;
+            u_out[xm * t.sx + t.p] = v;
         }
+        m2 = m1;
+        m1 = m0;
     };
-    const int x0 = t.x0;
-    Vp R0 = load_v(x0 - 1), R1 = load_v(x0), R2 = load_v(x0 + 1), R3 = load_v(x0 + 2), R4;
-    H H0 = load_h(x0, t.hv, t.hp), H1 = load_h(x0 + 1, t.hv, t.hp), H2, H3, H4;
-    for (int x = x0; x < t.x1; x += kDerRing) {
-        step(x, R0, R1, R2, R4, H0, H2);
-        step(x + 1, R1, R2, R3, R0, H1, H3);
-        step(x + 2, R2, R3, R4, R1, H2, H4);
-        step(x + 3, R3, R4, R0, R2, H3, H0);
-        step(x + 4, R4, R0, R1, R3, H4, H1);
+    // a ring of four planes (x - 1, x, x + 1 and x + 2 in flight), unrolled by
+    // four; steps past the chunk's last plane store nothing
+    F R0 = load_v(xs - 2), R1 = load_v(xs - 1), R2 = load_v(xs), R3 = load_v(xs + 1);
+    F H0 = load_h(xs - 2), H1 = load_h(xs - 1), H2 = load_h(xs), H3 = load_h(xs + 1);
+    for (int x = xs; x <= xlast; x += 4) {
+        step(x, R1, R2, R3, R0, H1, H2, H3, H0);
+        step(x + 1, R2, R3, R0, R1, H2, H3, H0, H1);
+        step(x + 2, R3, R0, R1, R2, H3, H0, H1, H2);
+        step(x + 3, R0, R1, R2, R3, H0, H1, H2, H3);
     }
 }
 
