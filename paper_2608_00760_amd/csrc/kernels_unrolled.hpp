@@ -392,14 +392,18 @@ __global__ __launch_bounds__(kDerThreads) void k_un_half_rev(const double* __res
 // other colour, so it equals the in-place sweep).  Each field is read once
 // for the two half-sweeps.  The column tiles march along x with two stages:
 // at step x, stage 1 forms u_mid on plane x over the tile plus a ring of
-// one (the ring recomputed from u_in and D over a ring of two in LDS), and
-// stage 2 forms u_out on plane x - 1 from u_mid of plane x - 1 in LDS and of
-// planes x - 2 and x in registers.  One barrier per step orders all LDS
-// traffic: u and u_mid are double-buffered by plane parity, D (which stage 2
-// reads one step later) is kept for three planes.  Neighbours in the order
-// +x, -x, +y, -y, +z, -z.
+// one, and stage 2 forms u_out on plane x - 1 from u_mid of plane x - 1 in
+// LDS and of planes x - 2 and x in registers.  u and D live in LDS over the
+// tile plus a ring of two for five planes (x - 2 .. x + 2; plane x + 1 is
+// published at step x, after it was loaded at step x - 1), so both stages
+// take their x-neighbours from LDS and a thread keeps only the plane in
+// flight and q, w of three planes in registers.  One barrier per step
+// orders all LDS traffic: a plane's slot is rewritten four steps after its
+// last reader's step ended, u_mid is double-buffered by plane parity.
+// Neighbours in the order +x, -x, +y, -y, +z, -z.
 constexpr int kSwRY = kDerTY + 4, kSwRZ = kDerTZ + 4, kSwCells = kSwRY * kSwRZ;
 constexpr int kSwHalo = kSwCells - kDerThreads;   // ring-2 cells (336)
+constexpr int kSwSlots = 5;
 
 template <bool HARM>
 __global__ __launch_bounds__(kDerThreads) void k_un_gs_sweep_t(const double* __restrict__ u_in,
@@ -415,7 +419,7 @@ __global__ __launch_bounds__(kDerThreads) void k_un_gs_sweep_t(const double* __r
             u_out[e.i] = v;
         }))
         return;
-    __shared__ double sU[2][kSwCells], sD[3][kSwCells], sM[2][kDerCells];
+    __shared__ double sU[kSwSlots][kSwCells], sD[kSwSlots][kSwCells], sM[2][kDerCells];
     DerTile t;
     der_tile(N, chunk, cover, t);
     const int n = t.n;
@@ -443,71 +447,85 @@ __global__ __launch_bounds__(kDerThreads) void k_un_gs_sweep_t(const double* __r
     const bool r1 = halo && ly >= -1 && ly <= kDerTY && lz >= -1 && lz <= kDerTZ;   // ring of one
     const int hcell2 = (ly + 2) * kSwRZ + lz + 2, hcell1 = (ly + 1) * kDerRZ + lz + 1;
     const int64_t hp = hv ? (int64_t)hy * n + hz : 0;
-    struct F {
-        double u, D, q, w;
+    struct UD {
+        double u, D;
+    };
+    struct QW {
+        double q, w;
     };
     const DerSpan sp(t, n, 2);
     const auto rU = sp.rsrc(u_in), rD = sp.rsrc(D), rQ = sp.rsrc(q), rW = sp.rsrc(w);
     const int xs = t.x0 - 1, xlast = t.x1;   // stage 1 runs on planes [xs, xlast]
-    auto load = [&](int x, bool valid, bool full, int64_t p) -> F {
+    auto load_ud = [&](int x, bool valid, int64_t p) -> UD {
         const int o = valid ? (int)(p * 8) : kOob, so = sp.off(x);
-        const int of = (full && x >= xs && x <= xlast) ? o : kOob;
-        return F{buf_load_s(rU, o, so), buf_load_s(rD, o, so), buf_load_s(rQ, of, so), buf_load_s(rW, of, so)};
+        return UD{buf_load_s(rU, o, so), buf_load_s(rD, o, so)};
     };
-    auto load_v = [&](int x) { return load(x, t.inb, true, t.p); };
-    auto load_h = [&](int x) { return load(x, hv, r1 && hv, hp); };
+    auto load_qw = [&](int x, bool valid, int64_t p) -> QW {
+        const int o = (valid && x >= xs && x <= xlast) ? (int)(p * 8) : kOob, so = sp.off(x);
+        return QW{buf_load_s(rQ, o, so), buf_load_s(rW, o, so)};
+    };
+    const bool hq = r1 && hv;
+    auto slot = [](int x) { return (x + 2 * kSwSlots) % kSwSlots; };   // x >= -3
+    auto publish = [&](int x, const UD& own, const UD& ring) {
+        const int k = slot(x);
+        sU[k][cell2] = own.u; sD[k][cell2] = own.D;
+        if (halo) { sU[k][hcell2] = ring.u; sD[k][hcell2] = ring.D; }
+    };
     auto fc = [&](double Da, double Db) { return face<HARM>(Da, Db, s); };
-    // stage 1 at one vertex of plane x: its value after the c1 half-sweep
-    auto stage1 = [&](int b, int b3, int x, int y, int z, int c, const F& Fm, const F& Fc, const F& Fp) {
-        if (!is_interior(N, x, y, z) || ((x + y + z) & 1) != c1) return Fc.u;
+    // stage 1 at one vertex (cell c of the ring-2 arrays) of plane x
+    auto stage1 = [&](int x, int y, int z, int c, const QW& f) {
+        const int k = slot(x), km = slot(x - 1), kp = slot(x + 1);
+        const double u = sU[k][c];
+        if (!is_interior(N, x, y, z) || ((x + y + z) & 1) != c1) return u;
+        const double Dc = sD[k][c];
         const int e[4] = {c + kSwRZ, c - kSwRZ, c + 1, c - 1};
-        double num = Fc.q + fc(Fc.D, Fp.D) * Fp.u + fc(Fc.D, Fm.D) * Fm.u;
-        for (int k = 0; k < 4; k++) num += fc(Fc.D, sD[b3][e[k]]) * sU[b][e[k]];
-        return num * Fc.w;
+        double num = f.q + fc(Dc, sD[kp][c]) * sU[kp][c] + fc(Dc, sD[km][c]) * sU[km][c];
+        for (int j = 0; j < 4; j++) num += fc(Dc, sD[k][e[j]]) * sU[k][e[j]];
+        return num * f.w;
     };
     const bool yz = t.y > 0 && t.y < N && t.z > 0 && t.z < N;
     double m2 = 0.0, m1 = 0.0;   // own u_mid at planes x - 2, x - 1
-    auto step = [&](int x, F& Rm, F& Rc, F& Rp, F& Rl, F& Hm, F& Hc, F& Hp, F& Hl) {
-        const int b = x & 1, b3 = (x + 3) % 3;   // x >= -1
-        sU[b][cell2] = Rc.u; sD[b3][cell2] = Rc.D;
-        if (halo) { sU[b][hcell2] = Hc.u; sD[b3][hcell2] = Hc.D; }
+    UD P, PH;                    // plane x + 1 (own, ring), published at step x
+    // step x: qm, qc hold q, w of planes x - 1, x; qn receives plane x + 1
+    auto step = [&](int x, QW& qm, QW& qc, QW& qn, QW& hqc, QW& hqn) {
+        publish(x + 1, P, PH);
         lds_barrier();
-        // stage 2's -x coefficient needs D of plane x - 2, whose registers
-        // take plane x + 2 now (first used at the next step)
-        const double fm = fc(Rm.D, Rl.D);
-        Rl = load_v(x + 2);
-        Hl = load_h(x + 2);
-        const double m0 = stage1(b, b3, x, t.y, t.z, cell2, Rm, Rc, Rp);
-        sM[b][t.cell] = m0;
-        if (r1) sM[b][hcell1] = stage1(b, b3, x, hy, hz, hcell2, Hm, Hc, Hp);
+        P = load_ud(x + 2, t.inb, t.p);
+        PH = load_ud(x + 2, hv, hp);
+        qn = load_qw(x + 1, t.inb, t.p);
+        hqn = load_qw(x + 1, hq, hp);
+        const double m0 = stage1(x, t.y, t.z, cell2, qc);
+        sM[x & 1][t.cell] = m0;
+        if (r1) sM[x & 1][hcell1] = stage1(x, hy, hz, hcell2, hqc);
         if (t.own && x >= t.x0 && x < t.x1) u_mid[x * t.sx + t.p] = m0;
-        // stage 2 on plane x - 1 (its u_mid and D in-plane from the previous step's slots)
+        // stage 2 on plane x - 1 (its u_mid from the previous step's slot)
         const int xm = x - 1;
         if (t.own && xm >= t.x0 && xm < t.x1) {
             double v = m1;
             if (yz && xm > 0 && xm < N && ((xm + t.y + t.z) & 1) == c2) {
-                const int bm = b ^ 1, bm3 = (x + 2) % 3;
-                const int c = (t.cell / kDerRZ + 1) * kSwRZ + t.cell % kDerRZ + 1;   // = cell2
+                const int k = slot(xm), bm = xm & 1;
+                const double Dc = sD[k][cell2];
                 const int e[4] = {t.cell + kDerRZ, t.cell - kDerRZ, t.cell + 1, t.cell - 1};
-                const int e2[4] = {c + kSwRZ, c - kSwRZ, c + 1, c - 1};
-                double num = Rm.q + fc(Rm.D, Rc.D) * m0 + fm * m2;
-                for (int k = 0; k < 4; k++) num += fc(Rm.D, sD[bm3][e2[k]]) * sM[bm][e[k]];
-                v = num * Rm.w;
+                const int e2[4] = {cell2 + kSwRZ, cell2 - kSwRZ, cell2 + 1, cell2 - 1};
+                double num = qm.q + fc(Dc, sD[slot(x)][cell2]) * m0 + fc(Dc, sD[slot(xm - 1)][cell2]) * m2;
+                for (int j = 0; j < 4; j++) num += fc(Dc, sD[k][e2[j]]) * sM[bm][e[j]];
+                v = num * qm.w;
             }
             u_out[xm * t.sx + t.p] = v;
         }
         m2 = m1;
         m1 = m0;
     };
-    // a ring of four planes (x - 1, x, x + 1 and x + 2 in flight), unrolled by
-    // four; steps past the chunk's last plane store nothing
-    F R0 = load_v(xs - 2), R1 = load_v(xs - 1), R2 = load_v(xs), R3 = load_v(xs + 1);
-    F H0 = load_h(xs - 2), H1 = load_h(xs - 1), H2 = load_h(xs), H3 = load_h(xs + 1);
-    for (int x = xs; x <= xlast; x += 4) {
-        step(x, R1, R2, R3, R0, H1, H2, H3, H0);
-        step(x + 1, R2, R3, R0, R1, H2, H3, H0, H1);
-        step(x + 2, R3, R0, R1, R2, H3, H0, H1, H2);
-        step(x + 3, R0, R1, R2, R3, H0, H1, H2, H3);
+    publish(xs - 1, load_ud(xs - 1, t.inb, t.p), load_ud(xs - 1, hv, hp));
+    publish(xs, load_ud(xs, t.inb, t.p), load_ud(xs, hv, hp));
+    P = load_ud(xs + 1, t.inb, t.p);
+    PH = load_ud(xs + 1, hv, hp);
+    QW Q0{0.0, 0.0}, Q1 = load_qw(xs, t.inb, t.p), Q2;
+    QW G0{0.0, 0.0}, G1 = load_qw(xs, hq, hp), G2;
+    for (int x = xs; x <= xlast; x += 3) {
+        step(x, Q0, Q1, Q2, G1, G2);
+        step(x + 1, Q1, Q2, Q0, G2, G0);
+        step(x + 2, Q2, Q0, Q1, G0, G1);
     }
 }
 
