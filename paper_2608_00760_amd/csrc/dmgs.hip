@@ -2973,24 +2973,30 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
         LAUNCHCHK();
         return DMGS_OK;
     }
-    // tiled levels: one pass per half-sweep, ubar ping-ponging between
-    // W.ubar[k] and W.V[k] (an even number of half-sweeps per phase leaves it
-    // in W.ubar[k]); x-march levels: V = ubar / d into W.V[k], then the gather
-    // updates ubar in place
+    // x-march levels: V = ubar / d into W.V[k], then the gather updates ubar
+    // in place
     auto half_rev = [&](const double* state, int colour) -> int {
         UNCHK(W, state, l.nv, "a recorded state");
+        hipLaunchKernelGGL(k_un_half_v, ug, dim3(kBlock), 0, st, (const double*)W.ubar[k], state, D, mu, l.N, s,
+                           colour, W.V[k], W.qbar[k], W.mbar[k], uchunk);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_un_half_gather, ug, dim3(kBlock), 0, st, W.ubar[k], (const double*)W.V[k], state, D,
+                           l.N, s, colour, W.Dbar[k], uchunk);
+        LAUNCHCHK();
+        return DMGS_OK;
+    };
+    // a whole sweep's reverse (its second colour first): on tiled levels one
+    // pass, ubar ping-ponging once
+    auto sweep_rev = [&](const double* sa, const double* sb) -> int {
         if (!tiled) {
-            hipLaunchKernelGGL(k_un_half_v, ug, dim3(kBlock), 0, st, (const double*)W.ubar[k], state, D, mu, l.N, s,
-                               colour, W.V[k], W.qbar[k], W.mbar[k], uchunk);
-            LAUNCHCHK();
-            hipLaunchKernelGGL(k_un_half_gather, ug, dim3(kBlock), 0, st, W.ubar[k], (const double*)W.V[k], state, D,
-                               l.N, s, colour, W.Dbar[k], uchunk);
-            LAUNCHCHK();
-            return DMGS_OK;
+            TRY(half_rev(sa, 1));
+            return half_rev(sb, 0);
         }
+        UNCHK(W, sa, l.nv, "a recorded state");
+        UNCHK(W, sb, l.nv, "a recorded state");
         auto launch = [&](auto harm) {
-            hipLaunchKernelGGL(k_un_half_rev<decltype(harm)::value>, g, dim3(kDerThreads), 0, st,
-                               (const double*)W.ubar[k], W.V[k], state, D, (const double*)l.w64, l.N, s, colour,
+            hipLaunchKernelGGL(k_un_sweep_rev_t<decltype(harm)::value>, g, dim3(kDerThreads), 0, st,
+                               (const double*)W.ubar[k], W.V[k], sa, sb, D, (const double*)l.w64, l.N, s, 1,
                                W.qbar[k], W.mbar[k], W.Dbar[k], chunk, cover);
         };
         if (s.harmonic) launch(std::true_type());
@@ -2999,7 +3005,7 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
         std::swap(W.ubar[k], W.V[k]);
         return DMGS_OK;
     };
-    for (int h = 2 * nu2 - 1; h >= 0; h--) TRY(half_rev(W.tape[k][2 * nu1 + h], h & 1));
+    for (int h = 2 * nu2 - 1; h >= 1; h -= 2) TRY(sweep_rev(W.tape[k][2 * nu1 + h], W.tape[k][2 * nu1 + h - 1]));
     // prolongation u += I ec: ecbar = I^T ubar = 8 R ubar
     const Level& c = P->lev[k + 1];
     UNCHK(W, W.ubar[k + 1], c.nv, "the coarse ubar");
@@ -3020,7 +3026,7 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
     LAUNCHCHK();
     defect_rev(W.ubar[k], (const double*)W.r[k], 0.125, pre_state(P, W, k));
     LAUNCHCHK();
-    for (int h = 2 * nu1 - 1; h >= 0; h--) TRY(half_rev(W.tape[k][h], h & 1));
+    for (int h = 2 * nu1 - 1; h >= 1; h -= 2) TRY(sweep_rev(W.tape[k][h], W.tape[k][h - 1]));
     return DMGS_OK;
 }
 }  // namespace

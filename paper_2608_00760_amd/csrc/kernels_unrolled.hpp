@@ -228,30 +228,6 @@ __global__ void k_un_defect(double* __restrict__ ubar, const double* __restrict_
 // neighbour j (the other faces join boundary vertices, whose cotangent terms
 // are 0).
 
-// reverse half-sweep: V = 0 at the vertex, V_j = ubar_j w_j if j is of colour C
-template <bool HARM>
-__device__ __forceinline__ void un_half_rev_edge(const DerEdge& e, const double* __restrict__ ubar_in,
-                                                 const double* __restrict__ up, const double* __restrict__ D,
-                                                 const double* __restrict__ w, int N, const Stencil<double>& s,
-                                                 int colour, double* __restrict__ Dbar) {
-    const int n = N + 1;
-    double dacc = 0.0;
-    if (e.jin) {
-        const int jx = (int)(e.j / ((int64_t)n * n)), jy = (int)((e.j / n) % n), jz = (int)(e.j % n);
-        const double Vj = ((jx + jy + jz) & 1) == colour ? ubar_in[e.j] * w[e.j] : 0.0;
-        const double Dv = D[e.i], Dj = D[e.j];
-        double dda;
-        if (HARM) {
-            const double t = Dv + Dj;
-            dda = Dj * Dj / (t * t) * s.two_inv_h2;
-        } else {
-            dda = s.half_inv_h2;
-        }
-        dacc += (0.0 - Vj) * (up[e.i] - up[e.j]) * dda;
-    }
-    Dbar[e.i] = Dbar[e.i] - dacc;
-}
-
 // defect reverse: rbar = 0 at the vertex, scale * rb_j at the interior neighbour
 template <bool HARM>
 __device__ __forceinline__ void un_defect_edge(const DerEdge& e, const double* __restrict__ rb, double scale,
@@ -271,117 +247,6 @@ __device__ __forceinline__ void un_defect_edge(const DerEdge& e, const double* _
         dacc += (0.0 - rj) * (u[e.i] - u[e.j]) * dda;
     }
     Dbar[e.i] = Dbar[e.i] - dacc;
-}
-
-// The whole reverse of one half-sweep of colour C in one pass (levels the
-// column tiles of kernels_deriv.hpp cover), with V_i = ubar_i w_i (w the
-// inverse diagonal 1 / d_i) formed where it is needed instead of stored:
-//   qbar_i += V_i, mubar_i -= V_i u'_i                      (C's interior)
-//   Dbar_i -= sum over faces of (V_i - V_j)(u'_i - u'_j) dc/dD_i   (every vertex)
-//   ubar_out_i = 0 (C's interior), ubar_in_i + sum_j c_ij V_j (other interior)
-// ubar is read from one buffer and written to another: a workgroup's ring
-// reads ubar of vertices that neighbouring workgroups update.  Boundary
-// entries of ubar_out are not written.  The march, tiles and ring are those
-// of k_coef_grads_col: own column's fields at x - 1, x, x + 1 in registers,
-// the plane's V, u' and D over the tile plus a ring of one in LDS.
-// Neighbours in the order +x, -x, +y, -y, +z, -z, as the two-kernel form.
-template <bool HARM>
-__global__ __launch_bounds__(kDerThreads) void k_un_half_rev(const double* __restrict__ ubar_in,
-                                                            double* __restrict__ ubar_out,
-                                                            const double* __restrict__ up,
-                                                            const double* __restrict__ D,
-                                                            const double* __restrict__ w, int N, Stencil<double> s,
-                                                            int colour, double* __restrict__ qbar,
-                                                            double* __restrict__ mubar, double* __restrict__ Dbar,
-                                                            int chunk, int cover) {
-    if (der_edge_block(N, chunk, [&](const DerEdge& e) {
-            un_half_rev_edge<HARM>(e, ubar_in, up, D, w, N, s, colour, Dbar);
-        }))
-        return;
-    __shared__ double sV[2][kDerCells], sU[2][kDerCells], sD[2][kDerCells];
-    DerTile t;
-    der_tile(N, chunk, cover, t);
-    const int n = t.n;
-    struct H {
-        double b, w, u, D;   // ubar_in, w, u', D
-    };
-    struct Vp : H {
-        double qb, mb, Db;   // own column only: qbar, mubar, Dbar
-    };
-    const DerSpan sp(t, n);
-    const auto rB = sp.rsrc(ubar_in), rW = sp.rsrc(w), rU = sp.rsrc(up), rD = sp.rsrc(D);
-    const auto rQ = sp.rsrc(qbar), rM = sp.rsrc(mubar), rDb = sp.rsrc(Dbar);
-    auto load_h = [&](int x, bool valid, int64_t p) -> H {
-        const int o = valid ? (int)(p * 8) : kOob, so = sp.off(x);
-        return H{buf_load_s(rB, o, so), buf_load_s(rW, o, so), buf_load_s(rU, o, so), buf_load_s(rD, o, so)};
-    };
-    auto load_v = [&](int x) -> Vp {
-        Vp v;
-        static_cast<H&>(v) = load_h(x, t.inb, t.p);
-        const int oo = (t.own && x < t.x1) ? (int)(t.p * 8) : kOob, so = sp.off(x);
-        v.qb = buf_load_s(rQ, oo, so);
-        v.mb = buf_load_s(rM, oo, so);
-        v.Db = buf_load_s(rDb, oo, so);
-        return v;
-    };
-    // V of a vertex from its own fields (0 off C's interior)
-    auto vof = [&](const H& h, int x, int y, int z) {
-        return (is_interior(N, x, y, z) && ((x + y + z) & 1) == colour) ? h.b * h.w : 0.0;
-    };
-    auto fc = [&](double Da, double Db) { return face<HARM>(Da, Db, s); };
-    auto dda = [&](double Da, double Db) {
-        if (HARM) {
-            const double u = Da + Db;
-            return Db * Db / (u * u) * s.two_inv_h2;
-        }
-        return s.half_inv_h2;
-    };
-    const bool halo = threadIdx.x < kDerHalo;
-    const bool yz = t.y > 0 && t.y < N && t.z > 0 && t.z < N;
-    auto step = [&](int x, Vp& Rm, Vp& Rc, Vp& Rp, Vp& Rl, H& Hc, H& Hl) {
-        const int b = x & 1;
-        const double Vc = vof(Rc, x, t.y, t.z);
-        sV[b][t.cell] = Vc; sU[b][t.cell] = Rc.u; sD[b][t.cell] = Rc.D;
-        if (halo) { sV[b][t.hcell] = vof(Hc, x, t.hy, t.hz); sU[b][t.hcell] = Hc.u; sD[b][t.hcell] = Hc.D; }
-        lds_barrier();
-        Rl = load_v(x + 3);
-        Hl = load_h(x + 2, t.hv, t.hp);
-        if (t.own && x < t.x1) {
-            const int64_t i = x * t.sx + t.p;
-            double dacc = 0.0, gath = 0.0;
-            auto nb = [&](double Dj, double Vj, double uj) {
-                dacc += (Vc - Vj) * (Rc.u - uj) * dda(Rc.D, Dj);
-                gath += fc(Rc.D, Dj) * Vj;
-            };
-            if (x < N) nb(Rp.D, vof(Rp, x + 1, t.y, t.z), Rp.u);
-            if (x > 0) nb(Rm.D, vof(Rm, x - 1, t.y, t.z), Rm.u);
-            auto cell = [&](int e) { nb(sD[b][e], sV[b][e], sU[b][e]); };
-            if (t.y < N) cell(t.cell + kDerRZ);
-            if (t.y > 0) cell(t.cell - kDerRZ);
-            if (t.z < N) cell(t.cell + 1);
-            if (t.z > 0) cell(t.cell - 1);
-            Dbar[i] = Rc.Db - dacc;
-            if (yz && x > 0 && x < N) {
-                if (((x + t.y + t.z) & 1) == colour) {
-                    qbar[i] = Rc.qb + Vc;
-                    mubar[i] = Rc.mb - Vc * Rc.u;
-                    ubar_out[i] = 0.0;
-                } else {
-                    ubar_out[i] = Rc.b + gath;
-                }
-            }
-        }
-    };
-    const int x0 = t.x0;
-    Vp R0 = load_v(x0 - 1), R1 = load_v(x0), R2 = load_v(x0 + 1), R3 = load_v(x0 + 2), R4;
-    H H0 = load_h(x0, t.hv, t.hp), H1 = load_h(x0 + 1, t.hv, t.hp), H2, H3, H4;
-    for (int x = x0; x < t.x1; x += kDerRing) {
-        step(x, R0, R1, R2, R4, H0, H2);
-        step(x + 1, R1, R2, R3, R0, H1, H3);
-        step(x + 2, R2, R3, R4, R1, H2, H4);
-        step(x + 3, R3, R4, R0, R2, H3, H0);
-        step(x + 4, R4, R0, R1, R3, H4, H1);
-    }
 }
 
 // A whole recorded sweep, out of place: u_mid = u_in after the half-sweep
@@ -405,6 +270,43 @@ constexpr int kSwRY = kDerTY + 4, kSwRZ = kDerTZ + 4, kSwCells = kSwRY * kSwRZ;
 constexpr int kSwHalo = kSwCells - kDerThreads;   // ring-2 cells (336)
 constexpr int kSwSlots = 5;
 
+// A thread's cells in arrays over the tile plus a ring of two: its own
+// column's, and its ring cell (tid < kSwHalo): rows y0 - 2, y0 - 1 and
+// y0 + 16, y0 + 17 whole, then columns z0 - 2, z0 - 1, z0 + 64, z0 + 65 of
+// the tile's rows.
+struct SwRing {
+    int cell2;            // own column in the ring-2 arrays
+    int hy, hz;           // the ring cell
+    bool halo, hv, r1;    // a ring thread; its cell inside the grid; at distance one
+    int hcell2, hcell1;   // the ring cell in the ring-2 and ring-1 arrays
+    int64_t hp;           // its in-plane offset
+};
+
+__device__ __forceinline__ void sw_ring(const DerTile& t, SwRing& r) {
+    const int tid = (int)threadIdx.x, n = t.n;
+    const int y0 = t.y - tid / kDerTZ, z0 = t.z - tid % kDerTZ;
+    r.cell2 = (tid / kDerTZ + 2) * kSwRZ + tid % kDerTZ + 2;
+    int ly, lz;
+    if (tid < 2 * kSwRZ) {
+        ly = tid / kSwRZ - 2; lz = tid % kSwRZ - 2;
+    } else if (tid < 4 * kSwRZ) {
+        ly = kDerTY + (tid - 2 * kSwRZ) / kSwRZ; lz = (tid - 2 * kSwRZ) % kSwRZ - 2;
+    } else {
+        const int u = tid - 4 * kSwRZ;   // < 4 * kDerTY for ring threads
+        ly = u / 4;
+        const int c = u % 4;
+        lz = c < 2 ? c - 2 : kDerTZ + c - 2;
+    }
+    r.halo = tid < kSwHalo;
+    r.hy = y0 + ly;
+    r.hz = z0 + lz;
+    r.hv = r.halo && r.hy >= 0 && r.hy < n && r.hz >= 0 && r.hz < n;
+    r.r1 = r.halo && ly >= -1 && ly <= kDerTY && lz >= -1 && lz <= kDerTZ;
+    r.hcell2 = (ly + 2) * kSwRZ + lz + 2;
+    r.hcell1 = (ly + 1) * kDerRZ + lz + 1;
+    r.hp = r.hv ? (int64_t)r.hy * n + r.hz : 0;
+}
+
 template <bool HARM>
 __global__ __launch_bounds__(kDerThreads) void k_un_gs_sweep_t(const double* __restrict__ u_in,
                                                               double* __restrict__ u_mid, double* __restrict__ u_out,
@@ -423,30 +325,12 @@ __global__ __launch_bounds__(kDerThreads) void k_un_gs_sweep_t(const double* __r
     DerTile t;
     der_tile(N, chunk, cover, t);
     const int n = t.n;
-    const int tid = (int)threadIdx.x;
     const int c2 = 1 - c1;
-    // this thread's cell in the ring-2 arrays, and its ring cell (tid <
-    // kSwHalo): rows y0 - 2, y0 - 1 and y0 + 16, y0 + 17 whole, then columns
-    // z0 - 2, z0 - 1, z0 + 64, z0 + 65 of the tile's rows
-    const int y0 = t.y - tid / kDerTZ, z0 = t.z - tid % kDerTZ;
-    const int cell2 = (tid / kDerTZ + 2) * kSwRZ + tid % kDerTZ + 2;
-    int ly, lz;
-    if (tid < 2 * kSwRZ) {
-        ly = tid / kSwRZ - 2; lz = tid % kSwRZ - 2;
-    } else if (tid < 4 * kSwRZ) {
-        ly = kDerTY + (tid - 2 * kSwRZ) / kSwRZ; lz = (tid - 2 * kSwRZ) % kSwRZ - 2;
-    } else {
-        const int u = tid - 4 * kSwRZ;   // < 4 * kDerTY for ring threads
-        ly = u / 4;
-        const int c = u % 4;
-        lz = c < 2 ? c - 2 : kDerTZ + c - 2;
-    }
-    const bool halo = tid < kSwHalo;
-    const int hy = y0 + ly, hz = z0 + lz;
-    const bool hv = halo && hy >= 0 && hy < n && hz >= 0 && hz < n;
-    const bool r1 = halo && ly >= -1 && ly <= kDerTY && lz >= -1 && lz <= kDerTZ;   // ring of one
-    const int hcell2 = (ly + 2) * kSwRZ + lz + 2, hcell1 = (ly + 1) * kDerRZ + lz + 1;
-    const int64_t hp = hv ? (int64_t)hy * n + hz : 0;
+    SwRing rg;
+    sw_ring(t, rg);
+    const int cell2 = rg.cell2, hy = rg.hy, hz = rg.hz, hcell2 = rg.hcell2, hcell1 = rg.hcell1;
+    const bool halo = rg.halo, hv = rg.hv, r1 = rg.r1;
+    const int64_t hp = rg.hp;
     struct UD {
         double u, D;
     };
@@ -526,6 +410,238 @@ __global__ __launch_bounds__(kDerThreads) void k_un_gs_sweep_t(const double* __r
         step(x, Q0, Q1, Q2, G1, G2);
         step(x + 1, Q1, Q2, Q0, G2, G0);
         step(x + 2, Q2, Q0, Q1, G0, G1);
+    }
+}
+
+// The planes y = N and z = N in the reverse of a whole sweep: Dbar of the
+// boundary vertex, by its one face to an interior neighbour j, first with
+// V^A_j (the later half-sweep's), then with V^B_j, which needs ubar' of j
+// after the first reverse: ubar_j + sum_k c_jk V^A_k over j's neighbours.
+template <bool HARM>
+__device__ __forceinline__ void un_sweep_rev_edge(const DerEdge& e, const double* __restrict__ ubar,
+                                                  const double* __restrict__ uA, const double* __restrict__ uB,
+                                                  const double* __restrict__ D, const double* __restrict__ w, int N,
+                                                  const Stencil<double>& s, int c1, double* __restrict__ Dbar) {
+    const int n = N + 1;
+    const int64_t nn = (int64_t)n * n;
+    double dA = 0.0, dB = 0.0;
+    if (e.jin) {
+        const int jx = (int)(e.j / nn), jy = (int)((e.j / n) % n), jz = (int)(e.j % n);
+        const bool jc1 = ((jx + jy + jz) & 1) == c1;
+        const double Dv = D[e.i], Dj = D[e.j];
+        double dd;
+        if (HARM) {
+            const double t = Dv + Dj;
+            dd = Dj * Dj / (t * t) * s.two_inv_h2;
+        } else {
+            dd = s.half_inv_h2;
+        }
+        const double VAj = jc1 ? ubar[e.j] * w[e.j] : 0.0;
+        dA += (0.0 - VAj) * (uA[e.i] - uA[e.j]) * dd;
+        double VBj = 0.0;
+        if (!jc1) {
+            const int d[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+            double g = 0.0;
+            for (int m = 0; m < 6; m++) {
+                const int kx = jx + d[m][0], ky = jy + d[m][1], kz = jz + d[m][2];
+                const int64_t k = ((int64_t)kx * n + ky) * n + kz;
+                const double VAk = (is_interior(N, kx, ky, kz) && ((kx + ky + kz) & 1) == c1) ? ubar[k] * w[k] : 0.0;
+                g += face<HARM>(Dj, D[k], s) * VAk;
+            }
+            VBj = (ubar[e.j] + g) * w[e.j];
+        }
+        dB += (0.0 - VBj) * (uB[e.i] - uB[e.j]) * dd;
+    }
+    Dbar[e.i] = (Dbar[e.i] - dA) - dB;
+}
+
+// The reverse of a whole recorded sweep in one pass (levels the column
+// tiles cover): the half-sweep of colour c1 (which ran last; its state uA)
+// reversed, then that of c2 = 1 - c1 (state uB), the two reverses in
+// sequence.  Per vertex i (V^A = ubar w on c1's interior, V^B = ubar' w
+// on c2's, ubar' = ubar + sum_j c_ij V^A_j on c2's interior, 0 elsewhere):
+//   c1's interior: qbar += V^A, mubar -= V^A uA, ubar_out = sum_j c_ij V^B_j
+//   c2's interior: qbar += V^B, mubar -= V^B uB, ubar_out = 0
+//   every vertex:  Dbar -= the face terms of V^A with uA, then of V^B with uB.
+// 96 instead of 2 x 88 bytes per vertex.  The column tiles march along x in
+// two stages: at step x, stage 1 forms V^B on plane x over the tile plus a
+// ring of one, from X (V^A on c1's interior, ubar on c2's, 0 elsewhere) and
+// D in LDS over a ring of two for four planes (x - 2 .. x + 1; plane x + 1
+// is published at step x); stage 2 forms the outputs on plane x - 1 from V^B,
+// uA and uB of that plane in LDS over a ring of one and the own column's
+// values of planes x - 2 and x in registers.  One barrier per step orders
+// all LDS traffic.  Neighbours in the order +x, -x, +y, -y, +z, -z.
+template <bool HARM>
+__global__ __launch_bounds__(kDerThreads) void k_un_sweep_rev_t(const double* __restrict__ ubar_in,
+                                                               double* __restrict__ ubar_out,
+                                                               const double* __restrict__ uA,
+                                                               const double* __restrict__ uB,
+                                                               const double* __restrict__ D,
+                                                               const double* __restrict__ w, int N, Stencil<double> s,
+                                                               int c1, double* __restrict__ qbar,
+                                                               double* __restrict__ mubar, double* __restrict__ Dbar,
+                                                               int chunk, int cover) {
+    if (der_edge_block(N, chunk, [&](const DerEdge& e) {
+            un_sweep_rev_edge<HARM>(e, ubar_in, uA, uB, D, w, N, s, c1, Dbar);
+        }))
+        return;
+    __shared__ double sX[4][kSwCells], sD[4][kSwCells], sVB[2][kDerCells], sUA[2][kDerCells], sUB[2][kDerCells];
+    DerTile t;
+    der_tile(N, chunk, cover, t);
+    const int n = t.n;
+    const int c2 = 1 - c1;
+    SwRing rg;
+    sw_ring(t, rg);
+    struct L {
+        double b, w, D;   // ubar, w, D
+    };
+    struct U {
+        double a, b;      // uA, uB
+    };
+    struct A {
+        double q, m, d;   // qbar, mubar, Dbar (own column)
+    };
+    const DerSpan sp(t, n, 2);
+    const auto rB = sp.rsrc(ubar_in), rW = sp.rsrc(w), rD = sp.rsrc(D), rA = sp.rsrc(uA), rBb = sp.rsrc(uB);
+    const auto rQ = sp.rsrc(qbar), rM = sp.rsrc(mubar), rDb = sp.rsrc(Dbar);
+    const int xs = t.x0 - 1, xlast = t.x1;   // stage 1 runs on planes [xs, xlast]
+    auto load_l = [&](int x, bool valid, int64_t p) -> L {
+        const int o = valid ? (int)(p * 8) : kOob, so = sp.off(x);
+        return L{buf_load_s(rB, o, so), buf_load_s(rW, o, so), buf_load_s(rD, o, so)};
+    };
+    auto load_u = [&](int x, bool valid, int64_t p) -> U {
+        const int o = valid ? (int)(p * 8) : kOob, so = sp.off(x);
+        return U{buf_load_s(rA, o, so), buf_load_s(rBb, o, so)};
+    };
+    auto load_a = [&](int x) -> A {
+        const int o = (t.own && x >= t.x0 && x < t.x1) ? (int)(t.p * 8) : kOob, so = sp.off(x);
+        return A{buf_load_s(rQ, o, so), buf_load_s(rM, o, so), buf_load_s(rDb, o, so)};
+    };
+    const bool hu = rg.r1 && rg.hv;
+    auto slot = [](int x) { return (x + 8) & 3; };   // x >= -3
+    auto interior_c = [&](int x, int y, int z, int c) { return is_interior(N, x, y, z) && ((x + y + z) & 1) == c; };
+    // X of a vertex from its own fields
+    auto xof = [&](const L& f, int x, int y, int z) {
+        return interior_c(x, y, z, c1) ? f.b * f.w : (interior_c(x, y, z, c2) ? f.b : 0.0);
+    };
+    auto vaof = [&](const L& f, int x, int y, int z) { return interior_c(x, y, z, c1) ? f.b * f.w : 0.0; };
+    auto fc = [&](double Da, double Db) { return face<HARM>(Da, Db, s); };
+    auto dda = [&](double Da, double Db) {
+        if (HARM) {
+            const double u = Da + Db;
+            return Db * Db / (u * u) * s.two_inv_h2;
+        }
+        return s.half_inv_h2;
+    };
+    // stage 1 at one vertex (cell c of the ring-2 arrays) of plane x: V^B
+    auto stage1 = [&](int x, int y, int z, int c, double wc) {
+        if (!interior_c(x, y, z, c2)) return 0.0;
+        const int k = slot(x), km = slot(x - 1), kp = slot(x + 1);
+        const double Dc = sD[k][c];
+        double g = 0.0;
+        g += fc(Dc, sD[kp][c]) * sX[kp][c];
+        g += fc(Dc, sD[km][c]) * sX[km][c];
+#pragma unroll 1
+        for (int j = 0; j < 4; j++) {
+            const int e = c + ((j & 1) ? -1 : 1) * (j < 2 ? kSwRZ : 1);
+            g += fc(Dc, sD[k][e]) * sX[k][e];
+        }
+        return (sX[k][c] + g) * wc;
+    };
+    const bool yz = t.y > 0 && t.y < N && t.z > 0 && t.z < N;
+    double m2 = 0.0, m1 = 0.0;   // own V^B at planes x - 2, x - 1
+    // step x: l2 .. l1 hold planes x - 2 .. x + 1 (l2 receives x + 2), h* the
+    // same for the ring cell; u3 .. u0 hold uA, uB of x - 3 (receives x + 1)
+    // .. x; a1 holds the accumulators of x - 1, a0 receives x; g1 holds the
+    // ring cell's uA, uB of x - 1, g0 receives x
+    auto step = [&](int x, L& l2, L& lm, L& lc, L& lp, L& h2, L& hm, L& hc, L& hp, U& u3, U& u2, U& um, U& uc,
+                    A& a1, A& a0, U& g1, U& g0) {
+        const int kp = slot(x + 1);
+        sX[kp][rg.cell2] = xof(lp, x + 1, t.y, t.z);
+        sD[kp][rg.cell2] = lp.D;
+        lp.b = vaof(lp, x + 1, t.y, t.z);   // from here on the field holds V^A
+        if (rg.halo) {
+            sX[kp][rg.hcell2] = xof(hp, x + 1, rg.hy, rg.hz);
+            sD[kp][rg.hcell2] = hp.D;
+        }
+        const int bm = (x - 1) & 1;
+        sUA[bm][t.cell] = um.a; sUB[bm][t.cell] = um.b;
+        if (rg.r1) { sUA[bm][rg.hcell1] = g1.a; sUB[bm][rg.hcell1] = g1.b; }
+        lds_barrier();
+        // plane x - 2's own values (its registers take plane x + 2 now)
+        const double D2 = l2.D, VA2 = l2.b;
+        l2 = load_l(x + 2, t.inb, t.p);
+        h2 = load_l(x + 2, rg.hv, rg.hp);
+        u3 = load_u(x + 1, t.inb, t.p);
+        g0 = load_u(x, hu, rg.hp);
+        a0 = load_a(x);
+        const double m0 = stage1(x, t.y, t.z, rg.cell2, lc.w);
+        sVB[x & 1][t.cell] = m0;
+        if (rg.r1) sVB[x & 1][rg.hcell1] = stage1(x, rg.hy, rg.hz, rg.hcell2, hc.w);
+        // stage 2 on plane q = x - 1
+        const int q = x - 1;
+        if (t.own && q >= t.x0 && q < t.x1) {
+            const bool intq = yz && q > 0 && q < N;
+            const bool own2 = ((q + t.y + t.z) & 1) == c2;
+            const double Dc = lm.D, VAc = lm.b, VBc = m1;
+            const double uAc = um.a, uBc = um.b;
+            double dA = 0.0, dB = 0.0, gB = 0.0;
+            auto nb = [&](double Dj, double VAj, double VBj, double uAj, double uBj) {
+                const double dd = dda(Dc, Dj);
+                dA += (VAc - VAj) * (uAc - uAj) * dd;
+                dB += (VBc - VBj) * (uBc - uBj) * dd;
+                gB += fc(Dc, Dj) * VBj;
+            };
+            if (q < N) nb(lc.D, lc.b, m0, uc.a, uc.b);
+            if (q > 0) nb(D2, VA2, m2, u2.a, u2.b);
+            const int kq = slot(q);
+            // in-plane neighbours one at a time (few LDS values in flight)
+#pragma unroll 1
+            for (int j = 0; j < 4; j++) {
+                const int sgn = (j & 1) ? -1 : 1;
+                const bool ok = j < 2 ? (j == 0 ? t.y < N : t.y > 0) : (j == 2 ? t.z < N : t.z > 0);
+                const int e = t.cell + sgn * (j < 2 ? kDerRZ : 1), e2 = rg.cell2 + sgn * (j < 2 ? kSwRZ : 1);
+                if (ok) nb(sD[kq][e2], own2 ? sX[kq][e2] : 0.0, sVB[bm][e], sUA[bm][e], sUB[bm][e]);
+            }
+            const int64_t i = q * t.sx + t.p;
+            Dbar[i] = (a1.d - dA) - dB;
+            if (intq) {
+                if (!own2) {
+                    qbar[i] = a1.q + VAc;
+                    mubar[i] = a1.m - VAc * uAc;
+                    ubar_out[i] = 0.0 + gB;
+                } else {
+                    qbar[i] = a1.q + VBc;
+                    mubar[i] = a1.m - VBc * uBc;
+                    ubar_out[i] = 0.0;
+                }
+            }
+        }
+        m2 = m1;
+        m1 = m0;
+    };
+    L L0{0.0, 0.0, 0.0}, L1 = load_l(xs - 1, t.inb, t.p), L2 = load_l(xs, t.inb, t.p), L3 = load_l(xs + 1, t.inb, t.p);
+    L H0{0.0, 0.0, 0.0}, H1 = load_l(xs - 1, rg.hv, rg.hp), H2 = load_l(xs, rg.hv, rg.hp),
+        H3 = load_l(xs + 1, rg.hv, rg.hp);
+    {
+        const int k0 = slot(xs - 1), k1 = slot(xs);
+        sX[k0][rg.cell2] = xof(L1, xs - 1, t.y, t.z); sD[k0][rg.cell2] = L1.D;
+        sX[k1][rg.cell2] = xof(L2, xs, t.y, t.z); sD[k1][rg.cell2] = L2.D;
+        L1.b = vaof(L1, xs - 1, t.y, t.z);
+        L2.b = vaof(L2, xs, t.y, t.z);
+        if (rg.halo) {
+            sX[k0][rg.hcell2] = xof(H1, xs - 1, rg.hy, rg.hz); sD[k0][rg.hcell2] = H1.D;
+            sX[k1][rg.hcell2] = xof(H2, xs, rg.hy, rg.hz); sD[k1][rg.hcell2] = H2.D;
+        }
+    }
+    U U0{0.0, 0.0}, U1{0.0, 0.0}, U2{0.0, 0.0}, U3 = load_u(xs, t.inb, t.p);
+    A A0{0.0, 0.0, 0.0}, A1{0.0, 0.0, 0.0};
+    U G0{0.0, 0.0}, G1{0.0, 0.0};
+    for (int x = xs; x <= xlast; x += 4) {
+        step(x, L0, L1, L2, L3, H0, H1, H2, H3, U0, U1, U2, U3, A1, A0, G1, G0);
+        step(x + 1, L1, L2, L3, L0, H1, H2, H3, H0, U1, U2, U3, U0, A0, A1, G0, G1);
+        step(x + 2, L2, L3, L0, L1, H2, H3, H0, H1, U2, U3, U0, U1, A1, A0, G1, G0);
+        step(x + 3, L3, L0, L1, L2, H3, H0, H1, H2, U3, U0, U1, U2, A0, A1, G0, G1);
     }
 }
 
