@@ -2909,18 +2909,17 @@ int vcycle_taped(dmgs_plan P, UnWork& W, int k, double* u, const double* q, cons
         src = W.tape[k][2 * (nu1 + nu2)];
     }
     const Level& c = P->lev[k + 1];
-    UNCHK(W, W.r[k], l.nv, "the defect");
     UNCHK(W, W.qc[k + 1], c.nv, "the coarse right-hand side");
     UNCHK(W, W.uc[k + 1], c.nv, "the coarse iterate");
-    TRY(apply_or_defect<double>(P, k, src, q, W.r[k], 0, st));
-    hipLaunchKernelGGL(k_restrict<double>, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)W.r[k], W.qc[k + 1], l.N);
-    LAUNCHCHK();
+    // qc = R (q - A u) in one streaming pass, the defect at every fine vertex
+    // (coarse boundary entries are not written; no step reads them)
+    TRY(defect_restrict<double>(P, k, src, q, W.qc[k + 1], st));
     TRY(fill<double>(W.uc[k + 1], c.nv, 0.0, st));
     const double* ec = nullptr;
     TRY(vcycle_taped(P, W, k + 1, W.uc[k + 1], W.qc[k + 1], &ec, st));
-    // the post-smoothing input: the pre-smoothed state plus the correction
-    if (src != u) HIPCHK(hipMemcpyAsync(u, src, bytes, hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_prolong_add<double>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, ec, u, l.N);
+    // the post-smoothing input: the pre-smoothed state plus the correction,
+    // out of place
+    hipLaunchKernelGGL(k_un_prolong_to, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, ec, src, u, l.N);
     LAUNCHCHK();
     src = u;
     for (int i = 0; i < nu2; i++, h += 2) {

@@ -741,6 +741,30 @@ __global__ __launch_bounds__(kDerThreads) void k_un_defect_t(double* __restrict_
     }
 }
 
+// u = u_pre + I ec (the trilinear prolongation of the coarse correction
+// added on interior vertices), u = u_pre on boundary ones: the recorded
+// cycle's post-smoothing input, formed out of place from the pre-smoothed
+// state.
+__global__ void k_un_prolong_to(const double* __restrict__ ec, const double* __restrict__ u_pre,
+                                double* __restrict__ u, int Nf) {
+    const int nf = Nf + 1, nc = Nf / 2 + 1;
+    const int64_t nv = (int64_t)nf * nf * nf;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        const int z = (int)(v % nf), y = (int)((v / nf) % nf), x = (int)(v / ((int64_t)nf * nf));
+        double r = u_pre[v];
+        if (is_interior(Nf, x, y, z)) {
+            const int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
+            const int x1 = x0 + (x & 1), y1 = y0 + (y & 1), z1 = z0 + (z & 1);
+            // the eight corners repeat one where a coordinate is even: 8 x the trilinear value
+            const double s = ec[vidx(nc, x0, y0, z0)] + ec[vidx(nc, x0, y0, z1)] + ec[vidx(nc, x0, y1, z0)] +
+                             ec[vidx(nc, x0, y1, z1)] + ec[vidx(nc, x1, y0, z0)] + ec[vidx(nc, x1, y0, z1)] +
+                             ec[vidx(nc, x1, y1, z0)] + ec[vidx(nc, x1, y1, z1)];
+            r += s * 0.125;
+        }
+        u[v] = r;
+    }
+}
+
 // a *= f
 __global__ void k_un_scale(double* __restrict__ a, int64_t n, double f) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) a[i] *= f;
