@@ -2124,6 +2124,10 @@ namespace {
 // ones tile every vertex.
 constexpr int kDerSplitMin = 128;
 
+// Levels of the unrolled adjoint from this size on run the column-tile
+// kernels (whole sweeps per pass), smaller ones the x-march kernels.
+constexpr int kUnTileMin = 96;
+
 dim3 der_grid(dmgs_plan P, int N, int* chunk, int* cover) {
     const int n = N + 1;
     *cover = N >= kDerSplitMin ? N : n;
@@ -2864,7 +2868,7 @@ int vcycle_taped(dmgs_plan P, UnWork& W, int k, double* u, const double* q, cons
     }
     int chunk = 1, cover = 0;
     const dim3 g = der_grid(P, l.N, &chunk, &cover);
-    const bool tiled = l.N >= kDerSplitMin;   // smaller levels: the x-march forms
+    const bool tiled = l.N >= kUnTileMin;   // smaller levels: the x-march forms
     int uchunk = 1;
     const dim3 ug = un_col_grid(l.N, &uchunk);
     // one recorded half-sweep on an x-march level
@@ -2939,7 +2943,7 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
     const int nu1 = P->opt.nu_pre, nu2 = P->opt.nu_post;
     int chunk = 1, cover = 0;
     const dim3 g = der_grid(P, l.N, &chunk, &cover);
-    const bool tiled = l.N >= kDerSplitMin;   // smaller levels: the x-march forms
+    const bool tiled = l.N >= kUnTileMin;   // smaller levels: the x-march forms
     int uchunk = 1;
     const dim3 ug = un_col_grid(l.N, &uchunk);
     const double *D = l.D64, *mu = l.mu64;
