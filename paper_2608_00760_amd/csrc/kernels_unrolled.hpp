@@ -550,12 +550,13 @@ __global__ __launch_bounds__(kDerThreads) void k_un_sweep_rev_t(const double* __
     };
     const bool yz = t.y > 0 && t.y < N && t.z > 0 && t.z < N;
     double m2 = 0.0, m1 = 0.0;   // own V^B at planes x - 2, x - 1
-    // step x: l2 .. l1 hold planes x - 2 .. x + 1 (l2 receives x + 2), h* the
-    // same for the ring cell; u3 .. u0 hold uA, uB of x - 3 (receives x + 1)
-    // .. x; a1 holds the accumulators of x - 1, a0 receives x; g1 holds the
-    // ring cell's uA, uB of x - 1, g0 receives x
+    // step x: l2 .. lp hold planes x - 2 .. x + 1 (l2 receives x + 2), h* the
+    // same for the ring cell; u3 .. uc hold uA, uB of x - 3 (receives x + 1)
+    // .. x; g1 holds the ring cell's uA, uB of x - 1, g0 receives x.  The
+    // accumulators of plane x - 1 are loaded in the same step (stage 1 runs
+    // while they arrive; a register ring for them would spill).
     auto step = [&](int x, L& l2, L& lm, L& lc, L& lp, L& h2, L& hm, L& hc, L& hp, U& u3, U& u2, U& um, U& uc,
-                    A& a1, A& a0, U& g1, U& g0) {
+                    U& g1, U& g0) {
         const int kp = slot(x + 1);
         sX[kp][rg.cell2] = xof(lp, x + 1, t.y, t.z);
         sD[kp][rg.cell2] = lp.D;
@@ -574,7 +575,7 @@ __global__ __launch_bounds__(kDerThreads) void k_un_sweep_rev_t(const double* __
         h2 = load_l(x + 2, rg.hv, rg.hp);
         u3 = load_u(x + 1, t.inb, t.p);
         g0 = load_u(x, hu, rg.hp);
-        a0 = load_a(x);
+        const A a1 = load_a(x - 1);
         const double m0 = stage1(x, t.y, t.z, rg.cell2, lc.w);
         sVB[x & 1][t.cell] = m0;
         if (rg.r1) sVB[x & 1][rg.hcell1] = stage1(x, rg.hy, rg.hz, rg.hcell2, hc.w);
@@ -635,13 +636,12 @@ __global__ __launch_bounds__(kDerThreads) void k_un_sweep_rev_t(const double* __
         }
     }
     U U0{0.0, 0.0}, U1{0.0, 0.0}, U2{0.0, 0.0}, U3 = load_u(xs, t.inb, t.p);
-    A A0{0.0, 0.0, 0.0}, A1{0.0, 0.0, 0.0};
     U G0{0.0, 0.0}, G1{0.0, 0.0};
     for (int x = xs; x <= xlast; x += 4) {
-        step(x, L0, L1, L2, L3, H0, H1, H2, H3, U0, U1, U2, U3, A1, A0, G1, G0);
-        step(x + 1, L1, L2, L3, L0, H1, H2, H3, H0, U1, U2, U3, U0, A0, A1, G0, G1);
-        step(x + 2, L2, L3, L0, L1, H2, H3, H0, H1, U2, U3, U0, U1, A1, A0, G1, G0);
-        step(x + 3, L3, L0, L1, L2, H3, H0, H1, H2, U3, U0, U1, U2, A0, A1, G0, G1);
+        step(x, L0, L1, L2, L3, H0, H1, H2, H3, U0, U1, U2, U3, G1, G0);
+        step(x + 1, L1, L2, L3, L0, H1, H2, H3, H0, U1, U2, U3, U0, G0, G1);
+        step(x + 2, L2, L3, L0, L1, H2, H3, H0, H1, U2, U3, U0, U1, G1, G0);
+        step(x + 3, L3, L0, L1, L2, H3, H0, H1, H2, U3, U0, U1, U2, G0, G1);
     }
 }
 
