@@ -323,16 +323,19 @@ def paper_sweep(args):
             # log D and log mua, through every step) for float64 3D plans
             unrolled = None
             if nd == 3 and prec == "fp64" and N <= args.sweep_unrolled_max:
+                # the first call allocates the plan's work buffers for it (the
+                # recorded states of every cycle, or checkpoints): measured
+                # as the device memory it takes
+                free0 = torch.cuda.mem_get_info()[0]
                 P.vjp_unrolled(q, w)
                 torch.cuda.synchronize()
+                work = free0 - torch.cuda.mem_get_info()[0]
                 tu = []
                 for _ in range(3):
                     t0u = time.perf_counter()
                     P.vjp_unrolled(q, w)
                     tu.append((time.perf_counter() - t0u) * 1e3)
                 tu.sort()
-                nvs = sum(((N >> k) + 1) ** 3 for k in range(P.levels))
-                work = 8 * (15 * (N + 1) ** 3 + (2 * 4 + 1 + 8) * nvs)
                 unrolled = {"ms_median": tu[1], "work_GB": work / 1e9,
                             "vs_vjp": tu[1] / res["vjp_ms_median"]}
             cpu = None

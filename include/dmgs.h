@@ -312,12 +312,17 @@ int dmgs_likelihood_grad(dmgs_plan plan, const double *q, const double *d, const
  * to dmgs_vjp's in fixed mode up to rounding), logD_bar and logmua_bar (the
  * derivative of the n-cycle map itself, which differs from dmgs_vjp's
  * adjoint-state gradients of the exact discrete solution by the iteration
- * error; logD_bar / logmua_bar may be NULL).  The finest iterate is kept at
- * the start of every cycle and each cycle is recomputed, recording its
- * states, before its reverse pass.  The first call on a plan allocates n +
- * about 1.14 (2 (nu_pre + nu_post) + 8) finest-level fields of device
- * memory for this; the plan keeps them for later calls and counts them in
- * its bytes, and dmgs_plan_destroy frees them.  The call waits for its work
+ * error; logD_bar / logmua_bar may be NULL).  The forward pass records the
+ * states of every cycle (after each half-sweep, on every level) when they
+ * take at most a quarter of the device's memory, about 1.14 n (2 (nu_pre +
+ * nu_post) + 1) finest-level fields (21 GB at N = 256, n = 15, V(2,2));
+ * otherwise it keeps the finest iterate at the start of every cycle (n
+ * fields) and records each cycle again before its reverse pass (the
+ * environment variable DMGS_UNROLLED_STORE = 1 / 0 forces either; both
+ * give the same results up to rounding).  The first call on a plan
+ * allocates these buffers and about 1.14 x 8 finest-level fields of work
+ * buffers; the plan keeps them for later calls and dmgs_plan_destroy frees
+ * them.  The call waits for its work
  * before it returns.  Three-dimensional
  * DMGS_FP64, DMGS_RBGS plans with fixed_cycles > 0 only, else
  * DMGS_ERR_INVALID; DMGS_ERR_OOM if the work buffers do not fit. */

@@ -2791,6 +2791,8 @@ struct UnWork {
     std::vector<void*> bufs;
     std::vector<size_t> sizes;
     size_t bytes = 0;
+    bool store_all = false;                       // every cycle's states kept (no checkpoints, no recompute)
+    std::vector<double*> sets;                    // the tape pointers of each kept cycle: [c][k][h]
     double* ckpt = nullptr;                       // the finest iterate at the start of every cycle
     double* u0 = nullptr;                         // the finest working iterate
     double* tape[kMaxLevels][33] = {};            // per level: the state after each half-sweep (pre, then post)
@@ -2818,10 +2820,31 @@ struct UnWork {
         }
         return false;
     }
+    // point the tape slots at cycle c's states
+    void use_cycle(int c) {
+        for (int k = 0; k < kMaxLevels; k++)
+            for (int h = 0; h < 33; h++) tape[k][h] = sets[((size_t)c * kMaxLevels + k) * 33 + h];
+    }
     ~UnWork() {
         for (void* p : bufs) (void)hipFree(p);
     }
 };
+
+// Whether the unrolled adjoint keeps the recorded states of every cycle
+// (bytes: their size).  DMGS_UNROLLED_STORE = 0 checkpoints the finest
+// iterate per cycle and records each cycle again in the reverse pass, 1
+// keeps every cycle's states; unset, they are kept when they take at most a
+// quarter of the device's memory.
+bool unrolled_store_all(size_t bytes, bool* forced) {
+    *forced = false;
+    if (const char* e = std::getenv("DMGS_UNROLLED_STORE")) {
+        *forced = true;
+        return std::atoi(e) != 0;
+    }
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
+    return bytes <= tot / 4;
+}
 
 unsigned un_grid(int64_t nv) { return (unsigned)((nv + kBlock - 1) / kBlock); }
 
@@ -3052,13 +3075,18 @@ int dmgs_vjp_unrolled(dmgs_plan P, const double* q, const double* rhobar, double
         // first call: allocate the work buffers; the plan keeps them
         UnWork* w = new (std::nothrow) UnWork();
         if (!w) { set_error("host allocation failed"); return DMGS_ERR_OOM; }
-        auto build = [&](UnWork& W) -> int {
-            TRY(W.alloc(&W.ckpt, (int64_t)n * l0.nv));
+        // the tapes of one cycle: one buffer, slots starting on 512-byte boundaries
+        auto up = [](int64_t v) { return (v + 63) / 64 * 64; };
+        int64_t per = 0;
+        for (int k = 0; k < L; k++) per += (int64_t)(k == L - 1 ? 1 : nstate) * up(P->lev[k].nv);
+        bool forced = false;
+        const bool all = n > 1 && unrolled_store_all((size_t)n * per * sizeof(double), &forced);
+        auto build = [&](UnWork& W, bool keep_all) -> int {
+            W.store_all = keep_all;
+            if (!keep_all) TRY(W.alloc(&W.ckpt, (int64_t)n * l0.nv));
             TRY(W.alloc(&W.u0, l0.nv));
             for (int k = 0; k < L; k++) {
                 const int64_t nv = P->lev[k].nv;
-                const int ns = k == L - 1 ? 1 : nstate;
-                for (int h = 0; h < ns; h++) TRY(W.alloc(&W.tape[k][h], nv));
                 if (k < L - 1) TRY(W.alloc(&W.r[k], nv));
                 if (k > 0) {
                     TRY(W.alloc(&W.uc[k], nv));
@@ -3070,9 +3098,29 @@ int dmgs_vjp_unrolled(dmgs_plan P, const double* q, const double* rhobar, double
                 TRY(W.alloc(&W.mbar[k], nv));
                 TRY(W.alloc(&W.V[k], nv));
             }
+            const int nsets = keep_all ? n : 1;
+            W.sets.assign((size_t)nsets * kMaxLevels * 33, nullptr);
+            for (int c = 0; c < nsets; c++) {
+                double* b = nullptr;
+                TRY(W.alloc(&b, per));
+                int64_t off = 0;
+                for (int k = 0; k < L; k++) {
+                    const int ns = k == L - 1 ? 1 : nstate;
+                    for (int h = 0; h < ns; h++, off += up(P->lev[k].nv))
+                        W.sets[((size_t)c * kMaxLevels + k) * 33 + h] = b + off;
+                }
+            }
+            W.use_cycle(0);
             return DMGS_OK;
         };
-        const int sb = build(*w);
+        int sb = build(*w, all);
+        if (sb == DMGS_ERR_OOM && all && !forced) {
+            // keeping every cycle did not fit after all: checkpoint instead
+            delete w;
+            w = new (std::nothrow) UnWork();
+            if (!w) { set_error("host allocation failed"); return DMGS_ERR_OOM; }
+            sb = build(*w, false);
+        }
         if (sb != DMGS_OK) {
             delete w;
             return sb;
@@ -3084,7 +3132,7 @@ int dmgs_vjp_unrolled(dmgs_plan P, const double* q, const double* rhobar, double
     UnWork& W = *static_cast<UnWork*>(P->unwork);
     {
         const int k = 0;
-        UNCHK(W, W.ckpt, (int64_t)n * l0.nv, "the checkpoints");
+        if (!W.store_all) UNCHK(W, W.ckpt, (int64_t)n * l0.nv, "the checkpoints");
         UNCHK(W, W.u0, l0.nv, "the working iterate");
     }
     for (int k = 0; k < L; k++) {
@@ -3096,10 +3144,21 @@ int dmgs_vjp_unrolled(dmgs_plan P, const double* q, const double* rhobar, double
         TRY(fill<double>(W.V[k], nv, 0.0, st));   // the partner of ubar in the reverse half-sweeps
     }
     const size_t b0 = l0.nv * sizeof(double);
-    // forward: n cycles of the solver's own (fused) V-cycle, keeping the
-    // iterate at the start of each; the reverse pass recomputes each cycle
-    // with the per-operator kernels, whose states agree to rounding
-    {
+    if (W.store_all) {
+        // forward: n recorded cycles, each into its own tapes
+        hipLaunchKernelGGL(k_init_iterate<double>, dim3(grid_for(l0.nv)), dim3(kBlock), 0, st, W.u0, l0.N, o.bc_value);
+        LAUNCHCHK();
+        for (int c = 0; c < n; c++) {
+            W.use_cycle(c);
+            const double* fin = nullptr;
+            TRY(vcycle_taped(P, W, 0, W.u0, q, &fin, st));
+            double* next = c + 1 < n ? W.u0 : rho;   // without post-smoothing fin is W.u0 itself
+            if (fin != next) HIPCHK(hipMemcpyAsync(next, fin, b0, hipMemcpyDeviceToDevice, st));
+        }
+    } else {
+        // forward: n cycles of the solver's own (fused) V-cycle, keeping the
+        // iterate at the start of each; the reverse pass records each cycle
+        // again with its own kernels, whose states agree to rounding
         double* cur = rho;
         double* oth = l0.t64;
         P->bc_zero = o.bc_value == 0.0;
@@ -3116,9 +3175,13 @@ int dmgs_vjp_unrolled(dmgs_plan P, const double* q, const double* rhobar, double
     HIPCHK(hipMemcpyAsync(W.ubar[0], rhobar, b0, hipMemcpyDeviceToDevice, st));
     TRY(set_boundary<double>(W.ubar[0], l0.N, 0.0, st));
     for (int c = n - 1; c >= 0; c--) {
-        HIPCHK(hipMemcpyAsync(W.u0, W.ckpt + (int64_t)c * l0.nv, b0, hipMemcpyDeviceToDevice, st));
-        const double* fin = nullptr;
-        TRY(vcycle_taped(P, W, 0, W.u0, q, &fin, st));
+        if (W.store_all) {
+            W.use_cycle(c);
+        } else {
+            HIPCHK(hipMemcpyAsync(W.u0, W.ckpt + (int64_t)c * l0.nv, b0, hipMemcpyDeviceToDevice, st));
+            const double* fin = nullptr;
+            TRY(vcycle_taped(P, W, 0, W.u0, q, &fin, st));
+        }
         TRY(vcycle_rev(P, W, 0, st));
     }
     // coarse coefficient cotangents to the finest level

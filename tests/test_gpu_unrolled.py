@@ -9,6 +9,8 @@
 * qbar equals dmgs_vjp's fixed-cycle pull-back.
 * At 64^3, central differences of the library's own fixed-cycle forward map
   along random log D and log mua directions match <grad, direction>.
+* Both policies for the recorded states (every cycle kept, or checkpoints
+  and a second recording) meet the oracle.
 * Plans the entry point does not take are rejected.
 """
 import numpy as np
@@ -52,6 +54,30 @@ def test_matches_oracle(N, n, nu, harmonic, g):
     # the q-part is the fixed-cycle pull-back
     (qb2, _, _), _ = P.vjp(rho, dev(w), coef_grads=False)
     assert rel_max(host(qb), host(qb2)) <= 1e-12
+
+
+@pytest.mark.parametrize("store", ["0", "1"])
+@pytest.mark.parametrize("N,n,nu,harmonic,g", [(48, 3, (2, 1), True, 0.2), (96, 2, (1, 2), False, 0.0)])
+def test_both_state_policies(store, N, n, nu, harmonic, g, monkeypatch):
+    """The forward pass either keeps every cycle's recorded states or keeps
+    the finest iterate per cycle and records each cycle again before its
+    reverse pass (DMGS_UNROLLED_STORE = 1 / 0, read when the plan first
+    allocates its buffers): both meet the oracle to 1e-12 (96^3: the finest
+    level on the column tiles)."""
+    from oracle import unrolled
+    monkeypatch.setenv("DMGS_UNROLLED_STORE", store)
+    say("unrolled store=%s N=%d n=%d nu=%s harmonic=%s g=%g" % (store, N, n, nu, harmonic, g))
+    logD, logmu, q, w = case(N, 300 + N)
+    fm = "harmonic" if harmonic else "arith"
+    P = plan_for(N, logD, logmu, fixed_cycles=n, nu_pre=nu[0], nu_post=nu[1], face_mean=fm, bc_value=g)
+    (rho, (qb, gD, gmu)), _ = P.vjp_unrolled(dev(q), dev(w))
+    U = unrolled.Unrolled(np.exp(logD), np.exp(logmu), g=g, harmonic=harmonic)
+    rr, (rqb, rgD, rgmu) = U.vjp(q, w, n, nu[0], nu[1])
+    errs = {name: rel_max(host(a), b) for name, a, b in (("rho", rho, rr), ("qbar", qb, rqb), ("logD", gD, rgD),
+                                                         ("logmua", gmu, rgmu))}
+    say("errors", {k: "%.1e" % v for k, v in errs.items()})
+    assert max(errs.values()) <= 1e-12, errs
+    P.close()
 
 
 def test_central_differences_at_64():
