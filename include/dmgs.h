@@ -188,6 +188,9 @@ size_t dmgs_forward_vjp_workspace_bytes(const dmgs_options *opt);
  *                               counts, red-black smoothing, N above the block
  *                               passes' range); 0: dense rows.  The footprint
  *                               (dmgs_workspace_bytes) counts the padding.
+ *   DMGS_UNROLLED_STORE         dmgs_vjp_unrolled keeps every cycle's recorded states (1)
+ *                               or checkpoints and records each cycle again (0); unset:
+ *                               keeps them when they take at most a quarter of device memory
  * DMGS_TRACE (0) is not a tuning knob: 1 records residual histories and
  * kernel times (dmgs_trace_read). */
 int dmgs_plan_create(const dmgs_options *opt, dmgs_plan *out);
