@@ -15,12 +15,14 @@
 //   defect's coefficient terms with lam;
 //   coefficient coarsening (full weighting, injection on the boundary):
 //     its transpose carries a coarse level's Dbar, mubar to the finer one.
-// The stencil kernels (the recorded half-sweep, the reverse of a half-sweep
-// and of the defect) march the column tiles of kernels_deriv.hpp on levels
-// N >= 128 (a thread's own column in registers, each plane's neighbours over
-// the tile plus a ring of one in LDS), and march one thread per plane vertex
-// (UnCol) on smaller levels.  The rest take one vertex per thread.  Cotangents are 0 on boundary vertices except Dbar, which
-// boundary faces reach.
+// On levels N >= 96 the stencil kernels march the column tiles of
+// kernels_deriv.hpp and take a whole red-black sweep per pass: the recorded
+// sweep (k_un_gs_sweep_t), its reverse (k_un_sweep_rev_t), and the defect's
+// reverse (k_un_defect_t), with each plane's neighbours over the tile plus a
+// ring in LDS.  Smaller levels march one thread per plane vertex (UnCol),
+// one half-sweep per pass.  The rest take one vertex per thread.
+// Cotangents are 0 on boundary vertices except Dbar, which boundary faces
+// reach.
 #pragma once
 #include "kernels_basic.hpp"
 #include "kernels_deriv.hpp"
@@ -36,9 +38,9 @@ __device__ __forceinline__ double dface_da(double Da, double Db, const Stencil<d
     return s.half_inv_h2;
 }
 
-// Levels below kDerSplitMin-sized grids (N < 128) run these x-march forms
-// instead of the column tiles: a thread per vertex column of the plane gives
-// small levels many more workgroups than whole 16 x 64 tiles would.
+// Levels below N = 96 run these x-march forms instead of the column tiles:
+// a thread per vertex column of the plane gives small levels many more
+// workgroups than whole 16 x 64 tiles would.
 //
 // Column march: thread p of a plane (p = y (N+1) + z, so a plane is one
 // coalesced run) walks the planes [x0, x0 + chunk) of chunk blockIdx.y and
