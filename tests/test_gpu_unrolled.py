@@ -57,13 +57,15 @@ def test_matches_oracle(N, n, nu, harmonic, g):
 
 
 @pytest.mark.parametrize("store", ["0", "1"])
-@pytest.mark.parametrize("N,n,nu,harmonic,g", [(48, 3, (2, 1), True, 0.2), (96, 2, (1, 2), False, 0.0)])
+@pytest.mark.parametrize("N,n,nu,harmonic,g", [(48, 3, (2, 1), True, 0.2), (96, 2, (1, 2), False, 0.0),
+                                               (24, 3, (2, 0), False, 0.1), (96, 2, (1, 1), True, 0.0)])
 def test_both_state_policies(store, N, n, nu, harmonic, g, monkeypatch):
     """The forward pass either keeps every cycle's recorded states or keeps
     the finest iterate per cycle and records each cycle again before its
     reverse pass (DMGS_UNROLLED_STORE = 1 / 0, read when the plan first
     allocates its buffers): both meet the oracle to 1e-12 (96^3: the finest
-    level on the column tiles)."""
+    level on the column tiles; V(2,0): the cycle's last state is its working
+    iterate)."""
     from oracle import unrolled
     monkeypatch.setenv("DMGS_UNROLLED_STORE", store)
     say("unrolled store=%s N=%d n=%d nu=%s harmonic=%s g=%g" % (store, N, n, nu, harmonic, g))
