@@ -2803,6 +2803,10 @@ struct UnWork {
     int alloc(double** p, int64_t n) {
         if (hipMalloc((void**)p, (size_t)n * sizeof(double)) != hipSuccess) {
             *p = nullptr;
+            // the failure is returned here; clear HIP's last error so that the
+            // next launch check does not report it again (the caller may fall
+            // back to a smaller layout and go on)
+            (void)hipGetLastError();
             set_error("hipMalloc of %lld bytes failed (unrolled reverse pass)", (long long)(n * sizeof(double)));
             return DMGS_ERR_OOM;
         }

@@ -82,6 +82,53 @@ def test_both_state_policies(store, N, n, nu, harmonic, g, monkeypatch):
     P.close()
 
 
+def test_state_policy_falls_back_when_memory_is_short(monkeypatch):
+    """With the policy left to the library, a plan whose states of every
+    cycle would fit in a quarter of device memory tries to keep them; when
+    the device has less free memory than that (the test occupies nearly all
+    of it first), the first call falls back to checkpoints and still returns
+    the checkpointed result, bitwise."""
+    import torch
+    monkeypatch.delenv("DMGS_UNROLLED_STORE", raising=False)
+    N, n = 128, 15
+    say("unrolled fallback N=%d n=%d" % (N, n))
+    logD, logmu, q, w = case(N, 400)
+    monkeypatch.setenv("DMGS_UNROLLED_STORE", "0")
+    R = plan_for(N, logD, logmu, fixed_cycles=n)
+    (r0, (qb0, gD0, gm0)), _ = R.vjp_unrolled(dev(q), dev(w))
+    torch.cuda.synchronize()
+    R.close()
+    monkeypatch.delenv("DMGS_UNROLLED_STORE")
+    P = plan_for(N, logD, logmu, fixed_cycles=n)
+    qd, wd = dev(q), dev(w)
+    torch.cuda.synchronize()
+    # leave about 1.5 GB free: less than the 2.7 GB of every cycle's states,
+    # more than the 0.6 GB of checkpoints and one cycle's states
+    hog = []
+    chunk = 8 << 30
+    while True:
+        free = torch.cuda.mem_get_info()[0]
+        if free < (2 << 30):
+            break
+        size = min(chunk, free - (3 << 29))
+        try:
+            hog.append(torch.empty(size, dtype=torch.uint8, device="cuda:0"))
+        except RuntimeError:
+            chunk //= 2
+            if chunk < (64 << 20):
+                break
+    say("  free while the call runs: %.2f GB" % (torch.cuda.mem_get_info()[0] / 1e9))
+    try:
+        (r1, (qb1, gD1, gm1)), _ = P.vjp_unrolled(qd, wd)
+        torch.cuda.synchronize()
+    finally:
+        del hog
+        torch.cuda.empty_cache()
+    for a, b in ((r0, r1), (qb0, qb1), (gD0, gD1), (gm0, gm1)):
+        assert torch.equal(a, b)
+    P.close()
+
+
 def test_central_differences_at_64():
     import torch
     say("unrolled 64^3 central differences")
