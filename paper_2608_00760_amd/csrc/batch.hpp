@@ -317,7 +317,7 @@ int dmgs_batch_create(dmgs_batch* out) {
     if (hipGetDevice(&B->device) != hipSuccess ||
         hipEventCreateWithFlags(&B->ev, hipEventDisableTiming) != hipSuccess) {
         delete B;
-        set_error("hipEventCreate failed");
+        (void)hipGetLastError(); set_error("hipEventCreate failed");
         return DMGS_ERR_HIP;
     }
     *out = B;

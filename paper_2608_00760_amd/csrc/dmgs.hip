@@ -41,10 +41,14 @@ void set_error(const char* fmt, ...) {
     va_end(ap);
 }
 
+// A failed HIP call is reported through the return code; HIP's per-thread
+// last error is cleared as well, so that a later call on this thread (after
+// an out-of-memory, say) is not failed by the next launch check.
 #define HIPCHK(expr)                                                                        \
     do {                                                                                    \
         hipError_t e_ = (expr);                                                             \
         if (e_ != hipSuccess) {                                                             \
+            (void)hipGetLastError();                                                        \
             set_error("%s:%d %s: %s", __FILE__, __LINE__, #expr, hipGetErrorString(e_));    \
             return DMGS_ERR_HIP;                                                            \
         }                                                                                   \
@@ -284,6 +288,7 @@ int dalloc(dmgs_plan P, T** p, int64_t count) {
     hipError_t e = hipMalloc((void**)p, (size_t)count * sizeof(T));
     if (e != hipSuccess) {
         *p = nullptr;
+        (void)hipGetLastError();   // reported here; not left for the next launch check
         set_error("hipMalloc of %lld bytes failed: %s", (long long)(count * sizeof(T)), hipGetErrorString(e));
         return DMGS_ERR_OOM;
     }
@@ -674,7 +679,7 @@ int sweep2_attributes() {
         {(const void*)k_rb_sweep2_col<double, kSweep2TY, kSweep2TZ64, kSweepPlain, true, false, true>, lds64}};
     for (const auto& f : fns)
         if (hipFuncSetAttribute(f.first, hipFuncAttributeMaxDynamicSharedMemorySize, f.second) != hipSuccess) {
-            set_error("hipFuncSetAttribute failed");
+            (void)hipGetLastError(); set_error("hipFuncSetAttribute failed");
             return DMGS_ERR_HIP;
         }
     return DMGS_OK;
@@ -911,7 +916,7 @@ int block_attributes() {
                         (int)BlockShape<kBlockB, kBlockPost>::lds_bytes(4), (int)BlockShape<kBlockB, kBlockPost>::lds_bytes(4)};
     for (int i = 0; i < 12; i++)
         if (hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, lims[i % 6]) != hipSuccess) {
-            set_error("hipFuncSetAttribute failed");
+            (void)hipGetLastError(); set_error("hipFuncSetAttribute failed");
             return DMGS_ERR_HIP;
         }
     return DMGS_OK;
@@ -2014,7 +2019,7 @@ int debug_check(dmgs_plan P, int k, int fp32, bool need_coarse) {
     if (is2d(P) || P->grid) { set_error("the diagnostic entry points take cubic three-dimensional plans"); return DMGS_ERR_INVALID; }
     if (k < 0 || k >= P->L || (need_coarse && k >= P->L - 1)) { set_error("bad level %d", k); return DMGS_ERR_INVALID; }
     if (fp32 && !is_ir(P)) { set_error("float32 arrays need a DMGS_FP32_IN_FP64 plan"); return DMGS_ERR_INVALID; }
-    if (hipSetDevice(P->device) != hipSuccess) { set_error("hipSetDevice failed"); return DMGS_ERR_HIP; }
+    if (hipSetDevice(P->device) != hipSuccess) { (void)hipGetLastError(); set_error("hipSetDevice failed"); return DMGS_ERR_HIP; }
     return DMGS_OK;
 }
 
@@ -2289,14 +2294,14 @@ int kernel_attributes(int device) {
                          (const void*)k_small_grp<float, false>, (const void*)k_small_grp<float, true>};
     for (const void* f : fns)
         if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) {
-            set_error("hipFuncSetAttribute failed");
+            (void)hipGetLastError(); set_error("hipFuncSetAttribute failed");
             return DMGS_ERR_HIP;
         }
     // the general-grid coarsest inverse: a plan's own size would lower the
     // limit for plans with a larger coarsest level, so the largest is set
     if (hipFuncSetAttribute((const void*)k_g_inverse, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(2 * kGridCoarseMax * kGridCoarseMax * sizeof(double))) != hipSuccess) {
-        set_error("hipFuncSetAttribute failed");
+        (void)hipGetLastError(); set_error("hipFuncSetAttribute failed");
         return DMGS_ERR_HIP;
     }
     TRY(sweep2_attributes());
@@ -2350,16 +2355,19 @@ int grid_plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
         P->hflag = &P->hflag_buf;
     } else {
         if (st == DMGS_OK && hipHostMalloc((void**)&P->hnorm, 4 * sizeof(double), hipHostMallocCoherent) != hipSuccess) {
+            (void)hipGetLastError();
             set_error("hipHostMalloc failed");
             st = DMGS_ERR_OOM;
         }
         if (st == DMGS_OK && hipHostMalloc((void**)&P->hflag, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
             set_error("hipHostMalloc failed");
             st = DMGS_ERR_OOM;
         }
         if (st == DMGS_OK && (hipEventCreate(&P->ev_start) != hipSuccess || hipEventCreate(&P->ev_stop) != hipSuccess ||
                               hipEventCreateWithFlags(&P->ev_norm, hipEventDisableTiming) != hipSuccess ||
                               hipEventCreateWithFlags(&P->ev_flag, hipEventDisableTiming) != hipSuccess)) {
+            (void)hipGetLastError();
             set_error("hipEventCreate failed");
             st = DMGS_ERR_HIP;
         }
@@ -2384,7 +2392,7 @@ int grid_plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
 
 int plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
     P->opt = *o;
-    if (hipGetDevice(&P->device) != hipSuccess) { set_error("hipGetDevice failed"); return DMGS_ERR_HIP; }
+    if (hipGetDevice(&P->device) != hipSuccess) { (void)hipGetLastError(); set_error("hipGetDevice failed"); return DMGS_ERR_HIP; }
     if (general_grid(o)) return grid_plan_init(P, o, zst);
     // cubic and square plans: one spacing (h_axis, when all three are given and equal, is it)
     if (o->ndim == 3) P->opt.h = axis_h(o, 0);
@@ -2444,16 +2452,19 @@ int plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
         P->hflag = &P->hflag_buf;
     } else {
         if (st == DMGS_OK && hipHostMalloc((void**)&P->hnorm, 4 * sizeof(double), hipHostMallocCoherent) != hipSuccess) {
+            (void)hipGetLastError();
             set_error("hipHostMalloc failed");
             st = DMGS_ERR_OOM;
         }
         if (st == DMGS_OK && hipHostMalloc((void**)&P->hflag, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
             set_error("hipHostMalloc failed");
             st = DMGS_ERR_OOM;
         }
         if (st == DMGS_OK && (hipEventCreate(&P->ev_start) != hipSuccess || hipEventCreate(&P->ev_stop) != hipSuccess ||
                               hipEventCreateWithFlags(&P->ev_norm, hipEventDisableTiming) != hipSuccess ||
                               hipEventCreateWithFlags(&P->ev_flag, hipEventDisableTiming) != hipSuccess)) {
+            (void)hipGetLastError();
             set_error("hipEventCreate failed");
             st = DMGS_ERR_HIP;
         }
@@ -2474,7 +2485,7 @@ int plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
                 else hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(cnt)), dim3(kBlock), 0, zst, (float*)ps[j], cnt, 0.0f);
                 if (hipGetLastError() != hipSuccess) { set_error("fill kernel launch failed"); st = DMGS_ERR_HIP; }
             } else if (hipMemset(ps[j], 0, cnt * sz[j]) != hipSuccess) {
-                set_error("hipMemset failed");
+                (void)hipGetLastError(); set_error("hipMemset failed");
                 st = DMGS_ERR_HIP;
             }
         }
@@ -2672,7 +2683,7 @@ int make_twin(dmgs_plan P) {
         size_t sz[] = {8, 8, 8, 4, 4, 4, 4};
         for (int j = 0; j < 7 && st == DMGS_OK; j++)
             if (ps[j] && hipMemset(ps[j], 0, (sz[j] == 8 ? l.nv : l.nv32) * sz[j]) != hipSuccess) {
-                set_error("hipMemset failed");
+                (void)hipGetLastError(); set_error("hipMemset failed");
                 st = DMGS_ERR_HIP;
             }
     }
@@ -2680,6 +2691,7 @@ int make_twin(dmgs_plan P) {
     if (ir && st == DMGS_OK) st = dalloc(T, &T->xalt64, T->lev[0].nv);
     if (st == DMGS_OK) st = dalloc(T, &T->partial, kMaxPartials);
     if (st == DMGS_OK && hipHostMalloc((void**)&T->hnorm, 4 * sizeof(double), hipHostMallocCoherent) != hipSuccess) {
+        (void)hipGetLastError();
         set_error("hipHostMalloc failed");
         st = DMGS_ERR_OOM;
     }
@@ -2688,7 +2700,7 @@ int make_twin(dmgs_plan P) {
                           hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
                           hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess ||
                           hipStreamCreateWithFlags(&P->twin_stream, hipStreamNonBlocking) != hipSuccess)) {
-        set_error("hipEventCreate / hipStreamCreate failed");
+        (void)hipGetLastError(); set_error("hipEventCreate / hipStreamCreate failed");
         st = DMGS_ERR_HIP;
     }
     if (st == DMGS_OK) st = hipDeviceSynchronize() == hipSuccess ? DMGS_OK : DMGS_ERR_HIP;
@@ -3341,7 +3353,7 @@ int dmgs_solve_once_noalloc(const dmgs_options* o, const double* D, const double
         void* p = nullptr;
         const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
         if (e != hipSuccess || !p) {
-            set_error("hipGetSymbolAddress of the static scratch failed: %s", hipGetErrorString(e));
+            (void)hipGetLastError(); set_error("hipGetSymbolAddress of the static scratch failed: %s", hipGetErrorString(e));
             return DMGS_ERR_HIP;
         }
         S.ptr = static_cast<unsigned char*>(p);

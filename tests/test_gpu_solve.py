@@ -165,6 +165,43 @@ def test_error_paths():
     assert info["cycles"] == 0 and float(zero.abs().max()) == 0.0
 
 
+def test_out_of_memory_leaves_other_plans_working(monkeypatch):
+    """A call whose work buffers do not fit on the device fails with
+    DMGS_ERR_OOM (here the unrolled adjoint at 256^3 told to keep the states
+    of 250 cycles, about 350 GB), and the next calls on this host thread, on
+    another plan and on the same one, still succeed: the failed allocation
+    is not left behind as HIP's last error for their launch checks."""
+    import torch
+    from paper_2608_00760_amd import _abi, synth
+    from paper_2608_00760_amd.solver import Options, Plan
+    say("out of memory")
+    N = 32
+    c = synth.grf_case(N, 555)
+    P = Plan(Options(N, precision="fp32-in-fp64"))
+    P.set_log_coefficients(dev(c["logD"]), dev(c["logmua"]))
+    q = dev(c["q"])
+    ref, _ = P.forward(q)
+    torch.cuda.synchronize()
+    monkeypatch.setenv("DMGS_UNROLLED_STORE", "1")
+    Nb = 256
+    Q = Plan(Options(Nb, fixed_cycles=250))
+    zero = torch.zeros(synth.shape(Nb), dtype=torch.float64, device="cuda:0")
+    Q.set_log_coefficients(zero, zero)
+    with pytest.raises(_abi.DMGSError) as e:
+        Q.vjp_unrolled(zero, zero)
+    assert e.value.status == _abi.DMGS_ERR_OOM
+    torch.cuda.synchronize()
+    rho, info = P.forward(q)
+    torch.cuda.synchronize()
+    assert info["status"] == _abi.DMGS_OK and torch.equal(rho, ref)
+    # the same plan: a plain solve (its own buffers were allocated at creation)
+    r, qi = Q.forward(zero)
+    torch.cuda.synchronize()
+    assert qi["status"] == _abi.DMGS_OK and float(r.abs().max()) == 0.0
+    Q.close()
+    P.close()
+
+
 def test_determinism_bitwise():
     from paper_2608_00760_amd import synth
     say("determinism")
