@@ -3054,17 +3054,14 @@ int vcycle_rev(dmgs_plan P, UnWork& W, int k, hipStream_t st) {
     UNCHK(W, W.qbar[k + 1], c.nv, "the coarse qbar");
     UNCHK(W, W.r[k], l.nv, "rbar");
     UNCHK(W, pre_state(P, W, k), l.nv, "the defect's recorded state");
-    hipLaunchKernelGGL(k_restrict<double>, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)W.ubar[k],
+    hipLaunchKernelGGL(k_un_restrict8, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, (const double*)W.ubar[k],
                        W.ubar[k + 1], l.N);
-    LAUNCHCHK();
-    hipLaunchKernelGGL(k_un_scale, dim3(grid_for(c.nv)), dim3(kBlock), 0, st, W.ubar[k + 1], c.nv, 8.0);
     LAUNCHCHK();
     TRY(fill<double>(W.qbar[k + 1], c.nv, 0.0, st));
     TRY(vcycle_rev(P, W, k + 1, st));
     // restriction qc = R r: rbar = R^T qcbar = I qcbar / 8; then the defect
-    TRY(fill<double>(W.r[k], l.nv, 0.0, st));
-    hipLaunchKernelGGL(k_prolong_add<double>, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, (const double*)W.qbar[k + 1],
-                       W.r[k], l.N);
+    hipLaunchKernelGGL(k_un_prolong_to, dim3(grid_for(l.nv)), dim3(kBlock), 0, st, (const double*)W.qbar[k + 1],
+                       (const double*)nullptr, W.r[k], l.N);
     LAUNCHCHK();
     defect_rev(W.ubar[k], (const double*)W.r[k], 0.125, pre_state(P, W, k));
     LAUNCHCHK();

@@ -746,14 +746,14 @@ __global__ __launch_bounds__(kDerThreads) void k_un_defect_t(double* __restrict_
 // u = u_pre + I ec (the trilinear prolongation of the coarse correction
 // added on interior vertices), u = u_pre on boundary ones: the recorded
 // cycle's post-smoothing input, formed out of place from the pre-smoothed
-// state.
+// state; with u_pre null, from zero (the reverse pass's rbar = I qcbar).
 __global__ void k_un_prolong_to(const double* __restrict__ ec, const double* __restrict__ u_pre,
                                 double* __restrict__ u, int Nf) {
     const int nf = Nf + 1, nc = Nf / 2 + 1;
     const int64_t nv = (int64_t)nf * nf * nf;
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
         const int z = (int)(v % nf), y = (int)((v / nf) % nf), x = (int)(v / ((int64_t)nf * nf));
-        double r = u_pre[v];
+        double r = u_pre ? u_pre[v] : 0.0;
         if (is_interior(Nf, x, y, z)) {
             const int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
             const int x1 = x0 + (x & 1), y1 = y0 + (y & 1), z1 = z0 + (z & 1);
@@ -767,9 +767,26 @@ __global__ void k_un_prolong_to(const double* __restrict__ ec, const double* __r
     }
 }
 
-// a *= f
-__global__ void k_un_scale(double* __restrict__ a, int64_t n, double f) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) a[i] *= f;
+// qc = 8 R r on coarse interior vertices (full weighting, then times 8: the
+// transpose of the prolongation I = 8 R^T), 0 on coarse boundary ones.
+__global__ void k_un_restrict8(const double* __restrict__ r, double* __restrict__ qc, int Nf) {
+    const int Nc = Nf / 2, nf = Nf + 1, nc = Nc + 1;
+    const int64_t nv = (int64_t)nc * nc * nc;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        const int Z = (int)(v % nc), Y = (int)((v / nc) % nc), X = (int)(v / ((int64_t)nc * nc));
+        if (!is_interior(Nc, X, Y, Z)) {
+            qc[v] = 0.0;
+            continue;
+        }
+        double s = 0.0;
+        for (int a = -1; a <= 1; a++)
+            for (int b = -1; b <= 1; b++) {
+                const double wab = (double)((2 - abs(a)) * (2 - abs(b)));
+                const double* row = r + vidx(nf, 2 * X + a, 2 * Y + b, 2 * Z);
+                s += wab * (row[-1] + 2.0 * row[0] + row[1]);
+            }
+        qc[v] = (s * (1.0 / 64.0)) * 8.0;
+    }
 }
 
 // fbar += (coarsening)^T cbar: full weighting (2-|a|)(2-|b|)(2-|c|)/64 from
