@@ -2159,7 +2159,7 @@ dim3 der_grid(dmgs_plan P, int N, int* chunk, int* cover) {
     return dim3((unsigned)tiles, (unsigned)(nch + erows));
 }
 
-// tangent right-hand side q' - A' rho of the push-forward (A9)
+// tangent right-hand side q' - A' rho of the push-forward (Sec. 2.3)
 int tangent_rhs(dmgs_plan P, const double* rho, const double* dq, const double* dlogD, const double* dlogmua,
                 double* out, hipStream_t st) {
     const Level& l0 = P->lev[0];
@@ -2187,7 +2187,7 @@ int tangent_rhs(dmgs_plan P, const double* rho, const double* dq, const double* 
     return DMGS_OK;
 }
 
-// coefficient gradients from the adjoint state lam (A10); with data d and
+// coefficient gradients from the adjoint state lam (the derivative of the discrete solution); with data d and
 // weights w, also the likelihood's direct log mua term
 int coef_grads(dmgs_plan P, const double* rho, const double* lam, double* gD, double* gmu, const double* d,
                const double* w, hipStream_t st) {
