@@ -174,7 +174,7 @@ size_t dmgs_forward_vjp_workspace_bytes(const dmgs_options *opt);
  *   DMGS_SWEEP_CFG (0)          float32 one-sweep pass tiles: 0 16x64, 1 8x64, 2 16x32
  *   DMGS_FUSE_MIN (32 / 16)     smallest N of the fused passes (float32 / float64 plans)
  *   DMGS_BLOCK_MAX (64)         largest N of the LDS block passes
- *   DMGS_DR_WGS (512)           target workgroups of the defect-restriction pass
+ *   DMGS_DR_WGS (512 / 1024)    target workgroups of the defect-restriction pass (float32 / float64 plans)
  *   DMGS_2D_SWEEP2_MIN (1536)   two-dimensional plans: smallest N of the two-sweep passes
  *   DMGS_2D_BLOCK_MIN (64)      ... smallest N of the LDS block passes
  *   DMGS_2D_DEFECT (1)          ... the last pre-smoothing pass writes the defect

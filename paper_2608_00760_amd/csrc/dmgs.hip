@@ -2513,7 +2513,9 @@ int plan_init(dmgs_plan P, const dmgs_options* o, hipStream_t zst) {
     }
     if (st == DMGS_OK) st = kernel_attributes(P->device);
     P->cfg_block_max = kn.block_max;
-    P->cfg_dr_wgs = 512;
+    // float64 plans: twice the workgroups (each moves twice the bytes of a
+    // float32 one; 20.76 -> 20.52 ms per 256^3 forward + VJP step)
+    P->cfg_dr_wgs = o->precision == DMGS_FP64 ? 1024 : 512;
     if (const char* e = std::getenv("DMGS_DR_WGS")) P->cfg_dr_wgs = std::max(16, std::atoi(e));
     P->cfg_defect = kn.defect;
     P->cfg_sweep2_min = kn.sweep2_min;
